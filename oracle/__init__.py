@@ -1,0 +1,460 @@
+"""CPU oracle of the multi-component mesh compressor (ctypes over liboracle.so).
+
+TEST INFRASTRUCTURE.  Only ``tests/``, the smoke check in
+``__graft_entry__`` and the CPU-baseline leg of ``bench.py`` may import this
+package.  It shares no code with the HIP library (``paper_2501_06910_amd``)
+and never imports it; inputs come from ``meshgen``.
+
+The C sources (``mco_*.c``) define what the hot path computes; this module
+only marshals numpy arrays and composes the steps in the paper's order:
+
+* compress (Alg. 3, closed loop): error split -> locate + resample f ->
+  grid compressor C(x1) -> reconstructed grid x1' -> back-interpolation
+  g(x1') -> residual compressor C(x2);
+* decompress (Alg. 4): grid decoder -> x1' -> g(x1') -> residual decoder
+  and recomposition x' = g(x1') + x2'.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c"]
+
+OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
+F32, F64 = 0, 1
+RADIUS = 32768
+BLOCK = 4096
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with gcc (no contraction, IEEE arithmetic)."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    if not force and os.path.exists(_LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs + [os.path.join(_HERE, "mco.h")])
+        if os.path.getmtime(_LIB_PATH) >= newest:
+            return _LIB_PATH
+    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class Grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n", C.c_int64 * 3), ("o", C.c_double * 3),
+                ("h", C.c_double * 3)]
+
+    @property
+    def count(self) -> int:
+        return int(self.n[0] * self.n[1] * self.n[2])
+
+    def dims(self):
+        return tuple(int(v) for v in self.n)
+
+
+class Bound(C.Structure):
+    _fields_ = [(k, C.c_double) for k in
+                ("tau", "tau1", "tau2", "c", "xmin", "xmax", "inv1", "step1", "inv2", "step2")]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        i64, i32, dbl = C.c_int64, C.c_int, C.c_double
+        sig = {
+            "mco_bound_compute": (i32, [P, i32, i64, dbl, i32, dbl, P]),
+            "mco_bbox": (None, [P, i32, i64, P, P]),
+            "mco_grid_from_dims": (i32, [P, i32, i64, P, P]),
+            "mco_grid_node": (None, [P, i64, P]),
+            "mco_bary": (i32, [i32, P, P, P, P]),
+            "mco_locate_brute": (i64, [P, P, i32, i64, i64, P, P, P, P]),
+            "mco_locate_raster": (i64, [P, P, i32, i64, i64, P, P, P, P]),
+            "mco_fill_unresolved": (None, [P, i32, i64, P, P, i32, P, P]),
+            "mco_resample": (None, [P, P, i32, i64, P, i32, dbl, P]),
+            "mco_vertex_cell": (None, [P, i32, i64, P, i64, P, P]),
+            "mco_back_interp": (None, [P, i32, i64, P, P, P]),
+            "mco_grid_quantize": (i32, [P, P, P, P, P, P, P, i64, P]),
+            "mco_grid_recon": (None, [P, i64, P, P]),
+            "mco_grid_decode": (i32, [P, P, P, i64, P, P]),
+            "mco_lorenzo": (None, [P, P, P]),
+            "mco_residual_quantize": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
+            "mco_learned_codes": (i32, [P, i32, i64, P, P, P, P, P, P, P, i64, P]),
+            "mco_vertex_decode": (None, [P, P, P, i64, P, P, i32, i64, P, P, P]),
+            "mco_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
+            "mco_bf16": (C.c_float, [C.c_float]),
+            "mco_mlp_kin": (i32, [i32]),
+            "mco_mlp_kpad": (i32, [i32]),
+            "mco_mlp_nparams": (i64, [i32]),
+            "mco_mlp_init": (None, [i32, C.c_uint64, P]),
+            "mco_mlp_features": (None, [P, i32, i64, P, P, P, C.c_float, i64, i64, P]),
+            "mco_mlp_feature_rms": (dbl, [P, i32, i64, P, P, P]),
+            "mco_mlp_forward": (None, [i32, P, P, i64, P, P, P, P]),
+            "mco_mlp_backward": (dbl, [i32, P, P, i64, P, i32, P]),
+            "mco_mlp_loss_exact": (dbl, [i32, P, P, i64, P, P]),
+            "mco_adam_step": (None, [i64, P, P, P, P, i64, C.c_float, C.c_float, C.c_float,
+                                     C.c_float]),
+            "mco_rho_quantize": (C.c_int32, [C.c_float]),
+            "mco_sample_indices": (None, [C.c_uint64, i64, i64, i64, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    if isinstance(a, C.Structure):
+        return C.addressof(a)
+    assert a.flags["C_CONTIGUOUS"], "arrays passed to the oracle must be contiguous"
+    return a.ctypes.data
+
+
+def _dtype_code(x: np.ndarray) -> int:
+    if x.dtype == np.float32:
+        return F32
+    if x.dtype == np.float64:
+        return F64
+    raise TypeError("field must be float32 or float64")
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status, what=""):
+        super().__init__(f"oracle status {status} {what}")
+        self.status = status
+
+
+# ---------------------------------------------------------------------------
+# step functions
+# ---------------------------------------------------------------------------
+
+def bound(x: np.ndarray, eb: float, relative: bool, split: float) -> Bound:
+    b = Bound()
+    st = lib().mco_bound_compute(_p(x), _dtype_code(x), x.size, eb, int(relative), split, _p(b))
+    if st != OK:
+        raise OracleError(st, "bound")
+    return b
+
+
+def bbox(coords):
+    lo = np.zeros(3, np.float32)
+    hi = np.zeros(3, np.float32)
+    lib().mco_bbox(_p(coords), coords.shape[0], coords.shape[1], _p(lo), _p(hi))
+    return lo, hi
+
+
+def grid_from_dims(coords, dims) -> Grid:
+    g = Grid()
+    d = np.array(list(dims) + [1] * (3 - len(dims)), np.int64)
+    st = lib().mco_grid_from_dims(_p(coords), coords.shape[0], coords.shape[1], _p(d), _p(g))
+    if st != OK:
+        raise OracleError(st, "grid")
+    return g
+
+
+def make_grid(dim, dims, origin, spacing) -> Grid:
+    g = Grid()
+    g.dim = dim
+    for d in range(3):
+        g.n[d] = dims[d] if d < dim else 1
+        g.o[d] = origin[d] if d < dim else 0.0
+        g.h[d] = spacing[d] if d < dim else 1.0
+    return g
+
+
+def grid_nodes(g: Grid) -> np.ndarray:
+    """FP32 node coordinates [3, n_g] (one call per node; small grids only)."""
+    out = np.zeros((3, g.count), np.float32)
+    y = np.zeros(3, np.float32)
+    for j in range(g.count):
+        lib().mco_grid_node(_p(g), j, _p(y))
+        out[:, j] = y
+    return out
+
+
+def bary(verts: np.ndarray, y: np.ndarray):
+    """(inside, lambdas[D+1], near_degenerate) for one simplex [D+1, D]."""
+    dim = verts.shape[1]
+    v = np.ascontiguousarray(verts, np.float32)
+    yy = np.ascontiguousarray(y, np.float32)
+    lam = np.zeros(dim + 1, np.float32)
+    nd = C.c_int(0)
+    inside = lib().mco_bary(dim, _p(v), _p(yy), _p(lam), C.byref(nd))
+    return bool(inside), lam, bool(nd.value)
+
+
+@dataclass
+class Mapping:
+    cell: np.ndarray      # int32 [n_g], -1 if unlocated
+    vid: np.ndarray       # int32 [D+1, n_g]
+    w: np.ndarray         # float32 [D+1, n_g]
+    n_unresolved: int
+
+
+def locate(coords, cells, g: Grid, method: str = "raster", fill: str = "nearest") -> Mapping:
+    dim = coords.shape[0]
+    ng = g.count
+    cell = np.empty(ng, np.int32)
+    vid = np.empty((dim + 1, ng), np.int32)
+    w = np.empty((dim + 1, ng), np.float32)
+    f = lib().mco_locate_brute if method == "brute" else lib().mco_locate_raster
+    nun = f(_p(coords), _p(cells), dim, coords.shape[1], cells.shape[1], _p(g), _p(cell),
+            _p(vid), _p(w))
+    if fill is not None:
+        lib().mco_fill_unresolved(_p(coords), dim, coords.shape[1], _p(g), _p(cell),
+                                  int(fill == "nearest"), _p(vid), _p(w))
+    return Mapping(cell, vid, w, int(nun))
+
+
+def resample(m: Mapping, x: np.ndarray, c: float) -> np.ndarray:
+    dim = m.vid.shape[0] - 1
+    v = np.empty(m.vid.shape[1], np.float32)
+    lib().mco_resample(_p(m.vid), _p(m.w), dim, m.vid.shape[1], _p(x), _dtype_code(x), c, _p(v))
+    return v
+
+
+def vertex_cells(coords, g: Grid):
+    dim, nv = coords.shape
+    idx = np.zeros((nv, 3), np.int32)
+    t = np.zeros((nv, 3), np.float32)
+    for v in range(nv):
+        lib().mco_vertex_cell(_p(coords), dim, nv, _p(g), v, _p(idx[v]), _p(t[v]))
+    return idx, t
+
+
+def back_interp(coords, g: Grid, xhat: np.ndarray) -> np.ndarray:
+    gv = np.empty(coords.shape[1], np.float32)
+    lib().mco_back_interp(_p(coords), coords.shape[0], coords.shape[1], _p(g), _p(xhat), _p(gv))
+    return gv
+
+
+def lorenzo(p: np.ndarray, g: Grid) -> np.ndarray:
+    d = np.empty(g.count, np.int64)
+    lib().mco_lorenzo(_p(np.ascontiguousarray(p, np.int32)), _p(g), _p(d))
+    return d
+
+
+@dataclass
+class GridCodes:
+    p: np.ndarray
+    codes: np.ndarray
+    out_idx: np.ndarray
+    out_delta: np.ndarray
+
+
+def grid_quantize(v: np.ndarray, g: Grid, b: Bound) -> GridCodes:
+    ng = g.count
+    p = np.empty(ng, np.int32)
+    codes = np.empty(ng, np.uint16)
+    cap = ng
+    oi = np.empty(cap, np.int32)
+    od = np.empty(cap, np.int32)
+    n = C.c_int64(0)
+    st = lib().mco_grid_quantize(_p(v), _p(g), _p(b), _p(p), _p(codes), _p(oi), _p(od), cap,
+                                 C.byref(n))
+    if st != OK:
+        raise OracleError(st, "grid_quantize")
+    return GridCodes(p, codes, oi[:n.value].copy(), od[:n.value].copy())
+
+
+def grid_recon(p: np.ndarray, b: Bound) -> np.ndarray:
+    x = np.empty(p.size, np.float32)
+    lib().mco_grid_recon(_p(p), p.size, _p(b), _p(x))
+    return x
+
+
+def grid_decode(codes, out_idx, out_delta, g: Grid) -> np.ndarray:
+    p = np.empty(g.count, np.int32)
+    st = lib().mco_grid_decode(_p(codes), _p(out_idx), _p(out_delta), out_idx.size, _p(g), _p(p))
+    if st != OK:
+        raise OracleError(st, "grid_decode")
+    return p
+
+
+@dataclass
+class VertexCodes:
+    codes: np.ndarray
+    out_idx: np.ndarray
+    out_val: np.ndarray
+    block_flags: np.ndarray | None = None
+
+
+def residual_quantize(x: np.ndarray, gv: np.ndarray, b: Bound) -> VertexCodes:
+    nv = x.size
+    codes = np.empty(nv, np.uint16)
+    oi = np.empty(nv, np.int32)
+    ov = np.empty(nv, x.dtype)
+    n = C.c_int64(0)
+    st = lib().mco_residual_quantize(_p(x), _dtype_code(x), nv, _p(gv), _p(b), _p(codes),
+                                     _p(oi), _p(ov), nv, C.byref(n))
+    if st != OK:
+        raise OracleError(st, "residual_quantize")
+    return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy())
+
+
+def learned_codes(x: np.ndarray, gv: np.ndarray, b: Bound, rho_q: np.ndarray) -> VertexCodes:
+    nv = x.size
+    nb = (nv + BLOCK - 1) // BLOCK
+    codes = np.empty(nv, np.uint16)
+    flags = np.zeros((nb + 31) // 32, np.uint32)
+    oi = np.empty(nv, np.int32)
+    ov = np.empty(nv, x.dtype)
+    n = C.c_int64(0)
+    rq = np.ascontiguousarray(rho_q, np.int32)
+    st = lib().mco_learned_codes(_p(x), _dtype_code(x), nv, _p(gv), _p(b), _p(rq), _p(codes),
+                                 _p(flags), _p(oi), _p(ov), nv, C.byref(n))
+    if st != OK:
+        raise OracleError(st, "learned_codes")
+    return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy(), flags)
+
+
+def vertex_decode(vc: VertexCodes, gv, b: Bound, dtype, rho_q=None) -> np.ndarray:
+    nv = vc.codes.size
+    out = np.empty(nv, dtype)
+    rq = None if rho_q is None else np.ascontiguousarray(rho_q, np.int32)
+    lib().mco_vertex_decode(_p(vc.codes), _p(vc.out_idx), _p(vc.out_val), vc.out_idx.size,
+                            _p(gv), _p(b), _dtype_code(out), nv, _p(rq),
+                            _p(vc.block_flags) if rq is not None else None, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# composed pipeline (Alg. 3 / Alg. 4)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Compressed:
+    bound: Bound
+    grid: GridCodes
+    vert: VertexCodes
+    xhat: np.ndarray
+    gv: np.ndarray
+    v: np.ndarray
+
+
+def compress(coords, m: Mapping, g: Grid, x: np.ndarray, eb: float, relative: bool,
+             split: float, rho_q=None) -> Compressed:
+    b = bound(x, eb, relative, split)
+    v = resample(m, x, b.c)
+    gc = grid_quantize(v, g, b)
+    xhat = grid_recon(gc.p, b)
+    gv = back_interp(coords, g, xhat)
+    vc = residual_quantize(x, gv, b) if rho_q is None else learned_codes(x, gv, b, rho_q)
+    return Compressed(b, gc, vc, xhat, gv, v)
+
+
+def decompress(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
+               rho_q=None) -> np.ndarray:
+    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g)
+    xhat = grid_recon(p, b)
+    gv = back_interp(coords, g, xhat)
+    return vertex_decode(vc, gv, b, dtype, rho_q)
+
+
+# ---------------------------------------------------------------------------
+# learned predictor
+# ---------------------------------------------------------------------------
+
+def splitmix64(seed: int, counter: int) -> int:
+    return int(lib().mco_splitmix64(seed, counter))
+
+
+def bf16(a: np.ndarray) -> np.ndarray:
+    f = np.vectorize(lambda v: lib().mco_bf16(float(v)), otypes=[np.float32])
+    return f(np.asarray(a, np.float32))
+
+
+def mlp_kin(dim): return int(lib().mco_mlp_kin(dim))
+def mlp_kpad(dim): return int(lib().mco_mlp_kpad(dim))
+def mlp_nparams(dim): return int(lib().mco_mlp_nparams(dim))
+
+
+def mlp_init(dim: int, seed: int) -> np.ndarray:
+    p = np.empty(mlp_nparams(dim), np.float32)
+    lib().mco_mlp_init(dim, seed, _p(p))
+    return p
+
+
+def mlp_features(coords, g: Grid, xhat, gv, kappa: float, v0: int = 0, count=None):
+    dim, nv = coords.shape
+    if count is None:
+        count = nv - v0
+    z = np.empty((count, mlp_kpad(dim)), np.float32)
+    lib().mco_mlp_features(_p(coords), dim, nv, _p(g), _p(xhat), _p(gv), kappa, v0, count, _p(z))
+    return z
+
+
+def mlp_feature_rms(coords, g: Grid, xhat, gv) -> float:
+    return float(lib().mco_mlp_feature_rms(_p(coords), coords.shape[0], coords.shape[1], _p(g),
+                                           _p(xhat), _p(gv)))
+
+
+def mlp_forward(dim, params, z):
+    B = z.shape[0]
+    h = [np.empty((B, 64), np.float32) for _ in range(3)]
+    rho = np.empty(B, np.float32)
+    lib().mco_mlp_forward(dim, _p(params), _p(np.ascontiguousarray(z, np.float32)), B,
+                          _p(h[0]), _p(h[1]), _p(h[2]), _p(rho))
+    return rho, h
+
+
+def mlp_backward(dim, params, z, y, round_bf16=True):
+    g = np.empty(mlp_nparams(dim), np.float32)
+    loss = lib().mco_mlp_backward(dim, _p(params), _p(np.ascontiguousarray(z, np.float32)),
+                                  z.shape[0], _p(np.ascontiguousarray(y, np.float32)),
+                                  int(round_bf16), _p(g))
+    return float(loss), g
+
+
+def mlp_loss_exact(dim, params64, z64, y64, want_grad=True):
+    g = np.empty(mlp_nparams(dim), np.float64) if want_grad else None
+    loss = lib().mco_mlp_loss_exact(dim, _p(params64), _p(z64), z64.shape[0], _p(y64), _p(g))
+    return float(loss), g
+
+
+def adam_step(params, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    lib().mco_adam_step(params.size, _p(params), _p(m), _p(v), _p(grad), t, lr, b1, b2, eps)
+
+
+def rho_quantize(rho: np.ndarray) -> np.ndarray:
+    return np.array([lib().mco_rho_quantize(float(r)) for r in np.asarray(rho, np.float32)],
+                    np.int32)
+
+
+def sample_indices(seed: int, step: int, batch: int, n: int) -> np.ndarray:
+    idx = np.empty(batch, np.int64)
+    lib().mco_sample_indices(seed, step, batch, n, _p(idx))
+    return idx
+
+
+def train(dim, z_all, y_all, steps, batch, seed, lr=1e-3, params=None):
+    """Adam training loop: minibatch of step s from sample_indices(seed, s)."""
+    if params is None:
+        params = mlp_init(dim, seed)
+    params = params.copy()
+    m = np.zeros_like(params)
+    v = np.zeros_like(params)
+    losses = []
+    for s in range(steps):
+        idx = sample_indices(seed, s, batch, z_all.shape[0])
+        loss, g = mlp_backward(dim, params, z_all[idx], y_all[idx])
+        adam_step(params, m, v, g, s + 1, lr)
+        losses.append(loss)
+    return params, losses
