@@ -1,0 +1,276 @@
+/*
+ * mc.h -- C ABI of the MI355X (gfx950) multi-component error-bounded
+ * compressor for values on unstructured triangle / tetrahedral meshes
+ * (Gong et al., "A General Framework for Error-controlled Unstructured
+ * Scientific Data Compression").
+ *
+ * The method (paper Sec. III, Sec. IV-B..IV-E, Algorithms 3 and 4):
+ * vertex values x are resampled onto a rectilinear grid (x1 = f(x)), the
+ * grid is compressed with bound tau1, the reconstructed grid x1' is
+ * interpolated back to the vertices (g, non-negative weights summing to one)
+ * and the residuals x - g(x1') are compressed with bound tau2, so every
+ * reconstructed vertex x' = g(x1') + x2' satisfies |x - x'| <= tau2 <= tau
+ * (Sec. III).  f is barycentric interpolation in the lowest-numbered cell
+ * containing the node (the "linear interpolation" f of Sec. IV-D); g is
+ * multilinear interpolation; the grid compressor is a Lorenzo predictor on
+ * prequantised integers with linear quantisation (the SZ-family predictor
+ * named in Sec. II); the residual compressor is linear quantisation with a
+ * per-vertex bound check.  An optional learned predictor (a small MLP)
+ * shifts residual codes per 4096-vertex block without changing the bound.
+ *
+ * Conventions
+ *  - Pointers prefixed d_ are device (HBM) pointers, h_ are host pointers.
+ *  - Layouts are structure-of-arrays: coordinates float[dim][n_vertices],
+ *    cells int32[dim+1][n_cells] (0-based vertex ids), grid arrays with
+ *    linear index i0 + n0*(i1 + n1*i2) (x fastest).
+ *  - Calls marked (sync) block the host; all others only enqueue work on the
+ *    given HIP stream and return.  Host-detectable argument errors return
+ *    before any HIP call.  Errors found on the device (NaN/Inf in the field,
+ *    integer range, outlier capacity) are written to mc_result.status and
+ *    are visible once the stream has been synchronised.
+ *  - The caller owns every buffer it passes; buffers must stay alive until
+ *    the stream has finished using them.  Plans and models are owned by the
+ *    library (mc_plan_destroy / mc_model_destroy).
+ *  - Calls on one plan use that plan's device workspace: they must be
+ *    ordered on one stream (overlapping calls on one plan race).
+ *  - No C++ exception crosses this ABI; mc_last_error() gives the text of
+ *    the last host-side failure of the calling thread.
+ */
+#ifndef MC_H
+#define MC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MC_OK = 0,
+    MC_ERR_ARG = 1,         /* invalid argument (host) or invalid field (device: NaN/Inf, tau <= 0) */
+    MC_ERR_RANGE = 2,       /* |(v - c) / (2 tau1)| >= 2^27: error bound too small for the data range */
+    MC_ERR_CAPACITY = 3,    /* more outliers than the caller's capacity; counts are still exact */
+    MC_ERR_NOMEM = 4,       /* device allocation failed */
+    MC_ERR_DEVICE = 5,      /* a HIP call failed */
+    MC_ERR_FORMAT = 6,      /* malformed serialized model or stream */
+    MC_ERR_UNSUPPORTED = 7  /* valid request outside what this build supports */
+} mc_status;
+
+typedef enum { MC_F32 = 0, MC_F64 = 1 } mc_dtype;
+typedef enum { MC_EB_ABS = 0, MC_EB_REL = 1 } mc_eb_mode;   /* REL: tau = eb * (max x - min x) */
+typedef enum { MC_FILL_NEAREST = 0, MC_FILL_MIDRANGE = 1 } mc_fill;
+
+#define MC_RADIUS 32768      /* quantisation radius R: code = value + R, code 0 = outlier */
+#define MC_BLOCK 4096        /* vertices per learned/plain decision block */
+
+/* Rectilinear grid.  Node (i0,i1,i2) is at origin + i * spacing; its FP32
+ * position is (float)origin + (float)i * (float)spacing.  dims >= 2 on every
+ * used axis; 2-D grids have dims[2] = 1. */
+typedef struct {
+    int32_t dim;
+    int64_t dims[3];
+    double origin[3];
+    double spacing[3];
+} mc_grid;
+
+typedef struct mc_plan_s* mc_plan;
+typedef struct mc_model_s* mc_model;
+
+typedef struct {
+    mc_fill fill;            /* nodes outside every cell: nearest vertex (default) or mid-range */
+    int32_t bin_nodes;       /* point-location bin edge in grid nodes (0 = tuned default) */
+} mc_plan_opts;
+
+typedef struct {
+    int64_t n_grid;          /* grid nodes */
+    int64_t n_vertices;
+    int64_t n_cells;
+    int64_t n_unresolved;    /* grid nodes in no cell (filled per mc_plan_opts.fill) */
+    int64_t n_near_degenerate;  /* cells whose weights were recomputed in FP64 */
+    int64_t n_pairs;         /* (bin, cell) pairs of the point-location index */
+    int64_t bin_nodes;
+    int64_t device_bytes;    /* device memory held by the plan */
+    int32_t invalid_cells;   /* cells with an out-of-range vertex id (plan creation fails) */
+} mc_plan_info;
+
+/* Compression parameters.  The grid receives tau1 = grid_share * tau and the
+ * residuals tau2 = tau - tau1 (Sec. III: tau1 + tau2 <= tau). */
+typedef struct {
+    double eb;               /* error bound, > 0 */
+    int32_t eb_mode;         /* mc_eb_mode */
+    double grid_share;       /* tau1 / tau, in (0, 1) */
+    mc_model model;          /* NULL: plain residual codes; else learned shift per block */
+} mc_params;
+
+/* Device-side result header, written by mc_compress and read by
+ * mc_decompress (it carries the quantisation steps). */
+typedef struct {
+    int32_t status;          /* mc_status of the device work */
+    int32_t dtype;
+    int64_t n_grid_outliers;
+    int64_t n_vertex_outliers;
+    int64_t n_learned_blocks;
+    double tau, tau1, tau2, c, xmin, xmax;
+    double kappa_unused;
+} mc_result;
+
+/* Compressed representation (caller-allocated device buffers).
+ *   grid_codes  uint16[n_grid]      code d + R of the Lorenzo error d, 0 = outlier
+ *   g_out_idx   int32[g_out_cap]    grid outlier node ids, ascending
+ *   g_out_delta int32[g_out_cap]    their Lorenzo errors
+ *   vert_codes  uint16[n_vertices]  residual code q + R (learned: q - rho_q + R), 0 = outlier
+ *   v_out_idx   int32[v_out_cap]    vertex outlier ids, ascending
+ *   v_out_val   T[v_out_cap]        their raw values (T = field dtype)
+ *   block_flags uint32[ceil(ceil(n_v/4096)/32)]  bit b: block b learned (may be NULL for plain)
+ *   result      mc_result (device)
+ * Optional diagnostics, written when non-NULL:
+ *   dbg_resampled float[n_grid] (f(x) on the grid), dbg_grid_p int32[n_grid]
+ *   (prequantised grid), dbg_vertex_g float[n_vertices] (g(x1') at the
+ *   vertices), rho_q int32[n_vertices] (learned shift, learned mode only). */
+typedef struct {
+    uint16_t* grid_codes;
+    int32_t* g_out_idx;
+    int32_t* g_out_delta;
+    int64_t g_out_cap;
+    uint16_t* vert_codes;
+    int32_t* v_out_idx;
+    void* v_out_val;
+    int64_t v_out_cap;
+    uint32_t* block_flags;
+    mc_result* result;
+    float* dbg_resampled;
+    int32_t* dbg_grid_p;
+    float* dbg_vertex_g;
+    int32_t* rho_q;
+} mc_codes;
+
+const char* mc_status_string(mc_status s);
+const char* mc_last_error(void);
+int32_t mc_abi_version(void);
+
+/* Grid spanning the bounding box of the vertices (Alg. 1 takes the grid
+ * corners from the minimum and maximum vertex coordinates): origin = min,
+ * spacing = (max - min) / (dims - 1).  (sync) */
+mc_status mc_grid_from_dims(const float* d_coords, int32_t dim, int64_t n_vertices,
+                            const int64_t dims[3], hipStream_t stream, mc_grid* out);
+/* Grid with the given spacing h over the bounding box:
+ * dims = ceil((max - min) / h) + 1.  (sync) */
+mc_status mc_grid_from_spacing(const float* d_coords, int32_t dim, int64_t n_vertices,
+                               const double spacing[3], hipStream_t stream, mc_grid* out);
+
+/* Field-independent plan (the paper's reusable mesh-grid mapping, Sec.
+ * IV-B/IV-C): a uniform bin index over the grid, the containing cell and
+ * barycentric weights of every grid node, and the fill of nodes outside the
+ * mesh.  The plan copies the coordinates; the caller may free the mesh once
+ * this returns.  (sync) */
+mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t dim,
+                         int64_t n_vertices, int64_t n_cells, const mc_grid* grid,
+                         const mc_plan_opts* opts, hipStream_t stream, mc_plan* out);
+mc_status mc_plan_get_info(mc_plan plan, mc_plan_info* out);
+/* Copies the mapping: d_vid int32[dim+1][n_grid] (-1 for mid-range-filled
+ * nodes), d_w float[dim+1][n_grid], d_cell int32[n_grid] (-1 = unresolved);
+ * any may be NULL. */
+mc_status mc_plan_mapping(mc_plan plan, int32_t* d_vid, float* d_w, int32_t* d_cell,
+                          hipStream_t stream);
+mc_status mc_plan_get_grid(mc_plan plan, mc_grid* out);
+mc_status mc_plan_destroy(mc_plan plan);
+
+/* Compress one field (Alg. 3, residuals against the reconstructed grid). */
+mc_status mc_compress(mc_plan plan, const void* d_field, mc_dtype dtype,
+                      const mc_params* params, const mc_codes* codes, hipStream_t stream);
+/* Decompress (Alg. 4) into d_field_out (dtype of the compressed field).
+ * model must be the model the field was compressed with (NULL if plain). */
+mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
+                        void* d_field_out, mc_dtype dtype, hipStream_t stream);
+
+/* One-shot form: builds a plan for the mesh and a grid with the given
+ * spacing, compresses, and releases the plan.  (sync) */
+mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_cells, int32_t dim,
+                           int64_t n_vertices, int64_t n_cells, const void* d_field,
+                           mc_dtype dtype, const double spacing[3], double eb,
+                           int32_t eb_mode, double grid_share, const mc_codes* codes,
+                           mc_grid* grid_out, hipStream_t stream);
+
+/* ---- learned residual predictor ----------------------------------------
+ * MLP in -> 64 -> 64 -> 64 -> 1 (ReLU).  Inputs per vertex: for the 4^dim
+ * grid nodes around its grid cell (indices clamped), bf16((x1'[n] - g) *
+ * kappa), then bf16(t_d - 0.5) per axis, zero-padded to 32 (2-D) or 96
+ * (3-D).  Weights BF16, accumulation FP32, output in residual-code units.
+ * Parameter vector (FP32, shared with the model file): W1[64][Kin]
+ * (output-major), b1[64], W2[64][64], b2, W3[64][64], b3, W4[64], b4[1];
+ * Kin = 4^dim + dim. */
+typedef struct {
+    int32_t steps;           /* Adam steps (default 2000) */
+    int32_t batch;           /* minibatch (default 8192) */
+    float lr;                /* default 1e-3 */
+    uint64_t seed;           /* SplitMix64 seed for init and sampling */
+    float* h_loss_out;       /* optional host float[steps]: loss per step */
+} mc_train_opts;
+
+int64_t mc_model_param_count(int32_t dim);
+/* Model from a host parameter vector and input scale kappa. */
+mc_status mc_model_create(int32_t dim, const float* h_params, float kappa, mc_model* out);
+/* Trains a model on the residuals of field_t0 (plain compression with
+ * params), on the GPU.  (sync) */
+mc_status mc_model_train(mc_plan plan, const void* d_field_t0, mc_dtype dtype,
+                         const mc_params* params, const mc_train_opts* opts,
+                         hipStream_t stream, mc_model* out);
+mc_status mc_model_get_params(mc_model model, float* h_params, float* kappa);
+mc_status mc_model_export(mc_model model, void* h_buf, size_t cap, size_t* written);
+mc_status mc_model_import(const void* h_buf, size_t n, mc_model* out);
+mc_status mc_model_destroy(mc_model model);
+/* Forward pass on given inputs d_z float[batch][Kpad] (BF16-valued):
+ * d_rho float[batch]. */
+mc_status mc_model_forward(mc_model model, const float* d_z, int64_t batch, float* d_rho,
+                           hipStream_t stream);
+/* Mean-squared-error loss and gradient (d_grad float[param_count]) over a
+ * batch, with the training kernels. */
+mc_status mc_model_loss_grad(mc_model model, const float* d_z, const float* d_y,
+                             int64_t batch, float* d_grad, float* d_loss,
+                             hipStream_t stream);
+/* Input features of vertices [v0, v0+count) for a compressed field: d_z
+ * float[count][Kpad]; uses the plan's last reconstructed grid. */
+mc_status mc_model_features(mc_model model, mc_plan plan, const mc_codes* codes, int64_t v0,
+                            int64_t count, float* d_z, hipStream_t stream);
+
+/* ---- batched compression ------------------------------------------------
+ * Many fields on many plans in one persistent launch (captured in a HIP
+ * graph on the first call with a given item list and replayed after). */
+typedef struct {
+    mc_plan plan;
+    const void* d_field;
+    mc_dtype dtype;
+    mc_params params;
+    mc_codes codes;
+} mc_batch_item;
+
+mc_status mc_batch_compress(const mc_batch_item* items, int32_t n_items, hipStream_t stream);
+
+/* ---- profiling -----------------------------------------------------------
+ * When enabled, every kernel launch is bracketed by HIP events on the
+ * launch stream; mc_profile_read returns per-kernel launch counts and
+ * summed milliseconds (sync). */
+mc_status mc_profile_enable(int32_t on);
+mc_status mc_profile_reset(void);
+/* Writes up to cap entries: names (each a static string), counts, total ms. */
+int32_t mc_profile_read(const char** names, int64_t* counts, double* total_ms, int32_t cap);
+
+/* ---- CPU entropy stage (host, outside the hot path) ---------------------
+ * Canonical Huffman (code lengths <= 24) over uint16 symbols plus the
+ * outlier lists; gives the compressed size used for the compression ratio
+ * S / (stream bytes) (the paper's ratio, Sec. IV-A, with original size S). */
+/* Bytes of the Huffman-coded symbol stream including its code table. */
+int64_t mc_huffman_size(const uint16_t* h_sym, int64_t n);
+/* Encode into h_out (cap bytes); returns bytes written or -1. */
+int64_t mc_huffman_encode(const uint16_t* h_sym, int64_t n, uint8_t* h_out, int64_t cap);
+/* Decode n symbols; returns bytes consumed or -1 on a malformed stream. */
+int64_t mc_huffman_decode(const uint8_t* h_in, int64_t n_in, uint16_t* h_sym, int64_t n);
+/* Empirical Shannon entropy of the symbols, bits per symbol. */
+double mc_entropy_bits(const uint16_t* h_sym, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

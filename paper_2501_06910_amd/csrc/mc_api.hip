@@ -1,0 +1,641 @@
+// mc_api.hip -- host side of the C ABI declared in include/mc.h: argument
+// validation (before any HIP call), plan construction, the compress and
+// decompress sequences, models, batching and the kernel profiler.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mc_internal.h"
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+mc_status mc_fail(mc_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+extern "C" const char* mc_last_error(void) { return g_last_error.c_str(); }
+extern "C" int32_t mc_abi_version(void) { return 1; }
+
+extern "C" const char* mc_status_string(mc_status s)
+{
+    switch (s) {
+    case MC_OK: return "ok";
+    case MC_ERR_ARG: return "invalid argument";
+    case MC_ERR_RANGE: return "error bound too small for the data range";
+    case MC_ERR_CAPACITY: return "outlier capacity exceeded";
+    case MC_ERR_NOMEM: return "device allocation failed";
+    case MC_ERR_DEVICE: return "HIP call failed";
+    case MC_ERR_FORMAT: return "malformed serialized data";
+    case MC_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+// ---------------------------------------------------------------------------
+// profiler: HIP events around each launch, on the launch stream
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+std::mutex g_pm;
+bool g_prof_on = false;
+std::vector<ProfRec> g_recs;
+std::vector<hipEvent_t> g_pool;
+
+hipEvent_t pool_get()
+{
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+mck::ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), idx(-1)
+{
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_pm);
+    hipEvent_t a = pool_get(), b = pool_get();
+    if (!a || !b) return;
+    hipEventRecord(a, s);
+    idx = (int)g_recs.size();
+    g_recs.push_back({n, a, b});
+}
+
+mck::ProfScope::~ProfScope()
+{
+    if (idx < 0) return;
+    std::lock_guard<std::mutex> lk(g_pm);
+    hipEventRecord(g_recs[idx].b, stream);
+}
+
+namespace {
+struct ProfAgg {
+    const char* name;
+    long long count;
+    double ms;
+};
+std::vector<ProfAgg> g_agg;
+
+void prof_drain()
+{
+    for (auto& r : g_recs) {
+        hipEventSynchronize(r.b);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, r.a, r.b);
+        bool found = false;
+        for (auto& a : g_agg)
+            if (strcmp(a.name, r.name) == 0) { a.count++; a.ms += ms; found = true; break; }
+        if (!found) g_agg.push_back({r.name, 1, (double)ms});
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_recs.clear();
+}
+}  // namespace
+
+extern "C" mc_status mc_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_pm);
+    g_prof_on = on != 0;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_pm);
+    prof_drain();
+    g_agg.clear();
+    return MC_OK;
+}
+
+extern "C" int32_t mc_profile_read(const char** names, int64_t* counts, double* total_ms, int32_t cap)
+{
+    std::lock_guard<std::mutex> lk(g_pm);
+    prof_drain();
+    int32_t n = 0;
+    for (auto& a : g_agg) {
+        if (n >= cap) break;
+        if (names) names[n] = a.name;
+        if (counts) counts[n] = a.count;
+        if (total_ms) total_ms[n] = a.ms;
+        ++n;
+    }
+    return n;
+}
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+struct TempAllocs {
+    std::vector<void*> ptrs;
+    ~TempAllocs()
+    {
+        for (void* p : ptrs) hipFree(p);
+    }
+    template <typename T> T* get(size_t n, hipError_t& err)
+    {
+        void* p = nullptr;
+        err = hipMalloc(&p, n * sizeof(T) > 0 ? n * sizeof(T) : 16);
+        if (err != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+};
+
+template <typename T> static hipError_t plan_alloc(mc_plan p, T** out, size_t n)
+{
+    void* q = nullptr;
+    size_t bytes = n * sizeof(T) > 0 ? n * sizeof(T) : 16;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return e;
+    p->allocs.push_back(q);
+    p->bytes += bytes;
+    *out = (T*)q;
+    return hipSuccess;
+}
+
+static float fkey_inv(unsigned k)
+{
+    unsigned b = (k >> 31) ? (k & 0x7fffffffu) : ~k;
+    float f;
+    memcpy(&f, &b, 4);
+    return f;
+}
+
+static mc_status device_bbox(const float* d_coords, int dim, long long nv, hipStream_t s, float lo[3], float hi[3])
+{
+    unsigned init[6] = {~0u, 0u, ~0u, 0u, ~0u, 0u};
+    TempAllocs ta;
+    hipError_t e;
+    unsigned* keys = ta.get<unsigned>(6, e);
+    if (!keys) return mc_fail(MC_ERR_NOMEM, "bbox keys: %s", hipGetErrorString(e));
+    if ((e = hipMemcpyAsync(keys, init, sizeof init, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = mck::bbox(d_coords, dim, nv, keys, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(init, keys, sizeof init, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return mc_fail(MC_ERR_DEVICE, "bbox: %s", hipGetErrorString(e));
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = d < dim ? fkey_inv(init[2 * d]) : 0.f;
+        hi[d] = d < dim ? fkey_inv(init[2 * d + 1]) : 0.f;
+    }
+    return MC_OK;
+}
+
+static mc_status check_mesh_args(const float* d_coords, int32_t dim, int64_t nv)
+{
+    if (!d_coords) return mc_fail(MC_ERR_ARG, "coordinates pointer is NULL");
+    if (dim != 2 && dim != 3) return mc_fail(MC_ERR_ARG, "dim must be 2 or 3 (got %d)", dim);
+    if (nv <= 0 || nv >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_vertices must be in [1, 2^31) (got %lld)", (long long)nv);
+    return MC_OK;
+}
+
+extern "C" mc_status mc_grid_from_dims(const float* d_coords, int32_t dim, int64_t n_vertices, const int64_t dims[3],
+                                       hipStream_t stream, mc_grid* out)
+{
+    mc_status st = check_mesh_args(d_coords, dim, n_vertices);
+    if (st != MC_OK) return st;
+    if (!dims || !out) return mc_fail(MC_ERR_ARG, "dims/out pointer is NULL");
+    for (int d = 0; d < dim; ++d)
+        if (dims[d] < 2) return mc_fail(MC_ERR_ARG, "grid dims must be >= 2 on every axis");
+    float lo[3], hi[3];
+    if ((st = device_bbox(d_coords, dim, n_vertices, stream, lo, hi)) != MC_OK) return st;
+    memset(out, 0, sizeof *out);
+    out->dim = dim;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+            if (!(hi[d] > lo[d])) return mc_fail(MC_ERR_ARG, "mesh has zero extent along axis %d", d);
+            out->dims[d] = dims[d];
+            out->origin[d] = (double)lo[d];
+            out->spacing[d] = ((double)hi[d] - (double)lo[d]) / (double)(dims[d] - 1);
+        } else {
+            out->dims[d] = 1;
+            out->origin[d] = 0.0;
+            out->spacing[d] = 1.0;
+        }
+    }
+    return MC_OK;
+}
+
+extern "C" mc_status mc_grid_from_spacing(const float* d_coords, int32_t dim, int64_t n_vertices,
+                                          const double spacing[3], hipStream_t stream, mc_grid* out)
+{
+    mc_status st = check_mesh_args(d_coords, dim, n_vertices);
+    if (st != MC_OK) return st;
+    if (!spacing || !out) return mc_fail(MC_ERR_ARG, "spacing/out pointer is NULL");
+    for (int d = 0; d < dim; ++d)
+        if (!(spacing[d] > 0.0) || !std::isfinite(spacing[d])) return mc_fail(MC_ERR_ARG, "spacing must be > 0");
+    float lo[3], hi[3];
+    if ((st = device_bbox(d_coords, dim, n_vertices, stream, lo, hi)) != MC_OK) return st;
+    memset(out, 0, sizeof *out);
+    out->dim = dim;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+            double n = std::ceil(((double)hi[d] - (double)lo[d]) / spacing[d]) + 1.0;
+            if (n < 2.0) n = 2.0;
+            if (n > 2147483647.0) return mc_fail(MC_ERR_ARG, "grid too large");
+            out->dims[d] = (int64_t)n;
+            out->origin[d] = (double)lo[d];
+            out->spacing[d] = spacing[d];
+        } else {
+            out->dims[d] = 1;
+            out->origin[d] = 0.0;
+            out->spacing[d] = 1.0;
+        }
+    }
+    return MC_OK;
+}
+
+mc_status mc_check_grid(const mc_grid* g, int32_t dim)
+{
+    if (!g) return mc_fail(MC_ERR_ARG, "grid pointer is NULL");
+    if (g->dim != dim) return mc_fail(MC_ERR_ARG, "grid dim %d does not match mesh dim %d", g->dim, dim);
+    long long ng = 1;
+    for (int d = 0; d < 3; ++d) {
+        if (d < dim) {
+            if (g->dims[d] < 2) return mc_fail(MC_ERR_ARG, "grid dims must be >= 2 on axis %d", d);
+            if (!(g->spacing[d] > 0.0) || !std::isfinite(g->spacing[d]) || !std::isfinite(g->origin[d]))
+                return mc_fail(MC_ERR_ARG, "grid spacing/origin invalid on axis %d", d);
+        } else if (g->dims[d] != 1) {
+            return mc_fail(MC_ERR_ARG, "unused grid axis %d must have dims 1", d);
+        }
+        ng *= g->dims[d];
+        if (ng >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "grid has 2^31 or more nodes");
+    }
+    if (g->dims[0] > 8192) return mc_fail(MC_ERR_UNSUPPORTED, "grid dims[0] > 8192 is not supported");
+    return MC_OK;
+}
+
+GridGeom mc_geom(const mc_grid& g)
+{
+    GridGeom gg;
+    gg.dim = g.dim;
+    gg.n0 = (int)g.dims[0];
+    gg.n1 = (int)g.dims[1];
+    gg.n2 = (int)g.dims[2];
+    for (int d = 0; d < 3; ++d) {
+        gg.of[d] = (float)g.origin[d];
+        gg.hf[d] = (float)g.spacing[d];
+        gg.ihf[d] = (float)(1.0 / g.spacing[d]);
+    }
+    return gg;
+}
+
+// ---------------------------------------------------------------------------
+// plan
+// ---------------------------------------------------------------------------
+#define PCHK(expr)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            mc_plan_destroy(p);                                                            \
+            return mc_fail(e_ == hipErrorOutOfMemory ? MC_ERR_NOMEM : MC_ERR_DEVICE, "%s: %s", \
+                           #expr, hipGetErrorString(e_));                                  \
+        }                                                                                  \
+    } while (0)
+
+static void decode_ws_shape(mc_plan p)
+{
+    const long long n0 = p->grid.dims[0], n1 = p->grid.dims[1], n2 = p->grid.dims[2];
+    long long rows = (n1 * n2) / 2048;
+    if (rows < 4) rows = 4;
+    if (rows > 64) rows = 64;
+    if (rows > n1) rows = n1;
+    p->dws.rows = (int)rows;
+    p->dws.nyc = (int)((n1 + rows - 1) / rows);
+    p->dws.nflag_xy = (long long)p->dws.nyc * n2;
+    const long long nxy = n0 * n1;
+    p->dws.nxyb = (int)((nxy + 1023) / 1024);
+    long long zp = 1;
+    if (p->dim == 3) {
+        zp = (long long)p->dws.nxyb * n2 / 2048;
+        if (zp < 2) zp = 2;
+        if (zp > 64) zp = 64;
+        if (zp > n2) zp = n2;
+    }
+    p->dws.zplanes = (int)zp;
+    p->dws.nzc = p->dim == 3 ? (int)((n2 + zp - 1) / zp) : 0;
+    p->dws.nflag_z = (long long)p->dws.nzc * p->dws.nxyb;
+}
+
+extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t n_vertices,
+                                    int64_t n_cells, const mc_grid* grid, const mc_plan_opts* opts,
+                                    hipStream_t stream, mc_plan* out)
+{
+    if (!out) return mc_fail(MC_ERR_ARG, "out pointer is NULL");
+    *out = nullptr;
+    mc_status st = check_mesh_args(d_coords, dim, n_vertices);
+    if (st != MC_OK) return st;
+    if (!d_cells) return mc_fail(MC_ERR_ARG, "cells pointer is NULL");
+    if (n_cells <= 0 || n_cells >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
+    if ((st = mc_check_grid(grid, dim)) != MC_OK) return st;
+    mc_fill fill = opts ? opts->fill : MC_FILL_NEAREST;
+    if (fill != MC_FILL_NEAREST && fill != MC_FILL_MIDRANGE) return mc_fail(MC_ERR_ARG, "unknown fill mode");
+    int B = opts && opts->bin_nodes > 0 ? opts->bin_nodes : 1;
+    if (B > 64) return mc_fail(MC_ERR_ARG, "bin_nodes must be <= 64");
+
+    mc_plan p = new mc_plan_s();
+    p->dim = dim;
+    p->nv = n_vertices;
+    p->nc = n_cells;
+    p->grid = *grid;
+    p->gg = mc_geom(*grid);
+    p->ng = grid->dims[0] * grid->dims[1] * grid->dims[2];
+    p->fill = fill;
+    p->B = B;
+    const long long ng = p->ng, nv = p->nv, nc = p->nc;
+    hipStream_t s = stream;
+
+    PCHK(plan_alloc(p, &p->coords, (size_t)dim * nv));
+    PCHK(hipMemcpyAsync(p->coords, d_coords, sizeof(float) * dim * nv, hipMemcpyDeviceToDevice, s));
+    PCHK(plan_alloc(p, &p->vid, (size_t)(dim + 1) * ng));
+    PCHK(plan_alloc(p, &p->w, (size_t)(dim + 1) * ng));
+    PCHK(plan_alloc(p, &p->cell, (size_t)ng));
+
+    {
+        TempAllocs ta;
+        hipError_t e = hipSuccess;
+        const int nb0 = (int)((grid->dims[0] + B - 1) / B), nb1 = (int)((grid->dims[1] + B - 1) / B),
+                  nb2 = (int)((grid->dims[2] + B - 1) / B);
+        const long long nbins = (long long)nb0 * nb1 * nb2;
+        unsigned* cnt = ta.get<unsigned>(nbins + 4, e);
+        PCHK(e);
+        unsigned* ctr = ta.get<unsigned>(16, e);     // [0] bad cells, [1] unresolved, [2] near-degenerate, [3] ticket
+        PCHK(e);
+        long long* start = ta.get<long long>(nbins + 1, e);
+        PCHK(e);
+        const long long nscan_tiles = (nbins + MC_TILE - 1) / MC_TILE + 1;
+        unsigned long long* sst = ta.get<unsigned long long>(nscan_tiles, e);
+        PCHK(e);
+        PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+        PCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 16, s));
+        PCHK(hipMemsetAsync(sst, 0, sizeof(unsigned long long) * nscan_tiles, s));
+        PCHK(mck::bins_count(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
+                             cnt, ctr + 0, s));
+        PCHK(mck::scan_u32(cnt, nbins, start, sst, ctr + 3, s));
+        long long total = 0;
+        unsigned hctr[16];
+        PCHK(hipMemcpyAsync(&total, start + nbins, sizeof total, hipMemcpyDeviceToHost, s));
+        PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
+        PCHK(hipStreamSynchronize(s));
+        if (hctr[0] != 0) {
+            p->invalid_cells = (int)hctr[0];
+            mc_plan_destroy(p);
+            return mc_fail(MC_ERR_ARG, "%u cells reference a vertex id outside [0, n_vertices)", hctr[0]);
+        }
+        p->n_pairs = total;
+        int32_t* list = ta.get<int32_t>((size_t)total + 1, e);
+        PCHK(e);
+        PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+        PCHK(mck::bins_fill(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
+                            start, cnt, list, s));
+        int32_t* unres = ta.get<int32_t>((size_t)ng, e);
+        PCHK(e);
+        PCHK(mck::locate(p->coords, d_cells, dim, nv, nc, p->gg, B, nb0, nb1, start, list, p->vid, p->w, p->cell,
+                         unres, ctr + 1, ctr + 2, s));
+        PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
+        PCHK(hipStreamSynchronize(s));
+        p->n_unresolved = hctr[1];
+        p->n_near_degenerate = hctr[2];
+        if (p->n_unresolved > 0) {
+            if (fill == MC_FILL_MIDRANGE) {
+                PCHK(mck::fill_midrange(dim, unres, p->n_unresolved, p->vid, p->w, ng, s));
+            } else {
+                const int VB = dim == 2 ? 4 : 2;
+                const int vb0 = (int)((grid->dims[0] + VB - 1) / VB), vb1 = (int)((grid->dims[1] + VB - 1) / VB),
+                          vb2 = dim == 3 ? (int)((grid->dims[2] + VB - 1) / VB) : 1;
+                const long long nvb = (long long)vb0 * vb1 * vb2;
+                unsigned* vcnt = ta.get<unsigned>(nvb + 4, e);
+                PCHK(e);
+                long long* vstart = ta.get<long long>(nvb + 1, e);
+                PCHK(e);
+                const long long vtiles = (nvb + MC_TILE - 1) / MC_TILE + 1;
+                unsigned long long* vst = ta.get<unsigned long long>(vtiles, e);
+                PCHK(e);
+                int32_t* vlist = ta.get<int32_t>((size_t)nv, e);
+                PCHK(e);
+                PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
+                PCHK(hipMemsetAsync(vst, 0, sizeof(unsigned long long) * vtiles, s));
+                PCHK(hipMemsetAsync(ctr + 4, 0, sizeof(unsigned), s));
+                PCHK(mck::vbins_count(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vcnt, s));
+                PCHK(mck::scan_u32(vcnt, nvb, vstart, vst, ctr + 4, s));
+                PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
+                PCHK(mck::vbins_fill(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vstart, vcnt,
+                                     vlist, s));
+                PCHK(mck::fill_nearest(p->coords, dim, nv, p->gg, grid->origin, grid->spacing, VB, vb0, vb1, vb2,
+                                       vstart, vlist, unres, p->n_unresolved, p->vid, p->w, ng, s));
+            }
+        }
+        PCHK(hipStreamSynchronize(s));
+    }
+
+    // compress / decompress workspace
+    p->ntg = (ng + MC_TILE - 1) / MC_TILE;
+    p->ntv = (nv + MC_TILE - 1) / MC_TILE;
+    p->range_blocks = 1024;
+    PCHK(plan_alloc(p, &p->p, (size_t)ng));
+    PCHK(plan_alloc(p, &p->rho, (size_t)nv));
+    PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * p->range_blocks));
+    PCHK(plan_alloc(p, &p->ctl, 64));
+    p->range = (RangeOut*)p->ctl;
+    p->done = (unsigned*)(p->ctl + 4);
+    p->err = (unsigned*)(p->ctl + 5);
+    p->tickets = (unsigned*)(p->ctl + 8);   // 8 tickets
+    PCHK(plan_alloc(p, &p->st, (size_t)(p->ntg + p->ntv)));
+    PCHK(hipMemsetAsync(p->ctl, 0, 64 * sizeof(unsigned long long), s));
+    decode_ws_shape(p);
+    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.nflag_xy * grid->dims[0]));
+    PCHK(plan_alloc(p, &p->dws.incl_xy, (size_t)p->dws.nflag_xy * grid->dims[0]));
+    PCHK(plan_alloc(p, &p->dec_flags, (size_t)(p->dws.nflag_xy + p->dws.nflag_z + 2)));
+    p->dws.flag_xy = p->dec_flags;
+    p->dws.flag_z = p->dec_flags + p->dws.nflag_xy;
+    p->dws.tickets = p->dec_flags + p->dws.nflag_xy + p->dws.nflag_z;
+    if (dim == 3) {
+        PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nflag_z * 1024));
+        PCHK(plan_alloc(p, &p->dws.incl_z, (size_t)p->dws.nflag_z * 1024));
+    }
+    PCHK(hipStreamSynchronize(s));
+    *out = p;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_get_info(mc_plan p, mc_plan_info* out)
+{
+    if (!p || !out) return mc_fail(MC_ERR_ARG, "plan/out is NULL");
+    out->n_grid = p->ng;
+    out->n_vertices = p->nv;
+    out->n_cells = p->nc;
+    out->n_unresolved = p->n_unresolved;
+    out->n_near_degenerate = p->n_near_degenerate;
+    out->n_pairs = p->n_pairs;
+    out->bin_nodes = p->B;
+    out->device_bytes = (int64_t)p->bytes;
+    out->invalid_cells = p->invalid_cells;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_get_grid(mc_plan p, mc_grid* out)
+{
+    if (!p || !out) return mc_fail(MC_ERR_ARG, "plan/out is NULL");
+    *out = p->grid;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_mapping(mc_plan p, int32_t* d_vid, float* d_w, int32_t* d_cell, hipStream_t s)
+{
+    if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    const size_t k = (size_t)(p->dim + 1) * p->ng;
+    hipError_t e = hipSuccess;
+    if (d_vid && e == hipSuccess) e = hipMemcpyAsync(d_vid, p->vid, k * 4, hipMemcpyDeviceToDevice, s);
+    if (d_w && e == hipSuccess) e = hipMemcpyAsync(d_w, p->w, k * 4, hipMemcpyDeviceToDevice, s);
+    if (d_cell && e == hipSuccess) e = hipMemcpyAsync(d_cell, p->cell, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mapping copy: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_destroy(mc_plan p)
+{
+    if (!p) return MC_OK;
+    for (void* q : p->allocs) hipFree(q);
+    delete p;
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// compress / decompress
+// ---------------------------------------------------------------------------
+static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
+{
+    if (!c) return mc_fail(MC_ERR_ARG, "codes pointer is NULL");
+    if (!c->grid_codes || !c->vert_codes || !c->result) return mc_fail(MC_ERR_ARG, "codes buffers are NULL");
+    if (c->g_out_cap < 0 || c->v_out_cap < 0) return mc_fail(MC_ERR_ARG, "negative outlier capacity");
+    if (c->g_out_cap > 0 && (!c->g_out_idx || !c->g_out_delta)) return mc_fail(MC_ERR_ARG, "grid outlier buffers are NULL");
+    if (c->v_out_cap > 0 && (!c->v_out_idx || !c->v_out_val)) return mc_fail(MC_ERR_ARG, "vertex outlier buffers are NULL");
+    if (need_flags && !c->block_flags) return mc_fail(MC_ERR_ARG, "block_flags is required with a model");
+    (void)p;
+    return MC_OK;
+}
+
+mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
+                              const mc_codes* codes, hipStream_t s)
+{
+    const long long nbf = (p->ntv + 31) / 32;
+    BoundParams bp;
+    bp.eb = prm->eb;
+    bp.split = prm->grid_share;
+    bp.relative = prm->eb_mode == MC_EB_REL;
+    bp.pad = 0;
+    hipError_t e;
+#define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
+    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, p->range_blocks, p->done, p->range, p->st,
+                    p->ntg + p->ntv, p->tickets, 8, p->err, s));
+    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->range, bp, p->p, codes->dbg_resampled,
+                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, s));
+    ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
+                      codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, p->st, p->tickets + 0,
+                      p->err, codes->result, s));
+    const int32_t* rho = nullptr;
+    if (prm->model) {
+        mc_status ms = mc_model_infer(prm->model, p, codes->result, nullptr, s);
+        if (ms != MC_OK) return ms;
+        rho = p->rho;
+    }
+    ECHK(mck::residual(p->coords, p->nv, p->gg, p->p, d_field, dtype, p->range, bp, rho, codes->vert_codes,
+                       codes->v_out_idx, codes->v_out_val, codes->v_out_cap, codes->block_flags, codes->dbg_vertex_g,
+                       p->st + p->ntg, p->tickets + 1, p->err, codes->result, s));
+    if (codes->dbg_grid_p) ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+    if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
+#undef ECHK
+    return MC_OK;
+}
+
+mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm, const mc_codes* codes)
+{
+    if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (!d_field) return mc_fail(MC_ERR_ARG, "field pointer is NULL");
+    if (dtype != MC_F32 && dtype != MC_F64) return mc_fail(MC_ERR_ARG, "dtype must be MC_F32 or MC_F64");
+    if (!prm) return mc_fail(MC_ERR_ARG, "params pointer is NULL");
+    if (!(prm->eb > 0.0) || !std::isfinite(prm->eb)) return mc_fail(MC_ERR_ARG, "eb must be finite and > 0");
+    if (prm->eb_mode != MC_EB_ABS && prm->eb_mode != MC_EB_REL) return mc_fail(MC_ERR_ARG, "unknown eb_mode");
+    if (!(prm->grid_share > 0.0) || !(prm->grid_share < 1.0)) return mc_fail(MC_ERR_ARG, "grid_share must be in (0, 1)");
+    if (prm->model && mc_model_dim(prm->model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
+    return check_codes(p, codes, prm->model != nullptr);
+}
+
+extern "C" mc_status mc_compress(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
+                                 const mc_codes* codes, hipStream_t s)
+{
+    mc_status st = mc_check_params(p, d_field, dtype, prm, codes);
+    if (st != MC_OK) return st;
+    return mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
+}
+
+extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
+                                   hipStream_t s)
+{
+    if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (!d_out) return mc_fail(MC_ERR_ARG, "output pointer is NULL");
+    if (dtype != MC_F32 && dtype != MC_F64) return mc_fail(MC_ERR_ARG, "dtype must be MC_F32 or MC_F64");
+    if (model && mc_model_dim(model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
+    mc_status st = check_codes(p, codes, model != nullptr);
+    if (st != MC_OK) return st;
+    hipError_t e;
+#define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
+    ECHK(mck::zero_u32(p->dec_flags, p->dws.nflag_xy + p->dws.nflag_z + 2, s));
+    ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
+                          p->dim,
+                          (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->dws, s));
+    const int32_t* rho = nullptr;
+    if (model) {
+        mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);
+        if (ms != MC_OK) return ms;
+        rho = p->rho;
+    }
+    ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->p, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
+                            codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, s));
+#undef ECHK
+    return MC_OK;
+}
+
+extern "C" mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t nv, int64_t nc,
+                                      const void* d_field, mc_dtype dtype, const double spacing[3], double eb,
+                                      int32_t eb_mode, double grid_share, const mc_codes* codes, mc_grid* grid_out,
+                                      hipStream_t s)
+{
+    mc_grid g;
+    mc_status st = mc_grid_from_spacing(d_coords, dim, nv, spacing, s, &g);
+    if (st != MC_OK) return st;
+    mc_plan p = nullptr;
+    if ((st = mc_plan_create(d_coords, d_cells, dim, nv, nc, &g, nullptr, s, &p)) != MC_OK) return st;
+    mc_params prm;
+    prm.eb = eb;
+    prm.eb_mode = eb_mode;
+    prm.grid_share = grid_share;
+    prm.model = nullptr;
+    st = mc_compress(p, d_field, dtype, &prm, codes, s);
+    if (st == MC_OK && hipStreamSynchronize(s) != hipSuccess) st = mc_fail(MC_ERR_DEVICE, "synchronize failed");
+    mc_plan_destroy(p);
+    if (st == MC_OK && grid_out) *grid_out = g;
+    return st;
+}

@@ -1,0 +1,251 @@
+// mc_dev.h -- device helpers shared by the gfx950 kernels: grid geometry,
+// error-bound split, ordered block compaction (wave ballots + a workgroup
+// scan) and decoupled look-back over tiles taken in ticket order.
+//
+// Every bit-exact formula is written as parenthesised and compiled with
+// -ffp-contract=off (and the pragma below), so each + - * / is one IEEE
+// round-to-nearest-even operation; rint() rounds half to even.
+#pragma once
+#pragma clang fp contract(off)
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define MC_R 32768
+#define MC_TILE 4096          // items per workgroup tile (256 threads x 16)
+#define MC_WG 256
+#define MC_IPT 16             // items per thread in a tile
+
+// error bits accumulated in the workspace while a compress call runs
+#define MC_EBIT_NONFINITE 1u
+#define MC_EBIT_RANGE 2u
+#define MC_EBIT_GCAP 4u
+#define MC_EBIT_VCAP 8u
+#define MC_EBIT_TAU 16u
+
+struct GridGeom {
+    int dim;
+    int n0, n1, n2;           // n2 = 1 in 2-D
+    float of[3], hf[3], ihf[3];   // (float)origin, (float)spacing, (float)(1/spacing)
+};
+
+// Field range in ordered-integer keys (min/max are exact and order-free).
+struct RangeOut {
+    unsigned long long kmin, kmax;
+    unsigned int flags;
+    unsigned int pad;
+};
+
+struct BoundParams {
+    double eb;
+    double split;
+    int relative;
+    int pad;
+};
+
+struct DevBound {
+    double tau, tau1, tau2, c, xmin, xmax, inv1, step1, inv2, step2;
+    int ok;
+};
+
+__device__ __forceinline__ unsigned long long dkey(double d)
+{
+    unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    if (d == 0.0) b = 0ull;                       // -0 and +0 are one key
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double dkey_inv(unsigned long long k)
+{
+    unsigned long long b = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// tau = eb * (xmax - xmin) or eb; tau1 = split * tau; tau2 = tau - tau1;
+// c = 0.5 * (xmin + xmax); step_k = 2 tau_k, inv_k = 1 / (2 tau_k).
+__device__ __forceinline__ DevBound make_bound(const RangeOut* r, BoundParams bp)
+{
+    DevBound b;
+    double mn = dkey_inv(r->kmin), mx = dkey_inv(r->kmax);
+    b.xmin = mn;
+    b.xmax = mx;
+    b.tau = bp.relative ? bp.eb * (mx - mn) : bp.eb;
+    b.tau1 = bp.split * b.tau;
+    b.tau2 = b.tau - b.tau1;
+    b.c = 0.5 * (mn + mx);
+    b.step1 = 2.0 * b.tau1;
+    b.inv1 = 1.0 / (2.0 * b.tau1);
+    b.step2 = 2.0 * b.tau2;
+    b.inv2 = 1.0 / (2.0 * b.tau2);
+    b.ok = !(r->flags & MC_EBIT_NONFINITE) && (b.tau1 > 0.0) && (b.tau2 > 0.0);
+    return b;
+}
+
+template <typename T> __device__ __forceinline__ double as_double(T v) { return (double)v; }
+template <typename T> __device__ __forceinline__ float as_float(T v) { return (float)v; }
+
+// Reconstructed grid value x1' = (float)(c + (double)p * step1).
+__device__ __forceinline__ float xhat_of(int32_t p, double c, double step1)
+{
+    return (float)(c + (double)p * step1);
+}
+
+__device__ __forceinline__ float lerpf_(float a, float b, float t)
+{
+    return (1.0f - t) * a + t * b;
+}
+
+// Grid cell and in-cell offset of a vertex coordinate along one axis:
+// u = (P - of) * ihf, i = clamp(floor(u), 0, n-2), t = clamp(u - i, 0, 1).
+__device__ __forceinline__ void axis_cell(float P, float of, float ihf, int n, int& i, float& t)
+{
+    float u = (P - of) * ihf;
+    float fl = floorf(u);
+    if (fl < 0.0f) i = 0;
+    else if (fl > (float)(n - 2)) i = n - 2;
+    else i = (int)fl;
+    float tt = u - (float)i;
+    if (tt < 0.0f) tt = 0.0f;
+    if (tt > 1.0f) tt = 1.0f;
+    t = tt;
+}
+
+// ---------------------------------------------------------------------------
+// wave / workgroup primitives (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ int mbcnt64(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+template <typename T> __device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T o = __shfl_up(v, d, 64);
+        if (l >= d) v += o;
+    }
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+// Ordered compaction of a 4096-item tile: item (i, t) of thread t is at
+// tile offset i*256 + t.  Returns each flagged item's exclusive rank in
+// index order and the tile total.  s_cnt needs MC_IPT*4 ints of LDS.
+__device__ __forceinline__ int tile_ranks(const bool (&flag)[MC_IPT], int (&rank)[MC_IPT], int* s_cnt)
+{
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    unsigned long long ball[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        ball[i] = __ballot(flag[i]);
+        if (l == 0) s_cnt[i * 4 + w] = __popcll(ball[i]);
+    }
+    __syncthreads();
+    if (w == 0) {
+        int v = s_cnt[l];                  // MC_IPT * 4 == 64 entries
+        int inc = wave_incl_scan(v);
+        s_cnt[l] = inc - v;
+        if (l == 63) s_cnt[64] = inc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) rank[i] = s_cnt[i * 4 + w] + mbcnt64(ball[i]);
+    int total = s_cnt[64];
+    return total;
+}
+
+// Block-wide sum of an int64 (256 threads); s needs 4 slots.
+__device__ __forceinline__ long long block_sum_i64(long long v, long long* s)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    long long t = s[0] + s[1] + s[2] + s[3];
+    __syncthreads();
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// decoupled look-back over tiles (scalar payload in the status word)
+// status word: bits 62..63 flag (1 = tile aggregate, 2 = inclusive prefix),
+// bits 0..61 value.  Tiles are numbered by an atomic ticket, so a tile only
+// waits on tiles that started earlier: every wait ends.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void lb_store(unsigned long long* st, long long tile, unsigned long long flag,
+                                         unsigned long long val)
+{
+    __hip_atomic_store(&st[tile], (flag << 62) | val, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ unsigned long long lb_exclusive(unsigned long long* st, long long tile)
+{
+    unsigned long long excl = 0;
+    long long k = tile - 1;
+    while (k >= 0) {
+        unsigned long long s = __hip_atomic_load(&st[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long f = s >> 62;
+        if (f == 0) {
+            __builtin_amdgcn_s_sleep(1);
+            continue;
+        }
+        excl += s & 0x3fffffffffffffffull;
+        if (f == 2) break;
+        --k;
+    }
+    return excl;
+}
+
+// Takes the next tile ticket; every thread of the block gets it.
+__device__ __forceinline__ long long take_ticket(unsigned int* counter, long long* s_slot)
+{
+    if (threadIdx.x == 0) *s_slot = (long long)atomicAdd(counter, 1u);
+    __syncthreads();
+    long long t = *s_slot;
+    __syncthreads();
+    return t;
+}
+
+// Publishes this tile's value (a count, or several counts packed in one
+// word) and returns the exclusive prefix over all earlier tiles (thread 0
+// does the look-back; the result is broadcast through LDS).
+__device__ __forceinline__ unsigned long long tile_prefix(unsigned long long* st, long long tile,
+                                                          unsigned long long val, long long* s_slot)
+{
+    if (threadIdx.x == 0) {
+        unsigned long long excl = 0;
+        if (tile == 0) {
+            lb_store(st, 0, 2ull, val);
+        } else {
+            lb_store(st, tile, 1ull, val);
+            excl = lb_exclusive(st, tile);
+            lb_store(st, tile, 2ull, excl + val);
+        }
+        *s_slot = (long long)excl;
+    }
+    __syncthreads();
+    unsigned long long e = (unsigned long long)*s_slot;
+    __syncthreads();
+    return e;
+}
+
+// Final status of a compress call from the accumulated error bits.
+__device__ __forceinline__ int status_from_bits(unsigned int e)
+{
+    if (e & (MC_EBIT_NONFINITE | MC_EBIT_TAU)) return 1;
+    if (e & MC_EBIT_RANGE) return 2;
+    if (e & (MC_EBIT_GCAP | MC_EBIT_VCAP)) return 3;
+    return 0;
+}

@@ -1,0 +1,57 @@
+// mc_internal.h -- host-side objects behind the opaque handles of mc.h.
+#pragma once
+#include <vector>
+
+#include "mc_kernels.h"
+
+struct mc_plan_s {
+    int dim = 0;
+    long long nv = 0, nc = 0, ng = 0;
+    mc_grid grid{};
+    GridGeom gg{};
+    int fill = 0;
+    int B = 1;
+    // mapping (device)
+    float* coords = nullptr;       // [dim][nv] copy
+    int32_t* vid = nullptr;        // [dim+1][ng]
+    float* w = nullptr;            // [dim+1][ng]
+    int32_t* cell = nullptr;       // [ng]
+    // workspace (device)
+    int32_t* p = nullptr;          // prequantised grid [ng]
+    int32_t* rho = nullptr;        // learned shift [nv]
+    unsigned long long* range_partial = nullptr;
+    int range_blocks = 0;
+    unsigned long long* ctl = nullptr;   // 64 words: range, counters, tickets
+    RangeOut* range = nullptr;
+    unsigned* done = nullptr;
+    unsigned* err = nullptr;
+    unsigned* tickets = nullptr;
+    unsigned long long* st = nullptr;    // look-back status [ntg + ntv]
+    long long ntg = 0, ntv = 0;
+    unsigned* dec_flags = nullptr;
+    mck::DecodeWs dws{};
+    // statistics
+    long long n_unresolved = 0, n_near_degenerate = 0, n_pairs = 0;
+    int invalid_cells = 0;
+    size_t bytes = 0;
+    std::vector<void*> allocs;
+};
+
+struct mc_model_s {
+    int dim = 0, kin = 0, kpad = 0;
+    float kappa = 1.0f;
+    std::vector<float> params;     // host FP32 master copy
+    void* dev = nullptr;           // packed device weights (bf16 + fp32 biases)
+    mck::MlpDev md{};
+};
+
+mc_status mc_fail(mc_status s, const char* fmt, ...);
+mc_status mc_check_grid(const mc_grid* g, int32_t dim);
+GridGeom mc_geom(const mc_grid& g);
+mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
+                          const mc_codes* codes);
+mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
+                              const mc_codes* codes, hipStream_t s);
+int mc_model_dim(mc_model m);
+// rho_q for every vertex (only_blocks == NULL) or the learned blocks only.
+mc_status mc_model_infer(mc_model m, mc_plan p, const mc_result* res, const uint32_t* only_blocks, hipStream_t s);

@@ -1,0 +1,111 @@
+// mc_kernels.h -- internal interface between the host API (mc_api.hip) and
+// the kernel files.  Launchers enqueue on the given stream and return the
+// HIP error of the launch.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mc.h"
+#include "mc_dev.h"
+
+namespace mck {
+
+// ---- profiling hook (mc_api.hip) -------------------------------------------
+struct ProfScope {
+    const char* name;
+    hipStream_t stream;
+    int idx;
+    ProfScope(const char* n, hipStream_t s);
+    ~ProfScope();
+};
+
+// ---- plan construction (k_plan.hip) ---------------------------------------
+hipError_t bbox(const float* coords, int dim, long long nv, unsigned int* keys /*[6]*/, hipStream_t s);
+hipError_t bins_count(const float* coords, const int32_t* cells, int dim, long long nv, long long nc,
+                      GridGeom gg, const double* o, const double* h, int B, int nb0, int nb1, int nb2,
+                      unsigned int* bin_count, unsigned int* bad_cells, hipStream_t s);
+hipError_t bins_fill(const float* coords, const int32_t* cells, int dim, long long nv, long long nc,
+                     GridGeom gg, const double* o, const double* h, int B, int nb0, int nb1, int nb2,
+                     const long long* bin_start, unsigned int* cursor, int32_t* list, hipStream_t s);
+hipError_t scan_u32(const unsigned int* in, long long n, long long* out /*[n+1]*/, unsigned long long* st,
+                    unsigned int* ticket, hipStream_t s);
+hipError_t locate(const float* coords, const int32_t* cells, int dim, long long nv, long long nc, GridGeom gg,
+                  int B, int nb0, int nb1, const long long* bin_start, const int32_t* list,
+                  int32_t* vid, float* w, int32_t* cell, int32_t* unres, unsigned int* n_unres,
+                  unsigned int* n_neardeg, hipStream_t s);
+hipError_t vbins_count(const float* coords, int dim, long long nv, const double* o, const double* h, int VB,
+                       int nb0, int nb1, int nb2, unsigned int* cnt, hipStream_t s);
+hipError_t vbins_fill(const float* coords, int dim, long long nv, const double* o, const double* h, int VB,
+                      int nb0, int nb1, int nb2, const long long* start, unsigned int* cursor, int32_t* list,
+                      hipStream_t s);
+hipError_t fill_nearest(const float* coords, int dim, long long nv, GridGeom gg, const double* o,
+                        const double* h, int VB, int nb0, int nb1, int nb2, const long long* vstart,
+                        const int32_t* vlist, const int32_t* unres, long long n_unres, int32_t* vid, float* w,
+                        long long ng, hipStream_t s);
+hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32_t* vid, float* w, long long ng,
+                         hipStream_t s);
+
+// ---- compression (k_compress.hip) -----------------------------------------
+hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, int nblocks,
+                 unsigned int* done, RangeOut* out, unsigned long long* zero_a, long long nzero_a,
+                 unsigned int* zero_b, long long nzero_b, unsigned int* err, hipStream_t s);
+hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
+                    const RangeOut* range, BoundParams bp, int32_t* p, float* dbg_v, uint32_t* bflags,
+                    long long nbflags, unsigned int* err, mc_result* res, hipStream_t s);
+hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
+                   int32_t* oidx, int32_t* odelta, long long cap, unsigned long long* st, unsigned int* ticket,
+                   unsigned int* err, mc_result* res, hipStream_t s);
+hipError_t residual(const float* coords, long long nv, GridGeom gg, const int32_t* p, const void* x, int dtype,
+                    const RangeOut* range, BoundParams bp, const int32_t* rho_q, uint16_t* codes, int32_t* oidx,
+                    void* oval, long long cap, uint32_t* bflags, float* dbg_g, unsigned long long* st,
+                    unsigned int* ticket, unsigned int* err, mc_result* res, hipStream_t s);
+
+// ---- decompression (k_decode.hip) -----------------------------------------
+struct DecodeWs {
+    int rows, nyc;                 // xy pass: rows per chunk, chunks per plane
+    int* agg_xy; int* incl_xy; unsigned int* flag_xy;
+    int zplanes, nzc, nxyb;        // z pass (3-D)
+    int* agg_z; int* incl_z; unsigned int* flag_z;
+    unsigned int* tickets;         // [2]
+    long long nflag_xy, nflag_z;
+};
+hipError_t zero_u32(unsigned int* a, long long n, hipStream_t s);
+hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
+                       const mc_result* res, int dim, int n0, int n1, int n2, int32_t* p, const DecodeWs& ws, hipStream_t s);
+hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const int32_t* p, const uint16_t* codes,
+                         const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
+                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, hipStream_t s);
+
+// ---- learned predictor (k_mlp.hip) ----------------------------------------
+struct MlpDev {
+    int dim, kin, kpad;
+    float kappa;
+    const uint16_t* w1;   // bf16 [64][kpad] (output-major, zero padded)
+    const uint16_t* w2;   // bf16 [64][64]
+    const uint16_t* w3;   // bf16 [64][64]
+    const uint16_t* w4;   // bf16 [64]
+    const float* b1; const float* b2; const float* b3; const float* b4;
+};
+hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, uint16_t* w3, uint16_t* w4,
+                    float* b1, float* b2, float* b3, float* b4, hipStream_t s);
+hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
+                     const mc_result* res, const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s);
+hipError_t mlp_features(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
+                        const mc_result* res, long long v0, long long count, float* z, hipStream_t s);
+hipError_t mlp_forward_z(const MlpDev& m, const float* z, long long batch, float* rho, hipStream_t s);
+hipError_t mlp_feature_sumsq(const float* coords, long long nv, GridGeom gg, const int32_t* p,
+                             const mc_result* res, int dim, double* partial, int nblocks, hipStream_t s);
+// training
+struct TrainWs {
+    float* params; float* m; float* v; float* grad_part; float* grad; float* loss_part;
+    int nparts;
+};
+hipError_t train_step_grad(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
+                           const mc_result* res, const float* z_given, const float* y_given, const void* x,
+                           int dtype, long long batch, unsigned long long seed, long long step, float* grad_part,
+                           float* loss_part, int nparts, hipStream_t s);
+hipError_t train_reduce_adam(int nparams, int nparts, const float* grad_part, const float* loss_part, float* grad,
+                             float* loss_out, float* params, float* m, float* v, long long t, float lr, int apply,
+                             hipStream_t s);
+
+}  // namespace mck

@@ -1,0 +1,529 @@
+"""Python binding of libmc (include/mc.h): argument marshalling only.
+
+Every step of the compressor runs in the HIP library; torch provides device
+memory (tensor storage) and the stream (``torch.cuda.current_stream()``).
+Loading fails loudly if the library has not been built -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmc.so")
+
+OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY, ERR_NOMEM, ERR_DEVICE, ERR_FORMAT, ERR_UNSUPPORTED = range(8)
+F32, F64 = 0, 1
+EB_ABS, EB_REL = 0, 1
+FILL_NEAREST, FILL_MIDRANGE = 0, 1
+RADIUS = 32768
+BLOCK = 4096
+
+
+class McGrid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("dims", C.c_int64 * 3), ("origin", C.c_double * 3),
+                ("spacing", C.c_double * 3)]
+
+
+class McPlanOpts(C.Structure):
+    _fields_ = [("fill", C.c_int), ("bin_nodes", C.c_int32)]
+
+
+class McPlanInfo(C.Structure):
+    _fields_ = [("n_grid", C.c_int64), ("n_vertices", C.c_int64), ("n_cells", C.c_int64),
+                ("n_unresolved", C.c_int64), ("n_near_degenerate", C.c_int64), ("n_pairs", C.c_int64),
+                ("bin_nodes", C.c_int64), ("device_bytes", C.c_int64), ("invalid_cells", C.c_int32)]
+
+
+class McParams(C.Structure):
+    _fields_ = [("eb", C.c_double), ("eb_mode", C.c_int32), ("grid_share", C.c_double),
+                ("model", C.c_void_p)]
+
+
+class McResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("dtype", C.c_int32), ("n_grid_outliers", C.c_int64),
+                ("n_vertex_outliers", C.c_int64), ("n_learned_blocks", C.c_int64),
+                ("tau", C.c_double), ("tau1", C.c_double), ("tau2", C.c_double), ("c", C.c_double),
+                ("xmin", C.c_double), ("xmax", C.c_double), ("kappa_unused", C.c_double)]
+
+
+class McCodes(C.Structure):
+    _fields_ = [("grid_codes", C.c_void_p), ("g_out_idx", C.c_void_p), ("g_out_delta", C.c_void_p),
+                ("g_out_cap", C.c_int64), ("vert_codes", C.c_void_p), ("v_out_idx", C.c_void_p),
+                ("v_out_val", C.c_void_p), ("v_out_cap", C.c_int64), ("block_flags", C.c_void_p),
+                ("result", C.c_void_p), ("dbg_resampled", C.c_void_p), ("dbg_grid_p", C.c_void_p),
+                ("dbg_vertex_g", C.c_void_p), ("rho_q", C.c_void_p)]
+
+
+class McTrainOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64),
+                ("h_loss_out", C.c_void_p)]
+
+
+class McBatchItem(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("d_field", C.c_void_p), ("dtype", C.c_int), ("params", McParams),
+                ("codes", McCodes)]
+
+
+# every symbol include/mc.h declares, with its ctypes signature
+_P = C.c_void_p
+_SIGS = {
+    "mc_status_string": (C.c_char_p, [C.c_int]),
+    "mc_last_error": (C.c_char_p, []),
+    "mc_abi_version": (C.c_int32, []),
+    "mc_grid_from_dims": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "mc_grid_from_spacing": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "mc_plan_create": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, _P, _P, _P]),
+    "mc_plan_get_info": (C.c_int, [_P, _P]),
+    "mc_plan_mapping": (C.c_int, [_P, _P, _P, _P, _P]),
+    "mc_plan_get_grid": (C.c_int, [_P, _P]),
+    "mc_plan_destroy": (C.c_int, [_P]),
+    "mc_compress": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
+    "mc_decompress": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+    "mc_compress_mesh": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, C.c_int, _P, C.c_double,
+                                   C.c_int32, C.c_double, _P, _P, _P]),
+    "mc_model_param_count": (C.c_int64, [C.c_int32]),
+    "mc_model_create": (C.c_int, [C.c_int32, _P, C.c_float, _P]),
+    "mc_model_train": (C.c_int, [_P, _P, C.c_int, _P, _P, _P, _P]),
+    "mc_model_get_params": (C.c_int, [_P, _P, _P]),
+    "mc_model_export": (C.c_int, [_P, _P, C.c_size_t, _P]),
+    "mc_model_import": (C.c_int, [_P, C.c_size_t, _P]),
+    "mc_model_destroy": (C.c_int, [_P]),
+    "mc_model_forward": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+    "mc_model_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
+    "mc_model_features": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P]),
+    "mc_batch_compress": (C.c_int, [_P, C.c_int32, _P]),
+    "mc_profile_enable": (C.c_int, [C.c_int32]),
+    "mc_profile_reset": (C.c_int, []),
+    "mc_profile_read": (C.c_int32, [_P, _P, _P, C.c_int32]),
+    "mc_huffman_size": (C.c_int64, [_P, C.c_int64]),
+    "mc_huffman_encode": (C.c_int64, [_P, C.c_int64, _P, C.c_int64]),
+    "mc_huffman_decode": (C.c_int64, [_P, C.c_int64, _P, C.c_int64]),
+    "mc_entropy_bits": (C.c_double, [_P, C.c_int64]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded libmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2501_06910_amd.build` (no CPU fallback exists)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class McError(RuntimeError):
+    def __init__(self, status, where=""):
+        msg = lib().mc_last_error().decode()
+        super().__init__(f"{where}: {lib().mc_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _check(st, where):
+    if st != OK:
+        raise McError(st, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError("field must be float32 or float64")
+
+
+def _require_cuda(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+
+
+# ---------------------------------------------------------------------------
+# grids and plans
+# ---------------------------------------------------------------------------
+
+def grid_from_dims(coords, dims) -> McGrid:
+    torch = _torch()
+    _require_cuda(coords, "coords", torch.float32)
+    g = McGrid()
+    d = (C.c_int64 * 3)(*(list(dims) + [1] * (3 - len(dims))))
+    _check(lib().mc_grid_from_dims(_ptr(coords), coords.shape[0], coords.shape[1], d, _stream(),
+                                   C.byref(g)), "mc_grid_from_dims")
+    return g
+
+
+def grid_from_spacing(coords, spacing) -> McGrid:
+    torch = _torch()
+    _require_cuda(coords, "coords", torch.float32)
+    g = McGrid()
+    h = (C.c_double * 3)(*(list(spacing) + [1.0] * (3 - len(spacing))))
+    _check(lib().mc_grid_from_spacing(_ptr(coords), coords.shape[0], coords.shape[1], h, _stream(),
+                                      C.byref(g)), "mc_grid_from_spacing")
+    return g
+
+
+def make_grid(dim, dims, origin, spacing) -> McGrid:
+    g = McGrid()
+    g.dim = dim
+    for d in range(3):
+        g.dims[d] = dims[d] if d < dim else 1
+        g.origin[d] = origin[d] if d < dim else 0.0
+        g.spacing[d] = spacing[d] if d < dim else 1.0
+    return g
+
+
+class Plan:
+    """Field-independent mesh-grid mapping (owns device memory)."""
+
+    def __init__(self, coords, cells, grid: McGrid | None = None, dims=None, fill: str = "nearest",
+                 bin_nodes: int = 0):
+        torch = _torch()
+        _require_cuda(coords, "coords", torch.float32)
+        _require_cuda(cells, "cells", torch.int32)
+        self.dim = int(coords.shape[0])
+        if grid is None:
+            grid = grid_from_dims(coords, dims)
+        self.grid = grid
+        opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, bin_nodes)
+        h = C.c_void_p()
+        _check(lib().mc_plan_create(_ptr(coords), _ptr(cells), self.dim, coords.shape[1], cells.shape[1],
+                                    C.byref(grid), C.byref(opts), _stream(), C.byref(h)), "mc_plan_create")
+        self.handle = h
+        self.n_vertices = int(coords.shape[1])
+        self.n_grid = int(grid.dims[0] * grid.dims[1] * grid.dims[2])
+
+    def info(self) -> dict:
+        i = McPlanInfo()
+        _check(lib().mc_plan_get_info(self.handle, C.byref(i)), "mc_plan_get_info")
+        return {k: getattr(i, k) for k, _ in McPlanInfo._fields_}
+
+    def mapping(self):
+        torch = _torch()
+        vid = torch.empty((self.dim + 1, self.n_grid), dtype=torch.int32, device="cuda")
+        w = torch.empty((self.dim + 1, self.n_grid), dtype=torch.float32, device="cuda")
+        cell = torch.empty(self.n_grid, dtype=torch.int32, device="cuda")
+        _check(lib().mc_plan_mapping(self.handle, _ptr(vid), _ptr(w), _ptr(cell), _stream()), "mc_plan_mapping")
+        return vid, w, cell
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().mc_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# compressed buffers
+# ---------------------------------------------------------------------------
+
+class Codes:
+    """Device buffers of one compressed field (allocated with torch)."""
+
+    def __init__(self, plan: Plan, dtype, g_cap=None, v_cap=None, learned=False, debug=False):
+        torch = _torch()
+        ng, nv = plan.n_grid, plan.n_vertices
+        g_cap = ng if g_cap is None else g_cap
+        v_cap = nv if v_cap is None else v_cap
+        dev = "cuda"
+        self.dtype = dtype
+        self.grid_codes = torch.empty(ng, dtype=torch.uint16, device=dev)
+        self.g_out_idx = torch.empty(max(g_cap, 1), dtype=torch.int32, device=dev)
+        self.g_out_delta = torch.empty(max(g_cap, 1), dtype=torch.int32, device=dev)
+        self.vert_codes = torch.empty(nv, dtype=torch.uint16, device=dev)
+        self.v_out_idx = torch.empty(max(v_cap, 1), dtype=torch.int32, device=dev)
+        self.v_out_val = torch.empty(max(v_cap, 1), dtype=dtype, device=dev)
+        nblocks = (nv + BLOCK - 1) // BLOCK
+        self.block_flags = torch.zeros((nblocks + 31) // 32, dtype=torch.int32, device=dev)
+        self.result = torch.zeros(C.sizeof(McResult), dtype=torch.uint8, device=dev)
+        self.dbg = debug
+        self.dbg_resampled = torch.empty(ng, dtype=torch.float32, device=dev) if debug else None
+        self.dbg_grid_p = torch.empty(ng, dtype=torch.int32, device=dev) if debug else None
+        self.dbg_vertex_g = torch.empty(nv, dtype=torch.float32, device=dev) if debug else None
+        self.rho_q = torch.empty(nv, dtype=torch.int32, device=dev) if (debug and learned) else None
+        self.struct = McCodes(
+            _ptr(self.grid_codes), _ptr(self.g_out_idx), _ptr(self.g_out_delta), g_cap, _ptr(self.vert_codes),
+            _ptr(self.v_out_idx), _ptr(self.v_out_val), v_cap, _ptr(self.block_flags), _ptr(self.result),
+            _ptr(self.dbg_resampled), _ptr(self.dbg_grid_p), _ptr(self.dbg_vertex_g), _ptr(self.rho_q))
+
+    def result_host(self) -> dict:
+        b = self.result.cpu().numpy().tobytes()
+        r = McResult.from_buffer_copy(b)
+        return {k: getattr(r, k) for k, _ in McResult._fields_}
+
+    def host(self) -> dict:
+        """Host copies of the compressed representation (synchronises)."""
+        r = self.result_host()
+        ng_out, nv_out = r["n_grid_outliers"], r["n_vertex_outliers"]
+        return dict(
+            result=r,
+            grid_codes=self.grid_codes.cpu().numpy().view(np.uint16),
+            g_out_idx=self.g_out_idx[:ng_out].cpu().numpy(),
+            g_out_delta=self.g_out_delta[:ng_out].cpu().numpy(),
+            vert_codes=self.vert_codes.cpu().numpy().view(np.uint16),
+            v_out_idx=self.v_out_idx[:nv_out].cpu().numpy(),
+            v_out_val=self.v_out_val[:nv_out].cpu().numpy(),
+            block_flags=self.block_flags.cpu().numpy().view(np.uint32),
+        )
+
+
+def compress(plan: Plan, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None,
+             codes: Codes | None = None, debug: bool = False) -> Codes:
+    _require_cuda(field, "field")
+    if codes is None:
+        codes = Codes(plan, field.dtype, learned=model is not None, debug=debug)
+    prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
+                   None if model is None else model.handle)
+    _check(lib().mc_compress(plan.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
+                             _stream()), "mc_compress")
+    return codes
+
+
+def decompress(plan: Plan, codes: Codes, model=None, out=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(plan.n_vertices, dtype=codes.dtype, device="cuda")
+    _check(lib().mc_decompress(plan.handle, C.byref(codes.struct), None if model is None else model.handle,
+                               _ptr(out), _dtype_code(out), _stream()), "mc_decompress")
+    return out
+
+
+def compress_mesh(coords, cells, field, spacing, eb, eb_mode="rel", grid_share=0.5):
+    """One-shot form: plan built and released inside the call."""
+    torch = _torch()
+    g = McGrid()
+    h = (C.c_double * 3)(*(list(spacing) + [1.0] * (3 - len(spacing))))
+    # grid first, to size the buffers
+    grid = grid_from_spacing(coords, spacing)
+    ng = int(grid.dims[0] * grid.dims[1] * grid.dims[2])
+
+    class _Shape:
+        n_grid = ng
+        n_vertices = int(coords.shape[1])
+    codes = Codes(_Shape, field.dtype)
+    _check(lib().mc_compress_mesh(_ptr(coords), _ptr(cells), coords.shape[0], coords.shape[1], cells.shape[1],
+                                  _ptr(field), _dtype_code(field), h, eb, EB_REL if eb_mode == "rel" else EB_ABS,
+                                  grid_share, C.byref(codes.struct), C.byref(g), _stream()), "mc_compress_mesh")
+    return codes, g
+
+
+# ---------------------------------------------------------------------------
+# learned predictor
+# ---------------------------------------------------------------------------
+
+def param_count(dim: int) -> int:
+    return int(lib().mc_model_param_count(dim))
+
+
+class Model:
+    def __init__(self, handle, dim):
+        self.handle = handle
+        self.dim = dim
+
+    @classmethod
+    def create(cls, dim: int, params: np.ndarray, kappa: float):
+        p = np.ascontiguousarray(params, np.float32)
+        h = C.c_void_p()
+        _check(lib().mc_model_create(dim, p.ctypes.data, kappa, C.byref(h)), "mc_model_create")
+        return cls(h, dim)
+
+    @classmethod
+    def train(cls, plan: Plan, field, eb=1e-4, eb_mode="rel", grid_share=0.5, steps=2000, batch=8192,
+              lr=1e-3, seed=0, return_loss=False):
+        prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share, None)
+        loss = np.zeros(steps, np.float32)
+        opts = McTrainOpts(steps, batch, lr, seed, loss.ctypes.data)
+        h = C.c_void_p()
+        _check(lib().mc_model_train(plan.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(opts),
+                                    _stream(), C.byref(h)), "mc_model_train")
+        m = cls(h, plan.dim)
+        return (m, loss) if return_loss else m
+
+    def params(self):
+        n = param_count(self.dim)
+        p = np.empty(n, np.float32)
+        k = C.c_float()
+        _check(lib().mc_model_get_params(self.handle, p.ctypes.data, C.byref(k)), "mc_model_get_params")
+        return p, float(k.value)
+
+    def export(self) -> bytes:
+        n = C.c_size_t()
+        _check(lib().mc_model_export(self.handle, None, 0, C.byref(n)), "mc_model_export")
+        buf = (C.c_char * n.value)()
+        _check(lib().mc_model_export(self.handle, buf, n.value, C.byref(n)), "mc_model_export")
+        return bytes(buf)
+
+    @classmethod
+    def load(cls, blob: bytes):
+        h = C.c_void_p()
+        _check(lib().mc_model_import(blob, len(blob), C.byref(h)), "mc_model_import")
+        return cls(h, int.from_bytes(blob[8:12], "little"))
+
+    def forward(self, z):
+        torch = _torch()
+        _require_cuda(z, "z", torch.float32)
+        rho = torch.empty(z.shape[0], dtype=torch.float32, device="cuda")
+        _check(lib().mc_model_forward(self.handle, _ptr(z), z.shape[0], _ptr(rho), _stream()), "mc_model_forward")
+        return rho
+
+    def loss_grad(self, z, y):
+        torch = _torch()
+        g = torch.empty(param_count(self.dim), dtype=torch.float32, device="cuda")
+        loss = torch.empty(1, dtype=torch.float32, device="cuda")
+        _check(lib().mc_model_loss_grad(self.handle, _ptr(z), _ptr(y), z.shape[0], _ptr(g), _ptr(loss), _stream()),
+               "mc_model_loss_grad")
+        return float(loss.item()), g
+
+    def features(self, plan: Plan, codes: Codes, v0=0, count=None):
+        torch = _torch()
+        count = plan.n_vertices - v0 if count is None else count
+        kpad = 32 if self.dim == 2 else 96
+        z = torch.empty((count, kpad), dtype=torch.float32, device="cuda")
+        _check(lib().mc_model_features(self.handle, plan.handle, C.byref(codes.struct), v0, count, _ptr(z),
+                                       _stream()), "mc_model_features")
+        return z
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().mc_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batching, profiling, entropy stage
+# ---------------------------------------------------------------------------
+
+def batch_compress(items):
+    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes)."""
+    arr = (McBatchItem * len(items))()
+    for i, (plan, field, eb, mode, share, model, codes) in enumerate(items):
+        arr[i].plan = plan.handle
+        arr[i].d_field = field.data_ptr()
+        arr[i].dtype = _dtype_code(field)
+        arr[i].params = McParams(eb, EB_REL if mode == "rel" else EB_ABS, share,
+                                 None if model is None else model.handle)
+        arr[i].codes = codes.struct
+    _check(lib().mc_batch_compress(arr, len(items), _stream()), "mc_batch_compress")
+
+
+def profile_enable(on=True):
+    lib().mc_profile_enable(1 if on else 0)
+
+
+def profile_reset():
+    lib().mc_profile_reset()
+
+
+def profile_read() -> dict:
+    cap = 64
+    names = (C.c_char_p * cap)()
+    counts = (C.c_int64 * cap)()
+    ms = (C.c_double * cap)()
+    n = lib().mc_profile_read(names, counts, ms, cap)
+    return {names[i].decode(): (int(counts[i]), float(ms[i])) for i in range(n)}
+
+
+def huffman_size(sym: np.ndarray) -> int:
+    s = np.ascontiguousarray(sym, np.uint16)
+    return int(lib().mc_huffman_size(s.ctypes.data, s.size))
+
+
+def huffman_encode(sym: np.ndarray) -> bytes:
+    s = np.ascontiguousarray(sym, np.uint16)
+    cap = huffman_size(s)
+    out = np.empty(cap, np.uint8)
+    n = lib().mc_huffman_encode(s.ctypes.data, s.size, out.ctypes.data, cap)
+    if n < 0:
+        raise RuntimeError("huffman encode failed")
+    return out[:n].tobytes()
+
+
+def huffman_decode(blob: bytes, n: int) -> np.ndarray:
+    out = np.empty(n, np.uint16)
+    buf = np.frombuffer(blob, np.uint8)
+    used = lib().mc_huffman_decode(buf.ctypes.data, buf.size, out.ctypes.data, n)
+    if used < 0:
+        raise ValueError("malformed Huffman stream")
+    return out
+
+
+def entropy_bits(sym: np.ndarray) -> float:
+    s = np.ascontiguousarray(sym, np.uint16)
+    return float(lib().mc_entropy_bits(s.ctypes.data, s.size))
+
+
+def _leb128_bytes(values: np.ndarray) -> int:
+    v = np.asarray(values, np.uint64)
+    n = np.ones(v.size, np.int64)
+    t = v >> np.uint64(7)
+    while np.any(t):
+        n += (t > 0)
+        t = t >> np.uint64(7)
+    return int(n.sum())
+
+
+HEADER_BYTES = 64
+
+
+def stream_bytes(host: dict, value_bytes: int, model_bytes: int = 0) -> dict:
+    """Size of the self-describing stream: header, Huffman-coded grid and
+    vertex codes, outlier lists (LEB128 index gaps + payloads), block flags
+    and the (amortised) model bytes."""
+    gi = host["g_out_idx"].astype(np.int64)
+    vi = host["v_out_idx"].astype(np.int64)
+    g_gap = np.diff(np.concatenate([[-1], gi])) - 1 if gi.size else gi
+    v_gap = np.diff(np.concatenate([[-1], vi])) - 1 if vi.size else vi
+    zz = lambda d: ((d.astype(np.int64) << 1) ^ (d.astype(np.int64) >> 63)).astype(np.uint64)
+    parts = dict(
+        header=HEADER_BYTES,
+        grid=huffman_size(host["grid_codes"]),
+        vert=huffman_size(host["vert_codes"]),
+        grid_outliers=_leb128_bytes(g_gap) + _leb128_bytes(zz(host["g_out_delta"])),
+        vert_outliers=_leb128_bytes(v_gap) + vi.size * value_bytes,
+        block_flags=host["block_flags"].size * 4 if host.get("learned") else 0,
+        model=model_bytes,
+    )
+    parts["total"] = sum(parts.values())
+    return parts
