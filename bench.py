@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the multi-component mesh compressor on one MI355X.
+
+A step is one pass of the whole hot path over one field: compress (range,
+resample + prequantise, Lorenzo codes, back-interpolation + residual codes)
+then decompress (grid decode, vertex decode).  The default workload is the
+16M-vertex tetrahedral mesh: a 252^3 jittered lattice with 6 Kuhn tets per
+cube, a float32 three-octave field, a 256^3 grid, relative eb 1e-4 and a
+50/50 split.  ``value`` is GB/s of mesh values (n_v * 4 bytes) per step.
+
+Prints one JSON line (see the design doc for every field).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
+    """Compulsory HBM bytes of one launch of each kernel (outliers ignored)."""
+    table = {
+        "k_range": nv * sT,
+        "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 4,
+        "k_lorenzo": ng * 4 + ng * 2,
+        "k_residual": nv * (4 * D + sT + 2) + ng * 4,
+        "k_residual_learned": nv * (4 * D + sT + 2 + 4) + ng * 4,
+        "k_dec_xy": ng * 2 + ng * 4,
+        "k_dec_z": ng * 8,
+        "k_vdecode": nv * (4 * D + 2 + sT) + ng * 4,
+        "k_vdecode_learned": nv * (4 * D + 2 + sT + 4) + ng * 4,
+    }
+    return table.get(kernel, 0)
+
+
+def method_bytes(nv: int, ng: int, D: int, sT: int):
+    """Algorithmic bytes of compress and decompress with the plan cached."""
+    bc = nv * sT + ng * 8 * (D + 1) + nv * sT + ng * 6 + nv * 4 * D + nv * sT + ng * 4 + nv * 2
+    bd = ng * 2 + ng * 8 + nv * (4 * D + 2 + sT)
+    return bc, bd
+
+
+def workload(name: str):
+    import meshgen as G
+    if name == "tet3d":
+        mesh, f, cfg = G.config_tet_3d()
+        desc = ("tet3d: 252^3 jittered lattice (+-20% of the spacing), 6 Kuhn tetrahedra per cube "
+                "(16,003,008 vertices, 94,879,506 tets); float32 three-octave sinusoid field; "
+                "256^3 grid; relative eb 1e-4; grid share 0.5")
+    elif name == "tet3d_small":
+        mesh, f, cfg = G.config_tet_3d(n=64, dims=65)
+        desc = "tet3d_small: 64^3 jittered Kuhn lattice, float32 field, 65^3 grid, relative eb 1e-4"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return mesh, f, cfg, desc
+
+
+def cpu_baseline(eb: float, split: float, min_seconds: float = 10.0, n: int = 96):
+    """The oracle (single thread) on a bounded sample of the same workload:
+    a C3-style n^3 lattice with a proportional grid; plan excluded, as the
+    paper excludes the mapping from its cost."""
+    import meshgen as G
+    import oracle as O
+    mesh, f, cfg = G.config_tet_3d(n=n, dims=int(round(n * 256 / 252)), eb=eb, split=split)
+    g = O.grid_from_dims(mesh.coords, cfg["dims"])
+    m = O.locate(mesh.coords, mesh.cells, g, "raster", fill="midrange")
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        cz = O.compress(mesh.coords, m, g, f, eb, True, split)
+        O.decompress(mesh.coords, g, cz.bound, cz.grid, cz.vert, f.dtype)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds:
+            break
+    gbps = mesh.n_vertices * 4 * reps / el / 1e9
+    return {"value": round(gbps, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n}^3 jittered Kuhn lattice ({mesh.n_vertices} vertices, {mesh.n_cells} tets), "
+                      f"grid {cfg['dims'][0]}^3, same field recipe/eb/split (mid-range fill of unlocated nodes); "
+                      f"compress+decompress x{reps} "
+                      f"in {el:.1f} s, one thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="tet3d")
+    ap.add_argument("--eb", type=float, default=1e-4)
+    ap.add_argument("--split", type=float, default=0.5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(the multi-GPU decomposition is described in DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_2501_06910_amd import mc as M
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    mesh, f, cfg, desc = workload(args.workload)
+    log(f"workload generated in {time.time() - t0:.1f} s: nv={mesh.n_vertices} nc={mesh.n_cells}")
+    D, nv = mesh.dim, mesh.n_vertices
+    sT = f.dtype.itemsize
+    coords = torch.from_numpy(mesh.coords).cuda()
+    cells = torch.from_numpy(mesh.cells).cuda()
+    x = torch.from_numpy(f).cuda()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plan = M.Plan(coords, cells, dims=cfg["dims"][:D])
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    del cells
+    info = plan.info()
+    ng = plan.n_grid
+    log(f"plan built in {plan_s:.2f} s: {info}")
+
+    codes = M.Codes(plan, x.dtype)
+    out = torch.empty_like(x)
+
+    def step():
+        M.compress(plan, x, args.eb, "rel", args.split, codes=codes)
+        M.decompress(plan, codes, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    res = codes.result_host()
+    if res["status"] != 0:
+        raise SystemExit(f"compress status {res['status']}")
+    err = (x.double() - out.double()).abs().max().item()
+    if not err <= res["tau2"]:
+        raise SystemExit(f"bound violated: {err} > {res['tau2']}")
+    log(f"warmup ok: max |x - x'| = {err:.3e} <= tau2 = {res['tau2']:.3e}")
+
+    # timed region: K steps, no per-kernel events
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
+
+    # per-kernel durations: HIP events around each launch on its stream
+    M.profile_reset()
+    M.profile_enable(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    M.profile_enable(False)
+    prof = M.profile_read()
+    kernels = {}
+    comp_ms = dec_ms = 0.0
+    for name, (cnt, tot) in prof.items():
+        avg = tot / cnt
+        b = alg_bytes(name, nv, ng, D, sT)
+        kernels[name] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": b,
+                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+        if name in ("k_range", "k_resample", "k_lorenzo", "k_residual", "k_residual_learned"):
+            comp_ms += avg
+        elif name in ("k_zero", "k_dec_xy", "k_dec_z", "k_vdecode", "k_vdecode_learned"):
+            dec_ms += avg
+    dom = max((k for k in kernels if kernels[k]["alg_bytes"]), key=lambda k: kernels[k]["avg_ms"])
+    dk = kernels[dom]
+    achieved = dk["alg_bytes"] / (dk["avg_ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_ms": dk["avg_ms"]}
+
+    bc, bd = method_bytes(nv, ng, D, sT)
+    h = codes.host()
+    sb = M.stream_bytes(h, sT)
+    cr = nv * sT / sb["total"]
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        bb = torch.empty_like(a)
+        for _ in range(3):
+            bb.copy_(a)
+        torch.cuda.synchronize()
+
+    value = nv * sT / (ms_step * 1e-3) / 1e9
+    line = {
+        "metric": "compress/decompress GB/s of mesh values + CR, learned vs plain, eb=1e-4",
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": desc, "n_vertices": nv, "n_cells": mesh.n_cells, "n_grid": ng,
+                   "eb": args.eb, "eb_mode": "rel", "grid_share": args.split},
+        "roofline": roofline,
+        "compress_GBps": round(nv * sT / (comp_ms * 1e-3) / 1e9, 2),
+        "decompress_GBps": round(nv * sT / (dec_ms * 1e-3) / 1e9, 2),
+        "compress_ms": round(comp_ms, 4),
+        "decompress_ms": round(dec_ms, 4),
+        "alg_bytes_compress": bc,
+        "alg_bytes_decompress": bd,
+        "hbm_frac_alg": round((bc + bd) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "cr": round(cr, 3),
+        "stream_bytes": sb,
+        "outliers": {"grid": h["result"]["n_grid_outliers"], "vertex": h["result"]["n_vertex_outliers"]},
+        "max_abs_err_over_tau": round(err / res["tau"], 4),
+        "plan_seconds": round(plan_s, 3),
+        "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle, one thread) ...")
+        line["cpu_baseline"] = cpu_baseline(args.eb, args.split)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
