@@ -24,19 +24,48 @@ HBM_PEAK_GBPS = 8000.0
 
 
 def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
-    """Compulsory HBM bytes of one launch of each kernel (outliers ignored)."""
+    """Compulsory HBM bytes of one launch of each kernel (outliers ignored):
+    each array the kernel must read or write, once."""
     table = {
-        "k_range": nv * sT,
-        "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 4,
-        "k_lorenzo": ng * 4 + ng * 2,
-        "k_residual": nv * (4 * D + sT + 2) + ng * 4,
+        "k_range": nv * sT,                                        # field
+        "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 8,         # mapping, field, p + x1' out
+        "k_lorenzo": ng * 4 + ng * 2,                              # p in, codes out
+        "k_learned_cost": nv * (4 * D + sT + 4) + ng * 4,          # coords, field, rho_q, x1'
+        "k_residual": nv * (4 * D + sT + 2) + ng * 4,              # coords, field, codes out, x1'
         "k_residual_learned": nv * (4 * D + sT + 2 + 4) + ng * 4,
-        "k_dec_xy": ng * 2 + ng * 4,
-        "k_dec_z": ng * 8,
-        "k_vdecode": nv * (4 * D + 2 + sT) + ng * 4,
+        "k_dec_xy_tot": ng * 2,                                    # 2-D: codes
+        "k_dec_z_tot": ng * 2,                                     # 3-D: codes
+        "k_dec_z_apply": ng * 2 + ng * 4,                          # codes in, z-prefixed errors out
+        "k_dec_xy_apply": (ng * 4 if D == 3 else ng * 2) + ng * 4,  # errors in, x1' out
+        "k_vdecode": nv * (4 * D + 2 + sT) + ng * 4,               # coords, codes, field out, x1'
         "k_vdecode_learned": nv * (4 * D + 2 + sT + 4) + ng * 4,
     }
     return table.get(kernel, 0)
+
+
+COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_residual", "k_scan_counts",
+                     "k_scatter", "k_mlp_infer_c")
+DECOMPRESS_PREFIXES = ("k_dec_", "k_vdecode", "k_mlp_infer_d")
+
+
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs,
+    or None when the kernel sources changed since they were taken."""
+    import glob
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "tet3d_16M_pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = b"".join(open(p, "rb").read()
+                   for p in sorted(glob.glob(os.path.join(here, "paper_2501_06910_amd", "csrc", "*"))))
+    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    for name, v in rec["kernels"].items():
+        if name.split("<")[0] == kernel:
+            return v["traffic_bytes"]
+    return None
 
 
 def method_bytes(nv: int, ng: int, D: int, sT: int):
@@ -171,15 +200,16 @@ def main():
         b = alg_bytes(name, nv, ng, D, sT)
         kernels[name] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": b,
                          "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
-        if name in ("k_range", "k_resample", "k_lorenzo", "k_residual", "k_residual_learned"):
+        if name.startswith(COMPRESS_PREFIXES):
             comp_ms += avg
-        elif name in ("k_zero", "k_dec_xy", "k_dec_z", "k_vdecode", "k_vdecode_learned"):
+        elif name.startswith(DECOMPRESS_PREFIXES):
             dec_ms += avg
     dom = max((k for k in kernels if kernels[k]["alg_bytes"]), key=lambda k: kernels[k]["avg_ms"])
     dk = kernels[dom]
     achieved = dk["alg_bytes"] / (dk["avg_ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                "traffic": pmc_traffic(dom) if args.workload == "tet3d" else None,
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_ms": dk["avg_ms"]}
 
     bc, bd = method_bytes(nv, ng, D, sT)

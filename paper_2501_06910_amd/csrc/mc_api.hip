@@ -78,7 +78,7 @@ mck::ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), id
     std::lock_guard<std::mutex> lk(g_pm);
     hipEvent_t a = pool_get(), b = pool_get();
     if (!a || !b) return;
-    hipEventRecord(a, s);
+    (void)hipEventRecord(a, s);
     idx = (int)g_recs.size();
     g_recs.push_back({n, a, b});
 }
@@ -87,7 +87,7 @@ mck::ProfScope::~ProfScope()
 {
     if (idx < 0) return;
     std::lock_guard<std::mutex> lk(g_pm);
-    hipEventRecord(g_recs[idx].b, stream);
+    (void)hipEventRecord(g_recs[idx].b, stream);
 }
 
 namespace {
@@ -101,9 +101,9 @@ std::vector<ProfAgg> g_agg;
 void prof_drain()
 {
     for (auto& r : g_recs) {
-        hipEventSynchronize(r.b);
+        (void)hipEventSynchronize(r.b);
         float ms = 0.f;
-        hipEventElapsedTime(&ms, r.a, r.b);
+        (void)hipEventElapsedTime(&ms, r.a, r.b);
         bool found = false;
         for (auto& a : g_agg)
             if (strcmp(a.name, r.name) == 0) { a.count++; a.ms += ms; found = true; break; }
@@ -152,7 +152,7 @@ struct TempAllocs {
     std::vector<void*> ptrs;
     ~TempAllocs()
     {
-        for (void* p : ptrs) hipFree(p);
+        for (void* p : ptrs) (void)hipFree(p);
     }
     template <typename T> T* get(size_t n, hipError_t& err)
     {
@@ -318,25 +318,30 @@ GridGeom mc_geom(const mc_grid& g)
 static void decode_ws_shape(mc_plan p)
 {
     const long long n0 = p->grid.dims[0], n1 = p->grid.dims[1], n2 = p->grid.dims[2];
-    long long rows = (n1 * n2) / 2048;
-    if (rows < 4) rows = 4;
-    if (rows > 64) rows = 64;
+    long long rows;
+    if (p->dim == 2) {
+        rows = (n1 + 1023) / 1024;          // about 1024 wave tiles
+        if (rows < 4) rows = 4;
+    } else {
+        long long cx = 1;                     // columns per thread of the z pass, as instantiated
+        while (cx * 256 < n0) cx *= 2;
+        rows = 32 / cx;                       // registers of the z pass: rows * cx <= 32
+        if (rows > 16) rows = 16;
+    }
     if (rows > n1) rows = n1;
+    if (rows < 1) rows = 1;
     p->dws.rows = (int)rows;
     p->dws.nyc = (int)((n1 + rows - 1) / rows);
-    p->dws.nflag_xy = (long long)p->dws.nyc * n2;
-    const long long nxy = n0 * n1;
-    p->dws.nxyb = (int)((nxy + 1023) / 1024);
-    long long zp = 1;
+    p->dws.ntiles_xy = (long long)p->dws.nyc * n2;
+    p->dws.zplanes = 1;
+    p->dws.nzc = 0;
     if (p->dim == 3) {
-        zp = (long long)p->dws.nxyb * n2 / 2048;
-        if (zp < 2) zp = 2;
-        if (zp > 64) zp = 64;
-        if (zp > n2) zp = n2;
+        long long nzc = (1024 + p->dws.nyc - 1) / p->dws.nyc;    // about 1024 workgroup tiles
+        if (nzc > n2) nzc = n2;
+        const long long zp = (n2 + nzc - 1) / nzc;
+        p->dws.zplanes = (int)zp;
+        p->dws.nzc = (int)((n2 + zp - 1) / zp);
     }
-    p->dws.zplanes = (int)zp;
-    p->dws.nzc = p->dim == 3 ? (int)((n2 + zp - 1) / zp) : 0;
-    p->dws.nflag_z = (long long)p->dws.nzc * p->dws.nxyb;
 }
 
 extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t n_vertices,
@@ -453,28 +458,32 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     // compress / decompress workspace
     p->ntg = (ng + MC_TILE - 1) / MC_TILE;
     p->ntv = (nv + MC_TILE - 1) / MC_TILE;
-    p->range_blocks = 1024;
+    p->nblk = (nv + MC_LBLOCK - 1) / MC_LBLOCK;
     PCHK(plan_alloc(p, &p->p, (size_t)ng));
     PCHK(plan_alloc(p, &p->rho, (size_t)nv));
-    PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * p->range_blocks));
     PCHK(plan_alloc(p, &p->ctl, 64));
-    p->range = (RangeOut*)p->ctl;
-    p->done = (unsigned*)(p->ctl + 4);
-    p->err = (unsigned*)(p->ctl + 5);
-    p->tickets = (unsigned*)(p->ctl + 8);   // 8 tickets
-    PCHK(plan_alloc(p, &p->st, (size_t)(p->ntg + p->ntv)));
-    PCHK(hipMemsetAsync(p->ctl, 0, 64 * sizeof(unsigned long long), s));
-    decode_ws_shape(p);
-    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.nflag_xy * grid->dims[0]));
-    PCHK(plan_alloc(p, &p->dws.incl_xy, (size_t)p->dws.nflag_xy * grid->dims[0]));
-    PCHK(plan_alloc(p, &p->dec_flags, (size_t)(p->dws.nflag_xy + p->dws.nflag_z + 2)));
-    p->dws.flag_xy = p->dec_flags;
-    p->dws.flag_z = p->dec_flags + p->dws.nflag_xy;
-    p->dws.tickets = p->dec_flags + p->dws.nflag_xy + p->dws.nflag_z;
-    if (dim == 3) {
-        PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nflag_z * 1024));
-        PCHK(plan_alloc(p, &p->dws.incl_z, (size_t)p->dws.nflag_z * 1024));
+    p->rbuf = (RangeOut*)p->ctl;                       // 2 slots of 3 words
+    {
+        RangeOut init[2];
+        for (int k = 0; k < 2; ++k) { init[k].kmin = ~0ull; init[k].kmax = 0ull; init[k].flags = 0u; init[k].pad = 0u; }
+        PCHK(hipMemsetAsync(p->ctl, 0, 64 * sizeof(unsigned long long), s));
+        PCHK(hipMemcpyAsync(p->rbuf, init, sizeof init, hipMemcpyHostToDevice, s));
     }
+    p->nsmall = 16 + 2 * p->nblk;
+    PCHK(plan_alloc(p, &p->small, (size_t)p->nsmall));
+    PCHK(hipMemsetAsync(p->small, 0, (size_t)p->nsmall * 4, s));
+    p->err = p->small + 2;
+    p->bcost = p->small + 16;
+    PCHK(plan_alloc(p, &p->counts, (size_t)2 * (p->ntg + p->ntv)));
+    p->gcount = p->counts;
+    p->vcount = p->counts + p->ntg;
+    p->goff = p->counts + p->ntg + p->ntv;
+    p->voff = p->goff + p->ntg;
+    decode_ws_shape(p);
+    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * grid->dims[0]));
+    if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * grid->dims[0] * grid->dims[1]));
+    PCHK(plan_alloc(p, &p->xh, (size_t)ng));
+    PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * 1024));
     PCHK(hipStreamSynchronize(s));
     *out = p;
     return MC_OK;
@@ -517,7 +526,7 @@ extern "C" mc_status mc_plan_mapping(mc_plan p, int32_t* d_vid, float* d_w, int3
 extern "C" mc_status mc_plan_destroy(mc_plan p)
 {
     if (!p) return MC_OK;
-    for (void* q : p->allocs) hipFree(q);
+    for (void* q : p->allocs) (void)hipFree(q);
     delete p;
     return MC_OK;
 }
@@ -540,7 +549,7 @@ static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
 mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
                               const mc_codes* codes, hipStream_t s)
 {
-    const long long nbf = (p->ntv + 31) / 32;
+    const long long nbf = (p->nblk + 31) / 32;
     BoundParams bp;
     bp.eb = prm->eb;
     bp.split = prm->grid_share;
@@ -548,22 +557,24 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     bp.pad = 0;
     hipError_t e;
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
-    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, p->range_blocks, p->done, p->range, p->st,
-                    p->ntg + p->ntv, p->tickets, 8, p->err, s));
-    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->range, bp, p->p, codes->dbg_resampled,
+    RangeOut* cur = p->rbuf;
+    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, p->small, p->nsmall, s));
+    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, cur, bp, p->p, p->xh, codes->dbg_resampled,
                        codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, s));
     ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
-                      codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, p->st, p->tickets + 0,
-                      p->err, codes->result, s));
+                      codes->grid_codes, p->gcount, s));
     const int32_t* rho = nullptr;
     if (prm->model) {
         mc_status ms = mc_model_infer(prm->model, p, codes->result, nullptr, s);
         if (ms != MC_OK) return ms;
         rho = p->rho;
     }
-    ECHK(mck::residual(p->coords, p->nv, p->gg, p->p, d_field, dtype, p->range, bp, rho, codes->vert_codes,
-                       codes->v_out_idx, codes->v_out_val, codes->v_out_cap, codes->block_flags, codes->dbg_vertex_g,
-                       p->st + p->ntg, p->tickets + 1, p->err, codes->result, s));
+    ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, cur, bp, rho, p->bcost, codes->vert_codes,
+                       codes->block_flags, codes->dbg_vertex_g, p->vcount, s));
+    ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes, p->gcount,
+                      p->goff, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
+                      codes->vert_codes, p->vcount, p->voff, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
+                      p->err, codes->result, s));
     if (codes->dbg_grid_p) ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
 #undef ECHK
@@ -602,17 +613,16 @@ extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model mo
     if (st != MC_OK) return st;
     hipError_t e;
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
-    ECHK(mck::zero_u32(p->dec_flags, p->dws.nflag_xy + p->dws.nflag_z + 2, s));
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
-                          p->dim,
-                          (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->dws, s));
+                          p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
+                          p->dws, s));
     const int32_t* rho = nullptr;
     if (model) {
         mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);
         if (ms != MC_OK) return ms;
         rho = p->rho;
     }
-    ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->p, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
+    ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
                             codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, s));
 #undef ECHK
     return MC_OK;

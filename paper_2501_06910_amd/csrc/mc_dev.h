@@ -12,9 +12,10 @@
 #include <stdint.h>
 
 #define MC_R 32768
-#define MC_TILE 4096          // items per workgroup tile (256 threads x 16)
+#define MC_TILE 1024          // items per workgroup tile (256 threads x 4)
 #define MC_WG 256
-#define MC_IPT 16             // items per thread in a tile
+#define MC_IPT 4              // items per thread in a tile
+#define MC_LBLOCK 4096        // vertices per learned/plain decision block
 
 // error bits accumulated in the workspace while a compress call runs
 #define MC_EBIT_NONFINITE 1u
@@ -110,6 +111,17 @@ __device__ __forceinline__ void axis_cell(float P, float of, float ihf, int n, i
     t = tt;
 }
 
+// XCD-aware tile order.  Workgroups are handed to the 8 XCDs round-robin
+// (block b runs on XCD b % 8); renumbering them so that XCD x processes a
+// contiguous range of tiles keeps neighbouring tiles -- and the grid planes,
+// rows and field values they share -- in one XCD's L2.  A bijection on
+// [0, n).
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
+{
+    const unsigned per = n >> 3, rem = n & 7u, x = b & 7u, r = b >> 3;
+    return (x < rem ? x * (per + 1u) : rem * (per + 1u) + (x - rem) * per) + r;
+}
+
 // ---------------------------------------------------------------------------
 // wave / workgroup primitives (wave64)
 // ---------------------------------------------------------------------------
@@ -140,9 +152,9 @@ template <typename T> __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
-// Ordered compaction of a 4096-item tile: item (i, t) of thread t is at
-// tile offset i*256 + t.  Returns each flagged item's exclusive rank in
-// index order and the tile total.  s_cnt needs MC_IPT*4 ints of LDS.
+// Ordered compaction of a tile: item (i, t) of thread t is at tile offset
+// i*256 + t.  Returns each flagged item's exclusive rank in index order and
+// the tile total.  s_cnt needs MC_IPT*4 + 1 ints of LDS.
 __device__ __forceinline__ int tile_ranks(const bool (&flag)[MC_IPT], int (&rank)[MC_IPT], int* s_cnt)
 {
     const int l = lane_id(), w = threadIdx.x >> 6;
@@ -154,16 +166,15 @@ __device__ __forceinline__ int tile_ranks(const bool (&flag)[MC_IPT], int (&rank
     }
     __syncthreads();
     if (w == 0) {
-        int v = s_cnt[l];                  // MC_IPT * 4 == 64 entries
-        int inc = wave_incl_scan(v);
-        s_cnt[l] = inc - v;
-        if (l == 63) s_cnt[64] = inc;
+        const int v = l < MC_IPT * 4 ? s_cnt[l] : 0;
+        const int inc = wave_incl_scan(v);
+        if (l < MC_IPT * 4) s_cnt[l] = inc - v;
+        if (l == 63) s_cnt[MC_IPT * 4] = inc;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) rank[i] = s_cnt[i * 4 + w] + mbcnt64(ball[i]);
-    int total = s_cnt[64];
-    return total;
+    return s_cnt[MC_IPT * 4];
 }
 
 // Block-wide sum of an int64 (256 threads); s needs 4 slots.
@@ -248,4 +259,41 @@ __device__ __forceinline__ int status_from_bits(unsigned int e)
     if (e & MC_EBIT_RANGE) return 2;
     if (e & (MC_EBIT_GCAP | MC_EBIT_VCAP)) return 3;
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// epoch-tagged status words for look-back with one word per element: bits
+// 62..63 flag (1 aggregate, 2 inclusive), bits 32..61 the call's epoch,
+// bits 0..31 the value.  A word from an earlier call carries another epoch
+// and reads as "not ready", so the arrays never need clearing.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long ep_word(unsigned flag, unsigned epoch, int v)
+{
+    return ((unsigned long long)flag << 62) | ((unsigned long long)(epoch & 0x3fffffffu) << 32) |
+           (unsigned long long)(unsigned)v;
+}
+
+__device__ __forceinline__ void ep_store(unsigned long long* a, unsigned long long w)
+{
+    __hip_atomic_store(a, w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Spins until the word carries this epoch; returns it.
+__device__ __forceinline__ unsigned long long ep_wait(unsigned long long* a, unsigned epoch)
+{
+    unsigned long long w;
+    for (;;) {
+        w = __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((w >> 62) != 0 && (unsigned)((w >> 32) & 0x3fffffffu) == (epoch & 0x3fffffffu)) return w;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Per-wave ticket from a monotonic 64-bit counter: tile = ticket - base.
+__device__ __forceinline__ long long wave_ticket(unsigned long long* counter, unsigned long long base)
+{
+    unsigned long long t = 0;
+    if (lane_id() == 0) t = atomicAdd(counter, 1ull);
+    t = __shfl(t, 0, 64);
+    return (long long)(t - base);
 }

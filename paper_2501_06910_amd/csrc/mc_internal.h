@@ -19,16 +19,20 @@ struct mc_plan_s {
     // workspace (device)
     int32_t* p = nullptr;          // prequantised grid [ng]
     int32_t* rho = nullptr;        // learned shift [nv]
-    unsigned long long* range_partial = nullptr;
-    int range_blocks = 0;
-    unsigned long long* ctl = nullptr;   // 64 words: range, counters, tickets
-    RangeOut* range = nullptr;
-    unsigned* done = nullptr;
-    unsigned* err = nullptr;
-    unsigned* tickets = nullptr;
-    unsigned long long* st = nullptr;    // look-back status [ntg + ntv]
-    long long ntg = 0, ntv = 0;
-    unsigned* dec_flags = nullptr;
+    float* xh = nullptr;           // reconstructed grid x1' [ng]
+    unsigned long long* range_partial = nullptr;   // [3 * 1024]
+    unsigned long long* ctl = nullptr;   // 64 words: the two range slots
+    RangeOut* rbuf = nullptr;            // field range of the current call
+    unsigned* small = nullptr;           // per-call state cleared by k_range (u32 words)
+    long long nsmall = 0;
+    unsigned* err = nullptr;             // small[2]
+    unsigned* bcost = nullptr;           // learned block costs [2 * nblk] (in small)
+    unsigned* counts = nullptr;          // per-tile outlier counts and offsets
+    unsigned* gcount = nullptr;
+    unsigned* vcount = nullptr;
+    unsigned* goff = nullptr;
+    unsigned* voff = nullptr;
+    long long ntg = 0, ntv = 0, nblk = 0;
     mck::DecodeWs dws{};
     // statistics
     long long n_unresolved = 0, n_near_degenerate = 0, n_pairs = 0;

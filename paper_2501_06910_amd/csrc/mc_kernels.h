@@ -46,33 +46,33 @@ hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32
                          hipStream_t s);
 
 // ---- compression (k_compress.hip) -----------------------------------------
-hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, int nblocks,
-                 unsigned int* done, RangeOut* out, unsigned long long* zero_a, long long nzero_a,
-                 unsigned int* zero_b, long long nzero_b, unsigned int* err, hipStream_t s);
+hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur,
+                 unsigned int* zero, long long nzero, hipStream_t s);
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, int32_t* p, float* dbg_v, uint32_t* bflags,
+                    const RangeOut* range, BoundParams bp, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
                     long long nbflags, unsigned int* err, mc_result* res, hipStream_t s);
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
-                   int32_t* oidx, int32_t* odelta, long long cap, unsigned long long* st, unsigned int* ticket,
-                   unsigned int* err, mc_result* res, hipStream_t s);
-hipError_t residual(const float* coords, long long nv, GridGeom gg, const int32_t* p, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, const int32_t* rho_q, uint16_t* codes, int32_t* oidx,
-                    void* oval, long long cap, uint32_t* bflags, float* dbg_g, unsigned long long* st,
-                    unsigned int* ticket, unsigned int* err, mc_result* res, hipStream_t s);
+                   unsigned int* count, hipStream_t s);
+hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
+                    const RangeOut* range, BoundParams bp, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
+                    uint32_t* bflags, float* dbg_g, unsigned int* count, hipStream_t s);
+hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, const uint16_t* gcodes, unsigned int* gcount,
+                   unsigned int* goff, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
+                   long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* voff, int32_t* vidx,
+                   void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s);
 
 // ---- decompression (k_decode.hip) -----------------------------------------
 struct DecodeWs {
-    int rows, nyc;                 // xy pass: rows per chunk, chunks per plane
-    int* agg_xy; int* incl_xy; unsigned int* flag_xy;
-    int zplanes, nzc, nxyb;        // z pass (3-D)
-    int* agg_z; int* incl_z; unsigned int* flag_z;
-    unsigned int* tickets;         // [2]
-    long long nflag_xy, nflag_z;
+    int rows, nyc;                 // rows per tile, row chunks per plane
+    long long ntiles_xy;           // nyc * n2
+    int* agg_xy;                   // [ntiles_xy][n0] column totals, then carries
+    int zplanes, nzc;              // 3-D: planes per chunk, plane chunks
+    int* agg_z;                    // [nzc][n0*n1] chunk totals, then carries
 };
-hipError_t zero_u32(unsigned int* a, long long n, hipStream_t s);
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
-                       const mc_result* res, int dim, int n0, int n1, int n2, int32_t* p, const DecodeWs& ws, hipStream_t s);
-hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const int32_t* p, const uint16_t* codes,
+                       const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,
+                       hipStream_t s);
+hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
                          const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
                          const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, hipStream_t s);
 
