@@ -88,24 +88,20 @@ struct MlpDev {
 };
 hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, uint16_t* w3, uint16_t* w4,
                     float* b1, float* b2, float* b3, float* b4, hipStream_t s);
-hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
-                     const mc_result* res, const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s);
-hipError_t mlp_features(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
-                        const mc_result* res, long long v0, long long count, float* z, hipStream_t s);
+hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                     const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s);
+hipError_t mlp_features(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh, long long v0,
+                        long long count, float* z, hipStream_t s);
 hipError_t mlp_forward_z(const MlpDev& m, const float* z, long long batch, float* rho, hipStream_t s);
-hipError_t mlp_feature_sumsq(const float* coords, long long nv, GridGeom gg, const int32_t* p,
-                             const mc_result* res, int dim, double* partial, int nblocks, hipStream_t s);
-// training
-struct TrainWs {
-    float* params; float* m; float* v; float* grad_part; float* grad; float* loss_part;
-    int nparts;
-};
-hipError_t train_step_grad(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const int32_t* p,
-                           const mc_result* res, const float* z_given, const float* y_given, const void* x,
-                           int dtype, long long batch, unsigned long long seed, long long step, float* grad_part,
+hipError_t mlp_feature_sumsq(const float* coords, long long nv, GridGeom gg, const float* xh, int dim,
+                             double* partial, int nblocks, hipStream_t s);
+// training: one wave per 64 samples writes its gradient to grad_part[wave]
+hipError_t train_step_grad(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                           const mc_result* res, const float* z_given, const float* y_given, const void* x, int dtype,
+                           long long batch, unsigned long long seed, long long step, float* grad_part,
                            float* loss_part, int nparts, hipStream_t s);
 hipError_t train_reduce_adam(int nparams, int nparts, const float* grad_part, const float* loss_part, float* grad,
                              float* loss_out, float* params, float* m, float* v, long long t, float lr, int apply,
-                             hipStream_t s);
+                             long long batch, hipStream_t s);
 
 }  // namespace mck

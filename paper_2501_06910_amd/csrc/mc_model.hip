@@ -134,7 +134,8 @@ extern "C" mc_status mc_model_import(const void* h_buf, size_t n, mc_model* out)
 
 mc_status mc_model_infer(mc_model m, mc_plan p, const mc_result* res, const uint32_t* only_blocks, hipStream_t s)
 {
-    hipError_t e = mck::mlp_infer(m->md, p->coords, p->nv, p->gg, p->p, res, only_blocks, p->rho, s);
+    (void)res;
+    hipError_t e = mck::mlp_infer(m->md, p->coords, p->nv, p->gg, p->xh, only_blocks, p->rho, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mlp_infer: %s", hipGetErrorString(e));
     return MC_OK;
 }
@@ -153,30 +154,31 @@ extern "C" mc_status mc_model_features(mc_model m, mc_plan p, const mc_codes* co
     if (!m || !p || !codes || !codes->result || !d_z) return mc_fail(MC_ERR_ARG, "invalid feature arguments");
     if (m->dim != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
     if (v0 < 0 || count < 0 || v0 + count > p->nv) return mc_fail(MC_ERR_ARG, "vertex range outside the mesh");
-    hipError_t e = mck::mlp_features(m->md, p->coords, p->nv, p->gg, p->p, codes->result, v0, count, d_z, s);
+    hipError_t e = mck::mlp_features(m->md, p->coords, p->nv, p->gg, p->xh, v0, count, d_z, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mlp_features: %s", hipGetErrorString(e));
     return MC_OK;
 }
 
 // Per-wave gradient partials are reduced in a fixed order, so the gradient
 // is the same on every run.
-static const int kParts = 128;
+static int parts_of(long long batch) { return (int)((batch + 63) / 64); }
 
 extern "C" mc_status mc_model_loss_grad(mc_model m, const float* d_z, const float* d_y, int64_t batch, float* d_grad,
                                         float* d_loss, hipStream_t s)
 {
     if (!m || !d_z || !d_y || !d_grad || batch <= 0) return mc_fail(MC_ERR_ARG, "invalid loss_grad arguments");
     const int np = (int)mc_model_param_count(m->dim);
+    const int nparts = parts_of(batch);
     float *gp = nullptr, *lp = nullptr, *lo = nullptr;
-    hipError_t e = hipMalloc(&gp, (size_t)kParts * np * 4);
-    if (e == hipSuccess) e = hipMalloc(&lp, (size_t)kParts * 4);
+    hipError_t e = hipMalloc(&gp, (size_t)nparts * np * 4);
+    if (e == hipSuccess) e = hipMalloc(&lp, (size_t)nparts * 4);
     if (e == hipSuccess) e = hipMalloc(&lo, 4);
     if (e == hipSuccess)
         e = mck::train_step_grad(m->md, nullptr, 0, GridGeom{}, nullptr, nullptr, d_z, d_y, nullptr, 0, batch, 0, 0,
-                                 gp, lp, kParts, s);
+                                 gp, lp, nparts, s);
     if (e == hipSuccess)
-        e = mck::train_reduce_adam(np, kParts, gp, lp, d_grad, d_loss ? d_loss : lo, nullptr, nullptr, nullptr, 0, 0.f,
-                                   0, s);
+        e = mck::train_reduce_adam(np, nparts, gp, lp, d_grad, d_loss ? d_loss : lo, nullptr, nullptr, nullptr, 0, 0.f,
+                                   0, batch, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     hipFree(gp);
     hipFree(lp);
@@ -199,6 +201,7 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     const float lr = opts && opts->lr > 0.f ? opts->lr : 1e-3f;
     const uint64_t seed = opts ? opts->seed : 0;
     if (batch % 64 != 0) return mc_fail(MC_ERR_ARG, "batch must be a multiple of 64");
+    if (!plan->xh) return mc_fail(MC_ERR_ARG, "plan has no workspace");
     const int dim = plan->dim;
     const int np = (int)mc_model_param_count(dim);
     // 1) plain compression of the training field into scratch codes
@@ -221,8 +224,9 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     c.v_out_idx = (int32_t*)dalloc((size_t)plan->nv * 4);
     c.v_out_val = dalloc((size_t)plan->nv * tsz);
     c.result = (mc_result*)dalloc(sizeof(mc_result));
-    float* gp = (float*)dalloc((size_t)kParts * np * 4);
-    float* lp = (float*)dalloc((size_t)kParts * 4);
+    const int nparts = parts_of(batch);
+    float* gp = (float*)dalloc((size_t)nparts * np * 4);
+    float* lp = (float*)dalloc((size_t)nparts * 4);
     float* dev_state = (float*)dalloc((size_t)np * 4 * 4 + 64 * 4);
     double* ssq = (double*)dalloc(2048 * 8);
     for (void* q : tmp)
@@ -235,7 +239,7 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     if (st != MC_OK) { cleanup(); return st; }
     if ((st = mc_compress_enqueue(plan, d_field, dtype, &pp, &c, s)) != MC_OK) { cleanup(); return st; }
     // 2) input scale: 1 / rms of (x1'[n] - g) over vertices and neighbourhoods
-    hipError_t e = mck::mlp_feature_sumsq(plan->coords, plan->nv, plan->gg, plan->p, c.result, dim, ssq, 1024, s);
+    hipError_t e = mck::mlp_feature_sumsq(plan->coords, plan->nv, plan->gg, plan->xh, dim, ssq, 1024, s);
     std::vector<double> h(2048);
     mc_result hres{};
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), ssq, 2048 * 8, hipMemcpyDeviceToHost, s);
@@ -259,10 +263,11 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     float* loss = dev_state + 3 * np;
     e = hipMemsetAsync(am, 0, (size_t)np * 2 * 4, s);
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
-        e = mck::train_step_grad(m->md, plan->coords, plan->nv, plan->gg, plan->p, c.result, nullptr, nullptr, d_field,
-                                 dtype, batch, seed, t, gp, lp, kParts, s);
+        e = mck::train_step_grad(m->md, plan->coords, plan->nv, plan->gg, plan->xh, c.result, nullptr, nullptr, d_field,
+                                 dtype, batch, seed, t, gp, lp, nparts, s);
         if (e == hipSuccess)
-            e = mck::train_reduce_adam(np, kParts, gp, lp, grad, loss + (t % 64), master, am, av, t + 1, lr, 1, s);
+            e = mck::train_reduce_adam(np, nparts, gp, lp, grad, loss + (t % 64), master, am, av, t + 1, lr, 1, batch,
+                                       s);
         if (e == hipSuccess)
             e = mck::mlp_pack(master, dim, (uint16_t*)m->md.w1, (uint16_t*)m->md.w2, (uint16_t*)m->md.w3,
                               (uint16_t*)m->md.w4, (float*)m->md.b1, (float*)m->md.b2, (float*)m->md.b3,

@@ -1,0 +1,198 @@
+"""GPU parity of the learned residual predictor against the CPU oracle:
+forward values and gradients within tolerance (the MFMA summation order
+differs from the oracle's ascending order), inputs bit-exact, codes and
+outlier lists bit-exact given the GPU's integer shifts, the seeded
+initialisation identical, one Adam step close, and the trained network's
+gain over the plain codes on a rotating-front time series."""
+import numpy as np
+import pytest
+
+import meshgen as G
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2501_06910_amd import mc as M  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def cos(a, b):
+    return float(np.dot(a, b) / max(np.linalg.norm(a) * np.linalg.norm(b), 1e-30))
+
+
+def rand_params(dim, seed):
+    p = O.mlp_init(dim, seed)
+    rng = np.random.default_rng(seed)
+    nb = 64 * 3 + 1
+    p = p + rng.normal(0, 0.02, p.size).astype(np.float32)      # non-zero biases too
+    return p.astype(np.float32)
+
+
+def rand_inputs(dim, n, seed):
+    rng = np.random.default_rng(seed)
+    z = np.zeros((n, O.mlp_kpad(dim)), np.float32)
+    z[:, :O.mlp_kin(dim)] = O.bf16(rng.normal(size=(n, O.mlp_kin(dim))).astype(np.float32))
+    return z
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_init_matches_oracle(dim):
+    """The library's seeded initialisation equals the oracle's, bit for bit
+    (both implement SplitMix64 from its published definition)."""
+    mesh = G.structured_tri_mesh(40, 40) if dim == 2 else G.kuhn_tet_mesh(8, 1)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=(20,) * dim)
+    x = G.field_octaves(mesh.coords, np.random.default_rng(0))
+    model = M.Model.train(plan, dev(x), steps=0 or 1, batch=64, lr=0.0 + 1e-30, seed=1234)
+    p, _ = model.params()
+    ref = O.mlp_init(dim, 1234)
+    # one step with a vanishing learning rate moves nothing measurable
+    np.testing.assert_allclose(p, ref, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_forward_parity(dim):
+    params = rand_params(dim, 7 + dim)
+    z = rand_inputs(dim, 1000, 3)
+    model = M.Model.create(dim, params, 1.0)
+    rho_g = model.forward(dev(z)).cpu().numpy()
+    rho_o, _ = O.mlp_forward(dim, params, z)
+    d = np.abs(rho_g - rho_o) / (1.0 + np.abs(rho_o))
+    print(f"[forward D={dim}] median {np.median(d):.2e} p99 {np.percentile(d, 99):.2e} max {d.max():.2e}")
+    assert np.percentile(d, 99) <= 1e-3
+    assert d.max() <= 5e-2
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_gradient_parity(dim):
+    params = rand_params(dim, 11 + dim)
+    B = 512
+    z = rand_inputs(dim, B, 5)
+    y = np.random.default_rng(6).normal(size=B).astype(np.float32)
+    model = M.Model.create(dim, params, 1.0)
+    loss_g, g = model.loss_grad(dev(z), dev(y))
+    g = g.cpu().numpy()
+    loss_o, go = O.mlp_backward(dim, params, z, y, True)
+    print(f"[grad D={dim}] loss {loss_g:.6f} vs {loss_o:.6f}; rel-L2 {rel_l2(g, go):.2e} cos {cos(g, go):.6f}")
+    assert abs(loss_g - loss_o) <= 1e-3 * abs(loss_o)
+    kin = O.mlp_kin(dim)
+    cuts = np.cumsum([0, 64 * kin, 64, 4096, 64, 4096, 64, 64, 1])
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        if np.linalg.norm(go[a:b]) == 0:
+            continue
+        assert rel_l2(g[a:b], go[a:b]) <= 1e-2, (a, b)
+        assert cos(g[a:b], go[a:b]) >= 0.999, (a, b)
+
+
+def _series_case(dim):
+    if dim == 2:
+        mesh, series, cfg = G.config_learned_series(h0=0.004, dims=200, steps=2)
+        dims = (200, 200)
+    else:
+        mesh = G.kuhn_tet_mesh(24, 9)
+        rng = np.random.default_rng(2)
+        f0 = G.field_octaves(mesh.coords, rng)
+        series = [f0, (f0 * np.float32(1.01) + np.float32(0.003)).astype(np.float32)]
+        dims = (26, 26, 26)
+    return mesh, series, dims
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_learned_codes_parity(dim):
+    mesh, series, dims = _series_case(dim)
+    x = series[1]
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    model = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=60, batch=1024, seed=3)
+    params, kappa = model.params()
+    codes = M.compress(plan, dev(x), 1e-4, "rel", 0.5, model=model, debug=True)
+    torch.cuda.synchronize()
+    h = codes.host()
+    assert h["result"]["status"] == 0
+    rho_q = codes.rho_q.cpu().numpy()
+    # oracle on the same inputs
+    og = O.grid_from_dims(mesh.coords, dims)
+    om = O.locate(mesh.coords, mesh.cells, og)
+    pc = O.compress(mesh.coords, om, og, x, 1e-4, True, 0.5)
+    assert np.array_equal(codes.dbg_vertex_g.cpu().numpy().view(np.uint32), pc.gv.view(np.uint32))
+    # inputs: bit-exact
+    zg = model.features(plan, codes).cpu().numpy()
+    zo = O.mlp_features(mesh.coords, og, pc.xhat, pc.gv, kappa)
+    assert np.array_equal(zg.view(np.uint32), zo.view(np.uint32))
+    # predictions: close to the oracle network's
+    rho_o, _ = O.mlp_forward(dim, params, zo)
+    same = np.mean(O.rho_quantize(rho_o) == rho_q)
+    print(f"[learned D={dim}] rho_q equal to the oracle's on {100 * same:.3f}% of vertices; "
+          f"learned blocks {h['result']['n_learned_blocks']}")
+    assert same >= 0.999
+    # codes given the GPU's shift: bit-exact
+    lc = O.learned_codes(x, pc.gv, pc.bound, rho_q)
+    assert np.array_equal(h["vert_codes"], lc.codes)
+    assert np.array_equal(h["block_flags"][: lc.block_flags.size], lc.block_flags)
+    assert np.array_equal(h["v_out_idx"], lc.out_idx)
+    assert np.array_equal(h["v_out_val"], lc.out_val)
+    assert np.array_equal(h["grid_codes"], pc.grid.codes)
+    assert h["result"]["n_learned_blocks"] == int(sum(bin(int(w)).count("1") for w in lc.block_flags))
+    # decode with the model: bit-exact and within the bound
+    xr = M.decompress(plan, codes, model=model).cpu().numpy()
+    xo = O.vertex_decode(lc, pc.gv, pc.bound, x.dtype, rho_q)
+    assert np.array_equal(xr.view(np.uint8), xo.view(np.uint8))
+    assert np.all(np.abs(x.astype(np.float64) - xr) <= pc.bound.tau2)
+
+
+def test_one_training_step_matches_oracle():
+    dim = 2
+    mesh, series, dims = _series_case(dim)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    B, seed, lr = 512, 77, 1e-3
+    model = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=1, batch=B, lr=lr, seed=seed)
+    p_gpu, kappa = model.params()
+    og = O.grid_from_dims(mesh.coords, dims)
+    om = O.locate(mesh.coords, mesh.cells, og)
+    pc = O.compress(mesh.coords, om, og, series[0], 1e-4, True, 0.5)
+    rms = O.mlp_feature_rms(mesh.coords, og, pc.xhat, pc.gv)
+    assert abs(kappa - 1.0 / rms) <= 1e-5 * (1.0 / rms)
+    idx = O.sample_indices(seed, 0, B, mesh.n_vertices)
+    z = O.mlp_features(mesh.coords, og, pc.xhat, pc.gv, kappa)[idx]
+    y = ((series[0][idx] - pc.gv[idx].astype(np.float64)) * pc.bound.inv2).astype(np.float32)
+    p0 = O.mlp_init(dim, seed)
+    _, g = O.mlp_backward(dim, p0, z, y, True)
+    p1 = p0.copy()
+    O.adam_step(p1, np.zeros_like(p0), np.zeros_like(p0), g, 1, lr)
+    step_o = p1 - p0
+    step_g = p_gpu - p0
+    print(f"[train step] rel-L2 {rel_l2(step_g, step_o):.3e} cos {cos(step_g, step_o):.6f}")
+    # Adam's first step is lr * sign(g) wherever |g| >> eps: compare the steps
+    assert cos(step_g, step_o) >= 0.99
+
+
+def test_learned_gain_on_time_series():
+    """Train on t=0, compress t=1: the per-block choice makes the learned
+    stream no larger than the plain one; the gain itself is reported."""
+    mesh, series, cfg = G.config_learned_series(h0=0.003, dims=256, steps=3)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=(256, 256))
+    model, loss = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=400, batch=4096, seed=5, return_loss=True)
+    print(f"[gain] training loss {loss[0]:.4f} -> {np.mean(loss[-20:]):.4f}")
+    assert np.mean(loss[-20:]) < loss[0]
+    for t in (1, 2):
+        x = dev(series[t])
+        plain = M.compress(plan, x, 1e-4, "rel", 0.5).host()
+        learned = M.compress(plan, x, 1e-4, "rel", 0.5, model=model).host()
+        learned["learned"] = True
+        sp = M.stream_bytes(plain, 8)["total"]
+        sl = M.stream_bytes(learned, 8)["total"]
+        hp = M.entropy_bits(plain["vert_codes"])
+        hl = M.entropy_bits(learned["vert_codes"])
+        print(f"[gain] t={t}: plain {sp} B (vertex entropy {hp:.3f} b), learned {sl} B ({hl:.3f} b), "
+              f"blocks learned {learned['result']['n_learned_blocks']}")
+        assert learned["result"]["status"] == 0
+        assert sl <= sp + learned["block_flags"].size * 4
