@@ -115,6 +115,245 @@ def cpu_baseline(eb: float, split: float, min_seconds: float = 10.0, n: int = 96
                       f"in {el:.1f} s, one thread"}
 
 
+def _timed(fn, reps=5):
+    """Median device milliseconds of fn() over reps, HIP events on the
+    current stream."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts))
+
+
+def mlp_flops_per_vertex(D: int) -> int:
+    """Multiply-adds of one inference (x2): K_in -> 64 -> 64 -> 64 -> 1 with
+    K_in = 4^D + D, the zero padding not counted."""
+    kin = 4 ** D + D
+    return 2 * (kin * 64 + 64 * 64 * 2 + 64)
+
+
+def learned_section(log, train_steps=2000, batch=8192):
+    """Learned vs plain on the rotating-front time series over the refined
+    2-D mesh: train on t=0, compress t=1..8 both ways at eb 1e-4; CR with the
+    BF16 model charged once to the sequence; both forms' GB/s."""
+    import torch
+    import meshgen as G
+    from paper_2501_06910_amd import mc as M
+    t0 = time.time()
+    mesh, series, cfg = G.config_learned_series()
+    log(f"learned: series generated in {time.time() - t0:.1f} s (nv={mesh.n_vertices}, {len(series)} steps)")
+    D, nv = mesh.dim, mesh.n_vertices
+    sT = series[0].dtype.itemsize
+    plan = M.Plan(torch.from_numpy(mesh.coords).cuda(), torch.from_numpy(mesh.cells).cuda(), dims=cfg["dims"][:2])
+    ng = plan.n_grid
+    x0 = torch.from_numpy(series[0]).cuda()
+    torch.cuda.synchronize()
+    M.profile_reset()
+    M.profile_enable(True)
+    t0 = time.time()
+    model, loss = M.Model.train(plan, x0, eb=cfg["eb"], steps=train_steps, batch=batch, seed=4, return_loss=True)
+    torch.cuda.synchronize()
+    train_s = time.time() - t0
+    M.profile_enable(False)
+    tprof = M.profile_read()
+    log(f"learned: trained {train_steps} steps x {batch} in {train_s:.2f} s, loss {loss[0]:.4f} -> "
+        f"{float(np.mean(loss[-50:])):.4f}")
+    model_bytes = 16 + 2 * M.param_count(D)          # header + BF16 weights
+    nT = len(series) - 1
+    per_t = []
+    cp, cl = M.Codes(plan, x0.dtype), M.Codes(plan, x0.dtype, learned=True)
+    out = torch.empty_like(x0)
+    tot = {"plain": 0, "learned": 0, "raw": 0}
+    times = {"plain_c": [], "plain_d": [], "learned_c": [], "learned_d": []}
+    for t in range(1, len(series)):
+        x = torch.from_numpy(series[t]).cuda()
+        times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=cp)))
+        times["plain_d"].append(_timed(lambda: M.decompress(plan, cp, out=out)))
+        ep = (x.double() - out.double()).abs().max().item()
+        times["learned_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, model=model, codes=cl)))
+        times["learned_d"].append(_timed(lambda: M.decompress(plan, cl, model=model, out=out)))
+        el = (x.double() - out.double()).abs().max().item()
+        hp, hl = cp.host(), cl.host()
+        hl["learned"] = True
+        if hp["result"]["status"] or hl["result"]["status"]:
+            raise SystemExit(f"learned section: status {hp['result']['status']} / {hl['result']['status']}")
+        tau2 = hp["result"]["tau2"]
+        if not (ep <= tau2 and el <= tau2):
+            raise SystemExit(f"learned section: bound violated at t={t}")
+        sp = M.stream_bytes(hp, sT)["total"]
+        sl = M.stream_bytes(hl, sT, model_bytes)["total"] - model_bytes   # model charged once below
+        tot["plain"] += sp
+        tot["learned"] += sl
+        tot["raw"] += nv * sT
+        per_t.append({"t": t, "cr_plain": round(nv * sT / sp, 3), "cr_learned": round(nv * sT / (sl + model_bytes / nT), 3),
+                      "vert_bits_plain": round(M.entropy_bits(hp["vert_codes"]), 3),
+                      "vert_bits_learned": round(M.entropy_bits(hl["vert_codes"]), 3),
+                      "learned_blocks": hl["result"]["n_learned_blocks"],
+                      "blocks": (nv + 4095) // 4096})
+        log(f"learned: t={t} {per_t[-1]}")
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    # inference kernel on its own: MFMA rate
+    M.profile_reset()
+    M.profile_enable(True)
+    for _ in range(5):
+        M.compress(plan, x0, cfg["eb"], "rel", 0.5, model=model, codes=cl)
+    torch.cuda.synchronize()
+    M.profile_enable(False)
+    iprof = M.profile_read()
+    inf = iprof.get("k_mlp_infer_c")
+    inf_ms = inf[1] / inf[0] if inf else None
+    fl = mlp_flops_per_vertex(D) * nv
+    tr = tprof.get("k_mlp_train")
+    tr_ms = tr[1] / tr[0] if tr else None
+    train_fl = 3 * mlp_flops_per_vertex(D) * batch      # forward + two backward products per layer
+    return {
+        "series": f"refined-annulus Delaunay mesh ({nv} vertices), float64 tanh front + noise rotated about a "
+                  f"seeded centre, {len(series)} timesteps, grid {cfg['dims'][0]}^2, relative eb 1e-4, split 0.5",
+        "model": f"MLP {4 ** D + D} -> 64 -> 64 -> 64 -> 1 (ReLU), BF16 weights, {M.param_count(D)} parameters, "
+                 f"{model_bytes} B in the stream (charged once to the {nT} coded timesteps)",
+        "train": {"steps": train_steps, "batch": batch, "seconds": round(train_s, 3),
+                  "loss_first": round(float(loss[0]), 5), "loss_last50": round(float(np.mean(loss[-50:])), 5),
+                  "k_mlp_train_avg_ms": round(tr_ms, 5) if tr_ms else None,
+                  "k_mlp_train_TFLOPs": round(train_fl / (tr_ms * 1e-3) / 1e12, 2) if tr_ms else None},
+        "cr_plain": round(tot["raw"] / tot["plain"], 3),
+        "cr_learned": round(tot["raw"] / (tot["learned"] + model_bytes), 3),
+        "plain_GBps": {"compress": round(nv * sT / (med["plain_c"] * 1e-3) / 1e9, 2),
+                       "decompress": round(nv * sT / (med["plain_d"] * 1e-3) / 1e9, 2)},
+        "learned_GBps": {"compress": round(nv * sT / (med["learned_c"] * 1e-3) / 1e9, 2),
+                         "decompress": round(nv * sT / (med["learned_d"] * 1e-3) / 1e9, 2)},
+        "inference": {"kernel": "k_mlp_infer_c", "avg_ms": round(inf_ms, 5) if inf_ms else None,
+                      "flops_per_vertex": mlp_flops_per_vertex(D),
+                      "TFLOPs": round(fl / (inf_ms * 1e-3) / 1e12, 2) if inf_ms else None,
+                      "mfma_peak_bf16_TFLOPs": 2500.0},
+        "per_timestep": per_t,
+        "n_vertices": nv, "n_grid": ng,
+    }
+
+
+def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), splits=(0.1, 0.3, 0.5, 0.7, 0.9)):
+    """CR, bits per value, outlier rates and errors of the tet3d workload
+    over relative error bounds and grid shares (CPU entropy stage)."""
+    import torch
+    import meshgen as G
+    from paper_2501_06910_amd import mc as M
+    mesh, f, cfg = G.config_tet_3d()
+    nv, sT = mesh.n_vertices, 4
+    plan = M.Plan(torch.from_numpy(mesh.coords).cuda(), torch.from_numpy(mesh.cells).cuda(), dims=cfg["dims"])
+    x = torch.from_numpy(f).cuda()
+    xd = x.double()
+    norm = torch.linalg.vector_norm(xd).item()
+    codes = M.Codes(plan, x.dtype)
+    out = torch.empty_like(x)
+    rows = []
+    for eb in ebs:
+        for sp in splits:
+            M.compress(plan, x, eb, "rel", sp, codes=codes)
+            M.decompress(plan, codes, out=out)
+            h = codes.host()
+            r = h["result"]
+            if r["status"]:
+                rows.append({"eb": eb, "split": sp, "status": r["status"]})
+                continue
+            d = (xd - out.double()).abs()
+            sb = M.stream_bytes(h, sT)
+            rows.append({"eb": eb, "split": sp, "cr": round(nv * sT / sb["total"], 3),
+                         "bits_per_value": round(8 * sb["total"] / nv, 4),
+                         "grid_outlier_rate": r["n_grid_outliers"] / plan.n_grid,
+                         "vertex_outlier_rate": r["n_vertex_outliers"] / nv,
+                         "linf_over_tau": round(d.max().item() / r["tau"], 4),
+                         "rel_l2": float(torch.linalg.vector_norm(d).item() / norm)})
+            log(f"cr sweep: {rows[-1]}")
+    return rows
+
+
+def batch_main(args, log):
+    """Many fields on many meshes: 12 meshes of 0.5M..20M vertices (2-D and
+    3-D, float32 and float64), 64 fields; a step is one batch compress and
+    one batch decompress, each a single HIP graph launch.  ``value`` is GB/s
+    of mesh values over all fields."""
+    import torch
+    import meshgen as G
+    from paper_2501_06910_amd import mc as M
+    t0 = time.time()
+    meshes, grids, fields = G.config_batch(scale=args.batch_scale)
+    log(f"batch: generated {len(meshes)} meshes / {len(fields)} fields in {time.time() - t0:.1f} s")
+    plans = []
+    t0 = time.time()
+    for m, g in zip(meshes, grids):
+        c, k = torch.from_numpy(m.coords).cuda(), torch.from_numpy(m.cells).cuda()
+        plans.append(M.Plan(c, k, dims=g[:m.dim]))
+        del c, k
+    torch.cuda.synchronize()
+    plan_s = time.time() - t0
+    xs = [torch.from_numpy(f["data"]).cuda() for f in fields]
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
+    outs = [torch.empty_like(x) for x in xs]
+    items = [(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], None, codes[i])
+             for i, f in enumerate(fields)]
+    ditems = [(plans[f["mesh"]], codes[i], None, outs[i]) for i, f in enumerate(fields)]
+    raw = sum(x.numel() * x.element_size() for x in xs)
+
+    def step():
+        M.batch_compress(items)
+        M.batch_decompress(ditems)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for i, x in enumerate(xs):
+        r = codes[i].result_host()
+        if r["status"]:
+            raise SystemExit(f"batch field {i}: status {r['status']}")
+        e = (x.double() - outs[i].double()).abs().max().item()
+        if not e <= r["tau2"]:
+            raise SystemExit(f"batch field {i}: bound violated")
+        worst = max(worst, e / r["tau"])
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    tc = _timed(lambda: M.batch_compress(items))
+    td = _timed(lambda: M.batch_decompress(ditems))
+    # the same work as separate calls on one stream, for the graph's gain
+    def serial():
+        for i, f in enumerate(fields):
+            M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], codes=codes[i])
+        for i, f in enumerate(fields):
+            M.decompress(plans[f["mesh"]], codes[i], out=outs[i])
+    ts = _timed(serial)
+    nv_all = [m.n_vertices for m in meshes]
+    line = {
+        "metric": "compress/decompress GB/s of mesh values + CR, learned vs plain, eb=1e-4",
+        "value": round(raw / (ms_step * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"batch: {len(meshes)} meshes ({min(nv_all)}..{max(nv_all)} vertices, "
+                               f"even 2-D jittered triangulations, odd 3-D Kuhn tetrahedra), {len(fields)} fields "
+                               f"(float32 on 2-D, float64 on 3-D meshes), relative eb 1e-3/1e-4/1e-5, grids of "
+                               f"about n_v/4 nodes, split 0.5",
+                   "scale": args.batch_scale, "n_vertices_total": int(sum(x.numel() for x in xs)),
+                   "raw_bytes": raw},
+        "compress_GBps": round(raw / (tc * 1e-3) / 1e9, 2),
+        "decompress_GBps": round(raw / (td * 1e-3) / 1e9, 2),
+        "separate_calls_ms": round(ts, 4),
+        "graph_ms": round(tc + td, 4),
+        "max_abs_err_over_tau": round(worst, 4),
+        "plan_seconds": round(plan_s, 3),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -124,6 +363,10 @@ def main():
     ap.add_argument("--eb", type=float, default=1e-4)
     ap.add_argument("--split", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time series section")
+    ap.add_argument("--train-steps", type=int, default=2000)
+    ap.add_argument("--cr-sweep", action="store_true", help="print the CR sweep over eb and split instead")
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="mesh size scale of the batch workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
@@ -137,6 +380,13 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.workload == "batch":
+        batch_main(args, log)
+        return
+    if args.cr_sweep:
+        print(json.dumps({"cr_sweep": cr_sweep(log), "workload": "tet3d"}), flush=True)
+        return
 
     t0 = time.time()
     mesh, f, cfg, desc = workload(args.workload)
@@ -188,10 +438,15 @@ def main():
     # per-kernel durations: HIP events around each launch on its stream
     M.profile_reset()
     M.profile_enable(True)
+    ev2, ev3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev2.record()
     for _ in range(args.steps):
         step()
+    ev3.record()
     torch.cuda.synchronize()
     M.profile_enable(False)
+    ms_step_ev = ev2.elapsed_time(ev3) / args.steps
+    log(f"profiled pass: {ms_step_ev:.4f} ms/step with per-launch events")
     prof = M.profile_read()
     kernels = {}
     comp_ms = dec_ms = 0.0
@@ -251,10 +506,13 @@ def main():
         "stream_bytes": sb,
         "outliers": {"grid": h["result"]["n_grid_outliers"], "vertex": h["result"]["n_vertex_outliers"]},
         "max_abs_err_over_tau": round(err / res["tau"], 4),
+        "ms_per_step_with_kernel_events": round(ms_step_ev, 4),
         "plan_seconds": round(plan_s, 3),
         "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
         "kernels": kernels,
     }
+    if not args.no_learned:
+        line["learned"] = learned_section(log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread) ...")
         line["cpu_baseline"] = cpu_baseline(args.eb, args.split)

@@ -236,8 +236,20 @@ mc_status mc_model_features(mc_model model, mc_plan plan, const mc_codes* codes,
                             int64_t count, float* d_z, hipStream_t stream);
 
 /* ---- batched compression ------------------------------------------------
- * Many fields on many plans in one persistent launch (captured in a HIP
- * graph on the first call with a given item list and replayed after). */
+ * Compresses many fields, on one or more plans, as one HIP graph.  The
+ * first call with a given item list (compared byte for byte, so zero the
+ * structs before filling them) captures the compress sequence of every item
+ * into a graph: one chain of kernels per distinct plan, the chains forked
+ * from and joined back to `stream`; items that share a plan run in list
+ * order on their chain, since they share its workspace.  Later calls with the
+ * same list replay the graph in one launch.  Each item follows mc_compress
+ * exactly (same codes, outliers and result), including its error statuses,
+ * which are written to that item's `codes.result` on the device.  Host-side
+ * argument errors of any item fail the whole call before anything is
+ * enqueued (MC_ERR_ARG, mc_last_error names the item).  Graph capture
+ * records no memset nodes.  At most 16 graphs are cached (least recently
+ * created dropped first); destroying a plan or model drops the graphs that
+ * use it.  Async with respect to the host. */
 typedef struct {
     mc_plan plan;
     const void* d_field;
@@ -247,6 +259,21 @@ typedef struct {
 } mc_batch_item;
 
 mc_status mc_batch_compress(const mc_batch_item* items, int32_t n_items, hipStream_t stream);
+
+/* The inverse (Alg. 4 for every item), captured and replayed the same way:
+ * each item follows mc_decompress exactly, writing d_out (T[n_vertices] of
+ * its plan, caller-owned).  `codes` are the buffers a compress filled. */
+typedef struct {
+    mc_plan plan;
+    mc_codes codes;
+    mc_model model;        /* the model the field was compressed with, or NULL */
+    void* d_out;
+    mc_dtype dtype;
+} mc_batch_ditem;
+
+mc_status mc_batch_decompress(const mc_batch_ditem* items, int32_t n_items, hipStream_t stream);
+/* Synchronises the device and frees every cached batch graph. */
+mc_status mc_batch_release(void);
 
 /* ---- profiling -----------------------------------------------------------
  * When enabled, every kernel launch is bracketed by HIP events on the

@@ -74,7 +74,7 @@ hipEvent_t pool_get()
 
 mck::ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), idx(-1)
 {
-    if (!g_prof_on) return;
+    if (!g_prof_on || mc_capturing) return;
     std::lock_guard<std::mutex> lk(g_pm);
     hipEvent_t a = pool_get(), b = pool_get();
     if (!a || !b) return;
@@ -526,6 +526,7 @@ extern "C" mc_status mc_plan_mapping(mc_plan p, int32_t* d_vid, float* d_w, int3
 extern "C" mc_status mc_plan_destroy(mc_plan p)
 {
     if (!p) return MC_OK;
+    mc_batch_forget(p);
     for (void* q : p->allocs) (void)hipFree(q);
     delete p;
     return MC_OK;
@@ -602,15 +603,18 @@ extern "C" mc_status mc_compress(mc_plan p, const void* d_field, mc_dtype dtype,
     return mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
 }
 
-extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
-                                   hipStream_t s)
+mc_status mc_check_decompress(mc_plan p, const mc_codes* codes, mc_model model, const void* d_out, mc_dtype dtype)
 {
     if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
     if (!d_out) return mc_fail(MC_ERR_ARG, "output pointer is NULL");
     if (dtype != MC_F32 && dtype != MC_F64) return mc_fail(MC_ERR_ARG, "dtype must be MC_F32 or MC_F64");
     if (model && mc_model_dim(model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
-    mc_status st = check_codes(p, codes, model != nullptr);
-    if (st != MC_OK) return st;
+    return check_codes(p, codes, model != nullptr);
+}
+
+mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
+                                hipStream_t s)
+{
     hipError_t e;
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
@@ -626,6 +630,14 @@ extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model mo
                             codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, s));
 #undef ECHK
     return MC_OK;
+}
+
+extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
+                                   hipStream_t s)
+{
+    mc_status st = mc_check_decompress(p, codes, model, d_out, dtype);
+    if (st != MC_OK) return st;
+    return mc_decompress_enqueue(p, codes, model, d_out, dtype, s);
 }
 
 extern "C" mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t nv, int64_t nc,

@@ -52,6 +52,12 @@ struct mc_model_s {
 mc_status mc_fail(mc_status s, const char* fmt, ...);
 mc_status mc_check_grid(const mc_grid* g, int32_t dim);
 GridGeom mc_geom(const mc_grid& g);
+// Drops cached batch graphs that reference a plan or model (mc_batch.hip).
+void mc_batch_forget(const void* obj);
+
+mc_status mc_check_decompress(mc_plan p, const mc_codes* codes, mc_model model, const void* d_out, mc_dtype dtype);
+mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
+                                hipStream_t s);
 mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
                           const mc_codes* codes);
 mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,

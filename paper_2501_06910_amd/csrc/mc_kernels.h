@@ -8,9 +8,14 @@
 #include "../../include/mc.h"
 #include "mc_dev.h"
 
+// True while the calling thread captures a batch graph (mc_batch.hip).
+extern thread_local bool mc_capturing;
+
 namespace mck {
 
 // ---- profiling hook (mc_api.hip) -------------------------------------------
+// Records a pair of events around one launch when profiling is on and the
+// calling thread is not capturing a graph.
 struct ProfScope {
     const char* name;
     hipStream_t stream;

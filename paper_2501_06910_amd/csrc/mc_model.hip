@@ -79,6 +79,7 @@ extern "C" mc_status mc_model_create(int32_t dim, const float* h_params, float k
 extern "C" mc_status mc_model_destroy(mc_model m)
 {
     if (!m) return MC_OK;
+    mc_batch_forget(m);
     if (m->dev) hipFree(m->dev);
     delete m;
     return MC_OK;

@@ -69,6 +69,11 @@ class McBatchItem(C.Structure):
                 ("codes", McCodes)]
 
 
+class McBatchDItem(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("codes", McCodes), ("model", C.c_void_p), ("d_out", C.c_void_p),
+                ("dtype", C.c_int)]
+
+
 # every symbol include/mc.h declares, with its ctypes signature
 _P = C.c_void_p
 _SIGS = {
@@ -97,6 +102,8 @@ _SIGS = {
     "mc_model_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
     "mc_model_features": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P]),
     "mc_batch_compress": (C.c_int, [_P, C.c_int32, _P]),
+    "mc_batch_release": (C.c_int, []),
+    "mc_batch_decompress": (C.c_int, [_P, C.c_int32, _P]),
     "mc_profile_enable": (C.c_int, [C.c_int32]),
     "mc_profile_reset": (C.c_int, []),
     "mc_profile_read": (C.c_int32, [_P, _P, _P, C.c_int32]),
@@ -436,7 +443,9 @@ class Model:
 # ---------------------------------------------------------------------------
 
 def batch_compress(items):
-    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes)."""
+    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes).
+    The first call with a given list captures a HIP graph; later calls with
+    the same plans, tensors and parameters replay it."""
     arr = (McBatchItem * len(items))()
     for i, (plan, field, eb, mode, share, model, codes) in enumerate(items):
         arr[i].plan = plan.handle
@@ -446,6 +455,25 @@ def batch_compress(items):
                                  None if model is None else model.handle)
         arr[i].codes = codes.struct
     _check(lib().mc_batch_compress(arr, len(items), _stream()), "mc_batch_compress")
+
+
+def batch_decompress(items):
+    """items: list of (plan, codes, model, out); graph captured and replayed
+    like batch_compress."""
+    arr = (McBatchDItem * len(items))()
+    for i, (plan, codes, model, out) in enumerate(items):
+        _require_cuda(out, "out")
+        arr[i].plan = plan.handle
+        arr[i].codes = codes.struct
+        arr[i].model = None if model is None else model.handle
+        arr[i].d_out = out.data_ptr()
+        arr[i].dtype = _dtype_code(out)
+    _check(lib().mc_batch_decompress(arr, len(items), _stream()), "mc_batch_decompress")
+
+
+def batch_release():
+    """Synchronises the device and frees every cached batch graph."""
+    _check(lib().mc_batch_release(), "mc_batch_release")
 
 
 def profile_enable(on=True):

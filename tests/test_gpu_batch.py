@@ -1,0 +1,155 @@
+"""GPU tests of batched compression: a batch of fields on several meshes of
+both dimensions and dtypes, captured once into a HIP graph and replayed,
+gives for every item exactly what a separate mc_compress call gives (codes,
+outlier lists, result), which the oracle checks in turn on a sample of
+items; replays read the fields' current contents; destroying a plan drops
+the graphs that used it."""
+import numpy as np
+import pytest
+
+import meshgen as G
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2501_06910_amd import mc as M  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def same(a, b):
+    ra, rb = dict(a["result"]), dict(b["result"])
+    assert ra == rb
+    for k in ("grid_codes", "vert_codes", "g_out_idx", "g_out_delta", "v_out_idx", "block_flags"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["v_out_val"].view(np.uint8), b["v_out_val"].view(np.uint8))
+
+
+@pytest.fixture(scope="module")
+def workload():
+    meshes, grids, fields = G.config_batch(seed=5, scale=0.002, n_meshes=4, n_fields=10)
+    plans = [M.Plan(dev(m.coords), dev(m.cells), dims=g[:2] if g[2] == 1 else g) for m, g in zip(meshes, grids)]
+    xs = [dev(f["data"]) for f in fields]
+    return meshes, grids, fields, plans, xs
+
+
+def _items(fields, plans, xs, codes, models=None):
+    items = []
+    for i, f in enumerate(fields):
+        model = None if models is None else models.get(f["mesh"])
+        items.append((plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], model, codes[i]))
+    return items
+
+
+def test_batch_equals_single_calls_and_oracle(workload):
+    meshes, grids, fields, plans, xs = workload
+    print(f"[batch] {len(meshes)} meshes (nv {[m.n_vertices for m in meshes]}), {len(fields)} fields")
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
+    M.batch_compress(_items(fields, plans, xs, codes))
+    torch.cuda.synchronize()
+    got = [c.host() for c in codes]
+    for i, f in enumerate(fields):
+        ref = M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"]).host()
+        same(got[i], ref)
+        assert got[i]["result"]["status"] == 0
+    # the oracle on one field per mesh
+    for m in range(len(meshes)):
+        i = m
+        g = grids[m][:2] if grids[m][2] == 1 else grids[m]
+        og = O.grid_from_dims(meshes[m].coords, g)
+        om = O.locate(meshes[m].coords, meshes[m].cells, og)
+        oc = O.compress(meshes[m].coords, om, og, fields[i]["data"], fields[i]["eb"], True, fields[i]["split"])
+        assert np.array_equal(got[i]["grid_codes"], oc.grid.codes)
+        assert np.array_equal(got[i]["vert_codes"], oc.vert.codes)
+        assert np.array_equal(got[i]["g_out_idx"], oc.grid.out_idx)
+        assert np.array_equal(got[i]["v_out_idx"], oc.vert.out_idx)
+
+
+def test_replay_reads_current_fields(workload):
+    meshes, grids, fields, plans, xs = workload
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
+    items = _items(fields, plans, xs, codes)
+    M.batch_compress(items)                     # capture (or replay of an identical list)
+    torch.cuda.synchronize()
+    saved = [x.clone() for x in xs]
+    for rep in range(3):
+        for i, x in enumerate(xs):              # new contents, same addresses
+            x.copy_(saved[i] * (1.0 + 0.25 * (rep + 1)) + 0.1 * rep)
+        M.batch_compress(items)                 # replay
+        torch.cuda.synchronize()
+        for i, f in enumerate(fields):
+            ref = M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"]).host()
+            same(codes[i].host(), ref)
+    for i, x in enumerate(xs):
+        x.copy_(saved[i])
+    torch.cuda.synchronize()
+
+
+def test_batch_with_models_and_errors(workload):
+    meshes, grids, fields, plans, xs = workload
+    # a model for the first 2-D and the first 3-D mesh, trained on that mesh's first field
+    models = {}
+    for m in (0, 1):
+        models[m] = M.Model.train(plans[m], xs[m], eb=1e-4, steps=20, batch=512, seed=m)
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype, learned=f["mesh"] in models) for i, f in enumerate(fields)]
+    items = _items(fields, plans, xs, codes, models)
+    # one item asks for a bound too fine for the grid quantizer's range
+    bad = list(items[2])
+    bad[2] = 1e-12
+    items[2] = tuple(bad)
+    M.batch_compress(items)
+    torch.cuda.synchronize()
+    for i, it in enumerate(items):
+        if i == 2:
+            continue
+        plan, x, eb, mode, share, model, _ = it
+        ref = M.compress(plan, x, eb, mode, share, model=model).host()
+        same(codes[i].host(), ref)
+        assert codes[i].result_host()["status"] == 0
+    assert codes[2].result_host()["status"] == M.ERR_RANGE
+
+
+def test_batch_decompress_equals_single_calls(workload):
+    meshes, grids, fields, plans, xs = workload
+    models = {0: M.Model.train(plans[0], xs[0], eb=1e-4, steps=10, batch=256, seed=9)}
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype, learned=f["mesh"] in models) for i, f in enumerate(fields)]
+    M.batch_compress(_items(fields, plans, xs, codes, models))
+    outs = [torch.empty_like(x) for x in xs]
+    ditems = [(plans[f["mesh"]], codes[i], models.get(f["mesh"]), outs[i]) for i, f in enumerate(fields)]
+    for rep in range(2):                       # capture, then replay
+        for o in outs:
+            o.fill_(7.0)
+        M.batch_decompress(ditems)
+        torch.cuda.synchronize()
+        for i, f in enumerate(fields):
+            ref = M.decompress(plans[f["mesh"]], codes[i], model=models.get(f["mesh"]))
+            assert torch.equal(outs[i].view(torch.uint8), ref.view(torch.uint8)), (rep, i)
+            tau2 = codes[i].result_host()["tau2"]
+            assert (outs[i].double() - xs[i].double()).abs().max().item() <= tau2
+
+
+def test_destroyed_plan_drops_its_graph():
+    mesh = G.structured_tri_mesh(60, 60, np.random.default_rng(1), 0.2)
+    x = dev(G.field_octaves(mesh.coords, np.random.default_rng(2)))
+    for dims in ((20, 20), (33, 17)):
+        plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+        codes = M.Codes(plan, x.dtype)
+        M.batch_compress([(plan, x, 1e-3, "rel", 0.5, None, codes)])
+        torch.cuda.synchronize()
+        same(codes.host(), M.compress(plan, x, 1e-3, "rel", 0.5).host())
+        plan.destroy()
+    M.batch_release()
+
+
+def test_batch_rejects_bad_items(workload):
+    meshes, grids, fields, plans, xs = workload
+    codes = M.Codes(plans[0], xs[0].dtype)
+    with pytest.raises(RuntimeError, match="item 1"):
+        M.batch_compress([(plans[0], xs[0], 1e-3, "rel", 0.5, None, codes),
+                          (plans[0], xs[0], -1.0, "rel", 0.5, None, codes)])
