@@ -121,11 +121,13 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
                                                   int32_t* __restrict__ p, float* __restrict__ xh,
                                                   float* __restrict__ dbg_v, uint32_t* __restrict__ bflags,
                                                   long long nbflags, unsigned int* __restrict__ err,
-                                                  mc_result* __restrict__ res, int dtype)
+                                                  mc_result* __restrict__ res, int dtype,
+                                                  unsigned int* __restrict__ gcount, long long ntg)
 {
     const DevBound b = make_bound(range, bp);
     const long long j = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (bflags && j < nbflags) bflags[j] = 0u;      // learned-block bits start clear
+    if (j < ntg) gcount[j] = 0u;                    // grid outlier counts (k_lorenzo adds)
     if (j == 0) {
         res->status = b.ok ? 0 : 1;
         res->dtype = dtype;
@@ -138,16 +140,23 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
         if (!b.ok) atomicOr(err, (range->flags & MC_EBIT_NONFINITE) ? MC_EBIT_NONFINITE : MC_EBIT_TAU);
     }
     if (!b.ok || j >= ng) return;
-    const int v0 = vid[j];
-    float v;
-    if (v0 < 0) {
-        v = (float)b.c;
-    } else {
-        float acc = w[j] * as_float(x[v0]);
+    // all mapping loads, then all field gathers (a node with vid < 0 is a
+    // mid-range fill and gathers vertex 0 for nothing)
+    int id[D + 1];
+    float wk[D + 1];
 #pragma unroll
-        for (int k = 1; k <= D; ++k) acc = acc + w[k * ng + j] * as_float(x[vid[k * ng + j]]);
-        v = acc;
+    for (int k = 0; k <= D; ++k) {
+        id[k] = vid[k * ng + j];
+        wk[k] = w[k * ng + j];
     }
+    const bool fill = id[0] < 0;
+    float f[D + 1];
+#pragma unroll
+    for (int k = 0; k <= D; ++k) f[k] = as_float(x[fill ? 0 : id[k]]);
+    float acc = wk[0] * f[0];
+#pragma unroll
+    for (int k = 1; k <= D; ++k) acc = acc + wk[k] * f[k];
+    const float v = fill ? (float)b.c : acc;
     const double s = ((double)v - b.c) * b.inv1;
     int32_t q = 0;
     if (!(fabs(s) < 134217728.0)) atomicOr(err, MC_EBIT_RANGE);
@@ -179,67 +188,100 @@ __device__ __forceinline__ long long lorenzo_delta(const int32_t* __restrict__ p
     return (long long)p[j] - pred;
 }
 
-// Codes of one tile (1024 nodes, 4 per thread, strided by 256) and its
-// outlier count; the outliers themselves are gathered by k_scatter.
+// Lorenzo codes by line sweeps.  The 3-D predictor error is the difference
+// of the 2-D (x, y) errors of consecutive z planes,
+//   d3(x,y,z) = d2(x,y,z) - d2(x,y,z-1),
+//   d2(x,y,z) = p(x,y,z) - p(x-1,y,z) - p(x,y-1,z) + p(x-1,y-1,z),
+// and the 2-D error the difference of the 1-D (x) errors of consecutive
+// rows, with zero outside the grid; both regroup the terms of the Lorenzo
+// formula exactly.  |p| < 2^27 keeps every partial in int32.  A wave owns
+// 64 consecutive x of one row (3-D) or of a run of rows (2-D) and sweeps
+// MC_LZ_CHUNK planes (rows), carrying the previous plane's (row's) error in a
+// register, so each node costs four (two) coalesced loads.  Outliers are
+// counted per 1024-node tile with at most two atomics per wave and row (a
+// 64-run meets at most two tiles); the counts were zeroed by k_resample.
+// Loads are unconditional (inactive lanes read node 0, neighbours outside
+// the grid are masked with bitwise ands, not selects) so that the compiler
+// keeps a sweep's loads together instead of sinking them into branches.
+// The result of an inactive lane is never used.
 template <int D>
-__global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, int n0, int n1, int n2,
-                                                 long long ng, uint16_t* __restrict__ codes,
+__device__ __forceinline__ int lz_line(const int32_t* __restrict__ p, unsigned j, bool act, bool hx, bool hy,
+                                       unsigned n0)
+{
+    const unsigned jj = act ? j : 0u;
+    const unsigned ox = (hx && act) ? 1u : 0u, oy = (hy && act) ? n0 : 0u;
+    const int mx = -(int)hx, my = -(int)hy;
+    const int a = p[jj];
+    const int b = p[jj - ox];
+    if (D == 2) return a - (b & mx);
+    const int c = p[jj - oy];
+    const int e = p[jj - oy - ox];
+    return ((a - (b & mx)) - (c & my)) + (e & (mx & my));
+}
+
+__device__ __forceinline__ void lz_count(unsigned j, bool out, bool act, unsigned int* __restrict__ count)
+{
+    const unsigned long long m = __ballot(out);
+    if (m == 0ull) return;
+    const unsigned long long live = __ballot(act);
+    const int first = __builtin_ctzll(live), last = 63 - __builtin_clzll(live);
+    const unsigned jf = __shfl(j, first, 64), jl = __shfl(j, last, 64);
+    const unsigned tf = jf / MC_TILE, tl = jl / MC_TILE;
+    const unsigned long long lo = __ballot(out && j / MC_TILE == tf), hi = m & ~lo;
+    if (lane_id() == first) {
+        if (lo) atomicAdd(&count[tf], (unsigned)__popcll(lo));
+        if (hi) atomicAdd(&count[tl], (unsigned)__popcll(hi));
+    }
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
+                                                 unsigned nunits, uint16_t* __restrict__ codes,
                                                  unsigned int* __restrict__ count)
 {
-    __shared__ int s_cnt[4];
-    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
-    const long long n01 = (long long)n0 * n1;
-    long long j = tile * MC_TILE + threadIdx.x;
-    const unsigned j32 = (unsigned)j, r32 = j32 / (unsigned)n0;     // ng < 2^31
-    int i0 = (int)(j32 - r32 * (unsigned)n0);
-    int i1 = (int)(r32 % (unsigned)n1);
-    int i2 = (int)(r32 / (unsigned)n1);
-    int nout = 0;
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        if (j < ng) {
-            const long long d = lorenzo_delta<D>(p, j, i0, i1, i2, n0, n01);
-            const bool in = d >= -(MC_R - 1) && d <= MC_R - 1;
-            codes[j] = in ? (uint16_t)(d + MC_R) : (uint16_t)0;
-            nout += in ? 0 : 1;
-        }
-        j += MC_WG;
-        i0 += MC_WG;
-        while (i0 >= n0) {
-            i0 -= n0;
-            if (++i1 == n1) { i1 = 0; ++i2; }
-        }
+    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    if (u >= nunits) return;
+    const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
+    const unsigned x = xs * 64u + (unsigned)lane_id();
+    const bool act = x < (unsigned)n0, hx = x > 0;
+    // the whole sweep's loads are issued before any is used
+    constexpr int CH = MC_LZ_CHUNK;
+    unsigned base, step;
+    int l0, l1;
+    bool hy = false;
+    if (D == 3) {
+        const unsigned y = r % (unsigned)n1, zc = r / (unsigned)n1;
+        base = x + (unsigned)n0 * y;
+        step = (unsigned)n0 * (unsigned)n1;
+        l0 = (int)zc * CH;
+        l1 = min(l0 + CH, n2);
+        hy = y > 0;
+    } else {
+        base = x;
+        step = (unsigned)n0;
+        l0 = (int)r * CH;
+        l1 = min(l0 + CH, n1);
     }
-    nout = wave_sum(nout);
-    if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = nout;
-    __syncthreads();
-    if (threadIdx.x == 0) count[tile] = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+    // plane (row) l0 - 1 for the first difference; past the end, the last
+    // plane (row) is read again and ignored
+    const int pz = lz_line<D>(p, base + step * (unsigned)(l0 > 0 ? l0 - 1 : 0), act, hx, hy, (unsigned)n0);
+    int prev = l0 > 0 ? pz : 0;
+    int cur[CH];
+#pragma unroll
+    for (int k = 0; k < CH; ++k) cur[k] = lz_line<D>(p, base + step * (unsigned)min(l0 + k, l1 - 1), act, hx, hy, (unsigned)n0);
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        if (l0 + k >= l1) break;
+        const int d = cur[k] - prev;
+        prev = cur[k];
+        const unsigned j = base + step * (unsigned)(l0 + k);
+        const bool in = d >= -(MC_R - 1) && d <= MC_R - 1;
+        if (act) codes[j] = in ? (uint16_t)(d + MC_R) : (uint16_t)0;
+        lz_count(j, act && !in, act, count);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// g(x1') at a vertex: multilinear interpolation of the reconstructed grid.
-template <int D>
-__device__ __forceinline__ float back_interp(const float* __restrict__ coords, long long nv, long long v,
-                                             const GridGeom& gg, const float* __restrict__ xh)
-{
-    int i0, i1, i2 = 0;
-    float t0, t1, t2 = 0.0f;
-    axis_cell(coords[v], gg.of[0], gg.ihf[0], gg.n0, i0, t0);
-    axis_cell(coords[nv + v], gg.of[1], gg.ihf[1], gg.n1, i1, t1);
-    if (D == 3) axis_cell(coords[2 * nv + v], gg.of[2], gg.ihf[2], gg.n2, i2, t2);
-    const int n0 = gg.n0;
-    const unsigned n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
-    const unsigned j = (unsigned)i0 + (unsigned)n0 * (unsigned)i1 + n01 * (unsigned)i2;
-    const float c00 = lerpf_(xh[j], xh[j + 1], t0);
-    const float c10 = lerpf_(xh[j + n0], xh[j + n0 + 1], t0);
-    const float c0 = lerpf_(c00, c10, t1);
-    if (D == 2) return c0;
-    const float c01 = lerpf_(xh[j + n01], xh[j + n01 + 1], t0);
-    const float c11 = lerpf_(xh[j + n01 + n0], xh[j + n01 + n0 + 1], t0);
-    const float c1 = lerpf_(c01, c11, t1);
-    return lerpf_(c0, c1, t2);
-}
-
 __device__ __forceinline__ int zz_bits(int k)
 {
     const unsigned z = ((unsigned)k << 1) ^ (unsigned)(k >> 31);
@@ -271,26 +313,40 @@ __global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ 
 {
     __shared__ long long s_red[4];
     const DevBound b = make_bound(range, bp);
-    const long long lb = xcd_tile(blockIdx.x, gridDim.x);
-    const long long v = lb * 256 + threadIdx.x;
+    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
     const int ocost = 32 + 8 * (int)sizeof(T);
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    T xv[MC_IPT];
+    int rq[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+        act[i] = v[i] < nv && b.ok;
+        const long long vc = act[i] ? v[i] : 0;
+        xv[i] = x[vc];
+        rq[i] = rho_q[vc];
+    }
+    float g[MC_IPT];
+    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
     int cp = 0, cl = 0;
-    if (v < nv && b.ok) {
-        const float g = back_interp<D>(coords, nv, v, gg, xh);
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        if (!act[i]) continue;
         int qi;
-        if (quantize_residual<T>(x[v], g, b, qi)) {
-            const int l = qi - rho_q[v];
-            cp = zz_bits(qi);
-            cl = (l >= -(MC_R - 1) && l <= MC_R - 1) ? zz_bits(l) : ocost;
+        if (quantize_residual<T>(xv[i], g[i], b, qi)) {
+            const int l = qi - rq[i];
+            cp += zz_bits(qi);
+            cl += (l >= -(MC_R - 1) && l <= MC_R - 1) ? zz_bits(l) : ocost;
         } else {
-            cp = ocost;
-            cl = ocost;
+            cp += ocost;
+            cl += ocost;
         }
     }
     const long long sp = block_sum_i64(cp, s_red);
     const long long sl = block_sum_i64(cl, s_red);
     if (threadIdx.x == 0) {
-        const long long blk = (lb * 256) / MC_LBLOCK;
+        const long long blk = (tile * MC_TILE) / MC_LBLOCK;   // a tile lies inside one block
         atomicAdd(&bcost[2 * blk], (unsigned)sp);
         atomicAdd(&bcost[2 * blk + 1], (unsigned)sl);
     }
@@ -314,22 +370,33 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
     const long long blk = (tile * MC_TILE) / MC_LBLOCK;
     bool learned = false;
     if (LEARNED) learned = bcost[2 * blk + 1] < bcost[2 * blk];
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    T xv[MC_IPT];
+    int rq[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+        act[i] = v[i] < nv && b.ok;
+        const long long vc = act[i] ? v[i] : 0;
+        xv[i] = x[vc];
+        rq[i] = (LEARNED && learned) ? rho_q[vc] : 0;
+    }
+    float g[MC_IPT];
+    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
     int nout = 0;
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
-        const long long v = tile * MC_TILE + i * MC_WG + threadIdx.x;
-        if (v < nv && b.ok) {
-            const float g = back_interp<D>(coords, nv, v, gg, xh);
-            if (dbg_g) dbg_g[v] = g;
-            int qi;
-            bool ok = quantize_residual<T>(x[v], g, b, qi);
-            if (LEARNED && ok && learned) {
-                qi -= rho_q[v];
-                ok = qi >= -(MC_R - 1) && qi <= MC_R - 1;
-            }
-            codes[v] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
-            nout += ok ? 0 : 1;
+        if (!act[i]) continue;
+        if (dbg_g) dbg_g[v[i]] = g[i];
+        int qi;
+        bool ok = quantize_residual<T>(xv[i], g[i], b, qi);
+        if (LEARNED && ok && learned) {
+            qi -= rq[i];
+            ok = qi >= -(MC_R - 1) && qi <= MC_R - 1;
         }
+        codes[v[i]] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
+        nout += ok ? 0 : 1;
     }
     const bool first_of_block = (tile * MC_TILE) % MC_LBLOCK == 0;
     nout = wave_sum(nout);
@@ -490,13 +557,14 @@ hipError_t range(const void* x, int dtype, long long n, unsigned long long* part
 
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
                     const RangeOut* range, BoundParams bp, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
-                    long long nbflags, unsigned int* err, mc_result* res, hipStream_t s)
+                    long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
+                    hipStream_t s)
 {
     ProfScope ps("k_resample", s);
     const long long need = ng > nbflags ? ng : nbflags;
     dim3 grid((unsigned)((need + 255) / 256));
 #define MC_RS(T, D) hipLaunchKernelGGL((k_resample<T, D>), grid, dim3(256), 0, s, vid, w, ng, (const T*)x, range, bp, \
-                                       p, xh, dbg_v, bflags, nbflags, err, res, dtype)
+                                       p, xh, dbg_v, bflags, nbflags, err, res, dtype, gcount, ntg)
     if (dtype == MC_F64) { if (dim == 2) MC_RS(double, 2); else MC_RS(double, 3); }
     else { if (dim == 2) MC_RS(float, 2); else MC_RS(float, 3); }
 #undef MC_RS
@@ -507,11 +575,16 @@ hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long 
                    unsigned int* count, hipStream_t s)
 {
     ProfScope ps("k_lorenzo", s);
-    const long long ntiles = (ng + MC_TILE - 1) / MC_TILE;
+    (void)ng;
+    const int nxs = (n0 + 63) / 64;
+    const long long lines = (long long)nxs * (dim == 3 ? (long long)n1 : 1);
+    const int len = dim == 3 ? n2 : n1;
+    const unsigned nunits = (unsigned)(lines * ((len + MC_LZ_CHUNK - 1) / MC_LZ_CHUNK));
+    dim3 grid((nunits + 3) / 4);
     if (dim == 2)
-        hipLaunchKernelGGL(k_lorenzo<2>, dim3((unsigned)ntiles), dim3(256), 0, s, p, n0, n1, n2, ng, codes, count);
+        hipLaunchKernelGGL(k_lorenzo<2>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count);
     else
-        hipLaunchKernelGGL(k_lorenzo<3>, dim3((unsigned)ntiles), dim3(256), 0, s, p, n0, n1, n2, ng, codes, count);
+        hipLaunchKernelGGL(k_lorenzo<3>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count);
     return hipGetLastError();
 }
 
@@ -522,7 +595,7 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
     const bool L = rho_q != nullptr;
     if (L) {
         ProfScope ps("k_learned_cost", s);
-        dim3 grid((unsigned)((nv + 255) / 256));
+        dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
 #define MC_LC(T, D) hipLaunchKernelGGL((k_learned_cost<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, \
                                        range, bp, rho_q, bcost)
         if (dtype == MC_F64) { if (gg.dim == 2) MC_LC(double, 2); else MC_LC(double, 3); }

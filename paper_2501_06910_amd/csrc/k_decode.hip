@@ -240,6 +240,193 @@ __global__ __launch_bounds__(256) void k_dec_z_apply(const uint16_t* __restrict_
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3-D decode on quads of x (n0 a multiple of 4, n0 <= 1024): the same five
+// passes as above, but every lane owns four consecutive x (8-byte code
+// loads, 16-byte integer and float stores) and issues all the loads of its
+// sweep before using any.
+//   k_d3_ztot    per (256-column segment, row, chunk of MC_DZ planes):
+//                the chunk's error sums
+//   (k_dec_z_carry: exclusive prefix over the plane chunks, in place)
+//   k_d3_zapply  workgroup = 4 waves x 2 rows = MC_DY rows of one segment,
+//                sweeping one plane chunk: z-prefixed errors written, and
+//                the MC_DY-row column sums of every plane (LDS reduction)
+//   (k_dec_xy_carry: exclusive prefix over the row chunks, in place)
+//   k_d3_xyapply wave = (plane, chunk of MC_DY rows), whole rows: running
+//                column sums from the carry plus a row scan, x1' written
+#define MC_DZ MC_DZ_PLANES
+#define MC_DY MC_DY_ROWS
+static_assert(MC_DY == 8, "k_d3_zapply: 4 waves x 2 rows");
+
+__device__ __forceinline__ ushort4 ld_codes4(const uint16_t* __restrict__ codes, unsigned j, bool act)
+{
+    if (!act) return make_ushort4(0, 0, 0, 0);
+    return *reinterpret_cast<const ushort4*>(codes + j);
+}
+
+__device__ __forceinline__ int dec1(unsigned c, const int32_t* __restrict__ oidx, const int32_t* __restrict__ odelta,
+                                    long long nout, unsigned j)
+{
+    if (c != 0u) return (int)c - MC_R;
+    const long long k = find_outlier(oidx, nout, (long long)j);
+    return k >= 0 ? odelta[k] : 0;
+}
+
+__global__ __launch_bounds__(256) void k_d3_ztot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                 const int32_t* __restrict__ odelta,
+                                                 const mc_result* __restrict__ res, long long gcap, int n0, int n1,
+                                                 int n2, int nxs, unsigned nunits, int* __restrict__ aggz)
+{
+    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    if (u >= nunits) return;
+    const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
+    const unsigned y = r % (unsigned)n1, zc = r / (unsigned)n1;
+    const unsigned x = xs * 256u + 4u * (unsigned)lane_id();
+    const bool act = x < (unsigned)n0;
+    const unsigned nxy = (unsigned)n0 * (unsigned)n1, base = x + (unsigned)n0 * y;
+    const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    ushort4 c[MC_DZ];
+#pragma unroll
+    for (int k = 0; k < MC_DZ; ++k) c[k] = ld_codes4(codes, base + nxy * (unsigned)(z0 + k), act && z0 + k < z1);
+    int4 t = make_int4(0, 0, 0, 0);
+#pragma unroll
+    for (int k = 0; k < MC_DZ; ++k) {
+        const unsigned j = base + nxy * (unsigned)(z0 + k);
+        t.x += dec1(c[k].x, oidx, odelta, nout, j);
+        t.y += dec1(c[k].y, oidx, odelta, nout, j + 1);
+        t.z += dec1(c[k].z, oidx, odelta, nout, j + 2);
+        t.w += dec1(c[k].w, oidx, odelta, nout, j + 3);
+    }
+    if (act) *reinterpret_cast<int4*>(aggz + (size_t)zc * nxy + base) = t;
+}
+
+__global__ __launch_bounds__(256) void k_d3_zapply(const uint16_t* __restrict__ codes,
+                                                   const int32_t* __restrict__ oidx,
+                                                   const int32_t* __restrict__ odelta,
+                                                   const mc_result* __restrict__ res, long long gcap, int n0, int n1,
+                                                   int n2, int nxs, int nyc, const int* __restrict__ carryz,
+                                                   int32_t* __restrict__ pz, int* __restrict__ agg_xy)
+{
+    __shared__ int4 s_cs[2][4][64];
+    const unsigned t = xcd_tile(blockIdx.x, gridDim.x);          // grid = exactly the tiles: no early exit
+    const unsigned xs = t % (unsigned)nxs, r = t / (unsigned)nxs;
+    const unsigned yc = r % (unsigned)nyc, zc = r / (unsigned)nyc;
+    const int w = threadIdx.x >> 6;
+    const unsigned x = xs * 256u + 4u * (unsigned)lane_id();
+    const bool actx = x < (unsigned)n0;
+    const unsigned nxy = (unsigned)n0 * (unsigned)n1;
+    const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    unsigned rb[2];
+    bool ar[2];
+    int4 run[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const unsigned y = yc * MC_DY + 2u * (unsigned)w + (unsigned)q;
+        ar[q] = actx && y < (unsigned)n1;
+        rb[q] = x + (unsigned)n0 * y;
+        run[q] = ar[q] ? *reinterpret_cast<const int4*>(carryz + (size_t)zc * nxy + rb[q]) : make_int4(0, 0, 0, 0);
+    }
+    ushort4 c[MC_DZ][2];
+#pragma unroll
+    for (int k = 0; k < MC_DZ; ++k)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) c[k][q] = ld_codes4(codes, rb[q] + nxy * (unsigned)(z0 + k), ar[q] && z0 + k < z1);
+#pragma unroll
+    for (int k = 0; k < MC_DZ; ++k) {
+        const bool zin = z0 + k < z1;
+        int4 cs = make_int4(0, 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const unsigned j = rb[q] + nxy * (unsigned)(z0 + k);
+            if (ar[q] && zin) {
+                run[q].x += dec1(c[k][q].x, oidx, odelta, nout, j);
+                run[q].y += dec1(c[k][q].y, oidx, odelta, nout, j + 1);
+                run[q].z += dec1(c[k][q].z, oidx, odelta, nout, j + 2);
+                run[q].w += dec1(c[k][q].w, oidx, odelta, nout, j + 3);
+                *reinterpret_cast<int4*>(pz + j) = run[q];
+                cs.x += run[q].x;
+                cs.y += run[q].y;
+                cs.z += run[q].z;
+                cs.w += run[q].w;
+            }
+        }
+        s_cs[k & 1][w][lane_id()] = cs;
+        __syncthreads();
+        if (w == 0 && zin && actx) {
+            int4 a = s_cs[k & 1][0][lane_id()];
+#pragma unroll
+            for (int v = 1; v < 4; ++v) {
+                const int4 b = s_cs[k & 1][v][lane_id()];
+                a.x += b.x;
+                a.y += b.y;
+                a.z += b.z;
+                a.w += b.w;
+            }
+            *reinterpret_cast<int4*>(agg_xy + ((size_t)(z0 + k) * nyc + yc) * n0 + x) = a;
+        }
+    }
+}
+
+template <int NXS>
+__global__ __launch_bounds__(256) void k_d3_xyapply(const int32_t* __restrict__ pz, const mc_result* __restrict__ res,
+                                                    int n0, int n1, int nyc, unsigned nunits,
+                                                    const int* __restrict__ carry, float* __restrict__ xh)
+{
+    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    if (u >= nunits) return;
+    const unsigned z = u / (unsigned)nyc, yc = u % (unsigned)nyc;
+    const int y0 = (int)yc * MC_DY, y1 = min(y0 + MC_DY, n1);
+    const double c = res->c, step1 = 2.0 * res->tau1;
+    const unsigned plane = (unsigned)n0 * (unsigned)n1 * z;
+    int4 col[NXS];
+    bool act[NXS];
+#pragma unroll
+    for (int sg = 0; sg < NXS; ++sg) {
+        const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
+        act[sg] = x < (unsigned)n0;
+        col[sg] = act[sg] ? *reinterpret_cast<const int4*>(carry + ((size_t)z * nyc + yc) * n0 + x)
+                          : make_int4(0, 0, 0, 0);
+    }
+    int4 v[MC_DY][NXS];
+#pragma unroll
+    for (int k = 0; k < MC_DY; ++k)
+#pragma unroll
+        for (int sg = 0; sg < NXS; ++sg) {
+            const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
+            v[k][sg] = (act[sg] && y0 + k < y1)
+                           ? *reinterpret_cast<const int4*>(pz + plane + (unsigned)n0 * (unsigned)(y0 + k) + x)
+                           : make_int4(0, 0, 0, 0);
+        }
+#pragma unroll
+    for (int k = 0; k < MC_DY; ++k) {
+        if (y0 + k >= y1) break;
+        int rowoff = 0;
+#pragma unroll
+        for (int sg = 0; sg < NXS; ++sg) {
+            col[sg].x += v[k][sg].x;
+            col[sg].y += v[k][sg].y;
+            col[sg].z += v[k][sg].z;
+            col[sg].w += v[k][sg].w;
+            const int a0 = col[sg].x, a1 = a0 + col[sg].y, a2 = a1 + col[sg].z, a3 = a2 + col[sg].w;
+            const int inc = wave_incl_scan(a3);
+            const int off = rowoff + inc - a3;
+            rowoff += __shfl(inc, 63, 64);
+            const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
+            if (act[sg]) {
+                float4 o;
+                o.x = xhat_of(off + a0, c, step1);
+                o.y = xhat_of(off + a1, c, step1);
+                o.z = xhat_of(off + a2, c, step1);
+                o.w = xhat_of(off + a3, c, step1);
+                *reinterpret_cast<float4*>(xh + plane + (unsigned)n0 * (unsigned)(y0 + k) + x) = o;
+            }
+        }
+    }
+}
+
+// Four vertices per thread (tile of 1024), every load issued before use.
 template <typename T, int D, bool LEARNED>
 __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                  const float* __restrict__ xh, const uint16_t* __restrict__ codes,
@@ -248,38 +435,38 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
                                                  const int32_t* __restrict__ rho_q,
                                                  const uint32_t* __restrict__ bflags, T* __restrict__ xout)
 {
-    const long long v = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
-    if (v >= nv) return;
-    const int code = codes[v];
-    if (code == 0) {
-        const long long n = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
-        const long long k = find_outlier(oidx, n, v);
-        xout[v] = k >= 0 ? oval[k] : (T)0;
-        return;
-    }
-    const double step2 = 2.0 * res->tau2;
-    int i0, i1, i2 = 0;
-    float t0, t1, t2 = 0.0f;
-    axis_cell(coords[v], gg.of[0], gg.ihf[0], gg.n0, i0, t0);
-    axis_cell(coords[nv + v], gg.of[1], gg.ihf[1], gg.n1, i1, t1);
-    if (D == 3) axis_cell(coords[2 * nv + v], gg.of[2], gg.ihf[2], gg.n2, i2, t2);
-    const int n0 = gg.n0;
-    const unsigned n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
-    const unsigned j = (unsigned)i0 + (unsigned)n0 * (unsigned)i1 + n01 * (unsigned)i2;
-    const float c00 = lerpf_(xh[j], xh[j + 1], t0);
-    const float c10 = lerpf_(xh[j + n0], xh[j + n0 + 1], t0);
-    float g = lerpf_(c00, c10, t1);
-    if (D == 3) {
-        const float c01 = lerpf_(xh[j + n01], xh[j + n01 + 1], t0);
-        const float c11 = lerpf_(xh[j + n01 + n0], xh[j + n01 + n0 + 1], t0);
-        g = lerpf_(g, lerpf_(c01, c11, t1), t2);
-    }
-    int q = code - MC_R;
+    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+    bool learned = false;
     if (LEARNED) {
-        const long long blk = v / MC_LBLOCK;
-        if ((bflags[blk >> 5] >> (blk & 31)) & 1u) q += rho_q[v];
+        const long long blk = (tile * MC_TILE) / MC_LBLOCK;       // a tile lies inside one block
+        learned = (bflags[blk >> 5] >> (blk & 31)) & 1u;
     }
-    xout[v] = (T)((double)g + (double)q * step2);
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    int code[MC_IPT], rq[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+        act[i] = v[i] < nv;
+        const long long vc = act[i] ? v[i] : 0;
+        code[i] = codes[vc];
+        rq[i] = (LEARNED && learned) ? rho_q[vc] : 0;
+    }
+    float g[MC_IPT];
+    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    const double step2 = 2.0 * res->tau2;
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        if (!act[i]) continue;
+        if (code[i] == 0) {
+            const long long n = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
+            const long long k = find_outlier(oidx, n, v[i]);
+            xout[v[i]] = k >= 0 ? oval[k] : (T)0;
+        } else {
+            const int q = code[i] - MC_R + rq[i];
+            xout[v[i]] = (T)((double)g[i] + (double)q * step2);
+        }
+    }
 }
 
 namespace mck {
@@ -305,6 +492,48 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         else MC_DXT(128);
 #undef MC_DXT
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if (ws.fast3) {
+        const long long nxy = (long long)n0 * n1;
+        const int nxs = (n0 + 255) / 256;
+        {
+            ProfScope ps("k_dec_z_tot", s);
+            const unsigned nunits = (unsigned)((long long)nxs * n1 * ws.nzc);
+            hipLaunchKernelGGL(k_d3_ztot, dim3((nunits + 3) / 4), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0,
+                               n1, n2, nxs, nunits, ws.agg_z);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_z_carry", s);
+            hipLaunchKernelGGL(k_dec_z_carry, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, s, ws.agg_z, nxy,
+                               ws.nzc);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_z_apply", s);
+            const unsigned ntiles = (unsigned)((long long)nxs * ws.nyc * ws.nzc);
+            hipLaunchKernelGGL(k_d3_zapply, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2,
+                               nxs, ws.nyc, ws.agg_z, pz, ws.agg_xy);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_xy_carry", s);
+            hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)(((long long)n0 * n2 + 255) / 256)), dim3(256), 0, s,
+                               ws.agg_xy, n0, n2, ws.nyc);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_xy_apply", s);
+            const unsigned nunits = (unsigned)((long long)n2 * ws.nyc);
+            dim3 g((nunits + 3) / 4);
+            if (nxs == 1)
+                hipLaunchKernelGGL(k_d3_xyapply<1>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+            else if (nxs == 2)
+                hipLaunchKernelGGL(k_d3_xyapply<2>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+            else
+                hipLaunchKernelGGL(k_d3_xyapply<4>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        return hipSuccess;
     } else {
         const long long nxy = (long long)n0 * n1;
         const int cx = (n0 + 255) / 256;
@@ -373,7 +602,7 @@ hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const f
                          const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, hipStream_t s)
 {
     ProfScope ps(rho_q ? "k_vdecode_learned" : "k_vdecode", s);
-    dim3 grid((unsigned)((nv + 255) / 256));
+    dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
 #define MC_VD(T, D, L) hipLaunchKernelGGL((k_vdecode<T, D, L>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, oidx, \
                                           (const T*)oval, res, vcap, rho_q, bflags, (T*)xout)
     const bool L = rho_q != nullptr;

@@ -318,6 +318,15 @@ GridGeom mc_geom(const mc_grid& g)
 static void decode_ws_shape(mc_plan p)
 {
     const long long n0 = p->grid.dims[0], n1 = p->grid.dims[1], n2 = p->grid.dims[2];
+    p->dws.fast3 = p->dim == 3 && n0 % 4 == 0 && n0 <= 1024;
+    if (p->dws.fast3) {
+        p->dws.rows = MC_DY_ROWS;
+        p->dws.nyc = (int)((n1 + MC_DY_ROWS - 1) / MC_DY_ROWS);
+        p->dws.ntiles_xy = (long long)p->dws.nyc * n2;
+        p->dws.zplanes = MC_DZ_PLANES;
+        p->dws.nzc = (int)((n2 + MC_DZ_PLANES - 1) / MC_DZ_PLANES);
+        return;
+    }
     long long rows;
     if (p->dim == 2) {
         rows = (n1 + 1023) / 1024;          // about 1024 wave tiles
@@ -561,7 +570,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     RangeOut* cur = p->rbuf;
     ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, p->small, p->nsmall, s));
     ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, cur, bp, p->p, p->xh, codes->dbg_resampled,
-                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, s));
+                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, s));
     ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
                       codes->grid_codes, p->gcount, s));
     const int32_t* rho = nullptr;

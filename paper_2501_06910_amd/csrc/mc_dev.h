@@ -13,6 +13,9 @@
 
 #define MC_R 32768
 #define MC_TILE 1024          // items per workgroup tile (256 threads x 4)
+#define MC_LZ_CHUNK 16        // planes (rows) per Lorenzo sweep
+#define MC_DZ_PLANES 8        // 3-D decode: planes per z chunk
+#define MC_DY_ROWS 8          // 3-D decode: rows per xy chunk (4 waves x 2 rows)
 #define MC_WG 256
 #define MC_IPT 4              // items per thread in a tile
 #define MC_LBLOCK 4096        // vertices per learned/plain decision block
@@ -100,15 +103,12 @@ __device__ __forceinline__ float lerpf_(float a, float b, float t)
 // u = (P - of) * ihf, i = clamp(floor(u), 0, n-2), t = clamp(u - i, 0, 1).
 __device__ __forceinline__ void axis_cell(float P, float of, float ihf, int n, int& i, float& t)
 {
-    float u = (P - of) * ihf;
-    float fl = floorf(u);
-    if (fl < 0.0f) i = 0;
-    else if (fl > (float)(n - 2)) i = n - 2;
-    else i = (int)fl;
-    float tt = u - (float)i;
-    if (tt < 0.0f) tt = 0.0f;
-    if (tt > 1.0f) tt = 1.0f;
-    t = tt;
+    const float u = (P - of) * ihf;
+    const float fl = floorf(u);
+    const int ic = (int)fl;
+    i = fl < 0.0f ? 0 : (fl > (float)(n - 2) ? n - 2 : ic);
+    const float tt = u - (float)i;
+    t = tt < 0.0f ? 0.0f : (tt > 1.0f ? 1.0f : tt);
 }
 
 // XCD-aware tile order.  Workgroups are handed to the 8 XCDs round-robin
@@ -120,6 +120,63 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
 {
     const unsigned per = n >> 3, rem = n & 7u, x = b & 7u, r = b >> 3;
     return (x < rem ? x * (per + 1u) : rem * (per + 1u) + (x - rem) * per) + r;
+}
+
+// ---------------------------------------------------------------------------
+// g(x1') for N vertices of one thread, loads first: all coordinates, then
+// every corner of every cell, then the nested lerps (x, then y, then z) in
+// the order of the definition.  act[i] false: vertex 0 stands in (its
+// result is ignored), so no load depends on a branch.
+template <int D, int N>
+__device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, long long nv, const GridGeom& gg,
+                                              const float* __restrict__ xh, const long long (&v)[N],
+                                              const bool (&act)[N], float (&g)[N])
+{
+    float P[N][3];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const long long vc = act[i] ? v[i] : 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[i][d] = coords[d * nv + vc];
+    }
+    const unsigned n0 = (unsigned)gg.n0, n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
+    unsigned j[N];
+    float t[N][3];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        int i0, i1, i2 = 0;
+        axis_cell(P[i][0], gg.of[0], gg.ihf[0], gg.n0, i0, t[i][0]);
+        axis_cell(P[i][1], gg.of[1], gg.ihf[1], gg.n1, i1, t[i][1]);
+        if (D == 3) axis_cell(P[i][2], gg.of[2], gg.ihf[2], gg.n2, i2, t[i][2]);
+        j[i] = (unsigned)i0 + n0 * (unsigned)i1 + n01 * (unsigned)i2;
+    }
+    float c[N][8];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        c[i][0] = xh[j[i]];
+        c[i][1] = xh[j[i] + 1];
+        c[i][2] = xh[j[i] + n0];
+        c[i][3] = xh[j[i] + n0 + 1];
+        if (D == 3) {
+            c[i][4] = xh[j[i] + n01];
+            c[i][5] = xh[j[i] + n01 + 1];
+            c[i][6] = xh[j[i] + n01 + n0];
+            c[i][7] = xh[j[i] + n01 + n0 + 1];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float c00 = lerpf_(c[i][0], c[i][1], t[i][0]);
+        const float c10 = lerpf_(c[i][2], c[i][3], t[i][0]);
+        const float c0 = lerpf_(c00, c10, t[i][1]);
+        if (D == 2) {
+            g[i] = c0;
+        } else {
+            const float c01 = lerpf_(c[i][4], c[i][5], t[i][0]);
+            const float c11 = lerpf_(c[i][6], c[i][7], t[i][0]);
+            g[i] = lerpf_(c0, lerpf_(c01, c11, t[i][1]), t[i][2]);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

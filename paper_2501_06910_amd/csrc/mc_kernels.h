@@ -55,7 +55,8 @@ hipError_t range(const void* x, int dtype, long long n, unsigned long long* part
                  unsigned int* zero, long long nzero, hipStream_t s);
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
                     const RangeOut* range, BoundParams bp, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
-                    long long nbflags, unsigned int* err, mc_result* res, hipStream_t s);
+                    long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
+                    hipStream_t s);
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
                    unsigned int* count, hipStream_t s);
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
@@ -68,6 +69,7 @@ hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, cons
 
 // ---- decompression (k_decode.hip) -----------------------------------------
 struct DecodeWs {
+    bool fast3;                    // 3-D with n0 % 4 == 0 and n0 <= 1024: the quad kernels
     int rows, nyc;                 // rows per tile, row chunks per plane
     long long ntiles_xy;           // nyc * n2
     int* agg_xy;                   // [ntiles_xy][n0] column totals, then carries

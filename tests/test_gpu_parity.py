@@ -58,6 +58,11 @@ def _cases():
     m4 = G.kuhn_tet_mesh(17, 6)
     x4 = G.field_octaves(m4.coords, np.random.default_rng(2), dtype=np.float64)
     out.append(("kuhn3d_f64_tiny_eb", m4, x4, (20, 19, 18), 1e-7, True, 0.9, "midrange"))
+    # x extent a multiple of 4 above 256 (two 256-column segments in the 3-D
+    # decode), ragged y and z chunks, grid outliers at eb 1e-6
+    m6 = G.kuhn_tet_mesh(30, 8)
+    out.append(("kuhn3d_wide_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(3)), (264, 21, 13), 1e-6,
+                True, 0.5, "nearest"))
     mesh5, f5, _ = G.config_large_2d(h0=0.004, dims=200)
     out.append(("refined2d_f64", mesh5, f5, (200, 200), 1e-6, True, 0.5, "nearest"))
     return out
