@@ -43,7 +43,7 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
     return table.get(kernel, 0)
 
 
-COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_residual", "k_scan_counts",
+COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_residual",
                      "k_scatter", "k_mlp_infer_c")
 DECOMPRESS_PREFIXES = ("k_dec_", "k_vdecode", "k_mlp_infer_d")
 
@@ -364,6 +364,7 @@ def main():
     ap.add_argument("--split", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time series section")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch order (no autotuning)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cr-sweep", action="store_true", help="print the CR sweep over eb and split instead")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="mesh size scale of the batch workload")
@@ -406,6 +407,12 @@ def main():
     ng = plan.n_grid
     log(f"plan built in {plan_s:.2f} s: {info}")
 
+    tune = {"remap_mask": plan.remap_mask, "seconds": 0.0}
+    if not args.no_tune:
+        t0 = time.time()
+        tune["remap_mask"] = plan.tune(x, args.eb, "rel", args.split, reps=5)
+        tune["seconds"] = round(time.time() - t0, 3)
+        log(f"tuned launch order: remap mask 0x{tune['remap_mask']:02x} in {tune['seconds']} s")
     codes = M.Codes(plan, x.dtype)
     out = torch.empty_like(x)
 
@@ -508,6 +515,7 @@ def main():
         "max_abs_err_over_tau": round(err / res["tau"], 4),
         "ms_per_step_with_kernel_events": round(ms_step_ev, 4),
         "plan_seconds": round(plan_s, 3),
+        "tuning": tune,
         "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
         "kernels": kernels,
     }

@@ -185,6 +185,31 @@ mc_status mc_compress(mc_plan plan, const void* d_field, mc_dtype dtype,
 mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
                         void* d_field_out, mc_dtype dtype, hipStream_t stream);
 
+/* ---- autotuning -----------------------------------------------------------
+ * Launch-order knobs of a plan: bit k of remap_mask set = kernel k takes
+ * its tiles in XCD-contiguous order (each of the 8 XCDs, with its own L2,
+ * gets one contiguous run of tiles), clear = in launch order.  Bits: 0
+ * resample, 1 Lorenzo codes, 2 residual codes (and the learned block
+ * costs), 3 vertex decode, 4/5/6 the 3-D grid decode's z totals, z apply
+ * and xy apply.  Codes and values never depend on the knobs.  Default: all
+ * set. */
+typedef struct {
+    uint32_t remap_mask;
+    uint32_t reserved[3];
+} mc_tuning;
+
+mc_status mc_plan_get_tuning(mc_plan plan, mc_tuning* out);
+mc_status mc_plan_set_tuning(mc_plan plan, const mc_tuning* tuning);
+/* Times every knob both ways on this plan and keeps, bit by bit, the
+ * setting with the smaller summed kernel time of `reps` compress +
+ * decompress passes of d_field (after one warm-up pass).  codes and d_out
+ * (T[n_vertices]) receive the last pass's results.  Uses the library's
+ * profiler, whose accumulated figures it clears.  Writes the choice to
+ * *chosen if not NULL.  (sync) */
+mc_status mc_plan_tune(mc_plan plan, const void* d_field, mc_dtype dtype, const mc_params* params,
+                       const mc_codes* codes, void* d_out, int32_t reps, hipStream_t stream,
+                       mc_tuning* chosen);
+
 /* One-shot form: builds a plan for the mesh and a grid with the given
  * spacing, compresses, and releases the plan.  (sync) */
 mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_cells, int32_t dim,

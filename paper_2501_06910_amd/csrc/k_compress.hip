@@ -12,13 +12,12 @@
 //   k_residual       g: multilinear x1' at each vertex, residual quantisation
 //                    with the per-vertex bound check, learned shift in the
 //                    blocks where it is cheaper, per-tile outlier counts
-//   k_scan_counts    exclusive scan of the per-tile counts
 //   k_scatter        outlier lists in index order (wave ballots)
 #include "mc_dev.h"
 #include "mc_kernels.h"
 
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool VEC>
 __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long long n,
                                                unsigned long long* __restrict__ partial,
                                                unsigned int* __restrict__ zero, long long nzero)
@@ -30,8 +29,44 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long lon
     for (long long i = gid; i < nzero; i += stride) zero[i] = 0u;
     double mn = __builtin_inf(), mx = -__builtin_inf();
     bool bad = false;
+    if (VEC) {
+        // quads of 16-byte aligned values, 4 quads per thread in flight
+        const long long nq = n / 4;
+        constexpr int UQ = 8;
+        long long q = gid;
+        for (; q + (UQ - 1) * stride < nq; q += UQ * stride) {
+            Quad<T> v[UQ];
+#pragma unroll
+            for (int u = 0; u < UQ; ++u) v[u] = load_quad(x + 4 * (q + u * stride));
+#pragma unroll
+            for (int u = 0; u < UQ; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const double d = (double)v[u].v[e];
+                    bad |= !isfinite(d);
+                    mn = fmin(mn, d);
+                    mx = fmax(mx, d);
+                }
+        }
+        for (; q < nq; q += stride) {
+            const Quad<T> v = load_quad(x + 4 * q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const double d = (double)v.v[e];
+                bad |= !isfinite(d);
+                mn = fmin(mn, d);
+                mx = fmax(mx, d);
+            }
+        }
+        if (gid < n - 4 * nq) {
+            const double d = (double)x[4 * nq + gid];
+            bad |= !isfinite(d);
+            mn = fmin(mn, d);
+            mx = fmax(mx, d);
+        }
+    }
     constexpr int U = 8;
-    long long i = gid;
+    long long i = VEC ? n : gid;
     for (; i + (U - 1) * stride < n; i += U * stride) {
         T v[U];
 #pragma unroll
@@ -79,17 +114,28 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long lon
 
 // One workgroup folds the per-block partials into the range slot.
 __global__ __launch_bounds__(256) void k_range_final(const unsigned long long* __restrict__ partial, int nparts,
-                                                     RangeOut* __restrict__ out)
+                                                     RangeOut* __restrict__ out, BoundParams bp,
+                                                     DevBound* __restrict__ bout)
 {
     __shared__ unsigned long long s_mn[4], s_mx[4];
     __shared__ unsigned int s_fl[4];
     unsigned long long kmn = ~0ull, kmx = 0ull;
     unsigned int fl = 0;
-    for (int i = threadIdx.x; i < nparts; i += 256) {
-        const unsigned long long a = partial[3 * i], b = partial[3 * i + 1];
-        kmn = a < kmn ? a : kmn;
-        kmx = b > kmx ? b : kmx;
-        fl |= (unsigned)partial[3 * i + 2];
+    for (int i0 = threadIdx.x; i0 < nparts; i0 += 256 * 8) {      // 8 partials per thread in flight
+        unsigned long long a[8], b[8], f[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int i = min(i0 + 256 * u, nparts - 1);
+            a[u] = partial[3 * i];
+            b[u] = partial[3 * i + 1];
+            f[u] = partial[3 * i + 2];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            kmn = a[u] < kmn ? a[u] : kmn;
+            kmx = b[u] > kmx ? b[u] : kmx;
+            fl |= (unsigned)f[u];
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -107,9 +153,13 @@ __global__ __launch_bounds__(256) void k_range_final(const unsigned long long* _
             kmx = s_mx[k] > kmx ? s_mx[k] : kmx;
             fl |= s_fl[k];
         }
-        out->kmin = kmn;
-        out->kmax = kmx;
-        out->flags = fl;
+        RangeOut r;
+        r.kmin = kmn;
+        r.kmax = kmx;
+        r.flags = fl;
+        r.pad = 0;
+        *out = r;
+        *bout = make_bound(&r, bp);
     }
 }
 
@@ -117,15 +167,15 @@ __global__ __launch_bounds__(256) void k_range_final(const unsigned long long* _
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vid, const float* __restrict__ w,
                                                   long long ng, const T* __restrict__ x,
-                                                  const RangeOut* __restrict__ range, BoundParams bp,
+                                                  const DevBound* __restrict__ bnd,
                                                   int32_t* __restrict__ p, float* __restrict__ xh,
                                                   float* __restrict__ dbg_v, uint32_t* __restrict__ bflags,
                                                   long long nbflags, unsigned int* __restrict__ err,
                                                   mc_result* __restrict__ res, int dtype,
-                                                  unsigned int* __restrict__ gcount, long long ntg)
+                                                  unsigned int* __restrict__ gcount, long long ntg, unsigned remap)
 {
-    const DevBound b = make_bound(range, bp);
-    const long long j = (long long)xcd_tile(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+    const DevBound b = *bnd;
+    const long long j = (long long)tile_of(remap) * 256 + threadIdx.x;
     if (bflags && j < nbflags) bflags[j] = 0u;      // learned-block bits start clear
     if (j < ntg) gcount[j] = 0u;                    // grid outlier counts (k_lorenzo adds)
     if (j == 0) {
@@ -137,7 +187,7 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
         res->c = b.c;
         res->xmin = b.xmin;
         res->xmax = b.xmax;
-        if (!b.ok) atomicOr(err, (range->flags & MC_EBIT_NONFINITE) ? MC_EBIT_NONFINITE : MC_EBIT_TAU);
+        if (!b.ok) atomicOr(err, (b.flags & MC_EBIT_NONFINITE) ? MC_EBIT_NONFINITE : MC_EBIT_TAU);
     }
     if (!b.ok || j >= ng) return;
     // all mapping loads, then all field gathers (a node with vid < 0 is a
@@ -195,31 +245,38 @@ __device__ __forceinline__ long long lorenzo_delta(const int32_t* __restrict__ p
 // and the 2-D error the difference of the 1-D (x) errors of consecutive
 // rows, with zero outside the grid; both regroup the terms of the Lorenzo
 // formula exactly.  |p| < 2^27 keeps every partial in int32.  A wave owns
-// 64 consecutive x of one row (3-D) or of a run of rows (2-D) and sweeps
-// MC_LZ_CHUNK planes (rows), carrying the previous plane's (row's) error in a
-// register, so each node costs four (two) coalesced loads.  Outliers are
-// counted per 1024-node tile with at most two atomics per wave and row (a
-// 64-run meets at most two tiles); the counts were zeroed by k_resample.
-// Loads are unconditional (inactive lanes read node 0, neighbours outside
-// the grid are masked with bitwise ands, not selects) so that the compiler
-// keeps a sweep's loads together instead of sinking them into branches.
-// The result of an inactive lane is never used.
-template <int D>
-__device__ __forceinline__ int lz_line(const int32_t* __restrict__ p, unsigned j, bool act, bool hx, bool hy,
-                                       unsigned n0)
+// 63 consecutive x of one row (3-D) or of a run of rows (2-D); its lane 0
+// loads the column to their left, and every lane takes its x - 1
+// neighbours from the lane below with a whole-wave DPP shift, so a node
+// costs two loads (3-D) or one (2-D).  The wave sweeps MC_LZ_CHUNK planes
+// (rows), carrying the previous plane's (row's) error in a register.
+// Outliers are counted per 1024-node tile and per group of tiles with at
+// most two atomics each per wave and row (a 63-run meets at most two
+// tiles); the counts were zeroed before the kernel.
+#define MC_LZ_W 63
+
+__device__ __forceinline__ int lane_below(int v)
 {
-    const unsigned jj = act ? j : 0u;
-    const unsigned ox = (hx && act) ? 1u : 0u, oy = (hy && act) ? n0 : 0u;
+    return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);   // wave_shr:1 (lane 0 gets 0)
+}
+
+// Loads are unconditional (addresses clamped into the grid, neighbours
+// outside it masked with bitwise ands, not selects) so that the compiler
+// keeps a sweep's loads together instead of sinking them into branches.
+template <int D>
+__device__ __forceinline__ int lz_line(const int32_t* __restrict__ p, unsigned j, bool hx, bool hy, unsigned n0)
+{
     const int mx = -(int)hx, my = -(int)hy;
-    const int a = p[jj];
-    const int b = p[jj - ox];
+    const int a = p[j];
+    const int b = lane_below(a);
     if (D == 2) return a - (b & mx);
-    const int c = p[jj - oy];
-    const int e = p[jj - oy - ox];
+    const int c = p[hy ? j - n0 : j];
+    const int e = lane_below(c);
     return ((a - (b & mx)) - (c & my)) + (e & (mx & my));
 }
 
-__device__ __forceinline__ void lz_count(unsigned j, bool out, bool act, unsigned int* __restrict__ count)
+__device__ __forceinline__ void lz_count(unsigned j, bool out, bool act, unsigned int* __restrict__ count,
+                                         unsigned int* __restrict__ gsum)
 {
     const unsigned long long m = __ballot(out);
     if (m == 0ull) return;
@@ -229,46 +286,53 @@ __device__ __forceinline__ void lz_count(unsigned j, bool out, bool act, unsigne
     const unsigned tf = jf / MC_TILE, tl = jl / MC_TILE;
     const unsigned long long lo = __ballot(out && j / MC_TILE == tf), hi = m & ~lo;
     if (lane_id() == first) {
-        if (lo) atomicAdd(&count[tf], (unsigned)__popcll(lo));
-        if (hi) atomicAdd(&count[tl], (unsigned)__popcll(hi));
+        if (lo) {
+            atomicAdd(&count[tf], (unsigned)__popcll(lo));
+            atomicAdd(&gsum[tf / MC_SC_TILES], (unsigned)__popcll(lo));
+        }
+        if (hi) {
+            atomicAdd(&count[tl], (unsigned)__popcll(hi));
+            atomicAdd(&gsum[tl / MC_SC_TILES], (unsigned)__popcll(hi));
+        }
     }
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
                                                  unsigned nunits, uint16_t* __restrict__ codes,
-                                                 unsigned int* __restrict__ count)
+                                                 unsigned int* __restrict__ count, unsigned int* __restrict__ gsum,
+                                                 unsigned remap)
 {
-    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
     if (u >= nunits) return;
     const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
-    const unsigned x = xs * 64u + (unsigned)lane_id();
-    const bool act = x < (unsigned)n0, hx = x > 0;
-    // the whole sweep's loads are issued before any is used
+    const int x = (int)(xs * MC_LZ_W) + lane_id() - 1;      // lane 0: the column to the left
+    const bool act = lane_id() > 0 && x < n0, hx = x > 0;
+    const unsigned xl = (unsigned)min(max(x, 0), n0 - 1);
     constexpr int CH = MC_LZ_CHUNK;
     unsigned base, step;
     int l0, l1;
     bool hy = false;
     if (D == 3) {
         const unsigned y = r % (unsigned)n1, zc = r / (unsigned)n1;
-        base = x + (unsigned)n0 * y;
+        base = xl + (unsigned)n0 * y;
         step = (unsigned)n0 * (unsigned)n1;
         l0 = (int)zc * CH;
         l1 = min(l0 + CH, n2);
         hy = y > 0;
     } else {
-        base = x;
+        base = xl;
         step = (unsigned)n0;
         l0 = (int)r * CH;
         l1 = min(l0 + CH, n1);
     }
     // plane (row) l0 - 1 for the first difference; past the end, the last
     // plane (row) is read again and ignored
-    const int pz = lz_line<D>(p, base + step * (unsigned)(l0 > 0 ? l0 - 1 : 0), act, hx, hy, (unsigned)n0);
+    const int pz = lz_line<D>(p, base + step * (unsigned)(l0 > 0 ? l0 - 1 : 0), hx, hy, (unsigned)n0);
     int prev = l0 > 0 ? pz : 0;
     int cur[CH];
 #pragma unroll
-    for (int k = 0; k < CH; ++k) cur[k] = lz_line<D>(p, base + step * (unsigned)min(l0 + k, l1 - 1), act, hx, hy, (unsigned)n0);
+    for (int k = 0; k < CH; ++k) cur[k] = lz_line<D>(p, base + step * (unsigned)min(l0 + k, l1 - 1), hx, hy, (unsigned)n0);
 #pragma unroll
     for (int k = 0; k < CH; ++k) {
         if (l0 + k >= l1) break;
@@ -277,7 +341,7 @@ __global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, 
         const unsigned j = base + step * (unsigned)(l0 + k);
         const bool in = d >= -(MC_R - 1) && d <= MC_R - 1;
         if (act) codes[j] = in ? (uint16_t)(d + MC_R) : (uint16_t)0;
-        lz_count(j, act && !in, act, count);
+        lz_count(j, act && !in, act, count, gsum);
     }
 }
 
@@ -307,13 +371,13 @@ __device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound&
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                       const float* __restrict__ xh, const T* __restrict__ x,
-                                                      const RangeOut* __restrict__ range, BoundParams bp,
+                                                      const DevBound* __restrict__ bnd,
                                                       const int32_t* __restrict__ rho_q,
-                                                      unsigned int* __restrict__ bcost)
+                                                      unsigned int* __restrict__ bcost, unsigned remap)
 {
     __shared__ long long s_red[4];
-    const DevBound b = make_bound(range, bp);
-    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const DevBound b = *bnd;
+    const long long tile = tile_of(remap);
     const int ocost = 32 + 8 * (int)sizeof(T);
     long long v[MC_IPT];
     bool act[MC_IPT];
@@ -357,15 +421,16 @@ __global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ 
 template <typename T, int D, bool LEARNED>
 __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                   const float* __restrict__ xh, const T* __restrict__ x,
-                                                  const RangeOut* __restrict__ range, BoundParams bp,
+                                                  const DevBound* __restrict__ bnd,
                                                   const int32_t* __restrict__ rho_q,
                                                   const unsigned int* __restrict__ bcost,
                                                   uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags,
-                                                  float* __restrict__ dbg_g, unsigned int* __restrict__ count)
+                                                  float* __restrict__ dbg_g, unsigned int* __restrict__ count,
+                                                  unsigned int* __restrict__ vsum, unsigned remap)
 {
     __shared__ int s_cnt[4];
-    const DevBound b = make_bound(range, bp);
-    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const DevBound b = *bnd;
+    const long long tile = tile_of(remap);
     // every tile lies inside one decision block (MC_LBLOCK % MC_TILE == 0)
     const long long blk = (tile * MC_TILE) / MC_LBLOCK;
     bool learned = false;
@@ -404,6 +469,7 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned c = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+        if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
         if (LEARNED && learned && first_of_block) {
             c |= 0x80000000u;
             atomicOr(&bflags[blk >> 5], 1u << (blk & 31));
@@ -412,123 +478,109 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
     }
 }
 
-// Exclusive scan of the per-tile outlier counts (bit 31 excluded), one
-// workgroup per list: block 0 the grid tiles, block 1 the vertex tiles.
-// Writes the totals to the result header and flags a capacity overflow.
-__global__ __launch_bounds__(1024) void k_scan_counts(const unsigned int* __restrict__ gcount, long long ntg,
-                                                      unsigned int* __restrict__ goff, long long gcap,
-                                                      const unsigned int* __restrict__ vcount, long long ntv,
-                                                      unsigned int* __restrict__ voff, long long vcap,
-                                                      unsigned int* __restrict__ err, mc_result* __restrict__ res)
-{
-    const int PT = 8;
-    __shared__ unsigned s_v[1024 * PT];
-    __shared__ unsigned s_w[16];
-    __shared__ unsigned s_carry, s_learn;
-    const bool vert = blockIdx.x == 1;
-    const unsigned int* cnt = vert ? vcount : gcount;
-    unsigned int* off = vert ? voff : goff;
-    const long long n = vert ? ntv : ntg;
-    if (threadIdx.x == 0) { s_carry = 0; s_learn = 0; }
-    unsigned learned = 0;
-    for (long long base = 0; base < n; base += 1024 * PT) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {            // coalesced load into LDS
-            const long long i = base + k * 1024 + threadIdx.x;
-            const unsigned c = i < n ? cnt[i] : 0u;
-            learned += c >> 31;
-            s_v[k * 1024 + threadIdx.x] = c & 0x7fffffffu;
-        }
-        __syncthreads();
-        unsigned v[PT], run = 0;
-#pragma unroll
-        for (int k = 0; k < PT; ++k) { v[k] = s_v[threadIdx.x * PT + k]; run += v[k]; }
-        const unsigned inc = wave_incl_scan(run);
-        const int w = threadIdx.x >> 6;
-        if (lane_id() == 63) s_w[w] = inc;
-        __syncthreads();
-        unsigned pre = s_carry, tot = 0;
-        for (int k = 0; k < 16; ++k) { if (k < w) pre += s_w[k]; tot += s_w[k]; }
-        unsigned acc = pre + inc - run;
-#pragma unroll
-        for (int k = 0; k < PT; ++k) { s_v[threadIdx.x * PT + k] = acc; acc += v[k]; }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < PT; ++k) {
-            const long long i = base + k * 1024 + threadIdx.x;
-            if (i < n) off[i] = s_v[k * 1024 + threadIdx.x];
-        }
-        if (threadIdx.x == 0) s_carry += tot;
-    }
-    learned = wave_sum(learned);
-    if (lane_id() == 0) atomicAdd(&s_learn, learned);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const long long total = s_carry;
-        if (vert) {
-            res->n_vertex_outliers = total;
-            res->n_learned_blocks = s_learn;
-            if (total > vcap) atomicOr(err, MC_EBIT_VCAP);
-        } else {
-            res->n_grid_outliers = total;
-            if (total > gcap) atomicOr(err, MC_EBIT_GCAP);
-        }
-    }
-}
-
-// Gathers the outliers of each tile that has any, in index order: grid
-// tiles (blocks < ntg) recompute the Lorenzo error of their code-0 nodes,
-// vertex tiles copy the raw value.  Block 0 also writes the final status.
+// Gathers the outliers in index order, one workgroup per group of
+// MC_SC_TILES tiles (grid groups first, then vertex groups): a group with
+// any outlier sums the group totals before it (its list offset), scans its
+// own tile counts, and ranks each tile's code-0 items with wave ballots.
+// Grid outliers get their Lorenzo error recomputed, vertex outliers the raw
+// value.  Block 0 also writes the list totals, the count of learned blocks
+// and the final status (capacity overflows included).
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng,
                                                  const uint16_t* __restrict__ gcodes,
                                                  const unsigned int* __restrict__ gcount,
-                                                 const unsigned int* __restrict__ goff, int32_t* __restrict__ gidx,
+                                                 const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
                                                  int32_t* __restrict__ gdelta, long long gcap, long long ntg,
                                                  const T* __restrict__ x, long long nv,
                                                  const uint16_t* __restrict__ vcodes,
                                                  const unsigned int* __restrict__ vcount,
-                                                 const unsigned int* __restrict__ voff, int32_t* __restrict__ vidx,
+                                                 const unsigned int* __restrict__ vsum, int32_t* __restrict__ vidx,
                                                  T* __restrict__ vval, long long vcap,
                                                  const unsigned int* __restrict__ err, mc_result* __restrict__ res)
 {
     __shared__ int s_cnt[MC_IPT * 4 + 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        unsigned e = *err;
-        if (res->n_grid_outliers > gcap) e |= MC_EBIT_GCAP;
-        if (res->n_vertex_outliers > vcap) e |= MC_EBIT_VCAP;
-        res->status = status_from_bits(e);
+    __shared__ unsigned s_c[MC_SC_TILES], s_off[MC_SC_TILES];
+    __shared__ unsigned long long s_red[4];
+    const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
+    const long long ngg = (ntg + MC_SC_TILES - 1) / MC_SC_TILES, ngv = (ntv + MC_SC_TILES - 1) / MC_SC_TILES;
+    if (blockIdx.x == 0) {
+        // totals of both lists and the learned-block count (bit 31 marks the
+        // first tile of a learned block: every MC_LBLOCK / MC_TILE-th tile)
+        unsigned long long tg = 0, tv = 0, nl = 0;
+        for (long long i = threadIdx.x; i < ngg; i += 256) tg += gsum[i];
+        for (long long i = threadIdx.x; i < ngv; i += 256) tv += vsum[i];
+        const long long step = MC_LBLOCK / MC_TILE;
+        for (long long i = threadIdx.x * step; i < ntv; i += 256 * step) nl += vcount[i] >> 31;
+        tg = block_sum_u64(tg, s_red);
+        tv = block_sum_u64(tv, s_red);
+        nl = block_sum_u64(nl, s_red);
+        if (threadIdx.x == 0) {
+            unsigned e = *err;
+            if ((long long)tg > gcap) e |= MC_EBIT_GCAP;
+            if ((long long)tv > vcap) e |= MC_EBIT_VCAP;
+            res->n_grid_outliers = (long long)tg;
+            res->n_vertex_outliers = (long long)tv;
+            res->n_learned_blocks = (long long)nl;
+            res->status = status_from_bits(e);
+        }
     }
-    const bool vert = blockIdx.x >= ntg;
-    const long long tile = vert ? blockIdx.x - ntg : blockIdx.x;
-    const unsigned c = (vert ? vcount[tile] : gcount[tile]) & 0x7fffffffu;
-    if (c == 0) return;
+    const bool vert = blockIdx.x >= ngg;
+    const long long grp = vert ? blockIdx.x - ngg : blockIdx.x;
+    const long long ntl = vert ? ntv : ntg;
+    const unsigned int* cnt = vert ? vcount : gcount;
+    const long long t0 = grp * MC_SC_TILES;
+    if (threadIdx.x < MC_SC_TILES) {
+        const long long t = t0 + threadIdx.x;
+        s_c[threadIdx.x] = t < ntl ? (cnt[t] & 0x7fffffffu) : 0u;
+    }
+    __syncthreads();
+    unsigned any = 0;
+#pragma unroll
+    for (int k = 0; k < MC_SC_TILES; ++k) any |= s_c[k];
+    if (any == 0) return;                          // uniform: no outlier in the group
+    // list offset of the group: sum of the group totals before it
+    const unsigned int* sums = vert ? vsum : gsum;
+    unsigned long long before = 0;
+    for (long long i = threadIdx.x; i < grp; i += 256) before += sums[i];
+    before = block_sum_u64(before, s_red);
+    if (threadIdx.x == 0) {
+        unsigned long long a = before;
+        for (int k = 0; k < MC_SC_TILES; ++k) {
+            s_off[k] = (unsigned)a;
+            a += s_c[k];
+        }
+    }
+    __syncthreads();
     const long long n = vert ? nv : ng;
     const uint16_t* codes = vert ? vcodes : gcodes;
-    bool flag[MC_IPT];
-    int rank[MC_IPT];
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
-        flag[i] = j < n && codes[j] == 0;
-    }
-    tile_ranks(flag, rank, s_cnt);
-    const long long base = vert ? voff[tile] : goff[tile];
     const long long n01 = (long long)n0 * n1;
+    for (int k = 0; k < MC_SC_TILES; ++k) {
+        if (s_c[k] == 0) continue;                 // uniform across the workgroup
+        const long long tile = t0 + k;
+        bool flag[MC_IPT];
+        int rank[MC_IPT];
 #pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        if (!flag[i]) continue;
-        const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
-        const long long pos = base + rank[i];
-        if (vert) {
-            if (pos < vcap) { vidx[pos] = (int32_t)j; vval[pos] = x[j]; }
-        } else if (pos < gcap) {
-            const int i0 = (int)(j % n0);
-            const long long r = j / n0;
-            gidx[pos] = (int32_t)j;
-            gdelta[pos] = (int32_t)lorenzo_delta<D>(p, j, i0, (int)(r % n1), (int)(r / n1), n0, n01);
+        for (int i = 0; i < MC_IPT; ++i) {
+            const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
+            flag[i] = j < n && codes[j] == 0;
         }
+        tile_ranks(flag, rank, s_cnt);
+        const long long base = s_off[k];
+#pragma unroll
+        for (int i = 0; i < MC_IPT; ++i) {
+            if (!flag[i]) continue;
+            const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
+            const long long pos = base + rank[i];
+            if (vert) {
+                if (pos < vcap) { vidx[pos] = (int32_t)j; vval[pos] = x[j]; }
+            } else if (pos < gcap) {
+                const int i0 = (int)(j % n0);
+                const long long r = j / n0;
+                gidx[pos] = (int32_t)j;
+                gdelta[pos] = (int32_t)lorenzo_delta<D>(p, j, i0, (int)(r % n1), (int)(r / n1), n0, n01);
+            }
+        }
+        __syncthreads();                           // s_cnt is reused by the next tile
     }
 }
 
@@ -537,34 +589,40 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
 // ---------------------------------------------------------------------------
 namespace mck {
 
-hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur,
+hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
+                 DevBound* bnd,
                  unsigned int* zero, long long nzero, hipStream_t s)
 {
-    const int nblocks = 1024;
+    const int nblocks = MC_RANGE_BLOCKS;      // one batch of 8 quads per thread at 16M values
     {
         ProfScope ps("k_range", s);
-        if (dtype == MC_F64)
-            hipLaunchKernelGGL(k_range<double>, dim3(nblocks), dim3(256), 0, s, (const double*)x, n, partial, zero, nzero);
-        else
-            hipLaunchKernelGGL(k_range<float>, dim3(nblocks), dim3(256), 0, s, (const float*)x, n, partial, zero, nzero);
+        const bool V = ((uintptr_t)x & 15u) == 0;
+#define MC_RG(T) do { if (V) hipLaunchKernelGGL((k_range<T, true>), dim3(nblocks), dim3(256), 0, s, (const T*)x, n, \
+                                                partial, zero, nzero); \
+                      else hipLaunchKernelGGL((k_range<T, false>), dim3(nblocks), dim3(256), 0, s, (const T*)x, n, \
+                                              partial, zero, nzero); } while (0)
+        if (dtype == MC_F64) MC_RG(double);
+        else MC_RG(float);
+#undef MC_RG
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     ProfScope ps("k_range_final", s);
-    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(256), 0, s, partial, nblocks, cur);
+    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(256), 0, s, partial, nblocks, cur, bp, bnd);
     return hipGetLastError();
 }
 
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
+                    const DevBound* bnd, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
                     long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
-                    hipStream_t s)
+                    unsigned remap, hipStream_t s)
 {
+    remap &= MC_KNOB_RESAMPLE;
     ProfScope ps("k_resample", s);
     const long long need = ng > nbflags ? ng : nbflags;
     dim3 grid((unsigned)((need + 255) / 256));
-#define MC_RS(T, D) hipLaunchKernelGGL((k_resample<T, D>), grid, dim3(256), 0, s, vid, w, ng, (const T*)x, range, bp, \
-                                       p, xh, dbg_v, bflags, nbflags, err, res, dtype, gcount, ntg)
+#define MC_RS(T, D) hipLaunchKernelGGL((k_resample<T, D>), grid, dim3(256), 0, s, vid, w, ng, (const T*)x, bnd, \
+                                       p, xh, dbg_v, bflags, nbflags, err, res, dtype, gcount, ntg, remap)
     if (dtype == MC_F64) { if (dim == 2) MC_RS(double, 2); else MC_RS(double, 3); }
     else { if (dim == 2) MC_RS(float, 2); else MC_RS(float, 3); }
 #undef MC_RS
@@ -572,32 +630,35 @@ hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, c
 }
 
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
-                   unsigned int* count, hipStream_t s)
+                   unsigned int* count, unsigned int* gsum, unsigned remap, hipStream_t s)
 {
+    remap &= MC_KNOB_LORENZO;
     ProfScope ps("k_lorenzo", s);
     (void)ng;
-    const int nxs = (n0 + 63) / 64;
+    const int nxs = (n0 + MC_LZ_W - 1) / MC_LZ_W;
     const long long lines = (long long)nxs * (dim == 3 ? (long long)n1 : 1);
     const int len = dim == 3 ? n2 : n1;
     const unsigned nunits = (unsigned)(lines * ((len + MC_LZ_CHUNK - 1) / MC_LZ_CHUNK));
     dim3 grid((nunits + 3) / 4);
     if (dim == 2)
-        hipLaunchKernelGGL(k_lorenzo<2>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count);
+        hipLaunchKernelGGL(k_lorenzo<2>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count, gsum, remap);
     else
-        hipLaunchKernelGGL(k_lorenzo<3>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count);
+        hipLaunchKernelGGL(k_lorenzo<3>, grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes, count, gsum, remap);
     return hipGetLastError();
 }
 
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, hipStream_t s)
+                    const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
+                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
+                    hipStream_t s)
 {
+    remap &= MC_KNOB_RESIDUAL;
     const bool L = rho_q != nullptr;
+    const dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
     if (L) {
         ProfScope ps("k_learned_cost", s);
-        dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
 #define MC_LC(T, D) hipLaunchKernelGGL((k_learned_cost<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, \
-                                       range, bp, rho_q, bcost)
+                                       bnd, rho_q, bcost, remap)
         if (dtype == MC_F64) { if (gg.dim == 2) MC_LC(double, 2); else MC_LC(double, 3); }
         else { if (gg.dim == 2) MC_LC(float, 2); else MC_LC(float, 3); }
 #undef MC_LC
@@ -605,10 +666,8 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
         if (e != hipSuccess) return e;
     }
     ProfScope ps(L ? "k_residual_learned" : "k_residual", s);
-    const long long ntiles = (nv + MC_TILE - 1) / MC_TILE;
-    dim3 grid((unsigned)ntiles);
 #define MC_RQ(T, D, LL) hipLaunchKernelGGL((k_residual<T, D, LL>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, \
-                                           range, bp, rho_q, bcost, codes, bflags, dbg_g, count)
+                                           bnd, rho_q, bcost, codes, bflags, dbg_g, count, vsum, remap)
     if (dtype == MC_F64) {
         if (gg.dim == 2) { if (L) MC_RQ(double, 2, true); else MC_RQ(double, 2, false); }
         else { if (L) MC_RQ(double, 3, true); else MC_RQ(double, 3, false); }
@@ -621,22 +680,15 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
 }
 
 hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, const uint16_t* gcodes, unsigned int* gcount,
-                   unsigned int* goff, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
-                   long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* voff, int32_t* vidx,
+                   unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
+                   long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
                    void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s)
 {
     const long long ntg = (ng + MC_TILE - 1) / MC_TILE, ntv = (nv + MC_TILE - 1) / MC_TILE;
-    {
-        ProfScope ps("k_scan_counts", s);
-        hipLaunchKernelGGL(k_scan_counts, dim3(2), dim3(1024), 0, s, gcount, ntg, goff, gcap, vcount, ntv, voff, vcap,
-                           err, res);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
     ProfScope ps("k_scatter", s);
-    dim3 grid((unsigned)(ntg + ntv));
-#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gcodes, gcount, goff, \
-                                       gidx, gdelta, gcap, ntg, (const T*)x, nv, vcodes, vcount, voff, vidx, (T*)vval, \
+    dim3 grid((unsigned)((ntg + MC_SC_TILES - 1) / MC_SC_TILES + (ntv + MC_SC_TILES - 1) / MC_SC_TILES));
+#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gcodes, gcount, gsum, \
+                                       gidx, gdelta, gcap, ntg, (const T*)x, nv, vcodes, vcount, vsum, vidx, (T*)vval, \
                                        vcap, err, res)
     if (dtype == MC_F64) { if (dim == 2) MC_SC(double, 2); else MC_SC(double, 3); }
     else { if (dim == 2) MC_SC(float, 2); else MC_SC(float, 3); }

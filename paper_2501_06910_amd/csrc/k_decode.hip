@@ -77,29 +77,29 @@ __global__ __launch_bounds__(256) void k_dec_xy_tot(const uint16_t* __restrict__
         if (c0 + k < n0) agg[tile * n0 + c0 + k] = tot[k];
 }
 
+// Exclusive prefix over chunks, in place: one thread per position, the
+// chunk values loaded 32 at a time before any is used.
+__device__ __forceinline__ void excl_prefix_strided(int* __restrict__ a, long long first, long long stride, int n)
+{
+    int run = 0;
+    for (int b = 0; b < n; b += 32) {
+        int t[32];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) t[u] = a[first + (long long)min(b + u, n - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            if (b + u < n) a[first + (long long)(b + u) * stride] = run;
+            run += b + u < n ? t[u] : 0;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_dec_xy_carry(int* __restrict__ agg, int n0, int n2, int nyc)
 {
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= (long long)n0 * n2) return;
     const long long z = i / n0, c = i % n0;
-    int run = 0;
-    int yc = 0;
-    for (; yc + 8 <= nyc; yc += 8) {
-        int t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = agg[(z * nyc + yc + u) * n0 + c];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            agg[(z * nyc + yc + u) * n0 + c] = run;
-            run += t[u];
-        }
-    }
-    for (; yc < nyc; ++yc) {
-        const long long k = (z * nyc + yc) * n0 + c;
-        const int t = agg[k];
-        agg[k] = run;
-        run += t;
-    }
+    excl_prefix_strided(agg, z * nyc * n0 + c, n0, nyc);
 }
 
 template <int CPT, bool FROM_CODES>
@@ -170,24 +170,7 @@ __global__ __launch_bounds__(256) void k_dec_z_carry(int* __restrict__ aggz, lon
 {
     const long long pos = (long long)blockIdx.x * 256 + threadIdx.x;
     if (pos >= nxy) return;
-    int run = 0;
-    int zc = 0;
-    for (; zc + 8 <= nzc; zc += 8) {
-        int t[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) t[u] = aggz[(long long)(zc + u) * nxy + pos];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            aggz[(long long)(zc + u) * nxy + pos] = run;
-            run += t[u];
-        }
-    }
-    for (; zc < nzc; ++zc) {
-        const long long k = (long long)zc * nxy + pos;
-        const int t = aggz[k];
-        aggz[k] = run;
-        run += t;
-    }
+    excl_prefix_strided(aggz, pos, nxy, nzc);
 }
 
 template <int CX>
@@ -275,9 +258,10 @@ __device__ __forceinline__ int dec1(unsigned c, const int32_t* __restrict__ oidx
 __global__ __launch_bounds__(256) void k_d3_ztot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                                  const int32_t* __restrict__ odelta,
                                                  const mc_result* __restrict__ res, long long gcap, int n0, int n1,
-                                                 int n2, int nxs, unsigned nunits, int* __restrict__ aggz)
+                                                 int n2, int nxs, unsigned nunits, int* __restrict__ aggz,
+                                                 unsigned remap)
 {
-    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
     if (u >= nunits) return;
     const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
     const unsigned y = r % (unsigned)n1, zc = r / (unsigned)n1;
@@ -306,10 +290,10 @@ __global__ __launch_bounds__(256) void k_d3_zapply(const uint16_t* __restrict__ 
                                                    const int32_t* __restrict__ odelta,
                                                    const mc_result* __restrict__ res, long long gcap, int n0, int n1,
                                                    int n2, int nxs, int nyc, const int* __restrict__ carryz,
-                                                   int32_t* __restrict__ pz, int* __restrict__ agg_xy)
+                                                   int32_t* __restrict__ pz, int* __restrict__ agg_xy, unsigned remap)
 {
     __shared__ int4 s_cs[2][4][64];
-    const unsigned t = xcd_tile(blockIdx.x, gridDim.x);          // grid = exactly the tiles: no early exit
+    const unsigned t = tile_of(remap);                           // grid = exactly the tiles: no early exit
     const unsigned xs = t % (unsigned)nxs, r = t / (unsigned)nxs;
     const unsigned yc = r % (unsigned)nyc, zc = r / (unsigned)nyc;
     const int w = threadIdx.x >> 6;
@@ -372,9 +356,10 @@ __global__ __launch_bounds__(256) void k_d3_zapply(const uint16_t* __restrict__ 
 template <int NXS>
 __global__ __launch_bounds__(256) void k_d3_xyapply(const int32_t* __restrict__ pz, const mc_result* __restrict__ res,
                                                     int n0, int n1, int nyc, unsigned nunits,
-                                                    const int* __restrict__ carry, float* __restrict__ xh)
+                                                    const int* __restrict__ carry, float* __restrict__ xh,
+                                                    unsigned remap)
 {
-    const unsigned u = xcd_tile(blockIdx.x, gridDim.x) * 4u + (threadIdx.x >> 6);
+    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
     if (u >= nunits) return;
     const unsigned z = u / (unsigned)nyc, yc = u % (unsigned)nyc;
     const int y0 = (int)yc * MC_DY, y1 = min(y0 + MC_DY, n1);
@@ -433,9 +418,10 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
                                                  const int32_t* __restrict__ oidx, const T* __restrict__ oval,
                                                  const mc_result* __restrict__ res, long long vcap,
                                                  const int32_t* __restrict__ rho_q,
-                                                 const uint32_t* __restrict__ bflags, T* __restrict__ xout)
+                                                 const uint32_t* __restrict__ bflags, T* __restrict__ xout,
+                                                 unsigned remap)
 {
-    const long long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const long long tile = tile_of(remap);
     bool learned = false;
     if (LEARNED) {
         const long long blk = (tile * MC_TILE) / MC_LBLOCK;       // a tile lies inside one block
@@ -473,7 +459,7 @@ namespace mck {
 
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
                        const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,
-                       hipStream_t s)
+                       unsigned remap, hipStream_t s)
 {
     hipError_t e;
     const int cpt = (n0 + 63) / 64;
@@ -499,7 +485,7 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
             ProfScope ps("k_dec_z_tot", s);
             const unsigned nunits = (unsigned)((long long)nxs * n1 * ws.nzc);
             hipLaunchKernelGGL(k_d3_ztot, dim3((nunits + 3) / 4), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0,
-                               n1, n2, nxs, nunits, ws.agg_z);
+                               n1, n2, nxs, nunits, ws.agg_z, remap & MC_KNOB_DZTOT);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
@@ -512,7 +498,7 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
             ProfScope ps("k_dec_z_apply", s);
             const unsigned ntiles = (unsigned)((long long)nxs * ws.nyc * ws.nzc);
             hipLaunchKernelGGL(k_d3_zapply, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2,
-                               nxs, ws.nyc, ws.agg_z, pz, ws.agg_xy);
+                               nxs, ws.nyc, ws.agg_z, pz, ws.agg_xy, remap & MC_KNOB_DZAPPLY);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
@@ -526,11 +512,14 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
             const unsigned nunits = (unsigned)((long long)n2 * ws.nyc);
             dim3 g((nunits + 3) / 4);
             if (nxs == 1)
-                hipLaunchKernelGGL(k_d3_xyapply<1>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+                hipLaunchKernelGGL(k_d3_xyapply<1>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
+                                   remap & MC_KNOB_DXYAPPLY);
             else if (nxs == 2)
-                hipLaunchKernelGGL(k_d3_xyapply<2>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+                hipLaunchKernelGGL(k_d3_xyapply<2>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
+                                   remap & MC_KNOB_DXYAPPLY);
             else
-                hipLaunchKernelGGL(k_d3_xyapply<4>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh);
+                hipLaunchKernelGGL(k_d3_xyapply<4>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
+                                   remap & MC_KNOB_DXYAPPLY);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         return hipSuccess;
@@ -599,12 +588,14 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
 
 hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
                          const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
-                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, hipStream_t s)
+                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
+                         hipStream_t s)
 {
+    remap &= MC_KNOB_VDECODE;
     ProfScope ps(rho_q ? "k_vdecode_learned" : "k_vdecode", s);
     dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
 #define MC_VD(T, D, L) hipLaunchKernelGGL((k_vdecode<T, D, L>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, oidx, \
-                                          (const T*)oval, res, vcap, rho_q, bflags, (T*)xout)
+                                          (const T*)oval, res, vcap, rho_q, bflags, (T*)xout, remap)
     const bool L = rho_q != nullptr;
     if (dtype == MC_F64) {
         if (gg.dim == 2) { if (L) MC_VD(double, 2, true); else MC_VD(double, 2, false); }

@@ -472,27 +472,31 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     PCHK(plan_alloc(p, &p->rho, (size_t)nv));
     PCHK(plan_alloc(p, &p->ctl, 64));
     p->rbuf = (RangeOut*)p->ctl;                       // 2 slots of 3 words
+    p->bound = (DevBound*)(p->ctl + 16);               // 11 words at word 16
     {
         RangeOut init[2];
         for (int k = 0; k < 2; ++k) { init[k].kmin = ~0ull; init[k].kmax = 0ull; init[k].flags = 0u; init[k].pad = 0u; }
         PCHK(hipMemsetAsync(p->ctl, 0, 64 * sizeof(unsigned long long), s));
         PCHK(hipMemcpyAsync(p->rbuf, init, sizeof init, hipMemcpyHostToDevice, s));
     }
-    p->nsmall = 16 + 2 * p->nblk;
+    // per-call state cleared by k_range: error bits, learned block costs,
+    // outlier totals per group of MC_SC_TILES tiles
+    const long long ngg = (p->ntg + MC_SC_TILES - 1) / MC_SC_TILES, ngv = (p->ntv + MC_SC_TILES - 1) / MC_SC_TILES;
+    p->nsmall = 16 + 2 * p->nblk + ngg + ngv;
     PCHK(plan_alloc(p, &p->small, (size_t)p->nsmall));
     PCHK(hipMemsetAsync(p->small, 0, (size_t)p->nsmall * 4, s));
     p->err = p->small + 2;
     p->bcost = p->small + 16;
-    PCHK(plan_alloc(p, &p->counts, (size_t)2 * (p->ntg + p->ntv)));
+    p->gsum = p->bcost + 2 * p->nblk;
+    p->vsum = p->gsum + ngg;
+    PCHK(plan_alloc(p, &p->counts, (size_t)(p->ntg + p->ntv)));
     p->gcount = p->counts;
     p->vcount = p->counts + p->ntg;
-    p->goff = p->counts + p->ntg + p->ntv;
-    p->voff = p->goff + p->ntg;
     decode_ws_shape(p);
     PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * grid->dims[0]));
     if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * grid->dims[0] * grid->dims[1]));
     PCHK(plan_alloc(p, &p->xh, (size_t)ng));
-    PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * 1024));
+    PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * MC_RANGE_BLOCKS));
     PCHK(hipStreamSynchronize(s));
     *out = p;
     return MC_OK;
@@ -568,22 +572,22 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     hipError_t e;
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
     RangeOut* cur = p->rbuf;
-    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, p->small, p->nsmall, s));
-    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, cur, bp, p->p, p->xh, codes->dbg_resampled,
-                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, s));
+    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, bp, p->bound, p->small, p->nsmall, s));
+    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, p->xh, codes->dbg_resampled,
+                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, p->knobs, s));
     ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
-                      codes->grid_codes, p->gcount, s));
+                      codes->grid_codes, p->gcount, p->gsum, p->knobs, s));
     const int32_t* rho = nullptr;
     if (prm->model) {
         mc_status ms = mc_model_infer(prm->model, p, codes->result, nullptr, s);
         if (ms != MC_OK) return ms;
         rho = p->rho;
     }
-    ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, cur, bp, rho, p->bcost, codes->vert_codes,
-                       codes->block_flags, codes->dbg_vertex_g, p->vcount, s));
+    ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, p->bcost, codes->vert_codes,
+                       codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes, p->gcount,
-                      p->goff, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
-                      codes->vert_codes, p->vcount, p->voff, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
+                      p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
+                      codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
                       p->err, codes->result, s));
     if (codes->dbg_grid_p) ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
@@ -628,7 +632,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
                           p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
-                          p->dws, s));
+                          p->dws, p->knobs, s));
     const int32_t* rho = nullptr;
     if (model) {
         mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);
@@ -636,7 +640,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
         rho = p->rho;
     }
     ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
-                            codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, s));
+                            codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, p->knobs, s));
 #undef ECHK
     return MC_OK;
 }
@@ -647,6 +651,75 @@ extern "C" mc_status mc_decompress(mc_plan p, const mc_codes* codes, mc_model mo
     mc_status st = mc_check_decompress(p, codes, model, d_out, dtype);
     if (st != MC_OK) return st;
     return mc_decompress_enqueue(p, codes, model, d_out, dtype, s);
+}
+
+// ---------------------------------------------------------------------------
+// autotuning of the launch-order knobs
+// ---------------------------------------------------------------------------
+extern "C" mc_status mc_plan_get_tuning(mc_plan p, mc_tuning* out)
+{
+    if (!p || !out) return mc_fail(MC_ERR_ARG, "plan or output is NULL");
+    *out = mc_tuning{};
+    out->remap_mask = p->knobs;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_set_tuning(mc_plan p, const mc_tuning* t)
+{
+    if (!p || !t) return mc_fail(MC_ERR_ARG, "plan or tuning is NULL");
+    if (t->remap_mask & ~(unsigned)mck::MC_KNOB_ALL) return mc_fail(MC_ERR_ARG, "unknown bits in remap_mask");
+    p->knobs = t->remap_mask;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_tune(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
+                                  const mc_codes* codes, void* d_out, int32_t reps, hipStream_t s, mc_tuning* chosen)
+{
+    mc_status st = mc_check_params(p, d_field, dtype, prm, codes);
+    if (st != MC_OK) return st;
+    if ((st = mc_check_decompress(p, codes, prm->model, d_out, dtype)) != MC_OK) return st;
+    if (reps < 1 || reps > 1000) return mc_fail(MC_ERR_ARG, "reps must be in [1, 1000]");
+    // summed kernel milliseconds of `reps` passes with the given knobs
+    auto measure = [&](unsigned knobs, double* ms) -> mc_status {
+        p->knobs = knobs;
+        mc_status r = mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
+        if (r == MC_OK) r = mc_decompress_enqueue(p, codes, prm->model, d_out, dtype, s);
+        if (r != MC_OK) return r;
+        if (hipStreamSynchronize(s) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "synchronize failed");
+        mc_profile_reset();
+        mc_profile_enable(1);
+        for (int i = 0; i < reps && r == MC_OK; ++i) {
+            r = mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
+            if (r == MC_OK) r = mc_decompress_enqueue(p, codes, prm->model, d_out, dtype, s);
+        }
+        mc_profile_enable(0);
+        if (hipStreamSynchronize(s) != hipSuccess) r = mc_fail(MC_ERR_DEVICE, "synchronize failed");
+        double tot[64];
+        const int32_t n = mc_profile_read(nullptr, nullptr, tot, 64);
+        *ms = 0.0;
+        for (int32_t i = 0; i < n; ++i) *ms += tot[i];
+        mc_profile_reset();
+        return r;
+    };
+    const bool was_on = g_prof_on;
+    unsigned best = mck::MC_KNOB_ALL;
+    double best_ms = 0.0;
+    if ((st = measure(best, &best_ms)) != MC_OK) return st;
+    for (unsigned bit = 1; bit & mck::MC_KNOB_ALL; bit <<= 1) {
+        double ms = 0.0;
+        if ((st = measure(best ^ bit, &ms)) != MC_OK) return st;
+        if (ms < best_ms) {
+            best ^= bit;
+            best_ms = ms;
+        }
+    }
+    p->knobs = best;
+    mc_profile_enable(was_on ? 1 : 0);
+    if (chosen) {
+        *chosen = mc_tuning{};
+        chosen->remap_mask = best;
+    }
+    return MC_OK;
 }
 
 extern "C" mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t nv, int64_t nc,

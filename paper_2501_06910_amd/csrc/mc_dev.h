@@ -14,6 +14,8 @@
 #define MC_R 32768
 #define MC_TILE 1024          // items per workgroup tile (256 threads x 4)
 #define MC_LZ_CHUNK 16        // planes (rows) per Lorenzo sweep
+#define MC_SC_TILES 16        // outlier scatter: tiles per workgroup
+#define MC_RANGE_BLOCKS 2048  // field range: per-block partials (3 words each)
 #define MC_DZ_PLANES 8        // 3-D decode: planes per z chunk
 #define MC_DY_ROWS 8          // 3-D decode: rows per xy chunk (4 waves x 2 rows)
 #define MC_WG 256
@@ -47,9 +49,12 @@ struct BoundParams {
     int pad;
 };
 
+// The error split of one call, computed once per call by k_range_final and
+// read by the kernels that quantise.
 struct DevBound {
     double tau, tau1, tau2, c, xmin, xmax, inv1, step1, inv2, step2;
     int ok;
+    unsigned flags;              // range flags (MC_EBIT_NONFINITE)
 };
 
 __device__ __forceinline__ unsigned long long dkey(double d)
@@ -82,6 +87,7 @@ __device__ __forceinline__ DevBound make_bound(const RangeOut* r, BoundParams bp
     b.step2 = 2.0 * b.tau2;
     b.inv2 = 1.0 / (2.0 * b.tau2);
     b.ok = !(r->flags & MC_EBIT_NONFINITE) && (b.tau1 > 0.0) && (b.tau2 > 0.0);
+    b.flags = (unsigned)r->flags;
     return b;
 }
 
@@ -123,22 +129,13 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
 }
 
 // ---------------------------------------------------------------------------
-// g(x1') for N vertices of one thread, loads first: all coordinates, then
+// g(x1') for N vertices of one thread from their coordinates P: cells, then
 // every corner of every cell, then the nested lerps (x, then y, then z) in
-// the order of the definition.  act[i] false: vertex 0 stands in (its
-// result is ignored), so no load depends on a branch.
+// the order of the definition, so that all gathers issue together.
 template <int D, int N>
-__device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, long long nv, const GridGeom& gg,
-                                              const float* __restrict__ xh, const long long (&v)[N],
-                                              const bool (&act)[N], float (&g)[N])
+__device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const GridGeom& gg,
+                                              const float* __restrict__ xh, float (&g)[N])
 {
-    float P[N][3];
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-        const long long vc = act[i] ? v[i] : 0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) P[i][d] = coords[d * nv + vc];
-    }
     const unsigned n0 = (unsigned)gg.n0, n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
     unsigned j[N];
     float t[N][3];
@@ -177,6 +174,44 @@ __device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, 
             g[i] = lerpf_(c0, lerpf_(c01, c11, t[i][1]), t[i][2]);
         }
     }
+}
+
+// The same for N vertices v[i] (strided ownership): coordinates loaded
+// first.  act[i] false: vertex 0 stands in (its result is ignored), so no
+// load depends on a branch.
+template <int D, int N>
+__device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, long long nv, const GridGeom& gg,
+                                              const float* __restrict__ xh, const long long (&v)[N],
+                                              const bool (&act)[N], float (&g)[N])
+{
+    float P[N][3];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const long long vc = act[i] ? v[i] : 0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) P[i][d] = coords[d * nv + vc];
+        if (D == 2) P[i][2] = 0.0f;
+    }
+    back_interp_p<D, N>(P, gg, xh, g);
+}
+
+// Four consecutive values of T from a 16-byte aligned address.
+template <typename T> struct Quad { T v[4]; };
+__device__ __forceinline__ Quad<float> load_quad(const float* __restrict__ p)
+{
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    return Quad<float>{{a.x, a.y, a.z, a.w}};
+}
+__device__ __forceinline__ Quad<double> load_quad(const double* __restrict__ p)
+{
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    return Quad<double>{{a.x, a.y, b.x, b.y}};
+}
+// Tile of this workgroup: XCD-contiguous order when `remap` is set.
+__device__ __forceinline__ unsigned tile_of(unsigned remap)
+{
+    return remap ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
 }
 
 // ---------------------------------------------------------------------------
@@ -234,6 +269,17 @@ __device__ __forceinline__ int tile_ranks(const bool (&flag)[MC_IPT], int (&rank
     return s_cnt[MC_IPT * 4];
 }
 
+// Block-wide sum of a uint64 (256 threads); s needs 4 slots.
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* s)
+{
+    v = wave_sum(v);
+    if (lane_id() == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const unsigned long long t = s[0] + s[1] + s[2] + s[3];
+    __syncthreads();
+    return t;
+}
+
 // Block-wide sum of an int64 (256 threads); s needs 4 slots.
 __device__ __forceinline__ long long block_sum_i64(long long v, long long* s)
 {
@@ -245,6 +291,7 @@ __device__ __forceinline__ long long block_sum_i64(long long v, long long* s)
     return t;
 }
 
+// ---------------------------------------------------------------------------
 // ---------------------------------------------------------------------------
 // decoupled look-back over tiles (scalar payload in the status word)
 // status word: bits 62..63 flag (1 = tile aggregate, 2 = inclusive prefix),

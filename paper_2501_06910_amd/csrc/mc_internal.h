@@ -20,9 +20,10 @@ struct mc_plan_s {
     int32_t* p = nullptr;          // prequantised grid [ng]
     int32_t* rho = nullptr;        // learned shift [nv]
     float* xh = nullptr;           // reconstructed grid x1' [ng]
-    unsigned long long* range_partial = nullptr;   // [3 * 1024]
+    unsigned long long* range_partial = nullptr;   // [3 * MC_RANGE_BLOCKS]
     unsigned long long* ctl = nullptr;   // 64 words: the two range slots
     RangeOut* rbuf = nullptr;            // field range of the current call
+    DevBound* bound = nullptr;           // error split of the current call (in ctl)
     unsigned* small = nullptr;           // per-call state cleared by k_range (u32 words)
     long long nsmall = 0;
     unsigned* err = nullptr;             // small[2]
@@ -30,10 +31,11 @@ struct mc_plan_s {
     unsigned* counts = nullptr;          // per-tile outlier counts and offsets
     unsigned* gcount = nullptr;
     unsigned* vcount = nullptr;
-    unsigned* goff = nullptr;
-    unsigned* voff = nullptr;
+    unsigned* gsum = nullptr;            // outliers per group of tiles (in small)
+    unsigned* vsum = nullptr;
     long long ntg = 0, ntv = 0, nblk = 0;
     mck::DecodeWs dws{};
+    unsigned knobs = mck::MC_KNOB_ALL;  // launch-order knobs (mc_plan_tune)
     // statistics
     long long n_unresolved = 0, n_near_degenerate = 0, n_pairs = 0;
     int invalid_cells = 0;

@@ -51,23 +51,39 @@ hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32
                          hipStream_t s);
 
 // ---- compression (k_compress.hip) -----------------------------------------
-hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur,
+hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
+                 DevBound* bnd,
                  unsigned int* zero, long long nzero, hipStream_t s);
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
+                    const DevBound* bnd, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
                     long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
-                    hipStream_t s);
+                    unsigned remap, hipStream_t s);
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
-                   unsigned int* count, hipStream_t s);
+                   unsigned int* count, unsigned int* gsum, unsigned remap, hipStream_t s);
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const RangeOut* range, BoundParams bp, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, hipStream_t s);
+                    const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
+                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
+                    hipStream_t s);
 hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, const uint16_t* gcodes, unsigned int* gcount,
-                   unsigned int* goff, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
-                   long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* voff, int32_t* vidx,
+                   unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
+                   long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
                    void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s);
 
 // ---- decompression (k_decode.hip) -----------------------------------------
+// Launch-order knobs (results do not depend on them): bit k set = kernel k
+// takes its tiles in XCD-contiguous order (xcd_tile), clear = in launch
+// order.  Chosen per plan by mc_plan_tune.
+enum {
+    MC_KNOB_RESAMPLE = 1u << 0,
+    MC_KNOB_LORENZO = 1u << 1,
+    MC_KNOB_RESIDUAL = 1u << 2,
+    MC_KNOB_VDECODE = 1u << 3,
+    MC_KNOB_DZTOT = 1u << 4,
+    MC_KNOB_DZAPPLY = 1u << 5,
+    MC_KNOB_DXYAPPLY = 1u << 6,
+    MC_KNOB_ALL = 0x7fu
+};
+
 struct DecodeWs {
     bool fast3;                    // 3-D with n0 % 4 == 0 and n0 <= 1024: the quad kernels
     int rows, nyc;                 // rows per tile, row chunks per plane
@@ -78,10 +94,11 @@ struct DecodeWs {
 };
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
                        const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,
-                       hipStream_t s);
+                       unsigned remap, hipStream_t s);
 hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
                          const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
-                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, hipStream_t s);
+                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
+                         hipStream_t s);
 
 // ---- learned predictor (k_mlp.hip) ----------------------------------------
 struct MlpDev {

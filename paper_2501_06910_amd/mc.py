@@ -69,6 +69,10 @@ class McBatchItem(C.Structure):
                 ("codes", McCodes)]
 
 
+class McTuning(C.Structure):
+    _fields_ = [("remap_mask", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
 class McBatchDItem(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("codes", McCodes), ("model", C.c_void_p), ("d_out", C.c_void_p),
                 ("dtype", C.c_int)]
@@ -103,6 +107,9 @@ _SIGS = {
     "mc_model_features": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P]),
     "mc_batch_compress": (C.c_int, [_P, C.c_int32, _P]),
     "mc_batch_release": (C.c_int, []),
+    "mc_plan_get_tuning": (C.c_int, [_P, _P]),
+    "mc_plan_set_tuning": (C.c_int, [_P, _P]),
+    "mc_plan_tune": (C.c_int, [_P, _P, C.c_int, _P, _P, _P, C.c_int32, _P, _P]),
     "mc_batch_decompress": (C.c_int, [_P, C.c_int32, _P]),
     "mc_profile_enable": (C.c_int, [C.c_int32]),
     "mc_profile_reset": (C.c_int, []),
@@ -243,6 +250,29 @@ class Plan:
         cell = torch.empty(self.n_grid, dtype=torch.int32, device="cuda")
         _check(lib().mc_plan_mapping(self.handle, _ptr(vid), _ptr(w), _ptr(cell), _stream()), "mc_plan_mapping")
         return vid, w, cell
+
+    @property
+    def remap_mask(self) -> int:
+        t = McTuning()
+        _check(lib().mc_plan_get_tuning(self.handle, C.byref(t)), "mc_plan_get_tuning")
+        return int(t.remap_mask)
+
+    @remap_mask.setter
+    def remap_mask(self, mask: int):
+        t = McTuning(mask)
+        _check(lib().mc_plan_set_tuning(self.handle, C.byref(t)), "mc_plan_set_tuning")
+
+    def tune(self, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None, reps: int = 5) -> int:
+        """Chooses the launch-order knobs by timing this field; returns the mask."""
+        torch = _torch()
+        codes = Codes(self, field.dtype, learned=model is not None)
+        out = torch.empty_like(field)
+        prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
+                       None if model is None else model.handle)
+        t = McTuning()
+        _check(lib().mc_plan_tune(self.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
+                                  _ptr(out), reps, _stream(), C.byref(t)), "mc_plan_tune")
+        return int(t.remap_mask)
 
     def destroy(self):
         if getattr(self, "handle", None):

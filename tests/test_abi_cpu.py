@@ -74,6 +74,14 @@ def test_host_validation_before_device_work():
     assert lib.mc_model_import(junk, len(junk), C.byref(out)) == M.ERR_FORMAT
     # grids
     assert lib.mc_grid_from_dims(None, 2, 10, None, None, C.byref(g)) == M.ERR_ARG
+    # tuning
+    t = M.McTuning(0x7F)
+    assert lib.mc_plan_get_tuning(None, C.byref(t)) == M.ERR_ARG
+    assert lib.mc_plan_set_tuning(None, C.byref(t)) == M.ERR_ARG
+    assert lib.mc_plan_tune(None, fake, M.F32, C.byref(prm), C.byref(codes), fake, 3, None, None) == M.ERR_ARG
+    # batches
+    assert lib.mc_batch_decompress(None, 1, None) == M.ERR_ARG
+    assert lib.mc_batch_compress(fake, 0, None) == M.ERR_ARG
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
