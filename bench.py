@@ -407,12 +407,14 @@ def main():
     ng = plan.n_grid
     log(f"plan built in {plan_s:.2f} s: {info}")
 
-    tune = {"remap_mask": plan.remap_mask, "seconds": 0.0}
+    tune = {"remap_mask": plan.remap_mask, "seconds": 0.0, "key": M.tuning_key(plan, x.dtype)}
     if not args.no_tune:
         t0 = time.time()
-        tune["remap_mask"] = plan.tune(x, args.eb, "rel", args.split, reps=5)
+        tune["cached"] = tune["key"] in M.tuning_cache()
+        tune["remap_mask"] = plan.tune(x, args.eb, "rel", args.split, reps=5, cache=True)
         tune["seconds"] = round(time.time() - t0, 3)
-        log(f"tuned launch order: remap mask 0x{tune['remap_mask']:02x} in {tune['seconds']} s")
+        log(f"launch order: remap mask 0x{tune['remap_mask']:02x} "
+            f"({'from the tuning cache' if tune['cached'] else 'tuned'}) in {tune['seconds']} s")
     codes = M.Codes(plan, x.dtype)
     out = torch.empty_like(x)
 

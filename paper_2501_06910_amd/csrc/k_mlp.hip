@@ -38,13 +38,21 @@ __device__ __forceinline__ unsigned short f2bf(float f)
 __device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
 __device__ __forceinline__ float bfround(float f) { return bf2f(f2bf(f)); }
 
+// Four floats to BF16 (round to nearest even) with the hardware's packed
+// conversion (v_cvt_pk_bf16_f32); the same rounding as f2bf on every
+// finite value.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
 {
+    const bf16x2_t lo = __builtin_convertvector((f32x2_t){a, b}, bf16x2_t);
+    const bf16x2_t hi = __builtin_convertvector((f32x2_t){c, d}, bf16x2_t);
+    const unsigned ul = __builtin_bit_cast(unsigned, lo), uh = __builtin_bit_cast(unsigned, hi);
     bf16x4 r;
-    r[0] = (short)f2bf(a);
-    r[1] = (short)f2bf(b);
-    r[2] = (short)f2bf(c);
-    r[3] = (short)f2bf(d);
+    r[0] = (short)(ul & 0xffffu);
+    r[1] = (short)(ul >> 16);
+    r[2] = (short)(uh & 0xffffu);
+    r[3] = (short)(uh >> 16);
     return r;
 }
 
@@ -96,6 +104,49 @@ __device__ void load_weights(LdsWeights<D, TRANSPOSED>& s, const mck::MlpDev& m)
     __syncthreads();
 }
 
+// Inference copy of the weights in LDS, fragment-major: the A fragment of
+// block (mb, kb) for lane l is entry (mb * KB + kb) * 64 + l, so a wave reads
+// 512 consecutive bytes per fragment (no bank conflicts, unlike 16 rows of
+// a row-major matrix read at one column).
+template <int D> struct LdsFrag {
+    bf16x4 w1[4 * MlpShape<D>::KB * 64];
+    bf16x4 w2[16 * 64];
+    bf16x4 w3[16 * 64];
+    float b1[HID], b2[HID], b3[HID], w4[HID];
+    float b4;
+};
+
+__device__ __forceinline__ bf16x4 frag_of(const unsigned short* w, int ld, int kblocks, int idx)
+{
+    const int l = idx & 63, kb = (idx >> 6) % kblocks, mb = (idx >> 6) / kblocks;
+    const unsigned short* src = w + (mb * 16 + (l & 15)) * ld + kb * 16 + 4 * (l >> 4);
+    bf16x4 r;
+    r[0] = (short)src[0];
+    r[1] = (short)src[1];
+    r[2] = (short)src[2];
+    r[3] = (short)src[3];
+    return r;
+}
+
+template <int D>
+__device__ void load_frag(LdsFrag<D>& s, const mck::MlpDev& m)
+{
+    constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD;
+    for (int i = threadIdx.x; i < 4 * KB * 64; i += blockDim.x) s.w1[i] = frag_of(m.w1, KPAD, KB, i);
+    for (int i = threadIdx.x; i < 16 * 64; i += blockDim.x) {
+        s.w2[i] = frag_of(m.w2, HID, 4, i);
+        s.w3[i] = frag_of(m.w3, HID, 4, i);
+    }
+    for (int i = threadIdx.x; i < HID; i += blockDim.x) {
+        s.b1[i] = m.b1[i];
+        s.b2[i] = m.b2[i];
+        s.b3[i] = m.b3[i];
+        s.w4[i] = bf2f(m.w4[i]);
+    }
+    if (threadIdx.x == 0) s.b4 = m.b4[0];
+    __syncthreads();
+}
+
 // A fragment: rows r0..r0+15 of a row-major bf16 matrix with leading
 // dimension ld, columns c0 + 4(l/16) .. +3 for lane l.
 __device__ __forceinline__ bf16x4 afrag(const unsigned short* w, int ld, int r0, int c0)
@@ -117,18 +168,31 @@ __device__ __forceinline__ VGeom vertex_geom(const float* __restrict__ coords, l
     VGeom q;
     q.i2 = 0;
     q.t2 = 0.0f;
-    axis_cell(coords[v], gg.of[0], gg.ihf[0], gg.n0, q.i0, q.t0);
-    axis_cell(coords[nv + v], gg.of[1], gg.ihf[1], gg.n1, q.i1, q.t1);
-    if (D == 3) axis_cell(coords[2 * nv + v], gg.of[2], gg.ihf[2], gg.n2, q.i2, q.t2);
+    // coordinates, then the cell's corners, each batch issued before use
+    const float p0 = coords[v], p1 = coords[nv + v], p2 = D == 3 ? coords[2 * nv + v] : 0.0f;
+    axis_cell(p0, gg.of[0], gg.ihf[0], gg.n0, q.i0, q.t0);
+    axis_cell(p1, gg.of[1], gg.ihf[1], gg.n1, q.i1, q.t1);
+    if (D == 3) axis_cell(p2, gg.of[2], gg.ihf[2], gg.n2, q.i2, q.t2);
     const int n0 = gg.n0;
     const unsigned n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
     const unsigned j = (unsigned)q.i0 + (unsigned)n0 * (unsigned)q.i1 + n01 * (unsigned)q.i2;
-    const float c00 = lerpf_(xh[j], xh[j + 1], q.t0);
-    const float c10 = lerpf_(xh[j + n0], xh[j + n0 + 1], q.t0);
+    float c[8];
+    c[0] = xh[j];
+    c[1] = xh[j + 1];
+    c[2] = xh[j + n0];
+    c[3] = xh[j + n0 + 1];
+    if (D == 3) {
+        c[4] = xh[j + n01];
+        c[5] = xh[j + n01 + 1];
+        c[6] = xh[j + n01 + n0];
+        c[7] = xh[j + n01 + n0 + 1];
+    }
+    const float c00 = lerpf_(c[0], c[1], q.t0);
+    const float c10 = lerpf_(c[2], c[3], q.t0);
     float g = lerpf_(c00, c10, q.t1);
     if (D == 3) {
-        const float c01 = lerpf_(xh[j + n01], xh[j + n01 + 1], q.t0);
-        const float c11 = lerpf_(xh[j + n01 + n0], xh[j + n01 + n0 + 1], q.t0);
+        const float c01 = lerpf_(c[4], c[5], q.t0);
+        const float c11 = lerpf_(c[6], c[7], q.t0);
         g = lerpf_(g, lerpf_(c01, c11, q.t1), q.t2);
     }
     q.g = g;
@@ -169,23 +233,62 @@ __device__ __forceinline__ float feature(int k, const VGeom& q, const GridGeom& 
     return 0.0f;
 }
 
-// Input fragments of the wave's 4 column blocks: zf[nb][kb].
+// Input fragments of the wave's 4 column blocks: zf[nb][kb].  Inputs
+// k < NN are neighbourhood differences (one gather each), the next D the
+// in-cell offsets, the rest zero padding; which fragment holds which is the
+// same for every lane (16 inputs per fragment, NN a multiple of 16), so the
+// gathers are issued NBB column blocks at a time, all before any is used,
+// with no branch around them (an invalid vertex gathers a clamped node and
+// its inputs are zeroed afterwards).
 template <int D>
 __device__ __forceinline__ void build_inputs(bf16x4 (&zf)[4][MlpShape<D>::KB], const VGeom& mine, bool valid_any,
                                              const GridGeom& gg, const float* __restrict__ xh, float kappa,
                                              const bool (&valid)[4])
 {
+    constexpr int NN = MlpShape<D>::NN, KB = MlpShape<D>::KB, KG = NN / 16;   // fragments with gathers
+    constexpr int NBB = D == 2 ? 4 : 2;                                          // column blocks per batch
     const int l = lane_id(), g4 = 4 * (l >> 4);
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        const VGeom q = shfl_geom(mine, nb * 16 + (l & 15));
+    for (int nb0 = 0; nb0 < 4; nb0 += NBB) {
+        VGeom q[NBB];
+        float val[NBB][KG][4];
 #pragma unroll
-        for (int kb = 0; kb < MlpShape<D>::KB; ++kb) {
-            float f[4];
+        for (int u = 0; u < NBB; ++u) {
+            q[u] = shfl_geom(mine, (nb0 + u) * 16 + (l & 15));
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                f[i] = valid[nb] ? feature<D>(kb * 16 + g4 + i, q, gg, xh, kappa) : 0.0f;
-            zf[nb][kb] = pack4(f[0], f[1], f[2], f[3]);
+            for (int kb = 0; kb < KG; ++kb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = kb * 16 + g4 + i;
+                    const int a0 = k & 3, a1 = (k >> 2) & 3, a2 = k >> 4;
+                    const int n0 = min(max(q[u].i0 - 1 + a0, 0), gg.n0 - 1);
+                    const int n1 = min(max(q[u].i1 - 1 + a1, 0), gg.n1 - 1);
+                    const int n2 = D == 3 ? min(max(q[u].i2 - 1 + a2, 0), gg.n2 - 1) : 0;
+                    val[u][kb][i] = xh[(unsigned)n0 + (unsigned)gg.n0 * ((unsigned)n1 + (unsigned)gg.n1 * (unsigned)n2)];
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < NBB; ++u) {
+            const int nb = nb0 + u;
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+                float f[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int k = kb * 16 + g4 + i;
+                    float x;
+                    if (kb < KG) {
+                        x = (val[u][kb < KG ? kb : 0][i] - q[u].g) * kappa;
+                    } else if (k < NN + D) {
+                        const float t = (k - NN) == 0 ? q[u].t0 : ((k - NN) == 1 ? q[u].t1 : q[u].t2);
+                        x = t - 0.5f;
+                    } else {
+                        x = 0.0f;
+                    }
+                    f[i] = valid[nb] ? x : 0.0f;
+                }
+                zf[nb][kb] = pack4(f[0], f[1], f[2], f[3]);
+            }
         }
     }
     (void)valid_any;
@@ -217,6 +320,36 @@ __device__ __forceinline__ void hidden_layer(const unsigned short* w, int ld, co
                 h[i] = x > 0.0f ? x : 0.0f;
             }
             pre[mb][nb] = (f32x4){h[0], h[1], h[2], h[3]};
+            out[nb][mb] = pack4(h[0], h[1], h[2], h[3]);
+        }
+    }
+}
+
+// The same layer with the weights in fragment-major LDS (inference).
+template <int KBLK>
+__device__ __forceinline__ void hidden_layer_f(const bf16x4* wf, const float* b, const bf16x4 (&in)[4][KBLK],
+                                               bf16x4 (&out)[4][4])
+{
+    const int l = lane_id(), g4 = 4 * (l >> 4);
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) {
+        f32x4 acc[4];
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < KBLK; ++kb) {
+            const bf16x4 a = wf[(mb * KBLK + kb) * 64 + l];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, in[nb][kb], acc[nb]);
+        }
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+            float h[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float x = acc[nb][i] + b[mb * 16 + g4 + i];
+                h[i] = x > 0.0f ? x : 0.0f;
+            }
             out[nb][mb] = pack4(h[0], h[1], h[2], h[3]);
         }
     }
@@ -255,6 +388,17 @@ __device__ __forceinline__ void forward(const LdsWeights<D, false>* sw0, const u
     (void)sw0;
 }
 
+template <int D>
+__device__ __forceinline__ void forward_f(const LdsFrag<D>& sw, const bf16x4 (&zf)[4][MlpShape<D>::KB],
+                                          float (&rho)[4])
+{
+    bf16x4 h1[4][4], h2[4][4], h3[4][4];
+    hidden_layer_f<MlpShape<D>::KB>(sw.w1, sw.b1, zf, h1);
+    hidden_layer_f<4>(sw.w2, sw.b2, h1, h2);
+    hidden_layer_f<4>(sw.w3, sw.b3, h2, h3);
+    head(sw.w4, sw.b4, h3, rho);
+}
+
 __device__ __forceinline__ int rho_quant(float r)
 {
     const double q = rint((double)r);
@@ -267,14 +411,15 @@ __device__ __forceinline__ int rho_quant(float r)
 // ---------------------------------------------------------------------------
 // inference: rho_q for every vertex (or only those in learned blocks)
 // ---------------------------------------------------------------------------
+// Register use is capped at 128 (4 waves per SIMD): the inputs, the layer
+// activations and the accumulators of a 64-vertex tile fit without spills.
 template <int D>
-__global__ __launch_bounds__(256) void k_mlp_infer(mck::MlpDev m, const float* __restrict__ coords, long long nv,
-                                                   GridGeom gg, const float* __restrict__ xh,
-                                                   const uint32_t* __restrict__ only_blocks,
-                                                   int32_t* __restrict__ rho_q)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_infer(
+    mck::MlpDev m, const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
+    const uint32_t* __restrict__ only_blocks, int32_t* __restrict__ rho_q)
 {
-    __shared__ LdsWeights<D, false> sw;
-    load_weights<D, false>(sw, m);
+    __shared__ LdsFrag<D> sw;
+    load_frag<D>(sw, m);
     const long long ntiles = (nv + 63) / 64;
     const int l = lane_id();
     for (long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
@@ -291,9 +436,8 @@ __global__ __launch_bounds__(256) void k_mlp_infer(mck::MlpDev m, const float* _
         for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
         bf16x4 zf[4][MlpShape<D>::KB];
         build_inputs<D>(zf, mine, true, gg, xh, m.kappa, valid);
-        bf16x4 h1[4][4], h2[4][4], h3[4][4];
         float rho[4];
-        forward<D>(nullptr, sw.w1, sw.w2, sw.w3, sw.b1, sw.b2, sw.b3, sw.w4, sw.b4, zf, h1, h2, h3, rho);
+        forward_f<D>(sw, zf, rho);
         // lane l holds vertex l of the tile as rho[l / 16]
         float r = rho[0];
         if ((l >> 4) == 1) r = rho[1];
@@ -321,8 +465,8 @@ template <int D>
 __global__ __launch_bounds__(256) void k_mlp_forward_z(mck::MlpDev m, const float* __restrict__ z, long long batch,
                                                        float* __restrict__ out)
 {
-    __shared__ LdsWeights<D, false> sw;
-    load_weights<D, false>(sw, m);
+    __shared__ LdsFrag<D> sw;
+    load_frag<D>(sw, m);
     constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD;
     const long long ntiles = (batch + 63) / 64;
     const int l = lane_id(), g4 = 4 * (l >> 4);
@@ -340,9 +484,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward_z(mck::MlpDev m, const floa
                 zf[nb][kb] = pack4(f[0], f[1], f[2], f[3]);
             }
         }
-        bf16x4 h1[4][4], h2[4][4], h3[4][4];
         float rho[4];
-        forward<D>(nullptr, sw.w1, sw.w2, sw.w3, sw.b1, sw.b2, sw.b3, sw.w4, sw.b4, zf, h1, h2, h3, rho);
+        forward_f<D>(sw, zf, rho);
         float r = rho[0];
         if ((l >> 4) == 1) r = rho[1];
         if ((l >> 4) == 2) r = rho[2];

@@ -8,6 +8,7 @@ fallback.
 from __future__ import annotations
 
 import ctypes as C
+import json
 import os
 from dataclasses import dataclass
 
@@ -262,9 +263,20 @@ class Plan:
         t = McTuning(mask)
         _check(lib().mc_plan_set_tuning(self.handle, C.byref(t)), "mc_plan_set_tuning")
 
-    def tune(self, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None, reps: int = 5) -> int:
-        """Chooses the launch-order knobs by timing this field; returns the mask."""
+    def tune(self, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None, reps: int = 5,
+             cache: bool = False) -> int:
+        """Chooses the launch-order knobs by timing this field; returns the
+        mask.  With cache=True, a mask stored for this device, grid and mesh
+        size (tuning_cache.json beside this module) is applied without
+        timing, and a new choice is stored there."""
         torch = _torch()
+        key = None
+        if cache:
+            key = tuning_key(self, field.dtype)
+            hit = tuning_cache().get(key)
+            if hit is not None:
+                self.remap_mask = int(hit["remap_mask"])
+                return int(hit["remap_mask"])
         codes = Codes(self, field.dtype, learned=model is not None)
         out = torch.empty_like(field)
         prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
@@ -272,6 +284,8 @@ class Plan:
         t = McTuning()
         _check(lib().mc_plan_tune(self.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
                                   _ptr(out), reps, _stream(), C.byref(t)), "mc_plan_tune")
+        if key is not None:
+            store_tuning(key, int(t.remap_mask))
         return int(t.remap_mask)
 
     def destroy(self):
@@ -289,6 +303,37 @@ class Plan:
 # ---------------------------------------------------------------------------
 # compressed buffers
 # ---------------------------------------------------------------------------
+
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+
+
+def tuning_key(plan: "Plan", dtype) -> str:
+    """Cache key of a tuning: device architecture, grid dims, vertex count, dtype."""
+    torch = _torch()
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    g = plan.grid
+    dims = "x".join(str(int(g.dims[d])) for d in range(plan.dim))
+    return f"{arch}|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
+
+
+def tuning_cache() -> dict:
+    if not os.path.exists(TUNING_CACHE):
+        return {}
+    with open(TUNING_CACHE) as f:
+        return json.load(f)
+
+
+def store_tuning(key: str, mask: int):
+    c = tuning_cache()
+    c[key] = {"remap_mask": mask}
+    try:
+        tmp = TUNING_CACHE + f".tmp{os.getpid()}"
+        with open(tmp, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+        os.replace(tmp, TUNING_CACHE)
+    except OSError:
+        pass            # a read-only install keeps tuning per process
+
 
 class Codes:
     """Device buffers of one compressed field (allocated with torch)."""
