@@ -61,6 +61,26 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// K = 32 products per instruction (gfx950).  Each lane supplies 8 values of
+// A and 8 of B; the instruction pairs A's and B's values of the same lane
+// group and slot, so any assignment of the 32 k indices to (lane group,
+// slot) gives the full sum as long as A and B use the same one.  Here slot
+// i < 4 of lane group g is k = 4g + i of the first 16-block and slot 4 + i
+// the same of the second: the B operand is then just two 16-wide fragments
+// side by side (the output of the 16-row MFMA layout), and the weights are
+// stored in that order.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ bf16x8 cat8(bf16x4 a, bf16x4 b)
+{
+    typedef short s8 __attribute__((ext_vector_type(8)));
+    const s8 v = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 template <int D> struct MlpShape {
     static constexpr int NN = D == 2 ? 16 : 64;     // neighbourhood nodes
     static constexpr int KIN = NN + D;
@@ -104,38 +124,40 @@ __device__ void load_weights(LdsWeights<D, TRANSPOSED>& s, const mck::MlpDev& m)
     __syncthreads();
 }
 
-// Inference copy of the weights in LDS, fragment-major: the A fragment of
-// block (mb, kb) for lane l is entry (mb * KB + kb) * 64 + l, so a wave reads
-// 512 consecutive bytes per fragment (no bank conflicts, unlike 16 rows of
-// a row-major matrix read at one column).
+// Inference copy of the weights in LDS, fragment-major for the K = 32
+// instruction: the A fragment of row block mb and k pair c (16-blocks 2c
+// and 2c + 1) for lane l is entry (mb * KC + c) * 64 + l, so a wave reads
+// 1 KB of consecutive bytes per fragment (no bank conflicts).
 template <int D> struct LdsFrag {
-    bf16x4 w1[4 * MlpShape<D>::KB * 64];
-    bf16x4 w2[16 * 64];
-    bf16x4 w3[16 * 64];
+    bf16x8 w1[4 * (MlpShape<D>::KB / 2) * 64];
+    bf16x8 w2[8 * 64];
+    bf16x8 w3[8 * 64];
     float b1[HID], b2[HID], b3[HID], w4[HID];
     float b4;
 };
 
-__device__ __forceinline__ bf16x4 frag_of(const unsigned short* w, int ld, int kblocks, int idx)
+__device__ __forceinline__ bf16x8 frag8_of(const unsigned short* w, int ld, int kpairs, int idx)
 {
-    const int l = idx & 63, kb = (idx >> 6) % kblocks, mb = (idx >> 6) / kblocks;
-    const unsigned short* src = w + (mb * 16 + (l & 15)) * ld + kb * 16 + 4 * (l >> 4);
-    bf16x4 r;
-    r[0] = (short)src[0];
-    r[1] = (short)src[1];
-    r[2] = (short)src[2];
-    r[3] = (short)src[3];
-    return r;
+    const int l = idx & 63, c = (idx >> 6) % kpairs, mb = (idx >> 6) / kpairs, g = l >> 4;
+    const unsigned short* row = w + (mb * 16 + (l & 15)) * ld;
+    typedef short s8 __attribute__((ext_vector_type(8)));
+    s8 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r[i] = (short)row[(2 * c) * 16 + 4 * g + i];
+        r[4 + i] = (short)row[(2 * c + 1) * 16 + 4 * g + i];
+    }
+    return __builtin_bit_cast(bf16x8, r);
 }
 
 template <int D>
 __device__ void load_frag(LdsFrag<D>& s, const mck::MlpDev& m)
 {
-    constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD;
-    for (int i = threadIdx.x; i < 4 * KB * 64; i += blockDim.x) s.w1[i] = frag_of(m.w1, KPAD, KB, i);
-    for (int i = threadIdx.x; i < 16 * 64; i += blockDim.x) {
-        s.w2[i] = frag_of(m.w2, HID, 4, i);
-        s.w3[i] = frag_of(m.w3, HID, 4, i);
+    constexpr int KC = MlpShape<D>::KB / 2, KPAD = MlpShape<D>::KPAD;
+    for (int i = threadIdx.x; i < 4 * KC * 64; i += blockDim.x) s.w1[i] = frag8_of(m.w1, KPAD, KC, i);
+    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) {
+        s.w2[i] = frag8_of(m.w2, HID, 2, i);
+        s.w3[i] = frag8_of(m.w3, HID, 2, i);
     }
     for (int i = threadIdx.x; i < HID; i += blockDim.x) {
         s.b1[i] = m.b1[i];
@@ -325,22 +347,29 @@ __device__ __forceinline__ void hidden_layer(const unsigned short* w, int ld, co
     }
 }
 
-// The same layer with the weights in fragment-major LDS (inference).
+// The same layer with the weights in fragment-major LDS and the K = 32
+// instruction (inference): KBLK 16-blocks of input, taken in pairs.
 template <int KBLK>
-__device__ __forceinline__ void hidden_layer_f(const bf16x4* wf, const float* b, const bf16x4 (&in)[4][KBLK],
+__device__ __forceinline__ void hidden_layer_f(const bf16x8* wf, const float* b, const bf16x4 (&in)[4][KBLK],
                                                bf16x4 (&out)[4][4])
 {
+    constexpr int KC = KBLK / 2;
     const int l = lane_id(), g4 = 4 * (l >> 4);
+    bf16x8 bin[4][KC];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb)
+#pragma unroll
+        for (int c = 0; c < KC; ++c) bin[nb][c] = cat8(in[nb][2 * c], in[nb][2 * c + 1]);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
         f32x4 acc[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kb = 0; kb < KBLK; ++kb) {
-            const bf16x4 a = wf[(mb * KBLK + kb) * 64 + l];
+        for (int c = 0; c < KC; ++c) {
+            const bf16x8 a = wf[(mb * KC + c) * 64 + l];
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, in[nb][kb], acc[nb]);
+            for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma32(a, bin[nb][c], acc[nb]);
         }
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) {
