@@ -84,6 +84,7 @@ def lib():
             "mco_locate_brute": (i64, [P, P, i32, i64, i64, P, P, P, P]),
             "mco_locate_raster": (i64, [P, P, i32, i64, i64, P, P, P, P]),
             "mco_fill_unresolved": (None, [P, i32, i64, P, P, i32, P, P]),
+            "mco_locate_nodes": (None, [P, P, i32, i64, i64, P, P, i64, P, i32, i32, P, P, P]),
             "mco_resample": (None, [P, P, i32, i64, P, i32, dbl, P]),
             "mco_vertex_cell": (None, [P, i32, i64, P, i64, P, P]),
             "mco_back_interp": (None, [P, i32, i64, P, P, P]),
@@ -221,6 +222,29 @@ def locate(coords, cells, g: Grid, method: str = "raster", fill: str = "nearest"
         lib().mco_fill_unresolved(_p(coords), dim, coords.shape[1], _p(g), _p(cell),
                                   int(fill == "nearest"), _p(vid), _p(w))
     return Mapping(cell, vid, w, int(nun))
+
+
+def locate_nodes(coords, cells, g: Grid, nodes, cand, fill: str = "nearest") -> Mapping:
+    """Location of the listed grid nodes: the lowest-id cell among cand[i]
+    (ascending cell ids, -1 = none) that contains node nodes[i], else the
+    fill.  Exact when cand[i] holds every cell that can contain the node.
+    Returns a Mapping over the listed nodes only."""
+    dim = coords.shape[0]
+    nodes = np.ascontiguousarray(nodes, np.int64)
+    cand = np.ascontiguousarray(cand, np.int32)
+    nn = nodes.size
+    cell = np.empty(nn, np.int32)
+    vid = np.empty((dim + 1, nn), np.int32)
+    w = np.empty((dim + 1, nn), np.float32)
+    lib().mco_locate_nodes(_p(coords), _p(cells), dim, coords.shape[1], cells.shape[1], _p(g), _p(nodes), nn,
+                           _p(cand), cand.shape[1], int(fill == "nearest"), _p(cell), _p(vid), _p(w))
+    return Mapping(cell, vid, w, int((cell < 0).sum()))
+
+
+def grid_node(g: Grid, j: int) -> np.ndarray:
+    y = np.zeros(3, np.float32)
+    lib().mco_grid_node(_p(g), int(j), _p(y))
+    return y
 
 
 def resample(m: Mapping, x: np.ndarray, c: float) -> np.ndarray:

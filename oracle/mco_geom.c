@@ -329,6 +329,57 @@ void mco_fill_unresolved(const float* coords, int dim, int64_t nv, const mco_gri
     }
 }
 
+/* Point location of selected grid nodes (the definition above, restricted):
+ * node nodes[i] is tested against the cells cand[i * ncand .. + ncand - 1]
+ * (cell ids, ascending; -1 entries are skipped), takes the lowest id that
+ * contains it, and otherwise the nearest-vertex fill (nearest != 0) or the
+ * mid-range marker.  Exact when the caller's candidate set holds every cell
+ * that can contain the node.  Outputs per listed node: cell_out[i],
+ * vid_out[k * nn + i], w_out[k * nn + i]. */
+void mco_locate_nodes(const float* coords, const int32_t* cells, int dim, int64_t nv, int64_t nc,
+                      const mco_grid* g, const int64_t* nodes, int64_t nn, const int32_t* cand, int ncand,
+                      int nearest, int32_t* cell_out, int32_t* vid_out, float* w_out)
+{
+    float y[3], verts[12], lam[4];
+    for (int64_t i = 0; i < nn; ++i) {
+        const int64_t j = nodes[i];
+        mco_grid_node(g, j, y);
+        int32_t hit = -1;
+        for (int q = 0; q < ncand && hit < 0; ++q) {
+            const int32_t c = cand[i * ncand + q];
+            if (c < 0 || c >= nc) continue;
+            gather_cell(coords, cells, dim, nv, nc, c, verts);
+            int nd = 0;
+            if (mco_bary(dim, verts, y, lam, &nd)) {
+                hit = c;
+                for (int k = 0; k <= dim; ++k) {
+                    vid_out[k * nn + i] = cells[(int64_t)k * nc + c];
+                    w_out[k * nn + i] = lam[k];
+                }
+            }
+        }
+        cell_out[i] = hit;
+        if (hit >= 0) continue;
+        int64_t best = -1;
+        float bd = 0.0f;
+        if (nearest)
+            for (int64_t v = 0; v < nv; ++v) {
+                float dx = coords[v] - y[0];
+                float dy = coords[nv + v] - y[1];
+                float dd = dx * dx + dy * dy;
+                if (dim == 3) {
+                    float dz = coords[2 * nv + v] - y[2];
+                    dd = dd + dz * dz;
+                }
+                if (best < 0 || dd < bd) { best = v; bd = dd; }
+            }
+        for (int k = 0; k <= dim; ++k) {
+            vid_out[k * nn + i] = (int32_t)best;
+            w_out[k * nn + i] = (nearest && k == 0) ? 1.0f : 0.0f;
+        }
+    }
+}
+
 static float field_as_float(const void* x, int dtype, int64_t i)
 {
     return dtype == MCO_F64 ? (float)((const double*)x)[i] : ((const float*)x)[i];

@@ -271,3 +271,36 @@ def test_grid_from_dims():
     assert list(g.o)[:2] == [0.25, -1.0]
     assert list(g.h)[:2] == [0.25, 1.0]
     assert g.dims() == (9, 5, 1)
+
+
+def test_locate_nodes_equals_brute_with_all_cells():
+    """The restricted locator with every cell as candidate is the brute-force
+    definition (2-D Delaunay with a ragged hull, nearest fill)."""
+    rng = np.random.default_rng(21)
+    mesh = G.delaunay_2d(G.stratified_points_2d(24, rng, drop=10))
+    g = O.grid_from_dims(mesh.coords, (17, 15))
+    ref = O.locate(mesh.coords, mesh.cells, g, "brute")
+    nodes = np.arange(g.count)
+    cand = np.tile(np.arange(mesh.n_cells, dtype=np.int32), (nodes.size, 1))
+    got = O.locate_nodes(mesh.coords, mesh.cells, g, nodes, cand)
+    assert np.array_equal(got.cell, ref.cell)
+    assert np.array_equal(got.vid, ref.vid)
+    assert np.array_equal(got.w.view(np.uint32), ref.w.view(np.uint32))
+
+
+def test_kuhn_candidates_are_complete():
+    """For a jittered Kuhn lattice the 27-cube candidate sets give exactly the
+    brute-force location of every node (so they may stand in for a full scan
+    on meshes too large to scan)."""
+    from kuhn_cells import kuhn_candidates
+    n = 9
+    mesh = G.kuhn_tet_mesh(n, 4)
+    g = O.grid_from_dims(mesh.coords, (11, 10, 12))
+    ref = O.locate(mesh.coords, mesh.cells, g, "brute")
+    nodes = np.arange(g.count)
+    pts = np.stack([O.grid_node(g, j) for j in nodes], axis=1)
+    got = O.locate_nodes(mesh.coords, mesh.cells, g, nodes, kuhn_candidates(pts, n))
+    assert np.array_equal(got.cell, ref.cell)
+    assert np.array_equal(got.vid, ref.vid)
+    assert np.array_equal(got.w.view(np.uint32), ref.w.view(np.uint32))
+    assert ref.n_unresolved > 0          # the ragged hull leaves nodes to the fill
