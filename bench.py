@@ -280,7 +280,7 @@ def batch_main(args, log):
     import meshgen as G
     from paper_2501_06910_amd import mc as M
     t0 = time.time()
-    meshes, grids, fields = G.config_batch(scale=args.batch_scale)
+    meshes, grids, fields = G.config_batch(scale=args.batch_scale, log=lambda m: log(f"batch: {m}"))
     log(f"batch: generated {len(meshes)} meshes / {len(fields)} fields in {time.time() - t0:.1f} s")
     plans = []
     t0 = time.time()

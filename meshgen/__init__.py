@@ -367,13 +367,14 @@ def config_learned_series(seed: int = 4, h0: float = 7.615e-4, dims: int = 2048,
 
 
 def config_batch(seed: int = 5, scale: float = 1.0, n_meshes: int = 12,
-                 n_fields: int = 64):
+                 n_fields: int = 64, log=None):
     """Uneven multi-mesh workload: ``n_meshes`` meshes with vertex counts
     log-uniform in [0.5M, 20M] * scale (the first two forced to the ends),
     even-indexed meshes 2-D jittered structured triangulations, odd-indexed
     3-D Kuhn meshes; field i lives on mesh i mod n_meshes, float32 for even
     i and float64 for odd i, relative eb 1e-3/1e-4/1e-5 by i mod 3, grids
-    with about one node per four vertices."""
+    with about one node per four vertices.  ``log`` (optional) is called
+    with a line per generated mesh."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
     lo, hi = 0.5e6 * scale, 20e6 * scale
     sizes = np.exp(rng.uniform(math.log(lo), math.log(hi), n_meshes))
@@ -392,6 +393,8 @@ def config_batch(seed: int = 5, scale: float = 1.0, n_meshes: int = 12,
             d = max(2, math.ceil((mesh.n_vertices / 4) ** (1 / 3)))
             grids.append((d, d, d))
         meshes.append(mesh)
+        if log:
+            log(f"mesh {m}: {mesh.dim}-D, {mesh.n_vertices} vertices, {mesh.n_cells} cells")
     fields = []
     for i in range(n_fields):
         m = i % n_meshes
