@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c"]
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c"]
 
 OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
 F32, F64 = 0, 1
@@ -85,6 +85,8 @@ def lib():
             "mco_locate_raster": (i64, [P, P, i32, i64, i64, P, P, P, P]),
             "mco_fill_unresolved": (None, [P, i32, i64, P, P, i32, P, P]),
             "mco_locate_nodes": (None, [P, P, i32, i64, i64, P, P, i64, P, i32, i32, P, P, P]),
+            "mco_serial_compress": (i32, [P, i32, i64, dbl, i32, P, P, P, i64, P, P]),
+            "mco_serial_decompress": (None, [P, P, P, i64, i64, P, i32, P]),
             "mco_resample": (None, [P, P, i32, i64, P, i32, dbl, P]),
             "mco_vertex_cell": (None, [P, i32, i64, P, i64, P, P]),
             "mco_back_interp": (None, [P, i32, i64, P, P, P]),
@@ -395,6 +397,28 @@ def decompress(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
 # ---------------------------------------------------------------------------
 # learned predictor
 # ---------------------------------------------------------------------------
+
+def serial_compress(x: np.ndarray, eb: float, relative: bool):
+    """1-D serialisation baseline: (codes, raw-outlier indices, raw values, bound)."""
+    n = x.size
+    codes = np.empty(n, np.uint16)
+    oi = np.empty(n, np.int32)
+    ov = np.empty(n, x.dtype)
+    k = C.c_int64(0)
+    b = Bound()
+    st = lib().mco_serial_compress(_p(x), _dtype_code(x), n, eb, int(relative), _p(codes), _p(oi), _p(ov), n,
+                                   C.byref(k), C.byref(b))
+    if st != OK:
+        raise OracleError(st, "serial_compress")
+    return codes, oi[:k.value].copy(), ov[:k.value].copy(), b
+
+
+def serial_decompress(codes, out_idx, out_val, b: Bound, dtype) -> np.ndarray:
+    out = np.empty(codes.size, dtype)
+    lib().mco_serial_decompress(_p(codes), _p(out_idx), _p(out_val), out_idx.size, codes.size, C.byref(b),
+                                _dtype_code(out), _p(out))
+    return out
+
 
 def splitmix64(seed: int, counter: int) -> int:
     return int(lib().mco_splitmix64(seed, counter))

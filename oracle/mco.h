@@ -127,6 +127,12 @@ int32_t mco_rho_quantize(float rho);
 void mco_sample_indices(uint64_t seed, int64_t step, int64_t batch, int64_t n,
                         int64_t* idx);
 
+/* 1-D serialisation baseline (mco_serial.c). */
+int mco_serial_compress(const void* x, int dtype, int64_t n, double eb, int relative, uint16_t* codes,
+                        int32_t* out_idx, void* out_val, int64_t cap, int64_t* n_out, mco_bound* b);
+void mco_serial_decompress(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
+                           int64_t n, const mco_bound* b, int dtype, void* out);
+
 #ifdef __cplusplus
 }
 #endif
