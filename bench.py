@@ -130,6 +130,60 @@ def _timed(fn, reps=5):
     return float(np.median(ts))
 
 
+def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
+    """The Sec. V-C comparison on one field: the 1-D serialisation baseline
+    (vertex order as generated, or a seeded random order) against the
+    multi-component result h_mc (host codes of the same field).  Improvement
+    ratio = CR_mc / CR_serial; overhead = (T_mc - T_serial) / T_serial per
+    direction, device times.  Renumbering the vertices permutes the
+    multi-component vertex codes (same Huffman size) and renumbers its
+    outliers, so its CR under the permutation is recomputed exactly from
+    h_mc."""
+    import torch
+    nv, sT = x.numel(), x.element_size()
+    h_mc = dict(h_mc)
+    if shuffle_seed is not None:
+        g = torch.Generator(device="cpu").manual_seed(shuffle_seed)
+        perm = torch.randperm(nv, generator=g)
+        inv = torch.empty_like(perm)
+        inv[perm] = torch.arange(nv)
+        x = x[perm.cuda()].contiguous()
+        h_mc["v_out_idx"] = np.sort(inv.numpy()[h_mc["v_out_idx"]])
+    cr_mc = nv * sT / M.stream_bytes(h_mc, sT)["total"]
+    ctx = M.Serial(nv)
+    codes = M.SerialCodes(nv, x.dtype)
+    out = torch.empty_like(x)
+    tc = _timed(lambda: M.serial_compress(ctx, x, eb, "rel", codes=codes))
+    td = _timed(lambda: M.serial_decompress(ctx, codes, out=out))
+    h = codes.host()
+    r = h["result"]
+    if r["status"]:
+        raise SystemExit(f"serial baseline ({label}): status {r['status']}")
+    err = (x.double() - out.double()).abs().max().item()
+    if not err <= r["tau"]:
+        raise SystemExit(f"serial baseline ({label}): bound violated")
+    sb = M.serial_stream_bytes(h, sT)
+    cr = nv * sT / sb["total"]
+    M.profile_reset()
+    M.profile_enable(True)
+    for _ in range(5):
+        M.serial_compress(ctx, x, eb, "rel", codes=codes)
+        M.serial_decompress(ctx, codes, out=out)
+    torch.cuda.synchronize()
+    M.profile_enable(False)
+    kern = {k: round(t / c, 5) for k, (c, t) in M.profile_read().items()}
+    row = {"order": "seeded random permutation" if shuffle_seed is not None else "as generated",
+           "cr_serial": round(cr, 3), "cr_mc": round(cr_mc, 3), "improvement_ratio": round(cr_mc / cr, 3),
+           "raw_values": r["n_vertex_outliers"],
+           "serial_GBps": {"compress": round(nv * sT / (tc * 1e-3) / 1e9, 2),
+                           "decompress": round(nv * sT / (td * 1e-3) / 1e9, 2)},
+           "overhead": {"compress": round((ms_mc[0] - tc) / tc, 3), "decompress": round((ms_mc[1] - td) / td, 3)},
+           "kernels_avg_ms": kern}
+    log(f"serial baseline {label}: {row}")
+    ctx.destroy()
+    return row
+
+
 def mlp_flops_per_vertex(D: int) -> int:
     """Multiply-adds of one inference (x2): K_in -> 64 -> 64 -> 64 -> 1 with
     K_in = 4^D + D, the zero padding not counted."""
@@ -168,8 +222,9 @@ def learned_section(log, train_steps=2000, batch=8192):
     per_t = []
     cp, cl = M.Codes(plan, x0.dtype), M.Codes(plan, x0.dtype, learned=True)
     out = torch.empty_like(x0)
-    tot = {"plain": 0, "learned": 0, "raw": 0}
+    tot = {"plain": 0, "learned": 0, "raw": 0, "serial": 0}
     times = {"plain_c": [], "plain_d": [], "learned_c": [], "learned_d": []}
+    sctx, scodes = M.Serial(nv), M.SerialCodes(nv, x0.dtype)
     for t in range(1, len(series)):
         x = torch.from_numpy(series[t]).cuda()
         times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=cp)))
@@ -190,7 +245,14 @@ def learned_section(log, train_steps=2000, batch=8192):
         tot["plain"] += sp
         tot["learned"] += sl
         tot["raw"] += nv * sT
+        M.serial_compress(sctx, x, cfg["eb"], "rel", codes=scodes)
+        hs = scodes.host()
+        if hs["result"]["status"]:
+            raise SystemExit(f"learned section: serial baseline status {hs['result']['status']}")
+        ss = M.serial_stream_bytes(hs, sT)["total"]
+        tot["serial"] += ss
         per_t.append({"t": t, "cr_plain": round(nv * sT / sp, 3), "cr_learned": round(nv * sT / (sl + model_bytes / nT), 3),
+                      "cr_serial": round(nv * sT / ss, 3),
                       "vert_bits_plain": round(M.entropy_bits(hp["vert_codes"]), 3),
                       "vert_bits_learned": round(M.entropy_bits(hl["vert_codes"]), 3),
                       "learned_blocks": hl["result"]["n_learned_blocks"],
@@ -222,6 +284,9 @@ def learned_section(log, train_steps=2000, batch=8192):
                   "k_mlp_train_TFLOPs": round(train_fl / (tr_ms * 1e-3) / 1e12, 2) if tr_ms else None},
         "cr_plain": round(tot["raw"] / tot["plain"], 3),
         "cr_learned": round(tot["raw"] / (tot["learned"] + model_bytes), 3),
+        "cr_serial": round(tot["raw"] / tot["serial"], 3),
+        "improvement_ratio": {"plain": round(tot["serial"] / tot["plain"], 3),
+                              "learned": round(tot["serial"] / (tot["learned"] + model_bytes), 3)},
         "plain_GBps": {"compress": round(nv * sT / (med["plain_c"] * 1e-3) / 1e9, 2),
                        "decompress": round(nv * sT / (med["plain_d"] * 1e-3) / 1e9, 2)},
         "learned_GBps": {"compress": round(nv * sT / (med["learned_c"] * 1e-3) / 1e9, 2),
@@ -521,6 +586,10 @@ def main():
         "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
         "kernels": kernels,
     }
+    mc_c = _timed(lambda: M.compress(plan, x, args.eb, "rel", args.split, codes=codes))
+    mc_d = _timed(lambda: M.decompress(plan, codes, out=out))
+    line["serial_baseline"] = [serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "generated order"),
+                               serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "random order", shuffle_seed=7)]
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:

@@ -300,6 +300,35 @@ mc_status mc_batch_decompress(const mc_batch_ditem* items, int32_t n_items, hipS
 /* Synchronises the device and frees every cached batch graph. */
 mc_status mc_batch_release(void);
 
+/* ---- 1-D serialisation baseline --------------------------------------------
+ * The comparison the multi-component scheme is measured against (Sec. V-C,
+ * the "default" compression: the underlying compressor applied to the
+ * vertex values as a serialised 1-D array).  With the whole bound tau on
+ * one component, c the mid-range and R = MC_RADIUS:
+ *   p_i = rint((x_i - c) / (2 tau))      (FP64, |.| < 2^27 else MC_ERR_RANGE)
+ *   d_i = p_i - p_{i-1}, p_{-1} = 0      (1-D Lorenzo)
+ *   x'_i = (T)(c + p_i 2 tau)
+ *   code_i = d_i + R if |d_i| <= R - 1 and |x_i - x'_i| <= tau, else 0 with
+ *   x_i stored raw (vertex order).
+ * Decoding rebuilds p_i as the running sum of the codes, restarting at each
+ * raw value from rint((raw - c) / (2 tau)).  Every vertex satisfies
+ * |x - x'| <= tau.
+ * Only the vertex fields of mc_codes are used: vert_codes (uint16[n]),
+ * v_out_idx / v_out_val / v_out_cap and result (tau1 = tau, tau2 = 0); the
+ * grid fields, block_flags and diagnostics may be NULL.  A context holds the
+ * device workspace for fields of up to n_max values; calls on one context
+ * must be ordered on one stream. */
+typedef struct mc_serial_s* mc_serial;
+
+mc_status mc_serial_create(int64_t n_max, mc_serial* out);                  /* (sync) */
+mc_status mc_serial_destroy(mc_serial ctx);
+/* Compress d_field (T[n], 1 <= n <= n_max). */
+mc_status mc_serial_compress(mc_serial ctx, const void* d_field, mc_dtype dtype, int64_t n, double eb,
+                             int32_t eb_mode, const mc_codes* codes, hipStream_t stream);
+/* Decompress into d_out (T[n]); n must be the compressed length. */
+mc_status mc_serial_decompress(mc_serial ctx, const mc_codes* codes, int64_t n, void* d_out, mc_dtype dtype,
+                               hipStream_t stream);
+
 /* ---- profiling -----------------------------------------------------------
  * When enabled, every kernel launch is bracketed by HIP events on the
  * launch stream; mc_profile_read returns per-kernel launch counts and

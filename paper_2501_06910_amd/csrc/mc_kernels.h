@@ -100,6 +100,13 @@ hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const f
                          const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
                          hipStream_t s);
 
+// ---- 1-D serialisation baseline (k_serial.hip) ----------------------------
+hipError_t serial_codes(const void* x, int dtype, long long n, const DevBound* bnd, uint16_t* codes, unsigned* count,
+                        unsigned* vsum, unsigned* err, mc_result* res, hipStream_t s);
+// agg: int2[], carry: int[], at least ceil(n / MC_TILE) entries each
+hipError_t serial_decode(const uint16_t* codes, const int32_t* oidx, const void* oval, long long vcap,
+                         const mc_result* res, long long n, int dtype, int2* agg, int* carry, void* out, hipStream_t s);
+
 // ---- learned predictor (k_mlp.hip) ----------------------------------------
 struct MlpDev {
     int dim, kin, kpad;

@@ -112,6 +112,10 @@ _SIGS = {
     "mc_plan_set_tuning": (C.c_int, [_P, _P]),
     "mc_plan_tune": (C.c_int, [_P, _P, C.c_int, _P, _P, _P, C.c_int32, _P, _P]),
     "mc_batch_decompress": (C.c_int, [_P, C.c_int32, _P]),
+    "mc_serial_create": (C.c_int, [C.c_int64, _P]),
+    "mc_serial_destroy": (C.c_int, [_P]),
+    "mc_serial_compress": (C.c_int, [_P, _P, C.c_int, C.c_int64, C.c_double, C.c_int32, _P, _P]),
+    "mc_serial_decompress": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int, _P]),
     "mc_profile_enable": (C.c_int, [C.c_int32]),
     "mc_profile_reset": (C.c_int, []),
     "mc_profile_read": (C.c_int32, [_P, _P, _P, C.c_int32]),
@@ -549,6 +553,88 @@ def batch_decompress(items):
 def batch_release():
     """Synchronises the device and frees every cached batch graph."""
     _check(lib().mc_batch_release(), "mc_batch_release")
+
+
+# ---------------------------------------------------------------------------
+# 1-D serialisation baseline (Sec. V-C comparison)
+# ---------------------------------------------------------------------------
+
+class Serial:
+    """Device workspace of the 1-D baseline for fields of up to n_max values."""
+
+    def __init__(self, n_max: int):
+        h = C.c_void_p()
+        _check(lib().mc_serial_create(int(n_max), C.byref(h)), "mc_serial_create")
+        self.handle = h
+        self.n_max = int(n_max)
+
+    def destroy(self):
+        if getattr(self, "handle", None):
+            lib().mc_serial_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class SerialCodes:
+    """Vertex codes, outliers and result header of one serially compressed field."""
+
+    def __init__(self, n: int, dtype, cap=None):
+        torch = _torch()
+        cap = n if cap is None else cap
+        self.n, self.dtype = n, dtype
+        self.codes = torch.empty(n, dtype=torch.uint16, device="cuda")
+        self.out_idx = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+        self.out_val = torch.empty(max(cap, 1), dtype=dtype, device="cuda")
+        self.result = torch.zeros(C.sizeof(McResult), dtype=torch.uint8, device="cuda")
+        self.struct = McCodes(None, None, None, 0, _ptr(self.codes), _ptr(self.out_idx), _ptr(self.out_val), cap,
+                              None, _ptr(self.result), None, None, None, None)
+
+    def result_host(self) -> dict:
+        r = McResult.from_buffer_copy(self.result.cpu().numpy().tobytes())
+        return {k: getattr(r, k) for k, _ in McResult._fields_}
+
+    def host(self) -> dict:
+        r = self.result_host()
+        k = min(r["n_vertex_outliers"], self.out_idx.numel())
+        return dict(result=r, codes=self.codes.cpu().numpy().view(np.uint16),
+                    out_idx=self.out_idx[:k].cpu().numpy(), out_val=self.out_val[:k].cpu().numpy())
+
+
+def serial_compress(ctx: Serial, field, eb: float, eb_mode: str = "rel", codes: SerialCodes | None = None,
+                    cap=None) -> SerialCodes:
+    _require_cuda(field, "field")
+    n = field.numel()
+    if codes is None:
+        codes = SerialCodes(n, field.dtype, cap)
+    _check(lib().mc_serial_compress(ctx.handle, _ptr(field), _dtype_code(field), n, eb,
+                                    EB_REL if eb_mode == "rel" else EB_ABS, C.byref(codes.struct), _stream()),
+           "mc_serial_compress")
+    return codes
+
+
+def serial_decompress(ctx: Serial, codes: SerialCodes, out=None):
+    torch = _torch()
+    if out is None:
+        out = torch.empty(codes.n, dtype=codes.dtype, device="cuda")
+    _check(lib().mc_serial_decompress(ctx.handle, C.byref(codes.struct), codes.n, _ptr(out), _dtype_code(out),
+                                      _stream()), "mc_serial_decompress")
+    return out
+
+
+def serial_stream_bytes(host: dict, value_bytes: int) -> dict:
+    """Size of the baseline's stream: header, Huffman-coded codes, outlier
+    index gaps (LEB128) and raw payloads."""
+    vi = host["out_idx"].astype(np.int64)
+    gap = np.diff(np.concatenate([[-1], vi])) - 1 if vi.size else vi
+    parts = dict(header=HEADER_BYTES, codes=huffman_size(host["codes"]),
+                 outliers=_leb128_bytes(gap) + vi.size * value_bytes)
+    parts["total"] = sum(parts.values())
+    return parts
 
 
 def profile_enable(on=True):

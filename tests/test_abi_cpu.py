@@ -82,6 +82,13 @@ def test_host_validation_before_device_work():
     # batches
     assert lib.mc_batch_decompress(None, 1, None) == M.ERR_ARG
     assert lib.mc_batch_compress(fake, 0, None) == M.ERR_ARG
+    # 1-D serialisation baseline
+    assert lib.mc_serial_create(0, C.byref(out)) == M.ERR_ARG
+    assert lib.mc_serial_create(1 << 31, C.byref(out)) == M.ERR_ARG
+    assert lib.mc_serial_create(16, None) == M.ERR_ARG
+    assert lib.mc_serial_destroy(None) == M.OK
+    assert lib.mc_serial_compress(None, fake, M.F32, 16, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
+    assert lib.mc_serial_decompress(None, C.byref(codes), 16, fake, M.F32, None) == M.ERR_ARG
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
