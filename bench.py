@@ -300,40 +300,78 @@ def learned_section(log, train_steps=2000, batch=8192):
     }
 
 
-def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), splits=(0.1, 0.3, 0.5, 0.7, 0.9)):
-    """CR, bits per value, outlier rates and errors of the tet3d workload
-    over relative error bounds and grid shares (CPU entropy stage)."""
+SWEEP_SPLITS = (("sum", 0.1), ("sum", 0.3), ("sum", 0.5), ("sum", 0.7), ("sum", 0.9),
+                ("full", 0.5), ("full", 1.0), ("full", 2.0), ("full", 4.0))
+
+
+def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), splits=SWEEP_SPLITS):
+    """CR of the tet3d workload over relative error bounds, grid resolutions
+    (the grid spacing hyperparameter of Sec. V-B) and error splits (sum:
+    tau1 + tau2 = tau; full: tau2 = tau), next to the 1-D serialisation
+    baseline in the generated and in a seeded random vertex order (CPU
+    entropy stage).  Improvement ratio = CR_mc / CR_serial."""
     import torch
     import meshgen as G
     from paper_2501_06910_amd import mc as M
     mesh, f, cfg = G.config_tet_3d()
     nv, sT = mesh.n_vertices, 4
-    plan = M.Plan(torch.from_numpy(mesh.coords).cuda(), torch.from_numpy(mesh.cells).cuda(), dims=cfg["dims"])
     x = torch.from_numpy(f).cuda()
     xd = x.double()
     norm = torch.linalg.vector_norm(xd).item()
-    codes = M.Codes(plan, x.dtype)
     out = torch.empty_like(x)
-    rows = []
+    gen = torch.Generator(device="cpu").manual_seed(7)
+    perm = torch.randperm(nv, generator=gen)
+    inv = torch.empty_like(perm)
+    inv[perm] = torch.arange(nv)
+    inv = inv.numpy()
+    xs = x[perm.cuda()].contiguous()
+    sctx, scodes = M.Serial(nv), M.SerialCodes(nv, x.dtype)
+    serial = {}
     for eb in ebs:
-        for sp in splits:
-            M.compress(plan, x, eb, "rel", sp, codes=codes)
-            M.decompress(plan, codes, out=out)
-            h = codes.host()
-            r = h["result"]
-            if r["status"]:
-                rows.append({"eb": eb, "split": sp, "status": r["status"]})
-                continue
-            d = (xd - out.double()).abs()
-            sb = M.stream_bytes(h, sT)
-            rows.append({"eb": eb, "split": sp, "cr": round(nv * sT / sb["total"], 3),
-                         "bits_per_value": round(8 * sb["total"] / nv, 4),
-                         "grid_outlier_rate": r["n_grid_outliers"] / plan.n_grid,
-                         "vertex_outlier_rate": r["n_vertex_outliers"] / nv,
-                         "linf_over_tau": round(d.max().item() / r["tau"], 4),
-                         "rel_l2": float(torch.linalg.vector_norm(d).item() / norm)})
-            log(f"cr sweep: {rows[-1]}")
-    return rows
+        row = {}
+        for name, xx in (("generated", x), ("random", xs)):
+            M.serial_compress(sctx, xx, eb, "rel", codes=scodes)
+            hs = scodes.host()
+            row[name] = round(nv * sT / M.serial_stream_bytes(hs, sT)["total"], 3) if not hs["result"]["status"] \
+                else None
+        serial[eb] = row
+        log(f"cr sweep: serial eb={eb} {row}")
+    sctx.destroy()
+    del xs
+    rows = []
+    coords = torch.from_numpy(mesh.coords).cuda()
+    cells = torch.from_numpy(mesh.cells).cuda()
+    for gd in grids:
+        plan = M.Plan(coords, cells, dims=(gd, gd, gd))
+        codes = M.Codes(plan, x.dtype)
+        for eb in ebs:
+            for mode, sp in splits:
+                M.compress(plan, x, eb, "rel", sp, codes=codes, split_mode=mode)
+                M.decompress(plan, codes, out=out)
+                h = codes.host()
+                r = h["result"]
+                base = {"grid": gd, "eb": eb, "split_mode": mode, "split": sp}
+                if r["status"]:
+                    rows.append(dict(base, status=r["status"]))
+                    continue
+                d = (xd - out.double()).abs()
+                sb = M.stream_bytes(h, sT)
+                hr = dict(h)
+                hr["v_out_idx"] = np.sort(inv[h["v_out_idx"]])
+                cr, crr = nv * sT / sb["total"], nv * sT / M.stream_bytes(hr, sT)["total"]
+                s_gen, s_rnd = serial[eb]["generated"], serial[eb]["random"]
+                rows.append(dict(base, cr=round(cr, 3), bits_per_value=round(8 * sb["total"] / nv, 4),
+                                 grid_bytes=sb["grid"], vert_bytes=sb["vert"],
+                                 improvement_vs_serial=round(cr / s_gen, 3) if s_gen else None,
+                                 improvement_vs_serial_random_order=round(crr / s_rnd, 3) if s_rnd else None,
+                                 grid_outlier_rate=r["n_grid_outliers"] / plan.n_grid,
+                                 vertex_outlier_rate=r["n_vertex_outliers"] / nv,
+                                 linf_over_tau=round(d.max().item() / r["tau"], 4),
+                                 rel_l2=float(torch.linalg.vector_norm(d).item() / norm)))
+                log(f"cr sweep: {rows[-1]}")
+        plan.destroy()
+        del codes
+    return {"serial": {str(k): v for k, v in serial.items()}, "rows": rows}
 
 
 def batch_main(args, log):

@@ -95,13 +95,22 @@ typedef struct {
     int32_t invalid_cells;   /* cells with an out-of-range vertex id (plan creation fails) */
 } mc_plan_info;
 
-/* Compression parameters.  The grid receives tau1 = grid_share * tau and the
- * residuals tau2 = tau - tau1 (Sec. III: tau1 + tau2 <= tau). */
+/* Error split.  MC_SPLIT_SUM: the grid receives tau1 = grid_share * tau and
+ * the residuals tau2 = tau - tau1 (Sec. III: tau1 + tau2 <= tau); every
+ * vertex ends within tau2.  MC_SPLIT_FULL: tau1 = grid_share * tau and
+ * tau2 = tau.  The residuals are taken against the reconstructed grid and
+ * checked per vertex, so a vertex's error is the residual's own
+ * quantisation error: tau2 alone bounds it, and tau1 only sets the grid's
+ * quantisation step (grid noise is absorbed by the residual). */
+typedef enum { MC_SPLIT_SUM = 0, MC_SPLIT_FULL = 1 } mc_split;
+
+/* Compression parameters (zero-initialise, then fill). */
 typedef struct {
     double eb;               /* error bound, > 0 */
     int32_t eb_mode;         /* mc_eb_mode */
-    double grid_share;       /* tau1 / tau, in (0, 1) */
+    double grid_share;       /* tau1 / tau: in (0, 1) for MC_SPLIT_SUM, (0, 16] for MC_SPLIT_FULL */
     mc_model model;          /* NULL: plain residual codes; else learned shift per block */
+    int32_t split_mode;      /* mc_split (0 = MC_SPLIT_SUM) */
 } mc_params;
 
 /* Device-side result header, written by mc_compress and read by

@@ -77,6 +77,7 @@ def lib():
         i64, i32, dbl = C.c_int64, C.c_int, C.c_double
         sig = {
             "mco_bound_compute": (i32, [P, i32, i64, dbl, i32, dbl, P]),
+            "mco_bound_compute_mode": (i32, [P, i32, i64, dbl, i32, dbl, i32, P]),
             "mco_bbox": (None, [P, i32, i64, P, P]),
             "mco_grid_from_dims": (i32, [P, i32, i64, P, P]),
             "mco_grid_node": (None, [P, i64, P]),
@@ -148,9 +149,14 @@ class OracleError(RuntimeError):
 # step functions
 # ---------------------------------------------------------------------------
 
-def bound(x: np.ndarray, eb: float, relative: bool, split: float) -> Bound:
+SPLIT_SUM, SPLIT_FULL = 0, 1
+
+
+def bound(x: np.ndarray, eb: float, relative: bool, split: float, mode: int = SPLIT_SUM) -> Bound:
+    """Error split (Sec. III): SPLIT_SUM tau1 + tau2 = tau; SPLIT_FULL
+    tau2 = tau with the grid's tau1 = split * tau (closed-loop residual)."""
     b = Bound()
-    st = lib().mco_bound_compute(_p(x), _dtype_code(x), x.size, eb, int(relative), split, _p(b))
+    st = lib().mco_bound_compute_mode(_p(x), _dtype_code(x), x.size, eb, int(relative), split, mode, _p(b))
     if st != OK:
         raise OracleError(st, "bound")
     return b
@@ -376,8 +382,8 @@ class Compressed:
 
 
 def compress(coords, m: Mapping, g: Grid, x: np.ndarray, eb: float, relative: bool,
-             split: float, rho_q=None) -> Compressed:
-    b = bound(x, eb, relative, split)
+             split: float, rho_q=None, mode: int = SPLIT_SUM) -> Compressed:
+    b = bound(x, eb, relative, split, mode)
     v = resample(m, x, b.c)
     gc = grid_quantize(v, g, b)
     xhat = grid_recon(gc.p, b)

@@ -54,6 +54,9 @@ typedef struct {
 } mco_bound;
 
 /* ---- error bound ------------------------------------------------------ */
+enum { MCO_SPLIT_SUM = 0, MCO_SPLIT_FULL = 1 };
+int mco_bound_compute_mode(const void* x, int dtype, int64_t n, double eb, int relative,
+                           double split, int mode, mco_bound* out);
 int mco_bound_compute(const void* x, int dtype, int64_t n, double eb, int relative,
                       double split, mco_bound* out);
 

@@ -24,9 +24,21 @@ static double field_at(const void* x, int dtype, int64_t i)
 int mco_bound_compute(const void* x, int dtype, int64_t n, double eb, int relative,
                       double split, mco_bound* out)
 {
+    return mco_bound_compute_mode(x, dtype, n, eb, relative, split, MCO_SPLIT_SUM, out);
+}
+
+/* mode MCO_SPLIT_SUM: tau1 = split tau, tau2 = tau - tau1 (Sec. III: the
+ * two components' bounds add up to tau), split in (0, 1).
+ * mode MCO_SPLIT_FULL: tau1 = split tau, tau2 = tau, split in (0, 16]: the
+ * residual is taken against the reconstructed grid, so a vertex's error is
+ * the residual's own quantisation error and tau2 alone bounds it; tau1 then
+ * only sets the grid's step. */
+int mco_bound_compute_mode(const void* x, int dtype, int64_t n, double eb, int relative,
+                           double split, int mode, mco_bound* out)
+{
     memset(out, 0, sizeof *out);
-    if (n <= 0 || !(eb > 0.0) || !isfinite(eb) || !(split > 0.0) || !(split < 1.0))
-        return MCO_ERR_ARG;
+    if (n <= 0 || !(eb > 0.0) || !isfinite(eb) || !(split > 0.0)) return MCO_ERR_ARG;
+    if (mode == MCO_SPLIT_SUM ? !(split < 1.0) : (mode != MCO_SPLIT_FULL || !(split <= 16.0))) return MCO_ERR_ARG;
     double mn = field_at(x, dtype, 0), mx = mn;
     for (int64_t i = 0; i < n; ++i) {
         double v = field_at(x, dtype, i);
@@ -36,7 +48,7 @@ int mco_bound_compute(const void* x, int dtype, int64_t n, double eb, int relati
     }
     double tau = relative ? eb * (mx - mn) : eb;
     double tau1 = split * tau;
-    double tau2 = tau - tau1;
+    double tau2 = mode == MCO_SPLIT_FULL ? tau : tau - tau1;
     if (!(tau1 > 0.0) || !(tau2 > 0.0)) return MCO_ERR_ARG;
     out->tau = tau;
     out->tau1 = tau1;

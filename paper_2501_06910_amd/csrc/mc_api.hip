@@ -568,7 +568,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     bp.eb = prm->eb;
     bp.split = prm->grid_share;
     bp.relative = prm->eb_mode == MC_EB_REL;
-    bp.pad = 0;
+    bp.mode = prm->split_mode;
     hipError_t e;
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
     RangeOut* cur = p->rbuf;
@@ -603,7 +603,11 @@ mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const 
     if (!prm) return mc_fail(MC_ERR_ARG, "params pointer is NULL");
     if (!(prm->eb > 0.0) || !std::isfinite(prm->eb)) return mc_fail(MC_ERR_ARG, "eb must be finite and > 0");
     if (prm->eb_mode != MC_EB_ABS && prm->eb_mode != MC_EB_REL) return mc_fail(MC_ERR_ARG, "unknown eb_mode");
-    if (!(prm->grid_share > 0.0) || !(prm->grid_share < 1.0)) return mc_fail(MC_ERR_ARG, "grid_share must be in (0, 1)");
+    if (prm->split_mode != MC_SPLIT_SUM && prm->split_mode != MC_SPLIT_FULL) return mc_fail(MC_ERR_ARG, "unknown split_mode");
+    if (prm->split_mode == MC_SPLIT_SUM && (!(prm->grid_share > 0.0) || !(prm->grid_share < 1.0)))
+        return mc_fail(MC_ERR_ARG, "grid_share must be in (0, 1)");
+    if (prm->split_mode == MC_SPLIT_FULL && (!(prm->grid_share > 0.0) || !(prm->grid_share <= 16.0)))
+        return mc_fail(MC_ERR_ARG, "grid_share must be in (0, 16] with MC_SPLIT_FULL");
     if (prm->model && mc_model_dim(prm->model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
     return check_codes(p, codes, prm->model != nullptr);
 }

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/mc.h"
+
 #define MC_R 32768
 #define MC_TILE 1024          // items per workgroup tile (256 threads x 4)
 #define MC_LZ_CHUNK 16        // planes (rows) per Lorenzo sweep
@@ -46,7 +48,7 @@ struct BoundParams {
     double eb;
     double split;
     int relative;
-    int pad;
+    int mode;                    // MC_SPLIT_SUM: tau2 = tau - tau1; MC_SPLIT_FULL: tau2 = tau
 };
 
 // The error split of one call, computed once per call by k_range_final and
@@ -80,7 +82,7 @@ __device__ __forceinline__ DevBound make_bound(const RangeOut* r, BoundParams bp
     b.xmax = mx;
     b.tau = bp.relative ? bp.eb * (mx - mn) : bp.eb;
     b.tau1 = bp.split * b.tau;
-    b.tau2 = b.tau - b.tau1;
+    b.tau2 = bp.mode == MC_SPLIT_FULL ? b.tau : b.tau - b.tau1;
     b.c = 0.5 * (mn + mx);
     b.step1 = 2.0 * b.tau1;
     b.inv1 = 1.0 / (2.0 * b.tau1);

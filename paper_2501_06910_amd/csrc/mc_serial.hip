@@ -88,7 +88,7 @@ extern "C" mc_status mc_serial_compress(mc_serial s, const void* d_field, mc_dty
     bp.eb = eb;
     bp.split = 0.5;                       // tau1 / tau2 unused: the codes take the whole tau
     bp.relative = eb_mode == MC_EB_REL;
-    bp.pad = 0;
+    bp.mode = MC_SPLIT_SUM;
     RangeOut* cur = (RangeOut*)s->ctl;
     DevBound* bound = (DevBound*)(s->ctl + 16);
     unsigned int* err = s->small + 2;

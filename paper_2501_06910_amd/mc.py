@@ -42,7 +42,18 @@ class McPlanInfo(C.Structure):
 
 class McParams(C.Structure):
     _fields_ = [("eb", C.c_double), ("eb_mode", C.c_int32), ("grid_share", C.c_double),
-                ("model", C.c_void_p)]
+                ("model", C.c_void_p), ("split_mode", C.c_int32)]
+
+
+SPLIT_SUM, SPLIT_FULL = 0, 1
+
+
+def _split_code(split_mode) -> int:
+    if split_mode in ("sum", SPLIT_SUM):
+        return SPLIT_SUM
+    if split_mode in ("full", SPLIT_FULL):
+        return SPLIT_FULL
+    raise ValueError("split_mode must be 'sum' or 'full'")
 
 
 class McResult(C.Structure):
@@ -268,7 +279,7 @@ class Plan:
         _check(lib().mc_plan_set_tuning(self.handle, C.byref(t)), "mc_plan_set_tuning")
 
     def tune(self, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None, reps: int = 5,
-             cache: bool = False) -> int:
+             cache: bool = False, split_mode="sum") -> int:
         """Chooses the launch-order knobs by timing this field; returns the
         mask.  With cache=True, a mask stored for this device, grid and mesh
         size (tuning_cache.json beside this module) is applied without
@@ -284,7 +295,7 @@ class Plan:
         codes = Codes(self, field.dtype, learned=model is not None)
         out = torch.empty_like(field)
         prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
-                       None if model is None else model.handle)
+                       None if model is None else model.handle, _split_code(split_mode))
         t = McTuning()
         _check(lib().mc_plan_tune(self.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
                                   _ptr(out), reps, _stream(), C.byref(t)), "mc_plan_tune")
@@ -390,12 +401,12 @@ class Codes:
 
 
 def compress(plan: Plan, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None,
-             codes: Codes | None = None, debug: bool = False) -> Codes:
+             codes: Codes | None = None, debug: bool = False, split_mode="sum") -> Codes:
     _require_cuda(field, "field")
     if codes is None:
         codes = Codes(plan, field.dtype, learned=model is not None, debug=debug)
     prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
-                   None if model is None else model.handle)
+                   None if model is None else model.handle, _split_code(split_mode))
     _check(lib().mc_compress(plan.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
                              _stream()), "mc_compress")
     return codes
@@ -451,8 +462,8 @@ class Model:
 
     @classmethod
     def train(cls, plan: Plan, field, eb=1e-4, eb_mode="rel", grid_share=0.5, steps=2000, batch=8192,
-              lr=1e-3, seed=0, return_loss=False):
-        prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share, None)
+              lr=1e-3, seed=0, return_loss=False, split_mode="sum"):
+        prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share, None, _split_code(split_mode))
         loss = np.zeros(steps, np.float32)
         opts = McTrainOpts(steps, batch, lr, seed, loss.ctypes.data)
         h = C.c_void_p()
@@ -522,16 +533,18 @@ class Model:
 # ---------------------------------------------------------------------------
 
 def batch_compress(items):
-    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes).
-    The first call with a given list captures a HIP graph; later calls with
-    the same plans, tensors and parameters replay it."""
+    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes[,
+    split_mode]).  The first call with a given list captures a HIP graph;
+    later calls with the same plans, tensors and parameters replay it."""
     arr = (McBatchItem * len(items))()
-    for i, (plan, field, eb, mode, share, model, codes) in enumerate(items):
+    for i, it in enumerate(items):
+        plan, field, eb, mode, share, model, codes = it[:7]
+        split = it[7] if len(it) > 7 else "sum"
         arr[i].plan = plan.handle
         arr[i].d_field = field.data_ptr()
         arr[i].dtype = _dtype_code(field)
         arr[i].params = McParams(eb, EB_REL if mode == "rel" else EB_ABS, share,
-                                 None if model is None else model.handle)
+                                 None if model is None else model.handle, _split_code(split))
         arr[i].codes = codes.struct
     _check(lib().mc_batch_compress(arr, len(items), _stream()), "mc_batch_compress")
 

@@ -24,11 +24,11 @@ def dev(a):
 
 
 class Case:
-    def __init__(self, name, mesh, x, dims, eb, rel, split, fill="nearest"):
+    def __init__(self, name, mesh, x, dims, eb, rel, split, fill="nearest", mode="sum"):
         self.name, self.mesh, self.x, self.dims = name, mesh, x, dims
-        self.eb, self.rel, self.split, self.fill = eb, rel, split, fill
+        self.eb, self.rel, self.split, self.fill, self.mode = eb, rel, split, fill, mode
         print(f"[case] {name}: nv={mesh.n_vertices} nc={mesh.n_cells} dims={dims} eb={eb} "
-              f"rel={rel} split={split} dtype={x.dtype} fill={fill}", flush=True)
+              f"rel={rel} split={split} ({mode}) dtype={x.dtype} fill={fill}", flush=True)
         self.og = O.grid_from_dims(mesh.coords, dims)
         self.om = O.locate(mesh.coords, mesh.cells, self.og, "raster", fill=fill)
         self.dc = dev(mesh.coords)
@@ -37,10 +37,12 @@ class Case:
         self.plan = M.Plan(self.dc, self.dcells, dims=dims, fill=fill)
 
     def oracle_compress(self):
-        return O.compress(self.mesh.coords, self.om, self.og, self.x, self.eb, self.rel, self.split)
+        return O.compress(self.mesh.coords, self.om, self.og, self.x, self.eb, self.rel, self.split,
+                          mode=O.SPLIT_FULL if self.mode == "full" else O.SPLIT_SUM)
 
     def gpu_compress(self, **kw):
-        codes = M.compress(self.plan, self.dx, self.eb, "rel" if self.rel else "abs", self.split, debug=True, **kw)
+        codes = M.compress(self.plan, self.dx, self.eb, "rel" if self.rel else "abs", self.split, debug=True,
+                           split_mode=self.mode, **kw)
         torch.cuda.synchronize()
         return codes
 
@@ -65,6 +67,11 @@ def _cases():
                 True, 0.5, "nearest"))
     mesh5, f5, _ = G.config_large_2d(h0=0.004, dims=200)
     out.append(("refined2d_f64", mesh5, f5, (200, 200), 1e-6, True, 0.5, "nearest"))
+    # the full split: tau2 = tau, grid step from tau1 = split * tau (up to 16 tau)
+    out.append(("small2d_full", mesh, f, (64, 64), cfg["eb"], False, 2.0, "nearest", "full"))
+    out.append(("kuhn3d_f32_full", m3, G.field_octaves(m3.coords, np.random.default_rng(1)), (12, 12, 11), 1e-4,
+                True, 16.0, "midrange", "full"))
+    out.append(("kuhn3d_f64_full_tiny", m4, x4, (20, 19, 18), 1e-7, True, 0.25, "nearest", "full"))
     return out
 
 

@@ -32,6 +32,20 @@ def test_bound_closed_form():
         O.bound(np.array([3.0, 3.0]), 0.1, True, 0.5)
 
 
+def test_bound_closed_form_full_split():
+    """SPLIT_FULL: tau1 = split * tau only sets the grid step; the residual
+    keeps the whole tau (its check alone bounds the vertex error)."""
+    x = np.array([2.0, 6.0, 3.0])
+    b = O.bound(x, 0.25, True, 2.0, O.SPLIT_FULL)
+    assert (b.tau, b.tau1, b.tau2, b.c) == (1.0, 2.0, 1.0, 4.0)
+    assert (b.step1, b.inv1, b.step2, b.inv2) == (4.0, 0.25, 2.0, 0.5)
+    b = O.bound(x, 0.25, True, 0.5, O.SPLIT_FULL)
+    assert (b.tau1, b.tau2) == (0.5, 1.0)
+    for split, mode in [(0.0, O.SPLIT_FULL), (16.5, O.SPLIT_FULL), (0.5, 2), (1.0, O.SPLIT_SUM)]:
+        with pytest.raises(O.OracleError):
+            O.bound(x, 0.25, True, split, mode)
+
+
 @pytest.mark.parametrize("dims", [(7, 5, 1), (4, 6, 5)])
 def test_lorenzo_roundtrip_and_annihilation(dims):
     dim = 2 if dims[2] == 1 else 3
@@ -154,10 +168,10 @@ def test_residual_textbook_quantizer():
     assert ok.sum() == x.size
 
 
-def _roundtrip(coords, cells, dims, x, eb, rel, split, fill="nearest"):
+def _roundtrip(coords, cells, dims, x, eb, rel, split, fill="nearest", mode=O.SPLIT_SUM):
     g = O.grid_from_dims(coords, dims)
     m = O.locate(coords, cells, g, "raster", fill=fill)
-    cz = O.compress(coords, m, g, x, eb, rel, split)
+    cz = O.compress(coords, m, g, x, eb, rel, split, mode=mode)
     xr = O.decompress(coords, g, cz.bound, cz.grid, cz.vert, x.dtype)
     return cz, xr
 
@@ -178,6 +192,25 @@ def test_bound_on_every_vertex_2d(eb, split):
         assert cz.grid.out_idx.size > 0
         if split == 0.9:
             assert cz.vert.out_idx.size > 0
+
+
+@pytest.mark.parametrize("eb,split", [(1e-2, 0.5), (1e-4, 1.0), (1e-4, 4.0), (1e-6, 0.25)])
+def test_bound_on_every_vertex_full_split(eb, split):
+    """Every vertex within tau2 = tau; the grid part equals the one of the
+    sum split with the same tau1 (it depends on tau1 only), and the residual
+    codes equal the plain quantiser of x - g(x1') with step 2 tau."""
+    rng = np.random.default_rng(9)
+    mesh = G.delaunay_2d(G.stratified_points_2d(40, rng))
+    x = G.field_bumps_2d(mesh.coords, rng)
+    cz, xr = _roundtrip(mesh.coords, mesh.cells, (33, 30), x, eb, True, split, mode=O.SPLIT_FULL)
+    assert cz.bound.tau2 == cz.bound.tau and cz.bound.tau1 == split * cz.bound.tau
+    assert np.all(np.abs(x - xr) <= cz.bound.tau)
+    q = np.rint((x - cz.gv.astype(np.float64)) * cz.bound.inv2)
+    ok = cz.vert.codes != 0
+    assert np.array_equal(cz.vert.codes[ok].astype(np.int64) - R, q[ok].astype(np.int64))
+    if split < 1.0:
+        cs, _ = _roundtrip(mesh.coords, mesh.cells, (33, 30), x, eb, True, split)
+        assert np.array_equal(cs.grid.codes, cz.grid.codes) and np.array_equal(cs.grid.p, cz.grid.p)
 
 
 def test_tiny_eb_is_a_range_error():
