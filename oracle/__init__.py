@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c"]
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c"]
 
 OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
 F32, F64 = 0, 1
@@ -96,6 +96,11 @@ def lib():
             "mco_grid_decode": (i32, [P, P, P, i64, P, P]),
             "mco_lorenzo": (None, [P, P, P]),
             "mco_residual_quantize": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
+            "mco_grid_quantize_f64": (i32, [P, P, P, P, P, P, P, i64, P]),
+            "mco_nearest_nodes": (None, [P, i32, i64, P, P]),
+            "mco_cluster_mean": (None, [P, i32, i64, P, i64, dbl, P, P]),
+            "mco_residual_nearest": (i32, [P, i32, i64, P, P, P, P, i32, P, P, P, i64, P]),
+            "mco_vertex_decode_nearest": (None, [P, P, P, i64, P, P, P, i32, i64, P]),
             "mco_learned_codes": (i32, [P, i32, i64, P, P, P, P, P, P, P, i64, P]),
             "mco_vertex_decode": (None, [P, P, P, i64, P, P, i32, i64, P, P, P]),
             "mco_splitmix64": (C.c_uint64, [C.c_uint64, C.c_uint64]),
@@ -424,6 +429,90 @@ def serial_decompress(codes, out_idx, out_val, b: Bound, dtype) -> np.ndarray:
     lib().mco_serial_decompress(_p(codes), _p(out_idx), _p(out_val), out_idx.size, codes.size, C.byref(b),
                                 _dtype_code(out), _p(out))
     return out
+
+
+# ---------------------------------------------------------------------------
+# the paper's own operator pair: nearest-node g, cluster-mean f
+# ---------------------------------------------------------------------------
+
+def nearest_nodes(coords: np.ndarray, g: Grid) -> np.ndarray:
+    """Nearest grid node of every vertex (Sec. IV-C)."""
+    nv = coords.shape[1]
+    m = np.empty(nv, np.int32)
+    lib().mco_nearest_nodes(_p(np.ascontiguousarray(coords, np.float32)), coords.shape[0], nv, _p(g), _p(m))
+    return m
+
+
+def cluster_mean(x: np.ndarray, m: np.ndarray, ng: int, c: float):
+    """Cluster-mean f (Sec. IV-D): (x1 float64[ng], count int32[ng])."""
+    x1 = np.empty(ng, np.float64)
+    cnt = np.empty(ng, np.int32)
+    lib().mco_cluster_mean(_p(x), _dtype_code(x), x.size, _p(np.ascontiguousarray(m, np.int32)), ng, c, _p(x1),
+                           _p(cnt))
+    return x1, cnt
+
+
+def grid_quantize_f64(v: np.ndarray, g: Grid, b: Bound) -> GridCodes:
+    ng = g.count
+    p = np.empty(ng, np.int32)
+    codes = np.empty(ng, np.uint16)
+    oi = np.empty(ng, np.int32)
+    od = np.empty(ng, np.int32)
+    n = C.c_int64(0)
+    st = lib().mco_grid_quantize_f64(_p(np.ascontiguousarray(v, np.float64)), _p(g), _p(b), _p(p), _p(codes),
+                                     _p(oi), _p(od), ng, C.byref(n))
+    if st != OK:
+        raise OracleError(st, "grid_quantize_f64")
+    return GridCodes(p, codes, oi[:n.value].copy(), od[:n.value].copy())
+
+
+def residual_nearest(x: np.ndarray, m: np.ndarray, x1: np.ndarray, p: np.ndarray, b: Bound,
+                     open_loop: bool) -> VertexCodes:
+    nv = x.size
+    codes = np.empty(nv, np.uint16)
+    oi = np.empty(nv, np.int32)
+    ov = np.empty(nv, x.dtype)
+    n = C.c_int64(0)
+    st = lib().mco_residual_nearest(_p(x), _dtype_code(x), nv, _p(m), _p(x1), _p(p), _p(b), int(open_loop),
+                                    _p(codes), _p(oi), _p(ov), nv, C.byref(n))
+    if st != OK:
+        raise OracleError(st, "residual_nearest")
+    return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy())
+
+
+def vertex_decode_nearest(vc: VertexCodes, m: np.ndarray, p: np.ndarray, b: Bound, dtype) -> np.ndarray:
+    nv = vc.codes.size
+    out = np.empty(nv, dtype)
+    lib().mco_vertex_decode_nearest(_p(vc.codes), _p(vc.out_idx), _p(vc.out_val), vc.out_idx.size, _p(m), _p(p),
+                                    _p(b), _dtype_code(out), nv, _p(out))
+    return out
+
+
+@dataclass
+class ClusterCompressed:
+    bound: Bound
+    m: np.ndarray
+    x1: np.ndarray
+    count: np.ndarray
+    grid: GridCodes
+    vert: VertexCodes
+
+
+def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, split: float,
+                     open_loop: bool = True, mode: int = SPLIT_SUM) -> ClusterCompressed:
+    """Alg. 3 with the nearest-node g and the cluster-mean f."""
+    b = bound(x, eb, relative, split, mode)
+    m = nearest_nodes(coords, g)
+    x1, cnt = cluster_mean(x, m, g.count, b.c)
+    gc = grid_quantize_f64(x1, g, b)
+    vc = residual_nearest(x, m, x1, gc.p, b, open_loop)
+    return ClusterCompressed(b, m, x1, cnt, gc, vc)
+
+
+def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype) -> np.ndarray:
+    """Alg. 4 with the nearest-node g."""
+    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g)
+    return vertex_decode_nearest(vc, nearest_nodes(coords, g), p, b, dtype)
 
 
 def splitmix64(seed: int, counter: int) -> int:

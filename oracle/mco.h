@@ -88,6 +88,9 @@ void mco_back_interp(const float* coords, int dim, int64_t nv, const mco_grid* g
 int mco_grid_quantize(const float* v, const mco_grid* g, const mco_bound* b, int32_t* p,
                       uint16_t* codes, int32_t* out_idx, int32_t* out_delta, int64_t cap,
                       int64_t* n_out);
+int mco_grid_quantize_f64(const double* v, const mco_grid* g, const mco_bound* b, int32_t* p,
+                          uint16_t* codes, int32_t* out_idx, int32_t* out_delta, int64_t cap,
+                          int64_t* n_out);
 void mco_grid_recon(const int32_t* p, int64_t ng, const mco_bound* b, float* xhat);
 int mco_grid_decode(const uint16_t* codes, const int32_t* out_idx, const int32_t* out_delta,
                     int64_t n_out, const mco_grid* g, int32_t* p);
@@ -129,6 +132,18 @@ void mco_adam_step(int64_t n, float* params, float* m, float* v, const float* gr
 int32_t mco_rho_quantize(float rho);
 void mco_sample_indices(uint64_t seed, int64_t step, int64_t batch, int64_t n,
                         int64_t* idx);
+
+/* The paper's own operator pair (mco_cluster.c): nearest-node g,
+ * cluster-mean f, open- or closed-loop residual. */
+void mco_nearest_nodes(const float* coords, int dim, int64_t nv, const mco_grid* g, int32_t* m);
+void mco_cluster_mean(const void* x, int dtype, int64_t nv, const int32_t* m, int64_t ng, double c,
+                      double* x1, int32_t* count);
+int mco_residual_nearest(const void* x, int dtype, int64_t nv, const int32_t* m, const double* x1,
+                         const int32_t* p, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
+                         void* out_val, int64_t cap, int64_t* n_out);
+void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
+                               const int32_t* m, const int32_t* p, const mco_bound* b, int dtype, int64_t nv,
+                               void* xout);
 
 /* 1-D serialisation baseline (mco_serial.c). */
 int mco_serial_compress(const void* x, int dtype, int64_t n, double eb, int relative, uint16_t* codes,

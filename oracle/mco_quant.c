@@ -94,22 +94,12 @@ void mco_lorenzo(const int32_t* p, const mco_grid* g, int64_t* delta)
             }
 }
 
-/* Grid compressor C(x1) with bound tau1.  Prequantise
- * p = (int32) rint(((double)v - c) * inv1), requiring
- * |((double)v - c) * inv1| < 2^27; Lorenzo-predict on the integers; a
- * prediction error |d| <= R-1 becomes code d + R, anything larger code 0
- * plus an outlier (j, d) in ascending j.  Returns MCO_ERR_RANGE or
- * MCO_ERR_CAPACITY (n_out still counts every outlier). */
-int mco_grid_quantize(const float* v, const mco_grid* g, const mco_bound* b, int32_t* p,
-                      uint16_t* codes, int32_t* out_idx, int32_t* out_delta, int64_t cap,
-                      int64_t* n_out)
+/* Lorenzo codes of the prequantised grid p: code d + R, or 0 with (index,
+ * d) listed when |d| > R - 1. */
+static int grid_codes_from_p(const int32_t* p, const mco_grid* g, uint16_t* codes, int32_t* out_idx,
+                             int32_t* out_delta, int64_t cap, int64_t* n_out)
 {
     int64_t ng = g->n[0] * g->n[1] * g->n[2];
-    for (int64_t j = 0; j < ng; ++j) {
-        double s = ((double)v[j] - b->c) * b->inv1;
-        if (!(fabs(s) < 134217728.0)) return MCO_ERR_RANGE;
-        p[j] = (int32_t)rint(s);
-    }
     int64_t* delta = (int64_t*)malloc((size_t)ng * sizeof(int64_t));
     if (!delta) return MCO_ERR_ARG;
     mco_lorenzo(p, g, delta);
@@ -127,6 +117,39 @@ int mco_grid_quantize(const float* v, const mco_grid* g, const mco_bound* b, int
     free(delta);
     *n_out = k;
     return k > cap ? MCO_ERR_CAPACITY : MCO_OK;
+}
+
+/* Grid compressor C(x1) with bound tau1.  Prequantise
+ * p = (int32) rint(((double)v - c) * inv1), requiring
+ * |((double)v - c) * inv1| < 2^27; Lorenzo-predict on the integers; a
+ * prediction error |d| <= R-1 becomes code d + R, anything larger code 0
+ * plus an outlier (j, d) in ascending j.  Returns MCO_ERR_RANGE or
+ * MCO_ERR_CAPACITY (n_out still counts every outlier). */
+int mco_grid_quantize(const float* v, const mco_grid* g, const mco_bound* b, int32_t* p,
+                      uint16_t* codes, int32_t* out_idx, int32_t* out_delta, int64_t cap,
+                      int64_t* n_out)
+{
+    int64_t ng = g->n[0] * g->n[1] * g->n[2];
+    for (int64_t j = 0; j < ng; ++j) {
+        double s = ((double)v[j] - b->c) * b->inv1;
+        if (!(fabs(s) < 134217728.0)) return MCO_ERR_RANGE;
+        p[j] = (int32_t)rint(s);
+    }
+    return grid_codes_from_p(p, g, codes, out_idx, out_delta, cap, n_out);
+}
+
+/* The same for FP64 grid values (the cluster-mean f). */
+int mco_grid_quantize_f64(const double* v, const mco_grid* g, const mco_bound* b, int32_t* p,
+                          uint16_t* codes, int32_t* out_idx, int32_t* out_delta, int64_t cap,
+                          int64_t* n_out)
+{
+    int64_t ng = g->n[0] * g->n[1] * g->n[2];
+    for (int64_t j = 0; j < ng; ++j) {
+        double s = (v[j] - b->c) * b->inv1;
+        if (!(fabs(s) < 134217728.0)) return MCO_ERR_RANGE;
+        p[j] = (int32_t)rint(s);
+    }
+    return grid_codes_from_p(p, g, codes, out_idx, out_delta, cap, n_out);
 }
 
 /* Reconstructed grid x1' = (float)(c + (double)p * step1); known at
