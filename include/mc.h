@@ -78,16 +78,28 @@ typedef struct {
 typedef struct mc_plan_s* mc_plan;
 typedef struct mc_model_s* mc_model;
 
+/* Operator pair of a plan.
+ * MC_OPS_LINEAR (default): f = barycentric interpolation in the lowest-id
+ *   cell holding the node, g = multilinear interpolation on the vertex's
+ *   grid cell; the residual is taken against the reconstructed grid.
+ * MC_OPS_CLUSTER: the paper's own pair (Sec. IV-C, IV-D): g = the nearest
+ *   grid node m_k (per axis rint((p - origin) / spacing), clamped), f = the
+ *   mean of the vertices whose nearest node it is (FP64, summed in
+ *   ascending vertex id; c for a node no vertex maps to).  Needs no
+ *   connectivity (d_cells may be NULL and n_cells 0).  No learned model. */
+typedef enum { MC_OPS_LINEAR = 0, MC_OPS_CLUSTER = 1 } mc_operators;
+
 typedef struct {
     mc_fill fill;            /* nodes outside every cell: nearest vertex (default) or mid-range */
     int32_t bin_nodes;       /* point-location bin edge in grid nodes (0 = tuned default) */
+    int32_t operators;       /* mc_operators (0 = MC_OPS_LINEAR) */
 } mc_plan_opts;
 
 typedef struct {
     int64_t n_grid;          /* grid nodes */
     int64_t n_vertices;
     int64_t n_cells;
-    int64_t n_unresolved;    /* grid nodes in no cell (filled per mc_plan_opts.fill) */
+    int64_t n_unresolved;    /* grid nodes in no cell (filled per mc_plan_opts.fill); MC_OPS_CLUSTER: nodes no vertex maps to */
     int64_t n_near_degenerate;  /* cells whose weights were recomputed in FP64 */
     int64_t n_pairs;         /* (bin, cell) pairs of the point-location index */
     int64_t bin_nodes;
@@ -104,6 +116,13 @@ typedef struct {
  * quantisation step (grid noise is absorbed by the residual). */
 typedef enum { MC_SPLIT_SUM = 0, MC_SPLIT_FULL = 1 } mc_split;
 
+/* Residual reference.  MC_RESIDUAL_CLOSED: x - g(x1'), the reconstructed
+ * grid; every vertex within tau2.  MC_RESIDUAL_OPEN: x - g(x1), the grid
+ * before its compression, as Alg. 3 writes it; every vertex within
+ * tau1 + tau2 = tau (Sec. III; each vertex is checked, values that miss are
+ * stored raw).  OPEN needs an MC_OPS_CLUSTER plan and MC_SPLIT_SUM. */
+typedef enum { MC_RESIDUAL_CLOSED = 0, MC_RESIDUAL_OPEN = 1 } mc_residual;
+
 /* Compression parameters (zero-initialise, then fill). */
 typedef struct {
     double eb;               /* error bound, > 0 */
@@ -111,6 +130,7 @@ typedef struct {
     double grid_share;       /* tau1 / tau: in (0, 1) for MC_SPLIT_SUM, (0, 16] for MC_SPLIT_FULL */
     mc_model model;          /* NULL: plain residual codes; else learned shift per block */
     int32_t split_mode;      /* mc_split (0 = MC_SPLIT_SUM) */
+    int32_t residual;        /* mc_residual (0 = MC_RESIDUAL_CLOSED) */
 } mc_params;
 
 /* Device-side result header, written by mc_compress and read by
@@ -180,10 +200,13 @@ mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t 
 mc_status mc_plan_get_info(mc_plan plan, mc_plan_info* out);
 /* Copies the mapping: d_vid int32[dim+1][n_grid] (-1 for mid-range-filled
  * nodes), d_w float[dim+1][n_grid], d_cell int32[n_grid] (-1 = unresolved);
- * any may be NULL. */
+ * any may be NULL (MC_OPS_LINEAR plans; MC_ERR_UNSUPPORTED otherwise). */
 mc_status mc_plan_mapping(mc_plan plan, int32_t* d_vid, float* d_w, int32_t* d_cell,
                           hipStream_t stream);
 mc_status mc_plan_get_grid(mc_plan plan, mc_grid* out);
+/* Copies the nearest node of every vertex, d_m int32[n_vertices]
+ * (MC_OPS_CLUSTER plans; MC_ERR_UNSUPPORTED otherwise). */
+mc_status mc_plan_nodes(mc_plan plan, int32_t* d_m, hipStream_t stream);
 mc_status mc_plan_destroy(mc_plan plan);
 
 /* Compress one field (Alg. 3, residuals against the reconstructed grid). */

@@ -466,24 +466,24 @@ def grid_quantize_f64(v: np.ndarray, g: Grid, b: Bound) -> GridCodes:
     return GridCodes(p, codes, oi[:n.value].copy(), od[:n.value].copy())
 
 
-def residual_nearest(x: np.ndarray, m: np.ndarray, x1: np.ndarray, p: np.ndarray, b: Bound,
+def residual_nearest(x: np.ndarray, m: np.ndarray, x1: np.ndarray, xhat: np.ndarray, b: Bound,
                      open_loop: bool) -> VertexCodes:
     nv = x.size
     codes = np.empty(nv, np.uint16)
     oi = np.empty(nv, np.int32)
     ov = np.empty(nv, x.dtype)
     n = C.c_int64(0)
-    st = lib().mco_residual_nearest(_p(x), _dtype_code(x), nv, _p(m), _p(x1), _p(p), _p(b), int(open_loop),
+    st = lib().mco_residual_nearest(_p(x), _dtype_code(x), nv, _p(m), _p(x1), _p(xhat), _p(b), int(open_loop),
                                     _p(codes), _p(oi), _p(ov), nv, C.byref(n))
     if st != OK:
         raise OracleError(st, "residual_nearest")
     return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy())
 
 
-def vertex_decode_nearest(vc: VertexCodes, m: np.ndarray, p: np.ndarray, b: Bound, dtype) -> np.ndarray:
+def vertex_decode_nearest(vc: VertexCodes, m: np.ndarray, xhat: np.ndarray, b: Bound, dtype) -> np.ndarray:
     nv = vc.codes.size
     out = np.empty(nv, dtype)
-    lib().mco_vertex_decode_nearest(_p(vc.codes), _p(vc.out_idx), _p(vc.out_val), vc.out_idx.size, _p(m), _p(p),
+    lib().mco_vertex_decode_nearest(_p(vc.codes), _p(vc.out_idx), _p(vc.out_val), vc.out_idx.size, _p(m), _p(xhat),
                                     _p(b), _dtype_code(out), nv, _p(out))
     return out
 
@@ -505,14 +505,14 @@ def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, 
     m = nearest_nodes(coords, g)
     x1, cnt = cluster_mean(x, m, g.count, b.c)
     gc = grid_quantize_f64(x1, g, b)
-    vc = residual_nearest(x, m, x1, gc.p, b, open_loop)
+    vc = residual_nearest(x, m, x1, grid_recon(gc.p, b), b, open_loop)
     return ClusterCompressed(b, m, x1, cnt, gc, vc)
 
 
 def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype) -> np.ndarray:
     """Alg. 4 with the nearest-node g."""
     p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g)
-    return vertex_decode_nearest(vc, nearest_nodes(coords, g), p, b, dtype)
+    return vertex_decode_nearest(vc, nearest_nodes(coords, g), grid_recon(p, b), b, dtype)
 
 
 def splitmix64(seed: int, counter: int) -> int:

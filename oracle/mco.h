@@ -139,10 +139,10 @@ void mco_nearest_nodes(const float* coords, int dim, int64_t nv, const mco_grid*
 void mco_cluster_mean(const void* x, int dtype, int64_t nv, const int32_t* m, int64_t ng, double c,
                       double* x1, int32_t* count);
 int mco_residual_nearest(const void* x, int dtype, int64_t nv, const int32_t* m, const double* x1,
-                         const int32_t* p, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
+                         const float* xhat, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
                          void* out_val, int64_t cap, int64_t* n_out);
 void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
-                               const int32_t* m, const int32_t* p, const mco_bound* b, int dtype, int64_t nv,
+                               const int32_t* m, const float* xhat, const mco_bound* b, int dtype, int64_t nv,
                                void* xout);
 
 /* 1-D serialisation baseline (mco_serial.c). */

@@ -12,7 +12,7 @@
  *   x1[j] = (sum of x_k over m_k = j, in FP64, ascending k) / count_j;
  *           a node no vertex maps to holds c (prequantised value 0)
  *   p[j]  = rint((x1[j] - c) / (2 tau1)), Lorenzo-coded as for the linear pair
- *   x1'[j] = c + p[j] 2 tau1                              (FP64)
+ *   x1'[j] = (float)(c + p[j] 2 tau1), the grid decoder's FP32 output
  *   open:   q_k = rint((x_k - x1[m_k]) / (2 tau2)), bound tau1 + tau2 = tau
  *   closed: q_k = rint((x_k - x1'[m_k]) / (2 tau2)), bound tau2
  *   x'_k = (T)(x1'[m_k] + q_k 2 tau2); code q + R when |q| <= R - 1 and
@@ -61,14 +61,14 @@ void mco_cluster_mean(const void* x, int dtype, int64_t nv, const int32_t* m, in
 }
 
 int mco_residual_nearest(const void* x, int dtype, int64_t nv, const int32_t* m, const double* x1,
-                         const int32_t* p, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
+                         const float* xhat, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
                          void* out_val, int64_t cap, int64_t* n_out)
 {
     const double bound = open ? b->tau : b->tau2;
     int64_t k = 0;
     for (int64_t i = 0; i < nv; ++i) {
         const double xi = val_at(x, dtype, i);
-        const double xh = b->c + (double)p[m[i]] * b->step1;
+        const double xh = (double)xhat[m[i]];
         const double ref = open ? x1[m[i]] : xh;
         const double q = rint((xi - ref) * b->inv2);
         const double sum = xh + q * b->step2;
@@ -90,7 +90,7 @@ int mco_residual_nearest(const void* x, int dtype, int64_t nv, const int32_t* m,
 }
 
 void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
-                               const int32_t* m, const int32_t* p, const mco_bound* b, int dtype, int64_t nv,
+                               const int32_t* m, const float* xhat, const mco_bound* b, int dtype, int64_t nv,
                                void* xout)
 {
     int64_t k = 0;
@@ -100,8 +100,7 @@ void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, co
             while (k < n_out && out_idx[k] < i) ++k;
             v = (k < n_out && out_idx[k] == i) ? val_at(out_val, dtype, k) : 0.0;
         } else {
-            const double xh = b->c + (double)p[m[i]] * b->step1;
-            v = xh + (double)((int)codes[i] - MCO_RADIUS) * b->step2;
+            v = (double)xhat[m[i]] + (double)((int)codes[i] - MCO_RADIUS) * b->step2;
         }
         if (dtype == MCO_F64) ((double*)xout)[i] = v;
         else ((float*)xout)[i] = (float)v;

@@ -1,0 +1,284 @@
+// k_cluster.hip -- the paper's own operator pair on gfx950: the nearest
+// grid node as back-interpolation g (Sec. IV-C) and the mean of the
+// vertices assigned to a node as resampling f (Sec. IV-D), with the
+// residual of Alg. 3 taken against the uncompressed grid (open loop) or the
+// reconstructed one (closed loop).
+//   plan:        k_nearest_node (node of every vertex, counts per node)
+//                -> scan of the counts -> stable radix sort of (node,
+//                vertex) pairs: each node's vertices in ascending id order
+//   compress:    k_cluster_mean (one thread per node sums its vertices in
+//                FP64 in ascending id order, prequantises) -> Lorenzo ->
+//                k_residual_nearest -> scatter
+//   decompress:  grid decode -> k_vdecode_nearest
+#include <cstring>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+
+#include "mc_dev.h"
+#include "mc_kernels.h"
+
+// m_k = per axis rint((p_d - o_d) / h_d) clamped to [0, n_d - 1] (FP64, IEEE
+// division, as the definition reads).
+__global__ __launch_bounds__(256) void k_nearest_node(const float* __restrict__ coords, int dim, long long nv,
+                                                      mck::NodeGeom ng_, int32_t* __restrict__ m,
+                                                      unsigned int* __restrict__ count)
+{
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nv) return;
+    long long idx[3] = {0, 0, 0};
+    for (int d = 0; d < dim; ++d) {
+        double t = rint(((double)coords[d * nv + k] - ng_.o[d]) / ng_.h[d]);
+        if (!(t >= 0.0)) t = 0.0;
+        if (t > (double)(ng_.n[d] - 1)) t = (double)(ng_.n[d] - 1);
+        idx[d] = (long long)t;
+    }
+    const long long j = idx[0] + ng_.n[0] * (idx[1] + ng_.n[1] * idx[2]);
+    m[k] = (int32_t)j;
+    atomicAdd(&count[j], 1u);
+}
+
+// Nodes no vertex maps to.
+__global__ __launch_bounds__(256) void k_count_empty(const unsigned int* __restrict__ count, long long ng,
+                                                     unsigned int* __restrict__ out)
+{
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    int e = j < ng && count[j] == 0 ? 1 : 0;
+    e = wave_sum(e);
+    if (lane_id() == 0 && e) atomicAdd(out, (unsigned)e);
+}
+
+// One thread per node: x1 = FP64 sum of its vertices' values in ascending
+// vertex order / count (c for a node without vertices), prequantised with
+// tau1; x1' = (float)(c + p 2 tau1).  Also clears the grid tile counts and
+// writes the result header.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cluster_mean(const long long* __restrict__ noff,
+                                                      const int32_t* __restrict__ vlist, long long ng,
+                                                      const T* __restrict__ x, const DevBound* __restrict__ bnd,
+                                                      int32_t* __restrict__ p, float* __restrict__ xh,
+                                                      double* __restrict__ x1,
+                                                      float* __restrict__ dbg_v, unsigned int* __restrict__ err,
+                                                      mc_result* __restrict__ res, int dtype,
+                                                      unsigned int* __restrict__ gcount, long long ntg)
+{
+    const DevBound b = *bnd;
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (j < ntg) gcount[j] = 0u;
+    if (j == 0) {
+        res->status = b.ok ? 0 : 1;
+        res->dtype = dtype;
+        res->tau = b.tau;
+        res->tau1 = b.tau1;
+        res->tau2 = b.tau2;
+        res->c = b.c;
+        res->xmin = b.xmin;
+        res->xmax = b.xmax;
+        if (!b.ok) atomicOr(err, (b.flags & MC_EBIT_NONFINITE) ? MC_EBIT_NONFINITE : MC_EBIT_TAU);
+    }
+    if (!b.ok || j >= ng) return;
+    const long long a = noff[j], e = noff[j + 1];
+    double sum = 0.0;
+    long long k = a;
+    for (; k + 4 <= e; k += 4) {               // four gathers in flight, added in order
+        const int32_t v0 = vlist[k], v1 = vlist[k + 1], v2 = vlist[k + 2], v3 = vlist[k + 3];
+        const double x0 = (double)x[v0], xa = (double)x[v1], xb = (double)x[v2], xc = (double)x[v3];
+        sum = sum + x0;
+        sum = sum + xa;
+        sum = sum + xb;
+        sum = sum + xc;
+    }
+    for (; k < e; ++k) sum = sum + (double)x[vlist[k]];
+    const double mean = e > a ? sum / (double)(e - a) : b.c;
+    const double s = (mean - b.c) * b.inv1;
+    int32_t q = 0;
+    if (!(fabs(s) < 134217728.0)) atomicOr(err, MC_EBIT_RANGE);
+    else q = (int32_t)rint(s);
+    p[j] = q;
+    xh[j] = xhat_of(q, b.c, b.step1);      // the grid decoder's FP32 output
+    if (x1) x1[j] = mean;
+    if (dbg_v) dbg_v[j] = (float)mean;
+}
+
+// Residual codes against the nearest node: ref = x1[m] (open loop, bound
+// tau) or x1'[m] (closed loop, bound tau2); x' = (T)(x1'[m] + q 2 tau2).
+template <typename T>
+__global__ __launch_bounds__(256) void k_residual_nearest(const int32_t* __restrict__ m, long long nv,
+                                                          const T* __restrict__ x, const double* __restrict__ x1,
+                                                          const float* __restrict__ xhat,
+                                                          const DevBound* __restrict__ bnd,
+                                                          uint16_t* __restrict__ codes, float* __restrict__ dbg_g,
+                                                          unsigned int* __restrict__ count,
+                                                          unsigned int* __restrict__ vsum)
+{
+    __shared__ int s_cnt[4];
+    const DevBound b = *bnd;
+    const long long tile = blockIdx.x;
+    const bool open = x1 != nullptr;
+    const double bound = open ? b.tau : b.tau2;
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    T xv[MC_IPT];
+    int32_t mi[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+        act[i] = v[i] < nv && b.ok;
+        const long long vc = act[i] ? v[i] : 0;
+        xv[i] = x[vc];
+        mi[i] = m[vc];
+    }
+    float xq[MC_IPT];
+    double ref[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        xq[i] = xhat[mi[i]];
+        ref[i] = open ? x1[mi[i]] : 0.0;
+    }
+    int nout = 0;
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        if (!act[i]) continue;
+        const double xi = (double)xv[i];
+        const double xh = (double)xq[i];
+        const double r = open ? ref[i] : xh;
+        const double q = rint((xi - r) * b.inv2);
+        const T xr = (T)(xh + q * b.step2);
+        const bool ok = fabs(q) <= (double)(MC_R - 1) && fabs(xi - (double)xr) <= bound;
+        if (dbg_g) dbg_g[v[i]] = (float)r;
+        codes[v[i]] = ok ? (uint16_t)((int)q + MC_R) : (uint16_t)0;
+        nout += ok ? 0 : 1;
+    }
+    nout = wave_sum(nout);
+    if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = nout;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned c = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+        if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
+        count[tile] = c;
+    }
+}
+
+__device__ __forceinline__ long long cl_find(const int32_t* __restrict__ oidx, long long n, long long j)
+{
+    long long lo = 0, hi = n;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)oidx[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && (long long)oidx[lo] == j) ? lo : -1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_vdecode_nearest(const int32_t* __restrict__ m, long long nv,
+                                                         const float* __restrict__ xhat,
+                                                         const uint16_t* __restrict__ codes,
+                                                         const int32_t* __restrict__ oidx, const T* __restrict__ oval,
+                                                         const mc_result* __restrict__ res, long long vcap,
+                                                         T* __restrict__ xout)
+{
+    const long long tile = blockIdx.x;
+    const double step2 = 2.0 * res->tau2;
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    int code[MC_IPT];
+    int32_t mi[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+        act[i] = v[i] < nv;
+        const long long vc = act[i] ? v[i] : 0;
+        code[i] = codes[vc];
+        mi[i] = m[vc];
+    }
+    float xq[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) xq[i] = xhat[mi[i]];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        if (!act[i]) continue;
+        if (code[i] == 0) {
+            const long long n = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
+            const long long k = cl_find(oidx, n, v[i]);
+            xout[v[i]] = k >= 0 ? oval[k] : (T)0;
+        } else {
+            xout[v[i]] = (T)((double)xq[i] + (double)(code[i] - MC_R) * step2);
+        }
+    }
+}
+
+namespace mck {
+
+hipError_t nearest_nodes(const float* coords, int dim, long long nv, NodeGeom g, int32_t* m, unsigned* count,
+                         hipStream_t s)
+{
+    ProfScope ps("k_nearest_node", s);
+    hipLaunchKernelGGL(k_nearest_node, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, coords, dim, nv, g, m,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t count_empty(const unsigned* count, long long ng, unsigned* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count_empty, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, count, ng, out);
+    return hipGetLastError();
+}
+
+hipError_t sort_by_node(const int32_t* m, long long nv, long long ng, uint32_t* keys_out, int32_t* vlist,
+                        void* temp, size_t* temp_bytes, hipStream_t s)
+{
+    unsigned bits = 1;
+    while (bits < 32 && (1ll << bits) < ng) ++bits;
+    rocprim::counting_iterator<int32_t> iota(0);
+    return rocprim::radix_sort_pairs(temp, *temp_bytes, (const uint32_t*)m, keys_out, iota, vlist, (size_t)nv, 0u,
+                                     bits, s);
+}
+
+hipError_t cluster_mean(const long long* noff, const int32_t* vlist, long long ng, const void* x, int dtype,
+                        const DevBound* bnd, int32_t* p, float* xh, double* x1, float* dbg_v, unsigned* err,
+                        mc_result* res, unsigned* gcount, long long ntg, hipStream_t s)
+{
+    ProfScope ps("k_cluster_mean", s);
+    const long long need = ng > ntg ? ng : ntg;
+    dim3 grid((unsigned)((need + 255) / 256));
+    if (dtype == MC_F64)
+        hipLaunchKernelGGL(k_cluster_mean<double>, grid, dim3(256), 0, s, noff, vlist, ng, (const double*)x, bnd, p, xh,
+                           x1, dbg_v, err, res, dtype, gcount, ntg);
+    else
+        hipLaunchKernelGGL(k_cluster_mean<float>, grid, dim3(256), 0, s, noff, vlist, ng, (const float*)x, bnd, p, xh,
+                           x1, dbg_v, err, res, dtype, gcount, ntg);
+    return hipGetLastError();
+}
+
+hipError_t residual_nearest(const int32_t* m, long long nv, const void* x, int dtype, const double* x1,
+                            const float* xhat, const DevBound* bnd, uint16_t* codes, float* dbg_g, unsigned* count,
+                            unsigned* vsum, hipStream_t s)
+{
+    ProfScope ps("k_residual_nearest", s);
+    dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
+    if (dtype == MC_F64)
+        hipLaunchKernelGGL(k_residual_nearest<double>, grid, dim3(256), 0, s, m, nv, (const double*)x, x1, xhat, bnd,
+                           codes, dbg_g, count, vsum);
+    else
+        hipLaunchKernelGGL(k_residual_nearest<float>, grid, dim3(256), 0, s, m, nv, (const float*)x, x1, xhat, bnd,
+                           codes, dbg_g, count, vsum);
+    return hipGetLastError();
+}
+
+hipError_t vertex_decode_nearest(const int32_t* m, long long nv, const float* xhat, const uint16_t* codes,
+                                 const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
+                                 void* xout, int dtype, hipStream_t s)
+{
+    ProfScope ps("k_vdecode_nearest", s);
+    dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
+    if (dtype == MC_F64)
+        hipLaunchKernelGGL(k_vdecode_nearest<double>, grid, dim3(256), 0, s, m, nv, xhat, codes, oidx,
+                           (const double*)oval, res, vcap, (double*)xout);
+    else
+        hipLaunchKernelGGL(k_vdecode_nearest<float>, grid, dim3(256), 0, s, m, nv, xhat, codes, oidx,
+                           (const float*)oval, res, vcap, (float*)xout);
+    return hipGetLastError();
+}
+
+}  // namespace mck

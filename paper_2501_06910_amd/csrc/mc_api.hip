@@ -353,6 +353,57 @@ static void decode_ws_shape(mc_plan p)
     }
 }
 
+// Nearest node of every vertex and each node's vertex list in ascending id
+// order (the cluster-mean f sums in that order).
+static mc_status build_cluster_map(mc_plan p, hipStream_t s)
+{
+    const long long nv = p->nv, ng = p->ng;
+    hipError_t e = hipSuccess;
+#define CCHK(expr)                                                                                   \
+    do {                                                                                             \
+        if ((e = (expr)) != hipSuccess)                                                              \
+            return mc_fail(e == hipErrorOutOfMemory ? MC_ERR_NOMEM : MC_ERR_DEVICE, "%s: %s", #expr, \
+                           hipGetErrorString(e));                                                    \
+    } while (0)
+    CCHK(plan_alloc(p, &p->m, (size_t)nv));
+    CCHK(plan_alloc(p, &p->vlist, (size_t)nv));
+    CCHK(plan_alloc(p, &p->noff, (size_t)ng + 1));
+    CCHK(plan_alloc(p, &p->x1, (size_t)ng));
+    TempAllocs ta;
+    unsigned* cnt = ta.get<unsigned>((size_t)ng, e);
+    CCHK(e);
+    unsigned* ctr = ta.get<unsigned>(16, e);
+    CCHK(e);
+    const long long nscan_tiles = (ng + MC_TILE - 1) / MC_TILE + 1;
+    unsigned long long* sst = ta.get<unsigned long long>((size_t)nscan_tiles, e);
+    CCHK(e);
+    uint32_t* keys = ta.get<uint32_t>((size_t)nv, e);
+    CCHK(e);
+    CCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * ng, s));
+    CCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 16, s));
+    CCHK(hipMemsetAsync(sst, 0, sizeof(unsigned long long) * nscan_tiles, s));
+    mck::NodeGeom geo;
+    for (int d = 0; d < 3; ++d) {
+        geo.o[d] = p->grid.origin[d];
+        geo.h[d] = p->grid.spacing[d];
+        geo.n[d] = p->grid.dims[d];
+    }
+    CCHK(mck::nearest_nodes(p->coords, p->dim, nv, geo, p->m, cnt, s));
+    CCHK(mck::scan_u32(cnt, ng, p->noff, sst, ctr + 3, s));
+    CCHK(mck::count_empty(cnt, ng, ctr + 1, s));
+    size_t tb = 0;
+    CCHK(mck::sort_by_node(p->m, nv, ng, keys, p->vlist, nullptr, &tb, s));
+    void* tmp = ta.get<unsigned char>(tb, e);
+    CCHK(e);
+    CCHK(mck::sort_by_node(p->m, nv, ng, keys, p->vlist, tmp, &tb, s));
+    unsigned hctr[16];
+    CCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
+    CCHK(hipStreamSynchronize(s));
+    p->n_unresolved = hctr[1];
+#undef CCHK
+    return MC_OK;
+}
+
 extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t n_vertices,
                                     int64_t n_cells, const mc_grid* grid, const mc_plan_opts* opts,
                                     hipStream_t stream, mc_plan* out)
@@ -361,8 +412,14 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     *out = nullptr;
     mc_status st = check_mesh_args(d_coords, dim, n_vertices);
     if (st != MC_OK) return st;
-    if (!d_cells) return mc_fail(MC_ERR_ARG, "cells pointer is NULL");
-    if (n_cells <= 0 || n_cells >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
+    const int ops = opts ? opts->operators : MC_OPS_LINEAR;
+    if (ops != MC_OPS_LINEAR && ops != MC_OPS_CLUSTER) return mc_fail(MC_ERR_ARG, "unknown operator pair");
+    if (ops == MC_OPS_LINEAR) {
+        if (!d_cells) return mc_fail(MC_ERR_ARG, "cells pointer is NULL");
+        if (n_cells <= 0 || n_cells >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
+    } else if (n_cells < 0 || n_cells >= (1ll << 31)) {
+        return mc_fail(MC_ERR_ARG, "n_cells must be in [0, 2^31)");
+    }
     if ((st = mc_check_grid(grid, dim)) != MC_OK) return st;
     mc_fill fill = opts ? opts->fill : MC_FILL_NEAREST;
     if (fill != MC_FILL_NEAREST && fill != MC_FILL_MIDRANGE) return mc_fail(MC_ERR_ARG, "unknown fill mode");
@@ -378,90 +435,99 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->ng = grid->dims[0] * grid->dims[1] * grid->dims[2];
     p->fill = fill;
     p->B = B;
+    p->ops = ops;
     const long long ng = p->ng, nv = p->nv, nc = p->nc;
     hipStream_t s = stream;
 
     PCHK(plan_alloc(p, &p->coords, (size_t)dim * nv));
     PCHK(hipMemcpyAsync(p->coords, d_coords, sizeof(float) * dim * nv, hipMemcpyDeviceToDevice, s));
-    PCHK(plan_alloc(p, &p->vid, (size_t)(dim + 1) * ng));
-    PCHK(plan_alloc(p, &p->w, (size_t)(dim + 1) * ng));
-    PCHK(plan_alloc(p, &p->cell, (size_t)ng));
-
-    {
-        TempAllocs ta;
-        hipError_t e = hipSuccess;
-        const int nb0 = (int)((grid->dims[0] + B - 1) / B), nb1 = (int)((grid->dims[1] + B - 1) / B),
-                  nb2 = (int)((grid->dims[2] + B - 1) / B);
-        const long long nbins = (long long)nb0 * nb1 * nb2;
-        unsigned* cnt = ta.get<unsigned>(nbins + 4, e);
-        PCHK(e);
-        unsigned* ctr = ta.get<unsigned>(16, e);     // [0] bad cells, [1] unresolved, [2] near-degenerate, [3] ticket
-        PCHK(e);
-        long long* start = ta.get<long long>(nbins + 1, e);
-        PCHK(e);
-        const long long nscan_tiles = (nbins + MC_TILE - 1) / MC_TILE + 1;
-        unsigned long long* sst = ta.get<unsigned long long>(nscan_tiles, e);
-        PCHK(e);
-        PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
-        PCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 16, s));
-        PCHK(hipMemsetAsync(sst, 0, sizeof(unsigned long long) * nscan_tiles, s));
-        PCHK(mck::bins_count(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
-                             cnt, ctr + 0, s));
-        PCHK(mck::scan_u32(cnt, nbins, start, sst, ctr + 3, s));
-        long long total = 0;
-        unsigned hctr[16];
-        PCHK(hipMemcpyAsync(&total, start + nbins, sizeof total, hipMemcpyDeviceToHost, s));
-        PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
-        PCHK(hipStreamSynchronize(s));
-        if (hctr[0] != 0) {
-            p->invalid_cells = (int)hctr[0];
+    if (ops == MC_OPS_CLUSTER) {
+        mc_status cs = build_cluster_map(p, s);
+        if (cs != MC_OK) {
             mc_plan_destroy(p);
-            return mc_fail(MC_ERR_ARG, "%u cells reference a vertex id outside [0, n_vertices)", hctr[0]);
+            return cs;
         }
-        p->n_pairs = total;
-        int32_t* list = ta.get<int32_t>((size_t)total + 1, e);
-        PCHK(e);
-        PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
-        PCHK(mck::bins_fill(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
-                            start, cnt, list, s));
-        int32_t* unres = ta.get<int32_t>((size_t)ng, e);
-        PCHK(e);
-        PCHK(mck::locate(p->coords, d_cells, dim, nv, nc, p->gg, B, nb0, nb1, start, list, p->vid, p->w, p->cell,
-                         unres, ctr + 1, ctr + 2, s));
-        PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
-        PCHK(hipStreamSynchronize(s));
-        p->n_unresolved = hctr[1];
-        p->n_near_degenerate = hctr[2];
-        if (p->n_unresolved > 0) {
-            if (fill == MC_FILL_MIDRANGE) {
-                PCHK(mck::fill_midrange(dim, unres, p->n_unresolved, p->vid, p->w, ng, s));
-            } else {
-                const int VB = dim == 2 ? 4 : 2;
-                const int vb0 = (int)((grid->dims[0] + VB - 1) / VB), vb1 = (int)((grid->dims[1] + VB - 1) / VB),
-                          vb2 = dim == 3 ? (int)((grid->dims[2] + VB - 1) / VB) : 1;
-                const long long nvb = (long long)vb0 * vb1 * vb2;
-                unsigned* vcnt = ta.get<unsigned>(nvb + 4, e);
-                PCHK(e);
-                long long* vstart = ta.get<long long>(nvb + 1, e);
-                PCHK(e);
-                const long long vtiles = (nvb + MC_TILE - 1) / MC_TILE + 1;
-                unsigned long long* vst = ta.get<unsigned long long>(vtiles, e);
-                PCHK(e);
-                int32_t* vlist = ta.get<int32_t>((size_t)nv, e);
-                PCHK(e);
-                PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
-                PCHK(hipMemsetAsync(vst, 0, sizeof(unsigned long long) * vtiles, s));
-                PCHK(hipMemsetAsync(ctr + 4, 0, sizeof(unsigned), s));
-                PCHK(mck::vbins_count(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vcnt, s));
-                PCHK(mck::scan_u32(vcnt, nvb, vstart, vst, ctr + 4, s));
-                PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
-                PCHK(mck::vbins_fill(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vstart, vcnt,
-                                     vlist, s));
-                PCHK(mck::fill_nearest(p->coords, dim, nv, p->gg, grid->origin, grid->spacing, VB, vb0, vb1, vb2,
-                                       vstart, vlist, unres, p->n_unresolved, p->vid, p->w, ng, s));
+    } else {
+        PCHK(plan_alloc(p, &p->vid, (size_t)(dim + 1) * ng));
+        PCHK(plan_alloc(p, &p->w, (size_t)(dim + 1) * ng));
+        PCHK(plan_alloc(p, &p->cell, (size_t)ng));
+
+        {
+            TempAllocs ta;
+            hipError_t e = hipSuccess;
+            const int nb0 = (int)((grid->dims[0] + B - 1) / B), nb1 = (int)((grid->dims[1] + B - 1) / B),
+                      nb2 = (int)((grid->dims[2] + B - 1) / B);
+            const long long nbins = (long long)nb0 * nb1 * nb2;
+            unsigned* cnt = ta.get<unsigned>(nbins + 4, e);
+            PCHK(e);
+            unsigned* ctr = ta.get<unsigned>(16, e);     // [0] bad cells, [1] unresolved, [2] near-degenerate, [3] ticket
+            PCHK(e);
+            long long* start = ta.get<long long>(nbins + 1, e);
+            PCHK(e);
+            const long long nscan_tiles = (nbins + MC_TILE - 1) / MC_TILE + 1;
+            unsigned long long* sst = ta.get<unsigned long long>(nscan_tiles, e);
+            PCHK(e);
+            PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+            PCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 16, s));
+            PCHK(hipMemsetAsync(sst, 0, sizeof(unsigned long long) * nscan_tiles, s));
+            PCHK(mck::bins_count(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
+                                 cnt, ctr + 0, s));
+            PCHK(mck::scan_u32(cnt, nbins, start, sst, ctr + 3, s));
+            long long total = 0;
+            unsigned hctr[16];
+            PCHK(hipMemcpyAsync(&total, start + nbins, sizeof total, hipMemcpyDeviceToHost, s));
+            PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
+            PCHK(hipStreamSynchronize(s));
+            if (hctr[0] != 0) {
+                p->invalid_cells = (int)hctr[0];
+                mc_plan_destroy(p);
+                return mc_fail(MC_ERR_ARG, "%u cells reference a vertex id outside [0, n_vertices)", hctr[0]);
             }
+            p->n_pairs = total;
+            int32_t* list = ta.get<int32_t>((size_t)total + 1, e);
+            PCHK(e);
+            PCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+            PCHK(mck::bins_fill(p->coords, d_cells, dim, nv, nc, p->gg, grid->origin, grid->spacing, B, nb0, nb1, nb2,
+                                start, cnt, list, s));
+            int32_t* unres = ta.get<int32_t>((size_t)ng, e);
+            PCHK(e);
+            PCHK(mck::locate(p->coords, d_cells, dim, nv, nc, p->gg, B, nb0, nb1, start, list, p->vid, p->w, p->cell,
+                             unres, ctr + 1, ctr + 2, s));
+            PCHK(hipMemcpyAsync(hctr, ctr, sizeof hctr, hipMemcpyDeviceToHost, s));
+            PCHK(hipStreamSynchronize(s));
+            p->n_unresolved = hctr[1];
+            p->n_near_degenerate = hctr[2];
+            if (p->n_unresolved > 0) {
+                if (fill == MC_FILL_MIDRANGE) {
+                    PCHK(mck::fill_midrange(dim, unres, p->n_unresolved, p->vid, p->w, ng, s));
+                } else {
+                    const int VB = dim == 2 ? 4 : 2;
+                    const int vb0 = (int)((grid->dims[0] + VB - 1) / VB), vb1 = (int)((grid->dims[1] + VB - 1) / VB),
+                              vb2 = dim == 3 ? (int)((grid->dims[2] + VB - 1) / VB) : 1;
+                    const long long nvb = (long long)vb0 * vb1 * vb2;
+                    unsigned* vcnt = ta.get<unsigned>(nvb + 4, e);
+                    PCHK(e);
+                    long long* vstart = ta.get<long long>(nvb + 1, e);
+                    PCHK(e);
+                    const long long vtiles = (nvb + MC_TILE - 1) / MC_TILE + 1;
+                    unsigned long long* vst = ta.get<unsigned long long>(vtiles, e);
+                    PCHK(e);
+                    int32_t* vlist = ta.get<int32_t>((size_t)nv, e);
+                    PCHK(e);
+                    PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
+                    PCHK(hipMemsetAsync(vst, 0, sizeof(unsigned long long) * vtiles, s));
+                    PCHK(hipMemsetAsync(ctr + 4, 0, sizeof(unsigned), s));
+                    PCHK(mck::vbins_count(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vcnt, s));
+                    PCHK(mck::scan_u32(vcnt, nvb, vstart, vst, ctr + 4, s));
+                    PCHK(hipMemsetAsync(vcnt, 0, sizeof(unsigned) * nvb, s));
+                    PCHK(mck::vbins_fill(p->coords, dim, nv, grid->origin, grid->spacing, VB, vb0, vb1, vb2, vstart, vcnt,
+                                         vlist, s));
+                    PCHK(mck::fill_nearest(p->coords, dim, nv, p->gg, grid->origin, grid->spacing, VB, vb0, vb1, vb2,
+                                           vstart, vlist, unres, p->n_unresolved, p->vid, p->w, ng, s));
+                }
+            }
+            PCHK(hipStreamSynchronize(s));
         }
-        PCHK(hipStreamSynchronize(s));
     }
 
     // compress / decompress workspace
@@ -527,12 +593,23 @@ extern "C" mc_status mc_plan_get_grid(mc_plan p, mc_grid* out)
 extern "C" mc_status mc_plan_mapping(mc_plan p, int32_t* d_vid, float* d_w, int32_t* d_cell, hipStream_t s)
 {
     if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (p->ops != MC_OPS_LINEAR) return mc_fail(MC_ERR_UNSUPPORTED, "the plan has no cell mapping (MC_OPS_CLUSTER)");
     const size_t k = (size_t)(p->dim + 1) * p->ng;
     hipError_t e = hipSuccess;
     if (d_vid && e == hipSuccess) e = hipMemcpyAsync(d_vid, p->vid, k * 4, hipMemcpyDeviceToDevice, s);
     if (d_w && e == hipSuccess) e = hipMemcpyAsync(d_w, p->w, k * 4, hipMemcpyDeviceToDevice, s);
     if (d_cell && e == hipSuccess) e = hipMemcpyAsync(d_cell, p->cell, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mapping copy: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_nodes(mc_plan p, int32_t* d_m, hipStream_t s)
+{
+    if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (!d_m) return mc_fail(MC_ERR_ARG, "output pointer is NULL");
+    if (p->ops != MC_OPS_CLUSTER) return mc_fail(MC_ERR_UNSUPPORTED, "the plan has no node map (MC_OPS_LINEAR)");
+    hipError_t e = hipMemcpyAsync(d_m, p->m, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "node map copy: %s", hipGetErrorString(e));
     return MC_OK;
 }
 
@@ -573,6 +650,22 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
 #define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
     RangeOut* cur = p->rbuf;
     ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, bp, p->bound, p->small, p->nsmall, s));
+    if (p->ops == MC_OPS_CLUSTER) {
+        double* x1 = prm->residual == MC_RESIDUAL_OPEN ? p->x1 : nullptr;
+        ECHK(mck::cluster_mean(p->noff, p->vlist, p->ng, d_field, dtype, p->bound, p->p, p->xh, x1,
+                               codes->dbg_resampled, p->err, codes->result, p->gcount, p->ntg, s));
+        ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
+                          codes->grid_codes, p->gcount, p->gsum, p->knobs, s));
+        ECHK(mck::residual_nearest(p->m, p->nv, d_field, dtype, x1, p->xh, p->bound, codes->vert_codes,
+                                   codes->dbg_vertex_g, p->vcount, p->vsum, s));
+        ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes,
+                          p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype,
+                          p->nv, codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val,
+                          codes->v_out_cap, p->err, codes->result, s));
+        if (codes->dbg_grid_p)
+            ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+        return MC_OK;
+    }
     ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, p->xh, codes->dbg_resampled,
                        codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, p->knobs, s));
     ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
@@ -609,6 +702,12 @@ mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const 
     if (prm->split_mode == MC_SPLIT_FULL && (!(prm->grid_share > 0.0) || !(prm->grid_share <= 16.0)))
         return mc_fail(MC_ERR_ARG, "grid_share must be in (0, 16] with MC_SPLIT_FULL");
     if (prm->model && mc_model_dim(prm->model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
+    if (prm->residual != MC_RESIDUAL_CLOSED && prm->residual != MC_RESIDUAL_OPEN)
+        return mc_fail(MC_ERR_ARG, "unknown residual reference");
+    if (prm->residual == MC_RESIDUAL_OPEN && (p->ops != MC_OPS_CLUSTER || prm->split_mode != MC_SPLIT_SUM))
+        return mc_fail(MC_ERR_UNSUPPORTED, "the open-loop residual needs an MC_OPS_CLUSTER plan and MC_SPLIT_SUM");
+    if (prm->model && p->ops != MC_OPS_LINEAR)
+        return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
     return check_codes(p, codes, prm->model != nullptr);
 }
 
@@ -626,6 +725,8 @@ mc_status mc_check_decompress(mc_plan p, const mc_codes* codes, mc_model model, 
     if (!d_out) return mc_fail(MC_ERR_ARG, "output pointer is NULL");
     if (dtype != MC_F32 && dtype != MC_F64) return mc_fail(MC_ERR_ARG, "dtype must be MC_F32 or MC_F64");
     if (model && mc_model_dim(model) != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
+    if (model && p->ops != MC_OPS_LINEAR)
+        return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
     return check_codes(p, codes, model != nullptr);
 }
 
@@ -637,6 +738,11 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
                           p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
                           p->dws, p->knobs, s));
+    if (p->ops == MC_OPS_CLUSTER) {
+        ECHK(mck::vertex_decode_nearest(p->m, p->nv, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
+                                        codes->v_out_cap, codes->result, d_out, dtype, s));
+        return MC_OK;
+    }
     const int32_t* rho = nullptr;
     if (model) {
         mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);

@@ -11,6 +11,12 @@ struct mc_plan_s {
     GridGeom gg{};
     int fill = 0;
     int B = 1;
+    int ops = MC_OPS_LINEAR;       // operator pair (mc_plan_opts.operators)
+    // nearest-node / cluster-mean pair (device)
+    int32_t* m = nullptr;          // nearest node of every vertex [nv]
+    int32_t* vlist = nullptr;      // vertices sorted by node, ascending ids within a node [nv]
+    long long* noff = nullptr;     // node j's vertices: vlist[noff[j] .. noff[j+1]) [ng + 1]
+    double* x1 = nullptr;          // cluster means of the current call [ng] (open loop)
     // mapping (device)
     float* coords = nullptr;       // [dim][nv] copy
     int32_t* vid = nullptr;        // [dim+1][ng]

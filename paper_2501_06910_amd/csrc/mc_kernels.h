@@ -107,6 +107,28 @@ hipError_t serial_codes(const void* x, int dtype, long long n, const DevBound* b
 hipError_t serial_decode(const uint16_t* codes, const int32_t* oidx, const void* oval, long long vcap,
                          const mc_result* res, long long n, int dtype, int2* agg, int* carry, void* out, hipStream_t s);
 
+// ---- nearest-node g and cluster-mean f (k_cluster.hip) --------------------
+struct NodeGeom {
+    double o[3], h[3];
+    long long n[3];
+};
+hipError_t nearest_nodes(const float* coords, int dim, long long nv, NodeGeom g, int32_t* m, unsigned* count,
+                         hipStream_t s);
+hipError_t count_empty(const unsigned* count, long long ng, unsigned* out, hipStream_t s);
+// Stable sort of the vertices by node (temp == NULL: *temp_bytes receives the size).
+hipError_t sort_by_node(const int32_t* m, long long nv, long long ng, uint32_t* keys_out, int32_t* vlist,
+                        void* temp, size_t* temp_bytes, hipStream_t s);
+hipError_t cluster_mean(const long long* noff, const int32_t* vlist, long long ng, const void* x, int dtype,
+                        const DevBound* bnd, int32_t* p, float* xh, double* x1, float* dbg_v, unsigned* err,
+                        mc_result* res, unsigned* gcount, long long ntg, hipStream_t s);
+// x1 == NULL: closed loop (against the reconstructed grid xhat), else open loop (against x1)
+hipError_t residual_nearest(const int32_t* m, long long nv, const void* x, int dtype, const double* x1,
+                            const float* xhat, const DevBound* bnd, uint16_t* codes, float* dbg_g, unsigned* count,
+                            unsigned* vsum, hipStream_t s);
+hipError_t vertex_decode_nearest(const int32_t* m, long long nv, const float* xhat, const uint16_t* codes,
+                                 const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
+                                 void* xout, int dtype, hipStream_t s);
+
 // ---- learned predictor (k_mlp.hip) ----------------------------------------
 struct MlpDev {
     int dim, kin, kpad;

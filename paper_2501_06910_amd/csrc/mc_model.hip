@@ -154,6 +154,7 @@ extern "C" mc_status mc_model_features(mc_model m, mc_plan p, const mc_codes* co
 {
     if (!m || !p || !codes || !codes->result || !d_z) return mc_fail(MC_ERR_ARG, "invalid feature arguments");
     if (m->dim != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
+    if (p->ops != MC_OPS_LINEAR) return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
     if (v0 < 0 || count < 0 || v0 + count > p->nv) return mc_fail(MC_ERR_ARG, "vertex range outside the mesh");
     hipError_t e = mck::mlp_features(m->md, p->coords, p->nv, p->gg, p->xh, v0, count, d_z, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mlp_features: %s", hipGetErrorString(e));
@@ -196,6 +197,7 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     if (!out) return mc_fail(MC_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!plan) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (plan->ops != MC_OPS_LINEAR) return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
     if (prm && prm->model) return mc_fail(MC_ERR_ARG, "training compresses plainly: params.model must be NULL");
     const int steps = opts && opts->steps > 0 ? opts->steps : 2000;
     const int batch = opts && opts->batch > 0 ? opts->batch : 8192;

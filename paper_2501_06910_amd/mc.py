@@ -31,7 +31,11 @@ class McGrid(C.Structure):
 
 
 class McPlanOpts(C.Structure):
-    _fields_ = [("fill", C.c_int), ("bin_nodes", C.c_int32)]
+    _fields_ = [("fill", C.c_int), ("bin_nodes", C.c_int32), ("operators", C.c_int32)]
+
+
+OPS_LINEAR, OPS_CLUSTER = 0, 1
+RESIDUAL_CLOSED, RESIDUAL_OPEN = 0, 1
 
 
 class McPlanInfo(C.Structure):
@@ -42,7 +46,7 @@ class McPlanInfo(C.Structure):
 
 class McParams(C.Structure):
     _fields_ = [("eb", C.c_double), ("eb_mode", C.c_int32), ("grid_share", C.c_double),
-                ("model", C.c_void_p), ("split_mode", C.c_int32)]
+                ("model", C.c_void_p), ("split_mode", C.c_int32), ("residual", C.c_int32)]
 
 
 SPLIT_SUM, SPLIT_FULL = 0, 1
@@ -103,6 +107,7 @@ _SIGS = {
     "mc_plan_mapping": (C.c_int, [_P, _P, _P, _P, _P]),
     "mc_plan_get_grid": (C.c_int, [_P, _P]),
     "mc_plan_destroy": (C.c_int, [_P]),
+    "mc_plan_nodes": (C.c_int, [_P, _P, _P]),
     "mc_compress": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
     "mc_decompress": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
     "mc_compress_mesh": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, C.c_int, _P, C.c_double,
@@ -238,18 +243,26 @@ class Plan:
     """Field-independent mesh-grid mapping (owns device memory)."""
 
     def __init__(self, coords, cells, grid: McGrid | None = None, dims=None, fill: str = "nearest",
-                 bin_nodes: int = 0):
+                 bin_nodes: int = 0, operators: str = "linear"):
+        """operators: "linear" (barycentric f, multilinear g) or "cluster"
+        (the paper's cluster-mean f and nearest-node g; cells may be None)."""
         torch = _torch()
         _require_cuda(coords, "coords", torch.float32)
-        _require_cuda(cells, "cells", torch.int32)
+        if operators not in ("linear", "cluster"):
+            raise ValueError("operators must be 'linear' or 'cluster'")
+        if cells is not None or operators == "linear":
+            _require_cuda(cells, "cells", torch.int32)
         self.dim = int(coords.shape[0])
+        self.operators = operators
         if grid is None:
             grid = grid_from_dims(coords, dims)
         self.grid = grid
-        opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, bin_nodes)
+        opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, bin_nodes,
+                          OPS_CLUSTER if operators == "cluster" else OPS_LINEAR)
         h = C.c_void_p()
-        _check(lib().mc_plan_create(_ptr(coords), _ptr(cells), self.dim, coords.shape[1], cells.shape[1],
-                                    C.byref(grid), C.byref(opts), _stream(), C.byref(h)), "mc_plan_create")
+        _check(lib().mc_plan_create(_ptr(coords), _ptr(cells), self.dim, coords.shape[1],
+                                    0 if cells is None else cells.shape[1], C.byref(grid), C.byref(opts), _stream(),
+                                    C.byref(h)), "mc_plan_create")
         self.handle = h
         self.n_vertices = int(coords.shape[1])
         self.n_grid = int(grid.dims[0] * grid.dims[1] * grid.dims[2])
@@ -266,6 +279,13 @@ class Plan:
         cell = torch.empty(self.n_grid, dtype=torch.int32, device="cuda")
         _check(lib().mc_plan_mapping(self.handle, _ptr(vid), _ptr(w), _ptr(cell), _stream()), "mc_plan_mapping")
         return vid, w, cell
+
+    def nodes(self):
+        """Nearest grid node of every vertex (cluster plans)."""
+        torch = _torch()
+        m = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
+        _check(lib().mc_plan_nodes(self.handle, _ptr(m), _stream()), "mc_plan_nodes")
+        return m
 
     @property
     def remap_mask(self) -> int:
@@ -401,12 +421,17 @@ class Codes:
 
 
 def compress(plan: Plan, field, eb: float, eb_mode: str = "rel", grid_share: float = 0.5, model=None,
-             codes: Codes | None = None, debug: bool = False, split_mode="sum") -> Codes:
+             codes: Codes | None = None, debug: bool = False, split_mode="sum", residual: str = "closed") -> Codes:
+    """residual: "closed" (against the reconstructed grid) or "open" (against
+    the grid before compression, Alg. 3; cluster plans, sum split)."""
     _require_cuda(field, "field")
     if codes is None:
         codes = Codes(plan, field.dtype, learned=model is not None, debug=debug)
+    if residual not in ("closed", "open"):
+        raise ValueError("residual must be 'closed' or 'open'")
     prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share,
-                   None if model is None else model.handle, _split_code(split_mode))
+                   None if model is None else model.handle, _split_code(split_mode),
+                   RESIDUAL_OPEN if residual == "open" else RESIDUAL_CLOSED)
     _check(lib().mc_compress(plan.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(codes.struct),
                              _stream()), "mc_compress")
     return codes

@@ -82,6 +82,12 @@ def test_host_validation_before_device_work():
     # batches
     assert lib.mc_batch_decompress(None, 1, None) == M.ERR_ARG
     assert lib.mc_batch_compress(fake, 0, None) == M.ERR_ARG
+    # operator pairs
+    bad_ops = M.McPlanOpts(M.FILL_NEAREST, 0, 7)
+    assert lib.mc_plan_create(fake, None, 2, 10, 0, C.byref(g), C.byref(bad_ops), None, C.byref(out)) == M.ERR_ARG
+    lin = M.McPlanOpts(M.FILL_NEAREST, 0, M.OPS_LINEAR)
+    assert lib.mc_plan_create(fake, None, 2, 10, 0, C.byref(g), C.byref(lin), None, C.byref(out)) == M.ERR_ARG
+    assert lib.mc_plan_nodes(None, fake, None) == M.ERR_ARG
     # 1-D serialisation baseline
     assert lib.mc_serial_create(0, C.byref(out)) == M.ERR_ARG
     assert lib.mc_serial_create(1 << 31, C.byref(out)) == M.ERR_ARG

@@ -1,0 +1,123 @@
+"""GPU parity of the paper's own operator pair (nearest-node g, cluster-mean
+f; Sec. IV-C/IV-D) with the open-loop residual of Alg. 3 and the closed-loop
+option: node map, cluster means (through the prequantised grid), grid and
+vertex codes, outlier lists and decoded values bit for bit against the
+oracle; every vertex within tau (open) or tau2 (closed)."""
+import numpy as np
+import pytest
+
+import meshgen as G
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2501_06910_amd import mc as M  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _cases():
+    out = []
+    m3 = G.kuhn_tet_mesh(22, 5)
+    f3 = G.field_octaves(m3.coords, np.random.default_rng(1))
+    out.append(("kuhn3d_f32_open", m3, f3, (12, 11, 10), 1e-4, True, 0.5, "open", "sum"))
+    out.append(("kuhn3d_f32_closed_full", m3, f3, (12, 11, 10), 1e-4, True, 2.0, "closed", "full"))
+    out.append(("kuhn3d_f32_fine_grid", m3, f3, (40, 37, 33), 1e-3, True, 0.3, "open", "sum"))   # many empty nodes
+    mesh, f, cfg = G.config_small_2d()
+    out.append(("small2d_f64_open", mesh, f, (40, 40), cfg["eb"], False, 0.5, "open", "sum"))
+    out.append(("small2d_f64_closed", mesh, f, (40, 40), cfg["eb"], False, 0.5, "closed", "sum"))
+    m4 = G.kuhn_tet_mesh(17, 6)
+    x4 = G.field_octaves(m4.coords, np.random.default_rng(2), dtype=np.float64)
+    out.append(("kuhn3d_f64_tiny_eb", m4, x4, (9, 10, 8), 1e-7, True, 0.9, "open", "sum"))
+    return out
+
+
+CASES = _cases()
+
+
+class Case:
+    def __init__(self, name, mesh, x, dims, eb, rel, split, residual, mode):
+        self.name, self.mesh, self.x, self.dims = name, mesh, x, dims
+        self.eb, self.rel, self.split, self.residual, self.mode = eb, rel, split, residual, mode
+        print(f"[cluster] {name}: nv={mesh.n_vertices} dims={dims} eb={eb} rel={rel} split={split} ({mode}) "
+              f"residual={residual} dtype={x.dtype}", flush=True)
+        self.og = O.grid_from_dims(mesh.coords, dims)
+        self.dx = dev(x)
+        self.plan = M.Plan(dev(mesh.coords), None, dims=dims, operators="cluster")
+
+    def oracle(self):
+        return O.compress_cluster(self.mesh.coords, self.og, self.x, self.eb, self.rel, self.split,
+                                  self.residual == "open", O.SPLIT_FULL if self.mode == "full" else O.SPLIT_SUM)
+
+    def gpu(self):
+        codes = M.compress(self.plan, self.dx, self.eb, "rel" if self.rel else "abs", self.split, debug=True,
+                           split_mode=self.mode, residual=self.residual)
+        torch.cuda.synchronize()
+        return codes
+
+
+@pytest.fixture(scope="module", params=range(len(CASES)), ids=[c[0] for c in CASES])
+def case(request):
+    return Case(*CASES[request.param])
+
+
+def test_node_map_and_cluster_means(case):
+    oc = case.oracle()
+    assert np.array_equal(case.plan.nodes().cpu().numpy(), oc.m)
+    assert case.plan.info()["n_unresolved"] == int((oc.count == 0).sum())
+    codes = case.gpu()
+    assert np.array_equal(codes.dbg_resampled.cpu().numpy().view(np.uint32),
+                          oc.x1.astype(np.float32).view(np.uint32))
+    assert np.array_equal(codes.dbg_grid_p.cpu().numpy(), oc.grid.p)
+    print(f"[cluster] {case.name}: {int((oc.count == 0).sum())} empty nodes of {oc.count.size}")
+
+
+def test_codes_bitexact(case):
+    oc = case.oracle()
+    h = case.gpu().host()
+    r = h["result"]
+    assert r["status"] == 0
+    for k in ("tau", "tau1", "tau2", "c", "xmin", "xmax"):
+        assert r[k] == getattr(oc.bound, k), k
+    assert np.array_equal(h["grid_codes"], oc.grid.codes)
+    assert np.array_equal(h["g_out_idx"], oc.grid.out_idx)
+    assert np.array_equal(h["g_out_delta"], oc.grid.out_delta)
+    assert np.array_equal(h["vert_codes"], oc.vert.codes)
+    assert np.array_equal(h["v_out_idx"], oc.vert.out_idx)
+    assert np.array_equal(h["v_out_val"].view(np.uint8), oc.vert.out_val.view(np.uint8))
+    print(f"[cluster] {case.name}: grid outliers {oc.grid.out_idx.size}, vertex outliers {oc.vert.out_idx.size}")
+
+
+def test_roundtrip_bitexact_and_bound(case):
+    oc = case.oracle()
+    codes = case.gpu()
+    xr = M.decompress(case.plan, codes)
+    torch.cuda.synchronize()
+    xg = xr.cpu().numpy()
+    xo = O.decompress_cluster(case.mesh.coords, case.og, oc.bound, oc.grid, oc.vert, case.x.dtype)
+    assert np.array_equal(xg.view(np.uint8), xo.view(np.uint8))
+    bound = oc.bound.tau if case.residual == "open" else oc.bound.tau2
+    assert np.all(np.abs(case.x.astype(np.float64) - xg.astype(np.float64)) <= bound)
+
+
+def test_rejected_combinations():
+    mesh = G.kuhn_tet_mesh(9, 2)
+    x = dev(G.field_octaves(mesh.coords, np.random.default_rng(6)))
+    lin = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=(8, 8, 8))
+    with pytest.raises(M.McError) as e:
+        M.compress(lin, x, 1e-3, residual="open")          # open loop needs the cluster pair
+    assert e.value.status == M.ERR_UNSUPPORTED
+    with pytest.raises(M.McError):
+        lin.nodes()
+    cl = M.Plan(dev(mesh.coords), None, dims=(8, 8, 8), operators="cluster")
+    with pytest.raises(M.McError) as e:
+        M.compress(cl, x, 1e-3, 2.0, split_mode="full", residual="open")
+    assert e.value.status == M.ERR_UNSUPPORTED
+    with pytest.raises(M.McError):
+        cl.mapping()

@@ -96,7 +96,7 @@ def test_bound_codes_and_roundtrip(eb, split, open_loop, mode, dtype):
     xd = x.astype(np.float64)
     assert np.all(np.abs(xd - xr) <= (b.tau if open_loop else b.tau2))
     # the definition, evaluated here independently
-    xh = b.c + cz.grid.p.astype(np.float64) * b.step1
+    xh = (b.c + cz.grid.p.astype(np.float64) * b.step1).astype(np.float32).astype(np.float64)
     ref = cz.x1 if open_loop else xh
     q = np.rint((xd - ref[cz.m]) * b.inv2)
     s = xh[cz.m] + q * b.step2
