@@ -184,6 +184,53 @@ def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
     return row
 
 
+def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="full", operators="linear",
+                 residual="closed"):
+    """The same field at another setting of the CR sweep (default: the
+    best one, a 128^3 grid, one node per ~8 vertices, with the full split
+    tau2 = tau and the grid step from tau1 = 4 tau): CR, both directions'
+    GB/s, the improvement over the 1-D baseline and the kernel times."""
+    import torch
+    nv, sT = x.numel(), x.element_size()
+    cells = torch.from_numpy(mesh.cells).cuda() if operators == "linear" else None
+    plan = M.Plan(coords, cells, dims=(dims, dims, dims), operators=operators)
+    del cells
+    codes = M.Codes(plan, x.dtype)
+    out = torch.empty_like(x)
+    kw = dict(split_mode=split_mode, residual=residual)
+    M.compress(plan, x, eb, "rel", split, codes=codes, **kw)
+    M.decompress(plan, codes, out=out)
+    h = codes.host()
+    r = h["result"]
+    err = (x.double() - out.double()).abs().max().item()
+    bound = r["tau"] if residual == "open" else r["tau2"]
+    if r["status"] or not err <= bound:
+        raise SystemExit(f"design point: status {r['status']}, max error {err} vs {bound}")
+    tc = _timed(lambda: M.compress(plan, x, eb, "rel", split, codes=codes, **kw))
+    td = _timed(lambda: M.decompress(plan, codes, out=out))
+    M.profile_reset()
+    M.profile_enable(True)
+    for _ in range(5):
+        M.compress(plan, x, eb, "rel", split, codes=codes, **kw)
+        M.decompress(plan, codes, out=out)
+    torch.cuda.synchronize()
+    M.profile_enable(False)
+    kern = {k: round(t / c, 5) for k, (c, t) in M.profile_read().items()}
+    sb = M.stream_bytes(h, sT)
+    ser = serial_compare(M, x, eb, h, (tc, td), log, f"{operators} {dims}^3, generated order")
+    row = {"operators": operators, "grid": [dims] * 3, "split_mode": split_mode, "grid_share": split,
+           "residual": residual, "cr": round(nv * sT / sb["total"], 3),
+           "max_abs_err_over_tau": round(err / r["tau"], 4),
+           "compress_GBps": round(nv * sT / (tc * 1e-3) / 1e9, 2),
+           "decompress_GBps": round(nv * sT / (td * 1e-3) / 1e9, 2),
+           "ms_per_step": round(tc + td, 4), "stream_bytes": sb,
+           "improvement_vs_serial": ser["improvement_ratio"], "cr_serial": ser["cr_serial"],
+           "kernels_avg_ms": kern}
+    log(f"design point: {row}")
+    plan.destroy()
+    return row
+
+
 def mlp_flops_per_vertex(D: int) -> int:
     """Multiply-adds of one inference (x2): K_in -> 64 -> 64 -> 64 -> 1 with
     K_in = 4^D + D, the zero padding not counted."""
@@ -302,6 +349,10 @@ def learned_section(log, train_steps=2000, batch=8192):
 
 SWEEP_SPLITS = (("sum", 0.1), ("sum", 0.3), ("sum", 0.5), ("sum", 0.7), ("sum", 0.9),
                 ("full", 0.5), ("full", 1.0), ("full", 2.0), ("full", 4.0))
+# the paper's operator pair: open-loop residual with the sum split, or the
+# closed loop with the full split
+SWEEP_CLUSTER = (("sum", 0.1, "open"), ("sum", 0.5, "open"), ("sum", 0.9, "open"),
+                 ("full", 1.0, "closed"), ("full", 4.0, "closed"))
 
 
 def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), splits=SWEEP_SPLITS):
@@ -341,36 +392,39 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
     rows = []
     coords = torch.from_numpy(mesh.coords).cuda()
     cells = torch.from_numpy(mesh.cells).cuda()
-    for gd in grids:
-        plan = M.Plan(coords, cells, dims=(gd, gd, gd))
-        codes = M.Codes(plan, x.dtype)
-        for eb in ebs:
-            for mode, sp in splits:
-                M.compress(plan, x, eb, "rel", sp, codes=codes, split_mode=mode)
-                M.decompress(plan, codes, out=out)
-                h = codes.host()
-                r = h["result"]
-                base = {"grid": gd, "eb": eb, "split_mode": mode, "split": sp}
-                if r["status"]:
-                    rows.append(dict(base, status=r["status"]))
-                    continue
-                d = (xd - out.double()).abs()
-                sb = M.stream_bytes(h, sT)
-                hr = dict(h)
-                hr["v_out_idx"] = np.sort(inv[h["v_out_idx"]])
-                cr, crr = nv * sT / sb["total"], nv * sT / M.stream_bytes(hr, sT)["total"]
-                s_gen, s_rnd = serial[eb]["generated"], serial[eb]["random"]
-                rows.append(dict(base, cr=round(cr, 3), bits_per_value=round(8 * sb["total"] / nv, 4),
-                                 grid_bytes=sb["grid"], vert_bytes=sb["vert"],
-                                 improvement_vs_serial=round(cr / s_gen, 3) if s_gen else None,
-                                 improvement_vs_serial_random_order=round(crr / s_rnd, 3) if s_rnd else None,
-                                 grid_outlier_rate=r["n_grid_outliers"] / plan.n_grid,
-                                 vertex_outlier_rate=r["n_vertex_outliers"] / nv,
-                                 linf_over_tau=round(d.max().item() / r["tau"], 4),
-                                 rel_l2=float(torch.linalg.vector_norm(d).item() / norm)))
-                log(f"cr sweep: {rows[-1]}")
-        plan.destroy()
-        del codes
+    for ops in ("linear", "cluster"):
+        for gd in grids:
+            plan = M.Plan(coords, cells if ops == "linear" else None, dims=(gd, gd, gd), operators=ops)
+            codes = M.Codes(plan, x.dtype)
+            settings = [(m_, sp, "closed") for m_, sp in splits] if ops == "linear" else SWEEP_CLUSTER
+            for eb in ebs:
+                for mode, sp, resid in settings:
+                    M.compress(plan, x, eb, "rel", sp, codes=codes, split_mode=mode, residual=resid)
+                    M.decompress(plan, codes, out=out)
+                    h = codes.host()
+                    r = h["result"]
+                    base = {"operators": ops, "grid": gd, "eb": eb, "split_mode": mode, "split": sp,
+                            "residual": resid}
+                    if r["status"]:
+                        rows.append(dict(base, status=r["status"]))
+                        continue
+                    d = (xd - out.double()).abs()
+                    sb = M.stream_bytes(h, sT)
+                    hr = dict(h)
+                    hr["v_out_idx"] = np.sort(inv[h["v_out_idx"]])
+                    cr, crr = nv * sT / sb["total"], nv * sT / M.stream_bytes(hr, sT)["total"]
+                    s_gen, s_rnd = serial[eb]["generated"], serial[eb]["random"]
+                    rows.append(dict(base, cr=round(cr, 3), bits_per_value=round(8 * sb["total"] / nv, 4),
+                                     grid_bytes=sb["grid"], vert_bytes=sb["vert"],
+                                     improvement_vs_serial=round(cr / s_gen, 3) if s_gen else None,
+                                     improvement_vs_serial_random_order=round(crr / s_rnd, 3) if s_rnd else None,
+                                     grid_outlier_rate=r["n_grid_outliers"] / plan.n_grid,
+                                     vertex_outlier_rate=r["n_vertex_outliers"] / nv,
+                                     linf_over_tau=round(d.max().item() / r["tau"], 4),
+                                     rel_l2=float(torch.linalg.vector_norm(d).item() / norm)))
+                    log(f"cr sweep: {rows[-1]}")
+            plan.destroy()
+            del codes
     return {"serial": {str(k): v for k, v in serial.items()}, "rows": rows}
 
 
@@ -628,6 +682,10 @@ def main():
     mc_d = _timed(lambda: M.decompress(plan, codes, out=out))
     line["serial_baseline"] = [serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "generated order"),
                                serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "random order", shuffle_seed=7)]
+    if args.workload == "tet3d":
+        line["design_points"] = [design_point(M, mesh, coords, x, args.eb, log),
+                                 design_point(M, mesh, coords, x, args.eb, log, split=0.1, split_mode="sum",
+                                              operators="cluster", residual="open")]
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
