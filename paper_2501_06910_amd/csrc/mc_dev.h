@@ -15,7 +15,7 @@
 
 #define MC_R 32768
 #define MC_TILE 1024          // items per workgroup tile (256 threads x 4)
-#define MC_LZ_CHUNK 16        // planes (rows) per Lorenzo sweep
+#define MC_LZ_CHUNK 16        // rows per 2-D Lorenzo sweep
 #define MC_SC_TILES 16        // outlier scatter: tiles per workgroup
 #define MC_RANGE_BLOCKS 2048  // field range: per-block partials (3 words each)
 #define MC_DZ_PLANES 8        // 3-D decode: planes per z chunk

@@ -51,9 +51,9 @@ hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32
                          hipStream_t s);
 
 // ---- compression (k_compress.hip) -----------------------------------------
+// Field range and error split (k_range, then one workgroup folds the partials).
 hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
-                 DevBound* bnd,
-                 unsigned int* zero, long long nzero, hipStream_t s);
+                 DevBound* bnd, unsigned int* zero, long long nzero, hipStream_t s);
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
                     const DevBound* bnd, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
                     long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
