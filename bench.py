@@ -48,20 +48,33 @@ COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_
 DECOMPRESS_PREFIXES = ("k_dec_", "k_vdecode", "k_mlp_infer_d")
 
 
-def pmc_traffic(kernel: str):
-    """HBM bytes per launch of `kernel` from the committed counter runs,
-    or None when the kernel sources changed since they were taken."""
+def _kernel_source(here: str, kernel: str):
+    """The csrc file that defines `kernel` (its __global__ declaration)."""
     import glob
+    import re
+    pat = re.compile(r"__global__[^;{]*?\b" + re.escape(kernel) + r"\s*\(")
+    for p in sorted(glob.glob(os.path.join(here, "paper_2501_06910_amd", "csrc", "*.hip"))):
+        if pat.search(open(p).read()):
+            return p
+    return None
+
+
+def pmc_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter runs, or
+    None when the file defining the kernel (or the shared device header)
+    changed since they were taken."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "tet3d_16M_pmc_traffic.json")
-    if not os.path.exists(path):
+    src = _kernel_source(here, kernel)
+    if not os.path.exists(path) or src is None:
         return None
     rec = json.load(open(path))
-    src = b"".join(open(p, "rb").read()
-                   for p in sorted(glob.glob(os.path.join(here, "paper_2501_06910_amd", "csrc", "*"))))
-    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
-        return None
+    shas = rec.get("source_sha256", {})
+    for p in (src, os.path.join(here, "paper_2501_06910_amd", "csrc", "mc_dev.h")):
+        name = os.path.basename(p)
+        if hashlib.sha256(open(p, "rb").read()).hexdigest() != shas.get(name):
+            return None
     for name, v in rec["kernels"].items():
         if name.split("<")[0] == kernel:
             return v["traffic_bytes"]
@@ -521,6 +534,8 @@ def main():
     ap.add_argument("--split", type=float, default=0.5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time series section")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the 1-D baseline and the design points (profiled runs: only the timed step's kernels)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch order (no autotuning)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cr-sweep", action="store_true", help="print the CR sweep over eb and split instead")
@@ -678,11 +693,13 @@ def main():
         "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
         "kernels": kernels,
     }
-    mc_c = _timed(lambda: M.compress(plan, x, args.eb, "rel", args.split, codes=codes))
-    mc_d = _timed(lambda: M.decompress(plan, codes, out=out))
-    line["serial_baseline"] = [serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "generated order"),
-                               serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "random order", shuffle_seed=7)]
-    if args.workload == "tet3d":
+    if not args.no_compare:
+        mc_c = _timed(lambda: M.compress(plan, x, args.eb, "rel", args.split, codes=codes))
+        mc_d = _timed(lambda: M.decompress(plan, codes, out=out))
+        line["serial_baseline"] = [serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "generated order"),
+                                   serial_compare(M, x, args.eb, h, (mc_c, mc_d), log, "random order",
+                                                  shuffle_seed=7)]
+    if args.workload == "tet3d" and not args.no_compare:
         line["design_points"] = [design_point(M, mesh, coords, x, args.eb, log),
                                  design_point(M, mesh, coords, x, args.eb, log, split=0.1, split_mode="sum",
                                               operators="cluster", residual="open")]

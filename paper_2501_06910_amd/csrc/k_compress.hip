@@ -579,11 +579,30 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
     if (blockIdx.x == 0) {
         // totals of both lists and the learned-block count (bit 31 marks the
         // first tile of a learned block: every MC_LBLOCK / MC_TILE-th tile)
+        // (8 independent loads in flight per thread in each sum)
         unsigned long long tg = 0, tv = 0, nl = 0;
-        for (long long i = threadIdx.x; i < ngg; i += 256) tg += gsum[i];
-        for (long long i = threadIdx.x; i < ngv; i += 256) tv += vsum[i];
+        for (long long i0 = threadIdx.x; i0 < ngg; i0 += 8 * 256) {
+            unsigned a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * u < ngg ? gsum[i0 + 256 * u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tg += a[u];
+        }
+        for (long long i0 = threadIdx.x; i0 < ngv; i0 += 8 * 256) {
+            unsigned a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * u < ngv ? vsum[i0 + 256 * u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) tv += a[u];
+        }
         const long long step = MC_LBLOCK / MC_TILE;
-        for (long long i = threadIdx.x * step; i < ntv; i += 256 * step) nl += vcount[i] >> 31;
+        for (long long i0 = threadIdx.x * step; i0 < ntv; i0 += 8 * 256 * step) {
+            unsigned a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * step * u < ntv ? vcount[i0 + 256 * step * u] : 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) nl += a[u] >> 31;
+        }
         tg = block_sum_u64(tg, s_red);
         tv = block_sum_u64(tv, s_red);
         nl = block_sum_u64(nl, s_red);
@@ -614,7 +633,13 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
     // list offset of the group: sum of the group totals before it
     const unsigned int* sums = vert ? vsum : gsum;
     unsigned long long before = 0;
-    for (long long i = threadIdx.x; i < grp; i += 256) before += sums[i];
+    for (long long i0 = threadIdx.x; i0 < grp; i0 += 8 * 256) {
+        unsigned a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * u < grp ? sums[i0 + 256 * u] : 0u;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) before += a[u];
+    }
     before = block_sum_u64(before, s_red);
     if (threadIdx.x == 0) {
         unsigned long long a = before;
