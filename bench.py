@@ -251,6 +251,56 @@ def mlp_flops_per_vertex(D: int) -> int:
     return 2 * (kin * 64 + 64 * 64 * 2 + 64)
 
 
+def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, split=1.0, split_mode="full",
+                         train_steps=2000, batch=8192):
+    """The rotating series at a coarser grid (512^2: one node per ~16
+    vertices) with the full split: plain and learned CR over t = 1..8 (the
+    model charged once), both forms' GB/s and the gain over the 1-D
+    baseline (serial_bytes: its total stream bytes over the same steps)."""
+    import torch
+    nv, sT = mesh.n_vertices, series[0].dtype.itemsize
+    plan = M.Plan(torch.from_numpy(mesh.coords).cuda(), torch.from_numpy(mesh.cells).cuda(), dims=(dims, dims))
+    xs = [torch.from_numpy(a).cuda() for a in series]
+    model = M.Model.train(plan, xs[0], eb=cfg["eb"], grid_share=split, split_mode=split_mode, steps=train_steps,
+                          batch=batch, seed=4)
+    model_bytes = 16 + 2 * M.param_count(mesh.dim)
+    cp, cl = M.Codes(plan, xs[0].dtype), M.Codes(plan, xs[0].dtype, learned=True)
+    out = torch.empty_like(xs[0])
+    tot = {"plain": 0, "learned": 0}
+    times = {"plain_c": [], "plain_d": [], "learned_c": [], "learned_d": []}
+    kw = dict(split_mode=split_mode)
+    for t in range(1, len(series)):
+        x = xs[t]
+        times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, codes=cp, **kw)))
+        times["plain_d"].append(_timed(lambda: M.decompress(plan, cp, out=out)))
+        ep = (x.double() - out.double()).abs().max().item()
+        times["learned_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, model=model, codes=cl,
+                                                            **kw)))
+        times["learned_d"].append(_timed(lambda: M.decompress(plan, cl, model=model, out=out)))
+        el = (x.double() - out.double()).abs().max().item()
+        hp, hl = cp.host(), cl.host()
+        hl["learned"] = True
+        tau2 = hp["result"]["tau2"]
+        if hp["result"]["status"] or hl["result"]["status"] or not (ep <= tau2 and el <= tau2):
+            raise SystemExit(f"learned design point: status or bound failure at t={t}")
+        tot["plain"] += M.stream_bytes(hp, sT)["total"]
+        tot["learned"] += M.stream_bytes(hl, sT)["total"]
+    raw = nv * sT * (len(series) - 1)
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    row = {"grid": [dims, dims], "split_mode": split_mode, "grid_share": split,
+           "cr_plain": round(raw / tot["plain"], 3), "cr_learned": round(raw / (tot["learned"] + model_bytes), 3),
+           "improvement_vs_serial": {"plain": round(serial_bytes / tot["plain"], 3),
+                                     "learned": round(serial_bytes / (tot["learned"] + model_bytes), 3)},
+           "plain_GBps": {"compress": round(nv * sT / (med["plain_c"] * 1e-3) / 1e9, 2),
+                          "decompress": round(nv * sT / (med["plain_d"] * 1e-3) / 1e9, 2)},
+           "learned_GBps": {"compress": round(nv * sT / (med["learned_c"] * 1e-3) / 1e9, 2),
+                            "decompress": round(nv * sT / (med["learned_d"] * 1e-3) / 1e9, 2)}}
+    log(f"learned design point: {row}")
+    model.destroy()
+    plan.destroy()
+    return row
+
+
 def learned_section(log, train_steps=2000, batch=8192):
     """Learned vs plain on the rotating-front time series over the refined
     2-D mesh: train on t=0, compress t=1..8 both ways at eb 1e-4; CR with the
@@ -357,6 +407,8 @@ def learned_section(log, train_steps=2000, batch=8192):
                       "mfma_peak_bf16_TFLOPs": 2500.0},
         "per_timestep": per_t,
         "n_vertices": nv, "n_grid": ng,
+        "design_point": learned_design_point(M, mesh, series, cfg, tot["serial"], log, train_steps=train_steps,
+                                             batch=batch),
     }
 
 

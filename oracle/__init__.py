@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c"]
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c", "mco_grid_init.c"]
 
 OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
 F32, F64 = 0, 1
@@ -98,6 +98,7 @@ def lib():
             "mco_residual_quantize": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
             "mco_grid_quantize_f64": (i32, [P, P, P, P, P, P, P, i64, P]),
             "mco_nearest_nodes": (None, [P, i32, i64, P, P]),
+            "mco_grid_init": (i32, [P, P, i32, i64, i64, dbl, i64, P, P]),
             "mco_cluster_mean": (None, [P, i32, i64, P, i64, dbl, P, P]),
             "mco_residual_nearest": (i32, [P, i32, i64, P, P, P, P, i32, P, P, P, i64, P]),
             "mco_vertex_decode_nearest": (None, [P, P, P, i64, P, P, P, i32, i64, P]),
@@ -429,6 +430,17 @@ def serial_decompress(codes, out_idx, out_val, b: Bound, dtype) -> np.ndarray:
     lib().mco_serial_decompress(_p(codes), _p(out_idx), _p(out_val), out_idx.size, codes.size, C.byref(b),
                                 _dtype_code(out), _p(out))
     return out
+
+
+def grid_init(coords: np.ndarray, cells: np.ndarray, k: float, g_max: int):
+    """Alg. 1: (grid, k used per axis)."""
+    g = Grid()
+    ku = np.zeros(3, np.float64)
+    st = lib().mco_grid_init(_p(np.ascontiguousarray(coords, np.float32)), _p(np.ascontiguousarray(cells, np.int32)),
+                             coords.shape[0], coords.shape[1], cells.shape[1], float(k), int(g_max), _p(g), _p(ku))
+    if st != OK:
+        raise OracleError(st, "grid_init")
+    return g, ku
 
 
 # ---------------------------------------------------------------------------

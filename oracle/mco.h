@@ -145,6 +145,13 @@ void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, co
                                const int32_t* m, const float* xhat, const mco_bound* b, int dtype, int64_t nv,
                                void* xout);
 
+/* Grid initialisation, Alg. 1 (mco_grid_init.c): per-axis spacing = the
+ * k-th percentile (nearest rank) of the cells' edge extents along the axis,
+ * k raised by one point while (max - min) / spacing >= g_max.  k_used may be
+ * NULL. */
+int mco_grid_init(const float* coords, const int32_t* cells, int dim, int64_t nv, int64_t nc, double k0,
+                  int64_t g_max, mco_grid* g, double k_used[3]);
+
 /* 1-D serialisation baseline (mco_serial.c). */
 int mco_serial_compress(const void* x, int dtype, int64_t n, double eb, int relative, uint16_t* codes,
                         int32_t* out_idx, void* out_val, int64_t cap, int64_t* n_out, mco_bound* b);

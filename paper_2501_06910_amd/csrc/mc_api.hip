@@ -842,7 +842,7 @@ extern "C" mc_status mc_compress_mesh(const float* d_coords, const int32_t* d_ce
     if (st != MC_OK) return st;
     mc_plan p = nullptr;
     if ((st = mc_plan_create(d_coords, d_cells, dim, nv, nc, &g, nullptr, s, &p)) != MC_OK) return st;
-    mc_params prm;
+    mc_params prm{};
     prm.eb = eb;
     prm.eb_mode = eb_mode;
     prm.grid_share = grid_share;
