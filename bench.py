@@ -493,6 +493,57 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
     return {"serial": {str(k): v for k, v in serial.items()}, "rows": rows}
 
 
+def grid_sweep(log, ks=(2.0, 5.0, 10.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0, 80.0, 90.0), g_max=512, eb=1e-4):
+    """CR of the tet3d field over the grid spacing of the paper's grid
+    initialisation (Alg. 1: the k-th percentile of the cells' edge extents,
+    G_max nodes per axis at most), the analogue of the spacing study of
+    Sec. V-B: per k, the grid, its build time, and the CR of the linear pair
+    (sum split 0.5 and full split 4.0) and of the paper's pair (open loop,
+    tau1 = 0.1 tau), next to the 1-D baseline."""
+    import torch
+    import meshgen as G
+    from paper_2501_06910_amd import mc as M
+    mesh, f, cfg = G.config_tet_3d()
+    nv, sT = mesh.n_vertices, 4
+    x = torch.from_numpy(f).cuda()
+    coords = torch.from_numpy(mesh.coords).cuda()
+    cells = torch.from_numpy(mesh.cells).cuda()
+    sctx, sc = M.Serial(nv), M.SerialCodes(nv, x.dtype)
+    M.serial_compress(sctx, x, eb, "rel", codes=sc)
+    cr_serial = nv * sT / M.serial_stream_bytes(sc.host(), sT)["total"]
+    sctx.destroy()
+    out = torch.empty_like(x)
+    rows = []
+    for k in ks:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        g, ku = M.grid_from_percentile(coords, cells, k, g_max)
+        torch.cuda.synchronize()
+        t_init = time.time() - t0
+        dims = [int(g.dims[d]) for d in range(3)]
+        row = {"k": k, "k_used": ku, "dims": dims, "spacing": [g.spacing[d] for d in range(3)],
+               "grid_init_seconds": round(t_init, 4), "cr_serial": round(cr_serial, 3)}
+        for ops, mode, share, resid in (("linear", "sum", 0.5, "closed"), ("linear", "full", 4.0, "closed"),
+                                        ("cluster", "sum", 0.1, "open")):
+            plan = M.Plan(coords, cells if ops == "linear" else None, grid=g, operators=ops)
+            codes = M.Codes(plan, x.dtype)
+            M.compress(plan, x, eb, "rel", share, codes=codes, split_mode=mode, residual=resid)
+            M.decompress(plan, codes, out=out)
+            h = codes.host()
+            r = h["result"]
+            bound = r["tau"] if resid == "open" else r["tau2"]
+            if r["status"] or not (x.double() - out.double()).abs().max().item() <= bound:
+                raise SystemExit(f"grid sweep: failure at k={k} {ops} {mode}")
+            cr = nv * sT / M.stream_bytes(h, sT)["total"]
+            row[f"cr_{ops}_{mode}_{share}"] = round(cr, 3)
+            row[f"improvement_{ops}_{mode}_{share}"] = round(cr / cr_serial, 3)
+            plan.destroy()
+            del codes
+        log(f"grid sweep: {row}")
+        rows.append(row)
+    return {"g_max": g_max, "eb": eb, "rows": rows}
+
+
 def batch_main(args, log):
     """Many fields on many meshes: 12 meshes of 0.5M..20M vertices (2-D and
     3-D, float32 and float64), 64 fields; a step is one batch compress and
@@ -591,6 +642,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch order (no autotuning)")
     ap.add_argument("--train-steps", type=int, default=2000)
     ap.add_argument("--cr-sweep", action="store_true", help="print the CR sweep over eb and split instead")
+    ap.add_argument("--grid-sweep", action="store_true",
+                    help="print the CR over the percentile grid spacing of the grid initialisation instead")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="mesh size scale of the batch workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
@@ -611,6 +664,9 @@ def main():
         return
     if args.cr_sweep:
         print(json.dumps({"cr_sweep": cr_sweep(log), "workload": "tet3d"}), flush=True)
+        return
+    if args.grid_sweep:
+        print(json.dumps({"grid_sweep": grid_sweep(log), "workload": "tet3d"}), flush=True)
         return
 
     t0 = time.time()

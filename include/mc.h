@@ -189,6 +189,20 @@ mc_status mc_grid_from_dims(const float* d_coords, int32_t dim, int64_t n_vertic
 mc_status mc_grid_from_spacing(const float* d_coords, int32_t dim, int64_t n_vertices,
                                const double spacing[3], hipStream_t stream, mc_grid* out);
 
+/* Grid by the paper's initialisation (Alg. 1, Sec. IV-C): the spacing of
+ * each axis is the k_percent-th percentile (nearest rank: the
+ * ceil(k N / 100)-th smallest, at least the first) of the N extents
+ * |p_a,d - p_b,d| (FP32) of every edge of every cell (3 per triangle, 6 per
+ * tetrahedron; an edge counts once per cell holding it); while
+ * (max_d - min_d) / spacing_d >= g_max, k rises by one point (at most to
+ * 100, else MC_ERR_ARG).  The grid spans the vertex bounding box with that
+ * spacing, dims = ceil((max - min) / spacing) + 1 (as
+ * mc_grid_from_spacing).  k_used (may be NULL) receives the final k per
+ * axis.  The percentile is an exact radix select on the GPU.  (sync) */
+mc_status mc_grid_from_percentile(const float* d_coords, const int32_t* d_cells, int32_t dim,
+                                  int64_t n_vertices, int64_t n_cells, double k_percent, int64_t g_max,
+                                  hipStream_t stream, mc_grid* out, double k_used[3]);
+
 /* Field-independent plan (the paper's reusable mesh-grid mapping, Sec.
  * IV-B/IV-C): a uniform bin index over the grid, the containing cell and
  * barycentric weights of every grid node, and the fill of nodes outside the

@@ -267,6 +267,111 @@ extern "C" mc_status mc_grid_from_spacing(const float* d_coords, int32_t dim, in
     return MC_OK;
 }
 
+// Exact k-th smallest (1-based rank r) FP32 edge extent along one axis by a
+// three-pass radix select; hist0 holds the first pass's histogram.
+static mc_status edge_select(const float* d_coords, const int32_t* d_cells, int dim, long long nv, long long nc,
+                             int axis, const std::vector<unsigned long long>& hist0, unsigned long long r,
+                             unsigned long long* d_hist, unsigned* d_bad, hipStream_t s, float* out)
+{
+    static const unsigned shifts[3] = {21u, 10u, 0u}, nbits[3] = {11u, 11u, 10u};
+    unsigned prefix = 0u, pmask = 0u;
+    std::vector<unsigned long long> h(2048);
+    for (int pass = 0; pass < 3; ++pass) {
+        const unsigned nb = 1u << nbits[pass];
+        if (pass == 0) {
+            h = hist0;
+        } else {
+            hipError_t e;
+            if ((e = hipMemsetAsync(d_hist, 0, sizeof(unsigned long long) * nb, s)) != hipSuccess ||
+                (e = mck::edge_hist(d_coords, d_cells, dim, nv, nc, axis, shifts[pass], nbits[pass], pmask, prefix,
+                                    d_hist, d_bad, s)) != hipSuccess ||
+                (e = hipMemcpyAsync(h.data(), d_hist, sizeof(unsigned long long) * nb, hipMemcpyDeviceToHost, s)) !=
+                    hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return mc_fail(MC_ERR_DEVICE, "edge histogram: %s", hipGetErrorString(e));
+        }
+        unsigned long long cum = 0;
+        unsigned b = 0;
+        for (; b < nb; ++b) {
+            if (cum + h[b] >= r) break;
+            cum += h[b];
+        }
+        if (b == nb) return mc_fail(MC_ERR_DEVICE, "edge histogram lost counts");
+        r -= cum;
+        prefix |= b << shifts[pass];
+        pmask |= (nb - 1u) << shifts[pass];
+    }
+    memcpy(out, &prefix, sizeof(float));
+    return MC_OK;
+}
+
+extern "C" mc_status mc_grid_from_percentile(const float* d_coords, const int32_t* d_cells, int32_t dim,
+                                             int64_t n_vertices, int64_t n_cells, double k_percent, int64_t g_max,
+                                             hipStream_t stream, mc_grid* out, double k_used[3])
+{
+    mc_status st = check_mesh_args(d_coords, dim, n_vertices);
+    if (st != MC_OK) return st;
+    if (!d_cells || !out) return mc_fail(MC_ERR_ARG, "cells/out pointer is NULL");
+    if (n_cells <= 0 || n_cells >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
+    if (!(k_percent >= 0.0) || !(k_percent <= 100.0)) return mc_fail(MC_ERR_ARG, "k_percent must be in [0, 100]");
+    if (g_max < 2) return mc_fail(MC_ERR_ARG, "g_max must be >= 2");
+    float lo[3], hi[3];
+    if ((st = device_bbox(d_coords, dim, n_vertices, stream, lo, hi)) != MC_OK) return st;
+    const unsigned long long N = (unsigned long long)n_cells * (dim == 2 ? 3u : 6u);
+    TempAllocs ta;
+    hipError_t e = hipSuccess;
+    unsigned long long* d_hist = ta.get<unsigned long long>(2048, e);
+    if (e != hipSuccess) return mc_fail(MC_ERR_NOMEM, "histogram: %s", hipGetErrorString(e));
+    unsigned* d_bad = ta.get<unsigned>(1, e);
+    if (e != hipSuccess) return mc_fail(MC_ERR_NOMEM, "flag: %s", hipGetErrorString(e));
+    if ((e = hipMemsetAsync(d_bad, 0, sizeof(unsigned), stream)) != hipSuccess)
+        return mc_fail(MC_ERR_DEVICE, "memset: %s", hipGetErrorString(e));
+    mc_grid g{};
+    g.dim = dim;
+    for (int d = 0; d < 3; ++d) {
+        g.dims[d] = 1;
+        g.origin[d] = 0.0;
+        g.spacing[d] = 1.0;
+        if (k_used) k_used[d] = 0.0;
+    }
+    for (int d = 0; d < dim; ++d) {
+        std::vector<unsigned long long> hist0(2048);
+        unsigned bad = 0;
+        if ((e = hipMemsetAsync(d_hist, 0, sizeof(unsigned long long) * 2048, stream)) != hipSuccess ||
+            (e = mck::edge_hist(d_coords, d_cells, dim, n_vertices, n_cells, d, 21u, 11u, 0u, 0u, d_hist, d_bad,
+                                stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(hist0.data(), d_hist, sizeof(unsigned long long) * 2048, hipMemcpyDeviceToHost,
+                                stream)) != hipSuccess ||
+            (e = hipMemcpyAsync(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return mc_fail(MC_ERR_DEVICE, "edge histogram: %s", hipGetErrorString(e));
+        if (bad) return mc_fail(MC_ERR_ARG, "cells reference a vertex id outside [0, n_vertices)");
+        const double extent = (double)hi[d] - (double)lo[d];
+        double k = k_percent, gs = 0.0;
+        for (;;) {
+            double r = std::ceil((k * (double)N) / 100.0);
+            if (r < 1.0) r = 1.0;
+            if (r > (double)N) r = (double)N;
+            float v;
+            if ((st = edge_select(d_coords, d_cells, dim, n_vertices, n_cells, d, hist0, (unsigned long long)r,
+                                  d_hist, d_bad, stream, &v)) != MC_OK)
+                return st;
+            gs = (double)v;
+            if (extent / gs < (double)g_max) break;          // also false when gs = 0
+            if (k >= 100.0) return mc_fail(MC_ERR_ARG, "axis %d: even the largest edge extent gives >= g_max nodes", d);
+            k = k + 1.0 > 100.0 ? 100.0 : k + 1.0;
+        }
+        double nd = std::ceil(extent / gs) + 1.0;
+        if (nd < 2.0) nd = 2.0;
+        g.dims[d] = (int64_t)nd;
+        g.origin[d] = (double)lo[d];
+        g.spacing[d] = gs;
+        if (k_used) k_used[d] = k;
+    }
+    *out = g;
+    return MC_OK;
+}
+
 mc_status mc_check_grid(const mc_grid* g, int32_t dim)
 {
     if (!g) return mc_fail(MC_ERR_ARG, "grid pointer is NULL");

@@ -107,6 +107,14 @@ hipError_t serial_codes(const void* x, int dtype, long long n, const DevBound* b
 hipError_t serial_decode(const uint16_t* codes, const int32_t* oidx, const void* oval, long long vcap,
                          const mc_result* res, long long n, int dtype, int2* agg, int* carry, void* out, hipStream_t s);
 
+// ---- grid initialisation (k_grid_init.hip) --------------------------------
+// Histogram (hist: 2^nbits u64 bins, zeroed by the caller) of bits
+// [shift, shift + nbits) of the FP32 edge extents along `axis` whose bits
+// under pmask equal pval; *bad |= 1 for a cell with an invalid vertex id.
+hipError_t edge_hist(const float* coords, const int32_t* cells, int dim, long long nv, long long nc, int axis,
+                     unsigned shift, unsigned nbits, unsigned pmask, unsigned pval, unsigned long long* hist,
+                     unsigned* bad, hipStream_t s);
+
 // ---- nearest-node g and cluster-mean f (k_cluster.hip) --------------------
 struct NodeGeom {
     double o[3], h[3];

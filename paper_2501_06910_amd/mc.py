@@ -102,6 +102,8 @@ _SIGS = {
     "mc_abi_version": (C.c_int32, []),
     "mc_grid_from_dims": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
     "mc_grid_from_spacing": (C.c_int, [_P, C.c_int32, C.c_int64, _P, _P, _P]),
+    "mc_grid_from_percentile": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, C.c_double, C.c_int64, _P, _P,
+                                          _P]),
     "mc_plan_create": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, _P, _P, _P]),
     "mc_plan_get_info": (C.c_int, [_P, _P]),
     "mc_plan_mapping": (C.c_int, [_P, _P, _P, _P, _P]),
@@ -227,6 +229,19 @@ def grid_from_spacing(coords, spacing) -> McGrid:
     _check(lib().mc_grid_from_spacing(_ptr(coords), coords.shape[0], coords.shape[1], h, _stream(),
                                       C.byref(g)), "mc_grid_from_spacing")
     return g
+
+
+def grid_from_percentile(coords, cells, k: float, g_max: int):
+    """The paper's grid initialisation (Alg. 1): (grid, k used per axis)."""
+    torch = _torch()
+    _require_cuda(coords, "coords", torch.float32)
+    _require_cuda(cells, "cells", torch.int32)
+    g = McGrid()
+    ku = (C.c_double * 3)()
+    _check(lib().mc_grid_from_percentile(_ptr(coords), _ptr(cells), coords.shape[0], coords.shape[1],
+                                         cells.shape[1], float(k), int(g_max), _stream(), C.byref(g), ku),
+           "mc_grid_from_percentile")
+    return g, [ku[0], ku[1], ku[2]]
 
 
 def make_grid(dim, dims, origin, spacing) -> McGrid:

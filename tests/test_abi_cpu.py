@@ -82,6 +82,10 @@ def test_host_validation_before_device_work():
     # batches
     assert lib.mc_batch_decompress(None, 1, None) == M.ERR_ARG
     assert lib.mc_batch_compress(fake, 0, None) == M.ERR_ARG
+    # grid initialisation
+    assert lib.mc_grid_from_percentile(None, fake, 2, 10, 10, 50.0, 100, None, C.byref(g), None) == M.ERR_ARG
+    assert lib.mc_grid_from_percentile(fake, fake, 2, 10, 10, 150.0, 100, None, C.byref(g), None) == M.ERR_ARG
+    assert lib.mc_grid_from_percentile(fake, fake, 2, 10, 10, 50.0, 1, None, C.byref(g), None) == M.ERR_ARG
     # operator pairs
     bad_ops = M.McPlanOpts(M.FILL_NEAREST, 0, 7)
     assert lib.mc_plan_create(fake, None, 2, 10, 0, C.byref(g), C.byref(bad_ops), None, C.byref(out)) == M.ERR_ARG
