@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c", "mco_grid_init.c"]
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c", "mco_grid_init.c", "mco_resdelta.c"]
 
 OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
 F32, F64 = 0, 1
@@ -99,6 +99,8 @@ def lib():
             "mco_grid_quantize_f64": (i32, [P, P, P, P, P, P, P, i64, P]),
             "mco_nearest_nodes": (None, [P, i32, i64, P, P]),
             "mco_grid_init": (i32, [P, P, i32, i64, i64, dbl, i64, P, P]),
+            "mco_residual_delta": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
+            "mco_vertex_decode_delta": (None, [P, P, P, i64, P, P, i32, i64, P]),
             "mco_cluster_mean": (None, [P, i32, i64, P, i64, dbl, P, P]),
             "mco_residual_nearest": (i32, [P, i32, i64, P, P, P, P, i32, P, P, P, i64, P]),
             "mco_vertex_decode_nearest": (None, [P, P, P, i64, P, P, P, i32, i64, P]),
@@ -363,6 +365,28 @@ def learned_codes(x: np.ndarray, gv: np.ndarray, b: Bound, rho_q: np.ndarray) ->
     return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy(), flags)
 
 
+def residual_delta(x: np.ndarray, gv: np.ndarray, b: Bound) -> VertexCodes:
+    """Residual codes with the 1-D Lorenzo predictor along the vertex order."""
+    nv = x.size
+    codes = np.empty(nv, np.uint16)
+    oi = np.empty(nv, np.int32)
+    ov = np.empty(nv, x.dtype)
+    n = C.c_int64(0)
+    st = lib().mco_residual_delta(_p(x), _dtype_code(x), nv, _p(np.ascontiguousarray(gv, np.float32)), _p(b),
+                                  _p(codes), _p(oi), _p(ov), nv, C.byref(n))
+    if st != OK:
+        raise OracleError(st, "residual_delta")
+    return VertexCodes(codes, oi[:n.value].copy(), ov[:n.value].copy())
+
+
+def vertex_decode_delta(vc: VertexCodes, gv, b: Bound, dtype) -> np.ndarray:
+    nv = vc.codes.size
+    out = np.empty(nv, dtype)
+    lib().mco_vertex_decode_delta(_p(vc.codes), _p(vc.out_idx), _p(vc.out_val), vc.out_idx.size,
+                                  _p(np.ascontiguousarray(gv, np.float32)), _p(b), _dtype_code(out), nv, _p(out))
+    return out
+
+
 def vertex_decode(vc: VertexCodes, gv, b: Bound, dtype, rho_q=None) -> np.ndarray:
     nv = vc.codes.size
     out = np.empty(nv, dtype)
@@ -388,21 +412,27 @@ class Compressed:
 
 
 def compress(coords, m: Mapping, g: Grid, x: np.ndarray, eb: float, relative: bool,
-             split: float, rho_q=None, mode: int = SPLIT_SUM) -> Compressed:
+             split: float, rho_q=None, mode: int = SPLIT_SUM, delta: bool = False) -> Compressed:
+    """delta: residual codes with the 1-D Lorenzo predictor (plain mode)."""
     b = bound(x, eb, relative, split, mode)
     v = resample(m, x, b.c)
     gc = grid_quantize(v, g, b)
     xhat = grid_recon(gc.p, b)
     gv = back_interp(coords, g, xhat)
-    vc = residual_quantize(x, gv, b) if rho_q is None else learned_codes(x, gv, b, rho_q)
+    if delta:
+        vc = residual_delta(x, gv, b)
+    else:
+        vc = residual_quantize(x, gv, b) if rho_q is None else learned_codes(x, gv, b, rho_q)
     return Compressed(b, gc, vc, xhat, gv, v)
 
 
 def decompress(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
-               rho_q=None) -> np.ndarray:
+               rho_q=None, delta: bool = False) -> np.ndarray:
     p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g)
     xhat = grid_recon(p, b)
     gv = back_interp(coords, g, xhat)
+    if delta:
+        return vertex_decode_delta(vc, gv, b, dtype)
     return vertex_decode(vc, gv, b, dtype, rho_q)
 
 

@@ -145,6 +145,13 @@ void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, co
                                const int32_t* m, const float* xhat, const mco_bound* b, int dtype, int64_t nv,
                                void* xout);
 
+/* Residuals with a 1-D Lorenzo predictor along the vertex order
+ * (mco_resdelta.c). */
+int mco_residual_delta(const void* x, int dtype, int64_t nv, const float* gv, const mco_bound* b, uint16_t* codes,
+                       int32_t* out_idx, void* out_val, int64_t cap, int64_t* n_out);
+void mco_vertex_decode_delta(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
+                             const float* gv, const mco_bound* b, int dtype, int64_t nv, void* xout);
+
 /* Grid initialisation, Alg. 1 (mco_grid_init.c): per-axis spacing = the
  * k-th percentile (nearest rank) of the cells' edge extents along the axis,
  * k raised by one point while (max - min) / spacing >= g_max.  k_used may be
