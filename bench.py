@@ -198,7 +198,7 @@ def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
 
 
 def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="full", operators="linear",
-                 residual="closed"):
+                 residual="closed", predictor="none"):
     """The same field at another setting of the CR sweep (default: the
     best one, a 128^3 grid, one node per ~8 vertices, with the full split
     tau2 = tau and the grid step from tau1 = 4 tau): CR, both directions'
@@ -208,7 +208,7 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     cells = torch.from_numpy(mesh.cells).cuda() if operators == "linear" else None
     plan = M.Plan(coords, cells, dims=(dims, dims, dims), operators=operators)
     del cells
-    codes = M.Codes(plan, x.dtype)
+    codes = M.Codes(plan, x.dtype, residual_predictor=predictor)
     out = torch.empty_like(x)
     kw = dict(split_mode=split_mode, residual=residual)
     M.compress(plan, x, eb, "rel", split, codes=codes, **kw)
@@ -232,7 +232,7 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     sb = M.stream_bytes(h, sT)
     ser = serial_compare(M, x, eb, h, (tc, td), log, f"{operators} {dims}^3, generated order")
     row = {"operators": operators, "grid": [dims] * 3, "split_mode": split_mode, "grid_share": split,
-           "residual": residual, "cr": round(nv * sT / sb["total"], 3),
+           "residual": residual, "residual_predictor": predictor, "cr": round(nv * sT / sb["total"], 3),
            "max_abs_err_over_tau": round(err / r["tau"], 4),
            "compress_GBps": round(nv * sT / (tc * 1e-3) / 1e9, 2),
            "decompress_GBps": round(nv * sT / (td * 1e-3) / 1e9, 2),
@@ -461,15 +461,19 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
         for gd in grids:
             plan = M.Plan(coords, cells if ops == "linear" else None, dims=(gd, gd, gd), operators=ops)
             codes = M.Codes(plan, x.dtype)
-            settings = [(m_, sp, "closed") for m_, sp in splits] if ops == "linear" else SWEEP_CLUSTER
+            settings = ([(m_, sp, "closed", "none") for m_, sp in splits] +
+                        [("full", 1.0, "closed", "delta"), ("full", 4.0, "closed", "delta")]) \
+                if ops == "linear" else [st + ("none",) for st in SWEEP_CLUSTER]
+            codes_d = M.Codes(plan, x.dtype, residual_predictor="delta") if ops == "linear" else None
             for eb in ebs:
-                for mode, sp, resid in settings:
-                    M.compress(plan, x, eb, "rel", sp, codes=codes, split_mode=mode, residual=resid)
-                    M.decompress(plan, codes, out=out)
-                    h = codes.host()
+                for mode, sp, resid, pred in settings:
+                    cc = codes_d if pred == "delta" else codes
+                    M.compress(plan, x, eb, "rel", sp, codes=cc, split_mode=mode, residual=resid)
+                    M.decompress(plan, cc, out=out)
+                    h = cc.host()
                     r = h["result"]
                     base = {"operators": ops, "grid": gd, "eb": eb, "split_mode": mode, "split": sp,
-                            "residual": resid}
+                            "residual": resid, "residual_predictor": pred}
                     if r["status"]:
                         rows.append(dict(base, status=r["status"]))
                         continue
@@ -482,14 +486,16 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
                     rows.append(dict(base, cr=round(cr, 3), bits_per_value=round(8 * sb["total"] / nv, 4),
                                      grid_bytes=sb["grid"], vert_bytes=sb["vert"],
                                      improvement_vs_serial=round(cr / s_gen, 3) if s_gen else None,
-                                     improvement_vs_serial_random_order=round(crr / s_rnd, 3) if s_rnd else None,
+                                     # renumbering changes delta codes: no exact figure from these codes
+                                     improvement_vs_serial_random_order=(round(crr / s_rnd, 3)
+                                                                         if s_rnd and pred == "none" else None),
                                      grid_outlier_rate=r["n_grid_outliers"] / plan.n_grid,
                                      vertex_outlier_rate=r["n_vertex_outliers"] / nv,
                                      linf_over_tau=round(d.max().item() / r["tau"], 4),
                                      rel_l2=float(torch.linalg.vector_norm(d).item() / norm)))
                     log(f"cr sweep: {rows[-1]}")
             plan.destroy()
-            del codes
+            del codes, codes_d
     return {"serial": {str(k): v for k, v in serial.items()}, "rows": rows}
 
 
@@ -809,6 +815,7 @@ def main():
                                                   shuffle_seed=7)]
     if args.workload == "tet3d" and not args.no_compare:
         line["design_points"] = [design_point(M, mesh, coords, x, args.eb, log),
+                                 design_point(M, mesh, coords, x, args.eb, log, predictor="delta"),
                                  design_point(M, mesh, coords, x, args.eb, log, split=0.1, split_mode="sum",
                                               operators="cluster", residual="open")]
     if not args.no_learned:

@@ -145,6 +145,17 @@ typedef struct {
     double kappa_unused;
 } mc_result;
 
+/* How vertex residual codes are formed.  MC_RESPRED_NONE: each vertex's
+ * quantised residual q on its own (code q + R).  MC_RESPRED_DELTA: the
+ * residuals serialised in vertex order through a 1-D Lorenzo predictor, as
+ * the paper's underlying compressors treat the serialised residual array
+ * (Sec. IV-B): code (q_i - q_{i-1}) + R with q_{-1} = 0; a vertex whose
+ * difference exceeds R - 1 (or whose reconstruction misses tau2) is stored
+ * raw and decoding restarts there from rint((raw - g) / (2 tau2)).
+ * MC_OPS_LINEAR plans without a learned model only (else MC_ERR_UNSUPPORTED).
+ * Decoding needs one more pass over the codes (tile aggregates). */
+typedef enum { MC_RESPRED_NONE = 0, MC_RESPRED_DELTA = 1 } mc_residual_predictor;
+
 /* Compressed representation (caller-allocated device buffers).
  *   grid_codes  uint16[n_grid]      code d + R of the Lorenzo error d, 0 = outlier
  *   g_out_idx   int32[g_out_cap]    grid outlier node ids, ascending
@@ -173,6 +184,7 @@ typedef struct {
     int32_t* dbg_grid_p;
     float* dbg_vertex_g;
     int32_t* rho_q;
+    int32_t residual_predictor;  /* mc_residual_predictor of vert_codes; the same for compress and decompress */
 } mc_codes;
 
 const char* mc_status_string(mc_status s);

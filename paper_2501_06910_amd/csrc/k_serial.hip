@@ -14,6 +14,7 @@
 //   k_ser_apply   p and x' of every value
 #include "mc_dev.h"
 #include "mc_kernels.h"
+#include "mc_seg.h"
 
 // Thread t of a tile codes its 4 consecutive values; p_{i-1} of its first
 // comes from the lane before (the wave's first lane loads it).  V: x is
@@ -100,31 +101,6 @@ __global__ __launch_bounds__(256) void k_ser_codes(const T* __restrict__ x, long
         if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
         count[tile] = c;
     }
-}
-
-// ---------------------------------------------------------------------------
-// segmented running sum: (f, v) = (restart seen, value); combining a then b
-// gives (a.f | b.f, b.f ? b.v : a.v + b.v); (0, 0) is neutral.
-struct Seg {
-    int f, v;
-};
-
-__device__ __forceinline__ Seg seg_op(Seg a, Seg b)
-{
-    return Seg{a.f | b.f, b.f ? b.v : a.v + b.v};
-}
-
-__device__ __forceinline__ Seg wave_seg_incl(Seg s)
-{
-    const int l = lane_id();
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        Seg o;
-        o.f = __shfl_up(s.f, d, 64);
-        o.v = __shfl_up(s.v, d, 64);
-        if (l >= d) s = seg_op(o, s);
-    }
-    return s;
 }
 
 // Index of outlier i in the ascending list (nout entries), or -1.
@@ -226,30 +202,6 @@ __device__ __forceinline__ void tile_seg_excl(const Seg (&sj)[MC_SER_SUB], Seg i
         ex[j] = seg_op(pre, e);
     }
     *total = run;
-}
-
-// Workgroup-wide exclusive segmented scan of one Seg per thread (NW waves),
-// started from `init`; *total receives init combined with every thread's.
-template <int NW>
-__device__ __forceinline__ Seg block_seg_excl(Seg s, Seg init, Seg* s_w, Seg* total)
-{
-    const int l = lane_id(), w = threadIdx.x >> 6;
-    const Seg inc = wave_seg_incl(s);
-    if (l == 63) s_w[w] = inc;
-    __syncthreads();
-    Seg pre = init, all = init;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-        const Seg a = s_w[k];
-        if (k < w) pre = seg_op(pre, a);
-        all = seg_op(all, a);
-    }
-    *total = all;
-    Seg ex;
-    ex.f = __shfl_up(inc.f, 1, 64);
-    ex.v = __shfl_up(inc.v, 1, 64);
-    if (l == 0) ex = Seg{0, 0};
-    return seg_op(pre, ex);
 }
 
 // Per-tile aggregate (restart seen, running value) of the codes.
@@ -361,6 +313,12 @@ hipError_t serial_codes(const void* x, int dtype, long long n, const DevBound* b
     if (dtype == MC_F64) { if (V) MC_SCK(double, true); else MC_SCK(double, false); }
     else { if (V) MC_SCK(float, true); else MC_SCK(float, false); }
 #undef MC_SCK
+    return hipGetLastError();
+}
+
+hipError_t seg_carry(const int2* agg, long long ntiles, int* carry, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ser_carry, dim3(1), dim3(MC_SER_CARRY_WG), 0, s, agg, ntiles, carry);
     return hipGetLastError();
 }
 

@@ -661,6 +661,8 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->gsum = p->bcost + 2 * p->nblk;
     p->vsum = p->gsum + ngg;
     PCHK(plan_alloc(p, &p->counts, (size_t)(p->ntg + p->ntv)));
+    PCHK(plan_alloc(p, &p->dagg, (size_t)p->ntv));
+    PCHK(plan_alloc(p, &p->dcarry, (size_t)p->ntv));
     p->gcount = p->counts;
     p->vcount = p->counts + p->ntg;
     decode_ws_shape(p);
@@ -733,6 +735,10 @@ extern "C" mc_status mc_plan_destroy(mc_plan p)
 static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
 {
     if (!c) return mc_fail(MC_ERR_ARG, "codes pointer is NULL");
+    if (c->residual_predictor != MC_RESPRED_NONE && c->residual_predictor != MC_RESPRED_DELTA)
+        return mc_fail(MC_ERR_ARG, "unknown residual predictor");
+    if (c->residual_predictor == MC_RESPRED_DELTA && (p->ops != MC_OPS_LINEAR || need_flags))
+        return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor needs an MC_OPS_LINEAR plan and no model");
     if (!c->grid_codes || !c->vert_codes || !c->result) return mc_fail(MC_ERR_ARG, "codes buffers are NULL");
     if (c->g_out_cap < 0 || c->v_out_cap < 0) return mc_fail(MC_ERR_ARG, "negative outlier capacity");
     if (c->g_out_cap > 0 && (!c->g_out_idx || !c->g_out_delta)) return mc_fail(MC_ERR_ARG, "grid outlier buffers are NULL");
@@ -752,7 +758,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     bp.relative = prm->eb_mode == MC_EB_REL;
     bp.mode = prm->split_mode;
     hipError_t e;
-#define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
+#define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     RangeOut* cur = p->rbuf;
     ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, bp, p->bound, p->small, p->nsmall, s));
     if (p->ops == MC_OPS_CLUSTER) {
@@ -781,8 +787,14 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         if (ms != MC_OK) return ms;
         rho = p->rho;
     }
-    ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, p->bcost, codes->vert_codes,
-                       codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
+    if (codes->residual_predictor == MC_RESPRED_DELTA) {
+        ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, codes->vert_codes,
+                                 codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
+    } else {
+        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, p->bcost,
+                           codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
+                           s));
+    }
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes, p->gcount,
                       p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
                       codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
@@ -839,7 +851,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
                                 hipStream_t s)
 {
     hipError_t e;
-#define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
+#define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
                           p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
                           p->dws, p->knobs, s));
@@ -853,6 +865,12 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
         mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);
         if (ms != MC_OK) return ms;
         rho = p->rho;
+    }
+    if (codes->residual_predictor == MC_RESPRED_DELTA) {
+        ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx,
+                                      codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,
+                                      dtype, s));
+        return MC_OK;
     }
     ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
                             codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, p->knobs, s));

@@ -17,6 +17,8 @@ struct mc_plan_s {
     int32_t* vlist = nullptr;      // vertices sorted by node, ascending ids within a node [nv]
     long long* noff = nullptr;     // node j's vertices: vlist[noff[j] .. noff[j+1]) [ng + 1]
     double* x1 = nullptr;          // cluster means of the current call [ng] (open loop)
+    int2* dagg = nullptr;          // residual delta decode: tile aggregates [ntv]
+    int* dcarry = nullptr;         // and their exclusive scan [ntv]
     // mapping (device)
     float* coords = nullptr;       // [dim][nv] copy
     int32_t* vid = nullptr;        // [dim+1][ng]

@@ -49,7 +49,7 @@ extern "C" mc_status mc_serial_create(int64_t n_max, mc_serial* out)
     const long long ngv = (s->ntiles + MC_SC_TILES - 1) / MC_SC_TILES;
     s->nsmall = 16 + ngv;
     hipError_t e;
-#define SCHK(x) if ((e = (x)) != hipSuccess) { mc_serial_destroy(s); return mc_fail(MC_ERR_NOMEM, "%s: %s", #x, hipGetErrorString(e)); }
+#define SCHK(x) do { if ((e = (x)) != hipSuccess) { mc_serial_destroy(s); return mc_fail(MC_ERR_NOMEM, "%s: %s", #x, hipGetErrorString(e)); } } while (0)
     SCHK(ser_alloc(s, &s->ctl, 64));
     SCHK(ser_alloc(s, &s->partial, (size_t)3 * MC_RANGE_BLOCKS));
     SCHK(ser_alloc(s, &s->small, (size_t)s->nsmall));
@@ -94,7 +94,7 @@ extern "C" mc_status mc_serial_compress(mc_serial s, const void* d_field, mc_dty
     unsigned int* err = s->small + 2;
     unsigned int* vsum = s->small + 16;
     hipError_t e;
-#define ECHK(x) if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e))
+#define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     ECHK(mck::range(d_field, dtype, n, s->partial, cur, bp, bound, s->small, s->nsmall, stream));
     ECHK(mck::serial_codes(d_field, dtype, n, bound, codes->vert_codes, s->count, vsum, err, codes->result, stream));
     ECHK(mck::compact(nullptr, 1, 1, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_field, dtype, n,
