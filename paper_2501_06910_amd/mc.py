@@ -578,17 +578,19 @@ class Model:
 
 def batch_compress(items):
     """items: list of (plan, field, eb, eb_mode, grid_share, model, codes[,
-    split_mode]).  The first call with a given list captures a HIP graph;
+    split_mode[, residual]]).  The first call with a given list captures a HIP graph;
     later calls with the same plans, tensors and parameters replay it."""
     arr = (McBatchItem * len(items))()
     for i, it in enumerate(items):
         plan, field, eb, mode, share, model, codes = it[:7]
         split = it[7] if len(it) > 7 else "sum"
+        resid = it[8] if len(it) > 8 else "closed"
         arr[i].plan = plan.handle
         arr[i].d_field = field.data_ptr()
         arr[i].dtype = _dtype_code(field)
         arr[i].params = McParams(eb, EB_REL if mode == "rel" else EB_ABS, share,
-                                 None if model is None else model.handle, _split_code(split))
+                                 None if model is None else model.handle, _split_code(split),
+                                 RESIDUAL_OPEN if resid == "open" else RESIDUAL_CLOSED)
         arr[i].codes = codes.struct
     _check(lib().mc_batch_compress(arr, len(items), _stream()), "mc_batch_compress")
 

@@ -153,3 +153,46 @@ def test_batch_rejects_bad_items(workload):
     with pytest.raises(RuntimeError, match="item 1"):
         M.batch_compress([(plans[0], xs[0], 1e-3, "rel", 0.5, None, codes),
                           (plans[0], xs[0], -1.0, "rel", 0.5, None, codes)])
+
+
+def test_batch_mixes_operator_pairs_and_residual_coders(workload):
+    """One graph over linear plans with plain and delta residual codes and
+    cluster plans (open loop): every item equals its single call, replays
+    included, and decompresses to the single call's values."""
+    meshes, grids, fields, plans, xs = workload
+    cplans = [M.Plan(dev(m.coords), None, dims=g[:2] if g[2] == 1 else g, operators="cluster")
+              for m, g in zip(meshes, grids)]
+    items, singles, codes = [], [], []
+    for i, f in enumerate(fields):
+        kind = i % 3
+        if kind == 0:
+            c = M.Codes(plans[f["mesh"]], xs[i].dtype, residual_predictor="delta")
+            items.append((plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], None, c))
+            singles.append(lambda i=i, f=f: M.compress(
+                plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"],
+                codes=M.Codes(plans[f["mesh"]], xs[i].dtype, residual_predictor="delta")))
+        elif kind == 1:
+            c = M.Codes(cplans[f["mesh"]], xs[i].dtype)
+            items.append((cplans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], None, c, "sum", "open"))
+            singles.append(lambda i=i, f=f: M.compress(cplans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"],
+                                                       residual="open"))
+        else:
+            c = M.Codes(plans[f["mesh"]], xs[i].dtype)
+            items.append((plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], None, c))
+            singles.append(lambda i=i, f=f: M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"]))
+        codes.append(c)
+    for rep in range(3):                                   # capture, then replays
+        for c in codes:
+            c.vert_codes.zero_()
+        M.batch_compress(items)
+        torch.cuda.synchronize()
+        for i, c in enumerate(codes):
+            ref = singles[i]()
+            same(c.host(), ref.host())
+            assert c.result_host()["status"] == 0
+            plan = items[i][0]
+            a, b = M.decompress(plan, c), M.decompress(plan, ref)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)
+    for p in cplans:
+        p.destroy()
