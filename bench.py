@@ -461,10 +461,10 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
         for gd in grids:
             plan = M.Plan(coords, cells if ops == "linear" else None, dims=(gd, gd, gd), operators=ops)
             codes = M.Codes(plan, x.dtype)
-            settings = ([(m_, sp, "closed", "none") for m_, sp in splits] +
-                        [("full", 1.0, "closed", "delta"), ("full", 4.0, "closed", "delta")]) \
-                if ops == "linear" else [st + ("none",) for st in SWEEP_CLUSTER]
-            codes_d = M.Codes(plan, x.dtype, residual_predictor="delta") if ops == "linear" else None
+            deltas = [("full", 1.0, "closed", "delta"), ("full", 4.0, "closed", "delta")]
+            settings = ([(m_, sp, "closed", "none") for m_, sp in splits] if ops == "linear"
+                        else [st + ("none",) for st in SWEEP_CLUSTER]) + deltas
+            codes_d = M.Codes(plan, x.dtype, residual_predictor="delta")
             for eb in ebs:
                 for mode, sp, resid, pred in settings:
                     cc = codes_d if pred == "delta" else codes

@@ -152,7 +152,9 @@ typedef struct {
  * (Sec. IV-B): code (q_i - q_{i-1}) + R with q_{-1} = 0; a vertex whose
  * difference exceeds R - 1 (or whose reconstruction misses tau2) is stored
  * raw and decoding restarts there from rint((raw - g) / (2 tau2)).
- * MC_OPS_LINEAR plans without a learned model only (else MC_ERR_UNSUPPORTED).
+ * Either operator pair (g = multilinear or nearest node), closed-loop
+ * residual, no learned model (else MC_ERR_UNSUPPORTED): the restart at a
+ * raw value needs the decoder-side reference x1'.
  * Decoding needs one more pass over the codes (tile aggregates). */
 typedef enum { MC_RESPRED_NONE = 0, MC_RESPRED_DELTA = 1 } mc_residual_predictor;
 

@@ -541,20 +541,32 @@ class ClusterCompressed:
 
 
 def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, split: float,
-                     open_loop: bool = True, mode: int = SPLIT_SUM) -> ClusterCompressed:
-    """Alg. 3 with the nearest-node g and the cluster-mean f."""
+                     open_loop: bool = True, mode: int = SPLIT_SUM, delta: bool = False) -> ClusterCompressed:
+    """Alg. 3 with the nearest-node g and the cluster-mean f; delta: the
+    closed-loop residuals through the 1-D Lorenzo predictor (g_k = x1'[m_k])."""
     b = bound(x, eb, relative, split, mode)
     m = nearest_nodes(coords, g)
     x1, cnt = cluster_mean(x, m, g.count, b.c)
     gc = grid_quantize_f64(x1, g, b)
-    vc = residual_nearest(x, m, x1, grid_recon(gc.p, b), b, open_loop)
+    xhat = grid_recon(gc.p, b)
+    if delta:
+        if open_loop:
+            raise ValueError("the delta residual predictor takes the closed loop")
+        vc = residual_delta(x, xhat[m], b)
+    else:
+        vc = residual_nearest(x, m, x1, xhat, b, open_loop)
     return ClusterCompressed(b, m, x1, cnt, gc, vc)
 
 
-def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype) -> np.ndarray:
+def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
+                       delta: bool = False) -> np.ndarray:
     """Alg. 4 with the nearest-node g."""
     p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g)
-    return vertex_decode_nearest(vc, nearest_nodes(coords, g), grid_recon(p, b), b, dtype)
+    m = nearest_nodes(coords, g)
+    xhat = grid_recon(p, b)
+    if delta:
+        return vertex_decode_delta(vc, xhat[m], b, dtype)
+    return vertex_decode_nearest(vc, m, xhat, b, dtype)
 
 
 def splitmix64(seed: int, counter: int) -> int:

@@ -4,6 +4,8 @@
 //   q_i = rint((x_i - g_i) / (2 tau2)), x'_i = (T)(g_i + q_i 2 tau2),
 //   code_i = (q_i - q_{i-1}) + R when |x_i - x'_i| <= tau2 and the
 //   difference is within R - 1, else 0 with x_i stored raw.
+// g is the multilinear back-interpolation (the linear pair) or the value of
+// the vertex's nearest node (the paper's pair, closed loop).
 // Compression keeps the usual tile layout (vertex tile*1024 + i*256 + t) and
 // stages the tile's q in LDS to take the differences; the vertex before a
 // tile is back-interpolated once more by the tile's first thread.
@@ -16,9 +18,28 @@
 #include "mc_kernels.h"
 #include "mc_seg.h"
 
-template <typename T, int D>
+// g of N vertices: multilinear back-interpolation (the linear pair) or the
+// nearest node's value (the paper's pair, m = node of every vertex).
+template <int D, bool NEAR, int N>
+__device__ __forceinline__ void g_of(const float* __restrict__ coords, long long nv, const GridGeom& gg,
+                                     const float* __restrict__ xh, const int32_t* __restrict__ m,
+                                     const long long (&v)[N], const bool (&act)[N], float (&g)[N])
+{
+    if (NEAR) {
+        int32_t j[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) j[i] = m[act[i] ? v[i] : 0];
+#pragma unroll
+        for (int i = 0; i < N; ++i) g[i] = xh[j[i]];
+    } else {
+        back_interp_n<D, N>(coords, nv, gg, xh, v, act, g);
+    }
+}
+
+template <typename T, int D, bool NEAR>
 __global__ __launch_bounds__(256) void k_residual_delta(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                        const float* __restrict__ xh, const T* __restrict__ x,
+                                                        const float* __restrict__ xh, const int32_t* __restrict__ m,
+                                                        const T* __restrict__ x,
                                                         const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
                                                         float* __restrict__ dbg_g, unsigned int* __restrict__ count,
                                                         unsigned int* __restrict__ vsum, unsigned int* __restrict__ err)
@@ -38,7 +59,7 @@ __global__ __launch_bounds__(256) void k_residual_delta(const float* __restrict_
         xv[i] = x[act[i] ? v[i] : 0];
     }
     float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    g_of<D, NEAR, MC_IPT>(coords, nv, gg, xh, m, v, act, g);
     int q[MC_IPT];
     bool ok[MC_IPT];
     bool range_bad = false;
@@ -59,7 +80,7 @@ __global__ __launch_bounds__(256) void k_residual_delta(const float* __restrict_
             const long long vb[1] = {tile * MC_TILE - 1};
             const bool ab[1] = {true};
             float gb[1];
-            back_interp_n<D, 1>(coords, nv, gg, xh, vb, ab, gb);
+            g_of<D, NEAR, 1>(coords, nv, gg, xh, m, vb, ab, gb);
             const double s = ((double)x[vb[0]] - (double)gb[0]) * b.inv2;
             qb = fabs(s) < 134217728.0 ? (int)rint(s) : 0;
         }
@@ -100,9 +121,10 @@ __device__ __forceinline__ long long rd_find(const int32_t* __restrict__ oidx, l
 
 // Raw value and restart q of a code-0 vertex (g computed here: such
 // vertices are rare).
-template <typename T, int D>
+template <typename T, int D, bool NEAR>
 __device__ __forceinline__ int restart_q(const float* __restrict__ coords, long long nv, const GridGeom& gg,
-                                         const float* __restrict__ xh, const int32_t* __restrict__ oidx,
+                                         const float* __restrict__ xh, const int32_t* __restrict__ m,
+                                         const int32_t* __restrict__ oidx,
                                          const T* __restrict__ oval, long long nout, long long vtx, double inv2,
                                          const float* g_known, T* raw_out)
 {
@@ -115,7 +137,7 @@ __device__ __forceinline__ int restart_q(const float* __restrict__ coords, long 
         const long long vb[1] = {vtx};
         const bool ab[1] = {true};
         float gb[1];
-        back_interp_n<D, 1>(coords, nv, gg, xh, vb, ab, gb);
+        g_of<D, NEAR, 1>(coords, nv, gg, xh, m, vb, ab, gb);
         g = gb[0];
     }
     if (raw_out) *raw_out = raw;
@@ -125,9 +147,10 @@ __device__ __forceinline__ int restart_q(const float* __restrict__ coords, long 
 // Segments of the tile in vertex order: element e of the tile is vertex
 // tile*1024 + e, owned by thread e % 256 (slot e / 256); thread t folds
 // elements 4t..4t+3 from LDS.
-template <typename T, int D>
+template <typename T, int D, bool NEAR>
 __global__ __launch_bounds__(256) void k_resd_tot(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                  const float* __restrict__ xh, const uint16_t* __restrict__ codes,
+                                                  const float* __restrict__ xh, const int32_t* __restrict__ m,
+                                                  const uint16_t* __restrict__ codes,
                                                   const int32_t* __restrict__ oidx, const T* __restrict__ oval,
                                                   const mc_result* __restrict__ res, long long vcap,
                                                   int2* __restrict__ agg)
@@ -148,7 +171,7 @@ __global__ __launch_bounds__(256) void k_resd_tot(const float* __restrict__ coor
         const long long vi = tile * MC_TILE + i * MC_WG + threadIdx.x;
         Seg sg{0, code[i] - MC_R};
         if (code[i] == 0)
-            sg = Seg{1, restart_q<T, D>(coords, nv, gg, xh, oidx, oval, nout, vi, inv2, nullptr, nullptr)};
+            sg = Seg{1, restart_q<T, D, NEAR>(coords, nv, gg, xh, m, oidx, oval, nout, vi, inv2, nullptr, nullptr)};
         s_seg[i * MC_WG + threadIdx.x] = sg;
     }
     __syncthreads();
@@ -160,9 +183,9 @@ __global__ __launch_bounds__(256) void k_resd_tot(const float* __restrict__ coor
     if (threadIdx.x == 0) agg[tile] = make_int2(total.f, total.v);
 }
 
-template <typename T, int D>
+template <typename T, int D, bool NEAR>
 __global__ __launch_bounds__(256) void k_vdecode_delta(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                       const float* __restrict__ xh,
+                                                       const float* __restrict__ xh, const int32_t* __restrict__ m,
                                                        const uint16_t* __restrict__ codes,
                                                        const int32_t* __restrict__ oidx, const T* __restrict__ oval,
                                                        const mc_result* __restrict__ res, long long vcap,
@@ -183,13 +206,14 @@ __global__ __launch_bounds__(256) void k_vdecode_delta(const float* __restrict__
         code[i] = act[i] ? (int)codes[v[i]] : MC_R;
     }
     float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    g_of<D, NEAR, MC_IPT>(coords, nv, gg, xh, m, v, act, g);
     T raw[MC_IPT];
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
         Seg sg{0, code[i] - MC_R};
         raw[i] = (T)0;
-        if (code[i] == 0) sg = Seg{1, restart_q<T, D>(coords, nv, gg, xh, oidx, oval, nout, v[i], inv2, &g[i], &raw[i])};
+        if (code[i] == 0)
+            sg = Seg{1, restart_q<T, D, NEAR>(coords, nv, gg, xh, m, oidx, oval, nout, v[i], inv2, &g[i], &raw[i])};
         s_seg[i * MC_WG + threadIdx.x] = sg;
     }
     __syncthreads();
@@ -219,21 +243,25 @@ __global__ __launch_bounds__(256) void k_vdecode_delta(const float* __restrict__
 
 namespace mck {
 
-hipError_t residual_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                          const DevBound* bnd, uint16_t* codes, float* dbg_g, unsigned* count, unsigned* vsum,
-                          unsigned* err, hipStream_t s)
+hipError_t residual_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* m,
+                          const void* x, int dtype, const DevBound* bnd, uint16_t* codes, float* dbg_g,
+                          unsigned* count, unsigned* vsum, unsigned* err, hipStream_t s)
 {
     ProfScope ps("k_residual_delta", s);
     const dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
-#define MC_RD(T, D) hipLaunchKernelGGL((k_residual_delta<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, \
-                                       (const T*)x, bnd, codes, dbg_g, count, vsum, err)
-    if (dtype == MC_F64) { if (gg.dim == 2) MC_RD(double, 2); else MC_RD(double, 3); }
-    else { if (gg.dim == 2) MC_RD(float, 2); else MC_RD(float, 3); }
+#define MC_RD(T, D, NR) hipLaunchKernelGGL((k_residual_delta<T, D, NR>), grid, dim3(256), 0, s, coords, nv, gg, xh, \
+                                           m, (const T*)x, bnd, codes, dbg_g, count, vsum, err)
+#define MC_RD2(T) do { if (m) MC_RD(T, 3, true); else if (gg.dim == 2) MC_RD(T, 2, false); \
+                       else MC_RD(T, 3, false); } while (0)
+    if (dtype == MC_F64) MC_RD2(double);
+    else MC_RD2(float);
+#undef MC_RD2
 #undef MC_RD
     return hipGetLastError();
 }
 
-hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
+hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* m,
+                               const uint16_t* codes,
                                const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
                                int2* agg, int* carry, void* xout, int dtype, hipStream_t s)
 {
@@ -242,10 +270,13 @@ hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, c
     hipError_t e;
     {
         ProfScope ps("k_resd_tot", s);
-#define MC_RT(T, D) hipLaunchKernelGGL((k_resd_tot<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, oidx, \
-                                       (const T*)oval, res, vcap, agg)
-        if (dtype == MC_F64) { if (gg.dim == 2) MC_RT(double, 2); else MC_RT(double, 3); }
-        else { if (gg.dim == 2) MC_RT(float, 2); else MC_RT(float, 3); }
+#define MC_RT(T, D, NR) hipLaunchKernelGGL((k_resd_tot<T, D, NR>), grid, dim3(256), 0, s, coords, nv, gg, xh, m, codes, \
+                                           oidx, (const T*)oval, res, vcap, agg)
+#define MC_RT2(T) do { if (m) MC_RT(T, 3, true); else if (gg.dim == 2) MC_RT(T, 2, false); \
+                       else MC_RT(T, 3, false); } while (0)
+        if (dtype == MC_F64) MC_RT2(double);
+        else MC_RT2(float);
+#undef MC_RT2
 #undef MC_RT
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
@@ -254,10 +285,13 @@ hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, c
         if ((e = seg_carry(agg, ntiles, carry, s)) != hipSuccess) return e;
     }
     ProfScope ps("k_vdecode_delta", s);
-#define MC_VD(T, D) hipLaunchKernelGGL((k_vdecode_delta<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, \
-                                       oidx, (const T*)oval, res, vcap, carry, (T*)xout)
-    if (dtype == MC_F64) { if (gg.dim == 2) MC_VD(double, 2); else MC_VD(double, 3); }
-    else { if (gg.dim == 2) MC_VD(float, 2); else MC_VD(float, 3); }
+#define MC_VD(T, D, NR) hipLaunchKernelGGL((k_vdecode_delta<T, D, NR>), grid, dim3(256), 0, s, coords, nv, gg, xh, m, \
+                                           codes, oidx, (const T*)oval, res, vcap, carry, (T*)xout)
+#define MC_VD2(T) do { if (m) MC_VD(T, 3, true); else if (gg.dim == 2) MC_VD(T, 2, false); \
+                       else MC_VD(T, 3, false); } while (0)
+    if (dtype == MC_F64) MC_VD2(double);
+    else MC_VD2(float);
+#undef MC_VD2
 #undef MC_VD
     return hipGetLastError();
 }

@@ -737,8 +737,8 @@ static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
     if (!c) return mc_fail(MC_ERR_ARG, "codes pointer is NULL");
     if (c->residual_predictor != MC_RESPRED_NONE && c->residual_predictor != MC_RESPRED_DELTA)
         return mc_fail(MC_ERR_ARG, "unknown residual predictor");
-    if (c->residual_predictor == MC_RESPRED_DELTA && (p->ops != MC_OPS_LINEAR || need_flags))
-        return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor needs an MC_OPS_LINEAR plan and no model");
+    if (c->residual_predictor == MC_RESPRED_DELTA && need_flags)
+        return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor takes no learned model");
     if (!c->grid_codes || !c->vert_codes || !c->result) return mc_fail(MC_ERR_ARG, "codes buffers are NULL");
     if (c->g_out_cap < 0 || c->v_out_cap < 0) return mc_fail(MC_ERR_ARG, "negative outlier capacity");
     if (c->g_out_cap > 0 && (!c->g_out_idx || !c->g_out_delta)) return mc_fail(MC_ERR_ARG, "grid outlier buffers are NULL");
@@ -767,8 +767,13 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                                codes->dbg_resampled, p->err, codes->result, p->gcount, p->ntg, s));
         ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
                           codes->grid_codes, p->gcount, p->gsum, p->knobs, s));
-        ECHK(mck::residual_nearest(p->m, p->nv, d_field, dtype, x1, p->xh, p->bound, codes->vert_codes,
-                                   codes->dbg_vertex_g, p->vcount, p->vsum, s));
+        if (codes->residual_predictor == MC_RESPRED_DELTA) {
+            ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, p->m, d_field, dtype, p->bound,
+                                     codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
+        } else {
+            ECHK(mck::residual_nearest(p->m, p->nv, d_field, dtype, x1, p->xh, p->bound, codes->vert_codes,
+                                       codes->dbg_vertex_g, p->vcount, p->vsum, s));
+        }
         ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes,
                           p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype,
                           p->nv, codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val,
@@ -788,8 +793,8 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         rho = p->rho;
     }
     if (codes->residual_predictor == MC_RESPRED_DELTA) {
-        ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, codes->vert_codes,
-                                 codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
+        ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, nullptr, d_field, dtype, p->bound,
+                                 codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
     } else {
         ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, p->bcost,
                            codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
@@ -825,6 +830,8 @@ mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const 
         return mc_fail(MC_ERR_UNSUPPORTED, "the open-loop residual needs an MC_OPS_CLUSTER plan and MC_SPLIT_SUM");
     if (prm->model && p->ops != MC_OPS_LINEAR)
         return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
+    if (codes && codes->residual_predictor == MC_RESPRED_DELTA && prm->residual == MC_RESIDUAL_OPEN)
+        return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor needs the closed loop");
     return check_codes(p, codes, prm->model != nullptr);
 }
 
@@ -855,6 +862,12 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
     ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
                           p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
                           p->dws, p->knobs, s));
+    if (p->ops == MC_OPS_CLUSTER && codes->residual_predictor == MC_RESPRED_DELTA) {
+        ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, p->m, codes->vert_codes, codes->v_out_idx,
+                                      codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,
+                                      dtype, s));
+        return MC_OK;
+    }
     if (p->ops == MC_OPS_CLUSTER) {
         ECHK(mck::vertex_decode_nearest(p->m, p->nv, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
                                         codes->v_out_cap, codes->result, d_out, dtype, s));
@@ -867,7 +880,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
         rho = p->rho;
     }
     if (codes->residual_predictor == MC_RESPRED_DELTA) {
-        ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx,
+        ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, nullptr, codes->vert_codes, codes->v_out_idx,
                                       codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,
                                       dtype, s));
         return MC_OK;

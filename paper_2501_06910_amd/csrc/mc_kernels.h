@@ -108,11 +108,13 @@ hipError_t serial_decode(const uint16_t* codes, const int32_t* oidx, const void*
                          const mc_result* res, long long n, int dtype, int2* agg, int* carry, void* out, hipStream_t s);
 
 // ---- residual codes with the 1-D Lorenzo predictor (k_resdelta.hip) -------
-hipError_t residual_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                          const DevBound* bnd, uint16_t* codes, float* dbg_g, unsigned* count, unsigned* vsum,
-                          unsigned* err, hipStream_t s);
+// m == NULL: g by multilinear back-interpolation; else g = xh[m[v]] (nearest node)
+hipError_t residual_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* m,
+                          const void* x, int dtype, const DevBound* bnd, uint16_t* codes, float* dbg_g,
+                          unsigned* count, unsigned* vsum, unsigned* err, hipStream_t s);
 // agg: int2[ceil(nv / MC_TILE)], carry: int[ceil(nv / MC_TILE)]
-hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
+hipError_t vertex_decode_delta(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* m,
+                               const uint16_t* codes,
                                const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
                                int2* agg, int* carry, void* xout, int dtype, hipStream_t s);
 // exclusive segmented scan of tile aggregates from a restart at 0 (k_serial.hip)

@@ -70,10 +70,35 @@ def test_delta_codes_and_roundtrip(name, mesh, x, dims, eb, rel, split, mode):
     print(f"[resdelta] {name}: {oc.vert.out_idx.size} raw vertices, {(plan.n_vertices + 1023) // 1024} tiles")
 
 
-def test_delta_rejected_with_model_or_cluster():
+@pytest.mark.parametrize("name,mesh,x,dims,eb,rel,split,mode", CASES, ids=[c[0] for c in CASES])
+def test_delta_codes_cluster_pair(name, mesh, x, dims, eb, rel, split, mode):
+    """The paper's pair (nearest-node g, cluster-mean f), closed loop."""
+    print(f"[resdelta] cluster {name}", flush=True)
+    og = O.grid_from_dims(mesh.coords, dims)
+    oc = O.compress_cluster(mesh.coords, og, x, eb, rel, split, False,
+                            O.SPLIT_FULL if mode == "full" else O.SPLIT_SUM, delta=True)
+    plan = M.Plan(dev(mesh.coords), None, dims=dims, operators="cluster")
+    xt = dev(x)
+    codes = M.Codes(plan, xt.dtype, residual_predictor="delta")
+    M.compress(plan, xt, eb, "rel" if rel else "abs", split, codes=codes, split_mode=mode)
+    out = M.decompress(plan, codes)
+    torch.cuda.synchronize()
+    h = codes.host()
+    assert h["result"]["status"] == 0
+    assert np.array_equal(h["grid_codes"], oc.grid.codes)
+    assert np.array_equal(h["vert_codes"], oc.vert.codes)
+    assert np.array_equal(h["v_out_idx"], oc.vert.out_idx)
+    assert np.array_equal(h["v_out_val"].view(np.uint8), oc.vert.out_val.view(np.uint8))
+    xo = O.decompress_cluster(mesh.coords, og, oc.bound, oc.grid, oc.vert, x.dtype, delta=True)
+    xg = out.cpu().numpy()
+    assert np.array_equal(xg.view(np.uint8), xo.view(np.uint8))
+    assert np.all(np.abs(x.astype(np.float64) - xg.astype(np.float64)) <= oc.bound.tau2)
+
+
+def test_delta_rejected_with_open_loop():
     mesh = G.kuhn_tet_mesh(9, 2)
     x = dev(G.field_octaves(mesh.coords, np.random.default_rng(6)))
     cl = M.Plan(dev(mesh.coords), None, dims=(8, 8, 8), operators="cluster")
     with pytest.raises(M.McError) as e:
-        M.compress(cl, x, 1e-3, codes=M.Codes(cl, x.dtype, residual_predictor="delta"))
+        M.compress(cl, x, 1e-3, codes=M.Codes(cl, x.dtype, residual_predictor="delta"), residual="open")
     assert e.value.status == M.ERR_UNSUPPORTED

@@ -77,3 +77,14 @@ def test_pipeline_bound(eb, split, mode):
     cz = O.compress(mesh.coords, m, g, x, eb, True, split, mode=mode, delta=True)
     xr = O.decompress(mesh.coords, g, cz.bound, cz.grid, cz.vert, x.dtype, delta=True)
     assert np.all(np.abs(x.astype(np.float64) - xr.astype(np.float64)) <= cz.bound.tau2)
+
+
+def test_cluster_pair_closed_loop_bound():
+    mesh = G.kuhn_tet_mesh(9, 2)
+    x = G.field_octaves(mesh.coords, np.random.default_rng(7))
+    g = O.grid_from_dims(mesh.coords, (5, 6, 4))
+    cz = O.compress_cluster(mesh.coords, g, x, 1e-4, True, 2.0, False, O.SPLIT_FULL, delta=True)
+    xr = O.decompress_cluster(mesh.coords, g, cz.bound, cz.grid, cz.vert, x.dtype, delta=True)
+    assert np.all(np.abs(x.astype(np.float64) - xr.astype(np.float64)) <= cz.bound.tau)
+    with pytest.raises(ValueError):
+        O.compress_cluster(mesh.coords, g, x, 1e-4, True, 0.5, True, delta=True)
