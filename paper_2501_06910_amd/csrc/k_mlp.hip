@@ -132,6 +132,7 @@ template <int D> struct LdsFrag {
     bf16x8 w1[4 * (MlpShape<D>::KB / 2) * 64];
     bf16x8 w2[8 * 64];
     bf16x8 w3[8 * 64];
+    bf16x8 w4f[2 * 64];          // the head as a 16 x 64 A operand: row 0 = W4, rows 1..15 zero
     float b1[HID], b2[HID], b3[HID], w4[HID];
     float b4;
 };
@@ -164,6 +165,17 @@ __device__ void load_frag(LdsFrag<D>& s, const mck::MlpDev& m)
         s.b2[i] = m.b2[i];
         s.b3[i] = m.b3[i];
         s.w4[i] = bf2f(m.w4[i]);
+    }
+    for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) {
+        const int l = i & 63, c = i >> 6, g = l >> 4;
+        typedef short s8 __attribute__((ext_vector_type(8)));
+        s8 r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            r[k] = (l & 15) == 0 ? (short)m.w4[32 * c + 4 * g + k] : (short)0;
+            r[4 + k] = (l & 15) == 0 ? (short)m.w4[32 * c + 16 + 4 * g + k] : (short)0;
+        }
+        s.w4f[i] = __builtin_bit_cast(bf16x8, r);
     }
     if (threadIdx.x == 0) s.b4 = m.b4[0];
     __syncthreads();
@@ -362,9 +374,12 @@ __device__ __forceinline__ void hidden_layer_f(const bf16x8* wf, const float* b,
         for (int c = 0; c < KC; ++c) bin[nb][c] = cat8(in[nb][2 * c], in[nb][2 * c + 1]);
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
+        // the bias starts the accumulation (one rounding order among others:
+        // the forward pass is compared with a tolerance)
+        const f32x4 bias = (f32x4){b[mb * 16 + g4], b[mb * 16 + g4 + 1], b[mb * 16 + g4 + 2], b[mb * 16 + g4 + 3]};
         f32x4 acc[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        for (int nb = 0; nb < 4; ++nb) acc[nb] = bias;
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
             const bf16x8 a = wf[(mb * KC + c) * 64 + l];
@@ -375,12 +390,25 @@ __device__ __forceinline__ void hidden_layer_f(const bf16x8* wf, const float* b,
         for (int nb = 0; nb < 4; ++nb) {
             float h[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = acc[nb][i] + b[mb * 16 + g4 + i];
-                h[i] = x > 0.0f ? x : 0.0f;
-            }
+            for (int i = 0; i < 4; ++i) h[i] = acc[nb][i] > 0.0f ? acc[nb][i] : 0.0f;
             out[nb][mb] = pack4(h[0], h[1], h[2], h[3]);
         }
+    }
+}
+
+// Head on the matrix cores: W4 as row 0 of a 16 x 64 A operand (the other
+// rows zero), two K = 32 instructions per column block; rho of vertex
+// nb*16 + c sits in lane c, element 0, and is broadcast to every lane.
+__device__ __forceinline__ void head_f(const bf16x8* w4f, float b4, const bf16x4 (&h3)[4][4], float (&rho)[4])
+{
+    const int l = lane_id();
+    const bf16x8 a0 = w4f[l], a1 = w4f[64 + l];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        f32x4 acc = (f32x4){b4, b4, b4, b4};
+        acc = mfma32(a0, cat8(h3[nb][0], h3[nb][1]), acc);
+        acc = mfma32(a1, cat8(h3[nb][2], h3[nb][3]), acc);
+        rho[nb] = __shfl(acc[0], l & 15, 64);
     }
 }
 
@@ -425,7 +453,7 @@ __device__ __forceinline__ void forward_f(const LdsFrag<D>& sw, const bf16x4 (&z
     hidden_layer_f<MlpShape<D>::KB>(sw.w1, sw.b1, zf, h1);
     hidden_layer_f<4>(sw.w2, sw.b2, h1, h2);
     hidden_layer_f<4>(sw.w3, sw.b3, h2, h3);
-    head(sw.w4, sw.b4, h3, rho);
+    head_f(sw.w4f, sw.b4, h3, rho);
 }
 
 __device__ __forceinline__ int rho_quant(float r)
