@@ -96,6 +96,14 @@ int mco_grid_decode(const uint16_t* codes, const int32_t* out_idx, const int32_t
                     int64_t n_out, const mco_grid* g, int32_t* p);
 void mco_lorenzo(const int32_t* p, const mco_grid* g, int64_t* delta);
 
+/* Multilevel interpolation predictor on the prequantised grid
+ * (mco_interp.c): cubic = 0 linear, 1 cubic; same code format. */
+void mco_interp_delta(const int32_t* p, const mco_grid* g, int cubic, int64_t* delta);
+int mco_interp_codes(const int32_t* p, const mco_grid* g, int cubic, uint16_t* codes, int32_t* out_idx,
+                     int32_t* out_delta, int64_t cap, int64_t* n_out);
+int mco_interp_decode(const uint16_t* codes, const int32_t* out_idx, const int32_t* out_delta, int64_t n_out,
+                      const mco_grid* g, int cubic, int32_t* p);
+
 /* ---- residual compressor ------------------------------------------------ */
 int mco_residual_quantize(const void* x, int dtype, int64_t nv, const float* gv,
                           const mco_bound* b, uint16_t* codes, int32_t* out_idx,
