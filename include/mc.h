@@ -158,10 +158,34 @@ typedef struct {
  * Decoding needs one more pass over the codes (tile aggregates). */
 typedef enum { MC_RESPRED_NONE = 0, MC_RESPRED_DELTA = 1 } mc_residual_predictor;
 
+/* How grid codes are formed from the prequantised grid p (the grid
+ * compressor C(x1) may be any error-controlled compressor, Sec. IV-D; the
+ * SZ family's predictors, Sec. II, include Lorenzo and interpolation).
+ * The bound tau1, p, x1' and the vertex codes do not depend on the choice.
+ * MC_GRIDPRED_LORENZO: the Lorenzo predictor (zeros outside the grid).
+ * MC_GRIDPRED_INTERP_LINEAR / _CUBIC: multilevel interpolation.  With L
+ * the least integer such that 2^L >= n_d on every axis, strides
+ * s = 2^(L-1) .. 1; the origin is predicted by 0; any other node is in
+ * class (s, a): s = 2^t, t the fewest trailing zero bits among its
+ * non-zero coordinates, a the highest axis whose coordinate is non-zero
+ * with t trailing zeros.  Its prediction along a, from the nodes at -s,
+ * +s (and -3s, +3s), all of earlier classes:
+ *   +s outside the grid:          p[-s]
+ *   CUBIC, -3s and +3s inside:    floor((-p[-3s] + 9 p[-s] + 9 p[+s] - p[+3s] + 8) / 16)
+ *   otherwise:                    floor((p[-s] + p[+s]) / 2)
+ * Decoding visits the origin, then the classes s = 2^(L-1) .. 1, and
+ * a = 0 .. D-1 within a stride: one launch per fine class, the coarse
+ * classes in one workgroup.  Unknown values: MC_ERR_ARG. */
+typedef enum {
+    MC_GRIDPRED_LORENZO = 0,
+    MC_GRIDPRED_INTERP_LINEAR = 1,
+    MC_GRIDPRED_INTERP_CUBIC = 2
+} mc_grid_predictor;
+
 /* Compressed representation (caller-allocated device buffers).
- *   grid_codes  uint16[n_grid]      code d + R of the Lorenzo error d, 0 = outlier
+ *   grid_codes  uint16[n_grid]      code d + R of the grid prediction error d, 0 = outlier
  *   g_out_idx   int32[g_out_cap]    grid outlier node ids, ascending
- *   g_out_delta int32[g_out_cap]    their Lorenzo errors
+ *   g_out_delta int32[g_out_cap]    their prediction errors
  *   vert_codes  uint16[n_vertices]  residual code q + R (learned: q - rho_q + R), 0 = outlier
  *   v_out_idx   int32[v_out_cap]    vertex outlier ids, ascending
  *   v_out_val   T[v_out_cap]        their raw values (T = field dtype)
@@ -187,6 +211,7 @@ typedef struct {
     float* dbg_vertex_g;
     int32_t* rho_q;
     int32_t residual_predictor;  /* mc_residual_predictor of vert_codes; the same for compress and decompress */
+    int32_t grid_predictor;      /* mc_grid_predictor of grid_codes; the same for compress and decompress */
 } mc_codes;
 
 const char* mc_status_string(mc_status s);

@@ -14,6 +14,7 @@
 //                    blocks where it is cheaper, per-tile outlier counts
 //   k_scatter        outlier lists in index order (wave ballots)
 #include "mc_dev.h"
+#include "mc_interp.h"
 #include "mc_kernels.h"
 
 // ---------------------------------------------------------------------------
@@ -555,11 +556,11 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
 // MC_SC_TILES tiles (grid groups first, then vertex groups): a group with
 // any outlier sums the group totals before it (its list offset), scans its
 // own tile counts, and ranks each tile's code-0 items with wave ballots.
-// Grid outliers get their Lorenzo error recomputed, vertex outliers the raw
-// value.  Block 0 also writes the list totals, the count of learned blocks
+// Grid outliers get their prediction error (Lorenzo or interpolation)
+// recomputed, vertex outliers the raw value.  Block 0 also writes the list totals, the count of learned blocks
 // and the final status (capacity overflows included).
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng,
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng, int gpred,
                                                  const uint16_t* __restrict__ gcodes,
                                                  const unsigned int* __restrict__ gcount,
                                                  const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
@@ -674,8 +675,11 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
             } else if (pos < gcap) {
                 const int i0 = (int)(j % n0);
                 const long long r = j / n0;
+                const int i1 = (int)(r % n1), i2 = (int)(r / n1), n2 = (int)(ng / n01);
                 gidx[pos] = (int32_t)j;
-                gdelta[pos] = (int32_t)lorenzo_delta<D>(p, j, i0, (int)(r % n1), (int)(r / n1), n0, n01);
+                gdelta[pos] = (int32_t)(gpred == MC_GRIDPRED_LORENZO ? lorenzo_delta<D>(p, j, i0, i1, i2, n0, n01)
+                                        : gpred == MC_GRIDPRED_INTERP_CUBIC ? ip_delta<true>(p, j, i0, i1, i2, n0, n1, n2)
+                                                                            : ip_delta<false>(p, j, i0, i1, i2, n0, n1, n2));
             }
         }
         __syncthreads();                           // s_cnt is reused by the next tile
@@ -778,15 +782,16 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
     return hipGetLastError();
 }
 
-hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, const uint16_t* gcodes, unsigned int* gcount,
-                   unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
+hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const uint16_t* gcodes,
+                   unsigned int* gcount, unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap,
+                   const void* x, int dtype,
                    long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
                    void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s)
 {
     const long long ntg = (ng + MC_TILE - 1) / MC_TILE, ntv = (nv + MC_TILE - 1) / MC_TILE;
     ProfScope ps("k_scatter", s);
     dim3 grid((unsigned)((ntg + MC_SC_TILES - 1) / MC_SC_TILES + (ntv + MC_SC_TILES - 1) / MC_SC_TILES));
-#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gcodes, gcount, gsum, \
+#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gpred, gcodes, gcount, gsum, \
                                        gidx, gdelta, gcap, ntg, (const T*)x, nv, vcodes, vcount, vsum, vidx, (T*)vval, \
                                        vcap, err, res)
     if (dtype == MC_F64) { if (dim == 2) MC_SC(double, 2); else MC_SC(double, 3); }

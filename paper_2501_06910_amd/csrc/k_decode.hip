@@ -11,26 +11,6 @@
 #include "mc_dev.h"
 #include "mc_kernels.h"
 
-__device__ __forceinline__ long long find_outlier(const int32_t* __restrict__ oidx, long long n, long long j)
-{
-    long long lo = 0, hi = n;           // first index with oidx >= j
-    while (lo < hi) {
-        long long mid = (lo + hi) >> 1;
-        if ((long long)oidx[mid] < j) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < n && (long long)oidx[lo] == j) ? lo : -1;
-}
-
-__device__ __forceinline__ int delta_at(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
-                                        const int32_t* __restrict__ odelta, long long nout, long long j)
-{
-    const int c = codes[j];
-    if (c != 0) return c - MC_R;
-    const long long k = find_outlier(oidx, nout, j);
-    return k >= 0 ? odelta[k] : 0;
-}
-
 // Exclusive scan across the 64 lanes of a wave.
 __device__ __forceinline__ int wave_excl_scan(int v)
 {

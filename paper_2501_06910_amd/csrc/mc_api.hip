@@ -737,6 +737,9 @@ static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
     if (!c) return mc_fail(MC_ERR_ARG, "codes pointer is NULL");
     if (c->residual_predictor != MC_RESPRED_NONE && c->residual_predictor != MC_RESPRED_DELTA)
         return mc_fail(MC_ERR_ARG, "unknown residual predictor");
+    if (c->grid_predictor != MC_GRIDPRED_LORENZO && c->grid_predictor != MC_GRIDPRED_INTERP_LINEAR &&
+        c->grid_predictor != MC_GRIDPRED_INTERP_CUBIC)
+        return mc_fail(MC_ERR_ARG, "unknown grid predictor");
     if (c->residual_predictor == MC_RESPRED_DELTA && need_flags)
         return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor takes no learned model");
     if (!c->grid_codes || !c->vert_codes || !c->result) return mc_fail(MC_ERR_ARG, "codes buffers are NULL");
@@ -746,6 +749,16 @@ static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
     if (need_flags && !c->block_flags) return mc_fail(MC_ERR_ARG, "block_flags is required with a model");
     (void)p;
     return MC_OK;
+}
+
+// Grid codes of the prequantised grid p->p under the chosen grid predictor.
+static hipError_t grid_codes(mc_plan p, const mc_codes* codes, hipStream_t s)
+{
+    const int n0 = (int)p->grid.dims[0], n1 = (int)p->grid.dims[1], n2 = (int)p->grid.dims[2];
+    if (codes->grid_predictor == MC_GRIDPRED_LORENZO)
+        return mck::lorenzo(p->p, p->dim, n0, n1, n2, p->ng, codes->grid_codes, p->gcount, p->gsum, p->knobs, s);
+    return mck::interp_codes(p->p, n0, n1, n2, p->ng, codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC,
+                             codes->grid_codes, p->gcount, p->gsum, s);
 }
 
 mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
@@ -765,8 +778,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         double* x1 = prm->residual == MC_RESIDUAL_OPEN ? p->x1 : nullptr;
         ECHK(mck::cluster_mean(p->noff, p->vlist, p->ng, d_field, dtype, p->bound, p->p, p->xh, x1,
                                codes->dbg_resampled, p->err, codes->result, p->gcount, p->ntg, s));
-        ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
-                          codes->grid_codes, p->gcount, p->gsum, p->knobs, s));
+        ECHK(grid_codes(p, codes, s));
         if (codes->residual_predictor == MC_RESPRED_DELTA) {
             ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, p->m, d_field, dtype, p->bound,
                                      codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
@@ -774,8 +786,8 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
             ECHK(mck::residual_nearest(p->m, p->nv, d_field, dtype, x1, p->xh, p->bound, codes->vert_codes,
                                        codes->dbg_vertex_g, p->vcount, p->vsum, s));
         }
-        ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes,
-                          p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype,
+        ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
+                          codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype,
                           p->nv, codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val,
                           codes->v_out_cap, p->err, codes->result, s));
         if (codes->dbg_grid_p)
@@ -784,8 +796,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     }
     ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, p->xh, codes->dbg_resampled,
                        codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, p->knobs, s));
-    ECHK(mck::lorenzo(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->ng,
-                      codes->grid_codes, p->gcount, p->gsum, p->knobs, s));
+    ECHK(grid_codes(p, codes, s));
     const int32_t* rho = nullptr;
     if (prm->model) {
         mc_status ms = mc_model_infer(prm->model, p, codes->result, nullptr, s);
@@ -800,7 +811,8 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                            codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
                            s));
     }
-    ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_codes, p->gcount,
+    ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
+                      codes->grid_codes, p->gcount,
                       p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
                       codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
                       p->err, codes->result, s));
@@ -859,9 +871,15 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
 {
     hipError_t e;
 #define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
-    ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, codes->result,
-                          p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2], p->p, p->xh,
-                          p->dws, p->knobs, s));
+    if (codes->grid_predictor == MC_GRIDPRED_LORENZO)
+        ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
+                              codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
+                              (int)p->grid.dims[2], p->p, p->xh, p->dws, p->knobs, s));
+    else
+        ECHK(mck::interp_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
+                                codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
+                                (int)p->grid.dims[2], codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC, p->p,
+                                p->xh, s));
     if (p->ops == MC_OPS_CLUSTER && codes->residual_predictor == MC_RESPRED_DELTA) {
         ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, p->m, codes->vert_codes, codes->v_out_idx,
                                       codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,

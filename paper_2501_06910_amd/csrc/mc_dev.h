@@ -102,6 +102,28 @@ __device__ __forceinline__ float xhat_of(int32_t p, double c, double step1)
     return (float)(c + (double)p * step1);
 }
 
+// Position of grid node j in the ascending outlier list, or -1.
+__device__ __forceinline__ long long find_outlier(const int32_t* __restrict__ oidx, long long n, long long j)
+{
+    long long lo = 0, hi = n;           // first index with oidx >= j
+    while (lo < hi) {
+        long long mid = (lo + hi) >> 1;
+        if ((long long)oidx[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && (long long)oidx[lo] == j) ? lo : -1;
+}
+
+// Prediction error of grid node j: its code, or its outlier entry.
+__device__ __forceinline__ int delta_at(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                        const int32_t* __restrict__ odelta, long long nout, long long j)
+{
+    const int c = codes[j];
+    if (c != 0) return c - MC_R;
+    const long long k = find_outlier(oidx, nout, j);
+    return k >= 0 ? odelta[k] : 0;
+}
+
 __device__ __forceinline__ float lerpf_(float a, float b, float t)
 {
     return (1.0f - t) * a + t * b;

@@ -1,0 +1,63 @@
+// mc_interp.h -- the multilevel interpolation grid predictor on the
+// prequantised grid p (the SZ family's interpolation predictor, Sec. II; any
+// grid compressor may stand in for C(x1), Sec. IV-D).  Shared by its
+// encoder and decoder (k_interp.hip) and the outlier gather (k_compress.hip).
+//
+// With L the least integer such that 2^L >= n_d on every axis, the strides
+// run s = 2^(L-1) .. 1.  The origin is predicted by 0; every other node
+// belongs to the class (s, a) where s = 2^t, t the fewest trailing zero
+// bits among its non-zero coordinates, and a the highest axis whose
+// coordinate is non-zero with t trailing zeros (an odd multiple of s).  Its
+// prediction interpolates along a from the nodes at -s and +s (and -3s,
+// +3s for the cubic rule), all of them in classes decoded before it:
+//   +s outside the grid:             p[-s]
+//   cubic and -3s, +3s inside:       floor((-p[-3s] + 9 p[-s] + 9 p[+s] - p[+3s] + 8) / 16)
+//   otherwise:                       floor((p[-s] + p[+s]) / 2)
+// Decoding runs the origin, then the classes in the order s = 2^(L-1) .. 1
+// and, within a stride, a = 0 .. D-1.  Integer arithmetic throughout.
+#pragma once
+#include <stdint.h>
+
+// Trailing zeros of a non-zero coordinate, 31 for zero.
+__device__ __forceinline__ int ip_tz(int v)
+{
+    return v ? __builtin_ctz((unsigned)v) : 31;
+}
+
+// log2 of the class stride (-1 for the origin) and the class axis.
+__device__ __forceinline__ int ip_class(int i0, int i1, int i2, int& axis)
+{
+    const int t0 = ip_tz(i0), t1 = ip_tz(i1), t2 = ip_tz(i2);
+    const int t = min(t0, min(t1, t2));
+    axis = t2 == t ? 2 : (t1 == t ? 1 : 0);
+    return t == 31 ? -1 : t;
+}
+
+// Prediction of the node at flat index j, coordinate x along its class axis
+// (extent n, flat step st between neighbours along it), stride s.
+template <bool CUBIC>
+__device__ __forceinline__ long long ip_predict(const int32_t* __restrict__ p, long long j, int x, int n, long long st,
+                                                int s)
+{
+    const long long a = p[j - (long long)s * st];
+    if (x + s > n - 1) return a;
+    const long long b = p[j + (long long)s * st];
+    if (CUBIC && x >= 3 * s && x + 3 * s <= n - 1) {
+        const long long a3 = p[j - 3ll * s * st], b3 = p[j + 3ll * s * st];
+        return (9 * (a + b) - a3 - b3 + 8) >> 4;
+    }
+    return (a + b) >> 1;
+}
+
+// Prediction error of node j from the fully known grid p (encoder side).
+template <bool CUBIC>
+__device__ __forceinline__ long long ip_delta(const int32_t* __restrict__ p, long long j, int i0, int i1, int i2,
+                                              int n0, int n1, int n2)
+{
+    int a;
+    const int t = ip_class(i0, i1, i2, a);
+    if (t < 0) return p[j];
+    const long long st = a == 0 ? 1ll : (a == 1 ? (long long)n0 : (long long)n0 * n1);
+    const int x = a == 0 ? i0 : (a == 1 ? i1 : i2), n = a == 0 ? n0 : (a == 1 ? n1 : n2);
+    return (long long)p[j] - ip_predict<CUBIC>(p, j, x, n, st, 1 << t);
+}

@@ -64,8 +64,10 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
                     const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
                     uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
                     hipStream_t s);
-hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, const uint16_t* gcodes, unsigned int* gcount,
-                   unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap, const void* x, int dtype,
+// gpred: the mc_grid_predictor whose errors the grid outliers carry
+hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const uint16_t* gcodes,
+                   unsigned int* gcount, unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap,
+                   const void* x, int dtype,
                    long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
                    void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s);
 
@@ -92,6 +94,15 @@ struct DecodeWs {
     int zplanes, nzc;              // 3-D: planes per chunk, plane chunks
     int* agg_z;                    // [nzc][n0*n1] chunk totals, then carries
 };
+// ---- multilevel interpolation grid predictor (k_interp.hip) ---------------
+// Codes of the prequantised grid p (outliers counted per tile, as lorenzo).
+hipError_t interp_codes(const int32_t* p, int n0, int n1, int n2, long long ng, bool cubic, uint16_t* codes,
+                        unsigned int* count, unsigned int* gsum, hipStream_t s);
+// p and x1' from the codes and outliers (all nodes written).
+hipError_t interp_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
+                         const mc_result* res, int dim, int n0, int n1, int n2, bool cubic, int32_t* p, float* xh,
+                         hipStream_t s);
+
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
                        const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,
                        unsigned remap, hipStream_t s);

@@ -72,7 +72,8 @@ class McCodes(C.Structure):
                 ("g_out_cap", C.c_int64), ("vert_codes", C.c_void_p), ("v_out_idx", C.c_void_p),
                 ("v_out_val", C.c_void_p), ("v_out_cap", C.c_int64), ("block_flags", C.c_void_p),
                 ("result", C.c_void_p), ("dbg_resampled", C.c_void_p), ("dbg_grid_p", C.c_void_p),
-                ("dbg_vertex_g", C.c_void_p), ("rho_q", C.c_void_p), ("residual_predictor", C.c_int32)]
+                ("dbg_vertex_g", C.c_void_p), ("rho_q", C.c_void_p), ("residual_predictor", C.c_int32),
+                ("grid_predictor", C.c_int32)]
 
 
 class McTrainOpts(C.Structure):
@@ -385,13 +386,18 @@ def store_tuning(key: str, mask: int):
         pass            # a read-only install keeps tuning per process
 
 
+GRID_PREDICTORS = {"lorenzo": 0, "linear": 1, "cubic": 2}
+
+
 class Codes:
     """Device buffers of one compressed field (allocated with torch)."""
 
     def __init__(self, plan: Plan, dtype, g_cap=None, v_cap=None, learned=False, debug=False,
-                 residual_predictor: str = "none"):
+                 residual_predictor: str = "none", grid_predictor: str = "lorenzo"):
         """residual_predictor: "none" or "delta" (1-D Lorenzo along the vertex
-        order); fixed for the buffers' lifetime, compress and decompress."""
+        order); grid_predictor: "lorenzo", "linear" or "cubic" (multilevel
+        interpolation); both fixed for the buffers' lifetime, compress and
+        decompress."""
         torch = _torch()
         ng, nv = plan.n_grid, plan.n_vertices
         g_cap = ng if g_cap is None else g_cap
@@ -416,7 +422,8 @@ class Codes:
             _ptr(self.grid_codes), _ptr(self.g_out_idx), _ptr(self.g_out_delta), g_cap, _ptr(self.vert_codes),
             _ptr(self.v_out_idx), _ptr(self.v_out_val), v_cap, _ptr(self.block_flags), _ptr(self.result),
             _ptr(self.dbg_resampled), _ptr(self.dbg_grid_p), _ptr(self.dbg_vertex_g), _ptr(self.rho_q),
-            {"none": 0, "delta": 1}[residual_predictor])
+            {"none": 0, "delta": 1}[residual_predictor], GRID_PREDICTORS[grid_predictor])
+        self.grid_predictor = grid_predictor
 
     def result_host(self) -> dict:
         b = self.result.cpu().numpy().tobytes()
