@@ -198,7 +198,7 @@ def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
 
 
 def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="full", operators="linear",
-                 residual="closed", predictor="none"):
+                 residual="closed", predictor="none", grid_predictor="lorenzo"):
     """The same field at another setting of the CR sweep (default: the
     best one, a 128^3 grid, one node per ~8 vertices, with the full split
     tau2 = tau and the grid step from tau1 = 4 tau): CR, both directions'
@@ -208,7 +208,7 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     cells = torch.from_numpy(mesh.cells).cuda() if operators == "linear" else None
     plan = M.Plan(coords, cells, dims=(dims, dims, dims), operators=operators)
     del cells
-    codes = M.Codes(plan, x.dtype, residual_predictor=predictor)
+    codes = M.Codes(plan, x.dtype, residual_predictor=predictor, grid_predictor=grid_predictor)
     out = torch.empty_like(x)
     kw = dict(split_mode=split_mode, residual=residual)
     M.compress(plan, x, eb, "rel", split, codes=codes, **kw)
@@ -232,7 +232,8 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     sb = M.stream_bytes(h, sT)
     ser = serial_compare(M, x, eb, h, (tc, td), log, f"{operators} {dims}^3, generated order")
     row = {"operators": operators, "grid": [dims] * 3, "split_mode": split_mode, "grid_share": split,
-           "residual": residual, "residual_predictor": predictor, "cr": round(nv * sT / sb["total"], 3),
+           "residual": residual, "residual_predictor": predictor, "grid_predictor": grid_predictor,
+           "cr": round(nv * sT / sb["total"], 3),
            "max_abs_err_over_tau": round(err / r["tau"], 4),
            "compress_GBps": round(nv * sT / (tc * 1e-3) / 1e9, 2),
            "decompress_GBps": round(nv * sT / (td * 1e-3) / 1e9, 2),
@@ -425,7 +426,9 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
     (the grid spacing hyperparameter of Sec. V-B) and error splits (sum:
     tau1 + tau2 = tau; full: tau2 = tau), next to the 1-D serialisation
     baseline in the generated and in a seeded random vertex order (CPU
-    entropy stage).  Improvement ratio = CR_mc / CR_serial."""
+    entropy stage).  Improvement ratio = CR_mc / CR_serial.  Every row also
+    carries the CR with the interpolation grid predictors (linear, cubic) in
+    place of the Lorenzo predictor: the same vertex stream, other grid codes."""
     import torch
     import meshgen as G
     from paper_2501_06910_amd import mc as M
@@ -465,7 +468,9 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
             settings = ([(m_, sp, "closed", "none") for m_, sp in splits] if ops == "linear"
                         else [st + ("none",) for st in SWEEP_CLUSTER]) + deltas
             codes_d = M.Codes(plan, x.dtype, residual_predictor="delta")
+            codes_g = {gp: M.Codes(plan, x.dtype, grid_predictor=gp) for gp in ("linear", "cubic")}
             for eb in ebs:
+                gcache = {}        # grid bytes per (tau1, grid predictor): the grid codes depend on nothing else
                 for mode, sp, resid, pred in settings:
                     cc = codes_d if pred == "delta" else codes
                     M.compress(plan, x, eb, "rel", sp, codes=cc, split_mode=mode, residual=resid)
@@ -483,8 +488,27 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
                     hr["v_out_idx"] = np.sort(inv[h["v_out_idx"]])
                     cr, crr = nv * sT / sb["total"], nv * sT / M.stream_bytes(hr, sT)["total"]
                     s_gen, s_rnd = serial[eb]["generated"], serial[eb]["random"]
+                    # the other grid predictors: same p, x1' and vertex codes, other grid codes
+                    other = {}
+                    for gp, cg in codes_g.items():
+                        key = (r["tau1"], gp)
+                        if key not in gcache:
+                            M.compress(plan, x, eb, "rel", sp, codes=cg, split_mode=mode, residual=resid)
+                            hg = cg.host_grid()
+                            if hg["result"]["status"]:
+                                gcache[key] = None
+                            else:
+                                gcache[key] = (M.grid_stream_bytes(hg["grid_codes"], hg["g_out_idx"],
+                                                                   hg["g_out_delta"]),
+                                               hg["result"]["n_grid_outliers"])
+                        if gcache[key] is not None:
+                            gb, gout = gcache[key]
+                            tot = sb["total"] - sb["grid"] - sb["grid_outliers"] + gb
+                            other[gp] = {"cr": round(nv * sT / tot, 3), "grid_bytes": gb,
+                                         "grid_outlier_rate": gout / plan.n_grid}
                     rows.append(dict(base, cr=round(cr, 3), bits_per_value=round(8 * sb["total"] / nv, 4),
-                                     grid_bytes=sb["grid"], vert_bytes=sb["vert"],
+                                     grid_bytes=sb["grid"] + sb["grid_outliers"], vert_bytes=sb["vert"],
+                                     grid_predictors=other,
                                      improvement_vs_serial=round(cr / s_gen, 3) if s_gen else None,
                                      # renumbering changes delta codes: no exact figure from these codes
                                      improvement_vs_serial_random_order=(round(crr / s_rnd, 3)
@@ -495,7 +519,7 @@ def cr_sweep(log, ebs=(1e-2, 1e-3, 1e-4, 1e-5, 1e-6), grids=(256, 128, 64), spli
                                      rel_l2=float(torch.linalg.vector_norm(d).item() / norm)))
                     log(f"cr sweep: {rows[-1]}")
             plan.destroy()
-            del codes, codes_d
+            del codes, codes_d, codes_g
     return {"serial": {str(k): v for k, v in serial.items()}, "rows": rows}
 
 
@@ -816,6 +840,10 @@ def main():
     if args.workload == "tet3d" and not args.no_compare:
         line["design_points"] = [design_point(M, mesh, coords, x, args.eb, log),
                                  design_point(M, mesh, coords, x, args.eb, log, predictor="delta"),
+                                 design_point(M, mesh, coords, x, args.eb, log, predictor="delta",
+                                              grid_predictor="cubic"),
+                                 design_point(M, mesh, coords, x, args.eb, log, dims=cfg["dims"][0],
+                                              split=args.split, split_mode="sum", grid_predictor="cubic"),
                                  design_point(M, mesh, coords, x, args.eb, log, split=0.1, split_mode="sum",
                                               operators="cluster", residual="open")]
     if not args.no_learned:

@@ -678,8 +678,8 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
                 const int i1 = (int)(r % n1), i2 = (int)(r / n1), n2 = (int)(ng / n01);
                 gidx[pos] = (int32_t)j;
                 gdelta[pos] = (int32_t)(gpred == MC_GRIDPRED_LORENZO ? lorenzo_delta<D>(p, j, i0, i1, i2, n0, n01)
-                                        : gpred == MC_GRIDPRED_INTERP_CUBIC ? ip_delta<true>(p, j, i0, i1, i2, n0, n1, n2)
-                                                                            : ip_delta<false>(p, j, i0, i1, i2, n0, n1, n2));
+                                        : gpred == MC_GRIDPRED_INTERP_CUBIC ? ip_delta<true>(p, (int)j, i0, i1, i2, n0, n1, n2)
+                                                                            : ip_delta<false>(p, (int)j, i0, i1, i2, n0, n1, n2));
             }
         }
         __syncthreads();                           // s_cnt is reused by the next tile

@@ -6,7 +6,9 @@
 // Encoder: the predictions read the prequantised grid p, which the encoder
 // holds whole, so every node is coded independently in one pass (thread per
 // node, codes and per-tile outlier counts; the outlier gather of
-// k_compress.hip recomputes the errors of the outliers).
+// k_compress.hip recomputes the errors of the outliers).  Encoder and class
+// passes take their 256-node tiles in XCD-contiguous order, so that the rows
+// and planes a prediction reads are mostly in the same XCD's L2.
 //
 // Decoder: classes in order.  The coarse classes (every node whose
 // coordinates are all multiples of SC, at most MC_IP_COARSE of them) are
@@ -25,26 +27,36 @@
 __host__ __device__ __forceinline__ int ip_mult(int m, int s) { return (m - 1) / s + 1; }
 __host__ __device__ __forceinline__ int ip_odd(int m, int s) { return ((m - 1) / s + 1) / 2; }
 
+// MC_IP_NPT nodes per thread, 256-node chunks: short-lived waves are
+// otherwise dispatch-bound.  Indices past the grid are clamped for the
+// loads (every load of the chunk issued together) and masked for the stores.
+#define MC_IP_NPT 8
 template <bool CUBIC>
 __global__ __launch_bounds__(256) void k_ip_codes(const int32_t* __restrict__ p, int n0, int n1, int n2, unsigned ng,
                                                   uint16_t* __restrict__ codes, unsigned int* __restrict__ count,
                                                   unsigned int* __restrict__ gsum)
 {
-    const unsigned j = blockIdx.x * 256u + threadIdx.x;
-    bool out = false;
-    if (j < ng) {
+    const unsigned j0 = xcd_tile(blockIdx.x, gridDim.x) * (256u * MC_IP_NPT) + threadIdx.x;
+    long long d[MC_IP_NPT];
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = min(j0 + 256u * u, ng - 1u);
         const unsigned r = j / (unsigned)n0;
         const int i0 = (int)(j - r * (unsigned)n0), i1 = (int)(r % (unsigned)n1), i2 = (int)(r / (unsigned)n1);
-        const long long d = ip_delta<CUBIC>(p, (long long)j, i0, i1, i2, n0, n1, n2);
-        out = !(d >= -(MC_R - 1) && d <= MC_R - 1);
-        codes[j] = out ? (uint16_t)0 : (uint16_t)(d + MC_R);
+        d[u] = ip_delta<CUBIC>(p, (int)j, i0, i1, i2, n0, n1, n2);
     }
-    // the 64 lanes of a wave lie in one MC_TILE tile (256-aligned blocks)
-    const unsigned long long m = __ballot(out);
-    if (m != 0ull && lane_id() == 0) {
-        const unsigned t = j / MC_TILE;
-        atomicAdd(&count[t], (unsigned)__popcll(m));
-        atomicAdd(&gsum[t / MC_SC_TILES], (unsigned)__popcll(m));
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = j0 + 256u * u;
+        const bool out = j < ng && !(d[u] >= -(MC_R - 1) && d[u] <= MC_R - 1);
+        if (j < ng) codes[j] = out ? (uint16_t)0 : (uint16_t)(d[u] + MC_R);
+        // the 64 lanes of a wave lie in one MC_TILE tile (256-aligned chunks)
+        const unsigned long long m = __ballot(out);
+        if (m != 0ull && lane_id() == 0) {
+            const unsigned t = j / MC_TILE;
+            atomicAdd(&count[t], (unsigned)__popcll(m));
+            atomicAdd(&gsum[t / MC_SC_TILES], (unsigned)__popcll(m));
+        }
     }
 }
 
@@ -64,9 +76,27 @@ __global__ __launch_bounds__(1024) void k_ip_coarse(const uint16_t* __restrict__
     auto flat = [&](int b0, int b1, int b2) {
         return (long long)b0 * SC + (long long)n0 * ((long long)b1 * SC + (long long)n1 * ((long long)b2 * SC));
     };
-    for (int k = threadIdx.x; k < mm; k += 1024) {
+    // every code load in flight before any is used (at most 4 per thread)
+    constexpr int PER = MC_IP_COARSE / 1024;
+    int cv[PER];
+    long long jv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int k = threadIdx.x + 1024 * u;
         const int b0 = k % m0, r = k / m0;
-        q[k] = delta_at(codes, oidx, odelta, nout, flat(b0, r % m1, r / m1));
+        jv[u] = k < mm ? flat(b0, r % m1, r / m1) : 0;
+        cv[u] = k < mm ? (int)codes[jv[u]] : MC_R;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int k = threadIdx.x + 1024 * u;
+        if (k >= mm) continue;
+        int e = cv[u] - MC_R;
+        if (cv[u] == 0) {
+            const long long o = find_outlier(oidx, nout, jv[u]);
+            e = o >= 0 ? odelta[o] : 0;
+        }
+        q[k] = e;
     }
     __syncthreads();
     // q holds the errors; each class pass turns its nodes into values (the
@@ -88,7 +118,7 @@ __global__ __launch_bounds__(1024) void k_ip_coarse(const uint16_t* __restrict__
 #pragma unroll
                 for (int d = 0; d < 3; ++d) b[d] = d == a ? (2 * b[d] + 1) * s : b[d] * (d < a ? s : 2 * s);
                 const int kk = b[0] + m0 * (b[1] + m1 * b[2]);
-                q[kk] = (int32_t)(ip_predict<CUBIC>(q, kk, b[a], mdim[a], st, s) + q[kk]);
+                q[kk] = (int32_t)(ip_predict<CUBIC>(q, kk, b[a], mdim[a], st * s, s) + q[kk]);
             }
             __syncthreads();
         }
@@ -102,27 +132,45 @@ __global__ __launch_bounds__(1024) void k_ip_coarse(const uint16_t* __restrict__
     }
 }
 
-// One finer class (s, a): c0 x c1 x c2 nodes.
+// One finer class (s, a): c0 x c1 x c2 nodes, MC_IP_PPT per thread in
+// 256-node chunks (loads first, indices past the class clamped).
+#define MC_IP_PPT 4
 template <bool CUBIC>
 __global__ __launch_bounds__(256) void k_ip_pass(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                                  const int32_t* __restrict__ odelta, const mc_result* __restrict__ res,
                                                  long long gcap, int n0, int n1, int n2, int s, int a, int c0, int c1,
                                                  unsigned tot, int32_t* __restrict__ p, float* __restrict__ xh)
 {
-    const unsigned k = blockIdx.x * 256u + threadIdx.x;
-    if (k >= tot) return;
+    const unsigned k0 = xcd_tile(blockIdx.x, gridDim.x) * (256u * MC_IP_PPT) + threadIdx.x;
     const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
-    const unsigned r = k / (unsigned)c0;
-    int b[3] = {(int)(k - r * (unsigned)c0), (int)(r % (unsigned)c1), (int)(r / (unsigned)c1)};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) b[d] = d == a ? (2 * b[d] + 1) * s : b[d] * (d < a ? s : 2 * s);
-    const long long j = (long long)b[0] + (long long)n0 * ((long long)b[1] + (long long)n1 * b[2]);
-    const long long st = a == 0 ? 1ll : (a == 1 ? (long long)n0 : (long long)n0 * n1);
+    const double cc = res->c, step1 = 2.0 * res->tau1;
+    const int st = a == 0 ? 1 : (a == 1 ? n0 : n0 * n1);
     const int n = a == 0 ? n0 : (a == 1 ? n1 : n2);
-    const int e = delta_at(codes, oidx, odelta, nout, j);
-    const int32_t v = (int32_t)(ip_predict<CUBIC>(p, j, b[a], n, st, s) + e);
-    p[j] = v;
-    xh[j] = xhat_of(v, res->c, 2.0 * res->tau1);
+    int jv[MC_IP_PPT], cv[MC_IP_PPT];
+    long long pred[MC_IP_PPT];
+#pragma unroll
+    for (int u = 0; u < MC_IP_PPT; ++u) {
+        const unsigned k = min(k0 + 256u * u, tot - 1u);
+        const unsigned r = k / (unsigned)c0;
+        int b[3] = {(int)(k - r * (unsigned)c0), (int)(r % (unsigned)c1), (int)(r / (unsigned)c1)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) b[d] = d == a ? (2 * b[d] + 1) * s : b[d] * (d < a ? s : 2 * s);
+        jv[u] = b[0] + n0 * (b[1] + n1 * b[2]);
+        cv[u] = codes[jv[u]];
+        pred[u] = ip_predict<CUBIC>(p, jv[u], b[a], n, st * s, s);
+    }
+#pragma unroll
+    for (int u = 0; u < MC_IP_PPT; ++u) {
+        if (k0 + 256u * u >= tot) break;
+        int e = cv[u] - MC_R;
+        if (cv[u] == 0) {       // an outlier: its error from the list
+            const long long o = find_outlier(oidx, nout, jv[u]);
+            e = o >= 0 ? odelta[o] : 0;
+        }
+        const int32_t v = (int32_t)(pred[u] + e);
+        p[jv[u]] = v;
+        xh[jv[u]] = xhat_of(v, cc, step1);
+    }
 }
 
 namespace mck {
@@ -131,7 +179,7 @@ hipError_t interp_codes(const int32_t* p, int n0, int n1, int n2, long long ng, 
                         unsigned int* count, unsigned int* gsum, hipStream_t s)
 {
     ProfScope ps("k_ip_codes", s);
-    const dim3 grid((unsigned)((ng + 255) / 256));
+    const dim3 grid((unsigned)((ng + 256 * MC_IP_NPT - 1) / (256 * MC_IP_NPT)));
     if (cubic) hipLaunchKernelGGL(k_ip_codes<true>, grid, dim3(256), 0, s, p, n0, n1, n2, (unsigned)ng, codes, count, gsum);
     else hipLaunchKernelGGL(k_ip_codes<false>, grid, dim3(256), 0, s, p, n0, n1, n2, (unsigned)ng, codes, count, gsum);
     return hipGetLastError();
@@ -173,7 +221,7 @@ hipError_t interp_decode(const uint16_t* codes, const int32_t* oidx, const int32
             for (int d = 0; d < 3; ++d) c[d] = d == a ? ip_odd(n[d], st) : ip_mult(n[d], d < a ? st : 2 * st);
             const unsigned tot = (unsigned)((long long)c[0] * c[1] * c[2]);
             if (tot == 0) continue;
-            const dim3 grid((tot + 255) / 256);
+            const dim3 grid((tot + 256 * MC_IP_PPT - 1) / (256 * MC_IP_PPT));
             if (cubic)
                 hipLaunchKernelGGL(k_ip_pass<true>, grid, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2,
                                    st, a, c[0], c[1], tot, p, xh);

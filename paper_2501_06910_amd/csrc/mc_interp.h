@@ -34,30 +34,43 @@ __device__ __forceinline__ int ip_class(int i0, int i1, int i2, int& axis)
 }
 
 // Prediction of the node at flat index j, coordinate x along its class axis
-// (extent n, flat step st between neighbours along it), stride s.
+// (extent n), stride s, flat distance ds = s * (flat step along the axis);
+// indices fit in int (fewer than 2^31 nodes), sums are taken in int64.
+// All four neighbour loads are issued unconditionally and together (a
+// neighbour a rule does not use reads the -s node again, which is always
+// inside the grid) and the rule is chosen with bitwise masks, not selects,
+// so that the compiler keeps the loads out of branches.  Without a +s
+// neighbour b reads a, and floor((a + a) / 2) = a is that case's rule.
 template <bool CUBIC>
-__device__ __forceinline__ long long ip_predict(const int32_t* __restrict__ p, long long j, int x, int n, long long st,
-                                                int s)
+__device__ __forceinline__ long long ip_predict(const int32_t* __restrict__ p, int j, int x, int n, int ds, int s)
 {
-    const long long a = p[j - (long long)s * st];
-    if (x + s > n - 1) return a;
-    const long long b = p[j + (long long)s * st];
-    if (CUBIC && x >= 3 * s && x + 3 * s <= n - 1) {
-        const long long a3 = p[j - 3ll * s * st], b3 = p[j + 3ll * s * st];
-        return (9 * (a + b) - a3 - b3 + 8) >> 4;
-    }
-    return (a + b) >> 1;
+    const bool hb = x + s <= n - 1;
+    const bool h3 = CUBIC && x >= 3 * s && x + 3 * s <= n - 1;
+    const int ia = j - ds;
+    const long long a = p[ia];
+    const long long b = p[hb ? j + ds : ia];
+    const long long lin = (a + b) >> 1;
+    if (!CUBIC) return lin;
+    const long long a3 = p[h3 ? j - 3 * ds : ia];
+    const long long b3 = p[h3 ? j + 3 * ds : ia];
+    const long long cub = (9 * (a + b) - a3 - b3 + 8) >> 4;
+    const long long m3 = -(long long)h3;
+    return (cub & m3) | (lin & ~m3);
 }
 
 // Prediction error of node j from the fully known grid p (encoder side).
+// The origin (prediction 0) takes the same loads at distance 0.
 template <bool CUBIC>
-__device__ __forceinline__ long long ip_delta(const int32_t* __restrict__ p, long long j, int i0, int i1, int i2,
-                                              int n0, int n1, int n2)
+__device__ __forceinline__ long long ip_delta(const int32_t* __restrict__ p, int j, int i0, int i1, int i2, int n0,
+                                              int n1, int n2)
 {
     int a;
     const int t = ip_class(i0, i1, i2, a);
-    if (t < 0) return p[j];
-    const long long st = a == 0 ? 1ll : (a == 1 ? (long long)n0 : (long long)n0 * n1);
+    const bool org = t < 0;
+    const int tt = org ? 0 : t;
+    const int st = a == 0 ? 1 : (a == 1 ? n0 : n0 * n1);
     const int x = a == 0 ? i0 : (a == 1 ? i1 : i2), n = a == 0 ? n0 : (a == 1 ? n1 : n2);
-    return (long long)p[j] - ip_predict<CUBIC>(p, j, x, n, st, 1 << t);
+    const long long self = p[j];
+    const long long pred = ip_predict<CUBIC>(p, j, x, n, org ? 0 : st << tt, 1 << tt);
+    return self - (org ? 0ll : pred);
 }

@@ -430,6 +430,13 @@ class Codes:
         r = McResult.from_buffer_copy(b)
         return {k: getattr(r, k) for k, _ in McResult._fields_}
 
+    def host_grid(self) -> dict:
+        """Host copies of the grid part only (synchronises)."""
+        r = self.result_host()
+        n = r["n_grid_outliers"]
+        return dict(result=r, grid_codes=self.grid_codes.cpu().numpy().view(np.uint16),
+                    g_out_idx=self.g_out_idx[:n].cpu().numpy(), g_out_delta=self.g_out_delta[:n].cpu().numpy())
+
     def host(self) -> dict:
         """Host copies of the compressed representation (synchronises)."""
         r = self.result_host()
@@ -760,6 +767,15 @@ def _leb128_bytes(values: np.ndarray) -> int:
 
 
 HEADER_BYTES = 64
+
+
+def grid_stream_bytes(grid_codes: np.ndarray, g_out_idx: np.ndarray, g_out_delta: np.ndarray) -> int:
+    """Bytes of the grid part of the stream (Huffman-coded grid codes and the
+    grid outlier list), as counted by stream_bytes."""
+    gi = g_out_idx.astype(np.int64)
+    g_gap = np.diff(np.concatenate([[-1], gi])) - 1 if gi.size else gi
+    zz = ((g_out_delta.astype(np.int64) << 1) ^ (g_out_delta.astype(np.int64) >> 63)).astype(np.uint64)
+    return huffman_size(grid_codes) + _leb128_bytes(g_gap) + _leb128_bytes(zz)
 
 
 def stream_bytes(host: dict, value_bytes: int, model_bytes: int = 0) -> dict:
