@@ -25,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c", "mco_grid_init.c", "mco_resdelta.c", "mco_interp.c"]
+_SOURCES = ["mco_geom.c", "mco_quant.c", "mco_mlp.c", "mco_serial.c", "mco_cluster.c", "mco_grid_init.c", "mco_resdelta.c", "mco_interp.c", "mco_temporal.c"]
 
 OK, ERR_ARG, ERR_RANGE, ERR_CAPACITY = 0, 1, 2, 3
 F32, F64 = 0, 1
@@ -98,6 +98,8 @@ def lib():
             "mco_interp_delta": (None, [P, P, i32, P]),
             "mco_interp_codes": (i32, [P, P, i32, P, P, P, i64, P]),
             "mco_interp_decode": (i32, [P, P, P, i64, P, i32, P]),
+            "mco_temporal_codes": (i32, [P, P, i64, P, P, P, P, i64, P]),
+            "mco_temporal_decode": (i32, [P, P, P, i64, P, i64, P, P]),
             "mco_residual_quantize": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
             "mco_grid_quantize_f64": (i32, [P, P, P, P, P, P, P, i64, P]),
             "mco_nearest_nodes": (None, [P, i32, i64, P, P]),
@@ -161,8 +163,9 @@ class OracleError(RuntimeError):
 # ---------------------------------------------------------------------------
 
 SPLIT_SUM, SPLIT_FULL = 0, 1
-# grid predictors: Lorenzo, multilevel linear / cubic interpolation (mco_interp.c)
-GPRED_LORENZO, GPRED_LINEAR, GPRED_CUBIC = 0, 1, 2
+# grid predictors: Lorenzo, multilevel linear / cubic interpolation (mco_interp.c),
+# time axis from a reference grid (mco_temporal.c)
+GPRED_LORENZO, GPRED_LINEAR, GPRED_CUBIC, GPRED_TEMPORAL = 0, 1, 2, 3
 
 
 def bound(x: np.ndarray, eb: float, relative: bool, split: float, mode: int = SPLIT_SUM) -> Bound:
@@ -331,14 +334,21 @@ def interp_delta(p: np.ndarray, g: Grid, cubic: bool) -> np.ndarray:
     return d
 
 
-def grid_codes(p: np.ndarray, g: Grid, gpred: int) -> GridCodes:
-    """Codes of the prequantised grid p under one of the grid predictors."""
+def grid_codes(p: np.ndarray, g: Grid, gpred: int, ref=None, b: Bound = None) -> GridCodes:
+    """Codes of the prequantised grid p under one of the grid predictors
+    (the time-axis one takes the reference grid ref and the bound b)."""
     p = np.ascontiguousarray(p, np.int32)
     ng = g.count
     codes = np.empty(ng, np.uint16)
     oi = np.empty(ng, np.int32)
     od = np.empty(ng, np.int32)
     n = C.c_int64(0)
+    if gpred == GPRED_TEMPORAL:
+        ref = np.ascontiguousarray(ref, np.float32)
+        st = lib().mco_temporal_codes(_p(p), _p(ref), ng, _p(b), _p(codes), _p(oi), _p(od), ng, C.byref(n))
+        if st != OK:
+            raise OracleError(st, "temporal_codes")
+        return GridCodes(p, codes, oi[:n.value].copy(), od[:n.value].copy())
     if gpred == GPRED_LORENZO:
         d = lorenzo(p, g)
         out = np.abs(d) > RADIUS - 1
@@ -354,9 +364,13 @@ def grid_codes(p: np.ndarray, g: Grid, gpred: int) -> GridCodes:
     return GridCodes(p, codes, oi[:n.value].copy(), od[:n.value].copy())
 
 
-def grid_decode(codes, out_idx, out_delta, g: Grid, gpred: int = GPRED_LORENZO) -> np.ndarray:
+def grid_decode(codes, out_idx, out_delta, g: Grid, gpred: int = GPRED_LORENZO, ref=None,
+                b: Bound = None) -> np.ndarray:
     p = np.empty(g.count, np.int32)
-    if gpred == GPRED_LORENZO:
+    if gpred == GPRED_TEMPORAL:
+        st = lib().mco_temporal_decode(_p(codes), _p(out_idx), _p(out_delta), out_idx.size,
+                                       _p(np.ascontiguousarray(ref, np.float32)), g.count, _p(b), _p(p))
+    elif gpred == GPRED_LORENZO:
         st = lib().mco_grid_decode(_p(codes), _p(out_idx), _p(out_delta), out_idx.size, _p(g), _p(p))
     elif gpred in (GPRED_LINEAR, GPRED_CUBIC):
         st = lib().mco_interp_decode(_p(codes), _p(out_idx), _p(out_delta), out_idx.size, _p(g),
@@ -453,14 +467,14 @@ class Compressed:
 
 def compress(coords, m: Mapping, g: Grid, x: np.ndarray, eb: float, relative: bool,
              split: float, rho_q=None, mode: int = SPLIT_SUM, delta: bool = False,
-             gpred: int = GPRED_LORENZO) -> Compressed:
+             gpred: int = GPRED_LORENZO, gref=None) -> Compressed:
     """delta: residual codes with the 1-D Lorenzo predictor (plain mode);
-    gpred: the grid predictor."""
+    gpred: the grid predictor (gref: the time-axis predictor's reference)."""
     b = bound(x, eb, relative, split, mode)
     v = resample(m, x, b.c)
     gc = grid_quantize(v, g, b)
     if gpred != GPRED_LORENZO:
-        gc = grid_codes(gc.p, g, gpred)
+        gc = grid_codes(gc.p, g, gpred, gref, b)
     xhat = grid_recon(gc.p, b)
     gv = back_interp(coords, g, xhat)
     if delta:
@@ -471,8 +485,8 @@ def compress(coords, m: Mapping, g: Grid, x: np.ndarray, eb: float, relative: bo
 
 
 def decompress(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
-               rho_q=None, delta: bool = False, gpred: int = GPRED_LORENZO) -> np.ndarray:
-    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred)
+               rho_q=None, delta: bool = False, gpred: int = GPRED_LORENZO, gref=None) -> np.ndarray:
+    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred, gref, b)
     xhat = grid_recon(p, b)
     gv = back_interp(coords, g, xhat)
     if delta:
@@ -586,7 +600,7 @@ class ClusterCompressed:
 
 def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, split: float,
                      open_loop: bool = True, mode: int = SPLIT_SUM, delta: bool = False,
-                     gpred: int = GPRED_LORENZO) -> ClusterCompressed:
+                     gpred: int = GPRED_LORENZO, gref=None) -> ClusterCompressed:
     """Alg. 3 with the nearest-node g and the cluster-mean f; delta: the
     closed-loop residuals through the 1-D Lorenzo predictor (g_k = x1'[m_k])."""
     b = bound(x, eb, relative, split, mode)
@@ -594,7 +608,7 @@ def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, 
     x1, cnt = cluster_mean(x, m, g.count, b.c)
     gc = grid_quantize_f64(x1, g, b)
     if gpred != GPRED_LORENZO:
-        gc = grid_codes(gc.p, g, gpred)
+        gc = grid_codes(gc.p, g, gpred, gref, b)
     xhat = grid_recon(gc.p, b)
     if delta:
         if open_loop:
@@ -606,9 +620,9 @@ def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, 
 
 
 def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
-                       delta: bool = False, gpred: int = GPRED_LORENZO) -> np.ndarray:
+                       delta: bool = False, gpred: int = GPRED_LORENZO, gref=None) -> np.ndarray:
     """Alg. 4 with the nearest-node g."""
-    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred)
+    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred, gref, b)
     m = nearest_nodes(coords, g)
     xhat = grid_recon(p, b)
     if delta:

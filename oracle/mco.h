@@ -104,6 +104,12 @@ int mco_interp_codes(const int32_t* p, const mco_grid* g, int cubic, uint16_t* c
 int mco_interp_decode(const uint16_t* codes, const int32_t* out_idx, const int32_t* out_delta, int64_t n_out,
                       const mco_grid* g, int cubic, int32_t* p);
 
+/* Time-axis predictor from a reference grid (mco_temporal.c). */
+int mco_temporal_codes(const int32_t* p, const float* ref, int64_t ng, const mco_bound* b, uint16_t* codes,
+                       int32_t* out_idx, int32_t* out_delta, int64_t cap, int64_t* n_out);
+int mco_temporal_decode(const uint16_t* codes, const int32_t* out_idx, const int32_t* out_delta, int64_t n_out,
+                        const float* ref, int64_t ng, const mco_bound* b, int32_t* p);
+
 /* ---- residual compressor ------------------------------------------------ */
 int mco_residual_quantize(const void* x, int dtype, int64_t nv, const float* gv,
                           const mco_bound* b, uint16_t* codes, int32_t* out_idx,
