@@ -175,11 +175,20 @@ typedef enum { MC_RESPRED_NONE = 0, MC_RESPRED_DELTA = 1 } mc_residual_predictor
  *   otherwise:                    floor((p[-s] + p[+s]) / 2)
  * Decoding visits the origin, then the classes s = 2^(L-1) .. 1, and
  * a = 0 .. D-1 within a stride: one launch per fine class, the coarse
- * classes in one workgroup.  Unknown values: MC_ERR_ARG. */
+ * classes in one workgroup.
+ * MC_GRIDPRED_TEMPORAL: the time axis (Sec. I: analyses read many
+ * timesteps of one mesh).  Node j is predicted from a reference grid r that
+ * compressor and decompressor both hold, normally the x1' of the previous
+ * timestep (mc_codes.xhat_out of that call):
+ *   P_j = rint(((double)r_j - c) / (2 tau1)) when below 2^27 in magnitude,
+ *   else 0 (also for a non-finite r_j); error p_j - P_j.
+ * mc_codes.grid_ref must then point to r (device, float[n_grid]), the
+ * same array at compress and decompress.  Unknown values: MC_ERR_ARG. */
 typedef enum {
     MC_GRIDPRED_LORENZO = 0,
     MC_GRIDPRED_INTERP_LINEAR = 1,
-    MC_GRIDPRED_INTERP_CUBIC = 2
+    MC_GRIDPRED_INTERP_CUBIC = 2,
+    MC_GRIDPRED_TEMPORAL = 3
 } mc_grid_predictor;
 
 /* Compressed representation (caller-allocated device buffers).
@@ -212,6 +221,9 @@ typedef struct {
     int32_t* rho_q;
     int32_t residual_predictor;  /* mc_residual_predictor of vert_codes; the same for compress and decompress */
     int32_t grid_predictor;      /* mc_grid_predictor of grid_codes; the same for compress and decompress */
+    const float* grid_ref;       /* MC_GRIDPRED_TEMPORAL: reference grid [n_grid] (device); else ignored */
+    float* xhat_out;             /* optional [n_grid] (device): x1' of this call, written by compress and
+                                    decompress after every other use of grid_ref (so it may be grid_ref) */
 } mc_codes;
 
 const char* mc_status_string(mc_status s);

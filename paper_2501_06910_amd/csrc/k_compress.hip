@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
 // and the final status (capacity overflows included).
 template <typename T, int D>
 __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng, int gpred,
-                                                 const uint16_t* __restrict__ gcodes,
+                                                 const float* __restrict__ gref, const uint16_t* __restrict__ gcodes,
                                                  const unsigned int* __restrict__ gcount,
                                                  const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
                                                  int32_t* __restrict__ gdelta, long long gcap, long long ntg,
@@ -677,9 +677,12 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
                 const long long r = j / n0;
                 const int i1 = (int)(r % n1), i2 = (int)(r / n1), n2 = (int)(ng / n01);
                 gidx[pos] = (int32_t)j;
-                gdelta[pos] = (int32_t)(gpred == MC_GRIDPRED_LORENZO ? lorenzo_delta<D>(p, j, i0, i1, i2, n0, n01)
-                                        : gpred == MC_GRIDPRED_INTERP_CUBIC ? ip_delta<true>(p, (int)j, i0, i1, i2, n0, n1, n2)
-                                                                            : ip_delta<false>(p, (int)j, i0, i1, i2, n0, n1, n2));
+                long long d;
+                if (gpred == MC_GRIDPRED_LORENZO) d = lorenzo_delta<D>(p, j, i0, i1, i2, n0, n01);
+                else if (gpred == MC_GRIDPRED_INTERP_CUBIC) d = ip_delta<true>(p, (int)j, i0, i1, i2, n0, n1, n2);
+                else if (gpred == MC_GRIDPRED_INTERP_LINEAR) d = ip_delta<false>(p, (int)j, i0, i1, i2, n0, n1, n2);
+                else d = (long long)p[j] - tp_pred(gref[j], res->c, 1.0 / (2.0 * res->tau1));
+                gdelta[pos] = (int32_t)d;
             }
         }
         __syncthreads();                           // s_cnt is reused by the next tile
@@ -782,7 +785,8 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
     return hipGetLastError();
 }
 
-hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const uint16_t* gcodes,
+hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const float* gref,
+                   const uint16_t* gcodes,
                    unsigned int* gcount, unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap,
                    const void* x, int dtype,
                    long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
@@ -791,9 +795,9 @@ hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int 
     const long long ntg = (ng + MC_TILE - 1) / MC_TILE, ntv = (nv + MC_TILE - 1) / MC_TILE;
     ProfScope ps("k_scatter", s);
     dim3 grid((unsigned)((ntg + MC_SC_TILES - 1) / MC_SC_TILES + (ntv + MC_SC_TILES - 1) / MC_SC_TILES));
-#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gpred, gcodes, gcount, gsum, \
-                                       gidx, gdelta, gcap, ntg, (const T*)x, nv, vcodes, vcount, vsum, vidx, (T*)vval, \
-                                       vcap, err, res)
+#define MC_SC(T, D) hipLaunchKernelGGL((k_scatter<T, D>), grid, dim3(256), 0, s, p, n0, n1, ng, gpred, gref, gcodes, gcount, \
+                                       gsum, gidx, gdelta, gcap, ntg, (const T*)x, nv, vcodes, vcount, vsum, vidx, \
+                                       (T*)vval, vcap, err, res)
     if (dtype == MC_F64) { if (dim == 2) MC_SC(double, 2); else MC_SC(double, 3); }
     else { if (dim == 2) MC_SC(float, 2); else MC_SC(float, 3); }
 #undef MC_SC

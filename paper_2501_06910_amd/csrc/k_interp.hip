@@ -1,7 +1,9 @@
-// k_interp.hip -- the multilevel interpolation grid predictor on gfx950
-// (an alternative grid compressor C(x1): the SZ family's interpolation
-// predictor, Sec. II; Sec. IV-D admits any compressor).  The classes,
-// their order and the prediction rules are stated in mc_interp.h.
+// k_interp.hip -- the multilevel interpolation and the time-axis grid
+// predictors on gfx950 (alternative grid compressors C(x1): the SZ family's
+// interpolation predictor, Sec. II; Sec. IV-D admits any compressor).  The
+// classes, their order and the prediction rules are stated in mc_interp.h.
+// The time-axis predictor codes and decodes every node on its own, one pass
+// each way.
 //
 // Encoder: the predictions read the prequantised grid p, which the encoder
 // holds whole, so every node is coded independently in one pass (thread per
@@ -173,7 +175,88 @@ __global__ __launch_bounds__(256) void k_ip_pass(const uint16_t* __restrict__ co
     }
 }
 
+// Time-axis predictor: every node on its own (MC_IP_NPT per thread).
+__global__ __launch_bounds__(256) void k_tp_codes(const int32_t* __restrict__ p, const float* __restrict__ ref,
+                                                  const DevBound* __restrict__ bnd, unsigned ng,
+                                                  uint16_t* __restrict__ codes, unsigned int* __restrict__ count,
+                                                  unsigned int* __restrict__ gsum)
+{
+    const double c = bnd->c, inv1 = bnd->inv1;
+    const unsigned j0 = xcd_tile(blockIdx.x, gridDim.x) * (256u * MC_IP_NPT) + threadIdx.x;
+    int pv[MC_IP_NPT];
+    float rv[MC_IP_NPT];
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = min(j0 + 256u * u, ng - 1u);
+        pv[u] = p[j];
+        rv[u] = ref[j];
+    }
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = j0 + 256u * u;
+        const long long d = (long long)pv[u] - tp_pred(rv[u], c, inv1);
+        const bool out = j < ng && !(d >= -(MC_R - 1) && d <= MC_R - 1);
+        if (j < ng) codes[j] = out ? (uint16_t)0 : (uint16_t)(d + MC_R);
+        const unsigned long long m = __ballot(out);
+        if (m != 0ull && lane_id() == 0) {
+            const unsigned t = j / MC_TILE;
+            atomicAdd(&count[t], (unsigned)__popcll(m));
+            atomicAdd(&gsum[t / MC_SC_TILES], (unsigned)__popcll(m));
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tp_decode(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                   const int32_t* __restrict__ odelta,
+                                                   const mc_result* __restrict__ res, long long gcap,
+                                                   const float* __restrict__ ref, unsigned ng, int32_t* __restrict__ p,
+                                                   float* __restrict__ xh)
+{
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    const double c = res->c, step1 = 2.0 * res->tau1, inv1 = 1.0 / (2.0 * res->tau1);
+    const unsigned j0 = xcd_tile(blockIdx.x, gridDim.x) * (256u * MC_IP_NPT) + threadIdx.x;
+    int cv[MC_IP_NPT];
+    float rv[MC_IP_NPT];
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = min(j0 + 256u * u, ng - 1u);
+        cv[u] = codes[j];
+        rv[u] = ref[j];
+    }
+#pragma unroll
+    for (int u = 0; u < MC_IP_NPT; ++u) {
+        const unsigned j = j0 + 256u * u;
+        if (j >= ng) break;
+        int e = cv[u] - MC_R;
+        if (cv[u] == 0) {
+            const long long o = find_outlier(oidx, nout, j);
+            e = o >= 0 ? odelta[o] : 0;
+        }
+        const int32_t v = (int32_t)(tp_pred(rv[u], c, inv1) + e);
+        p[j] = v;
+        xh[j] = xhat_of(v, c, step1);
+    }
+}
+
 namespace mck {
+
+hipError_t temporal_codes(const int32_t* p, const float* ref, const DevBound* bnd, long long ng, uint16_t* codes,
+                          unsigned int* count, unsigned int* gsum, hipStream_t s)
+{
+    ProfScope ps("k_tp_codes", s);
+    const dim3 grid((unsigned)((ng + 256 * MC_IP_NPT - 1) / (256 * MC_IP_NPT)));
+    hipLaunchKernelGGL(k_tp_codes, grid, dim3(256), 0, s, p, ref, bnd, (unsigned)ng, codes, count, gsum);
+    return hipGetLastError();
+}
+
+hipError_t temporal_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
+                           const mc_result* res, const float* ref, long long ng, int32_t* p, float* xh, hipStream_t s)
+{
+    ProfScope ps("k_tp_decode", s);
+    const dim3 grid((unsigned)((ng + 256 * MC_IP_NPT - 1) / (256 * MC_IP_NPT)));
+    hipLaunchKernelGGL(k_tp_decode, grid, dim3(256), 0, s, codes, oidx, odelta, res, gcap, ref, (unsigned)ng, p, xh);
+    return hipGetLastError();
+}
 
 hipError_t interp_codes(const int32_t* p, int n0, int n1, int n2, long long ng, bool cubic, uint16_t* codes,
                         unsigned int* count, unsigned int* gsum, hipStream_t s)

@@ -738,8 +738,10 @@ static mc_status check_codes(mc_plan p, const mc_codes* c, bool need_flags)
     if (c->residual_predictor != MC_RESPRED_NONE && c->residual_predictor != MC_RESPRED_DELTA)
         return mc_fail(MC_ERR_ARG, "unknown residual predictor");
     if (c->grid_predictor != MC_GRIDPRED_LORENZO && c->grid_predictor != MC_GRIDPRED_INTERP_LINEAR &&
-        c->grid_predictor != MC_GRIDPRED_INTERP_CUBIC)
+        c->grid_predictor != MC_GRIDPRED_INTERP_CUBIC && c->grid_predictor != MC_GRIDPRED_TEMPORAL)
         return mc_fail(MC_ERR_ARG, "unknown grid predictor");
+    if (c->grid_predictor == MC_GRIDPRED_TEMPORAL && !c->grid_ref)
+        return mc_fail(MC_ERR_ARG, "the time-axis grid predictor needs grid_ref");
     if (c->residual_predictor == MC_RESPRED_DELTA && need_flags)
         return mc_fail(MC_ERR_UNSUPPORTED, "the delta residual predictor takes no learned model");
     if (!c->grid_codes || !c->vert_codes || !c->result) return mc_fail(MC_ERR_ARG, "codes buffers are NULL");
@@ -757,6 +759,8 @@ static hipError_t grid_codes(mc_plan p, const mc_codes* codes, hipStream_t s)
     const int n0 = (int)p->grid.dims[0], n1 = (int)p->grid.dims[1], n2 = (int)p->grid.dims[2];
     if (codes->grid_predictor == MC_GRIDPRED_LORENZO)
         return mck::lorenzo(p->p, p->dim, n0, n1, n2, p->ng, codes->grid_codes, p->gcount, p->gsum, p->knobs, s);
+    if (codes->grid_predictor == MC_GRIDPRED_TEMPORAL)
+        return mck::temporal_codes(p->p, codes->grid_ref, p->bound, p->ng, codes->grid_codes, p->gcount, p->gsum, s);
     return mck::interp_codes(p->p, n0, n1, n2, p->ng, codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC,
                              codes->grid_codes, p->gcount, p->gsum, s);
 }
@@ -787,11 +791,13 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                                        codes->dbg_vertex_g, p->vcount, p->vsum, s));
         }
         ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
-                          codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype,
-                          p->nv, codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val,
-                          codes->v_out_cap, p->err, codes->result, s));
+                          codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx,
+                          codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv, codes->vert_codes, p->vcount,
+                          p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, p->err, codes->result, s));
         if (codes->dbg_grid_p)
             ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+        if (codes->xhat_out)
+            ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
         return MC_OK;
     }
     ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, p->xh, codes->dbg_resampled,
@@ -812,11 +818,11 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                            s));
     }
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
-                      codes->grid_codes, p->gcount,
-                      p->gsum, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv,
-                      codes->vert_codes, p->vcount, p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap,
-                      p->err, codes->result, s));
+                      codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta,
+                      codes->g_out_cap, d_field, dtype, p->nv, codes->vert_codes, p->vcount, p->vsum,
+                      codes->v_out_idx, codes->v_out_val, codes->v_out_cap, p->err, codes->result, s));
     if (codes->dbg_grid_p) ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+    if (codes->xhat_out) ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
 #undef ECHK
     return MC_OK;
@@ -875,11 +881,16 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
         ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
                               codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
                               (int)p->grid.dims[2], p->p, p->xh, p->dws, p->knobs, s));
+    else if (codes->grid_predictor == MC_GRIDPRED_TEMPORAL)
+        ECHK(mck::temporal_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
+                                  codes->result, codes->grid_ref, p->ng, p->p, p->xh, s));
     else
         ECHK(mck::interp_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
                                 codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
                                 (int)p->grid.dims[2], codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC, p->p,
                                 p->xh, s));
+    if (codes->xhat_out)
+        ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (p->ops == MC_OPS_CLUSTER && codes->residual_predictor == MC_RESPRED_DELTA) {
         ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, p->m, codes->vert_codes, codes->v_out_idx,
                                       codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,

@@ -1,7 +1,8 @@
-// mc_interp.h -- the multilevel interpolation grid predictor on the
-// prequantised grid p (the SZ family's interpolation predictor, Sec. II; any
-// grid compressor may stand in for C(x1), Sec. IV-D).  Shared by its
-// encoder and decoder (k_interp.hip) and the outlier gather (k_compress.hip).
+// mc_interp.h -- the multilevel interpolation and the time-axis grid
+// predictors on the prequantised grid p (the SZ family's interpolation
+// predictor, Sec. II; any grid compressor may stand in for C(x1),
+// Sec. IV-D).  Shared by their encoders and decoders (k_interp.hip) and the
+// outlier gather (k_compress.hip).
 //
 // With L the least integer such that 2^L >= n_d on every axis, the strides
 // run s = 2^(L-1) .. 1.  The origin is predicted by 0; every other node
@@ -73,4 +74,13 @@ __device__ __forceinline__ long long ip_delta(const int32_t* __restrict__ p, int
     const long long self = p[j];
     const long long pred = ip_predict<CUBIC>(p, j, x, n, org ? 0 : st << tt, 1 << tt);
     return self - (org ? 0ll : pred);
+}
+
+// Time-axis prediction of a node from its reference grid value r (the
+// previous timestep's x1'): rint((r - c) * inv1) when that is below 2^27 in
+// magnitude, else 0 (a non-finite r included).
+__device__ __forceinline__ long long tp_pred(float r, double c, double inv1)
+{
+    const double s = ((double)r - c) * inv1;
+    return fabs(s) < 134217728.0 ? (long long)rint(s) : 0ll;
 }

@@ -64,8 +64,10 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
                     const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
                     uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
                     hipStream_t s);
-// gpred: the mc_grid_predictor whose errors the grid outliers carry
-hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const uint16_t* gcodes,
+// gpred: the mc_grid_predictor whose errors the grid outliers carry (gref:
+// the time-axis predictor's reference grid)
+hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const float* gref,
+                   const uint16_t* gcodes,
                    unsigned int* gcount, unsigned int* gsum, int32_t* gidx, int32_t* gdelta, long long gcap,
                    const void* x, int dtype,
                    long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
@@ -102,6 +104,12 @@ hipError_t interp_codes(const int32_t* p, int n0, int n1, int n2, long long ng, 
 hipError_t interp_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
                          const mc_result* res, int dim, int n0, int n1, int n2, bool cubic, int32_t* p, float* xh,
                          hipStream_t s);
+
+// Time-axis predictor from the reference grid ref (k_interp.hip).
+hipError_t temporal_codes(const int32_t* p, const float* ref, const DevBound* bnd, long long ng, uint16_t* codes,
+                          unsigned int* count, unsigned int* gsum, hipStream_t s);
+hipError_t temporal_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
+                           const mc_result* res, const float* ref, long long ng, int32_t* p, float* xh, hipStream_t s);
 
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
                        const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,

@@ -73,7 +73,7 @@ class McCodes(C.Structure):
                 ("v_out_val", C.c_void_p), ("v_out_cap", C.c_int64), ("block_flags", C.c_void_p),
                 ("result", C.c_void_p), ("dbg_resampled", C.c_void_p), ("dbg_grid_p", C.c_void_p),
                 ("dbg_vertex_g", C.c_void_p), ("rho_q", C.c_void_p), ("residual_predictor", C.c_int32),
-                ("grid_predictor", C.c_int32)]
+                ("grid_predictor", C.c_int32), ("grid_ref", C.c_void_p), ("xhat_out", C.c_void_p)]
 
 
 class McTrainOpts(C.Structure):
@@ -386,18 +386,22 @@ def store_tuning(key: str, mask: int):
         pass            # a read-only install keeps tuning per process
 
 
-GRID_PREDICTORS = {"lorenzo": 0, "linear": 1, "cubic": 2}
+GRID_PREDICTORS = {"lorenzo": 0, "linear": 1, "cubic": 2, "temporal": 3}
 
 
 class Codes:
     """Device buffers of one compressed field (allocated with torch)."""
 
     def __init__(self, plan: Plan, dtype, g_cap=None, v_cap=None, learned=False, debug=False,
-                 residual_predictor: str = "none", grid_predictor: str = "lorenzo"):
+                 residual_predictor: str = "none", grid_predictor: str = "lorenzo", grid_ref=None,
+                 xhat_out=None):
         """residual_predictor: "none" or "delta" (1-D Lorenzo along the vertex
         order); grid_predictor: "lorenzo", "linear" or "cubic" (multilevel
-        interpolation); both fixed for the buffers' lifetime, compress and
-        decompress."""
+        interpolation) or "temporal" (from the reference grid grid_ref, a
+        float32 device tensor of n_grid values, normally the previous
+        timestep's x1'); both fixed for the buffers' lifetime, compress and
+        decompress.  xhat_out: optional float32 device tensor of n_grid
+        values that receives x1' at every compress and decompress."""
         torch = _torch()
         ng, nv = plan.n_grid, plan.n_vertices
         g_cap = ng if g_cap is None else g_cap
@@ -422,8 +426,26 @@ class Codes:
             _ptr(self.grid_codes), _ptr(self.g_out_idx), _ptr(self.g_out_delta), g_cap, _ptr(self.vert_codes),
             _ptr(self.v_out_idx), _ptr(self.v_out_val), v_cap, _ptr(self.block_flags), _ptr(self.result),
             _ptr(self.dbg_resampled), _ptr(self.dbg_grid_p), _ptr(self.dbg_vertex_g), _ptr(self.rho_q),
-            {"none": 0, "delta": 1}[residual_predictor], GRID_PREDICTORS[grid_predictor])
+            {"none": 0, "delta": 1}[residual_predictor], GRID_PREDICTORS[grid_predictor],
+            _ptr(self._grid_tensor(grid_ref, ng, "grid_ref")), _ptr(self._grid_tensor(xhat_out, ng, "xhat_out")))
         self.grid_predictor = grid_predictor
+        self.grid_ref, self.xhat_out = grid_ref, xhat_out      # kept alive with the buffers
+
+    def set_grid_ref(self, grid_ref):
+        """Point the time-axis predictor at another reference grid (the next
+        timestep's compress and decompress)."""
+        self.struct.grid_ref = _ptr(self._grid_tensor(grid_ref, self.grid_codes.numel(), "grid_ref"))
+        self.grid_ref = grid_ref
+
+    @staticmethod
+    def _grid_tensor(t, ng, what):
+        if t is None:
+            return None
+        _require_cuda(t, what)
+        torch = _torch()
+        if t.dtype != torch.float32 or t.numel() != ng or not t.is_contiguous():
+            raise ValueError(f"{what} must be a contiguous float32 tensor of n_grid values")
+        return t
 
     def result_host(self) -> dict:
         b = self.result.cpu().numpy().tobytes()
