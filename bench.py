@@ -275,6 +275,12 @@ def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, spli
         times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, codes=cp, **kw)))
         times["plain_d"].append(_timed(lambda: M.decompress(plan, cp, out=out)))
         ep = (x.double() - out.double()).abs().max().item()
+        # the time-axis grid predictor against step t - 1's x1' (same vertex stream)
+        times["temporal_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=ct)))
+        times["temporal_d"].append(_timed(lambda: M.decompress(plan, ct, out=out)))
+        et = (x.double() - out.double()).abs().max().item()
+        hg = ct.host_grid()
+        gb_t = M.grid_stream_bytes(hg["grid_codes"], hg["g_out_idx"], hg["g_out_delta"])
         times["learned_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, model=model, codes=cl,
                                                             **kw)))
         times["learned_d"].append(_timed(lambda: M.decompress(plan, cl, model=model, out=out)))
@@ -305,7 +311,9 @@ def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, spli
 def learned_section(log, train_steps=2000, batch=8192):
     """Learned vs plain on the rotating-front time series over the refined
     2-D mesh: train on t=0, compress t=1..8 both ways at eb 1e-4; CR with the
-    BF16 model charged once to the sequence; both forms' GB/s."""
+    BF16 model charged once to the sequence; both forms' GB/s.  The plain
+    codes are also coded with the time-axis grid predictor against the
+    previous step's x1' (the same vertex stream, other grid codes)."""
     import torch
     import meshgen as G
     from paper_2501_06910_amd import mc as M
@@ -331,16 +339,27 @@ def learned_section(log, train_steps=2000, batch=8192):
     model_bytes = 16 + 2 * M.param_count(D)          # header + BF16 weights
     nT = len(series) - 1
     per_t = []
-    cp, cl = M.Codes(plan, x0.dtype), M.Codes(plan, x0.dtype, learned=True)
+    # x1' of the previous and the current step for the time-axis grid predictor
+    prev = torch.empty(ng, dtype=torch.float32, device="cuda")
+    cur = torch.empty(ng, dtype=torch.float32, device="cuda")
+    M.compress(plan, x0, cfg["eb"], "rel", 0.5, codes=M.Codes(plan, x0.dtype, xhat_out=prev))
+    cp, cl = M.Codes(plan, x0.dtype, xhat_out=cur), M.Codes(plan, x0.dtype, learned=True)
+    ct = M.Codes(plan, x0.dtype, grid_predictor="temporal", grid_ref=prev)
     out = torch.empty_like(x0)
-    tot = {"plain": 0, "learned": 0, "raw": 0, "serial": 0}
-    times = {"plain_c": [], "plain_d": [], "learned_c": [], "learned_d": []}
+    tot = {"plain": 0, "learned": 0, "raw": 0, "serial": 0, "temporal": 0}
+    times = {"plain_c": [], "plain_d": [], "learned_c": [], "learned_d": [], "temporal_c": [], "temporal_d": []}
     sctx, scodes = M.Serial(nv), M.SerialCodes(nv, x0.dtype)
     for t in range(1, len(series)):
         x = torch.from_numpy(series[t]).cuda()
         times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=cp)))
         times["plain_d"].append(_timed(lambda: M.decompress(plan, cp, out=out)))
         ep = (x.double() - out.double()).abs().max().item()
+        # the time-axis grid predictor against step t - 1's x1' (same vertex stream)
+        times["temporal_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=ct)))
+        times["temporal_d"].append(_timed(lambda: M.decompress(plan, ct, out=out)))
+        et = (x.double() - out.double()).abs().max().item()
+        hg = ct.host_grid()
+        gb_t = M.grid_stream_bytes(hg["grid_codes"], hg["g_out_idx"], hg["g_out_delta"])
         times["learned_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, model=model, codes=cl)))
         times["learned_d"].append(_timed(lambda: M.decompress(plan, cl, model=model, out=out)))
         el = (x.double() - out.double()).abs().max().item()
@@ -349,9 +368,13 @@ def learned_section(log, train_steps=2000, batch=8192):
         if hp["result"]["status"] or hl["result"]["status"]:
             raise SystemExit(f"learned section: status {hp['result']['status']} / {hl['result']['status']}")
         tau2 = hp["result"]["tau2"]
-        if not (ep <= tau2 and el <= tau2):
-            raise SystemExit(f"learned section: bound violated at t={t}")
-        sp = M.stream_bytes(hp, sT)["total"]
+        if not (ep <= tau2 and el <= tau2 and et <= tau2) or hg["result"]["status"]:
+            raise SystemExit(f"learned section: bound violated or status at t={t}")
+        sbp = M.stream_bytes(hp, sT)
+        sp = sbp["total"]
+        gb_p = sbp["grid"] + sbp["grid_outliers"]
+        tot["temporal"] += sp - gb_p + gb_t
+        prev.copy_(cur)                                   # x1' of step t: the next step's reference
         sl = M.stream_bytes(hl, sT, model_bytes)["total"] - model_bytes   # model charged once below
         tot["plain"] += sp
         tot["learned"] += sl
@@ -364,6 +387,8 @@ def learned_section(log, train_steps=2000, batch=8192):
         tot["serial"] += ss
         per_t.append({"t": t, "cr_plain": round(nv * sT / sp, 3), "cr_learned": round(nv * sT / (sl + model_bytes / nT), 3),
                       "cr_serial": round(nv * sT / ss, 3),
+                      "cr_temporal_grid": round(nv * sT / (sp - gb_p + gb_t), 3),
+                      "grid_bytes": {"lorenzo": gb_p, "temporal": gb_t},
                       "vert_bits_plain": round(M.entropy_bits(hp["vert_codes"]), 3),
                       "vert_bits_learned": round(M.entropy_bits(hl["vert_codes"]), 3),
                       "learned_blocks": hl["result"]["n_learned_blocks"],
@@ -396,6 +421,9 @@ def learned_section(log, train_steps=2000, batch=8192):
         "cr_plain": round(tot["raw"] / tot["plain"], 3),
         "cr_learned": round(tot["raw"] / (tot["learned"] + model_bytes), 3),
         "cr_serial": round(tot["raw"] / tot["serial"], 3),
+        "cr_temporal_grid": round(tot["raw"] / tot["temporal"], 3),
+        "temporal_GBps": {"compress": round(nv * sT / (med["temporal_c"] * 1e-3) / 1e9, 2),
+                          "decompress": round(nv * sT / (med["temporal_d"] * 1e-3) / 1e9, 2)},
         "improvement_ratio": {"plain": round(tot["serial"] / tot["plain"], 3),
                               "learned": round(tot["serial"] / (tot["learned"] + model_bytes), 3)},
         "plain_GBps": {"compress": round(nv * sT / (med["plain_c"] * 1e-3) / 1e9, 2),
