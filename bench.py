@@ -275,12 +275,6 @@ def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, spli
         times["plain_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, codes=cp, **kw)))
         times["plain_d"].append(_timed(lambda: M.decompress(plan, cp, out=out)))
         ep = (x.double() - out.double()).abs().max().item()
-        # the time-axis grid predictor against step t - 1's x1' (same vertex stream)
-        times["temporal_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", 0.5, codes=ct)))
-        times["temporal_d"].append(_timed(lambda: M.decompress(plan, ct, out=out)))
-        et = (x.double() - out.double()).abs().max().item()
-        hg = ct.host_grid()
-        gb_t = M.grid_stream_bytes(hg["grid_codes"], hg["g_out_idx"], hg["g_out_delta"])
         times["learned_c"].append(_timed(lambda: M.compress(plan, x, cfg["eb"], "rel", split, model=model, codes=cl,
                                                             **kw)))
         times["learned_d"].append(_timed(lambda: M.decompress(plan, cl, model=model, out=out)))
