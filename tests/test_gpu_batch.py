@@ -196,3 +196,48 @@ def test_batch_mixes_operator_pairs_and_residual_coders(workload):
             assert torch.equal(a, b)
     for p in cplans:
         p.destroy()
+
+
+def test_batch_grid_predictors(workload):
+    """One graph over items whose grid codes use the interpolation (linear,
+    cubic) and time-axis predictors, and the inverse graph: every item
+    equals its single call over replays, and the batch decompress equals
+    the single decompress."""
+    meshes, grids, fields, plans, xs = workload
+    refs = {}
+    items, ditems, singles, codes, outs = [], [], [], [], []
+    kinds = ("cubic", "linear", "temporal")
+    for i, f in enumerate(fields):
+        plan = plans[f["mesh"]]
+        gp = kinds[i % 3]
+        kw = {}
+        if gp == "temporal":
+            if f["mesh"] not in refs:              # the reference grid: x1' of another field on the mesh
+                r = torch.empty(plan.n_grid, dtype=torch.float32, device="cuda")
+                M.compress(plan, xs[i], f["eb"], f["eb_mode"], f["split"], codes=M.Codes(plan, xs[i].dtype,
+                                                                                            xhat_out=r))
+                refs[f["mesh"]] = r
+            kw = dict(grid_ref=refs[f["mesh"]])
+        c = M.Codes(plan, xs[i].dtype, grid_predictor=gp, **kw)
+        items.append((plan, xs[i], f["eb"], f["eb_mode"], f["split"], None, c))
+        outs.append(torch.empty_like(xs[i]))
+        ditems.append((plan, c, None, outs[-1]))
+        singles.append(lambda i=i, f=f, gp=gp, kw=kw: M.compress(
+            plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"],
+            codes=M.Codes(plans[f["mesh"]], xs[i].dtype, grid_predictor=gp, **kw)))
+        codes.append(c)
+    print(f"[batch] grid predictors over {len(items)} items", flush=True)
+    for rep in range(3):                                   # capture, then replays
+        for c, o in zip(codes, outs):
+            c.grid_codes.zero_()
+            o.zero_()
+        M.batch_compress(items)
+        M.batch_decompress(ditems)
+        torch.cuda.synchronize()
+        for i, c in enumerate(codes):
+            ref = singles[i]()
+            same(c.host(), ref.host())
+            assert c.result_host()["status"] == 0
+            b = M.decompress(items[i][0], ref)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[i], b), (rep, i)
