@@ -152,6 +152,9 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
     return (x < rem ? x * (per + 1u) : rem * (per + 1u) + (x - rem) * per) + r;
 }
 
+// Two consecutive floats at a 4-byte aligned address.
+typedef float f2a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 // ---------------------------------------------------------------------------
 // g(x1') for N vertices of one thread from their coordinates P: cells, then
 // every corner of every cell, then the nested lerps (x, then y, then z) in
@@ -171,18 +174,25 @@ __device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const Grid
         if (D == 3) axis_cell(P[i][2], gg.of[2], gg.ihf[2], gg.n2, i2, t[i][2]);
         j[i] = (unsigned)i0 + n0 * (unsigned)i1 + n01 * (unsigned)i2;
     }
+    // the two corners of a cell edge along x are adjacent: one 8-byte load
+    // each (4-byte aligned, which global loads of two dwords accept), half
+    // the gather instructions of single-value loads
     float c[N][8];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        c[i][0] = xh[j[i]];
-        c[i][1] = xh[j[i] + 1];
-        c[i][2] = xh[j[i] + n0];
-        c[i][3] = xh[j[i] + n0 + 1];
+        const f2a4 e0 = *reinterpret_cast<const f2a4*>(xh + j[i]);
+        const f2a4 e1 = *reinterpret_cast<const f2a4*>(xh + j[i] + n0);
+        c[i][0] = e0.x;
+        c[i][1] = e0.y;
+        c[i][2] = e1.x;
+        c[i][3] = e1.y;
         if (D == 3) {
-            c[i][4] = xh[j[i] + n01];
-            c[i][5] = xh[j[i] + n01 + 1];
-            c[i][6] = xh[j[i] + n01 + n0];
-            c[i][7] = xh[j[i] + n01 + n0 + 1];
+            const f2a4 e2 = *reinterpret_cast<const f2a4*>(xh + j[i] + n01);
+            const f2a4 e3 = *reinterpret_cast<const f2a4*>(xh + j[i] + n01 + n0);
+            c[i][4] = e2.x;
+            c[i][5] = e2.y;
+            c[i][6] = e3.x;
+            c[i][7] = e3.y;
         }
     }
 #pragma unroll
