@@ -211,15 +211,19 @@ __device__ __forceinline__ VGeom vertex_geom(const float* __restrict__ coords, l
     const unsigned n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
     const unsigned j = (unsigned)q.i0 + (unsigned)n0 * (unsigned)q.i1 + n01 * (unsigned)q.i2;
     float c[8];
-    c[0] = xh[j];
-    c[1] = xh[j + 1];
-    c[2] = xh[j + n0];
-    c[3] = xh[j + n0 + 1];
+    const f2a4 e0 = *reinterpret_cast<const f2a4*>(xh + j);       // x-adjacent corners: one 8-byte load
+    const f2a4 e1 = *reinterpret_cast<const f2a4*>(xh + j + n0);
+    c[0] = e0.x;
+    c[1] = e0.y;
+    c[2] = e1.x;
+    c[3] = e1.y;
     if (D == 3) {
-        c[4] = xh[j + n01];
-        c[5] = xh[j + n01 + 1];
-        c[6] = xh[j + n01 + n0];
-        c[7] = xh[j + n01 + n0 + 1];
+        const f2a4 e2 = *reinterpret_cast<const f2a4*>(xh + j + n01);
+        const f2a4 e3 = *reinterpret_cast<const f2a4*>(xh + j + n01 + n0);
+        c[4] = e2.x;
+        c[5] = e2.y;
+        c[6] = e3.x;
+        c[7] = e3.y;
     }
     const float c00 = lerpf_(c[0], c[1], q.t0);
     const float c10 = lerpf_(c[2], c[3], q.t0);
