@@ -389,13 +389,22 @@ __global__ __launch_bounds__(256) void k_fill_nearest(const float* __restrict__ 
     float bd = 0.0f;
     long long bv = -1;
     for (int r = 0; r <= rmax; ++r) {
+        // the ring's bins inside the bin grid only: (dz, dy) over the ring's
+        // cross-section clamped to the grid; dx over the whole clamped row
+        // where (dz, dy) is on the ring already, else only dx = -r and +r
+        // (a ring scanned as a full cube costs (2r + 1)^3 steps, far too many
+        // on a grid much finer along one axis, where many rings are needed)
         const int zr = D == 3 ? r : 0;
-        for (int dz = -zr; dz <= zr; ++dz)
-            for (int dy = -r; dy <= r; ++dy)
-                for (int dx = -r; dx <= r; ++dx) {
-                    if (max(max(abs(dx), abs(dy)), abs(dz)) != r) continue;
+        const int z0 = max(-zr, -c2), z1 = min(zr, nb2 - 1 - c2);
+        const int y0 = max(-r, -c1), y1 = min(r, nb1 - 1 - c1);
+        const int x0 = max(-r, -c0), x1 = min(r, nb0 - 1 - c0);
+        for (int dz = z0; dz <= z1; ++dz)
+            for (int dy = y0; dy <= y1; ++dy) {
+                const bool edge = max(abs(dy), abs(dz)) == r;
+                const int xs = edge ? 1 : 2 * r;                   // step: every dx, or -r then +r
+                for (int dx = edge ? x0 : -r; dx <= (edge ? x1 : r); dx += (xs > 0 ? xs : 1)) {
+                    if (dx < x0 || dx > x1) continue;
                     const int b0 = c0 + dx, b1 = c1 + dy, b2 = c2 + dz;
-                    if (b0 < 0 || b1 < 0 || b2 < 0 || b0 >= nb0 || b1 >= nb1 || b2 >= nb2) continue;
                     const long long b = b0 + (long long)nb0 * (b1 + (long long)nb1 * b2);
                     for (long long k = start[b]; k < start[b + 1]; ++k) {
                         const long long v = list[k];
@@ -409,6 +418,7 @@ __global__ __launch_bounds__(256) void k_fill_nearest(const float* __restrict__ 
                         if (bv < 0 || dd < bd || (dd == bd && v < bv)) { bd = dd; bv = v; }
                     }
                 }
+            }
         if (bv >= 0) {
             double lb = (double)r * VB * hmin - eps;
             if (lb > 0.0 && (double)bd < lb * lb * (1.0 - 1e-5)) break;

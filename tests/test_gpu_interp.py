@@ -161,6 +161,33 @@ def test_interp_full_size():
     print(f"[interp] full size: grid outliers {oc.out_idx.size}")
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2), (3, 2, 2), (2, 2, 65), (8192, 2, 2), (2, 3, 1000)])
+@pytest.mark.parametrize("gpred", ["linear", "cubic", "temporal"])
+def test_extreme_grid_shapes(dims, gpred):
+    """Smallest grids (only the coarse workgroup), the widest x extent and
+    long thin grids along y and z (many fine launches of few nodes)."""
+    mesh = G.kuhn_tet_mesh(9, 4)
+    x = G.field_octaves(mesh.coords, np.random.default_rng(8))
+    print(f"[interp] extreme {dims} {gpred}", flush=True)
+    og = O.grid_from_dims(mesh.coords, dims)
+    om = O.locate(mesh.coords, mesh.cells, og)
+    ref = None
+    if gpred == "temporal":
+        ref = O.compress(mesh.coords, om, og, (x * np.float32(0.99)).astype(np.float32), 1e-4, True, 0.5).xhat
+    gp = {"linear": O.GPRED_LINEAR, "cubic": O.GPRED_CUBIC, "temporal": O.GPRED_TEMPORAL}[gpred]
+    oc = O.compress(mesh.coords, om, og, x, 1e-4, True, 0.5, gpred=gp, gref=ref)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    xt = dev(x)
+    kw = {} if ref is None else dict(grid_ref=dev(ref))
+    codes = M.Codes(plan, xt.dtype, grid_predictor=gpred, **kw)
+    M.compress(plan, xt, 1e-4, "rel", 0.5, codes=codes)
+    out = M.decompress(plan, codes)
+    torch.cuda.synchronize()
+    check_grid(codes.host(), oc)
+    xo = O.decompress(mesh.coords, og, oc.bound, oc.grid, oc.vert, x.dtype, gpred=gp, gref=ref)
+    assert np.array_equal(out.cpu().numpy().view(np.uint8), xo.view(np.uint8))
+
+
 def test_unknown_grid_predictor_rejected():
     mesh = G.kuhn_tet_mesh(9, 2)
     x = dev(G.field_octaves(mesh.coords, np.random.default_rng(6)))
