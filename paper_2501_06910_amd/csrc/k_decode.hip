@@ -1,5 +1,6 @@
 // k_decode.hip -- decompression on gfx950 (paper Alg. 4).
-//   k_dec_xy_* Lorenzo inverse within each z-plane: d = code - R (outliers
+//   k_d2_*     2-D Lorenzo inverse on 256-column row segments (below)
+//   k_dec_xy_* (3-D) inverse within each z-plane: d = code - R (outliers
 //              by binary search in the ascending outlier list); column
 //              totals per chunk of rows, their prefix over the plane's
 //              chunks, then running column sums plus a wave scan along x
@@ -23,40 +24,12 @@ __device__ __forceinline__ int wave_excl_scan(int v)
 // 2 tau1) directly.  Tiles: (chunk of rows) x (all x) per plane for the xy
 // part, (chunk of planes) x (the same chunk of rows) for the z part, so the
 // z pass can also emit the xy column totals.
-//   k_dec_xy_tot    2-D: column totals of each (plane, row chunk) tile
 //   k_dec_xy_carry  per (plane, column): exclusive prefix over row chunks
 //   k_dec_xy_apply  running column sums from the carry, x-scan of each row,
-//                   x1' written (input: codes in 2-D, z-prefixed errors in 3-D)
+//                   x1' written (input: the z-prefixed errors)
 //   k_dec_z_tot     3-D: per (plane chunk, position): sum of the errors
 //   k_dec_z_carry   per position: exclusive prefix over plane chunks
 //   k_dec_z_apply   z-prefixed errors + xy column totals of every tile
-template <int CPT>
-__global__ __launch_bounds__(256) void k_dec_xy_tot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
-                                                    const int32_t* __restrict__ odelta,
-                                                    const mc_result* __restrict__ res, long long gcap, int n0, int n1,
-                                                    int rows, int nyc, long long ntiles, int* __restrict__ agg)
-{
-    const long long tile = (long long)xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
-    if (tile >= ntiles) return;
-    const int z = (int)(tile / nyc), yc = (int)(tile % nyc);
-    const int y0 = yc * rows, y1 = min(n1, y0 + rows);
-    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
-    const int c0 = lane_id() * CPT;
-    const long long plane = (long long)z * n1 * n0;
-    int tot[CPT];
-#pragma unroll
-    for (int k = 0; k < CPT; ++k) tot[k] = 0;
-    for (int y = y0; y < y1; ++y) {
-        const long long base_r = plane + (long long)y * n0;
-#pragma unroll
-        for (int k = 0; k < CPT; ++k)
-            if (c0 + k < n0) tot[k] += delta_at(codes, oidx, odelta, nout, base_r + c0 + k);
-    }
-#pragma unroll
-    for (int k = 0; k < CPT; ++k)
-        if (c0 + k < n0) agg[tile * n0 + c0 + k] = tot[k];
-}
-
 // Exclusive prefix over chunks, in place: one thread per position, the
 // chunk values loaded 32 at a time before any is used.
 __device__ __forceinline__ void excl_prefix_strided(int* __restrict__ a, long long first, long long stride, int n)
@@ -435,6 +408,153 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
     }
 }
 
+// ---------------------------------------------------------------------------
+// 2-D decode on row segments.  A wave owns a segment of 256 columns (lane l:
+// columns 256 sg + l + 64 k, k < 4, so every load and store is coalesced)
+// and a chunk of MC_D2_R rows; with Y(x, y) the column prefix of the
+// errors (the difference of the decoded grid along x) and S(y, sg) its sum
+// over a segment,
+//   k_d2_tot    per (segment, chunk): the chunk's column totals of the errors
+//   (k_dec_xy_carry: exclusive prefix over the chunks, in place)
+//   k_d2_rowsum per (segment, chunk): Y from the carries, S written per row
+//   k_d2_apply  per (segment, chunk): Y again, its prefix along the segment
+//               (four wave scans) plus the S of the segments to the left:
+//               the decoded grid, x1' written
+// Every partial sum is a difference of two decoded values, so int32 holds it.
+__device__ __forceinline__ void d2_unit(int unit, int nseg, int n0, int n1, int& sg, int& y0, int& y1)
+{
+    sg = unit % nseg;
+    y0 = (unit / nseg) * MC_D2_R;
+    y1 = min(n1, y0 + MC_D2_R);
+}
+
+// The errors of rows y0 .. y0 + MC_D2_R - 1 (past n1 and past n0: 0) at the
+// lane's four columns, every code load issued before any is used.
+__device__ __forceinline__ void d2_errors(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                          const int32_t* __restrict__ odelta, long long nout, int n0, int n1, int x0,
+                                          int y0, int y1, int (&e)[MC_D2_R][4])
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = min(x0 + l + 64 * k, n0 - 1), y = min(y0 + r, n1 - 1);
+            e[r][k] = codes[(long long)y * n0 + x];
+        }
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int x = x0 + l + 64 * k, y = y0 + r;
+            int d = e[r][k] - MC_R;
+            if (e[r][k] == 0) {
+                const long long o = find_outlier(oidx, nout, (long long)min(y, n1 - 1) * n0 + min(x, n0 - 1));
+                d = o >= 0 ? odelta[o] : 0;
+            }
+            e[r][k] = (x < n0 && y < y1) ? d : 0;
+        }
+}
+
+__global__ __launch_bounds__(256) void k_d2_tot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                const int32_t* __restrict__ odelta, const mc_result* __restrict__ res,
+                                                long long gcap, int n0, int n1, int nseg, int nunits,
+                                                int* __restrict__ agg)
+{
+    const int unit = (int)xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (unit >= nunits) return;
+    int sg, y0, y1;
+    d2_unit(unit, nseg, n0, n1, sg, y0, y1);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    int e[MC_D2_R][4];
+    d2_errors(codes, oidx, odelta, nout, n0, n1, sg * 256, y0, y1, e);
+    const long long row = (long long)(unit / nseg) * n0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int t = 0;
+#pragma unroll
+        for (int r = 0; r < MC_D2_R; ++r) t += e[r][k];
+        const int x = sg * 256 + lane_id() + 64 * k;
+        if (x < n0) agg[row + x] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_d2_rowsum(const uint16_t* __restrict__ codes,
+                                                   const int32_t* __restrict__ oidx,
+                                                   const int32_t* __restrict__ odelta,
+                                                   const mc_result* __restrict__ res, long long gcap, int n0, int n1,
+                                                   int nseg, int nunits, const int* __restrict__ carry,
+                                                   int* __restrict__ segsum)
+{
+    const int unit = (int)xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (unit >= nunits) return;
+    int sg, y0, y1;
+    d2_unit(unit, nseg, n0, n1, sg, y0, y1);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    const long long row = (long long)(unit / nseg) * n0;
+    int col[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = sg * 256 + lane_id() + 64 * k;
+        col[k] = x < n0 ? carry[row + x] : 0;
+    }
+    int e[MC_D2_R][4];
+    d2_errors(codes, oidx, odelta, nout, n0, n1, sg * 256, y0, y1, e);
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r) {
+        int t = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            col[k] += e[r][k];
+            t += col[k];
+        }
+        t = wave_sum(t);
+        if (lane_id() == 0 && y0 + r < y1) segsum[(long long)(y0 + r) * nseg + sg] = t;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_d2_apply(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                  const int32_t* __restrict__ odelta,
+                                                  const mc_result* __restrict__ res, long long gcap, int n0, int n1,
+                                                  int nseg, int nunits, const int* __restrict__ carry,
+                                                  const int* __restrict__ segsum, float* __restrict__ xh)
+{
+    const int unit = (int)xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    if (unit >= nunits) return;
+    int sg, y0, y1;
+    d2_unit(unit, nseg, n0, n1, sg, y0, y1);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    const double c = res->c, step1 = 2.0 * res->tau1;
+    const long long row = (long long)(unit / nseg) * n0;
+    const int l = lane_id();
+    int col[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = sg * 256 + l + 64 * k;
+        col[k] = x < n0 ? carry[row + x] : 0;
+    }
+    // the segment sums to the left of this one, per row (nseg <= 32 lanes)
+    int left[MC_D2_R];
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r)
+        left[r] = (l < sg && y0 + r < y1) ? segsum[(long long)(y0 + r) * nseg + l] : 0;
+    int e[MC_D2_R][4];
+    d2_errors(codes, oidx, odelta, nout, n0, n1, sg * 256, y0, y1, e);
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r) {
+        if (y0 + r >= y1) break;                         // uniform across the wave
+        int run = wave_sum(left[r]);
+        const long long base = (long long)(y0 + r) * n0 + sg * 256 + l;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            col[k] += e[r][k];
+            const int inc = wave_incl_scan(col[k]);
+            if (sg * 256 + l + 64 * k < n0) xh[base + 64 * k] = xhat_of(run + inc, c, step1);
+            run += __shfl(inc, 63, 64);
+        }
+    }
+}
+
 namespace mck {
 
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
@@ -445,20 +565,32 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
     const int cpt = (n0 + 63) / 64;
     const unsigned nb_xy = (unsigned)((ws.ntiles_xy + 3) / 4);
     if (dim == 2) {
-        ProfScope ps("k_dec_xy_tot", s);
-#define MC_DXT(C) hipLaunchKernelGGL(k_dec_xy_tot<C>, dim3(nb_xy), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, \
-                                     n1, ws.rows, ws.nyc, ws.ntiles_xy, ws.agg_xy)
-        if (cpt <= 1) MC_DXT(1);
-        else if (cpt <= 2) MC_DXT(2);
-        else if (cpt <= 4) MC_DXT(4);
-        else if (cpt <= 8) MC_DXT(8);
-        else if (cpt <= 16) MC_DXT(16);
-        else if (cpt <= 32) MC_DXT(32);
-        else if (cpt <= 64) MC_DXT(64);
-        else MC_DXT(128);
-#undef MC_DXT
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-    } else if (ws.fast3) {
+        const int nseg = (n0 + 255) / 256, nunits = nseg * ws.nyc;
+        const dim3 g((unsigned)((nunits + 3) / 4));
+        {
+            ProfScope ps("k_dec_xy_tot", s);
+            hipLaunchKernelGGL(k_d2_tot, g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, nseg, nunits,
+                               ws.agg_xy);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_xy_carry", s);
+            hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)((n0 + 255) / 256)), dim3(256), 0, s, ws.agg_xy, n0, 1,
+                               ws.nyc);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        {
+            ProfScope ps("k_dec_xy_rowsum", s);
+            hipLaunchKernelGGL(k_d2_rowsum, g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, nseg, nunits,
+                               ws.agg_xy, ws.segsum);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        ProfScope ps("k_dec_xy_apply", s);
+        hipLaunchKernelGGL(k_d2_apply, g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, nseg, nunits,
+                           ws.agg_xy, ws.segsum, xh);
+        return hipGetLastError();
+    }
+    if (ws.fast3) {
         const long long nxy = (long long)n0 * n1;
         const int nxs = (n0 + 255) / 256;
         {
@@ -550,7 +682,7 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         ProfScope ps("k_dec_xy_apply", s);
 #define MC_DXA(C, F) hipLaunchKernelGGL((k_dec_xy_apply<C, F>), dim3(nb_xy), dim3(256), 0, s, codes, oidx, odelta, pz, res, \
                                         gcap, n0, n1, ws.rows, ws.nyc, ws.ntiles_xy, ws.agg_xy, xh)
-#define MC_DXA2(C) do { if (dim == 2) MC_DXA(C, true); else MC_DXA(C, false); } while (0)
+#define MC_DXA2(C) MC_DXA(C, false)
         if (cpt <= 1) MC_DXA2(1);
         else if (cpt <= 2) MC_DXA2(2);
         else if (cpt <= 4) MC_DXA2(4);

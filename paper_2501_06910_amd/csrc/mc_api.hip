@@ -434,8 +434,7 @@ static void decode_ws_shape(mc_plan p)
     }
     long long rows;
     if (p->dim == 2) {
-        rows = (n1 + 1023) / 1024;          // about 1024 wave tiles
-        if (rows < 4) rows = 4;
+        rows = MC_D2_R;                     // rows per chunk of the row-segment decoder
     } else {
         long long cx = 1;                     // columns per thread of the z pass, as instantiated
         while (cx * 256 < n0) cx *= 2;
@@ -668,6 +667,7 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     decode_ws_shape(p);
     PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * grid->dims[0]));
     if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * grid->dims[0] * grid->dims[1]));
+    if (dim == 2) PCHK(plan_alloc(p, &p->dws.segsum, (size_t)grid->dims[1] * ((grid->dims[0] + 255) / 256)));
     PCHK(plan_alloc(p, &p->xh, (size_t)ng));
     PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * MC_RANGE_BLOCKS));
     PCHK(hipStreamSynchronize(s));

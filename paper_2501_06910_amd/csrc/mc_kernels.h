@@ -88,6 +88,7 @@ enum {
     MC_KNOB_ALL = 0x7fu
 };
 
+#define MC_D2_R 8                  // 2-D decode: rows per chunk (rows of DecodeWs in 2-D)
 struct DecodeWs {
     bool fast3;                    // 3-D with n0 % 4 == 0 and n0 <= 1024: the quad kernels
     int rows, nyc;                 // rows per tile, row chunks per plane
@@ -95,6 +96,7 @@ struct DecodeWs {
     int* agg_xy;                   // [ntiles_xy][n0] column totals, then carries
     int zplanes, nzc;              // 3-D: planes per chunk, plane chunks
     int* agg_z;                    // [nzc][n0*n1] chunk totals, then carries
+    int* segsum;                   // 2-D: [n1][ceil(n0 / 256)] row-segment sums
 };
 // ---- multilevel interpolation grid predictor (k_interp.hip) ---------------
 // Codes of the prequantised grid p (outliers counted per tile, as lorenzo).
