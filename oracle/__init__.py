@@ -103,6 +103,7 @@ def lib():
             "mco_residual_quantize": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
             "mco_grid_quantize_f64": (i32, [P, P, P, P, P, P, P, i64, P]),
             "mco_nearest_nodes": (None, [P, i32, i64, P, P]),
+            "mco_grid_coarsen": (None, [P, i64, P, P, P, P]),
             "mco_grid_init": (i32, [P, P, i32, i64, i64, dbl, i64, P, P]),
             "mco_residual_delta": (i32, [P, i32, i64, P, P, P, P, P, i64, P]),
             "mco_vertex_decode_delta": (None, [P, P, P, i64, P, P, i32, i64, P]),
@@ -543,6 +544,17 @@ def nearest_nodes(coords: np.ndarray, g: Grid) -> np.ndarray:
     return m
 
 
+def grid_coarsen(m: np.ndarray, g: Grid):
+    """Grid_Coarsen (Alg. 2): (keep, coarsened grid, m on it); keep holds each
+    plane's coarsened index or -1, axis 0 then 1 then 2."""
+    keep = np.empty(int(sum(g.dims())), np.int32)
+    nn = (C.c_int64 * 3)()
+    mo = np.empty_like(m)
+    lib().mco_grid_coarsen(_p(np.ascontiguousarray(m, np.int32)), m.size, _p(g), _p(keep), nn, _p(mo))
+    gc = make_grid(g.dim, tuple(int(v) for v in nn), tuple(g.o), tuple(g.h))
+    return keep, gc, mo
+
+
 def cluster_mean(x: np.ndarray, m: np.ndarray, ng: int, c: float):
     """Cluster-mean f (Sec. IV-D): (x1 float64[ng], count int32[ng])."""
     x1 = np.empty(ng, np.float64)
@@ -600,11 +612,14 @@ class ClusterCompressed:
 
 def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, split: float,
                      open_loop: bool = True, mode: int = SPLIT_SUM, delta: bool = False,
-                     gpred: int = GPRED_LORENZO, gref=None) -> ClusterCompressed:
+                     gpred: int = GPRED_LORENZO, gref=None, coarsen: bool = False) -> ClusterCompressed:
     """Alg. 3 with the nearest-node g and the cluster-mean f; delta: the
-    closed-loop residuals through the 1-D Lorenzo predictor (g_k = x1'[m_k])."""
+    closed-loop residuals through the 1-D Lorenzo predictor (g_k = x1'[m_k]);
+    coarsen: on the grid of Grid_Coarsen (Alg. 2)."""
     b = bound(x, eb, relative, split, mode)
     m = nearest_nodes(coords, g)
+    if coarsen:
+        _, g, m = grid_coarsen(m, g)
     x1, cnt = cluster_mean(x, m, g.count, b.c)
     gc = grid_quantize_f64(x1, g, b)
     if gpred != GPRED_LORENZO:
@@ -620,10 +635,13 @@ def compress_cluster(coords, g: Grid, x: np.ndarray, eb: float, relative: bool, 
 
 
 def decompress_cluster(coords, g: Grid, b: Bound, gc: GridCodes, vc: VertexCodes, dtype,
-                       delta: bool = False, gpred: int = GPRED_LORENZO, gref=None) -> np.ndarray:
-    """Alg. 4 with the nearest-node g."""
-    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred, gref, b)
+                       delta: bool = False, gpred: int = GPRED_LORENZO, gref=None,
+                       coarsen: bool = False) -> np.ndarray:
+    """Alg. 4 with the nearest-node g (coarsen: the grid of Grid_Coarsen)."""
     m = nearest_nodes(coords, g)
+    if coarsen:
+        _, g, m = grid_coarsen(m, g)
+    p = grid_decode(gc.codes, gc.out_idx, gc.out_delta, g, gpred, gref, b)
     xhat = grid_recon(p, b)
     if delta:
         return vertex_decode_delta(vc, xhat[m], b, dtype)

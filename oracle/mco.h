@@ -155,6 +155,9 @@ void mco_cluster_mean(const void* x, int dtype, int64_t nv, const int32_t* m, in
 int mco_residual_nearest(const void* x, int dtype, int64_t nv, const int32_t* m, const double* x1,
                          const float* xhat, const mco_bound* b, int open, uint16_t* codes, int32_t* out_idx,
                          void* out_val, int64_t cap, int64_t* n_out);
+/* Grid_Coarsen (Alg. 2) for the nearest-node g (mco_cluster.c). */
+void mco_grid_coarsen(const int32_t* m, int64_t nv, const mco_grid* g, int32_t* keep, int64_t new_n[3],
+                      int32_t* m_out);
 void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, const void* out_val, int64_t n_out,
                                const int32_t* m, const float* xhat, const mco_bound* b, int dtype, int64_t nv,
                                void* xout);

@@ -106,3 +106,38 @@ void mco_vertex_decode_nearest(const uint16_t* codes, const int32_t* out_idx, co
         else ((float*)xout)[i] = (float)v;
     }
 }
+
+/* Grid_Coarsen (Alg. 2) for the nearest-node g: a grid plane (all nodes
+ * with one coordinate fixed along one axis) that no vertex maps to is
+ * dropped, axis by axis; an axis left with fewer than two planes keeps all
+ * of its planes.  keep[off_d + i] is plane i's index on the coarsened axis
+ * d, or -1 when dropped (off_0 = 0, off_1 = n_0, off_2 = n_0 + n_1);
+ * new_n the coarsened extents; m_out the vertices' nodes on the coarsened
+ * grid.  Only the node indices change: every vertex keeps its node. */
+void mco_grid_coarsen(const int32_t* m, int64_t nv, const mco_grid* g, int32_t* keep, int64_t new_n[3],
+                      int32_t* m_out)
+{
+    const int64_t n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+    const int64_t off[3] = {0, n0, n0 + n1};
+    for (int64_t i = 0; i < n0 + n1 + n2; ++i) keep[i] = 0;
+    for (int64_t k = 0; k < nv; ++k) {            /* visited planes */
+        const int64_t j = m[k];
+        keep[off[0] + j % n0] = 1;
+        keep[off[1] + (j / n0) % n1] = 1;
+        keep[off[2] + j / (n0 * n1)] = 1;
+    }
+    for (int d = 0; d < 3; ++d) {
+        int64_t cnt = 0;
+        for (int64_t i = 0; i < g->n[d]; ++i) cnt += keep[off[d] + i];
+        if (cnt < 2 && g->n[d] >= 2)
+            for (int64_t i = 0; i < g->n[d]; ++i) keep[off[d] + i] = 1;
+        int64_t next = 0;
+        for (int64_t i = 0; i < g->n[d]; ++i) keep[off[d] + i] = keep[off[d] + i] ? (int32_t)next++ : -1;
+        new_n[d] = next;
+    }
+    for (int64_t k = 0; k < nv; ++k) {
+        const int64_t j = m[k];
+        const int64_t a = keep[off[0] + j % n0], b = keep[off[1] + (j / n0) % n1], c = keep[off[2] + j / (n0 * n1)];
+        m_out[k] = (int32_t)(a + new_n[0] * (b + new_n[1] * c));
+    }
+}

@@ -110,3 +110,50 @@ def test_bound_codes_and_roundtrip(eb, split, open_loop, mode, dtype):
     assert np.array_equal(cz.grid.p, np.rint((cz.x1 - b.c) * b.inv1).astype(np.int32))
     if eb == 1e-6:
         assert cz.vert.out_idx.size > 0 or cz.grid.out_idx.size > 0
+
+
+@pytest.mark.parametrize("dims", [(40, 37, 33), (60, 58, 50), (12, 11, 10)])
+def test_grid_coarsen_planes(dims):
+    """Grid_Coarsen (Alg. 2): the kept planes of each axis are exactly those
+    holding a vertex's nearest node (numpy's unique over the node
+    coordinates, an independent count), in their original order; every
+    vertex keeps its node's original coordinates."""
+    mesh = G.kuhn_tet_mesh(22, 5)
+    g = O.grid_from_dims(mesh.coords, dims)
+    m = O.nearest_nodes(mesh.coords, g)
+    keep, gc, mc = O.grid_coarsen(m, g)
+    n = g.dims()
+    coords = [m % n[0], (m // n[0]) % n[1], m // (n[0] * n[1])]
+    off = [0, n[0], n[0] + n[1]]
+    back = []
+    for d in range(3):
+        visited = np.unique(coords[d])
+        k = keep[off[d]:off[d] + n[d]]
+        expect = visited if visited.size >= 2 or n[d] < 2 else np.arange(n[d])
+        assert np.array_equal(np.nonzero(k >= 0)[0], expect)
+        assert np.array_equal(k[k >= 0], np.arange(expect.size))
+        assert gc.dims()[d] == expect.size
+        back.append(np.nonzero(k >= 0)[0])
+    nc = gc.dims()
+    cc = [mc % nc[0], (mc // nc[0]) % nc[1], mc // (nc[0] * nc[1])]
+    for d in range(3):
+        assert np.array_equal(back[d][cc[d]], coords[d])
+    print(f"coarsened {dims} -> {nc}")
+
+
+def test_grid_coarsen_keeps_every_value():
+    """The dropped planes hold no vertex, so on the coarsened grid every
+    cluster mean, vertex code and decoded value is the same as on the full
+    grid (open and closed loop); only the grid codes shrink."""
+    mesh = G.kuhn_tet_mesh(22, 5)
+    x = G.field_octaves(mesh.coords, np.random.default_rng(3))
+    g = O.grid_from_dims(mesh.coords, (60, 58, 50))     # finer than the vertex lattice: empty planes
+    for open_loop in (True, False):
+        full = O.compress_cluster(mesh.coords, g, x, 1e-4, True, 0.5, open_loop)
+        co = O.compress_cluster(mesh.coords, g, x, 1e-4, True, 0.5, open_loop, coarsen=True)
+        assert co.grid.codes.size < full.grid.codes.size
+        assert np.array_equal(co.x1[co.m], full.x1[full.m])
+        assert np.array_equal(co.vert.codes, full.vert.codes)
+        a = O.decompress_cluster(mesh.coords, g, full.bound, full.grid, full.vert, x.dtype)
+        b = O.decompress_cluster(mesh.coords, g, co.bound, co.grid, co.vert, x.dtype, coarsen=True)
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
