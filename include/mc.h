@@ -93,6 +93,11 @@ typedef struct {
     mc_fill fill;            /* nodes outside every cell: nearest vertex (default) or mid-range */
     int32_t bin_nodes;       /* point-location bin edge in grid nodes (0 = tuned default) */
     int32_t operators;       /* mc_operators (0 = MC_OPS_LINEAR) */
+    int32_t coarsen;         /* 1: Grid_Coarsen (Alg. 2), MC_OPS_CLUSTER only (else MC_ERR_UNSUPPORTED):
+                                a grid plane that no vertex's nearest node lies in is dropped, axis by axis
+                                (an axis left with fewer than two planes keeps all of them); the plan then
+                                works on the coarsened grid, whose dims mc_plan_get_grid returns and whose
+                                planes mc_plan_kept_planes lists; 0: the grid as given */
 } mc_plan_opts;
 
 typedef struct {
@@ -269,9 +274,16 @@ mc_status mc_plan_get_info(mc_plan plan, mc_plan_info* out);
 mc_status mc_plan_mapping(mc_plan plan, int32_t* d_vid, float* d_w, int32_t* d_cell,
                           hipStream_t stream);
 mc_status mc_plan_get_grid(mc_plan plan, mc_grid* out);
-/* Copies the nearest node of every vertex, d_m int32[n_vertices]
- * (MC_OPS_CLUSTER plans; MC_ERR_UNSUPPORTED otherwise). */
+/* Copies the nearest node of every vertex, d_m int32[n_vertices], on the
+ * plan's (coarsened) grid (MC_OPS_CLUSTER plans; MC_ERR_UNSUPPORTED
+ * otherwise). */
 mc_status mc_plan_nodes(mc_plan plan, int32_t* d_m, hipStream_t stream);
+/* Grid_Coarsen (Alg. 2) of a plan made with mc_plan_opts.coarsen = 1 (sync):
+ * h_keep (host, int32[dims0 + dims1 + dims2] of the grid given at plan
+ * creation, axis 0 first) receives each original plane's index on the
+ * coarsened axis, or -1 where the plane was dropped.  MC_ERR_CAPACITY if
+ * cap is smaller; MC_ERR_UNSUPPORTED for a plan without coarsening. */
+mc_status mc_plan_kept_planes(mc_plan plan, int32_t* h_keep, int64_t cap);
 mc_status mc_plan_destroy(mc_plan plan);
 
 /* Compress one field (Alg. 3, residuals against the reconstructed grid). */

@@ -39,6 +39,36 @@ __global__ __launch_bounds__(256) void k_nearest_node(const float* __restrict__ 
 }
 
 // Nodes no vertex maps to.
+// Grid_Coarsen (Alg. 2): every plane holding a vertex's node is marked
+// (flags: axis 0, then 1, then 2; each mark writes the same 1).
+__global__ __launch_bounds__(256) void k_mark_planes(const int32_t* __restrict__ m, long long nv, int n0, int n1, int n2,
+                                                     int* __restrict__ flags)
+{
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nv) return;
+    const unsigned j = (unsigned)m[k], r = j / (unsigned)n0;
+    flags[j - r * (unsigned)n0] = 1;
+    flags[n0 + (int)(r % (unsigned)n1)] = 1;
+    flags[n0 + n1 + (int)(r / (unsigned)n1)] = 1;
+    (void)n2;
+}
+
+// Every vertex's node on the coarsened grid (c0 x c1 x ...) from the kept
+// planes' new indices, and the vertex count per coarsened node.
+__global__ __launch_bounds__(256) void k_remap_nodes(int32_t* __restrict__ m, long long nv, int n0, int n1,
+                                                     const int* __restrict__ keep, int c0, int c1,
+                                                     unsigned int* __restrict__ count)
+{
+    const long long k = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nv) return;
+    const unsigned j = (unsigned)m[k], r = j / (unsigned)n0;
+    const int a = keep[j - r * (unsigned)n0], b = keep[n0 + (int)(r % (unsigned)n1)],
+              c = keep[n0 + n1 + (int)(r / (unsigned)n1)];
+    const int jn = a + c0 * (b + c1 * c);
+    m[k] = jn;
+    atomicAdd(&count[jn], 1u);
+}
+
 __global__ __launch_bounds__(256) void k_count_empty(const unsigned int* __restrict__ count, long long ng,
                                                      unsigned int* __restrict__ out)
 {
@@ -215,6 +245,20 @@ hipError_t nearest_nodes(const float* coords, int dim, long long nv, NodeGeom g,
 {
     ProfScope ps("k_nearest_node", s);
     hipLaunchKernelGGL(k_nearest_node, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, coords, dim, nv, g, m,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t mark_planes(const int32_t* m, long long nv, int n0, int n1, int n2, int* flags, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mark_planes, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, m, nv, n0, n1, n2, flags);
+    return hipGetLastError();
+}
+
+hipError_t remap_nodes(int32_t* m, long long nv, int n0, int n1, const int* keep, int c0, int c1, unsigned* count,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(k_remap_nodes, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, m, nv, n0, n1, keep, c0, c1,
                        count);
     return hipGetLastError();
 }

@@ -461,7 +461,8 @@ static void decode_ws_shape(mc_plan p)
 // order (the cluster-mean f sums in that order).
 static mc_status build_cluster_map(mc_plan p, hipStream_t s)
 {
-    const long long nv = p->nv, ng = p->ng;
+    const long long nv = p->nv;
+    long long ng = p->ng;
     hipError_t e = hipSuccess;
 #define CCHK(expr)                                                                                   \
     do {                                                                                             \
@@ -493,6 +494,40 @@ static mc_status build_cluster_map(mc_plan p, hipStream_t s)
         geo.n[d] = p->grid.dims[d];
     }
     CCHK(mck::nearest_nodes(p->coords, p->dim, nv, geo, p->m, cnt, s));
+    if (p->coarsen) {
+        // Grid_Coarsen (Alg. 2): drop the planes no node lies in, renumber
+        // the nodes on the coarsened grid and count them again
+        const int n0 = (int)p->grid.dims[0], n1 = (int)p->grid.dims[1], n2 = (int)p->grid.dims[2];
+        const long long nf = (long long)n0 + n1 + n2;
+        int* flags = ta.get<int>((size_t)nf, e);
+        CCHK(e);
+        CCHK(hipMemsetAsync(flags, 0, sizeof(int) * nf, s));
+        CCHK(mck::mark_planes(p->m, nv, n0, n1, n2, flags, s));
+        std::vector<int32_t> hf((size_t)nf);
+        CCHK(hipMemcpyAsync(hf.data(), flags, sizeof(int) * nf, hipMemcpyDeviceToHost, s));
+        CCHK(hipStreamSynchronize(s));
+        const long long off[3] = {0, n0, (long long)n0 + n1};
+        long long nn[3];
+        for (int d = 0; d < 3; ++d) {
+            const long long n = p->grid.dims[d];
+            long long kept = 0;
+            for (long long i = 0; i < n; ++i) kept += hf[off[d] + i];
+            if (kept < 2 && n >= 2)                       // fewer than two planes: the axis stays whole
+                for (long long i = 0; i < n; ++i) hf[off[d] + i] = 1;
+            long long next = 0;
+            for (long long i = 0; i < n; ++i) hf[off[d] + i] = hf[off[d] + i] ? (int32_t)next++ : -1;
+            nn[d] = next;
+        }
+        ng = nn[0] * nn[1] * nn[2];
+        CCHK(hipMemcpyAsync(flags, hf.data(), sizeof(int) * nf, hipMemcpyHostToDevice, s));
+        CCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * ng, s));
+        CCHK(mck::remap_nodes(p->m, nv, n0, n1, flags, (int)nn[0], (int)nn[1], cnt, s));
+        CCHK(hipStreamSynchronize(s));                    // hf is read by the copy above
+        p->keep = std::move(hf);
+        for (int d = 0; d < 3; ++d) p->grid.dims[d] = nn[d];
+        p->ng = ng;
+        p->gg = mc_geom(p->grid);
+    }
     CCHK(mck::scan_u32(cnt, ng, p->noff, sst, ctr + 3, s));
     CCHK(mck::count_empty(cnt, ng, ctr + 1, s));
     size_t tb = 0;
@@ -518,6 +553,10 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     if (st != MC_OK) return st;
     const int ops = opts ? opts->operators : MC_OPS_LINEAR;
     if (ops != MC_OPS_LINEAR && ops != MC_OPS_CLUSTER) return mc_fail(MC_ERR_ARG, "unknown operator pair");
+    const int coarsen = opts ? opts->coarsen : 0;
+    if (coarsen != 0 && coarsen != 1) return mc_fail(MC_ERR_ARG, "coarsen must be 0 or 1");
+    if (coarsen && ops != MC_OPS_CLUSTER)
+        return mc_fail(MC_ERR_UNSUPPORTED, "Grid_Coarsen needs the nearest-node pair (MC_OPS_CLUSTER)");
     if (ops == MC_OPS_LINEAR) {
         if (!d_cells) return mc_fail(MC_ERR_ARG, "cells pointer is NULL");
         if (n_cells <= 0 || n_cells >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
@@ -540,6 +579,7 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->fill = fill;
     p->B = B;
     p->ops = ops;
+    p->coarsen = coarsen;
     const long long ng = p->ng, nv = p->nv, nc = p->nc;
     hipStream_t s = stream;
 
@@ -634,11 +674,12 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
         }
     }
 
-    // compress / decompress workspace
-    p->ntg = (ng + MC_TILE - 1) / MC_TILE;
+    // compress / decompress workspace (on the coarsened grid when coarsened)
+    const long long ngw = p->ng;
+    p->ntg = (ngw + MC_TILE - 1) / MC_TILE;
     p->ntv = (nv + MC_TILE - 1) / MC_TILE;
     p->nblk = (nv + MC_LBLOCK - 1) / MC_LBLOCK;
-    PCHK(plan_alloc(p, &p->p, (size_t)ng));
+    PCHK(plan_alloc(p, &p->p, (size_t)ngw));
     PCHK(plan_alloc(p, &p->rho, (size_t)nv));
     PCHK(plan_alloc(p, &p->ctl, 64));
     p->rbuf = (RangeOut*)p->ctl;                       // 2 slots of 3 words
@@ -665,10 +706,10 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->gcount = p->counts;
     p->vcount = p->counts + p->ntg;
     decode_ws_shape(p);
-    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * grid->dims[0]));
-    if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * grid->dims[0] * grid->dims[1]));
-    if (dim == 2) PCHK(plan_alloc(p, &p->dws.segsum, (size_t)grid->dims[1] * ((grid->dims[0] + 255) / 256)));
-    PCHK(plan_alloc(p, &p->xh, (size_t)ng));
+    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * p->grid.dims[0]));
+    if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * p->grid.dims[0] * p->grid.dims[1]));
+    if (dim == 2) PCHK(plan_alloc(p, &p->dws.segsum, (size_t)p->grid.dims[1] * ((p->grid.dims[0] + 255) / 256)));
+    PCHK(plan_alloc(p, &p->xh, (size_t)ngw));
     PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * MC_RANGE_BLOCKS));
     PCHK(hipStreamSynchronize(s));
     *out = p;
@@ -707,6 +748,15 @@ extern "C" mc_status mc_plan_mapping(mc_plan p, int32_t* d_vid, float* d_w, int3
     if (d_w && e == hipSuccess) e = hipMemcpyAsync(d_w, p->w, k * 4, hipMemcpyDeviceToDevice, s);
     if (d_cell && e == hipSuccess) e = hipMemcpyAsync(d_cell, p->cell, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mapping copy: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
+extern "C" mc_status mc_plan_kept_planes(mc_plan p, int32_t* h_keep, int64_t cap)
+{
+    if (!p || !h_keep) return mc_fail(MC_ERR_ARG, "plan/output pointer is NULL");
+    if (!p->coarsen) return mc_fail(MC_ERR_UNSUPPORTED, "the plan was made without Grid_Coarsen");
+    if (cap < (int64_t)p->keep.size()) return mc_fail(MC_ERR_CAPACITY, "h_keep needs %zu entries", p->keep.size());
+    memcpy(h_keep, p->keep.data(), p->keep.size() * sizeof(int32_t));
     return MC_OK;
 }
 

@@ -12,6 +12,8 @@ struct mc_plan_s {
     int fill = 0;
     int B = 1;
     int ops = MC_OPS_LINEAR;       // operator pair (mc_plan_opts.operators)
+    int coarsen = 0;               // Grid_Coarsen applied (mc_plan_opts.coarsen)
+    std::vector<int32_t> keep;     // per original plane: coarsened index or -1 (coarsen only)
     // nearest-node / cluster-mean pair (device)
     int32_t* m = nullptr;          // nearest node of every vertex [nv]
     int32_t* vlist = nullptr;      // vertices sorted by node, ascending ids within a node [nv]

@@ -156,6 +156,12 @@ struct NodeGeom {
 };
 hipError_t nearest_nodes(const float* coords, int dim, long long nv, NodeGeom g, int32_t* m, unsigned* count,
                          hipStream_t s);
+// Grid_Coarsen: mark the planes holding a node (flags int[n0 + n1 + n2],
+// zeroed by the caller); remap the nodes to the coarsened grid through keep
+// (new index per plane) and count the vertices per coarsened node.
+hipError_t mark_planes(const int32_t* m, long long nv, int n0, int n1, int n2, int* flags, hipStream_t s);
+hipError_t remap_nodes(int32_t* m, long long nv, int n0, int n1, const int* keep, int c0, int c1, unsigned* count,
+                       hipStream_t s);
 hipError_t count_empty(const unsigned* count, long long ng, unsigned* out, hipStream_t s);
 // Stable sort of the vertices by node (temp == NULL: *temp_bytes receives the size).
 hipError_t sort_by_node(const int32_t* m, long long nv, long long ng, uint32_t* keys_out, int32_t* vlist,

@@ -31,7 +31,7 @@ class McGrid(C.Structure):
 
 
 class McPlanOpts(C.Structure):
-    _fields_ = [("fill", C.c_int), ("bin_nodes", C.c_int32), ("operators", C.c_int32)]
+    _fields_ = [("fill", C.c_int), ("bin_nodes", C.c_int32), ("operators", C.c_int32), ("coarsen", C.c_int32)]
 
 
 OPS_LINEAR, OPS_CLUSTER = 0, 1
@@ -111,6 +111,7 @@ _SIGS = {
     "mc_plan_get_grid": (C.c_int, [_P, _P]),
     "mc_plan_destroy": (C.c_int, [_P]),
     "mc_plan_nodes": (C.c_int, [_P, _P, _P]),
+    "mc_plan_kept_planes": (C.c_int, [_P, _P, C.c_int64]),
     "mc_compress": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
     "mc_decompress": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
     "mc_compress_mesh": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, C.c_int, _P, C.c_double,
@@ -259,9 +260,11 @@ class Plan:
     """Field-independent mesh-grid mapping (owns device memory)."""
 
     def __init__(self, coords, cells, grid: McGrid | None = None, dims=None, fill: str = "nearest",
-                 bin_nodes: int = 0, operators: str = "linear"):
+                 bin_nodes: int = 0, operators: str = "linear", coarsen: bool = False):
         """operators: "linear" (barycentric f, multilinear g) or "cluster"
-        (the paper's cluster-mean f and nearest-node g; cells may be None)."""
+        (the paper's cluster-mean f and nearest-node g; cells may be None);
+        coarsen: Grid_Coarsen (cluster plans), after which `grid` and
+        `n_grid` describe the coarsened grid and `kept_planes()` lists it."""
         torch = _torch()
         _require_cuda(coords, "coords", torch.float32)
         if operators not in ("linear", "cluster"):
@@ -274,14 +277,27 @@ class Plan:
             grid = grid_from_dims(coords, dims)
         self.grid = grid
         opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, bin_nodes,
-                          OPS_CLUSTER if operators == "cluster" else OPS_LINEAR)
+                          OPS_CLUSTER if operators == "cluster" else OPS_LINEAR, 1 if coarsen else 0)
         h = C.c_void_p()
         _check(lib().mc_plan_create(_ptr(coords), _ptr(cells), self.dim, coords.shape[1],
                                     0 if cells is None else cells.shape[1], C.byref(grid), C.byref(opts), _stream(),
                                     C.byref(h)), "mc_plan_create")
         self.handle = h
         self.n_vertices = int(coords.shape[1])
-        self.n_grid = int(grid.dims[0] * grid.dims[1] * grid.dims[2])
+        self.grid_given = grid
+        self.coarsen = bool(coarsen)
+        actual = McGrid()
+        _check(lib().mc_plan_get_grid(self.handle, C.byref(actual)), "mc_plan_get_grid")
+        self.grid = actual
+        self.n_grid = int(actual.dims[0] * actual.dims[1] * actual.dims[2])
+
+    def kept_planes(self) -> np.ndarray:
+        """Grid_Coarsen: each given plane's index on the coarsened axis, or -1
+        (axis 0, then 1, then 2)."""
+        n = int(sum(self.grid_given.dims[d] for d in range(3)))
+        out = np.empty(n, np.int32)
+        _check(lib().mc_plan_kept_planes(self.handle, out.ctypes.data_as(C.c_void_p), n), "mc_plan_kept_planes")
+        return out
 
     def info(self) -> dict:
         i = McPlanInfo()

@@ -121,3 +121,67 @@ def test_rejected_combinations():
     assert e.value.status == M.ERR_UNSUPPORTED
     with pytest.raises(M.McError):
         cl.mapping()
+
+
+@pytest.mark.parametrize("which,dims,open_loop,gpred", [
+    ("kuhn3d", (60, 58, 50), True, "lorenzo"),
+    ("kuhn3d", (60, 58, 50), False, "cubic"),
+    ("kuhn3d", (13, 12, 11), True, "lorenzo"),          # coarser than the lattice: nothing to drop
+    ("struct2d", (700, 520), True, "lorenzo"),
+    ("struct2d", (700, 520), False, "temporal"),
+])
+def test_grid_coarsen(which, dims, open_loop, gpred):
+    """Grid_Coarsen (Alg. 2) on the GPU: kept planes, node map, codes and
+    decoded values bit for bit against the oracle, and the decoded values
+    equal to those of the plan without coarsening."""
+    if which == "kuhn3d":
+        mesh = G.kuhn_tet_mesh(22, 5)
+        x = G.field_octaves(mesh.coords, np.random.default_rng(1))
+        eb, rel = 1e-4, True
+    else:
+        rng = np.random.default_rng(21)
+        mesh = G.structured_tri_mesh(201, 151, rng, 0.2)             # jittered lattice: empty grid lines
+        x = G.field_octaves(mesh.coords, rng, dtype=np.float64)
+        eb, rel = 1e-6, True
+    print(f"[cluster] coarsen {which} {dims} open={open_loop} {gpred}", flush=True)
+    og = O.grid_from_dims(mesh.coords, dims)
+    keep, ogc, om = O.grid_coarsen(O.nearest_nodes(mesh.coords, og), og)
+    gp = {"lorenzo": O.GPRED_LORENZO, "cubic": O.GPRED_CUBIC, "temporal": O.GPRED_TEMPORAL}[gpred]
+    ref = None
+    if gpred == "temporal":
+        ref = np.linspace(-1.0, 1.0, ogc.count).astype(np.float32)      # any reference both sides hold
+    oc = O.compress_cluster(mesh.coords, og, x, eb, rel, 0.5, open_loop, gpred=gp, gref=ref, coarsen=True)
+    plan = M.Plan(dev(mesh.coords), None, dims=dims, operators="cluster", coarsen=True)
+    assert np.array_equal(plan.kept_planes(), keep)
+    assert tuple(plan.grid.dims) == ogc.dims() and plan.n_grid == ogc.count
+    assert np.array_equal(plan.nodes().cpu().numpy(), om)
+    xt = dev(x)
+    kw = {} if ref is None else dict(grid_ref=dev(ref))
+    codes = M.Codes(plan, xt.dtype, grid_predictor=gpred, **kw)
+    M.compress(plan, xt, eb, "rel" if rel else "abs", 0.5, codes=codes, residual="open" if open_loop else "closed")
+    out = M.decompress(plan, codes)
+    torch.cuda.synchronize()
+    h = codes.host()
+    assert h["result"]["status"] == 0
+    assert np.array_equal(h["grid_codes"], oc.grid.codes)
+    assert np.array_equal(h["g_out_idx"], oc.grid.out_idx)
+    assert np.array_equal(h["vert_codes"], oc.vert.codes)
+    xo = O.decompress_cluster(mesh.coords, og, oc.bound, oc.grid, oc.vert, x.dtype, gpred=gp, gref=ref, coarsen=True)
+    assert np.array_equal(out.cpu().numpy().view(np.uint8), xo.view(np.uint8))
+    full = M.Plan(dev(mesh.coords), None, dims=dims, operators="cluster")
+    fc = M.compress(full, xt, eb, "rel" if rel else "abs", 0.5, residual="open" if open_loop else "closed")
+    fo = M.decompress(full, fc)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy().view(np.uint8), fo.cpu().numpy().view(np.uint8))
+    print(f"[cluster] coarsened {dims} -> {ogc.dims()}")
+
+
+def test_grid_coarsen_rejected():
+    mesh = G.kuhn_tet_mesh(9, 2)
+    with pytest.raises(M.McError) as e:
+        M.Plan(dev(mesh.coords), dev(mesh.cells), dims=(8, 8, 8), coarsen=True)
+    assert e.value.status == M.ERR_UNSUPPORTED
+    plan = M.Plan(dev(mesh.coords), None, dims=(8, 8, 8), operators="cluster")
+    with pytest.raises(M.McError) as e:
+        plan.kept_planes()
+    assert e.value.status == M.ERR_UNSUPPORTED
