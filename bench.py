@@ -198,7 +198,7 @@ def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
 
 
 def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="full", operators="linear",
-                 residual="closed", predictor="none", grid_predictor="lorenzo"):
+                 residual="closed", predictor="none", grid_predictor="lorenzo", coarsen=False):
     """The same field at another setting of the CR sweep (default: the
     best one, a 128^3 grid, one node per ~8 vertices, with the full split
     tau2 = tau and the grid step from tau1 = 4 tau): CR, both directions'
@@ -206,7 +206,7 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     import torch
     nv, sT = x.numel(), x.element_size()
     cells = torch.from_numpy(mesh.cells).cuda() if operators == "linear" else None
-    plan = M.Plan(coords, cells, dims=(dims, dims, dims), operators=operators)
+    plan = M.Plan(coords, cells, dims=(dims, dims, dims), operators=operators, coarsen=coarsen)
     del cells
     codes = M.Codes(plan, x.dtype, residual_predictor=predictor, grid_predictor=grid_predictor)
     out = torch.empty_like(x)
@@ -231,7 +231,8 @@ def design_point(M, mesh, coords, x, eb, log, dims=128, split=4.0, split_mode="f
     kern = {k: round(t / c, 5) for k, (c, t) in M.profile_read().items()}
     sb = M.stream_bytes(h, sT)
     ser = serial_compare(M, x, eb, h, (tc, td), log, f"{operators} {dims}^3, generated order")
-    row = {"operators": operators, "grid": [dims] * 3, "split_mode": split_mode, "grid_share": split,
+    row = {"operators": operators, "grid": [dims] * 3, "coarsened_grid": list(plan.grid.dims) if coarsen else None,
+           "split_mode": split_mode, "grid_share": split,
            "residual": residual, "residual_predictor": predictor, "grid_predictor": grid_predictor,
            "cr": round(nv * sT / sb["total"], 3),
            "max_abs_err_over_tau": round(err / r["tau"], 4),
@@ -867,7 +868,14 @@ def main():
                                  design_point(M, mesh, coords, x, args.eb, log, dims=cfg["dims"][0],
                                               split=args.split, split_mode="sum", grid_predictor="cubic"),
                                  design_point(M, mesh, coords, x, args.eb, log, split=0.1, split_mode="sum",
-                                              operators="cluster", residual="open")]
+                                              operators="cluster", residual="open"),
+                                 # the paper's pair on a grid twice as fine as the vertex lattice (about
+                                 # every other plane holds no vertex's node), without and with
+                                 # Grid_Coarsen (Alg. 2)
+                                 design_point(M, mesh, coords, x, args.eb, log, dims=503, split=0.1,
+                                              split_mode="sum", operators="cluster", residual="open"),
+                                 design_point(M, mesh, coords, x, args.eb, log, dims=503, split=0.1,
+                                              split_mode="sum", operators="cluster", residual="open", coarsen=True)]
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
