@@ -600,8 +600,10 @@ def grid_sweep(log, ks=(2.0, 5.0, 10.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0, 80.0
 def batch_main(args, log):
     """Many fields on many meshes: 12 meshes of 0.5M..20M vertices (2-D and
     3-D, float32 and float64), 64 fields; a step is one batch compress and
-    one batch decompress, each a single HIP graph launch.  ``value`` is GB/s
-    of mesh values over all fields."""
+    one batch decompress, each a single HIP graph launch.  Measured plain and
+    with the learned predictor per block (one model per mesh, trained on its
+    first field); ``value`` is the learned form's GB/s of mesh values over all
+    fields."""
     import torch
     import meshgen as G
     from paper_2501_06910_amd import mc as M
@@ -617,64 +619,93 @@ def batch_main(args, log):
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     xs = [torch.from_numpy(f["data"]).cuda() for f in fields]
-    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
     outs = [torch.empty_like(x) for x in xs]
-    items = [(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], None, codes[i])
-             for i, f in enumerate(fields)]
-    ditems = [(plans[f["mesh"]], codes[i], None, outs[i]) for i, f in enumerate(fields)]
     raw = sum(x.numel() * x.element_size() for x in xs)
 
-    def step():
-        M.batch_compress(items)
-        M.batch_decompress(ditems)
+    def measure(models, tag):
+        """One batch compress + one batch decompress per step, each a single
+        graph launch; models: per mesh, or None for the plain path."""
+        learned = models is not None
+        codes = [M.Codes(plans[f["mesh"]], xs[i].dtype, learned=learned) for i, f in enumerate(fields)]
+        mod = [models[f["mesh"]] if learned else None for f in fields]
+        items = [(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], mod[i], codes[i])
+                 for i, f in enumerate(fields)]
+        ditems = [(plans[f["mesh"]], codes[i], mod[i], outs[i]) for i, f in enumerate(fields)]
 
-    for _ in range(args.warmup):
-        step()
+        def step():
+            M.batch_compress(items)
+            M.batch_decompress(ditems)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        worst, total = 0.0, 0
+        for i, x in enumerate(xs):
+            h = codes[i].host()
+            r = h["result"]
+            if r["status"]:
+                raise SystemExit(f"batch {tag} field {i}: status {r['status']}")
+            e = (x.double() - outs[i].double()).abs().max().item()
+            if not e <= r["tau2"]:
+                raise SystemExit(f"batch {tag} field {i}: bound violated")
+            worst = max(worst, e / r["tau"])
+            h["learned"] = learned
+            total += M.stream_bytes(h, x.element_size())["total"]
+        if learned:
+            total += sum(16 + 2 * M.param_count(m.dim) for m in models.values())   # every model charged once
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.steps):
+            step()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        tc = _timed(lambda: M.batch_compress(items))
+        td = _timed(lambda: M.batch_decompress(ditems))
+
+        def serial():                      # the same work as separate calls on one stream
+            for i, f in enumerate(fields):
+                M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], model=mod[i], codes=codes[i])
+            for i, f in enumerate(fields):
+                M.decompress(plans[f["mesh"]], codes[i], model=mod[i], out=outs[i])
+        ts = _timed(serial)
+        res = {"GBps": round(raw / (ms_step * 1e-3) / 1e9, 2), "ms_per_step": round(ms_step, 4),
+               "cr": round(raw / total, 3),
+               "compress_GBps": round(raw / (tc * 1e-3) / 1e9, 2),
+               "decompress_GBps": round(raw / (td * 1e-3) / 1e9, 2),
+               "separate_calls_ms": round(ts, 4), "graph_ms": round(tc + td, 4),
+               "max_abs_err_over_tau": round(worst, 4)}
+        log(f"batch {tag}: {res}")
+        return res
+
+    plain = measure(None, "plain")
+    # the learned predictor per block: one model per mesh, trained on its first field
+    t0 = time.time()
+    models = {}
+    for i, f in enumerate(fields):
+        if f["mesh"] not in models:
+            models[f["mesh"]] = M.Model.train(plans[f["mesh"]], xs[i], eb=f["eb"], eb_mode=f["eb_mode"],
+                                              grid_share=f["split"], steps=args.train_steps, seed=4)
     torch.cuda.synchronize()
-    worst = 0.0
-    for i, x in enumerate(xs):
-        r = codes[i].result_host()
-        if r["status"]:
-            raise SystemExit(f"batch field {i}: status {r['status']}")
-        e = (x.double() - outs[i].double()).abs().max().item()
-        if not e <= r["tau2"]:
-            raise SystemExit(f"batch field {i}: bound violated")
-        worst = max(worst, e / r["tau"])
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    tc = _timed(lambda: M.batch_compress(items))
-    td = _timed(lambda: M.batch_decompress(ditems))
-    # the same work as separate calls on one stream, for the graph's gain
-    def serial():
-        for i, f in enumerate(fields):
-            M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"], codes=codes[i])
-        for i, f in enumerate(fields):
-            M.decompress(plans[f["mesh"]], codes[i], out=outs[i])
-    ts = _timed(serial)
+    train_s = time.time() - t0
+    learned = measure(models, "learned")
+    learned["train_seconds"] = round(train_s, 3)
     nv_all = [m.n_vertices for m in meshes]
     line = {
         "metric": "compress/decompress GB/s of mesh values + CR, learned vs plain, eb=1e-4",
-        "value": round(raw / (ms_step * 1e-3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "value": learned["GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": learned["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"batch: {len(meshes)} meshes ({min(nv_all)}..{max(nv_all)} vertices, "
                                f"even 2-D jittered triangulations, odd 3-D Kuhn tetrahedra), {len(fields)} fields "
                                f"(float32 on 2-D, float64 on 3-D meshes), relative eb 1e-3/1e-4/1e-5, grids of "
-                               f"about n_v/4 nodes, split 0.5",
+                               f"about n_v/4 nodes, split 0.5, learned predictor per block (one model per mesh)",
                    "scale": args.batch_scale, "n_vertices_total": int(sum(x.numel() for x in xs)),
                    "raw_bytes": raw},
-        "compress_GBps": round(raw / (tc * 1e-3) / 1e9, 2),
-        "decompress_GBps": round(raw / (td * 1e-3) / 1e9, 2),
-        "separate_calls_ms": round(ts, 4),
-        "graph_ms": round(tc + td, 4),
-        "max_abs_err_over_tau": round(worst, 4),
+        "learned": learned,
+        "plain": plain,
         "plan_seconds": round(plan_s, 3),
     }
     print(json.dumps(line), flush=True)
