@@ -271,6 +271,9 @@ __device__ __forceinline__ float feature(int k, const VGeom& q, const GridGeom& 
     return 0.0f;
 }
 
+// Four consecutive floats at a 4-byte aligned address.
+typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
+
 // Input fragments of the wave's 4 column blocks: zf[nb][kb].  Inputs
 // k < NN are neighbourhood differences (one gather each), the next D the
 // in-cell offsets, the rest zero padding; which fragment holds which is the
@@ -290,20 +293,44 @@ __device__ __forceinline__ void build_inputs(bf16x4 (&zf)[4][MlpShape<D>::KB], c
     for (int nb0 = 0; nb0 < 4; nb0 += NBB) {
         VGeom q[NBB];
         float val[NBB][KG][4];
+        // a lane's four inputs of a fragment are the x-neighbours i0-1 .. i0+2
+        // of one (y, z) row: one 16-byte load when the whole wave is away from
+        // the grid's x ends, else one clamped load each
 #pragma unroll
-        for (int u = 0; u < NBB; ++u) {
-            q[u] = shfl_geom(mine, (nb0 + u) * 16 + (l & 15));
+        for (int u = 0; u < NBB; ++u) q[u] = shfl_geom(mine, (nb0 + u) * 16 + (l & 15));
+        bool inner = true;
 #pragma unroll
-            for (int kb = 0; kb < KG; ++kb)
+        for (int u = 0; u < NBB; ++u) inner = inner && q[u].i0 >= 1 && q[u].i0 + 2 <= gg.n0 - 1;
+        if (__all(inner)) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int k = kb * 16 + g4 + i;
-                    const int a0 = k & 3, a1 = (k >> 2) & 3, a2 = k >> 4;
-                    const int n0 = min(max(q[u].i0 - 1 + a0, 0), gg.n0 - 1);
+            for (int u = 0; u < NBB; ++u)
+#pragma unroll
+                for (int kb = 0; kb < KG; ++kb) {
+                    const int a1 = (l >> 4) & 3, a2 = kb;
                     const int n1 = min(max(q[u].i1 - 1 + a1, 0), gg.n1 - 1);
                     const int n2 = D == 3 ? min(max(q[u].i2 - 1 + a2, 0), gg.n2 - 1) : 0;
-                    val[u][kb][i] = xh[(unsigned)n0 + (unsigned)gg.n0 * ((unsigned)n1 + (unsigned)gg.n1 * (unsigned)n2)];
+                    const f4a4 r = *reinterpret_cast<const f4a4*>(
+                        xh + ((unsigned)(q[u].i0 - 1) + (unsigned)gg.n0 * ((unsigned)n1 + (unsigned)gg.n1 * (unsigned)n2)));
+                    val[u][kb][0] = r.x;
+                    val[u][kb][1] = r.y;
+                    val[u][kb][2] = r.z;
+                    val[u][kb][3] = r.w;
                 }
+        } else {
+#pragma unroll
+            for (int u = 0; u < NBB; ++u)
+#pragma unroll
+                for (int kb = 0; kb < KG; ++kb)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = kb * 16 + g4 + i;
+                        const int a0 = k & 3, a1 = (k >> 2) & 3, a2 = k >> 4;
+                        const int n0 = min(max(q[u].i0 - 1 + a0, 0), gg.n0 - 1);
+                        const int n1 = min(max(q[u].i1 - 1 + a1, 0), gg.n1 - 1);
+                        const int n2 = D == 3 ? min(max(q[u].i2 - 1 + a2, 0), gg.n2 - 1) : 0;
+                        val[u][kb][i] =
+                            xh[(unsigned)n0 + (unsigned)gg.n0 * ((unsigned)n1 + (unsigned)gg.n1 * (unsigned)n2)];
+                    }
         }
 #pragma unroll
         for (int u = 0; u < NBB; ++u) {
