@@ -36,6 +36,8 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
         "k_dec_xy_tot": ng * 2,                                    # 2-D: codes
         "k_dec_z_tot": ng * 2,                                     # 3-D: codes
         "k_dec_z_apply": ng * 2 + ng * 4,                          # codes in, z-prefixed errors out
+        "k_dec3_tot": ng * 2,                                      # 3-D quads: codes
+        "k_dec3_apply": ng * 2 + ng * 4,                           # 3-D quads: codes in, x1' out
         "k_dec_xy_apply": (ng * 4 if D == 3 else ng * 2) + ng * 4,  # errors in, x1' out
         "k_vdecode": nv * (4 * D + 2 + sT) + ng * 4,               # coords, codes, field out, x1'
         "k_vdecode_learned": nv * (4 * D + 2 + sT + 4) + ng * 4,
@@ -45,7 +47,7 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
 
 COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_residual",
                      "k_scatter", "k_mlp_infer_c")
-DECOMPRESS_PREFIXES = ("k_dec_", "k_vdecode", "k_mlp_infer_d")
+DECOMPRESS_PREFIXES = ("k_dec_", "k_dec3_", "k_vdecode", "k_mlp_infer_d")
 
 
 def _kernel_source(here: str, kernel: str):

@@ -177,22 +177,30 @@ __global__ __launch_bounds__(256) void k_dec_z_apply(const uint16_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// 3-D decode on quads of x (n0 a multiple of 4, n0 <= 1024): the same five
-// passes as above, but every lane owns four consecutive x (8-byte code
-// loads, 16-byte integer and float stores) and issues all the loads of its
-// sweep before using any.
-//   k_d3_ztot    per (256-column segment, row, chunk of MC_DZ planes):
-//                the chunk's error sums
-//   (k_dec_z_carry: exclusive prefix over the plane chunks, in place)
-//   k_d3_zapply  workgroup = 4 waves x 2 rows = MC_DY rows of one segment,
-//                sweeping one plane chunk: z-prefixed errors written, and
-//                the MC_DY-row column sums of every plane (LDS reduction)
-//   (k_dec_xy_carry: exclusive prefix over the row chunks, in place)
-//   k_d3_xyapply wave = (plane, chunk of MC_DY rows), whole rows: running
-//                column sums from the carry plus a row scan, x1' written
+// 3-D decode on quads of x (n0 a multiple of 4, n0 <= 1024).  Tiles are
+// (x range) x (MC_DY rows of row chunk j) x (MC_DZ planes of plane chunk k);
+// lanes own four consecutive x (8-byte code loads, 16-byte stores) and
+// issue all loads of a sweep before using any.  With d the errors, the
+// inclusive prefix p splits at the tile's first row Y0 and first plane Z0:
+//   p(x,y,z) = sum_{x' <= x} A(x',y,z),
+//   A(x,y,z) = E(x) + sum_{Z0<=z'<=z} Fy(x,z') + sum_{Y0<=y'<=y} R(x,y',z),
+//   R(x,y,z) = Fz(x,y) + sum_{Z0<=z'<=z} d(x,y,z'),
+// with Fz(x,y) = sum_{z'<Z0} d(x,y,z'), Fy(x,z) = sum_{y'<Y0} d(x,y',z) and
+// E(x) = sum_{y'<Y0, z'<Z0} d(x,y',z').  Three launches:
+//   k_d3_tot    per tile (256-column segment): the tile's z sums per (x,y)
+//               (agg_z), y sums per (x,z) (agg_y, through LDS) and its
+//               total per x (agg_t)
+//   k_d3_carry  exclusive prefixes: agg_z over plane chunks (-> Fz), agg_y
+//               over row chunks (-> Fy), agg_t over both (-> E)
+//   k_d3_apply  per tile, whole rows: R by a running sum over the planes,
+//               the y prefix across the four waves through LDS (the lead
+//               wave adds E + Fy), the x scan of every row, x1' written
+// Integer sums wrap as in two's complement; p itself fits in 32 bits, so
+// the wrapped partial sums still add up to it.
 #define MC_DZ MC_DZ_PLANES
 #define MC_DY MC_DY_ROWS
-static_assert(MC_DY == 8, "k_d3_zapply: 4 waves x 2 rows");
+static_assert(MC_DY == 8, "3-D quad decode: 4 waves x 2 rows");
+static_assert(MC_DZ % 4 == 0, "3-D quad decode: planes prefetched in quarters");
 
 __device__ __forceinline__ ushort4 ld_codes4(const uint16_t* __restrict__ codes, unsigned j, bool act)
 {
@@ -208,157 +216,234 @@ __device__ __forceinline__ int dec1(unsigned c, const int32_t* __restrict__ oidx
     return k >= 0 ? odelta[k] : 0;
 }
 
-__global__ __launch_bounds__(256) void k_d3_ztot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
-                                                 const int32_t* __restrict__ odelta,
-                                                 const mc_result* __restrict__ res, long long gcap, int n0, int n1,
-                                                 int n2, int nxs, unsigned nunits, int* __restrict__ aggz,
-                                                 unsigned remap)
+__device__ __forceinline__ int4 dec4(ushort4 c, const int32_t* __restrict__ oidx, const int32_t* __restrict__ odelta,
+                                     long long nout, unsigned j)
 {
-    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
-    if (u >= nunits) return;
-    const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
-    const unsigned y = r % (unsigned)n1, zc = r / (unsigned)n1;
-    const unsigned x = xs * 256u + 4u * (unsigned)lane_id();
-    const bool act = x < (unsigned)n0;
-    const unsigned nxy = (unsigned)n0 * (unsigned)n1, base = x + (unsigned)n0 * y;
-    const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
-    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
-    ushort4 c[MC_DZ];
-#pragma unroll
-    for (int k = 0; k < MC_DZ; ++k) c[k] = ld_codes4(codes, base + nxy * (unsigned)(z0 + k), act && z0 + k < z1);
-    int4 t = make_int4(0, 0, 0, 0);
-#pragma unroll
-    for (int k = 0; k < MC_DZ; ++k) {
-        const unsigned j = base + nxy * (unsigned)(z0 + k);
-        t.x += dec1(c[k].x, oidx, odelta, nout, j);
-        t.y += dec1(c[k].y, oidx, odelta, nout, j + 1);
-        t.z += dec1(c[k].z, oidx, odelta, nout, j + 2);
-        t.w += dec1(c[k].w, oidx, odelta, nout, j + 3);
-    }
-    if (act) *reinterpret_cast<int4*>(aggz + (size_t)zc * nxy + base) = t;
+    return make_int4(dec1(c.x, oidx, odelta, nout, j), dec1(c.y, oidx, odelta, nout, j + 1),
+                     dec1(c.z, oidx, odelta, nout, j + 2), dec1(c.w, oidx, odelta, nout, j + 3));
 }
 
-__global__ __launch_bounds__(256) void k_d3_zapply(const uint16_t* __restrict__ codes,
-                                                   const int32_t* __restrict__ oidx,
-                                                   const int32_t* __restrict__ odelta,
-                                                   const mc_result* __restrict__ res, long long gcap, int n0, int n1,
-                                                   int n2, int nxs, int nyc, const int* __restrict__ carryz,
-                                                   int32_t* __restrict__ pz, int* __restrict__ agg_xy, unsigned remap)
+__device__ __forceinline__ int4 add4(int4 a, int4 b)
 {
-    __shared__ int4 s_cs[2][4][64];
+    return make_int4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+__global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                const int32_t* __restrict__ odelta, const mc_result* __restrict__ res,
+                                                long long gcap, int n0, int n1, int n2, int nxs, int nyc, int nzc,
+                                                int* __restrict__ agg_z, int* __restrict__ agg_y,
+                                                int* __restrict__ agg_t, unsigned remap)
+{
+    __shared__ int4 s_p[MC_DZ + 1][4][64];                      // per plane, then the tile total; per wave
     const unsigned t = tile_of(remap);                           // grid = exactly the tiles: no early exit
     const unsigned xs = t % (unsigned)nxs, r = t / (unsigned)nxs;
     const unsigned yc = r % (unsigned)nyc, zc = r / (unsigned)nyc;
-    const int w = threadIdx.x >> 6;
-    const unsigned x = xs * 256u + 4u * (unsigned)lane_id();
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const unsigned x = xs * 256u + 4u * (unsigned)lane;
     const bool actx = x < (unsigned)n0;
     const unsigned nxy = (unsigned)n0 * (unsigned)n1;
     const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
     const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
     unsigned rb[2];
     bool ar[2];
-    int4 run[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const unsigned y = yc * MC_DY + 2u * (unsigned)w + (unsigned)q;
         ar[q] = actx && y < (unsigned)n1;
         rb[q] = x + (unsigned)n0 * y;
-        run[q] = ar[q] ? *reinterpret_cast<const int4*>(carryz + (size_t)zc * nxy + rb[q]) : make_int4(0, 0, 0, 0);
     }
     ushort4 c[MC_DZ][2];
 #pragma unroll
     for (int k = 0; k < MC_DZ; ++k)
 #pragma unroll
         for (int q = 0; q < 2; ++q) c[k][q] = ld_codes4(codes, rb[q] + nxy * (unsigned)(z0 + k), ar[q] && z0 + k < z1);
+    int4 sz[2] = {make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
 #pragma unroll
     for (int k = 0; k < MC_DZ; ++k) {
-        const bool zin = z0 + k < z1;
         int4 cs = make_int4(0, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const unsigned j = rb[q] + nxy * (unsigned)(z0 + k);
-            if (ar[q] && zin) {
-                run[q].x += dec1(c[k][q].x, oidx, odelta, nout, j);
-                run[q].y += dec1(c[k][q].y, oidx, odelta, nout, j + 1);
-                run[q].z += dec1(c[k][q].z, oidx, odelta, nout, j + 2);
-                run[q].w += dec1(c[k][q].w, oidx, odelta, nout, j + 3);
-                *reinterpret_cast<int4*>(pz + j) = run[q];
-                cs.x += run[q].x;
-                cs.y += run[q].y;
-                cs.z += run[q].z;
-                cs.w += run[q].w;
+        for (int q = 0; q < 2; ++q)
+            if (ar[q] && z0 + k < z1) {
+                const int4 d = dec4(c[k][q], oidx, odelta, nout, rb[q] + nxy * (unsigned)(z0 + k));
+                sz[q] = add4(sz[q], d);
+                cs = add4(cs, d);
             }
-        }
-        s_cs[k & 1][w][lane_id()] = cs;
-        __syncthreads();
-        if (w == 0 && zin && actx) {
-            int4 a = s_cs[k & 1][0][lane_id()];
+        s_p[k][w][lane] = cs;
+    }
+    s_p[MC_DZ][w][lane] = add4(sz[0], sz[1]);
 #pragma unroll
-            for (int v = 1; v < 4; ++v) {
-                const int4 b = s_cs[k & 1][v][lane_id()];
-                a.x += b.x;
-                a.y += b.y;
-                a.z += b.z;
-                a.w += b.w;
-            }
-            *reinterpret_cast<int4*>(agg_xy + ((size_t)(z0 + k) * nyc + yc) * n0 + x) = a;
+    for (int q = 0; q < 2; ++q)
+        if (ar[q]) *reinterpret_cast<int4*>(agg_z + (size_t)zc * nxy + rb[q]) = sz[q];
+    __syncthreads();
+    for (int k = w; k <= MC_DZ; k += 4) {
+        if (!actx) continue;
+        int4 a = s_p[k][0][lane];
+#pragma unroll
+        for (int v = 1; v < 4; ++v) a = add4(a, s_p[k][v][lane]);
+        if (k < MC_DZ) {
+            if (z0 + k < z1) *reinterpret_cast<int4*>(agg_y + ((size_t)(z0 + k) * nyc + yc) * n0 + x) = a;
+        } else {
+            *reinterpret_cast<int4*>(agg_t + ((size_t)yc * nzc + zc) * n0 + x) = a;
         }
     }
 }
 
-template <int NXS>
-__global__ __launch_bounds__(256) void k_d3_xyapply(const int32_t* __restrict__ pz, const mc_result* __restrict__ res,
-                                                    int n0, int n1, int nyc, unsigned nunits,
-                                                    const int* __restrict__ carry, float* __restrict__ xh,
-                                                    unsigned remap)
+// Exclusive prefix of a[0], a[stride], ... a[(n-1) stride] in place, B
+// values loaded before any is used (32-bit offsets: every workspace array
+// holds fewer than 2^32 entries).
+template <int B>
+__device__ __forceinline__ void excl_prefix_b(int* __restrict__ a, unsigned stride, int n)
 {
-    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
-    if (u >= nunits) return;
-    const unsigned z = u / (unsigned)nyc, yc = u % (unsigned)nyc;
-    const int y0 = (int)yc * MC_DY, y1 = min(y0 + MC_DY, n1);
+    int run = 0;
+    for (int b = 0; b < n; b += B) {
+        int t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = a[(unsigned)min(b + u, n - 1) * stride];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (b + u < n) a[(unsigned)(b + u) * stride] = run;
+            run += b + u < n ? t[u] : 0;
+        }
+    }
+}
+
+// Blocks [0, nbt): agg_t, 2^xb_log x per block, the rest of the block's
+// threads per x taking the row chunks (pass 1, prefix over plane chunks)
+// and then the plane chunks (pass 2, prefix over row chunks) -- the longest
+// dependent chain, so dispatched first; [nbt, nbt + nbz): agg_z, one
+// position each; the rest: agg_y, one (x, plane) each.  Pass 2 reads what
+// other waves of the block wrote in pass 1, after the block barrier (which
+// makes a block's global stores visible to the whole block).
+__global__ __launch_bounds__(256, 3) void k_d3_carry(int* __restrict__ agg_z, int* __restrict__ agg_y,
+                                                     int* __restrict__ agg_t, long long nxy, int n0, int n2, int nyc,
+                                                     int nzc, unsigned nbt, unsigned nbz, int xb_log)
+{
+    const unsigned b = blockIdx.x;
+    if (b >= nbt + nbz) {
+        const long long i = (long long)(b - nbt - nbz) * 256 + threadIdx.x;
+        if (i < (long long)n0 * n2) {
+            const long long z = i / n0, c = i % n0;
+            excl_prefix_b<16>(agg_y + z * nyc * n0 + c, (unsigned)n0, nyc);
+        }
+        return;
+    }
+    if (b >= nbt) {
+        const long long pos = (long long)(b - nbt) * 256 + threadIdx.x;
+        if (pos < nxy) excl_prefix_b<16>(agg_z + pos, (unsigned)nxy, nzc);
+        return;
+    }
+    const int x = (int)(b << xb_log) + (int)(threadIdx.x & ((1u << xb_log) - 1u));
+    const int sl = (int)(threadIdx.x >> xb_log), nsl = 256 >> xb_log;
+    const bool act = x < n0;
+    if (act)
+        for (int j = sl; j < nyc; j += nsl)
+            excl_prefix_b<32>(agg_t + (long long)j * nzc * n0 + x, (unsigned)n0, nzc);
+    __syncthreads();
+    if (act)
+        for (int k = sl; k < nzc; k += nsl)
+            excl_prefix_b<32>(agg_t + (long long)k * n0 + x, (unsigned)nzc * (unsigned)n0, nyc);
+}
+
+// Workgroup = one (row chunk, plane chunk) tile over all x: 4 waves x 2
+// rows, NXS 256-column segments per row.  Codes of PF planes are loaded
+// before any is used.
+template <int NXS>
+__global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                                  const int32_t* __restrict__ odelta,
+                                                  const mc_result* __restrict__ res, long long gcap, int n0, int n1,
+                                                  int n2, int nyc, int nzc, const int* __restrict__ agg_z,
+                                                  const int* __restrict__ agg_y, const int* __restrict__ agg_t,
+                                                  float* __restrict__ xh, unsigned remap)
+{
+    constexpr int PF = NXS == 1 ? MC_DZ : (NXS == 2 ? MC_DZ / 2 : MC_DZ / 4);
+    __shared__ int4 s_cs[2][4][NXS][64];
+    const unsigned t = tile_of(remap);                           // grid = exactly the tiles: no early exit
+    const unsigned yc = t % (unsigned)nyc, zc = t / (unsigned)nyc;
+    const int w = threadIdx.x >> 6, lane = lane_id();
+    const bool lead = w == 0;
+    const unsigned nxy = (unsigned)n0 * (unsigned)n1;
+    const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
     const double c = res->c, step1 = 2.0 * res->tau1;
-    const unsigned plane = (unsigned)n0 * (unsigned)n1 * z;
-    int4 col[NXS];
-    bool act[NXS];
+    unsigned xq[NXS];
+    bool ax[NXS];
 #pragma unroll
     for (int sg = 0; sg < NXS; ++sg) {
-        const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
-        act[sg] = x < (unsigned)n0;
-        col[sg] = act[sg] ? *reinterpret_cast<const int4*>(carry + ((size_t)z * nyc + yc) * n0 + x)
-                          : make_int4(0, 0, 0, 0);
+        xq[sg] = (unsigned)sg * 256u + 4u * (unsigned)lane;
+        ax[sg] = xq[sg] < (unsigned)n0;
     }
-    int4 v[MC_DY][NXS];
+    unsigned yb[2];
+    bool ar[2];
 #pragma unroll
-    for (int k = 0; k < MC_DY; ++k)
+    for (int q = 0; q < 2; ++q) {
+        const unsigned y = yc * MC_DY + 2u * (unsigned)w + (unsigned)q;
+        ar[q] = y < (unsigned)n1;
+        yb[q] = (unsigned)n0 * y;
+    }
+    int4 run[2][NXS], own[NXS];
 #pragma unroll
-        for (int sg = 0; sg < NXS; ++sg) {
-            const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
-            v[k][sg] = (act[sg] && y0 + k < y1)
-                           ? *reinterpret_cast<const int4*>(pz + plane + (unsigned)n0 * (unsigned)(y0 + k) + x)
-                           : make_int4(0, 0, 0, 0);
+    for (int sg = 0; sg < NXS; ++sg) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            run[q][sg] = (ar[q] && ax[sg]) ? *reinterpret_cast<const int4*>(agg_z + (size_t)zc * nxy + yb[q] + xq[sg])
+                                           : make_int4(0, 0, 0, 0);
+        own[sg] = (lead && ax[sg]) ? *reinterpret_cast<const int4*>(agg_t + ((size_t)yc * nzc + zc) * n0 + xq[sg])
+                                   : make_int4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int k0 = 0; k0 < MC_DZ; k0 += PF) {
+        if (z0 + k0 >= z1) break;                                // uniform over the workgroup
+        ushort4 cc[PF][2][NXS];
+        int4 fy[PF][NXS];
+#pragma unroll
+        for (int kk = 0; kk < PF; ++kk) {
+            const int z = z0 + k0 + kk;
+#pragma unroll
+            for (int sg = 0; sg < NXS; ++sg) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    cc[kk][q][sg] = ld_codes4(codes, nxy * (unsigned)z + yb[q] + xq[sg], ar[q] && ax[sg] && z < z1);
+                fy[kk][sg] = (lead && ax[sg] && z < z1)
+                                 ? *reinterpret_cast<const int4*>(agg_y + ((size_t)z * nyc + yc) * n0 + xq[sg])
+                                 : make_int4(0, 0, 0, 0);
+            }
         }
 #pragma unroll
-    for (int k = 0; k < MC_DY; ++k) {
-        if (y0 + k >= y1) break;
-        int rowoff = 0;
+        for (int kk = 0; kk < PF; ++kk) {
+            const int k = k0 + kk, z = z0 + k;
+            if (z >= z1) break;                                  // uniform over the workgroup
 #pragma unroll
-        for (int sg = 0; sg < NXS; ++sg) {
-            col[sg].x += v[k][sg].x;
-            col[sg].y += v[k][sg].y;
-            col[sg].z += v[k][sg].z;
-            col[sg].w += v[k][sg].w;
-            const int a0 = col[sg].x, a1 = a0 + col[sg].y, a2 = a1 + col[sg].z, a3 = a2 + col[sg].w;
-            const int inc = wave_incl_scan(a3);
-            const int off = rowoff + inc - a3;
-            rowoff += __shfl(inc, 63, 64);
-            const unsigned x = (unsigned)sg * 256u + 4u * (unsigned)lane_id();
-            if (act[sg]) {
-                float4 o;
-                o.x = xhat_of(off + a0, c, step1);
-                o.y = xhat_of(off + a1, c, step1);
-                o.z = xhat_of(off + a2, c, step1);
-                o.w = xhat_of(off + a3, c, step1);
-                *reinterpret_cast<float4*>(xh + plane + (unsigned)n0 * (unsigned)(y0 + k) + x) = o;
+            for (int sg = 0; sg < NXS; ++sg) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+                    if (ar[q] && ax[sg])
+                        run[q][sg] = add4(run[q][sg],
+                                          dec4(cc[kk][q][sg], oidx, odelta, nout, nxy * (unsigned)z + yb[q] + xq[sg]));
+                own[sg] = add4(own[sg], fy[kk][sg]);
+                s_cs[k & 1][w][sg][lane] = add4(own[sg], add4(run[0][sg], run[1][sg]));
+            }
+            __syncthreads();
+            int rowoff[2] = {0, 0};
+#pragma unroll
+            for (int sg = 0; sg < NXS; ++sg) {
+                int4 a = own[sg];
+                for (int v = 0; v < w; ++v) a = add4(a, s_cs[k & 1][v][sg][lane]);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    a = add4(a, run[q][sg]);
+                    const int a0 = a.x, a1 = a0 + a.y, a2 = a1 + a.z, a3 = a2 + a.w;
+                    const int inc = wave_incl_scan(a3);
+                    const int off = rowoff[q] + inc - a3;
+                    rowoff[q] += __shfl(inc, 63, 64);
+                    if (ar[q] && ax[sg]) {
+                        float4 o;
+                        o.x = xhat_of(off + a0, c, step1);
+                        o.y = xhat_of(off + a1, c, step1);
+                        o.z = xhat_of(off + a2, c, step1);
+                        o.w = xhat_of(off + a3, c, step1);
+                        *reinterpret_cast<float4*>(xh + nxy * (unsigned)z + yb[q] + xq[sg]) = o;
+                    }
+                }
             }
         }
     }
@@ -594,44 +679,33 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         const long long nxy = (long long)n0 * n1;
         const int nxs = (n0 + 255) / 256;
         {
-            ProfScope ps("k_dec_z_tot", s);
-            const unsigned nunits = (unsigned)((long long)nxs * n1 * ws.nzc);
-            hipLaunchKernelGGL(k_d3_ztot, dim3((nunits + 3) / 4), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0,
-                               n1, n2, nxs, nunits, ws.agg_z, remap & MC_KNOB_DZTOT);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        {
-            ProfScope ps("k_dec_z_carry", s);
-            hipLaunchKernelGGL(k_dec_z_carry, dim3((unsigned)((nxy + 255) / 256)), dim3(256), 0, s, ws.agg_z, nxy,
-                               ws.nzc);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-        }
-        {
-            ProfScope ps("k_dec_z_apply", s);
+            ProfScope ps("k_dec3_tot", s);
             const unsigned ntiles = (unsigned)((long long)nxs * ws.nyc * ws.nzc);
-            hipLaunchKernelGGL(k_d3_zapply, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2,
-                               nxs, ws.nyc, ws.agg_z, pz, ws.agg_xy, remap & MC_KNOB_DZAPPLY);
+            hipLaunchKernelGGL(k_d3_tot, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2, nxs,
+                               ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, remap & MC_KNOB_DZTOT);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
-            ProfScope ps("k_dec_xy_carry", s);
-            hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)(((long long)n0 * n2 + 255) / 256)), dim3(256), 0, s,
-                               ws.agg_xy, n0, n2, ws.nyc);
+            ProfScope ps("k_dec3_carry", s);
+            const unsigned nbz = (unsigned)((nxy + 255) / 256), nby = (unsigned)(((long long)n0 * n2 + 255) / 256);
+            const int mx = ws.nyc > ws.nzc ? ws.nyc : ws.nzc;   // longest run of the tile-total prefix
+            int xb_log = 4;                                      // x per block: 256 / xb >= mx when it can be
+            while (xb_log > 0 && (256 >> xb_log) < mx) --xb_log;
+            const unsigned nbt = (unsigned)((n0 + (1 << xb_log) - 1) >> xb_log);
+            hipLaunchKernelGGL(k_d3_carry, dim3(nbt + nbz + nby), dim3(256), 0, s, ws.agg_z, ws.agg_xy, ws.agg_t, nxy,
+                               n0, n2, ws.nyc, ws.nzc, nbt, nbz, xb_log);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
-            ProfScope ps("k_dec_xy_apply", s);
-            const unsigned nunits = (unsigned)((long long)n2 * ws.nyc);
-            dim3 g((nunits + 3) / 4);
-            if (nxs == 1)
-                hipLaunchKernelGGL(k_d3_xyapply<1>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
-                                   remap & MC_KNOB_DXYAPPLY);
-            else if (nxs == 2)
-                hipLaunchKernelGGL(k_d3_xyapply<2>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
-                                   remap & MC_KNOB_DXYAPPLY);
-            else
-                hipLaunchKernelGGL(k_d3_xyapply<4>, g, dim3(256), 0, s, pz, res, n0, n1, ws.nyc, nunits, ws.agg_xy, xh,
-                                   remap & MC_KNOB_DXYAPPLY);
+            ProfScope ps("k_dec3_apply", s);
+            const dim3 g((unsigned)((long long)ws.nyc * ws.nzc));
+            const unsigned rm = remap & MC_KNOB_DZAPPLY;
+#define MC_D3A(X) hipLaunchKernelGGL(k_d3_apply<X>, g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2, \
+                                     ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, xh, rm)
+            if (nxs == 1) MC_D3A(1);
+            else if (nxs == 2) MC_D3A(2);
+            else MC_D3A(4);
+#undef MC_D3A
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         return hipSuccess;

@@ -708,6 +708,7 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     decode_ws_shape(p);
     PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * p->grid.dims[0]));
     if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * p->grid.dims[0] * p->grid.dims[1]));
+    if (p->dws.fast3) PCHK(plan_alloc(p, &p->dws.agg_t, (size_t)p->dws.nyc * p->dws.nzc * p->grid.dims[0]));
     if (dim == 2) PCHK(plan_alloc(p, &p->dws.segsum, (size_t)p->grid.dims[1] * ((p->grid.dims[0] + 255) / 256)));
     PCHK(plan_alloc(p, &p->xh, (size_t)ngw));
     PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * MC_RANGE_BLOCKS));

@@ -82,9 +82,9 @@ enum {
     MC_KNOB_LORENZO = 1u << 1,
     MC_KNOB_RESIDUAL = 1u << 2,
     MC_KNOB_VDECODE = 1u << 3,
-    MC_KNOB_DZTOT = 1u << 4,
-    MC_KNOB_DZAPPLY = 1u << 5,
-    MC_KNOB_DXYAPPLY = 1u << 6,
+    MC_KNOB_DZTOT = 1u << 4,        // 3-D decode on x quads: tile sums
+    MC_KNOB_DZAPPLY = 1u << 5,      // 3-D decode on x quads: apply
+    MC_KNOB_DXYAPPLY = 1u << 6,     // no kernel reads it (kept so the mask keeps its meaning)
     MC_KNOB_ALL = 0x7fu
 };
 
@@ -96,6 +96,7 @@ struct DecodeWs {
     int* agg_xy;                   // [ntiles_xy][n0] column totals, then carries
     int zplanes, nzc;              // 3-D: planes per chunk, plane chunks
     int* agg_z;                    // [nzc][n0*n1] chunk totals, then carries
+    int* agg_t;                    // 3-D quads: [nyc][nzc][n0] tile totals, then their 2-D exclusive prefix
     int* segsum;                   // 2-D: [n1][ceil(n0 / 256)] row-segment sums
 };
 // ---- multilevel interpolation grid predictor (k_interp.hip) ---------------

@@ -65,6 +65,9 @@ def _cases():
     m6 = G.kuhn_tet_mesh(30, 8)
     out.append(("kuhn3d_wide_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(3)), (264, 21, 13), 1e-6,
                 True, 0.5, "nearest"))
+    # three 256-column segments (the decode's four-segment instance, one idle)
+    out.append(("kuhn3d_wider_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(4)), (516, 11, 10), 1e-5,
+                True, 0.5, "nearest"))
     mesh5, f5, _ = G.config_large_2d(h0=0.004, dims=200)
     out.append(("refined2d_f64", mesh5, f5, (200, 200), 1e-6, True, 0.5, "nearest"))
     # the full split: tau2 = tau, grid step from tau1 = split * tau (up to 16 tau)
