@@ -208,19 +208,49 @@ __device__ __forceinline__ ushort4 ld_codes4(const uint16_t* __restrict__ codes,
     return *reinterpret_cast<const ushort4*>(codes + j);
 }
 
-__device__ __forceinline__ int dec1(unsigned c, const int32_t* __restrict__ oidx, const int32_t* __restrict__ odelta,
-                                    long long nout, unsigned j)
+// Outliers of the 16 (plane, row) runs of a wave.  Run r covers node
+// indices [s_r, e_r); lane r < 16 returns the first outlier position with
+// index >= s_r and lane 16 + r that with index >= e_r (the list ascends),
+// so a zero code of run r searches positions [lo_r, hi_r) only.  Every lane
+// passes its run's bounds for run (lane & 15).
+__device__ __forceinline__ int run_bound(const int32_t* __restrict__ oidx, long long nout, long long s, long long e,
+                                         bool valid)
 {
-    if (c != 0u) return (int)c - MC_R;
-    const long long k = find_outlier(oidx, nout, (long long)j);
-    return k >= 0 ? odelta[k] : 0;
+    const int l = lane_id();
+    if (nout == 0 || l >= 32 || !valid) return 0;
+    const long long key = l < 16 ? s : e;
+    long long lo = 0, hi = nout;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)oidx[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int)lo;
 }
 
-__device__ __forceinline__ int4 dec4(ushort4 c, const int32_t* __restrict__ oidx, const int32_t* __restrict__ odelta,
-                                     long long nout, unsigned j)
+// Error of one node of run r: its code, or its entry among the run's
+// outliers (positions [lo, hi), read from lanes r and 16 + r of `bounds`).
+__device__ __forceinline__ int dec1r(unsigned c, const int32_t* __restrict__ oidx,
+                                     const int32_t* __restrict__ odelta, int lo, int hi, unsigned j)
 {
-    return make_int4(dec1(c.x, oidx, odelta, nout, j), dec1(c.y, oidx, odelta, nout, j + 1),
-                     dec1(c.z, oidx, odelta, nout, j + 2), dec1(c.w, oidx, odelta, nout, j + 3));
+    if (c != 0u) return (int)c - MC_R;
+    int a = lo, b = hi;
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if ((unsigned)oidx[mid] < j) a = mid + 1;
+        else b = mid;
+    }
+    return (a < hi && (unsigned)oidx[a] == j) ? odelta[a] : 0;
+}
+
+__device__ __forceinline__ int4 dec4r(ushort4 c, const int32_t* __restrict__ oidx,
+                                      const int32_t* __restrict__ odelta, int bounds, int r, unsigned j)
+{
+    const int lo = __builtin_amdgcn_readlane(bounds, r), hi = __builtin_amdgcn_readlane(bounds, 16 + r);
+    if ((c.x != 0u) & (c.y != 0u) & (c.z != 0u) & (c.w != 0u))
+        return make_int4((int)c.x - MC_R, (int)c.y - MC_R, (int)c.z - MC_R, (int)c.w - MC_R);
+    return make_int4(dec1r(c.x, oidx, odelta, lo, hi, j), dec1r(c.y, oidx, odelta, lo, hi, j + 1),
+                     dec1r(c.z, oidx, odelta, lo, hi, j + 2), dec1r(c.w, oidx, odelta, lo, hi, j + 3));
 }
 
 __device__ __forceinline__ int4 add4(int4 a, int4 b)
@@ -257,6 +287,13 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
     for (int k = 0; k < MC_DZ; ++k)
 #pragma unroll
         for (int q = 0; q < 2; ++q) c[k][q] = ld_codes4(codes, rb[q] + nxy * (unsigned)(z0 + k), ar[q] && z0 + k < z1);
+    int bnd;
+    {
+        const int r = lane & 15, zr = z0 + (r >> 1);
+        const unsigned yr = yc * MC_DY + 2u * (unsigned)w + (unsigned)(r & 1);
+        const long long s0 = (long long)nxy * zr + (long long)n0 * yr + xs * 256u;
+        bnd = run_bound(oidx, nout, s0, s0 + min(256, n0 - (int)xs * 256), yr < (unsigned)n1 && zr < z1);
+    }
     int4 sz[2] = {make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
 #pragma unroll
     for (int k = 0; k < MC_DZ; ++k) {
@@ -264,7 +301,7 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (ar[q] && z0 + k < z1) {
-                const int4 d = dec4(c[k][q], oidx, odelta, nout, rb[q] + nxy * (unsigned)(z0 + k));
+                const int4 d = dec4r(c[k][q], oidx, odelta, bnd, 2 * k + q, rb[q] + nxy * (unsigned)(z0 + k));
                 sz[q] = add4(sz[q], d);
                 cs = add4(cs, d);
             }
@@ -380,6 +417,13 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
         ar[q] = y < (unsigned)n1;
         yb[q] = (unsigned)n0 * y;
     }
+    int bnd;
+    {
+        const int r = lane & 15, zr = z0 + (r >> 1);
+        const unsigned yr = yc * MC_DY + 2u * (unsigned)w + (unsigned)(r & 1);
+        const long long s0 = (long long)nxy * zr + (long long)n0 * yr;
+        bnd = run_bound(oidx, nout, s0, s0 + n0, yr < (unsigned)n1 && zr < z1);
+    }
     int4 run[2][NXS], own[NXS];
 #pragma unroll
     for (int sg = 0; sg < NXS; ++sg) {
@@ -417,8 +461,8 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
                     if (ar[q] && ax[sg])
-                        run[q][sg] = add4(run[q][sg],
-                                          dec4(cc[kk][q][sg], oidx, odelta, nout, nxy * (unsigned)z + yb[q] + xq[sg]));
+                        run[q][sg] = add4(run[q][sg], dec4r(cc[kk][q][sg], oidx, odelta, bnd, 2 * k + q,
+                                                            nxy * (unsigned)z + yb[q] + xq[sg]));
                 own[sg] = add4(own[sg], fy[kk][sg]);
                 s_cs[k & 1][w][sg][lane] = add4(own[sg], add4(run[0][sg], run[1][sg]));
             }
