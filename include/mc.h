@@ -300,7 +300,7 @@ mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
  * gets one contiguous run of tiles), clear = in launch order.  Bits: 0
  * resample, 1 Lorenzo codes, 2 residual codes (and the learned block
  * costs), 3 vertex decode, 4/5 the 3-D grid decode's tile sums and apply
- * (grids with n0 a multiple of 4 and at most 1024); bit 6 has no effect.
+ * (grids with n0 at most 1024); bit 6 has no effect.
  * Codes and values never depend on the knobs.  Default: all set. */
 typedef struct {
     uint32_t remap_mask;

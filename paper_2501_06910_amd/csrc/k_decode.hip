@@ -177,7 +177,9 @@ __global__ __launch_bounds__(256) void k_dec_z_apply(const uint16_t* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// 3-D decode on quads of x (n0 a multiple of 4, n0 <= 1024).  Tiles are
+// 3-D decode on quads of x (n0 <= 1024; when n0 is not a multiple of 4 each
+// row ends in a partial quad, and the workspace rows are padded to a
+// multiple of 4 so that its 16-byte accesses stay aligned).  Tiles are
 // (x range) x (MC_DY rows of row chunk j) x (MC_DZ planes of plane chunk k);
 // lanes own four consecutive x (8-byte code loads, 16-byte stores) and
 // issue all loads of a sweep before using any.  With d the errors, the
@@ -202,10 +204,18 @@ __global__ __launch_bounds__(256) void k_dec_z_apply(const uint16_t* __restrict_
 static_assert(MC_DY == 8, "3-D quad decode: 4 waves x 2 rows");
 static_assert(MC_DZ % 4 == 0, "3-D quad decode: planes prefetched in quarters");
 
-__device__ __forceinline__ ushort4 ld_codes4(const uint16_t* __restrict__ codes, unsigned j, bool act)
+// Codes of the quad at node j (x, x+1, x+2, x+3 of one row).  AL: the row
+// length is a multiple of 4 (one 8-byte load); otherwise `left` = n0 - x
+// elements remain in the row and those past its end read as the neutral
+// code R (error 0).
+template <bool AL>
+__device__ __forceinline__ ushort4 ld_codes4(const uint16_t* __restrict__ codes, unsigned j, bool act, unsigned left)
 {
     if (!act) return make_ushort4(0, 0, 0, 0);
-    return *reinterpret_cast<const ushort4*>(codes + j);
+    if (AL) return *reinterpret_cast<const ushort4*>(codes + j);
+    const unsigned short R = (unsigned short)MC_R;
+    return make_ushort4(codes[j], left > 1u ? codes[j + 1] : R, left > 2u ? codes[j + 2] : R,
+                        left > 3u ? codes[j + 3] : R);
 }
 
 // Outliers of the 16 (plane, row) runs of a wave.  Run r covers node
@@ -258,10 +268,11 @@ __device__ __forceinline__ int4 add4(int4 a, int4 b)
     return make_int4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
 }
 
+template <bool AL>
 __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                                 const int32_t* __restrict__ odelta, const mc_result* __restrict__ res,
-                                                long long gcap, int n0, int n1, int n2, int nxs, int nyc, int nzc,
-                                                int* __restrict__ agg_z, int* __restrict__ agg_y,
+                                                long long gcap, int n0, int n0p, int n1, int n2, int nxs, int nyc,
+                                                int nzc, int* __restrict__ agg_z, int* __restrict__ agg_y,
                                                 int* __restrict__ agg_t, unsigned remap)
 {
     __shared__ int4 s_p[MC_DZ + 1][4][64];                      // per plane, then the tile total; per wave
@@ -271,22 +282,25 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
     const int w = threadIdx.x >> 6, lane = lane_id();
     const unsigned x = xs * 256u + 4u * (unsigned)lane;
     const bool actx = x < (unsigned)n0;
-    const unsigned nxy = (unsigned)n0 * (unsigned)n1;
+    const unsigned nxy = (unsigned)n0 * (unsigned)n1, nxyp = (unsigned)n0p * (unsigned)n1;
+    const unsigned left = (unsigned)n0 - x;
     const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
     const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
-    unsigned rb[2];
+    unsigned rb[2], rp[2];                                       // code index, workspace index of the row
     bool ar[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const unsigned y = yc * MC_DY + 2u * (unsigned)w + (unsigned)q;
         ar[q] = actx && y < (unsigned)n1;
         rb[q] = x + (unsigned)n0 * y;
+        rp[q] = x + (unsigned)n0p * y;
     }
     ushort4 c[MC_DZ][2];
 #pragma unroll
     for (int k = 0; k < MC_DZ; ++k)
 #pragma unroll
-        for (int q = 0; q < 2; ++q) c[k][q] = ld_codes4(codes, rb[q] + nxy * (unsigned)(z0 + k), ar[q] && z0 + k < z1);
+        for (int q = 0; q < 2; ++q)
+            c[k][q] = ld_codes4<AL>(codes, rb[q] + nxy * (unsigned)(z0 + k), ar[q] && z0 + k < z1, left);
     int bnd;
     {
         const int r = lane & 15, zr = z0 + (r >> 1);
@@ -310,7 +324,7 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
     s_p[MC_DZ][w][lane] = add4(sz[0], sz[1]);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
-        if (ar[q]) *reinterpret_cast<int4*>(agg_z + (size_t)zc * nxy + rb[q]) = sz[q];
+        if (ar[q]) *reinterpret_cast<int4*>(agg_z + (size_t)zc * nxyp + rp[q]) = sz[q];
     __syncthreads();
     for (int k = w; k <= MC_DZ; k += 4) {
         if (!actx) continue;
@@ -318,9 +332,9 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
 #pragma unroll
         for (int v = 1; v < 4; ++v) a = add4(a, s_p[k][v][lane]);
         if (k < MC_DZ) {
-            if (z0 + k < z1) *reinterpret_cast<int4*>(agg_y + ((size_t)(z0 + k) * nyc + yc) * n0 + x) = a;
+            if (z0 + k < z1) *reinterpret_cast<int4*>(agg_y + ((size_t)(z0 + k) * nyc + yc) * n0p + x) = a;
         } else {
-            *reinterpret_cast<int4*>(agg_t + ((size_t)yc * nzc + zc) * n0 + x) = a;
+            *reinterpret_cast<int4*>(agg_t + ((size_t)yc * nzc + zc) * n0p + x) = a;
         }
     }
 }
@@ -384,11 +398,11 @@ __global__ __launch_bounds__(256, 3) void k_d3_carry(int* __restrict__ agg_z, in
 // Workgroup = one (row chunk, plane chunk) tile over all x: 4 waves x 2
 // rows, NXS 256-column segments per row.  Codes of PF planes are loaded
 // before any is used.
-template <int NXS>
+template <int NXS, bool AL>
 __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                                   const int32_t* __restrict__ odelta,
-                                                  const mc_result* __restrict__ res, long long gcap, int n0, int n1,
-                                                  int n2, int nyc, int nzc, const int* __restrict__ agg_z,
+                                                  const mc_result* __restrict__ res, long long gcap, int n0, int n0p,
+                                                  int n1, int n2, int nyc, int nzc, const int* __restrict__ agg_z,
                                                   const int* __restrict__ agg_y, const int* __restrict__ agg_t,
                                                   float* __restrict__ xh, unsigned remap)
 {
@@ -398,7 +412,7 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
     const unsigned yc = t % (unsigned)nyc, zc = t / (unsigned)nyc;
     const int w = threadIdx.x >> 6, lane = lane_id();
     const bool lead = w == 0;
-    const unsigned nxy = (unsigned)n0 * (unsigned)n1;
+    const unsigned nxy = (unsigned)n0 * (unsigned)n1, nxyp = (unsigned)n0p * (unsigned)n1;
     const int z0 = (int)zc * MC_DZ, z1 = min(z0 + MC_DZ, n2);
     const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
     const double c = res->c, step1 = 2.0 * res->tau1;
@@ -409,13 +423,14 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
         xq[sg] = (unsigned)sg * 256u + 4u * (unsigned)lane;
         ax[sg] = xq[sg] < (unsigned)n0;
     }
-    unsigned yb[2];
+    unsigned yb[2], ybp[2];                                      // row start: codes and x1', workspace
     bool ar[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const unsigned y = yc * MC_DY + 2u * (unsigned)w + (unsigned)q;
         ar[q] = y < (unsigned)n1;
         yb[q] = (unsigned)n0 * y;
+        ybp[q] = (unsigned)n0p * y;
     }
     int bnd;
     {
@@ -429,9 +444,9 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
     for (int sg = 0; sg < NXS; ++sg) {
 #pragma unroll
         for (int q = 0; q < 2; ++q)
-            run[q][sg] = (ar[q] && ax[sg]) ? *reinterpret_cast<const int4*>(agg_z + (size_t)zc * nxy + yb[q] + xq[sg])
+            run[q][sg] = (ar[q] && ax[sg]) ? *reinterpret_cast<const int4*>(agg_z + (size_t)zc * nxyp + ybp[q] + xq[sg])
                                            : make_int4(0, 0, 0, 0);
-        own[sg] = (lead && ax[sg]) ? *reinterpret_cast<const int4*>(agg_t + ((size_t)yc * nzc + zc) * n0 + xq[sg])
+        own[sg] = (lead && ax[sg]) ? *reinterpret_cast<const int4*>(agg_t + ((size_t)yc * nzc + zc) * n0p + xq[sg])
                                    : make_int4(0, 0, 0, 0);
     }
 #pragma unroll
@@ -446,9 +461,10 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
             for (int sg = 0; sg < NXS; ++sg) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
-                    cc[kk][q][sg] = ld_codes4(codes, nxy * (unsigned)z + yb[q] + xq[sg], ar[q] && ax[sg] && z < z1);
+                    cc[kk][q][sg] = ld_codes4<AL>(codes, nxy * (unsigned)z + yb[q] + xq[sg], ar[q] && ax[sg] && z < z1,
+                                                  (unsigned)n0 - xq[sg]);
                 fy[kk][sg] = (lead && ax[sg] && z < z1)
-                                 ? *reinterpret_cast<const int4*>(agg_y + ((size_t)z * nyc + yc) * n0 + xq[sg])
+                                 ? *reinterpret_cast<const int4*>(agg_y + ((size_t)z * nyc + yc) * n0p + xq[sg])
                                  : make_int4(0, 0, 0, 0);
             }
         }
@@ -485,7 +501,16 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
                         o.y = xhat_of(off + a1, c, step1);
                         o.z = xhat_of(off + a2, c, step1);
                         o.w = xhat_of(off + a3, c, step1);
-                        *reinterpret_cast<float4*>(xh + nxy * (unsigned)z + yb[q] + xq[sg]) = o;
+                        float* dst = xh + nxy * (unsigned)z + yb[q] + xq[sg];
+                        if (AL) {
+                            *reinterpret_cast<float4*>(dst) = o;
+                        } else {
+                            const unsigned left = (unsigned)n0 - xq[sg];
+                            dst[0] = o.x;
+                            if (left > 1u) dst[1] = o.y;
+                            if (left > 2u) dst[2] = o.z;
+                            if (left > 3u) dst[3] = o.w;
+                        }
                     }
                 }
             }
@@ -720,35 +745,41 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         return hipGetLastError();
     }
     if (ws.fast3) {
-        const long long nxy = (long long)n0 * n1;
+        const int n0p = ws.pitch;                                // workspace row pitch: n0 rounded up to 4
+        const long long nxyp = (long long)n0p * n1;
         const int nxs = (n0 + 255) / 256;
+        const bool al = n0 % 4 == 0;
         {
             ProfScope ps("k_dec3_tot", s);
             const unsigned ntiles = (unsigned)((long long)nxs * ws.nyc * ws.nzc);
-            hipLaunchKernelGGL(k_d3_tot, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2, nxs,
-                               ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, remap & MC_KNOB_DZTOT);
+            const unsigned rm = remap & MC_KNOB_DZTOT;
+#define MC_D3T(A) hipLaunchKernelGGL(k_d3_tot<A>, dim3(ntiles), dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n0p, \
+                                     n1, n2, nxs, ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, rm)
+            if (al) MC_D3T(true);
+            else MC_D3T(false);
+#undef MC_D3T
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
             ProfScope ps("k_dec3_carry", s);
-            const unsigned nbz = (unsigned)((nxy + 255) / 256), nby = (unsigned)(((long long)n0 * n2 + 255) / 256);
+            const unsigned nbz = (unsigned)((nxyp + 255) / 256), nby = (unsigned)(((long long)n0p * n2 + 255) / 256);
             const int mx = ws.nyc > ws.nzc ? ws.nyc : ws.nzc;   // longest run of the tile-total prefix
             int xb_log = 4;                                      // x per block: 256 / xb >= mx when it can be
             while (xb_log > 0 && (256 >> xb_log) < mx) --xb_log;
-            const unsigned nbt = (unsigned)((n0 + (1 << xb_log) - 1) >> xb_log);
-            hipLaunchKernelGGL(k_d3_carry, dim3(nbt + nbz + nby), dim3(256), 0, s, ws.agg_z, ws.agg_xy, ws.agg_t, nxy,
-                               n0, n2, ws.nyc, ws.nzc, nbt, nbz, xb_log);
+            const unsigned nbt = (unsigned)((n0p + (1 << xb_log) - 1) >> xb_log);
+            hipLaunchKernelGGL(k_d3_carry, dim3(nbt + nbz + nby), dim3(256), 0, s, ws.agg_z, ws.agg_xy, ws.agg_t, nxyp,
+                               n0p, n2, ws.nyc, ws.nzc, nbt, nbz, xb_log);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
         {
             ProfScope ps("k_dec3_apply", s);
             const dim3 g((unsigned)((long long)ws.nyc * ws.nzc));
             const unsigned rm = remap & MC_KNOB_DZAPPLY;
-#define MC_D3A(X) hipLaunchKernelGGL(k_d3_apply<X>, g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, n1, n2, \
-                                     ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, xh, rm)
-            if (nxs == 1) MC_D3A(1);
-            else if (nxs == 2) MC_D3A(2);
-            else MC_D3A(4);
+#define MC_D3A(X, A) hipLaunchKernelGGL((k_d3_apply<X, A>), g, dim3(256), 0, s, codes, oidx, odelta, res, gcap, n0, \
+                                        n0p, n1, n2, ws.nyc, ws.nzc, ws.agg_z, ws.agg_xy, ws.agg_t, xh, rm)
+            if (nxs == 1) { if (al) MC_D3A(1, true); else MC_D3A(1, false); }
+            else if (nxs == 2) { if (al) MC_D3A(2, true); else MC_D3A(2, false); }
+            else { if (al) MC_D3A(4, true); else MC_D3A(4, false); }
 #undef MC_D3A
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }

@@ -423,7 +423,8 @@ GridGeom mc_geom(const mc_grid& g)
 static void decode_ws_shape(mc_plan p)
 {
     const long long n0 = p->grid.dims[0], n1 = p->grid.dims[1], n2 = p->grid.dims[2];
-    p->dws.fast3 = p->dim == 3 && n0 % 4 == 0 && n0 <= 1024;
+    p->dws.fast3 = p->dim == 3 && n0 <= 1024;
+    p->dws.pitch = (int)(p->dws.fast3 ? (n0 + 3) / 4 * 4 : n0);
     if (p->dws.fast3) {
         p->dws.rows = MC_DY_ROWS;
         p->dws.nyc = (int)((n1 + MC_DY_ROWS - 1) / MC_DY_ROWS);
@@ -706,9 +707,9 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->gcount = p->counts;
     p->vcount = p->counts + p->ntg;
     decode_ws_shape(p);
-    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * p->grid.dims[0]));
-    if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * p->grid.dims[0] * p->grid.dims[1]));
-    if (p->dws.fast3) PCHK(plan_alloc(p, &p->dws.agg_t, (size_t)p->dws.nyc * p->dws.nzc * p->grid.dims[0]));
+    PCHK(plan_alloc(p, &p->dws.agg_xy, (size_t)p->dws.ntiles_xy * p->dws.pitch));
+    if (dim == 3) PCHK(plan_alloc(p, &p->dws.agg_z, (size_t)p->dws.nzc * p->dws.pitch * p->grid.dims[1]));
+    if (p->dws.fast3) PCHK(plan_alloc(p, &p->dws.agg_t, (size_t)p->dws.nyc * p->dws.nzc * p->dws.pitch));
     if (dim == 2) PCHK(plan_alloc(p, &p->dws.segsum, (size_t)p->grid.dims[1] * ((p->grid.dims[0] + 255) / 256)));
     PCHK(plan_alloc(p, &p->xh, (size_t)ngw));
     PCHK(plan_alloc(p, &p->range_partial, (size_t)3 * MC_RANGE_BLOCKS));

@@ -90,13 +90,14 @@ enum {
 
 #define MC_D2_R 8                  // 2-D decode: rows per chunk (rows of DecodeWs in 2-D)
 struct DecodeWs {
-    bool fast3;                    // 3-D with n0 % 4 == 0 and n0 <= 1024: the quad kernels
+    bool fast3;                    // 3-D with n0 <= 1024: the quad kernels
+    int pitch;                     // row pitch of the workspace arrays: n0, rounded up to 4 on the quad path
     int rows, nyc;                 // rows per tile, row chunks per plane
     long long ntiles_xy;           // nyc * n2
-    int* agg_xy;                   // [ntiles_xy][n0] column totals, then carries
+    int* agg_xy;                   // [ntiles_xy][pitch] column totals, then carries
     int zplanes, nzc;              // 3-D: planes per chunk, plane chunks
-    int* agg_z;                    // [nzc][n0*n1] chunk totals, then carries
-    int* agg_t;                    // 3-D quads: [nyc][nzc][n0] tile totals, then their 2-D exclusive prefix
+    int* agg_z;                    // [nzc][pitch*n1] chunk totals, then carries
+    int* agg_t;                    // 3-D quads: [nyc][nzc][pitch] tile totals, then their 2-D exclusive prefix
     int* segsum;                   // 2-D: [n1][ceil(n0 / 256)] row-segment sums
 };
 // ---- multilevel interpolation grid predictor (k_interp.hip) ---------------

@@ -65,6 +65,12 @@ def _cases():
     m6 = G.kuhn_tet_mesh(30, 8)
     out.append(("kuhn3d_wide_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(3)), (264, 21, 13), 1e-6,
                 True, 0.5, "nearest"))
+    # rows that end in a partial quad (two segments, grid outliers), and an
+    # x extent above the quad decoder's 1024 (the generic decoder)
+    out.append(("kuhn3d_ragged_quads_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(5)), (263, 21, 13),
+                1e-6, True, 0.5, "nearest"))
+    out.append(("kuhn3d_long_x_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(6)), (1030, 6, 5), 1e-5,
+                True, 0.5, "nearest"))
     # three 256-column segments (the decode's four-segment instance, one idle)
     out.append(("kuhn3d_wider_f32", m6, G.field_octaves(m6.coords, np.random.default_rng(4)), (516, 11, 10), 1e-5,
                 True, 0.5, "nearest"))
