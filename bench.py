@@ -30,7 +30,6 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
         "k_range": nv * sT,                                        # field
         "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 8,         # mapping, field, p + x1' out
         "k_lorenzo": ng * 4 + ng * 2,                              # p in, codes out
-        "k_learned_cost": nv * (4 * D + sT + 4) + ng * 4,          # coords, field, rho_q, x1'
         "k_residual": nv * (4 * D + sT + 2) + ng * 4,              # coords, field, codes out, x1'
         "k_residual_learned": nv * (4 * D + sT + 2 + 4) + ng * 4,
         "k_dec_xy_tot": ng * 2,                                    # 2-D: codes
@@ -45,7 +44,7 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
     return table.get(kernel, 0)
 
 
-COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_learned_cost", "k_residual",
+COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_residual",
                      "k_scatter", "k_mlp_infer_c")
 DECOMPRESS_PREFIXES = ("k_dec_", "k_dec3_", "k_vdecode", "k_mlp_infer_d")
 

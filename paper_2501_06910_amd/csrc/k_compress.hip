@@ -8,10 +8,10 @@
 //                    reconstructed grid x1'_j = (float)(c + p_j * 2 tau1)
 //   k_lorenzo        Lorenzo prediction error of p, uint16 codes, per-tile
 //                    outlier counts
-//   k_learned_cost   learned mode: both code costs per 4096-vertex block
 //   k_residual       g: multilinear x1' at each vertex, residual quantisation
-//                    with the per-vertex bound check, learned shift in the
-//                    blocks where it is cheaper, per-tile outlier counts
+//                    with the per-vertex bound check, per-tile outlier counts
+//   k_residual_learned  learned mode, one workgroup per 4096-vertex block:
+//                    both code costs, the cheaper kind, then the codes
 //   k_scatter        outlier lists in index order (wave ballots)
 #include "mc_dev.h"
 #include "mc_interp.h"
@@ -439,87 +439,25 @@ __device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound&
     return ok;
 }
 
-// Learned mode, first pass: per 4096-vertex block, the cost of the plain and
-// of the shifted codes: sum of bitlen(zigzag(code)) over coded vertices plus
-// (32 + 8 sizeof(T)) per outlier.  Integer atomics: order-independent.
+// Residual codes of one tile (1024 vertices) and its outlier count.
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_learned_cost(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                      const float* __restrict__ xh, const T* __restrict__ x,
-                                                      const DevBound* __restrict__ bnd,
-                                                      const int32_t* __restrict__ rho_q,
-                                                      unsigned int* __restrict__ bcost, unsigned remap)
-{
-    __shared__ long long s_red[4];
-    const DevBound b = *bnd;
-    const long long tile = tile_of(remap);
-    const int ocost = 32 + 8 * (int)sizeof(T);
-    long long v[MC_IPT];
-    bool act[MC_IPT];
-    T xv[MC_IPT];
-    int rq[MC_IPT];
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
-        act[i] = v[i] < nv && b.ok;
-        const long long vc = act[i] ? v[i] : 0;
-        xv[i] = x[vc];
-        rq[i] = rho_q[vc];
-    }
-    float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
-    int cp = 0, cl = 0;
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        if (!act[i]) continue;
-        int qi;
-        if (quantize_residual<T>(xv[i], g[i], b, qi)) {
-            const int l = qi - rq[i];
-            cp += zz_bits(qi);
-            cl += (l >= -(MC_R - 1) && l <= MC_R - 1) ? zz_bits(l) : ocost;
-        } else {
-            cp += ocost;
-            cl += ocost;
-        }
-    }
-    const long long sp = block_sum_i64(cp, s_red);
-    const long long sl = block_sum_i64(cl, s_red);
-    if (threadIdx.x == 0) {
-        const long long blk = (tile * MC_TILE) / MC_LBLOCK;   // a tile lies inside one block
-        atomicAdd(&bcost[2 * blk], (unsigned)sp);
-        atomicAdd(&bcost[2 * blk + 1], (unsigned)sl);
-    }
-}
-
-// Residual codes of one tile (1024 vertices) and its outlier count; bit 31
-// of the count marks the first tile of a learned block.
-template <typename T, int D, bool LEARNED>
 __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                   const float* __restrict__ xh, const T* __restrict__ x,
-                                                  const DevBound* __restrict__ bnd,
-                                                  const int32_t* __restrict__ rho_q,
-                                                  const unsigned int* __restrict__ bcost,
-                                                  uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags,
+                                                  const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
                                                   float* __restrict__ dbg_g, unsigned int* __restrict__ count,
                                                   unsigned int* __restrict__ vsum, unsigned remap)
 {
     __shared__ int s_cnt[4];
     const DevBound b = *bnd;
     const long long tile = tile_of(remap);
-    // every tile lies inside one decision block (MC_LBLOCK % MC_TILE == 0)
-    const long long blk = (tile * MC_TILE) / MC_LBLOCK;
-    bool learned = false;
-    if (LEARNED) learned = bcost[2 * blk + 1] < bcost[2 * blk];
     long long v[MC_IPT];
     bool act[MC_IPT];
     T xv[MC_IPT];
-    int rq[MC_IPT];
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
         v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
         act[i] = v[i] < nv && b.ok;
-        const long long vc = act[i] ? v[i] : 0;
-        xv[i] = x[vc];
-        rq[i] = (LEARNED && learned) ? rho_q[vc] : 0;
+        xv[i] = x[act[i] ? v[i] : 0];
     }
     float g[MC_IPT];
     back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
@@ -529,22 +467,107 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
         if (!act[i]) continue;
         if (dbg_g) dbg_g[v[i]] = g[i];
         int qi;
-        bool ok = quantize_residual<T>(xv[i], g[i], b, qi);
-        if (LEARNED && ok && learned) {
+        const bool ok = quantize_residual<T>(xv[i], g[i], b, qi);
+        codes[v[i]] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
+        nout += ok ? 0 : 1;
+    }
+    nout = wave_sum(nout);
+    if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = nout;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned c = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+        if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
+        count[tile] = c;
+    }
+}
+
+// Learned mode: one workgroup per decision block of MC_LBLOCK vertices (its
+// MC_LBLOCK / MC_TILE tiles, 256 threads each, with the plain kernel's
+// vertex order).  The block's cost of the plain and of the shifted codes
+// (sum of bitlen(zigzag(code)) over coded vertices plus (32 + 8 sizeof(T))
+// per outlier), the choice (shifted only when strictly cheaper), then the
+// codes and each tile's outlier count; bit 31 of the count marks the first
+// tile of a learned block.  One back-interpolation serves both.
+constexpr int MC_LTILES = MC_LBLOCK / MC_TILE;
+static_assert(MC_LBLOCK % MC_TILE == 0 && MC_LTILES * MC_WG <= 1024, "decision block = whole tiles, <= 1024 threads");
+
+template <typename T, int D>
+__global__ __launch_bounds__(MC_LTILES * MC_WG) void k_residual_learned(
+    const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
+    const T* __restrict__ x, const DevBound* __restrict__ bnd, const int32_t* __restrict__ rho_q,
+    uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags, float* __restrict__ dbg_g,
+    unsigned int* __restrict__ count, unsigned int* __restrict__ vsum, long long ntv, unsigned remap)
+{
+    constexpr int NW = MC_LTILES * MC_WG / 64;
+    __shared__ long long s_sp[NW], s_sl[NW];
+    __shared__ int s_cnt[NW];
+    const DevBound b = *bnd;
+    const long long blk = tile_of(remap);
+    const int sub = threadIdx.x / MC_WG, lt = threadIdx.x % MC_WG;
+    const long long tile = blk * MC_LTILES + sub;
+    const int ocost = 32 + 8 * (int)sizeof(T);
+    long long v[MC_IPT];
+    bool act[MC_IPT];
+    T xv[MC_IPT];
+    int rq[MC_IPT];
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        v[i] = tile * MC_TILE + i * MC_WG + lt;
+        act[i] = v[i] < nv && b.ok;
+        const long long vc = act[i] ? v[i] : 0;
+        xv[i] = x[vc];
+        rq[i] = rho_q[vc];
+    }
+    float g[MC_IPT];
+    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    int qv[MC_IPT];
+    bool okv[MC_IPT];
+    long long cp = 0, cl = 0;
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        okv[i] = act[i] && quantize_residual<T>(xv[i], g[i], b, qv[i]);
+        if (!act[i]) continue;
+        if (okv[i]) {
+            const int l = qv[i] - rq[i];
+            cp += zz_bits(qv[i]);
+            cl += (l >= -(MC_R - 1) && l <= MC_R - 1) ? zz_bits(l) : ocost;
+        } else {
+            cp += ocost;
+            cl += ocost;
+        }
+    }
+    cp = wave_sum(cp);
+    cl = wave_sum(cl);
+    const int w = threadIdx.x >> 6;
+    if (lane_id() == 0) { s_sp[w] = cp; s_sl[w] = cl; }
+    __syncthreads();
+    long long sp = 0, sl = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) { sp += s_sp[k]; sl += s_sl[k]; }
+    const bool learned = sl < sp;                                // uniform over the workgroup
+    int nout = 0;
+#pragma unroll
+    for (int i = 0; i < MC_IPT; ++i) {
+        if (!act[i]) continue;
+        if (dbg_g) dbg_g[v[i]] = g[i];
+        int qi = qv[i];
+        bool ok = okv[i];
+        if (ok && learned) {
             qi -= rq[i];
             ok = qi >= -(MC_R - 1) && qi <= MC_R - 1;
         }
         codes[v[i]] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
         nout += ok ? 0 : 1;
     }
-    const bool first_of_block = (tile * MC_TILE) % MC_LBLOCK == 0;
     nout = wave_sum(nout);
-    if (lane_id() == 0) s_cnt[threadIdx.x >> 6] = nout;
+    if (lane_id() == 0) s_cnt[w] = nout;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned c = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
+    if (lt == 0 && tile < ntv) {
+        unsigned c = 0;
+#pragma unroll
+        for (int k = 0; k < MC_WG / 64; ++k) c += (unsigned)s_cnt[sub * (MC_WG / 64) + k];
         if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
-        if (LEARNED && learned && first_of_block) {
+        if (learned && sub == 0) {
             c |= 0x80000000u;
             atomicOr(&bflags[blk >> 5], 1u << (blk & 31));
         }
@@ -754,33 +777,27 @@ hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long 
 }
 
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
-                    hipStream_t s)
+                    const DevBound* bnd, const int32_t* rho_q, uint16_t* codes, uint32_t* bflags, float* dbg_g,
+                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s)
 {
     remap &= MC_KNOB_RESIDUAL;
-    const bool L = rho_q != nullptr;
-    const dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
-    if (L) {
-        ProfScope ps("k_learned_cost", s);
-#define MC_LC(T, D) hipLaunchKernelGGL((k_learned_cost<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, \
-                                       bnd, rho_q, bcost, remap)
-        if (dtype == MC_F64) { if (gg.dim == 2) MC_LC(double, 2); else MC_LC(double, 3); }
-        else { if (gg.dim == 2) MC_LC(float, 2); else MC_LC(float, 3); }
-#undef MC_LC
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
+    if (rho_q) {
+        ProfScope ps("k_residual_learned", s);
+        const dim3 grid((unsigned)((nv + MC_LBLOCK - 1) / MC_LBLOCK));
+#define MC_RL(T, D) hipLaunchKernelGGL((k_residual_learned<T, D>), grid, dim3(MC_LTILES * MC_WG), 0, s, coords, nv, gg, \
+                                       xh, (const T*)x, bnd, rho_q, codes, bflags, dbg_g, count, vsum, ntv, remap)
+        if (dtype == MC_F64) { if (gg.dim == 2) MC_RL(double, 2); else MC_RL(double, 3); }
+        else { if (gg.dim == 2) MC_RL(float, 2); else MC_RL(float, 3); }
+#undef MC_RL
+        return hipGetLastError();
     }
-    ProfScope ps(L ? "k_residual_learned" : "k_residual", s);
-#define MC_RQ(T, D, LL) hipLaunchKernelGGL((k_residual<T, D, LL>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, \
-                                           bnd, rho_q, bcost, codes, bflags, dbg_g, count, vsum, remap)
-    if (dtype == MC_F64) {
-        if (gg.dim == 2) { if (L) MC_RQ(double, 2, true); else MC_RQ(double, 2, false); }
-        else { if (L) MC_RQ(double, 3, true); else MC_RQ(double, 3, false); }
-    } else {
-        if (gg.dim == 2) { if (L) MC_RQ(float, 2, true); else MC_RQ(float, 2, false); }
-        else { if (L) MC_RQ(float, 3, true); else MC_RQ(float, 3, false); }
-    }
+    ProfScope ps("k_residual", s);
+    const dim3 grid((unsigned)ntv);
+#define MC_RQ(T, D) hipLaunchKernelGGL((k_residual<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, bnd, \
+                                       codes, dbg_g, count, vsum, remap)
+    if (dtype == MC_F64) { if (gg.dim == 2) MC_RQ(double, 2); else MC_RQ(double, 3); }
+    else { if (gg.dim == 2) MC_RQ(float, 2); else MC_RQ(float, 3); }
 #undef MC_RQ
     return hipGetLastError();
 }

@@ -691,15 +691,14 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
         PCHK(hipMemsetAsync(p->ctl, 0, 64 * sizeof(unsigned long long), s));
         PCHK(hipMemcpyAsync(p->rbuf, init, sizeof init, hipMemcpyHostToDevice, s));
     }
-    // per-call state cleared by k_range: error bits, learned block costs,
-    // outlier totals per group of MC_SC_TILES tiles
+    // per-call state cleared by k_range: error bits, outlier totals per group
+    // of MC_SC_TILES tiles
     const long long ngg = (p->ntg + MC_SC_TILES - 1) / MC_SC_TILES, ngv = (p->ntv + MC_SC_TILES - 1) / MC_SC_TILES;
-    p->nsmall = 16 + 2 * p->nblk + ngg + ngv;
+    p->nsmall = 16 + ngg + ngv;
     PCHK(plan_alloc(p, &p->small, (size_t)p->nsmall));
     PCHK(hipMemsetAsync(p->small, 0, (size_t)p->nsmall * 4, s));
     p->err = p->small + 2;
-    p->bcost = p->small + 16;
-    p->gsum = p->bcost + 2 * p->nblk;
+    p->gsum = p->small + 16;
     p->vsum = p->gsum + ngg;
     PCHK(plan_alloc(p, &p->counts, (size_t)(p->ntg + p->ntv)));
     PCHK(plan_alloc(p, &p->dagg, (size_t)p->ntv));
@@ -865,9 +864,8 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, nullptr, d_field, dtype, p->bound,
                                  codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
     } else {
-        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, p->bcost,
-                           codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
-                           s));
+        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, codes->vert_codes,
+                           codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
     }
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
                       codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta,

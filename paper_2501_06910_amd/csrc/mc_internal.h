@@ -37,7 +37,6 @@ struct mc_plan_s {
     unsigned* small = nullptr;           // per-call state cleared by k_range (u32 words)
     long long nsmall = 0;
     unsigned* err = nullptr;             // small[2]
-    unsigned* bcost = nullptr;           // learned block costs [2 * nblk] (in small)
     unsigned* counts = nullptr;          // per-tile outlier counts and offsets
     unsigned* gcount = nullptr;
     unsigned* vcount = nullptr;

@@ -61,9 +61,8 @@ hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, c
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
                    unsigned int* count, unsigned int* gsum, unsigned remap, hipStream_t s);
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const DevBound* bnd, const int32_t* rho_q, unsigned int* bcost, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
-                    hipStream_t s);
+                    const DevBound* bnd, const int32_t* rho_q, uint16_t* codes, uint32_t* bflags, float* dbg_g,
+                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s);
 // gpred: the mc_grid_predictor whose errors the grid outliers carry (gref:
 // the time-axis predictor's reference grid)
 hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const float* gref,
