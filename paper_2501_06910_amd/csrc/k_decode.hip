@@ -1,11 +1,15 @@
 // k_decode.hip -- decompression on gfx950 (paper Alg. 4).
 //   k_d2_*     2-D Lorenzo inverse on 256-column row segments (below)
-//   k_dec_xy_* (3-D) inverse within each z-plane: d = code - R (outliers
-//              by binary search in the ascending outlier list); column
-//              totals per chunk of rows, their prefix over the plane's
-//              chunks, then running column sums plus a wave scan along x
-//   k_dec_z_*  (3-D) inclusive prefix along z in chunks of planes: totals,
-//              prefix over the chunks, apply; in place
+//   k_d3_*     3-D Lorenzo inverse for rows of at most 1024 nodes: tile
+//              face sums, their prefixes, then x1' straight from the codes
+//              (below)
+//   k_dec_xy_* (3-D, longer rows) inverse within each z-plane: d = code - R
+//              (outliers by binary search in the ascending outlier list);
+//              column totals per chunk of rows, their prefix over the
+//              plane's chunks, then running column sums plus a wave scan
+//              along x
+//   k_dec_z_*  (3-D, longer rows) inclusive prefix along z in chunks of
+//              planes: totals, prefix over the chunks, apply; in place
 //   k_vdecode  g(x1') at each vertex from the decoded grid, dequantisation
 //              x' = (T)(g + q * 2 tau2), learned shift in learned blocks,
 //              raw values for outliers
@@ -19,7 +23,7 @@ __device__ __forceinline__ int wave_excl_scan(int v)
 }
 
 // The grid decoder is the inclusive prefix sum of the Lorenzo errors along
-// every axis.  In 3-D the z prefix runs first (on the decoded errors), then
+// every axis.  Generic 3-D path: the z prefix runs first (on the decoded errors), then
 // the 2-D prefix of each plane; the last pass writes x1' = (float)(c + p *
 // 2 tau1) directly.  Tiles: (chunk of rows) x (all x) per plane for the xy
 // part, (chunk of planes) x (the same chunk of rows) for the z part, so the
