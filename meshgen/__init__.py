@@ -31,7 +31,7 @@ __all__ = [
     "kuhn_tet_mesh", "structured_tri_mesh", "aligned_tri_mesh",
     "field_bumps_2d", "field_front_2d", "field_octaves", "rotated_front_series",
     "config_small_2d", "config_large_2d", "config_tet_3d", "config_learned_series",
-    "config_batch",
+    "config_batch", "sliver_mesh",
 ]
 
 
@@ -403,3 +403,47 @@ def config_batch(seed: int = 5, scale: float = 1.0, n_meshes: int = 12,
         fields.append(dict(mesh=m, data=field_octaves(meshes[m].coords, fr, dtype=dt),
                            eb=(1e-3, 1e-4, 1e-5)[i % 3], eb_mode="rel", split=0.5))
     return meshes, grids, fields
+
+
+# ---------------------------------------------------------------------------
+# Meshes with near-degenerate cells over grid nodes
+# ---------------------------------------------------------------------------
+
+def sliver_mesh(dim: int, seed: int = 0):
+    """A mesh over [0,1]^dim whose lowest-numbered cells are slivers: thin
+    triangles (2-D) or flat tetrahedra (3-D) whose thickness is about 5e-4
+    against an extent near 0.8, laid across rows (2-D) or planes (3-D) of
+    the grid returned with it, so that grid nodes lie strictly inside them.
+    Each sliver's base sits 1e-4 below the nominal row / plane position and
+    its apex 4e-4 above, so FP32 rounding of node positions (about 1e-7)
+    cannot move a node across.  The rest of the mesh is an unjittered
+    structured triangulation (13 x 11) or Kuhn lattice (9^3) covering the
+    box, so every node is located.  Returns (mesh, dims, field float32)."""
+    rng = np.random.default_rng(seed)
+    if dim == 2:
+        base = structured_tri_mesh(13, 11)
+        dims = (41, 37)
+        slivers = []
+        for row in (9, 20):                 # horizontal slivers across node rows
+            y = row / (dims[1] - 1)
+            slivers.append([(0.05, y - 1e-4), (0.95, y - 1e-4), (0.5, y + 4e-4)])
+        col = 30                            # a vertical one across a node column
+        x = col / (dims[0] - 1)
+        slivers.append([(x - 1e-4, 0.05), (x + 4e-4, 0.5), (x - 1e-4, 0.95)])
+    else:
+        base = kuhn_tet_mesh(9, seed, jitter=0.0)
+        dims = (17, 15, 13)
+        z = 6 / (dims[2] - 1)
+        x = 4 / (dims[0] - 1)
+        slivers = [
+            [(0.1, 0.1, z - 1e-4), (0.9, 0.15, z - 1e-4), (0.3, 0.9, z - 1e-4), (0.5, 0.45, z + 4e-4)],
+            [(x - 1e-4, 0.1, 0.1), (x - 1e-4, 0.9, 0.2), (x - 1e-4, 0.2, 0.9), (x + 4e-4, 0.5, 0.5)],
+        ]
+    nv = base.n_vertices
+    extra = np.array([p for s in slivers for p in s], np.float64).T
+    coords = np.ascontiguousarray(np.concatenate([base.coords, extra.astype(np.float32)], axis=1))
+    k = dim + 1
+    sc = (nv + np.arange(len(slivers) * k, dtype=np.int32)).reshape(len(slivers), k).T
+    cells = np.ascontiguousarray(np.concatenate([sc, base.cells], axis=1).astype(np.int32))
+    mesh = Mesh(coords, cells, {"kind": f"sliver{dim}d", "n_slivers": len(slivers)})
+    return mesh, dims, field_octaves(coords, rng)

@@ -86,6 +86,7 @@ def lib():
             "mco_locate_raster": (i64, [P, P, i32, i64, i64, P, P, P, P]),
             "mco_fill_unresolved": (None, [P, i32, i64, P, P, i32, P, P]),
             "mco_locate_nodes": (None, [P, P, i32, i64, i64, P, P, i64, P, i32, i32, P, P, P]),
+            "mco_fill_candidates": (None, [P, i32, i64, P, P, i64, P, P, P, P]),
             "mco_serial_compress": (i32, [P, i32, i64, dbl, i32, P, P, P, i64, P, P]),
             "mco_serial_decompress": (None, [P, P, P, i64, i64, P, i32, P]),
             "mco_resample": (None, [P, P, i32, i64, P, i32, dbl, P]),
@@ -234,7 +235,17 @@ class Mapping:
     n_unresolved: int
 
 
-def locate(coords, cells, g: Grid, method: str = "raster", fill: str = "nearest") -> Mapping:
+def locate(coords, cells, g: Grid, method: str = "raster", fill: str = "nearest",
+           fill_method: str = "brute") -> Mapping:
+    """Point location of every grid node (lowest-id containing cell), then
+    the fill of the nodes no cell contains.  fill_method "brute" scans every
+    vertex per unresolved node; "kdtree" scans, per node, only the vertices
+    a k-d tree ball query returns (see fill_nearest_kdtree), for meshes too
+    large for the scan."""
+    if fill == "nearest" and fill_method == "kdtree":
+        m = locate(coords, cells, g, method, fill=None)
+        fill_nearest_kdtree(coords, g, m)
+        return m
     dim = coords.shape[0]
     ng = g.count
     cell = np.empty(ng, np.int32)
@@ -247,6 +258,41 @@ def locate(coords, cells, g: Grid, method: str = "raster", fill: str = "nearest"
         lib().mco_fill_unresolved(_p(coords), dim, coords.shape[1], _p(g), _p(cell),
                                   int(fill == "nearest"), _p(vid), _p(w))
     return Mapping(cell, vid, w, int(nun))
+
+
+def fill_nearest_kdtree(coords, g: Grid, m: Mapping) -> None:
+    """Nearest-vertex fill of the unresolved nodes of m, in place.  A k-d
+    tree (scipy, a library nearest-neighbour search in exact FP64 distances
+    of the FP32 coordinates) gives each node its nearest distance d; every
+    vertex within d * (1 + 1e-5) is then a candidate, and the node takes the
+    candidate of smallest FP32 squared distance (ties: lowest id), the
+    definition of mco_fill_unresolved.  The FP32 metric is within a relative
+    6 * 2^-24 of the exact squared distance, so any vertex attaining its
+    minimum lies within d * (1 + 4e-7): the candidate lists are complete."""
+    from scipy.spatial import cKDTree
+    dim = coords.shape[0]
+    nodes = np.nonzero(m.cell < 0)[0].astype(np.int64)
+    if nodes.size == 0:
+        return
+    pts = grid_nodes_of(g, nodes)[:dim].T
+    tree = cKDTree(coords.T.astype(np.float64))
+    d, _ = tree.query(pts.astype(np.float64), k=1)
+    lists = tree.query_ball_point(pts.astype(np.float64), d * (1.0 + 1e-5) + 1e-30)
+    ptr = np.zeros(nodes.size + 1, np.int64)
+    ptr[1:] = np.cumsum([len(a) for a in lists])
+    cand = np.ascontiguousarray(np.concatenate([np.asarray(a, np.int32) for a in lists]), np.int32)
+    lib().mco_fill_candidates(_p(np.ascontiguousarray(coords, np.float32)), dim, coords.shape[1], _p(g),
+                              _p(nodes), nodes.size, _p(ptr), _p(cand), _p(m.vid), _p(m.w))
+
+
+def grid_nodes_of(g: Grid, nodes) -> np.ndarray:
+    """FP32 coordinates [3, len(nodes)] of the listed nodes (one C call per node)."""
+    out = np.zeros((3, len(nodes)), np.float32)
+    y = np.zeros(3, np.float32)
+    for i, j in enumerate(nodes):
+        lib().mco_grid_node(_p(g), int(j), _p(y))
+        out[:, i] = y
+    return out
 
 
 def locate_nodes(coords, cells, g: Grid, nodes, cand, fill: str = "nearest") -> Mapping:

@@ -74,6 +74,8 @@ int64_t mco_locate_raster(const float* coords, const int32_t* cells, int dim, in
                           int32_t* vid, float* w);
 void mco_fill_unresolved(const float* coords, int dim, int64_t nv, const mco_grid* g,
                          const int32_t* cell_of_node, int nearest, int32_t* vid, float* w);
+void mco_fill_candidates(const float* coords, int dim, int64_t nv, const mco_grid* g, const int64_t* nodes,
+                         int64_t nn, const int64_t* cand_ptr, const int32_t* cand, int32_t* vid, float* w);
 void mco_locate_nodes(const float* coords, const int32_t* cells, int dim, int64_t nv, int64_t nc,
                       const mco_grid* g, const int64_t* nodes, int64_t nn, const int32_t* cand, int ncand,
                       int nearest, int32_t* cell_out, int32_t* vid_out, float* w_out);

@@ -329,6 +329,42 @@ void mco_fill_unresolved(const float* coords, int dim, int64_t nv, const mco_gri
     }
 }
 
+/* Nearest-vertex fill of selected nodes (Sec. 8 reading of Fig. 1: a node
+ * outside every cell takes the value of its nearest vertex), the same FP32
+ * metric and lowest-id tie-break as mco_fill_unresolved, each node's
+ * minimum taken over its own candidate vertices only:
+ * cand[cand_ptr[i] .. cand_ptr[i+1]) for node nodes[i].  Equal to the
+ * definition whenever every candidate list holds all vertices that can
+ * attain that node's minimum.  Writes vid/w of the full grid arrays
+ * (k * ng + node). */
+void mco_fill_candidates(const float* coords, int dim, int64_t nv, const mco_grid* g, const int64_t* nodes,
+                         int64_t nn, const int64_t* cand_ptr, const int32_t* cand, int32_t* vid, float* w)
+{
+    int64_t ng = grid_count(g);
+    float y[3];
+    for (int64_t i = 0; i < nn; ++i) {
+        int64_t j = nodes[i];
+        mco_grid_node(g, j, y);
+        int64_t best = -1;
+        float bd = 0.0f;
+        for (int64_t k = cand_ptr[i]; k < cand_ptr[i + 1]; ++k) {
+            int64_t v = cand[k];
+            float dx = coords[v] - y[0];
+            float dy = coords[nv + v] - y[1];
+            float dd = dx * dx + dy * dy;
+            if (dim == 3) {
+                float dz = coords[2 * nv + v] - y[2];
+                dd = dd + dz * dz;
+            }
+            if (best < 0 || dd < bd || (dd == bd && v < best)) { best = v; bd = dd; }
+        }
+        for (int k = 0; k <= dim; ++k) {
+            vid[(int64_t)k * ng + j] = (int32_t)best;
+            w[(int64_t)k * ng + j] = k == 0 ? 1.0f : 0.0f;
+        }
+    }
+}
+
 /* Point location of selected grid nodes (the definition above, restricted):
  * node nodes[i] is tested against the cells cand[i * ncand .. + ncand - 1]
  * (cell ids, ascending; -1 entries are skipped), takes the lowest id that

@@ -3,13 +3,21 @@
 1e-4, split 0.5) in the launch order bench.py times.
 
 Properties checked everywhere: the error split equals the oracle's closed
-form, every vertex is within tau2.  On a seeded sample of grid nodes and of
-vertices the oracle computes the results one by one: the nodes involved are
-located against the 27-cube candidate sets of the lattice (pinned against
-brute-force location by a CPU test), resampled, prequantised and Lorenzo
-coded; the vertices are back-interpolated from those nodes, quantised and
-decoded.  Mapping, grid codes, vertex codes, outlier payloads and decoded
-values must match bit for bit."""
+form, every vertex is within tau2.
+
+Whole arrays: the oracle locates every grid node (bin-raster location,
+pinned against brute force by CPU tests; the nodes outside the mesh filled
+through k-d tree candidate lists, pinned against the brute-force fill) and
+compresses and decompresses the whole field; the plan's mapping, every
+grid and vertex code, both outlier lists and every decoded value must
+match bit for bit.
+
+Sampled, independently of the raster: on a seeded sample of grid nodes and
+of vertices (every vertex outlier included) the oracle computes the results
+one by one: the nodes involved are located against the 27-cube candidate
+sets of the lattice (pinned against brute-force location by a CPU test),
+resampled, prequantised and Lorenzo coded; the vertices are
+back-interpolated from those nodes, quantised and decoded."""
 import numpy as np
 import pytest
 
@@ -54,6 +62,30 @@ def test_bound_everywhere(run):
     assert np.all(err <= b.tau2)
 
 
+def test_full_parity(run):
+    mesh, f, cfg, plan, h, xr = run
+    g = O.grid_from_dims(mesh.coords, cfg["dims"])
+    m = O.locate(mesh.coords, mesh.cells, g, "raster", fill="nearest", fill_method="kdtree")
+    print(f"[fullsize] oracle located {g.count} nodes ({m.n_unresolved} filled)", flush=True)
+    vid_g, w_g, cell_g = plan.mapping()
+    assert np.array_equal(cell_g.cpu().numpy(), m.cell)
+    assert np.array_equal(vid_g.cpu().numpy(), m.vid)
+    assert np.array_equal(w_g.cpu().numpy().view(np.uint32), m.w.view(np.uint32))
+    del vid_g, w_g, cell_g
+    assert plan.info()["n_unresolved"] == m.n_unresolved
+    oc = O.compress(mesh.coords, m, g, f, cfg["eb"], True, cfg["split"])
+    assert np.array_equal(h["grid_codes"], oc.grid.codes)
+    assert np.array_equal(h["g_out_idx"], oc.grid.out_idx)
+    assert np.array_equal(h["g_out_delta"], oc.grid.out_delta)
+    assert np.array_equal(h["vert_codes"], oc.vert.codes)
+    assert np.array_equal(h["v_out_idx"], oc.vert.out_idx)
+    assert np.array_equal(h["v_out_val"].view(np.uint32), oc.vert.out_val.view(np.uint32))
+    xo = O.decompress(mesh.coords, g, oc.bound, oc.grid, oc.vert, f.dtype)
+    assert np.array_equal(xr.view(np.uint32), xo.view(np.uint32))
+    print(f"[fullsize] whole arrays equal: {g.count} grid codes ({oc.grid.out_idx.size} outliers), "
+          f"{mesh.n_vertices} vertex codes ({oc.vert.out_idx.size} outliers), decoded values", flush=True)
+
+
 def test_sampled_parity(run):
     mesh, f, cfg, plan, h, xr = run
     g = O.grid_from_dims(mesh.coords, cfg["dims"])
@@ -61,7 +93,7 @@ def test_sampled_parity(run):
     b = O.bound(f, cfg["eb"], True, cfg["split"])
     rng = np.random.default_rng(2024)
     gs = np.sort(rng.choice(g.count, 256, replace=False))
-    vs = np.sort(rng.choice(mesh.n_vertices, 256, replace=False))
+    vs = np.union1d(rng.choice(mesh.n_vertices, 256, replace=False), h["v_out_idx"])
 
     # nodes the samples depend on: Lorenzo neighbours of gs, cell corners of vs
     need = set()

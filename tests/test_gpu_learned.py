@@ -175,9 +175,57 @@ def test_one_training_step_matches_oracle():
     assert cos(step_g, step_o) >= 0.99
 
 
+def _tensor_cuts(dim):
+    kin = O.mlp_kin(dim)
+    return np.cumsum([0, 64 * kin, 64, 4096, 64, 4096, 64, 64, 1])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_training_trajectory_matches_oracle(dim):
+    """24 Adam steps on the GPU and in the oracle from the same seeded
+    initialisation on the same SplitMix64 minibatches of the t = 0
+    residuals: per-step losses, and per weight tensor the parameters and
+    their displacement from the initialisation.  Gradients differ by the
+    MFMA summation order (rel-L2 ~1e-3, test_gradient_parity); Adam turns
+    each gradient entry into a step of about lr * sign, so entries whose
+    gradient hovers near zero may step differently.  Measured on MI355X:
+    displacement cosine >= 0.9999 and rel-L2 <= 1.4e-2 per tensor, loss
+    within 1e-3; the bounds below leave about 2x of that."""
+    mesh, series, dims = _series_case(dim)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    B, seed, lr, T = 1024, 91, 1e-3, 24
+    model, loss_g = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=T, batch=B, lr=lr, seed=seed,
+                                  return_loss=True)
+    p_gpu, kappa = model.params()
+    og = O.grid_from_dims(mesh.coords, dims)
+    om = O.locate(mesh.coords, mesh.cells, og)
+    pc = O.compress(mesh.coords, om, og, series[0], 1e-4, True, 0.5)
+    z = O.mlp_features(mesh.coords, og, pc.xhat, pc.gv, kappa)
+    y = ((series[0].astype(np.float64) - pc.gv.astype(np.float64)) * pc.bound.inv2).astype(np.float32)
+    p0 = O.mlp_init(dim, seed)
+    p_o, loss_o = O.train(dim, z, y, T, B, seed, lr)
+    loss_o = np.array(loss_o)
+    dl = np.abs(loss_g - loss_o) / np.abs(loss_o)
+    print(f"[trajectory D={dim}] loss {loss_o[0]:.4f} -> {loss_o[-1]:.4f}; max rel loss diff {dl.max():.2e}")
+    assert dl.max() <= 1e-2
+    assert loss_o[-1] < loss_o[0]
+    cuts = _tensor_cuts(dim)
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        dg, do = p_gpu[a:b] - p0[a:b], p_o[a:b] - p0[a:b]
+        r, c = rel_l2(dg, do), cos(dg, do)
+        rp = rel_l2(p_gpu[a:b], p_o[a:b])
+        print(f"[trajectory D={dim}] tensor [{a}:{b}] displacement rel-L2 {r:.2e} cos {c:.5f}; "
+              f"parameters rel-L2 {rp:.2e}")
+        assert c >= 0.999, (a, b)
+        assert r <= 3e-2, (a, b)
+        assert rp <= 2e-2, (a, b)
+
+
 def test_learned_gain_on_time_series():
-    """Train on t=0, compress t=1: the per-block choice makes the learned
-    stream no larger than the plain one; the gain itself is reported."""
+    """Train on t=0, compress t=1 and t=2: the per-block choice makes the
+    learned stream no larger than the plain one by construction; here the
+    trained network also wins blocks, and the vertex stream and its code
+    entropy shrink (a network that predicts nothing wins no block)."""
     mesh, series, cfg = G.config_learned_series(h0=0.003, dims=256, steps=3)
     plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=(256, 256))
     model, loss = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=400, batch=4096, seed=5, return_loss=True)
@@ -196,3 +244,6 @@ def test_learned_gain_on_time_series():
               f"blocks learned {learned['result']['n_learned_blocks']}")
         assert learned["result"]["status"] == 0
         assert sl <= sp + learned["block_flags"].size * 4
+        assert learned["result"]["n_learned_blocks"] > 0
+        assert sl < sp
+        assert hl < hp

@@ -81,6 +81,12 @@ def _cases():
     out.append(("kuhn3d_f32_full", m3, G.field_octaves(m3.coords, np.random.default_rng(1)), (12, 12, 11), 1e-4,
                 True, 16.0, "midrange", "full"))
     out.append(("kuhn3d_f64_full_tiny", m4, x4, (20, 19, 18), 1e-7, True, 0.25, "nearest", "full"))
+    # slivers with the lowest ids over grid rows / planes: nodes whose
+    # weights come from the FP64 recompute of near-degenerate cells
+    for dim in (2, 3):
+        ms, ds, fs = G.sliver_mesh(dim, 11)
+        out.append((f"sliver{dim}d_f32", ms, fs, ds, 1e-5, True, 0.5, "nearest"))
+        out.append((f"sliver{dim}d_f64", ms, fs.astype(np.float64), ds, 1e-6, True, 0.5, "midrange"))
     return out
 
 
@@ -107,6 +113,27 @@ def test_plan_mapping_bitexact(case):
     assert np.array_equal(cell.cpu().numpy(), case.om.cell)
     assert np.array_equal(vid.cpu().numpy(), case.om.vid)
     assert np.array_equal(w.cpu().numpy().view(np.uint32), case.om.w.view(np.uint32))
+
+
+def test_near_degenerate_count(case):
+    """The plan's count of nodes whose weights came from the FP64 recompute
+    equals the number of nodes whose chosen cell meets the near-degenerate
+    trigger (each checked with the oracle's barycentric routine); the sliver
+    meshes have such nodes."""
+    info = case.plan.info()
+    cells = case.mesh.cells
+    coords = case.mesh.coords
+    dim = case.mesh.dim
+    nd_cells = {}
+    expect = 0
+    for c in case.om.cell[case.om.cell >= 0].tolist():
+        if c not in nd_cells:
+            verts = coords[:, cells[:, c]].T
+            nd_cells[c] = O.bary(verts, verts[0])[2]
+        expect += int(nd_cells[c])
+    assert info["n_near_degenerate"] == expect
+    if case.name.startswith("sliver"):
+        assert expect >= 40
 
 
 def test_compress_bitexact(case):

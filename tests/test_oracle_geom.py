@@ -304,3 +304,63 @@ def test_kuhn_candidates_are_complete():
     assert np.array_equal(got.vid, ref.vid)
     assert np.array_equal(got.w.view(np.uint32), ref.w.view(np.uint32))
     assert ref.n_unresolved > 0          # the ragged hull leaves nodes to the fill
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_near_degenerate_cells_located_with_fp64_weights(dim):
+    """Slivers with the lowest cell ids lie across grid rows / planes: the
+    nodes inside them are located there (brute force = bin raster), each
+    chosen sliver meets the near-degenerate trigger, and the stored weights
+    are the exact rational barycentric coordinates rounded once to FP32
+    (within one FP32 ulp plus 2^-40), which the FP64 recompute delivers."""
+    mesh, dims, _ = G.sliver_mesh(dim)
+    ns = mesh.info["n_slivers"]
+    g = O.grid_from_dims(mesh.coords, dims)
+    mb = O.locate(mesh.coords, mesh.cells, g, "brute", fill=None)
+    mr = O.locate(mesh.coords, mesh.cells, g, "raster", fill=None)
+    assert np.array_equal(mb.cell, mr.cell)
+    assert np.array_equal(mb.w.view(np.uint32), mr.w.view(np.uint32))
+    sel = np.nonzero((mb.cell >= 0) & (mb.cell < ns))[0]
+    assert sel.size >= 40
+    assert set(mb.cell[sel].tolist()) == set(range(ns))
+    for j in sel:
+        c = mb.cell[j]
+        verts = mesh.coords[:, mesh.cells[:, c]].T
+        y = O.grid_node(g, j)[:dim]
+        inside, lam, nd = O.bary(verts, y)
+        assert nd and inside
+        ex = exact_bary(verts, y)
+        for k in range(dim + 1):
+            e = float(ex[k])
+            ulp = np.spacing(np.float32(abs(e))).astype(np.float64)
+            assert abs(float(mb.w[k, j]) - e) <= ulp + 2.0 ** -40, (j, k)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fill_kdtree_equals_brute(dim):
+    """The k-d tree candidate fill gives the brute-force nearest-vertex fill
+    (FP32 metric, lowest id on ties) on meshes with ragged hulls, including
+    a lattice where many vertices tie (unjittered, grid nodes equidistant
+    from several vertices)."""
+    rng = np.random.default_rng(40 + dim)
+    cases = []
+    if dim == 2:
+        cases.append((G.delaunay_2d(G.stratified_points_2d(30, rng, drop=40)), (37, 33)))
+        s = G.structured_tri_mesh(9, 9)
+        cen = s.coords[:, s.cells].mean(axis=1)
+        keep = np.hypot(cen[0] - 0.5, cen[1] - 0.5) > 0.3
+        cases.append((G.Mesh(s.coords, np.ascontiguousarray(s.cells[:, keep])), (17, 17)))
+    else:
+        cases.append((G.kuhn_tet_mesh(7, 3), (13, 12, 11)))
+        s = G.kuhn_tet_mesh(6, 4, jitter=0.0)        # a hole: drop the central cubes' tets
+        cen = s.coords[:, s.cells].mean(axis=1)
+        keep = np.abs(cen - 0.5).max(axis=0) > 0.25
+        cases.append((G.Mesh(s.coords, np.ascontiguousarray(s.cells[:, keep])), (11, 11, 11)))
+    for mesh, dims in cases:
+        g = O.grid_from_dims(mesh.coords, dims)
+        a = O.locate(mesh.coords, mesh.cells, g, "raster", fill="nearest")
+        b = O.locate(mesh.coords, mesh.cells, g, "raster", fill="nearest", fill_method="kdtree")
+        assert a.n_unresolved > 0
+        assert np.array_equal(a.cell, b.cell)
+        assert np.array_equal(a.vid, b.vid)
+        assert np.array_equal(a.w.view(np.uint32), b.w.view(np.uint32))

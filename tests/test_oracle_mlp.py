@@ -137,3 +137,55 @@ def test_training_reduces_loss():
     y = (z[:, :kin] @ wt).astype(np.float32) * 3
     params, losses = O.train(dim, z, y, steps=150, batch=128, seed=7, lr=3e-3)
     assert np.mean(losses[-10:]) < 0.2 * np.mean(losses[:10])
+
+
+def test_adam_constant_gradient_closed_form():
+    """With the same gradient g at every step from m = v = 0, the moments are
+    m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2 exactly, so the bias-corrected
+    estimates are g and g^2 at every t and each step moves lr g / (|g| + eps).
+    A bias correction with the wrong power of beta at any t >= 2 moves the
+    parameters by a visibly different amount (1 + b1 = 1.9 times as far for
+    1 - b1 in place of 1 - b1^2)."""
+    rng = np.random.default_rng(8)
+    p = rng.normal(size=64).astype(np.float32)
+    g = (rng.normal(size=64) * 10.0 ** rng.integers(-2, 2, 64)).astype(np.float32)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    p0 = p.astype(np.float64)
+    step = 1e-3 * g.astype(np.float64) / (np.abs(g.astype(np.float64)) + 1e-8)
+    for t in range(1, 11):
+        O.adam_step(p, m, v, g, t, 1e-3)
+        np.testing.assert_allclose(p, p0 - t * step, rtol=0, atol=2e-6)
+        np.testing.assert_allclose(m, (1 - 0.9 ** t) * g, rtol=2e-6, atol=0)
+        np.testing.assert_allclose(v, (1 - 0.999 ** t) * g.astype(np.float64) ** 2, rtol=2e-5, atol=0)
+
+
+def test_adam_three_steps_hand_derived():
+    """Gradients 1, -2, 1/2 on one parameter from p = 1, lr 1e-3, b1 0.9,
+    b2 0.999, eps 1e-8, worked by hand:
+      t=1: m = 1/10, v = 1/1000; m_hat = 1, v_hat = 1
+      t=2: m = 9/100 - 2/10 = -11/100; v = 999/10^6 + 4/1000 = 4999/10^6;
+           m_hat = (-11/100) / (19/100) = -11/19; v_hat = 4999/1999
+      t=3: m = -99/1000 + 5/100 = -49/1000; v = 999*4999/10^9 + 25/10^5
+           = 5244001/10^9; m_hat = (-49/1000) / (271/1000) = -49/271;
+           v_hat = 5244001/2997001
+    and p_t = p_{t-1} - lr m_hat / (sqrt(v_hat) + eps).  A correction
+    left at its t = 1 value would make steps 2 and 3 34 % and 57 % larger,
+    far above the FP32 tolerance used."""
+    from math import sqrt
+    m_hat = [1.0, -11 / 19, -49 / 271]
+    v_hat = [1.0, 4999 / 1999, 5244001 / 2997001]
+    m_exp = [0.1, -0.11, -0.049]
+    v_exp = [1e-3, 4999e-6, 5244001e-9]
+    p = np.array([1.0], np.float32)
+    m = np.zeros(1, np.float32)
+    v = np.zeros(1, np.float32)
+    ref = 1.0
+    for t, gt in enumerate([1.0, -2.0, 0.5], start=1):
+        O.adam_step(p, m, v, np.array([gt], np.float32), t, 1e-3)
+        ref -= 1e-3 * m_hat[t - 1] / (sqrt(v_hat[t - 1]) + 1e-8)
+        # b1 and b2 are FP32 (0.9f and 0.999f differ from 0.9 and 0.999 by
+        # 2.4e-8 and 1.3e-8, i.e. up to 1.3e-5 relative in 1 - b2)
+        assert abs(float(m[0]) - m_exp[t - 1]) <= 1e-6 * abs(m_exp[t - 1])
+        assert abs(float(v[0]) - v_exp[t - 1]) <= 3e-5 * v_exp[t - 1]
+        assert abs(float(p[0]) - ref) <= 2e-7, t
