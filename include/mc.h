@@ -438,6 +438,23 @@ mc_status mc_serial_compress(mc_serial ctx, const void* d_field, mc_dtype dtype,
 mc_status mc_serial_decompress(mc_serial ctx, const mc_codes* codes, int64_t n, void* d_out, mc_dtype dtype,
                                hipStream_t stream);
 
+/* Compress without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc): mc_serial_compress without a context.  Its scratch
+ * (range partials, control block, outlier counters; about 1.2 MB) is one
+ * fixed array in device memory per GPU, held from the first call on that
+ * GPU until the process ends; n is limited to MC_SERIAL_NOALLOC_MAX
+ * values (above it: MC_ERR_CAPACITY, nothing enqueued).  Codes, outliers
+ * and result equal mc_serial_compress's for the same input.  Every call on
+ * one GPU shares that array (each call re-initialises it on the stream
+ * before use): calls that may overlap on one GPU -- different streams,
+ * different host threads -- race and must be serialised by the caller.
+ * Calls no hipMalloc, hipFree or allocating library routine. */
+#define MC_SERIAL_NOALLOC_MAX (1LL << 28)
+int64_t mc_serial_noalloc_max(void);
+mc_status mc_serial_compress_noalloc(const void* d_field, mc_dtype dtype, int64_t n, double eb, int32_t eb_mode,
+                                     const mc_codes* codes, hipStream_t stream);
+
 /* ---- profiling -----------------------------------------------------------
  * When enabled, every kernel launch is bracketed by HIP events on the
  * launch stream; mc_profile_read returns per-kernel launch counts and

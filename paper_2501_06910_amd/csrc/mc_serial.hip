@@ -3,7 +3,11 @@
 // decompress sequences.
 //   compress:   k_range -> k_range_final -> k_ser_codes -> k_scatter
 //   decompress: k_ser_tot -> k_ser_carry -> k_ser_apply
+// mc_serial_compress_noalloc runs the same compress sequence on a
+// fixed-size scratch array in device memory (one copy per GPU, resolved
+// with hipGetSymbolAddress) instead of a context's allocations.
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "mc_internal.h"
@@ -99,6 +103,92 @@ extern "C" mc_status mc_serial_compress(mc_serial s, const void* d_field, mc_dty
     ECHK(mck::serial_codes(d_field, dtype, n, bound, codes->vert_codes, s->count, vsum, err, codes->result, stream));
     ECHK(mck::compact(nullptr, 1, 1, 1, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_field, dtype, n,
                       codes->vert_codes, s->count, vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, err,
+                      codes->result, stream));
+#undef ECHK
+    return MC_OK;
+}
+
+// ---- compress without allocation --------------------------------------------
+// Scratch words of the compress sequence for n values (the layout of a
+// context's allocations, packed): RangeOut/DevBound control block, range
+// partials, the per-call counters that k_range clears (err at word 2,
+// per-group outlier sums from word 16) and the per-tile outlier counts.
+namespace {
+constexpr long long kNoallocTiles = (MC_SERIAL_NOALLOC_MAX + MC_TILE - 1) / MC_TILE;
+constexpr long long kNoallocGroups = (kNoallocTiles + MC_SC_TILES - 1) / MC_SC_TILES;
+constexpr size_t kCtlBytes = 64 * 8;
+constexpr size_t kPartialBytes = (size_t)3 * MC_RANGE_BLOCKS * 8;
+constexpr size_t kSmallBytes = ((size_t)(16 + kNoallocGroups) * 4 + 255) / 256 * 256;
+constexpr size_t kCountBytes = ((size_t)kNoallocTiles * 4 + 255) / 256 * 256;
+constexpr size_t kScratchBytes = kCtlBytes + kPartialBytes + kSmallBytes + kCountBytes;
+}  // namespace
+
+// The scratch array itself.  Its name is only a host-side handle: device
+// code gets the per-GPU address from hipGetSymbolAddress below.
+static __device__ __align__(256) unsigned char scratch[(kScratchBytes + 255) / 256 * 256];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64];           // per device, resolved once with that device current
+
+static mc_status scratch_address(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return mc_fail(MC_ERR_UNSUPPORTED, "device index %d above 63", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return mc_fail(MC_ERR_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return MC_OK;
+}
+
+extern "C" int64_t mc_serial_noalloc_max(void) { return MC_SERIAL_NOALLOC_MAX; }
+
+extern "C" mc_status mc_serial_compress_noalloc(const void* d_field, mc_dtype dtype, int64_t n, double eb,
+                                                int32_t eb_mode, const mc_codes* codes, hipStream_t stream)
+{
+    if (!d_field) return mc_fail(MC_ERR_ARG, "field pointer is NULL");
+    if (dtype != MC_F32 && dtype != MC_F64) return mc_fail(MC_ERR_ARG, "dtype must be MC_F32 or MC_F64");
+    if (n < 1) return mc_fail(MC_ERR_ARG, "n = %lld must be at least 1", (long long)n);
+    if (n > MC_SERIAL_NOALLOC_MAX)
+        return mc_fail(MC_ERR_CAPACITY, "n = %lld above the no-allocation limit of %lld values", (long long)n,
+                       (long long)MC_SERIAL_NOALLOC_MAX);
+    if (!(eb > 0.0) || !std::isfinite(eb)) return mc_fail(MC_ERR_ARG, "eb must be finite and > 0");
+    if (eb_mode != MC_EB_ABS && eb_mode != MC_EB_REL) return mc_fail(MC_ERR_ARG, "unknown eb_mode");
+    mc_status st = ser_check_codes(codes);
+    if (st != MC_OK) return st;
+    void* base = nullptr;
+    st = scratch_address(&base);
+    if (st != MC_OK) return st;
+    unsigned char* b = (unsigned char*)base;
+    unsigned long long* ctl = (unsigned long long*)b;
+    unsigned long long* partial = (unsigned long long*)(b + kCtlBytes);
+    unsigned int* small = (unsigned int*)(b + kCtlBytes + kPartialBytes);
+    unsigned int* count = (unsigned int*)(b + kCtlBytes + kPartialBytes + kSmallBytes);
+    const long long ntiles = (n + MC_TILE - 1) / MC_TILE;
+    const long long nsmall = 16 + (ntiles + MC_SC_TILES - 1) / MC_SC_TILES;
+    BoundParams bp;
+    bp.eb = eb;
+    bp.split = 0.5;
+    bp.relative = eb_mode == MC_EB_REL;
+    bp.mode = MC_SPLIT_SUM;
+    RangeOut* cur = (RangeOut*)ctl;
+    DevBound* bound = (DevBound*)(ctl + 16);
+    unsigned int* err = small + 2;
+    unsigned int* vsum = small + 16;
+    hipError_t e;
+#define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
+    // k_range clears small[0 .. nsmall) (err, the outlier sums) before anything reads it
+    ECHK(mck::range(d_field, dtype, n, partial, cur, bp, bound, small, nsmall, stream));
+    ECHK(mck::serial_codes(d_field, dtype, n, bound, codes->vert_codes, count, vsum, err, codes->result, stream));
+    ECHK(mck::compact(nullptr, 1, 1, 1, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_field, dtype, n,
+                      codes->vert_codes, count, vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, err,
                       codes->result, stream));
 #undef ECHK
     return MC_OK;

@@ -136,6 +136,8 @@ _SIGS = {
     "mc_serial_destroy": (C.c_int, [_P]),
     "mc_serial_compress": (C.c_int, [_P, _P, C.c_int, C.c_int64, C.c_double, C.c_int32, _P, _P]),
     "mc_serial_decompress": (C.c_int, [_P, _P, C.c_int64, _P, C.c_int, _P]),
+    "mc_serial_noalloc_max": (C.c_int64, []),
+    "mc_serial_compress_noalloc": (C.c_int, [_P, C.c_int, C.c_int64, C.c_double, C.c_int32, _P, _P]),
     "mc_profile_enable": (C.c_int, [C.c_int32]),
     "mc_profile_reset": (C.c_int, []),
     "mc_profile_read": (C.c_int32, [_P, _P, _P, C.c_int32]),
@@ -726,6 +728,25 @@ def serial_compress(ctx: Serial, field, eb: float, eb_mode: str = "rel", codes: 
                                     EB_REL if eb_mode == "rel" else EB_ABS, C.byref(codes.struct), _stream()),
            "mc_serial_compress")
     return codes
+
+
+def serial_compress_noalloc(field, eb: float, eb_mode: str = "rel", codes: SerialCodes | None = None,
+                            cap=None) -> SerialCodes:
+    """mc_serial_compress_noalloc: the 1-D baseline's compress on the
+    library's fixed per-GPU scratch (no context, no device allocation by
+    the library; fields of up to serial_noalloc_max() values)."""
+    _require_cuda(field, "field")
+    n = field.numel()
+    if codes is None:
+        codes = SerialCodes(n, field.dtype, cap)
+    _check(lib().mc_serial_compress_noalloc(_ptr(field), _dtype_code(field), n, eb,
+                                            EB_REL if eb_mode == "rel" else EB_ABS, C.byref(codes.struct),
+                                            _stream()), "mc_serial_compress_noalloc")
+    return codes
+
+
+def serial_noalloc_max() -> int:
+    return int(lib().mc_serial_noalloc_max())
 
 
 def serial_decompress(ctx: Serial, codes: SerialCodes, out=None):

@@ -99,6 +99,14 @@ def test_host_validation_before_device_work():
     assert lib.mc_serial_destroy(None) == M.OK
     assert lib.mc_serial_compress(None, fake, M.F32, 16, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
     assert lib.mc_serial_decompress(None, C.byref(codes), 16, fake, M.F32, None) == M.ERR_ARG
+    # the allocation-free compress: limits and pointers checked on the host
+    assert lib.mc_serial_noalloc_max() == 1 << 28
+    assert lib.mc_serial_compress_noalloc(None, M.F32, 16, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
+    assert lib.mc_serial_compress_noalloc(fake, M.F32, 0, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
+    assert lib.mc_serial_compress_noalloc(fake, M.F32, (1 << 28) + 1, 1e-3, M.EB_REL, C.byref(codes),
+                                          None) == M.ERR_CAPACITY
+    assert b"no-allocation limit" in lib.mc_last_error()
+    assert lib.mc_serial_compress_noalloc(fake, M.F32, 16, 0.0, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
