@@ -28,9 +28,9 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
     each array the kernel must read or write, once."""
     table = {
         "k_range": nv * sT,                                        # field
-        "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 8,         # mapping, field, p + x1' out
+        "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 4,         # mapping, field gather, one grid array out
         "k_lorenzo": ng * 4 + ng * 2,                              # p in, codes out
-        "k_residual": nv * (4 * D + sT + 2) + ng * 4,              # coords, field, codes out, x1'
+        "k_residual": nv * (4 * D + sT + 2) + ng * 4,              # coords, field, codes out, grid (p or x1')
         "k_residual_learned": nv * (4 * D + sT + 2 + 4) + ng * 4,
         "k_dec_xy_tot": ng * 2,                                    # 2-D: codes
         "k_dec_z_tot": ng * 2,                                     # 3-D: codes
@@ -104,29 +104,95 @@ def workload(name: str):
     return mesh, f, cfg, desc
 
 
-def cpu_baseline(eb: float, split: float, min_seconds: float = 10.0, n: int = 96):
-    """The oracle (single thread) on a bounded sample of the same workload:
-    a C3-style n^3 lattice with a proportional grid; plan excluded, as the
-    paper excludes the mapping from its cost."""
-    import meshgen as G
+def host_description() -> dict:
+    """nproc and the CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except Exception:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": model}
+
+
+def cpu_baseline(mesh, f, cfg, eb: float, split: float, h_gpu=None, x_gpu=None, reps: int = 5):
+    """The oracle as it stands (plain C, one thread) on the same inputs as
+    the timed step: the mapping is computed first and not timed (the paper
+    excludes the mapping from its cost), then compress + decompress are
+    timed, median of `reps`.  When the GPU's codes and decoded values are
+    given they must equal the oracle's, element by element."""
     import oracle as O
-    mesh, f, cfg = G.config_tet_3d(n=n, dims=int(round(n * 256 / 252)), eb=eb, split=split)
-    g = O.grid_from_dims(mesh.coords, cfg["dims"])
-    m = O.locate(mesh.coords, mesh.cells, g, "raster", fill="midrange")
-    reps, t0 = 0, time.perf_counter()
-    while True:
+    t0 = time.perf_counter()
+    g = O.grid_from_dims(mesh.coords, cfg["dims"][:mesh.dim])
+    m = O.locate(mesh.coords, mesh.cells, g, "raster", fill="nearest", fill_method="kdtree")
+    plan_s = time.perf_counter() - t0
+    tc, td = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
         cz = O.compress(mesh.coords, m, g, f, eb, True, split)
-        O.decompress(mesh.coords, g, cz.bound, cz.grid, cz.vert, f.dtype)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= min_seconds:
-            break
-    gbps = mesh.n_vertices * 4 * reps / el / 1e9
-    return {"value": round(gbps, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n}^3 jittered Kuhn lattice ({mesh.n_vertices} vertices, {mesh.n_cells} tets), "
-                      f"grid {cfg['dims'][0]}^3, same field recipe/eb/split (mid-range fill of unlocated nodes); "
-                      f"compress+decompress x{reps} "
-                      f"in {el:.1f} s, one thread"}
+        t1 = time.perf_counter()
+        xo = O.decompress(mesh.coords, g, cz.bound, cz.grid, cz.vert, f.dtype)
+        t2 = time.perf_counter()
+        tc.append(t1 - t0)
+        td.append(t2 - t1)
+    same = None
+    if h_gpu is not None:
+        same = bool(np.array_equal(h_gpu["grid_codes"], cz.grid.codes)
+                    and np.array_equal(h_gpu["g_out_idx"], cz.grid.out_idx)
+                    and np.array_equal(h_gpu["vert_codes"], cz.vert.codes)
+                    and np.array_equal(h_gpu["v_out_idx"], cz.vert.out_idx)
+                    and (x_gpu is None or np.array_equal(x_gpu.view(np.uint8), xo.view(np.uint8))))
+    c, d = float(np.median(tc)), float(np.median(td))
+    nb = mesh.n_vertices * f.dtype.itemsize
+    return {"value": round(nb / (c + d) / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"the timed workload itself ({mesh.n_vertices} vertices, {mesh.n_cells} cells, grid "
+                      f"{'x'.join(str(int(v)) for v in cfg['dims'][:mesh.dim])}), mapping untimed "
+                      f"({plan_s:.1f} s); compress + decompress, median of {reps}, one thread",
+            "compress_s": round(c, 4), "decompress_s": round(d, 4),
+            "compress_GBps": round(nb / c / 1e9, 4), "decompress_GBps": round(nb / d / 1e9, 4),
+            "codes_equal_gpu": same, "host": host_description()}
+
+
+def cold_step_ms(step, reps: int = 20, flush_bytes: int = 1 << 30):
+    """Median milliseconds of one step after writing a flush_bytes scratch
+    buffer (evicts the 4 MB L2 of every XCD and the 256 MB Infinity
+    Cache), HIP events on the current stream around the step only."""
+    import torch
+    scratch = torch.empty(flush_bytes // 4, dtype=torch.float32, device="cuda")
+    ts = []
+    for i in range(reps):
+        scratch.fill_(float(i))
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        step()
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    del scratch
+    return float(np.median(ts))
+
+
+def copy_ceiling_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
+    """HBM rate of a plain device-to-device copy (read + write bytes per
+    second), the practical ceiling the kernels are also compared with."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    return 2 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
 
 
 def _timed(fn, reps=5):
@@ -266,7 +332,7 @@ def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, spli
     xs = [torch.from_numpy(a).cuda() for a in series]
     model = M.Model.train(plan, xs[0], eb=cfg["eb"], grid_share=split, split_mode=split_mode, steps=train_steps,
                           batch=batch, seed=4)
-    model_bytes = 16 + 2 * M.param_count(mesh.dim)
+    model_bytes = len(model.export())                 # the model file as embedded in the stream
     cp, cl = M.Codes(plan, xs[0].dtype), M.Codes(plan, xs[0].dtype, learned=True)
     out = torch.empty_like(xs[0])
     tot = {"plain": 0, "learned": 0}
@@ -332,7 +398,7 @@ def learned_section(log, train_steps=2000, batch=8192):
     tprof = M.profile_read()
     log(f"learned: trained {train_steps} steps x {batch} in {train_s:.2f} s, loss {loss[0]:.4f} -> "
         f"{float(np.mean(loss[-50:])):.4f}")
-    model_bytes = 16 + 2 * M.param_count(D)          # header + BF16 weights
+    model_bytes = len(model.export())                # the model file as embedded once in the sequence's stream
     nT = len(series) - 1
     per_t = []
     # x1' of the previous and the current step for the time-axis grid predictor
@@ -371,7 +437,7 @@ def learned_section(log, train_steps=2000, batch=8192):
         gb_p = sbp["grid"] + sbp["grid_outliers"]
         tot["temporal"] += sp - gb_p + gb_t
         prev.copy_(cur)                                   # x1' of step t: the next step's reference
-        sl = M.stream_bytes(hl, sT, model_bytes)["total"] - model_bytes   # model charged once below
+        sl = M.stream_bytes(hl)["total"]                  # the model is charged once, below
         tot["plain"] += sp
         tot["learned"] += sl
         tot["raw"] += nv * sT
@@ -653,7 +719,7 @@ def batch_main(args, log):
             h["learned"] = learned
             total += M.stream_bytes(h, x.element_size())["total"]
         if learned:
-            total += sum(16 + 2 * M.param_count(m.dim) for m in models.values())   # every model charged once
+            total += sum(len(m.export()) for m in models.values())   # every model file charged once
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record()
@@ -843,6 +909,7 @@ def main():
 
     bc, bd = method_bytes(nv, ng, D, sT)
     h = codes.host()
+    xr_host = out.cpu().numpy()                     # decoded values of the last timed step
     sb = M.stream_bytes(h, sT)
     cr = nv * sT / sb["total"]
     if args.copy_calibration:
@@ -852,6 +919,11 @@ def main():
             bb.copy_(a)
         torch.cuda.synchronize()
 
+    cold_ms = cold_step_ms(step)
+    log(f"cold-cache step (1 GiB flush before each): {cold_ms:.4f} ms")
+    copy_gbps = copy_ceiling_gbps()
+    log(f"copy ceiling: {copy_gbps:.0f} GB/s")
+    roofline["frac_of_copy"] = round(achieved / copy_gbps, 4)
     value = nv * sT / (ms_step * 1e-3) / 1e9
     line = {
         "metric": "compress/decompress GB/s of mesh values + CR, learned vs plain, eb=1e-4",
@@ -876,6 +948,11 @@ def main():
         "alg_bytes_compress": bc,
         "alg_bytes_decompress": bd,
         "hbm_frac_alg": round((bc + bd) / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "cold_cache": {"ms_per_step": round(cold_ms, 4), "GBps": round(nv * sT / (cold_ms * 1e-3) / 1e9, 2),
+                       "hbm_frac_alg": round((bc + bd) / (cold_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                       "flush": "1 GiB written before each of 20 steps; median"},
+        "copy_ceiling_GBps": round(copy_gbps, 1),
+        "copy_frac_alg": round((bc + bd) / (ms_step * 1e-3) / 1e9 / copy_gbps, 4),
         "cr": round(cr, 3),
         "stream_bytes": sb,
         "outliers": {"grid": h["result"]["n_grid_outliers"], "vertex": h["result"]["n_vertex_outliers"]},
@@ -911,8 +988,9 @@ def main():
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle, one thread) ...")
-        line["cpu_baseline"] = cpu_baseline(args.eb, args.split)
+        log("cpu baseline (oracle, one thread, the same inputs) ...")
+        line["cpu_baseline"] = cpu_baseline(mesh, f, cfg, args.eb, args.split, h_gpu=h, x_gpu=xr_host)
+        log(f"cpu baseline: {line['cpu_baseline']}")
     print(json.dumps(line), flush=True)
 
 

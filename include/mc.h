@@ -295,13 +295,18 @@ mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
                         void* d_field_out, mc_dtype dtype, hipStream_t stream);
 
 /* ---- autotuning -----------------------------------------------------------
- * Launch-order knobs of a plan: bit k of remap_mask set = kernel k takes
- * its tiles in XCD-contiguous order (each of the 8 XCDs, with its own L2,
- * gets one contiguous run of tiles), clear = in launch order.  Bits: 0
- * resample, 1 Lorenzo codes, 2 residual codes (and the learned block
- * costs), 3 vertex decode, 4/5 the 3-D grid decode's tile sums and apply
- * (grids with n0 at most 1024); bit 6 has no effect.
- * Codes and values never depend on the knobs.  Default: all set. */
+ * Launch knobs of a plan.  Bits 0-6: bit k set = kernel k takes its tiles
+ * in XCD-contiguous order (each of the 8 XCDs, with its own L2, gets one
+ * contiguous run of tiles), clear = in launch order: 0 resample, 1 Lorenzo
+ * codes, 2 residual codes (and the learned block costs), 3 vertex decode,
+ * 4/5 the 3-D grid decode's tile sums and apply (grids with n0 at most
+ * 1024); bit 6 has no effect.  Bits 7-8 pick the cache policy of data a
+ * kernel streams once: set = non-temporal loads and stores, so the stream
+ * does not evict lines that other threads read again; 7 the resample's
+ * mapping, 8 the coordinates, field, codes and decoded values of the
+ * residual codes and the vertex decode.
+ * Codes and values never depend on the knobs.  Default: 0x1e0 (the best
+ * mask measured on a 16M-vertex tetrahedral mesh with a 256^3 grid). */
 typedef struct {
     uint32_t remap_mask;
     uint32_t reserved[3];
@@ -309,8 +314,8 @@ typedef struct {
 
 mc_status mc_plan_get_tuning(mc_plan plan, mc_tuning* out);
 mc_status mc_plan_set_tuning(mc_plan plan, const mc_tuning* tuning);
-/* Times every knob both ways on this plan and keeps, bit by bit, the
- * setting with the smaller summed kernel time of `reps` compress +
+/* Times every knob both ways on this plan (starting from the default) and
+ * keeps, bit by bit, the setting with the smaller summed kernel time of `reps` compress +
  * decompress passes of d_field (after one warm-up pass).  codes and d_out
  * (T[n_vertices]) receive the last pass's results.  Uses the library's
  * profiler, whose accumulated figures it clears.  Writes the choice to
@@ -476,6 +481,59 @@ int64_t mc_huffman_encode(const uint16_t* h_sym, int64_t n, uint8_t* h_out, int6
 int64_t mc_huffman_decode(const uint8_t* h_in, int64_t n_in, uint16_t* h_sym, int64_t n);
 /* Empirical Shannon entropy of the symbols, bits per symbol. */
 double mc_entropy_bits(const uint16_t* h_sym, int64_t n);
+
+/* ---- self-describing stream (host, outside the hot path) -----------------
+ * The compressed bytes whose size gives the compression ratio (Sec. IV-A:
+ * original size over compressed size; mesh, grid and mapping are reusable
+ * state and not part of it): a header (dims, dtype, predictors, tau, tau1,
+ * tau2, c), the canonical Huffman streams of the grid and vertex codes,
+ * both outlier lists (LEB128 index gaps; grid errors zigzag-LEB128, vertex
+ * values raw), the block flags in learned mode, optionally the model file,
+ * and a checksum.  Host arrays throughout; sizes follow from the header
+ * (n_grid = dims[0] * dims[1] * dims[2]). */
+typedef struct {
+    int32_t dim;                 /* 2 or 3; 1: a 1-D serialisation baseline stream (no grid sections,
+                                    dims unused, tau1 = tau, tau2 = 0) */
+    int32_t dtype;               /* mc_dtype of the field */
+    int64_t dims[3];             /* grid nodes per axis; dims[2] = 1 in 2-D */
+    int64_t n_vertices;
+    int32_t grid_predictor;      /* mc_grid_predictor of the grid codes */
+    int32_t residual_predictor;  /* mc_residual_predictor of the vertex codes */
+    int32_t learned;             /* 1: vertex codes carry the learned shift; block flags present */
+    int32_t reserved;
+    double tau, tau1, tau2, c;   /* as in mc_result */
+    int64_t n_grid_outliers, n_vertex_outliers;
+} mc_stream_header;
+
+typedef struct {
+    uint16_t* grid_codes;        /* [n_grid] (unused for dim 1) */
+    int32_t* g_out_idx;          /* [n_grid_outliers], ascending */
+    int32_t* g_out_delta;        /* [n_grid_outliers] */
+    uint16_t* vert_codes;        /* [n_vertices] */
+    int32_t* v_out_idx;          /* [n_vertex_outliers], ascending */
+    void* v_out_val;             /* [n_vertex_outliers] values of dtype */
+    uint32_t* block_flags;       /* [ceil(ceil(n_vertices / 4096) / 32)], learned only */
+} mc_stream_arrays;
+
+/* Bytes of the stream (-1 on invalid input; mc_last_error says why).
+ * model (model_bytes, 0 = none) is embedded when given, e.g. once per
+ * timestep sequence.  section_bytes (may be NULL) receives 8 sizes: header,
+ * grid codes, vertex codes, grid outliers, vertex outliers, block flags,
+ * model, checksum. */
+int64_t mc_stream_size(const mc_stream_header* hdr, const mc_stream_arrays* a, const void* model,
+                       int64_t model_bytes, int64_t* section_bytes);
+/* Writes the stream into h_out; returns its length, or -1 (invalid input or
+ * cap too small: MC_ERR_CAPACITY in mc_last_error). */
+int64_t mc_stream_write(const mc_stream_header* hdr, const mc_stream_arrays* a, const void* model,
+                        int64_t model_bytes, uint8_t* h_out, int64_t cap, int64_t* section_bytes);
+/* Header of a stream (checksum and ranges checked) and the size of its
+ * embedded model (0 if none). */
+mc_status mc_stream_read_header(const uint8_t* h_in, int64_t n, mc_stream_header* hdr, int64_t* model_bytes);
+/* Arrays of a stream into caller buffers sized from its header; model
+ * (model_cap bytes, may be NULL to skip) receives the embedded model.
+ * MC_ERR_FORMAT for a malformed or truncated stream. */
+mc_status mc_stream_read(const uint8_t* h_in, int64_t n, const mc_stream_arrays* a, void* model,
+                         int64_t model_cap);
 
 #ifdef __cplusplus
 }

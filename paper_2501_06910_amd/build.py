@@ -18,7 +18,7 @@ ARCH = os.environ.get("MC_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["k_compress.hip", "k_decode.hip", "k_plan.hip", "k_mlp.hip", "mc_api.hip", "mc_model.hip",
            "mc_batch.hip", "k_serial.hip", "mc_serial.hip", "k_cluster.hip", "k_grid_init.hip", "k_resdelta.hip", "k_interp.hip",
-           "entropy.cpp"]
+           "entropy.cpp", "stream.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",

@@ -4,12 +4,15 @@
 //                    then one workgroup) and non-finite check; clears the
 //                    per-call state of the kernels after it
 //   k_resample       f: v_j = sum_k w_kj * x[vid_kj] (FP32, fixed order), the
-//                    prequantised grid p_j = rint((v_j - c) / (2 tau1)) and the
-//                    reconstructed grid x1'_j = (float)(c + p_j * 2 tau1)
+//                    prequantised grid p_j = rint((v_j - c) / (2 tau1)) and,
+//                    when a consumer reads it, the reconstructed grid
+//                    x1'_j = (float)(c + p_j * 2 tau1)
 //   k_lorenzo        Lorenzo prediction error of p, uint16 codes, per-tile
 //                    outlier counts
-//   k_residual       g: multilinear x1' at each vertex, residual quantisation
-//                    with the per-vertex bound check, per-tile outlier counts
+//   k_residual       g: multilinear x1' at each vertex (corners read from x1',
+//                    or from p and converted as the decoder does), residual
+//                    quantisation with the per-vertex bound check, per-tile
+//                    outlier counts
 //   k_residual_learned  learned mode, one workgroup per 4096-vertex block:
 //                    both code costs, the cheaper kind, then the codes
 //   k_scatter        outlier lists in index order (wave ballots)
@@ -166,7 +169,7 @@ __global__ __launch_bounds__(256) void k_range_final(const unsigned long long* _
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int D>
+template <typename T, int D, bool NT>
 __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vid, const float* __restrict__ w,
                                                   long long ng, const T* __restrict__ x,
                                                   const DevBound* __restrict__ bnd,
@@ -198,8 +201,8 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
     float wk[D + 1];
 #pragma unroll
     for (int k = 0; k <= D; ++k) {
-        id[k] = vid[k * ng + j];
-        wk[k] = w[k * ng + j];
+        id[k] = ld_s<NT>(vid + k * ng + j);
+        wk[k] = ld_s<NT>(w + k * ng + j);
     }
     const bool fill = id[0] < 0;
     float f[D + 1];
@@ -214,7 +217,7 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
     if (!(fabs(s) < 134217728.0)) atomicOr(err, MC_EBIT_RANGE);
     else q = (int32_t)rint(s);
     p[j] = q;
-    xh[j] = xhat_of(q, b.c, b.step1);      // reconstructed grid x1', as the decoder rebuilds it
+    if (xh) xh[j] = xhat_of(q, b.c, b.step1);      // reconstructed grid x1', as the decoder rebuilds it
     if (dbg_v) dbg_v[j] = v;
 }
 
@@ -440,9 +443,9 @@ __device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound&
 }
 
 // Residual codes of one tile (1024 vertices) and its outlier count.
-template <typename T, int D>
+template <typename T, int D, bool FROM_P, bool NT>
 __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                  const float* __restrict__ xh, const T* __restrict__ x,
+                                                  const void* __restrict__ xh, const T* __restrict__ x,
                                                   const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
                                                   float* __restrict__ dbg_g, unsigned int* __restrict__ count,
                                                   unsigned int* __restrict__ vsum, unsigned remap)
@@ -457,10 +460,10 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
     for (int i = 0; i < MC_IPT; ++i) {
         v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
         act[i] = v[i] < nv && b.ok;
-        xv[i] = x[act[i] ? v[i] : 0];
+        xv[i] = ld_s<NT>(x + (act[i] ? v[i] : 0));
     }
     float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    back_interp_n<D, MC_IPT, FROM_P, NT>(coords, nv, gg, xh, b.c, b.step1, v, act, g);
     int nout = 0;
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
@@ -468,7 +471,7 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
         if (dbg_g) dbg_g[v[i]] = g[i];
         int qi;
         const bool ok = quantize_residual<T>(xv[i], g[i], b, qi);
-        codes[v[i]] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
+        st_s<NT>(codes + v[i], ok ? (uint16_t)(qi + MC_R) : (uint16_t)0);
         nout += ok ? 0 : 1;
     }
     nout = wave_sum(nout);
@@ -519,7 +522,7 @@ __global__ __launch_bounds__(MC_LTILES * MC_WG) void k_residual_learned(
         rq[i] = rho_q[vc];
     }
     float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    back_interp_n<D, MC_IPT, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
     int qv[MC_IPT];
     bool okv[MC_IPT];
     long long cp = 0, cl = 0;
@@ -597,40 +600,42 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
 {
     __shared__ int s_cnt[MC_IPT * 4 + 1];
     __shared__ unsigned s_c[MC_SC_TILES], s_off[MC_SC_TILES];
-    __shared__ unsigned long long s_red[4];
+    __shared__ unsigned long long s_red[3][4];
     const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
     const long long ngg = (ntg + MC_SC_TILES - 1) / MC_SC_TILES, ngv = (ntv + MC_SC_TILES - 1) / MC_SC_TILES;
+    const int w = threadIdx.x >> 6;
     if (blockIdx.x == 0) {
         // totals of both lists and the learned-block count (bit 31 marks the
-        // first tile of a learned block: every MC_LBLOCK / MC_TILE-th tile)
-        // (8 independent loads in flight per thread in each sum)
+        // first tile of a learned block: every MC_LBLOCK / MC_TILE-th tile),
+        // all loads of the three sums issued before any is added
         unsigned long long tg = 0, tv = 0, nl = 0;
-        for (long long i0 = threadIdx.x; i0 < ngg; i0 += 8 * 256) {
-            unsigned a[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * u < ngg ? gsum[i0 + 256 * u] : 0u;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) tg += a[u];
-        }
-        for (long long i0 = threadIdx.x; i0 < ngv; i0 += 8 * 256) {
-            unsigned a[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * u < ngv ? vsum[i0 + 256 * u] : 0u;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) tv += a[u];
-        }
         const long long step = MC_LBLOCK / MC_TILE;
-        for (long long i0 = threadIdx.x * step; i0 < ntv; i0 += 8 * 256 * step) {
-            unsigned a[8];
+        const long long nlb = (ntv + step - 1) / step;
+        for (long long i0 = threadIdx.x; i0 < ngg || i0 < ngv || i0 < nlb; i0 += 4 * 256) {
+            unsigned a[4], b[4], c[4];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[u] = i0 + 256 * step * u < ntv ? vcount[i0 + 256 * step * u] : 0u;
+            for (int u = 0; u < 4; ++u) {
+                const long long i = i0 + 256 * u;
+                a[u] = i < ngg ? gsum[i] : 0u;
+                b[u] = i < ngv ? vsum[i] : 0u;
+                c[u] = i < nlb ? vcount[i * step] : 0u;
+            }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) nl += a[u] >> 31;
+            for (int u = 0; u < 4; ++u) {
+                tg += a[u];
+                tv += b[u];
+                nl += c[u] >> 31;
+            }
         }
-        tg = block_sum_u64(tg, s_red);
-        tv = block_sum_u64(tv, s_red);
-        nl = block_sum_u64(nl, s_red);
+        tg = wave_sum(tg);
+        tv = wave_sum(tv);
+        nl = wave_sum(nl);
+        if (lane_id() == 0) { s_red[0][w] = tg; s_red[1][w] = tv; s_red[2][w] = nl; }
+        __syncthreads();
         if (threadIdx.x == 0) {
+            tg = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+            tv = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+            nl = s_red[2][0] + s_red[2][1] + s_red[2][2] + s_red[2][3];
             unsigned e = *err;
             if ((long long)tg > gcap) e |= MC_EBIT_GCAP;
             if ((long long)tv > vcap) e |= MC_EBIT_VCAP;
@@ -639,22 +644,20 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
             res->n_learned_blocks = (long long)nl;
             res->status = status_from_bits(e);
         }
+        __syncthreads();                           // s_red is reused below
     }
     const bool vert = blockIdx.x >= ngg;
     const long long grp = vert ? blockIdx.x - ngg : blockIdx.x;
     const long long ntl = vert ? ntv : ntg;
     const unsigned int* cnt = vert ? vcount : gcount;
     const long long t0 = grp * MC_SC_TILES;
+    // the group's tile counts and its list offset (the sum of the group
+    // totals before it) are loaded together, before either is known to be
+    // needed: one round trip to memory instead of two
     if (threadIdx.x < MC_SC_TILES) {
         const long long t = t0 + threadIdx.x;
         s_c[threadIdx.x] = t < ntl ? (cnt[t] & 0x7fffffffu) : 0u;
     }
-    __syncthreads();
-    unsigned any = 0;
-#pragma unroll
-    for (int k = 0; k < MC_SC_TILES; ++k) any |= s_c[k];
-    if (any == 0) return;                          // uniform: no outlier in the group
-    // list offset of the group: sum of the group totals before it
     const unsigned int* sums = vert ? vsum : gsum;
     unsigned long long before = 0;
     for (long long i0 = threadIdx.x; i0 < grp; i0 += 8 * 256) {
@@ -664,9 +667,15 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
 #pragma unroll
         for (int u = 0; u < 8; ++u) before += a[u];
     }
-    before = block_sum_u64(before, s_red);
+    before = wave_sum(before);
+    if (lane_id() == 0) s_red[0][w] = before;
+    __syncthreads();
+    unsigned any = 0;
+#pragma unroll
+    for (int k = 0; k < MC_SC_TILES; ++k) any |= s_c[k];
+    if (any == 0) return;                          // uniform: no outlier in the group
     if (threadIdx.x == 0) {
-        unsigned long long a = before;
+        unsigned long long a = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
         for (int k = 0; k < MC_SC_TILES; ++k) {
             s_off[k] = (unsigned)a;
             a += s_c[k];
@@ -681,10 +690,12 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
         const long long tile = t0 + k;
         bool flag[MC_IPT];
         int rank[MC_IPT];
+        T xv[MC_IPT];                              // raw values loaded with the codes (vertex tiles)
 #pragma unroll
         for (int i = 0; i < MC_IPT; ++i) {
             const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
             flag[i] = j < n && codes[j] == 0;
+            xv[i] = (vert && j < n) ? x[j] : (T)0;
         }
         tile_ranks(flag, rank, s_cnt);
         const long long base = s_off[k];
@@ -694,7 +705,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
             const long long j = tile * MC_TILE + i * MC_WG + threadIdx.x;
             const long long pos = base + rank[i];
             if (vert) {
-                if (pos < vcap) { vidx[pos] = (int32_t)j; vval[pos] = x[j]; }
+                if (pos < vcap) { vidx[pos] = (int32_t)j; vval[pos] = xv[i]; }
             } else if (pos < gcap) {
                 const int i0 = (int)(j % n0);
                 const long long r = j / n0;
@@ -710,6 +721,16 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
         }
         __syncthreads();                           // s_cnt is reused by the next tile
     }
+}
+
+// x1' of the whole grid from p (for consumers that read x1' after a plain
+// compression that wrote only p).
+__global__ __launch_bounds__(256) void k_xhat_from_p(const int32_t* __restrict__ p, long long ng,
+                                                     const DevBound* __restrict__ bnd, float* __restrict__ xh)
+{
+    const double c = bnd->c, step1 = bnd->step1;
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (j < ng) xh[j] = xhat_of(p[j], c, step1);
 }
 
 // ---------------------------------------------------------------------------
@@ -744,15 +765,18 @@ hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, c
                     long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
                     unsigned remap, hipStream_t s)
 {
-    remap &= MC_KNOB_RESAMPLE;
     ProfScope ps("k_resample", s);
     const long long need = ng > nbflags ? ng : nbflags;
     dim3 grid((unsigned)((need + 255) / 256));
-#define MC_RS(T, D) hipLaunchKernelGGL((k_resample<T, D>), grid, dim3(256), 0, s, vid, w, ng, (const T*)x, bnd, \
-                                       p, xh, dbg_v, bflags, nbflags, err, res, dtype, gcount, ntg, remap)
+    const bool nt = (remap & MC_KNOB_NT_MAP) != 0;
+    remap &= MC_KNOB_RESAMPLE;
+#define MC_RS0(T, D, NT) hipLaunchKernelGGL((k_resample<T, D, NT>), grid, dim3(256), 0, s, vid, w, ng, (const T*)x, \
+                                            bnd, p, xh, dbg_v, bflags, nbflags, err, res, dtype, gcount, ntg, remap)
+#define MC_RS(T, D) do { if (nt) MC_RS0(T, D, true); else MC_RS0(T, D, false); } while (0)
     if (dtype == MC_F64) { if (dim == 2) MC_RS(double, 2); else MC_RS(double, 3); }
     else { if (dim == 2) MC_RS(float, 2); else MC_RS(float, 3); }
 #undef MC_RS
+#undef MC_RS0
     return hipGetLastError();
 }
 
@@ -776,10 +800,12 @@ hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long 
     return hipGetLastError();
 }
 
-hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const DevBound* bnd, const int32_t* rho_q, uint16_t* codes, uint32_t* bflags, float* dbg_g,
-                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s)
+hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* pq,
+                    const void* x, int dtype, const DevBound* bnd, const int32_t* rho_q, uint16_t* codes,
+                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
+                    hipStream_t s)
 {
+    const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
     remap &= MC_KNOB_RESIDUAL;
     const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
     if (rho_q) {
@@ -794,11 +820,22 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
     }
     ProfScope ps("k_residual", s);
     const dim3 grid((unsigned)ntv);
-#define MC_RQ(T, D) hipLaunchKernelGGL((k_residual<T, D>), grid, dim3(256), 0, s, coords, nv, gg, xh, (const T*)x, bnd, \
-                                       codes, dbg_g, count, vsum, remap)
-    if (dtype == MC_F64) { if (gg.dim == 2) MC_RQ(double, 2); else MC_RQ(double, 3); }
-    else { if (gg.dim == 2) MC_RQ(float, 2); else MC_RQ(float, 3); }
+#define MC_RQ(T, D, FP, NT) hipLaunchKernelGGL((k_residual<T, D, FP, NT>), grid, dim3(256), 0, s, coords, nv, gg, \
+                                               FP ? (const void*)pq : (const void*)xh, (const T*)x, bnd, codes, \
+                                               dbg_g, count, vsum, remap)
+#define MC_RQD(T, D) do { if (pq) { if (nt) MC_RQ(T, D, true, true); else MC_RQ(T, D, true, false); } \
+                          else { if (nt) MC_RQ(T, D, false, true); else MC_RQ(T, D, false, false); } } while (0)
+    if (dtype == MC_F64) { if (gg.dim == 2) MC_RQD(double, 2); else MC_RQD(double, 3); }
+    else { if (gg.dim == 2) MC_RQD(float, 2); else MC_RQD(float, 3); }
+#undef MC_RQD
 #undef MC_RQ
+    return hipGetLastError();
+}
+
+hipError_t xhat_from_p(const int32_t* p, long long ng, const DevBound* bnd, float* xh, hipStream_t s)
+{
+    ProfScope ps("k_xhat_from_p", s);
+    hipLaunchKernelGGL(k_xhat_from_p, dim3((unsigned)((ng + 255) / 256)), dim3(256), 0, s, p, ng, bnd, xh);
     return hipGetLastError();
 }
 

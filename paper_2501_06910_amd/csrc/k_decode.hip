@@ -523,7 +523,7 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
 }
 
 // Four vertices per thread (tile of 1024), every load issued before use.
-template <typename T, int D, bool LEARNED>
+template <typename T, int D, bool LEARNED, bool NT>
 __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                  const float* __restrict__ xh, const uint16_t* __restrict__ codes,
                                                  const int32_t* __restrict__ oidx, const T* __restrict__ oval,
@@ -546,11 +546,11 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
         v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
         act[i] = v[i] < nv;
         const long long vc = act[i] ? v[i] : 0;
-        code[i] = codes[vc];
+        code[i] = ld_s<NT>(codes + vc);
         rq[i] = (LEARNED && learned) ? rho_q[vc] : 0;
     }
     float g[MC_IPT];
-    back_interp_n<D, MC_IPT>(coords, nv, gg, xh, v, act, g);
+    back_interp_n<D, MC_IPT, false, NT>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
     const double step2 = 2.0 * res->tau2;
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
@@ -558,10 +558,10 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
         if (code[i] == 0) {
             const long long n = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
             const long long k = find_outlier(oidx, n, v[i]);
-            xout[v[i]] = k >= 0 ? oval[k] : (T)0;
+            st_s<NT>(xout + v[i], k >= 0 ? oval[k] : (T)0);
         } else {
             const int q = code[i] - MC_R + rq[i];
-            xout[v[i]] = (T)((double)g[i] + (double)q * step2);
+            st_s<NT>(xout + v[i], (T)((double)g[i] + (double)q * step2));
         }
     }
 }
@@ -856,11 +856,13 @@ hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const f
                          const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
                          hipStream_t s)
 {
+    const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
     remap &= MC_KNOB_VDECODE;
     ProfScope ps(rho_q ? "k_vdecode_learned" : "k_vdecode", s);
     dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
-#define MC_VD(T, D, L) hipLaunchKernelGGL((k_vdecode<T, D, L>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, oidx, \
-                                          (const T*)oval, res, vcap, rho_q, bflags, (T*)xout, remap)
+#define MC_VD0(T, D, L, NT) hipLaunchKernelGGL((k_vdecode<T, D, L, NT>), grid, dim3(256), 0, s, coords, nv, gg, xh, \
+                                               codes, oidx, (const T*)oval, res, vcap, rho_q, bflags, (T*)xout, remap)
+#define MC_VD(T, D, L) do { if (nt) MC_VD0(T, D, L, true); else MC_VD0(T, D, L, false); } while (0)
     const bool L = rho_q != nullptr;
     if (dtype == MC_F64) {
         if (gg.dim == 2) { if (L) MC_VD(double, 2, true); else MC_VD(double, 2, false); }
@@ -870,6 +872,7 @@ hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const f
         else { if (L) MC_VD(float, 3, true); else MC_VD(float, 3, false); }
     }
 #undef MC_VD
+#undef MC_VD0
     return hipGetLastError();
 }
 

@@ -833,6 +833,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         double* x1 = prm->residual == MC_RESIDUAL_OPEN ? p->x1 : nullptr;
         ECHK(mck::cluster_mean(p->noff, p->vlist, p->ng, d_field, dtype, p->bound, p->p, p->xh, x1,
                                codes->dbg_resampled, p->err, codes->result, p->gcount, p->ntg, s));
+        p->xh_valid = true;
         ECHK(grid_codes(p, codes, s));
         if (codes->residual_predictor == MC_RESPRED_DELTA) {
             ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, p->m, d_field, dtype, p->bound,
@@ -851,8 +852,13 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
             ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
         return MC_OK;
     }
-    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, p->xh, codes->dbg_resampled,
-                       codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result, p->gcount, p->ntg, p->knobs, s));
+    // plain value-by-value residual codes read the cell corners from p (x1' is
+    // then never written); the learned and delta coders and xhat_out read x1'
+    const bool from_p = !prm->model && codes->residual_predictor == MC_RESPRED_NONE && !codes->xhat_out;
+    ECHK(mck::resample(p->vid, p->w, p->dim, p->ng, d_field, dtype, p->bound, p->p, from_p ? nullptr : p->xh,
+                       codes->dbg_resampled, codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result,
+                       p->gcount, p->ntg, p->knobs, s));
+    p->xh_valid = !from_p;
     ECHK(grid_codes(p, codes, s));
     const int32_t* rho = nullptr;
     if (prm->model) {
@@ -864,8 +870,9 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, nullptr, d_field, dtype, p->bound,
                                  codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
     } else {
-        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound, rho, codes->vert_codes,
-                           codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
+        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, from_p ? p->p : nullptr, d_field, dtype, p->bound, rho,
+                           codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
+                           s));
     }
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
                       codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta,
@@ -875,6 +882,15 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     if (codes->xhat_out) ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
 #undef ECHK
+    return MC_OK;
+}
+
+mc_status mc_plan_ensure_xh(mc_plan p, hipStream_t s)
+{
+    if (p->xh_valid) return MC_OK;
+    hipError_t e = mck::xhat_from_p(p->p, p->ng, p->bound, p->xh, s);
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "xhat_from_p: %s", hipGetErrorString(e));
+    p->xh_valid = true;
     return MC_OK;
 }
 
@@ -939,6 +955,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
                                 codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
                                 (int)p->grid.dims[2], codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC, p->p,
                                 p->xh, s));
+    p->xh_valid = true;
     if (codes->xhat_out)
         ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (p->ops == MC_OPS_CLUSTER && codes->residual_predictor == MC_RESPRED_DELTA) {
@@ -1027,7 +1044,7 @@ extern "C" mc_status mc_plan_tune(mc_plan p, const void* d_field, mc_dtype dtype
         return r;
     };
     const bool was_on = g_prof_on;
-    unsigned best = mck::MC_KNOB_ALL;
+    unsigned best = mck::MC_KNOB_DEFAULT;
     double best_ms = 0.0;
     if ((st = measure(best, &best_ms)) != MC_OK) return st;
     for (unsigned bit = 1; bit & mck::MC_KNOB_ALL; bit <<= 1) {

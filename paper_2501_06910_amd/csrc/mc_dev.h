@@ -152,6 +152,22 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned n)
     return (x < rem ? x * (per + 1u) : rem * (per + 1u) + (x - rem) * per) + r;
 }
 
+// Loads and stores of data streamed once through a kernel.  NT: the
+// non-temporal (streaming) cache policy, so that the stream does not evict
+// lines other threads will read again (cell corners, gathered field values).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_s(const T* __restrict__ p)
+{
+    if (NT) return __builtin_nontemporal_load(p);
+    return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_s(T* __restrict__ p, T v)
+{
+    if (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Two consecutive floats at a 4-byte aligned address.
 typedef float f2a4 __attribute__((ext_vector_type(2), aligned(4)));
 
@@ -159,9 +175,29 @@ typedef float f2a4 __attribute__((ext_vector_type(2), aligned(4)));
 // g(x1') for N vertices of one thread from their coordinates P: cells, then
 // every corner of every cell, then the nested lerps (x, then y, then z) in
 // the order of the definition, so that all gathers issue together.
-template <int D, int N>
+// FROM_P: src is the prequantised grid (int32) and each corner is converted
+// to x1' = (float)(c + p * step1) exactly as the grid decoder produces it;
+// otherwise src is x1' itself (float).
+typedef int i2a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <bool FROM_P>
+__device__ __forceinline__ void corner_pair(const void* __restrict__ src, unsigned j, double c, double step1,
+                                            float& a, float& b)
+{
+    if (FROM_P) {
+        const i2a4 q = *reinterpret_cast<const i2a4*>((const int32_t*)src + j);
+        a = xhat_of(q.x, c, step1);
+        b = xhat_of(q.y, c, step1);
+    } else {
+        const f2a4 e = *reinterpret_cast<const f2a4*>((const float*)src + j);
+        a = e.x;
+        b = e.y;
+    }
+}
+
+template <int D, int N, bool FROM_P>
 __device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const GridGeom& gg,
-                                              const float* __restrict__ xh, float (&g)[N])
+                                              const void* __restrict__ src, double cc, double step1, float (&g)[N])
 {
     const unsigned n0 = (unsigned)gg.n0, n01 = (unsigned)gg.n0 * (unsigned)gg.n1;
     unsigned j[N];
@@ -180,19 +216,11 @@ __device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const Grid
     float c[N][8];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-        const f2a4 e0 = *reinterpret_cast<const f2a4*>(xh + j[i]);
-        const f2a4 e1 = *reinterpret_cast<const f2a4*>(xh + j[i] + n0);
-        c[i][0] = e0.x;
-        c[i][1] = e0.y;
-        c[i][2] = e1.x;
-        c[i][3] = e1.y;
+        corner_pair<FROM_P>(src, j[i], cc, step1, c[i][0], c[i][1]);
+        corner_pair<FROM_P>(src, j[i] + n0, cc, step1, c[i][2], c[i][3]);
         if (D == 3) {
-            const f2a4 e2 = *reinterpret_cast<const f2a4*>(xh + j[i] + n01);
-            const f2a4 e3 = *reinterpret_cast<const f2a4*>(xh + j[i] + n01 + n0);
-            c[i][4] = e2.x;
-            c[i][5] = e2.y;
-            c[i][6] = e3.x;
-            c[i][7] = e3.y;
+            corner_pair<FROM_P>(src, j[i] + n01, cc, step1, c[i][4], c[i][5]);
+            corner_pair<FROM_P>(src, j[i] + n01 + n0, cc, step1, c[i][6], c[i][7]);
         }
     }
 #pragma unroll
@@ -210,23 +238,38 @@ __device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const Grid
     }
 }
 
+template <int D, int N>
+__device__ __forceinline__ void back_interp_p(const float (&P)[N][3], const GridGeom& gg,
+                                              const float* __restrict__ xh, float (&g)[N])
+{
+    back_interp_p<D, N, false>(P, gg, xh, 0.0, 0.0, g);
+}
+
 // The same for N vertices v[i] (strided ownership): coordinates loaded
 // first.  act[i] false: vertex 0 stands in (its result is ignored), so no
 // load depends on a branch.
-template <int D, int N>
+template <int D, int N, bool FROM_P, bool NT = false>
 __device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, long long nv, const GridGeom& gg,
-                                              const float* __restrict__ xh, const long long (&v)[N],
-                                              const bool (&act)[N], float (&g)[N])
+                                              const void* __restrict__ src, double cc, double step1,
+                                              const long long (&v)[N], const bool (&act)[N], float (&g)[N])
 {
     float P[N][3];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const long long vc = act[i] ? v[i] : 0;
 #pragma unroll
-        for (int d = 0; d < D; ++d) P[i][d] = coords[d * nv + vc];
+        for (int d = 0; d < D; ++d) P[i][d] = ld_s<NT>(coords + d * nv + vc);
         if (D == 2) P[i][2] = 0.0f;
     }
-    back_interp_p<D, N>(P, gg, xh, g);
+    back_interp_p<D, N, FROM_P>(P, gg, src, cc, step1, g);
+}
+
+template <int D, int N>
+__device__ __forceinline__ void back_interp_n(const float* __restrict__ coords, long long nv, const GridGeom& gg,
+                                              const float* __restrict__ xh, const long long (&v)[N],
+                                              const bool (&act)[N], float (&g)[N])
+{
+    back_interp_n<D, N, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
 }
 
 // Four consecutive values of T from a 16-byte aligned address.

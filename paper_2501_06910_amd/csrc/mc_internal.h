@@ -30,6 +30,8 @@ struct mc_plan_s {
     int32_t* p = nullptr;          // prequantised grid [ng]
     int32_t* rho = nullptr;        // learned shift [nv]
     float* xh = nullptr;           // reconstructed grid x1' [ng]
+    bool xh_valid = false;         // xh holds the x1' of the last enqueued call (a plain
+                                   // compression writes only p: mc_plan_ensure_xh converts)
     unsigned long long* range_partial = nullptr;   // [3 * MC_RANGE_BLOCKS]
     unsigned long long* ctl = nullptr;   // 64 words: the two range slots
     RangeOut* rbuf = nullptr;            // field range of the current call
@@ -44,7 +46,7 @@ struct mc_plan_s {
     unsigned* vsum = nullptr;
     long long ntg = 0, ntv = 0, nblk = 0;
     mck::DecodeWs dws{};
-    unsigned knobs = mck::MC_KNOB_ALL;  // launch-order knobs (mc_plan_tune)
+    unsigned knobs = mck::MC_KNOB_DEFAULT;  // launch knobs (mc_plan_tune)
     // statistics
     long long n_unresolved = 0, n_near_degenerate = 0, n_pairs = 0;
     int invalid_cells = 0;
@@ -74,5 +76,8 @@ mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const 
 mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
                               const mc_codes* codes, hipStream_t s);
 int mc_model_dim(mc_model m);
+// Makes p->xh the x1' of the last enqueued compression (converting p when
+// that call wrote only p).  Stream-ordered.
+mc_status mc_plan_ensure_xh(mc_plan p, hipStream_t s);
 // rho_q for every vertex (only_blocks == NULL) or the learned blocks only.
 mc_status mc_model_infer(mc_model m, mc_plan p, const mc_result* res, const uint32_t* only_blocks, hipStream_t s);

@@ -54,15 +54,22 @@ hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32
 // Field range and error split (k_range, then one workgroup folds the partials).
 hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
                  DevBound* bnd, unsigned int* zero, long long nzero, hipStream_t s);
+// xh may be NULL (x1' not written)
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
                     const DevBound* bnd, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
                     long long nbflags, unsigned int* err, mc_result* res, unsigned int* gcount, long long ntg,
                     unsigned remap, hipStream_t s);
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
                    unsigned int* count, unsigned int* gsum, unsigned remap, hipStream_t s);
-hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const void* x, int dtype,
-                    const DevBound* bnd, const int32_t* rho_q, uint16_t* codes, uint32_t* bflags, float* dbg_g,
-                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s);
+// pq non-NULL (plain codes only): the cell corners are read from the
+// prequantised grid and converted as x1' = (float)(c + p * 2 tau1); else
+// from x1' (xh).
+hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* pq,
+                    const void* x, int dtype, const DevBound* bnd, const int32_t* rho_q, uint16_t* codes,
+                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
+                    hipStream_t s);
+// x1' = (float)(c + p * 2 tau1) over the whole grid (bound from bnd).
+hipError_t xhat_from_p(const int32_t* p, long long ng, const DevBound* bnd, float* xh, hipStream_t s);
 // gpred: the mc_grid_predictor whose errors the grid outliers carry (gref:
 // the time-axis predictor's reference grid)
 hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int gpred, const float* gref,
@@ -84,7 +91,13 @@ enum {
     MC_KNOB_DZTOT = 1u << 4,        // 3-D decode on x quads: tile sums
     MC_KNOB_DZAPPLY = 1u << 5,      // 3-D decode on x quads: apply
     MC_KNOB_DXYAPPLY = 1u << 6,     // no kernel reads it (kept so the mask keeps its meaning)
-    MC_KNOB_ALL = 0x7fu
+    MC_KNOB_NT_MAP = 1u << 7,       // resample: the mapping streamed with the non-temporal policy
+    MC_KNOB_NT_VERT = 1u << 8,      // residual codes and vertex decode: coordinates, field, codes and
+                                    // decoded values streamed with the non-temporal policy
+    MC_KNOB_ALL = 0x1ffu,           // every valid bit
+    MC_KNOB_DEFAULT = 0x1e0u        // a new plan: the best mask measured on the 16M-vertex tet mesh (launch
+                                    // order for resample, Lorenzo, residual and vertex decode, XCD order
+                                    // for the 3-D decode, non-temporal streams)
 };
 
 #define MC_D2_R 8                  // 2-D decode: rows per chunk (rows of DecodeWs in 2-D)

@@ -156,6 +156,8 @@ extern "C" mc_status mc_model_features(mc_model m, mc_plan p, const mc_codes* co
     if (m->dim != p->dim) return mc_fail(MC_ERR_ARG, "model dim does not match the plan");
     if (p->ops != MC_OPS_LINEAR) return mc_fail(MC_ERR_UNSUPPORTED, "the learned predictor needs an MC_OPS_LINEAR plan");
     if (v0 < 0 || count < 0 || v0 + count > p->nv) return mc_fail(MC_ERR_ARG, "vertex range outside the mesh");
+    mc_status st = mc_plan_ensure_xh(p, s);
+    if (st != MC_OK) return st;
     hipError_t e = mck::mlp_features(m->md, p->coords, p->nv, p->gg, p->xh, v0, count, d_z, s);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mlp_features: %s", hipGetErrorString(e));
     return MC_OK;
@@ -241,6 +243,7 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     mc_status st = mc_check_params(plan, d_field, dtype, &pp, &c);
     if (st != MC_OK) { cleanup(); return st; }
     if ((st = mc_compress_enqueue(plan, d_field, dtype, &pp, &c, s)) != MC_OK) { cleanup(); return st; }
+    if ((st = mc_plan_ensure_xh(plan, s)) != MC_OK) { cleanup(); return st; }
     // 2) input scale: 1 / rms of (x1'[n] - g) over vertices and neighbourhoods
     hipError_t e = mck::mlp_feature_sumsq(plan->coords, plan->nv, plan->gg, plan->xh, dim, ssq, 1024, s);
     std::vector<double> h(2048);

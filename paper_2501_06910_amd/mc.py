@@ -90,6 +90,19 @@ class McTuning(C.Structure):
     _fields_ = [("remap_mask", C.c_uint32), ("reserved", C.c_uint32 * 3)]
 
 
+class McStreamHeader(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("dtype", C.c_int32), ("dims", C.c_int64 * 3), ("n_vertices", C.c_int64),
+                ("grid_predictor", C.c_int32), ("residual_predictor", C.c_int32), ("learned", C.c_int32),
+                ("reserved", C.c_int32), ("tau", C.c_double), ("tau1", C.c_double), ("tau2", C.c_double),
+                ("c", C.c_double), ("n_grid_outliers", C.c_int64), ("n_vertex_outliers", C.c_int64)]
+
+
+class McStreamArrays(C.Structure):
+    _fields_ = [("grid_codes", C.c_void_p), ("g_out_idx", C.c_void_p), ("g_out_delta", C.c_void_p),
+                ("vert_codes", C.c_void_p), ("v_out_idx", C.c_void_p), ("v_out_val", C.c_void_p),
+                ("block_flags", C.c_void_p)]
+
+
 class McBatchDItem(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("codes", McCodes), ("model", C.c_void_p), ("d_out", C.c_void_p),
                 ("dtype", C.c_int)]
@@ -145,6 +158,10 @@ _SIGS = {
     "mc_huffman_encode": (C.c_int64, [_P, C.c_int64, _P, C.c_int64]),
     "mc_huffman_decode": (C.c_int64, [_P, C.c_int64, _P, C.c_int64]),
     "mc_entropy_bits": (C.c_double, [_P, C.c_int64]),
+    "mc_stream_size": (C.c_int64, [_P, _P, _P, C.c_int64, _P]),
+    "mc_stream_write": (C.c_int64, [_P, _P, _P, C.c_int64, _P, C.c_int64, _P]),
+    "mc_stream_read_header": (C.c_int, [_P, C.c_int64, _P, _P]),
+    "mc_stream_read": (C.c_int, [_P, C.c_int64, _P, _P, C.c_int64]),
 }
 
 _lib = None
@@ -382,7 +399,8 @@ def tuning_key(plan: "Plan", dtype) -> str:
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     g = plan.grid
     dims = "x".join(str(int(g.dims[d])) for d in range(plan.dim))
-    return f"{arch}|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
+    # "k9": masks over the nine knob bits of this library version
+    return f"{arch}|k9|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
 
 
 def tuning_cache() -> dict:
@@ -448,6 +466,11 @@ class Codes:
             _ptr(self._grid_tensor(grid_ref, ng, "grid_ref")), _ptr(self._grid_tensor(xhat_out, ng, "xhat_out")))
         self.grid_predictor = grid_predictor
         self.grid_ref, self.xhat_out = grid_ref, xhat_out      # kept alive with the buffers
+        g = plan.grid
+        self.meta = dict(dim=plan.dim, dims=tuple(int(g.dims[d]) for d in range(3)),
+                         dtype=F64 if dtype == torch.float64 else F32,
+                         grid_predictor=GRID_PREDICTORS[grid_predictor],
+                         residual_predictor={"none": 0, "delta": 1}[residual_predictor])
 
     def set_grid_ref(self, grid_ref):
         """Point the time-axis predictor at another reference grid (the next
@@ -464,6 +487,39 @@ class Codes:
         if t.dtype != torch.float32 or t.numel() != ng or not t.is_contiguous():
             raise ValueError(f"{what} must be a contiguous float32 tensor of n_grid values")
         return t
+
+    @classmethod
+    def from_stream(cls, plan: Plan, blob: bytes):
+        """Device codes of a stream written by write_stream (mc_stream_read,
+        then uploaded), ready for decompress with this plan.  Returns
+        (codes, model file bytes or None)."""
+        torch = _torch()
+        h = read_stream(blob)
+        if "meta" not in h:
+            raise ValueError("a 1-D baseline stream has no grid: decode it with serial_decompress")
+        m = h["meta"]
+        g = plan.grid
+        if m["dim"] != plan.dim or any(int(g.dims[d]) != m["dims"][d] for d in range(plan.dim)) or \
+                h["vert_codes"].size != plan.n_vertices:
+            raise ValueError("stream and plan disagree on the grid or the vertex count")
+        dtype = torch.float64 if m["dtype"] == F64 else torch.float32
+        inv = {v: k for k, v in GRID_PREDICTORS.items()}
+        c = cls(plan, dtype, g_cap=max(int(h["g_out_idx"].size), 1), v_cap=max(int(h["v_out_idx"].size), 1),
+                learned=h["learned"], grid_predictor=inv[m["grid_predictor"]],
+                residual_predictor={0: "none", 1: "delta"}[m["residual_predictor"]])
+        c.grid_codes.view(torch.int16).copy_(torch.from_numpy(h["grid_codes"].view(np.int16)))
+        c.vert_codes.view(torch.int16).copy_(torch.from_numpy(h["vert_codes"].view(np.int16)))
+        for dst, src in ((c.g_out_idx, h["g_out_idx"]), (c.g_out_delta, h["g_out_delta"]),
+                         (c.v_out_idx, h["v_out_idx"]), (c.v_out_val, h["v_out_val"])):
+            if src.size:
+                dst[:src.size].copy_(torch.from_numpy(np.ascontiguousarray(src)))
+        c.block_flags.copy_(torch.from_numpy(h["block_flags"].view(np.int32)))
+        r = h["result"]
+        nl = int(sum(bin(int(w)).count("1") for w in h["block_flags"])) if h["learned"] else 0
+        res = McResult(0, m["dtype"], int(r["n_grid_outliers"]), int(r["n_vertex_outliers"]), nl,
+                       r["tau"], r["tau1"], r["tau2"], r["c"], 0.0, 0.0, 0.0)
+        c.result.copy_(torch.frombuffer(bytearray(bytes(res)), dtype=torch.uint8))
+        return c, h["model"]
 
     def result_host(self) -> dict:
         b = self.result.cpu().numpy().tobytes()
@@ -490,6 +546,7 @@ class Codes:
             v_out_idx=self.v_out_idx[:nv_out].cpu().numpy(),
             v_out_val=self.v_out_val[:nv_out].cpu().numpy(),
             block_flags=self.block_flags.cpu().numpy().view(np.uint32),
+            meta=dict(self.meta),
         )
 
 
@@ -758,15 +815,11 @@ def serial_decompress(ctx: Serial, codes: SerialCodes, out=None):
     return out
 
 
-def serial_stream_bytes(host: dict, value_bytes: int) -> dict:
-    """Size of the baseline's stream: header, Huffman-coded codes, outlier
-    index gaps (LEB128) and raw payloads."""
-    vi = host["out_idx"].astype(np.int64)
-    gap = np.diff(np.concatenate([[-1], vi])) - 1 if vi.size else vi
-    parts = dict(header=HEADER_BYTES, codes=huffman_size(host["codes"]),
-                 outliers=_leb128_bytes(gap) + vi.size * value_bytes)
-    parts["total"] = sum(parts.values())
-    return parts
+def serial_stream_bytes(host: dict, value_bytes: int | None = None) -> dict:
+    """Section sizes of the baseline's stream (a dim-1 stream: header,
+    Huffman-coded codes, outlier index gaps and raw values, checksum), from
+    the bytes mc_stream_write produces."""
+    return write_stream(host)[1]
 
 
 def profile_enable(on=True):
@@ -815,45 +868,124 @@ def entropy_bits(sym: np.ndarray) -> float:
     return float(lib().mc_entropy_bits(s.ctypes.data, s.size))
 
 
-def _leb128_bytes(values: np.ndarray) -> int:
-    v = np.asarray(values, np.uint64)
-    n = np.ones(v.size, np.int64)
-    t = v >> np.uint64(7)
-    while np.any(t):
-        n += (t > 0)
-        t = t >> np.uint64(7)
-    return int(n.sum())
+STREAM_SECTIONS = ("header", "grid", "vert", "grid_outliers", "vert_outliers", "block_flags", "model", "checksum")
 
 
-HEADER_BYTES = 64
+def _stream_args(host: dict):
+    """Header and array structs of a host dict (Codes.host() or
+    SerialCodes.host()); the arrays stay referenced by the returned list."""
+    keep = []
+
+    def ptr(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dt)
+        keep.append(a)
+        return a.ctypes.data
+    r = host["result"]
+    h = McStreamHeader()
+    if "meta" in host:                               # multi-component codes
+        m = host["meta"]
+        h.dim, h.dtype = m["dim"], m["dtype"]
+        for d in range(3):
+            h.dims[d] = m["dims"][d] if d < m["dim"] else 1
+        h.n_vertices = host["vert_codes"].size
+        h.grid_predictor, h.residual_predictor = m["grid_predictor"], m["residual_predictor"]
+        h.learned = 1 if host.get("learned") else 0
+        vv = host["v_out_val"]
+        arr = McStreamArrays(ptr(host["grid_codes"], np.uint16), ptr(host["g_out_idx"], np.int32),
+                             ptr(host["g_out_delta"], np.int32), ptr(host["vert_codes"], np.uint16),
+                             ptr(host["v_out_idx"], np.int32), ptr(vv, vv.dtype),
+                             ptr(host["block_flags"], np.uint32) if h.learned else None)
+        h.n_grid_outliers, h.n_vertex_outliers = host["g_out_idx"].size, host["v_out_idx"].size
+    else:                                            # the 1-D baseline
+        vv = host["out_val"]
+        h.dim, h.dtype = 1, F64 if vv.dtype == np.float64 else F32
+        h.dims[0] = h.dims[1] = h.dims[2] = 1
+        h.n_vertices = host["codes"].size
+        arr = McStreamArrays(None, None, None, ptr(host["codes"], np.uint16), ptr(host["out_idx"], np.int32),
+                             ptr(vv, vv.dtype), None)
+        h.n_grid_outliers, h.n_vertex_outliers = 0, host["out_idx"].size
+    h.tau, h.tau1, h.tau2, h.c = r["tau"], r["tau1"], r["tau2"], r["c"]
+    return h, arr, keep
+
+
+def write_stream(host: dict, model: bytes | None = None) -> tuple:
+    """The self-describing stream of one compressed field (mc_stream_write)
+    and its section sizes (plus "total").  model: the model file to embed
+    (Model.export()), normally once per timestep sequence."""
+    h, arr, keep = _stream_args(host)
+    mb = 0 if model is None else len(model)
+    sec = (C.c_int64 * 8)()
+    n = lib().mc_stream_size(C.byref(h), C.byref(arr), model, mb, sec)
+    if n < 0:
+        raise McError(ERR_ARG, "mc_stream_size")
+    buf = (C.c_uint8 * n)()
+    got = lib().mc_stream_write(C.byref(h), C.byref(arr), model, mb, buf, n, None)
+    if got != n:
+        raise McError(ERR_ARG, "mc_stream_write")
+    parts = {k: int(sec[i]) for i, k in enumerate(STREAM_SECTIONS)}
+    parts["total"] = int(n)
+    return bytes(buf), parts
+
+
+def read_stream(blob: bytes) -> dict:
+    """Arrays of a stream (mc_stream_read): a dict shaped like Codes.host()
+    (or SerialCodes.host() for a baseline stream) plus "model" (bytes or
+    None)."""
+    h = McStreamHeader()
+    mb = C.c_int64()
+    _check(lib().mc_stream_read_header(blob, len(blob), C.byref(h), C.byref(mb)), "mc_stream_read_header")
+    vdt = np.float64 if h.dtype == F64 else np.float32
+    nv = int(h.n_vertices)
+    ng = 0 if h.dim == 1 else int(h.dims[0] * h.dims[1] * h.dims[2])
+    gc = np.empty(max(ng, 1), np.uint16)
+    gi = np.empty(max(int(h.n_grid_outliers), 1), np.int32)
+    gd = np.empty_like(gi)
+    vc = np.empty(nv, np.uint16)
+    vi = np.empty(max(int(h.n_vertex_outliers), 1), np.int32)
+    vv = np.empty(max(int(h.n_vertex_outliers), 1), vdt)
+    nb = (nv + BLOCK - 1) // BLOCK
+    bf = np.zeros((nb + 31) // 32, np.uint32)
+    arr = McStreamArrays(gc.ctypes.data, gi.ctypes.data, gd.ctypes.data, vc.ctypes.data, vi.ctypes.data,
+                         vv.ctypes.data, bf.ctypes.data)
+    model = (C.c_uint8 * max(mb.value, 1))()
+    _check(lib().mc_stream_read(blob, len(blob), C.byref(arr), model, mb.value), "mc_stream_read")
+    r = {k: getattr(h, k) for k in ("tau", "tau1", "tau2", "c", "n_grid_outliers", "n_vertex_outliers")}
+    ko, kv = int(h.n_grid_outliers), int(h.n_vertex_outliers)
+    if h.dim == 1:
+        out = dict(result=r, codes=vc, out_idx=vi[:kv], out_val=vv[:kv])
+    else:
+        out = dict(result=r, grid_codes=gc[:ng], g_out_idx=gi[:ko], g_out_delta=gd[:ko], vert_codes=vc,
+                   v_out_idx=vi[:kv], v_out_val=vv[:kv], block_flags=bf, learned=bool(h.learned),
+                   meta=dict(dim=int(h.dim), dims=tuple(int(h.dims[d]) for d in range(3)), dtype=int(h.dtype),
+                             grid_predictor=int(h.grid_predictor), residual_predictor=int(h.residual_predictor)))
+    out["model"] = bytes(model)[:mb.value] if mb.value > 0 else None
+    return out
 
 
 def grid_stream_bytes(grid_codes: np.ndarray, g_out_idx: np.ndarray, g_out_delta: np.ndarray) -> int:
-    """Bytes of the grid part of the stream (Huffman-coded grid codes and the
-    grid outlier list), as counted by stream_bytes."""
+    """Bytes of the grid sections of a stream (the Huffman-coded grid codes
+    with their length prefix, and the grid outlier list): what the sections
+    "grid" and "grid_outliers" of write_stream count, for other grid codes
+    of the same field."""
+    def leb(values):
+        v = np.asarray(values, np.uint64)
+        n = np.ones(v.size, np.int64)
+        t = v >> np.uint64(7)
+        while np.any(t):
+            n += (t > 0)
+            t = t >> np.uint64(7)
+        return int(n.sum())
     gi = g_out_idx.astype(np.int64)
     g_gap = np.diff(np.concatenate([[-1], gi])) - 1 if gi.size else gi
     zz = ((g_out_delta.astype(np.int64) << 1) ^ (g_out_delta.astype(np.int64) >> 63)).astype(np.uint64)
-    return huffman_size(grid_codes) + _leb128_bytes(g_gap) + _leb128_bytes(zz)
+    hs = huffman_size(grid_codes)
+    return leb([hs]) + hs + leb(g_gap) + leb(zz)
 
 
-def stream_bytes(host: dict, value_bytes: int, model_bytes: int = 0) -> dict:
-    """Size of the self-describing stream: header, Huffman-coded grid and
-    vertex codes, outlier lists (LEB128 index gaps + payloads), block flags
-    and the (amortised) model bytes."""
-    gi = host["g_out_idx"].astype(np.int64)
-    vi = host["v_out_idx"].astype(np.int64)
-    g_gap = np.diff(np.concatenate([[-1], gi])) - 1 if gi.size else gi
-    v_gap = np.diff(np.concatenate([[-1], vi])) - 1 if vi.size else vi
-    zz = lambda d: ((d.astype(np.int64) << 1) ^ (d.astype(np.int64) >> 63)).astype(np.uint64)
-    parts = dict(
-        header=HEADER_BYTES,
-        grid=huffman_size(host["grid_codes"]),
-        vert=huffman_size(host["vert_codes"]),
-        grid_outliers=_leb128_bytes(g_gap) + _leb128_bytes(zz(host["g_out_delta"])),
-        vert_outliers=_leb128_bytes(v_gap) + vi.size * value_bytes,
-        block_flags=host["block_flags"].size * 4 if host.get("learned") else 0,
-        model=model_bytes,
-    )
-    parts["total"] = sum(parts.values())
-    return parts
+def stream_bytes(host: dict, value_bytes: int | None = None, model: bytes | None = None) -> dict:
+    """Section sizes (and "total") of the stream mc_stream_write produces for
+    this compressed field, with the model file embedded when given.
+    value_bytes is implied by the stored values and ignored."""
+    return write_stream(host, model)[1]

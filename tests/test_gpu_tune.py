@@ -38,10 +38,10 @@ def test_knobs_do_not_change_results(dim):
         dims = (32, 28, 36)          # x a multiple of 4: the quad decode kernels
     x = dev(G.field_octaves(mesh.coords, np.random.default_rng(4)))
     plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
-    assert plan.remap_mask == 0x7F
+    assert plan.remap_mask == 0x1E0
     ref_h, ref_x = _run(plan, x, 1e-5)
     rng = np.random.default_rng(0)
-    for mask in [0, 0x7F, 0x55, 0x2A] + [int(m) for m in rng.integers(0, 128, 3)]:
+    for mask in [0, 0x7F, 0x1FF, 0x55, 0x12A, 0x180] + [int(m) for m in rng.integers(0, 512, 3)]:
         plan.remap_mask = mask
         h, xo = _run(plan, x, 1e-5)
         assert h["result"] == ref_h["result"], mask
@@ -49,7 +49,7 @@ def test_knobs_do_not_change_results(dim):
             assert np.array_equal(h[k], ref_h[k]), (mask, k)
         assert np.array_equal(xo.view(np.uint8), ref_x.view(np.uint8)), mask
     with pytest.raises(RuntimeError):
-        plan.remap_mask = 0x80
+        plan.remap_mask = 0x200
 
 
 def test_tune_picks_a_mask_and_keeps_results():
@@ -64,7 +64,7 @@ def test_tune_picks_a_mask_and_keeps_results():
     torch.cuda.synchronize()
     assert "k_resample" in M.profile_read()      # profiling was left on
     M.profile_enable(False)
-    assert 0 <= mask <= 0x7F and plan.remap_mask == mask
+    assert 0 <= mask <= 0x1FF and plan.remap_mask == mask
     print(f"[tune] chosen remap mask 0x{mask:02x}")
     h, xo = _run(plan, x, 1e-4)
     assert np.array_equal(h["vert_codes"], ref_h["vert_codes"])
