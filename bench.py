@@ -30,6 +30,7 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
         "k_range": nv * sT,                                        # field
         "k_resample": ng * (D + 1) * 8 + nv * sT + ng * 4,         # mapping, field gather, one grid array out
         "k_lorenzo": ng * 4 + ng * 2,                              # p in, codes out
+        "k_codes": ng * 4 + ng * 2 + nv * (4 * D + sT + 2) + ng * 4,   # k_lorenzo + k_residual in one launch
         "k_residual": nv * (4 * D + sT + 2) + ng * 4,              # coords, field, codes out, grid (p or x1')
         "k_residual_learned": nv * (4 * D + sT + 2 + 4) + ng * 4,
         "k_dec_xy_tot": ng * 2,                                    # 2-D: codes
@@ -44,7 +45,7 @@ def alg_bytes(kernel: str, nv: int, ng: int, D: int, sT: int) -> int:
     return table.get(kernel, 0)
 
 
-COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_residual",
+COMPRESS_PREFIXES = ("k_range", "k_resample", "k_lorenzo", "k_residual", "k_codes",
                      "k_scatter", "k_mlp_infer_c")
 DECOMPRESS_PREFIXES = ("k_dec_", "k_dec3_", "k_vdecode", "k_mlp_infer_d")
 
@@ -830,7 +831,14 @@ def main():
     x = torch.from_numpy(f).cuda()
     torch.cuda.synchronize()
     t0 = time.time()
-    plan = M.Plan(coords, cells, dims=cfg["dims"][:D])
+    grid = M.grid_from_dims(coords, cfg["dims"][:D])
+    bins = None
+    if not args.no_tune:
+        b, rec = M.tune_bins(coords, cells, grid)
+        bins = {"bin_nodes": b, "timed": rec, "seconds": round(time.time() - t0, 3)}
+        log(f"bin edge: {bins}")
+        t0 = time.time()
+    plan = M.Plan(coords, cells, grid=grid, bin_nodes=bins["bin_nodes"] if bins else 0)
     torch.cuda.synchronize()
     plan_s = time.time() - t0
     del cells
@@ -960,6 +968,7 @@ def main():
         "ms_per_step_with_kernel_events": round(ms_step_ev, 4),
         "plan_seconds": round(plan_s, 3),
         "tuning": tune,
+        "bin_tuning": bins,
         "plan": {k: info[k] for k in ("n_unresolved", "n_near_degenerate", "n_pairs", "bin_nodes")},
         "kernels": kernels,
     }

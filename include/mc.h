@@ -268,6 +268,16 @@ mc_status mc_plan_create(const float* d_coords, const int32_t* d_cells, int32_t 
                          int64_t n_vertices, int64_t n_cells, const mc_grid* grid,
                          const mc_plan_opts* opts, hipStream_t stream, mc_plan* out);
 mc_status mc_plan_get_info(mc_plan plan, mc_plan_info* out);
+/* Autotuning of the point-location bin edge (mc_plan_opts.bin_nodes) for a
+ * mesh and grid: for each of the n_candidates (1..16) bin edges in
+ * h_candidates (1..64 grid nodes), times the bin index build and the
+ * location kernel on scratch buffers (HIP events) and writes the fastest
+ * edge to *best_bin_nodes and each candidate's milliseconds to h_ms (may be
+ * NULL).  The mapping a plan gets is the same for every bin edge.  (sync) */
+mc_status mc_plan_tune_bins(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t n_vertices,
+                            int64_t n_cells, const mc_grid* grid, const int32_t* h_candidates, int32_t n_candidates,
+                            hipStream_t stream, int32_t* best_bin_nodes, double* h_ms);
+
 /* Copies the mapping: d_vid int32[dim+1][n_grid] (-1 for mid-range-filled
  * nodes), d_w float[dim+1][n_grid], d_cell int32[n_grid] (-1 = unresolved);
  * any may be NULL (MC_OPS_LINEAR plans; MC_ERR_UNSUPPORTED otherwise). */
@@ -314,12 +324,13 @@ typedef struct {
 
 mc_status mc_plan_get_tuning(mc_plan plan, mc_tuning* out);
 mc_status mc_plan_set_tuning(mc_plan plan, const mc_tuning* tuning);
-/* Times every knob both ways on this plan (starting from the default) and
- * keeps, bit by bit, the setting with the smaller summed kernel time of `reps` compress +
- * decompress passes of d_field (after one warm-up pass).  codes and d_out
- * (T[n_vertices]) receive the last pass's results.  Uses the library's
- * profiler, whose accumulated figures it clears.  Writes the choice to
- * *chosen if not NULL.  (sync) */
+/* Coordinate descent over the knob bits from the default mask (two sweeps):
+ * each candidate is timed as `reps` whole compress + decompress passes of
+ * d_field (HIP events on the stream, after one untimed pass) and a bit is
+ * flipped when that makes the passes faster.  codes and d_out
+ * (T[n_vertices]) receive the last pass's results.  The per-launch
+ * profiler is paused while timing and left as it was.  Writes the choice
+ * to *chosen if not NULL.  (sync) */
 mc_status mc_plan_tune(mc_plan plan, const void* d_field, mc_dtype dtype, const mc_params* params,
                        const mc_codes* codes, void* d_out, int32_t reps, hipStream_t stream,
                        mc_tuning* chosen);

@@ -305,12 +305,11 @@ __device__ __forceinline__ void lz_count(unsigned j, bool out, bool act, unsigne
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
-                                                 unsigned nunits, uint16_t* __restrict__ codes,
-                                                 unsigned int* __restrict__ count, unsigned int* __restrict__ gsum,
-                                                 unsigned remap)
+__device__ __forceinline__ void lorenzo_block(unsigned t, const int32_t* __restrict__ p, int n0, int n1, int n2,
+                                              int nxs, unsigned nunits, uint16_t* __restrict__ codes,
+                                              unsigned int* __restrict__ count, unsigned int* __restrict__ gsum)
 {
-    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
+    const unsigned u = t * 4u + (threadIdx.x >> 6);
     if (u >= nunits) return;
     const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
     const int x = (int)(xs * MC_LZ_W) + lane_id() - 1;      // lane 0: the column to the left
@@ -352,6 +351,15 @@ __global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, 
     }
 }
 
+template <int D>
+__global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
+                                                 unsigned nunits, uint16_t* __restrict__ codes,
+                                                 unsigned int* __restrict__ count, unsigned int* __restrict__ gsum,
+                                                 unsigned remap)
+{
+    lorenzo_block<D>(tile_of(remap), p, n0, n1, n2, nxs, nunits, codes, count, gsum);
+}
+
 // 3-D Lorenzo codes with MC_LZ_RY rows per wave: a wave owns 63 columns of
 // MC_LZ_RY consecutive rows over MC_LZ3_CH planes and loads each row's
 // MC_LZ3_CH + 1 planes once (plus the row before the first), so a node
@@ -367,13 +375,12 @@ __global__ __launch_bounds__(256) void k_lorenzo(const int32_t* __restrict__ p, 
 #define MC_LZ3_CH 4
 #endif
 
-__global__ __launch_bounds__(256) void k_lorenzo3(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
-                                                  int nyb, unsigned nunits, uint16_t* __restrict__ codes,
-                                                  unsigned int* __restrict__ count, unsigned int* __restrict__ gsum,
-                                                  unsigned remap)
+__device__ __forceinline__ void lorenzo3_block(unsigned t, const int32_t* __restrict__ p, int n0, int n1, int n2,
+                                               int nxs, int nyb, unsigned nunits, uint16_t* __restrict__ codes,
+                                               unsigned int* __restrict__ count, unsigned int* __restrict__ gsum)
 {
     constexpr int CH = MC_LZ3_CH, RY = MC_LZ_RY;
-    const unsigned u = tile_of(remap) * 4u + (threadIdx.x >> 6);
+    const unsigned u = t * 4u + (threadIdx.x >> 6);
     if (u >= nunits) return;
     const unsigned xs = u % (unsigned)nxs, r = u / (unsigned)nxs;
     const unsigned yb = r % (unsigned)nyb, zc = r / (unsigned)nyb;
@@ -422,6 +429,14 @@ __global__ __launch_bounds__(256) void k_lorenzo3(const int32_t* __restrict__ p,
     }
 }
 
+__global__ __launch_bounds__(256) void k_lorenzo3(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
+                                                  int nyb, unsigned nunits, uint16_t* __restrict__ codes,
+                                                  unsigned int* __restrict__ count, unsigned int* __restrict__ gsum,
+                                                  unsigned remap)
+{
+    lorenzo3_block(tile_of(remap), p, n0, n1, n2, nxs, nyb, nunits, codes, count, gsum);
+}
+
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int zz_bits(int k)
 {
@@ -444,15 +459,14 @@ __device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound&
 
 // Residual codes of one tile (1024 vertices) and its outlier count.
 template <typename T, int D, bool FROM_P, bool NT>
-__global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                  const void* __restrict__ xh, const T* __restrict__ x,
-                                                  const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
-                                                  float* __restrict__ dbg_g, unsigned int* __restrict__ count,
-                                                  unsigned int* __restrict__ vsum, unsigned remap)
+__device__ __forceinline__ void residual_block(long long tile, const float* __restrict__ coords, long long nv,
+                                               const GridGeom& gg, const void* __restrict__ xh,
+                                               const T* __restrict__ x, const DevBound* __restrict__ bnd,
+                                               uint16_t* __restrict__ codes, float* __restrict__ dbg_g,
+                                               unsigned int* __restrict__ count, unsigned int* __restrict__ vsum)
 {
     __shared__ int s_cnt[4];
     const DevBound b = *bnd;
-    const long long tile = tile_of(remap);
     long long v[MC_IPT];
     bool act[MC_IPT];
     T xv[MC_IPT];
@@ -481,6 +495,43 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
         const unsigned c = (unsigned)(s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3]);
         if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
         count[tile] = c;
+    }
+}
+
+template <typename T, int D, bool FROM_P, bool NT>
+__global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coords, long long nv, GridGeom gg,
+                                                  const void* __restrict__ xh, const T* __restrict__ x,
+                                                  const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
+                                                  float* __restrict__ dbg_g, unsigned int* __restrict__ count,
+                                                  unsigned int* __restrict__ vsum, unsigned remap)
+{
+    residual_block<T, D, FROM_P, NT>(tile_of(remap), coords, nv, gg, xh, x, bnd, codes, dbg_g, count, vsum);
+}
+
+// Grid codes (Lorenzo) and vertex residual codes in one launch: the two
+// read the prequantised grid and write disjoint outputs, so blocks
+// [0, nbl) take Lorenzo units and the rest residual tiles (nbl a multiple
+// of 8, so each part keeps its own XCD order); one launch boundary less,
+// and the tail of one part overlaps the other.
+template <typename T, int D, bool FROM_P, bool NT>
+__global__ __launch_bounds__(256) void k_codes(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
+                                               int nyb, unsigned nunits, uint16_t* __restrict__ gcodes,
+                                               unsigned int* __restrict__ gcount, unsigned int* __restrict__ gsum,
+                                               unsigned nbl, const float* __restrict__ coords, long long nv,
+                                               GridGeom gg, const void* __restrict__ xh, const T* __restrict__ x,
+                                               const DevBound* __restrict__ bnd, uint16_t* __restrict__ vcodes,
+                                               float* __restrict__ dbg_g, unsigned int* __restrict__ vcount,
+                                               unsigned int* __restrict__ vsum, unsigned remap_l, unsigned remap_r)
+{
+    const unsigned bi = blockIdx.x;
+    if (bi < nbl) {
+        const unsigned t = remap_l ? xcd_tile(bi, nbl) : bi;
+        if (D == 3) lorenzo3_block(t, p, n0, n1, n2, nxs, nyb, nunits, gcodes, gcount, gsum);
+        else lorenzo_block<2>(t, p, n0, n1, n2, nxs, nunits, gcodes, gcount, gsum);
+    } else {
+        const unsigned b = bi - nbl, nbr = gridDim.x - nbl;
+        residual_block<T, D, FROM_P, NT>(remap_r ? xcd_tile(b, nbr) : b, coords, nv, gg, xh, x, bnd, vcodes, dbg_g,
+                                          vcount, vsum);
     }
 }
 
@@ -797,6 +848,39 @@ hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long 
     const unsigned nunits = (unsigned)((long long)nxs * ((n1 + MC_LZ_CHUNK - 1) / MC_LZ_CHUNK));
     hipLaunchKernelGGL(k_lorenzo<2>, dim3((nunits + 3) / 4), dim3(256), 0, s, p, n0, n1, n2, nxs, nunits, codes,
                        count, gsum, remap);
+    return hipGetLastError();
+}
+
+hipError_t codes(const int32_t* p, int dim, int n0, int n1, int n2, uint16_t* gcodes, unsigned int* gcount,
+                 unsigned int* gsum, const float* coords, long long nv, GridGeom gg, const float* xh,
+                 const int32_t* pq, const void* x, int dtype, const DevBound* bnd, uint16_t* vcodes, float* dbg_g,
+                 unsigned int* vcount, unsigned int* vsum, unsigned remap, hipStream_t s)
+{
+    const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
+    const unsigned rl = remap & MC_KNOB_LORENZO, rr = remap & MC_KNOB_RESIDUAL;
+    ProfScope ps("k_codes", s);
+    const int nxs = (n0 + MC_LZ_W - 1) / MC_LZ_W;
+    int nyb = 0;
+    unsigned nunits;
+    if (dim == 3) {
+        nyb = (n1 + MC_LZ_RY - 1) / MC_LZ_RY;
+        nunits = (unsigned)((long long)nxs * nyb * ((n2 + MC_LZ3_CH - 1) / MC_LZ3_CH));
+    } else {
+        nunits = (unsigned)((long long)nxs * ((n1 + MC_LZ_CHUNK - 1) / MC_LZ_CHUNK));
+    }
+    const unsigned nbl = ((nunits + 3) / 4 + 7) / 8 * 8;
+    const unsigned nbr = (unsigned)((nv + MC_TILE - 1) / MC_TILE);
+    const dim3 grid(nbl + nbr);
+#define MC_CD(T, D, FP, NT) hipLaunchKernelGGL((k_codes<T, D, FP, NT>), grid, dim3(256), 0, s, p, n0, n1, n2, nxs, nyb, \
+                                               nunits, gcodes, gcount, gsum, nbl, coords, nv, gg, \
+                                               FP ? (const void*)pq : (const void*)xh, (const T*)x, bnd, vcodes, dbg_g, \
+                                               vcount, vsum, rl, rr)
+#define MC_CDD(T, D) do { if (pq) { if (nt) MC_CD(T, D, true, true); else MC_CD(T, D, true, false); } \
+                          else { if (nt) MC_CD(T, D, false, true); else MC_CD(T, D, false, false); } } while (0)
+    if (dtype == MC_F64) { if (dim == 2) MC_CDD(double, 2); else MC_CDD(double, 3); }
+    else { if (dim == 2) MC_CDD(float, 2); else MC_CDD(float, 3); }
+#undef MC_CDD
+#undef MC_CD
     return hipGetLastError();
 }
 

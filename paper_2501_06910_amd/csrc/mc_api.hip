@@ -717,6 +717,101 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     return MC_OK;
 }
 
+// Times the point-location index build (cell counts per bin, their scan,
+// the bin lists) and the location kernel for each candidate bin edge, on
+// scratch buffers.  The mapping does not depend on the bin edge (bins only
+// narrow the candidate cells of the lowest-id rule), so only time is
+// compared.
+extern "C" mc_status mc_plan_tune_bins(const float* d_coords, const int32_t* d_cells, int32_t dim, int64_t nv,
+                                       int64_t nc, const mc_grid* grid, const int32_t* h_candidates,
+                                       int32_t n_candidates, hipStream_t s, int32_t* best_bin_nodes,
+                                       double* h_ms)
+{
+    mc_status st = check_mesh_args(d_coords, dim, nv);
+    if (st != MC_OK) return st;
+    if (!d_cells) return mc_fail(MC_ERR_ARG, "cells pointer is NULL");
+    if (nc <= 0 || nc >= (1ll << 31)) return mc_fail(MC_ERR_ARG, "n_cells must be in [1, 2^31)");
+    if ((st = mc_check_grid(grid, dim)) != MC_OK) return st;
+    if (!h_candidates || n_candidates < 1 || n_candidates > 16) return mc_fail(MC_ERR_ARG, "1 to 16 candidates");
+    for (int k = 0; k < n_candidates; ++k)
+        if (h_candidates[k] < 1 || h_candidates[k] > 64) return mc_fail(MC_ERR_ARG, "bin edges must be in [1, 64]");
+    if (!best_bin_nodes) return mc_fail(MC_ERR_ARG, "best_bin_nodes is NULL");
+    const GridGeom gg = mc_geom(*grid);
+    const long long ng = grid->dims[0] * grid->dims[1] * grid->dims[2];
+    TempAllocs keep;
+    hipError_t e = hipSuccess;
+#define TCHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
+    float* coords = keep.get<float>((size_t)dim * nv, e);
+    TCHK(e);
+    TCHK(hipMemcpyAsync(coords, d_coords, sizeof(float) * dim * nv, hipMemcpyDeviceToDevice, s));
+    int32_t* vid = keep.get<int32_t>((size_t)(dim + 1) * ng, e);
+    TCHK(e);
+    float* w = keep.get<float>((size_t)(dim + 1) * ng, e);
+    TCHK(e);
+    int32_t* cell = keep.get<int32_t>((size_t)ng, e);
+    TCHK(e);
+    int32_t* unres = keep.get<int32_t>((size_t)ng, e);
+    TCHK(e);
+    unsigned* ctr = keep.get<unsigned>(16, e);
+    TCHK(e);
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (int k = 0; k < 4; ++k) TCHK(hipEventCreate(&ev[k]));
+    struct EvFree {
+        hipEvent_t* ev;
+        ~EvFree() { for (int k = 0; k < 4; ++k) if (ev[k]) (void)hipEventDestroy(ev[k]); }
+    } evfree{ev};
+    double best_ms = 0.0;
+    for (int k = 0; k < n_candidates; ++k) {
+        const int B = h_candidates[k];
+        TempAllocs ta;
+        const int nb0 = (int)((grid->dims[0] + B - 1) / B), nb1 = (int)((grid->dims[1] + B - 1) / B),
+                  nb2 = (int)((grid->dims[2] + B - 1) / B);
+        const long long nbins = (long long)nb0 * nb1 * nb2;
+        unsigned* cnt = ta.get<unsigned>(nbins + 4, e);
+        TCHK(e);
+        long long* start = ta.get<long long>(nbins + 1, e);
+        TCHK(e);
+        const long long nscan_tiles = (nbins + MC_TILE - 1) / MC_TILE + 1;
+        unsigned long long* sst = ta.get<unsigned long long>(nscan_tiles, e);
+        TCHK(e);
+        TCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+        TCHK(hipMemsetAsync(ctr, 0, sizeof(unsigned) * 16, s));
+        TCHK(hipMemsetAsync(sst, 0, sizeof(unsigned long long) * nscan_tiles, s));
+        TCHK(hipEventRecord(ev[0], s));
+        TCHK(mck::bins_count(coords, d_cells, dim, nv, nc, gg, grid->origin, grid->spacing, B, nb0, nb1, nb2, cnt,
+                             ctr + 0, s));
+        TCHK(mck::scan_u32(cnt, nbins, start, sst, ctr + 3, s));
+        TCHK(hipEventRecord(ev[1], s));
+        long long total = 0;
+        unsigned bad = 0;
+        TCHK(hipMemcpyAsync(&total, start + nbins, sizeof total, hipMemcpyDeviceToHost, s));
+        TCHK(hipMemcpyAsync(&bad, ctr, sizeof bad, hipMemcpyDeviceToHost, s));
+        TCHK(hipStreamSynchronize(s));
+        if (bad != 0) return mc_fail(MC_ERR_ARG, "%u cells reference a vertex id outside [0, n_vertices)", bad);
+        int32_t* list = ta.get<int32_t>((size_t)total + 1, e);
+        TCHK(e);
+        TCHK(hipMemsetAsync(cnt, 0, sizeof(unsigned) * nbins, s));
+        TCHK(hipEventRecord(ev[2], s));
+        TCHK(mck::bins_fill(coords, d_cells, dim, nv, nc, gg, grid->origin, grid->spacing, B, nb0, nb1, nb2, start,
+                            cnt, list, s));
+        TCHK(mck::locate(coords, d_cells, dim, nv, nc, gg, B, nb0, nb1, start, list, vid, w, cell, unres, ctr + 1,
+                         ctr + 2, s));
+        TCHK(hipEventRecord(ev[3], s));
+        TCHK(hipEventSynchronize(ev[3]));
+        float t01 = 0.f, t23 = 0.f;
+        TCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+        TCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+        const double ms = (double)t01 + (double)t23;
+        if (h_ms) h_ms[k] = ms;
+        if (k == 0 || ms < best_ms) {
+            best_ms = ms;
+            *best_bin_nodes = B;
+        }
+    }
+#undef TCHK
+    return MC_OK;
+}
+
 extern "C" mc_status mc_plan_get_info(mc_plan p, mc_plan_info* out)
 {
     if (!p || !out) return mc_fail(MC_ERR_ARG, "plan/out is NULL");
@@ -859,6 +954,19 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                        codes->dbg_resampled, codes->block_flags, codes->block_flags ? nbf : 0, p->err, codes->result,
                        p->gcount, p->ntg, p->knobs, s));
     p->xh_valid = !from_p;
+    if (from_p && codes->grid_predictor == MC_GRIDPRED_LORENZO) {
+        // grid and vertex codes in one launch
+        ECHK(mck::codes(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], (int)p->grid.dims[2],
+                        codes->grid_codes, p->gcount, p->gsum, p->coords, p->nv, p->gg, p->xh, p->p, d_field, dtype,
+                        p->bound, codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
+        ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
+                          codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx,
+                          codes->g_out_delta, codes->g_out_cap, d_field, dtype, p->nv, codes->vert_codes, p->vcount,
+                          p->vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, p->err, codes->result, s));
+        if (codes->dbg_grid_p)
+            ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+        return MC_OK;
+    }
     ECHK(grid_codes(p, codes, s));
     const int32_t* rho = nullptr;
     if (prm->model) {
@@ -1021,39 +1129,57 @@ extern "C" mc_status mc_plan_tune(mc_plan p, const void* d_field, mc_dtype dtype
     if (st != MC_OK) return st;
     if ((st = mc_check_decompress(p, codes, prm->model, d_out, dtype)) != MC_OK) return st;
     if (reps < 1 || reps > 1000) return mc_fail(MC_ERR_ARG, "reps must be in [1, 1000]");
-    // summed kernel milliseconds of `reps` passes with the given knobs
+    // device milliseconds of `reps` whole compress + decompress passes with
+    // the given knobs (HIP events on the stream around the passes, after one
+    // untimed pass; the per-launch profiler stays off while timing, since its
+    // events would add to every launch)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return mc_fail(MC_ERR_DEVICE, "hipEventCreate failed");
+    }
     auto measure = [&](unsigned knobs, double* ms) -> mc_status {
         p->knobs = knobs;
         mc_status r = mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
         if (r == MC_OK) r = mc_decompress_enqueue(p, codes, prm->model, d_out, dtype, s);
         if (r != MC_OK) return r;
-        if (hipStreamSynchronize(s) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "synchronize failed");
-        mc_profile_reset();
-        mc_profile_enable(1);
+        if (hipEventRecord(e0, s) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "hipEventRecord failed");
         for (int i = 0; i < reps && r == MC_OK; ++i) {
             r = mc_compress_enqueue(p, d_field, dtype, prm, codes, s);
             if (r == MC_OK) r = mc_decompress_enqueue(p, codes, prm->model, d_out, dtype, s);
         }
-        mc_profile_enable(0);
-        if (hipStreamSynchronize(s) != hipSuccess) r = mc_fail(MC_ERR_DEVICE, "synchronize failed");
-        double tot[64];
-        const int32_t n = mc_profile_read(nullptr, nullptr, tot, 64);
-        *ms = 0.0;
-        for (int32_t i = 0; i < n; ++i) *ms += tot[i];
-        mc_profile_reset();
-        return r;
+        if (r != MC_OK) return r;
+        float t = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return mc_fail(MC_ERR_DEVICE, "timing events failed");
+        *ms = t;
+        return MC_OK;
     };
     const bool was_on = g_prof_on;
+    mc_profile_enable(0);
+    // coordinate descent from the default mask, two sweeps over the bits
     unsigned best = mck::MC_KNOB_DEFAULT;
     double best_ms = 0.0;
-    if ((st = measure(best, &best_ms)) != MC_OK) return st;
-    for (unsigned bit = 1; bit & mck::MC_KNOB_ALL; bit <<= 1) {
-        double ms = 0.0;
-        if ((st = measure(best ^ bit, &ms)) != MC_OK) return st;
-        if (ms < best_ms) {
-            best ^= bit;
-            best_ms = ms;
+    st = measure(best, &best_ms);
+    for (int sweep = 0; sweep < 2 && st == MC_OK; ++sweep) {
+        bool changed = false;
+        for (unsigned bit = 1; (bit & mck::MC_KNOB_ALL) && st == MC_OK; bit <<= 1) {
+            double ms = 0.0;
+            if ((st = measure(best ^ bit, &ms)) != MC_OK) break;
+            if (ms < best_ms) {
+                best ^= bit;
+                best_ms = ms;
+                changed = true;
+            }
         }
+        if (!changed) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != MC_OK) {
+        mc_profile_enable(was_on ? 1 : 0);
+        return st;
     }
     p->knobs = best;
     mc_profile_enable(was_on ? 1 : 0);

@@ -61,6 +61,12 @@ hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, c
                     unsigned remap, hipStream_t s);
 hipError_t lorenzo(const int32_t* p, int dim, int n0, int n1, int n2, long long ng, uint16_t* codes,
                    unsigned int* count, unsigned int* gsum, unsigned remap, hipStream_t s);
+// Lorenzo grid codes and plain vertex residual codes in one launch (see
+// lorenzo and residual; pq as for residual).
+hipError_t codes(const int32_t* p, int dim, int n0, int n1, int n2, uint16_t* gcodes, unsigned int* gcount,
+                 unsigned int* gsum, const float* coords, long long nv, GridGeom gg, const float* xh,
+                 const int32_t* pq, const void* x, int dtype, const DevBound* bnd, uint16_t* vcodes, float* dbg_g,
+                 unsigned int* vcount, unsigned int* vsum, unsigned remap, hipStream_t s);
 // pq non-NULL (plain codes only): the cell corners are read from the
 // prequantised grid and converted as x1' = (float)(c + p * 2 tau1); else
 // from x1' (xh).

@@ -119,6 +119,7 @@ _SIGS = {
     "mc_grid_from_percentile": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, C.c_double, C.c_int64, _P, _P,
                                           _P]),
     "mc_plan_create": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, _P, _P, _P]),
+    "mc_plan_tune_bins": (C.c_int, [_P, _P, C.c_int32, C.c_int64, C.c_int64, _P, _P, C.c_int32, _P, _P, _P]),
     "mc_plan_get_info": (C.c_int, [_P, _P]),
     "mc_plan_mapping": (C.c_int, [_P, _P, _P, _P, _P]),
     "mc_plan_get_grid": (C.c_int, [_P, _P]),
@@ -279,11 +280,14 @@ class Plan:
     """Field-independent mesh-grid mapping (owns device memory)."""
 
     def __init__(self, coords, cells, grid: McGrid | None = None, dims=None, fill: str = "nearest",
-                 bin_nodes: int = 0, operators: str = "linear", coarsen: bool = False):
+                 bin_nodes=0, operators: str = "linear", coarsen: bool = False):
         """operators: "linear" (barycentric f, multilinear g) or "cluster"
         (the paper's cluster-mean f and nearest-node g; cells may be None);
         coarsen: Grid_Coarsen (cluster plans), after which `grid` and
-        `n_grid` describe the coarsened grid and `kept_planes()` lists it."""
+        `n_grid` describe the coarsened grid and `kept_planes()` lists it;
+        bin_nodes: the point-location bin edge in grid nodes (0: the
+        library's default, "auto": the fastest of BIN_CANDIDATES timed by
+        mc_plan_tune_bins, kept in the tuning cache per mesh signature)."""
         torch = _torch()
         _require_cuda(coords, "coords", torch.float32)
         if operators not in ("linear", "cluster"):
@@ -295,7 +299,12 @@ class Plan:
         if grid is None:
             grid = grid_from_dims(coords, dims)
         self.grid = grid
-        opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, bin_nodes,
+        self.bin_tuning = None
+        if bin_nodes == "auto":
+            bin_nodes = 0
+            if operators == "linear":
+                bin_nodes, self.bin_tuning = tune_bins(coords, cells, grid)
+        opts = McPlanOpts(FILL_NEAREST if fill == "nearest" else FILL_MIDRANGE, int(bin_nodes),
                           OPS_CLUSTER if operators == "cluster" else OPS_LINEAR, 1 if coarsen else 0)
         h = C.c_void_p()
         _check(lib().mc_plan_create(_ptr(coords), _ptr(cells), self.dim, coords.shape[1],
@@ -403,6 +412,33 @@ def tuning_key(plan: "Plan", dtype) -> str:
     return f"{arch}|k9|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
 
 
+BIN_CANDIDATES = (1, 2, 3, 4)
+
+
+def tune_bins(coords, cells, grid: McGrid, candidates=BIN_CANDIDATES):
+    """The fastest point-location bin edge for this mesh and grid
+    (mc_plan_tune_bins), from the tuning cache when this device, grid and
+    mesh size were timed before.  Returns (bin_nodes, {edge: ms} or the
+    cache entry)."""
+    torch = _torch()
+    arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
+    dim = int(coords.shape[0])
+    dims = "x".join(str(int(grid.dims[d])) for d in range(dim))
+    key = f"{arch}|bins|dim{dim}|{dims}|nv{int(coords.shape[1])}|nc{int(cells.shape[1])}"
+    hit = tuning_cache().get(key)
+    if hit is not None:
+        return int(hit["bin_nodes"]), hit
+    cand = np.ascontiguousarray(candidates, np.int32)
+    ms = np.zeros(cand.size, np.float64)
+    best = C.c_int32()
+    _check(lib().mc_plan_tune_bins(_ptr(coords), _ptr(cells), dim, coords.shape[1], cells.shape[1], C.byref(grid),
+                                   cand.ctypes.data, cand.size, _stream(), C.byref(best), ms.ctypes.data),
+           "mc_plan_tune_bins")
+    rec = {"bin_nodes": int(best.value), "ms": {str(int(c)): round(float(t), 4) for c, t in zip(cand, ms)}}
+    store_tuning(key, rec)
+    return int(best.value), rec
+
+
 def tuning_cache() -> dict:
     if not os.path.exists(TUNING_CACHE):
         return {}
@@ -410,9 +446,9 @@ def tuning_cache() -> dict:
         return json.load(f)
 
 
-def store_tuning(key: str, mask: int):
+def store_tuning(key: str, mask):
     c = tuning_cache()
-    c[key] = {"remap_mask": mask}
+    c[key] = mask if isinstance(mask, dict) else {"remap_mask": mask}
     try:
         tmp = TUNING_CACHE + f".tmp{os.getpid()}"
         with open(tmp, "w") as f:

@@ -99,6 +99,13 @@ def test_host_validation_before_device_work():
     assert lib.mc_serial_destroy(None) == M.OK
     assert lib.mc_serial_compress(None, fake, M.F32, 16, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG
     assert lib.mc_serial_decompress(None, C.byref(codes), 16, fake, M.F32, None) == M.ERR_ARG
+    # bin tuning: arguments checked on the host
+    cand = (C.c_int32 * 2)(1, 2)
+    best = C.c_int32()
+    assert lib.mc_plan_tune_bins(fake, None, 2, 10, 10, C.byref(g), cand, 2, None, C.byref(best), None) == M.ERR_ARG
+    assert lib.mc_plan_tune_bins(fake, fake, 2, 10, 10, C.byref(g), cand, 0, None, C.byref(best), None) == M.ERR_ARG
+    bad_c = (C.c_int32 * 1)(65)
+    assert lib.mc_plan_tune_bins(fake, fake, 2, 10, 10, C.byref(g), bad_c, 1, None, C.byref(best), None) == M.ERR_ARG
     # the allocation-free compress: limits and pointers checked on the host
     assert lib.mc_serial_noalloc_max() == 1 << 28
     assert lib.mc_serial_compress_noalloc(None, M.F32, 16, 1e-3, M.EB_REL, C.byref(codes), None) == M.ERR_ARG

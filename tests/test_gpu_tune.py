@@ -70,3 +70,32 @@ def test_tune_picks_a_mask_and_keeps_results():
     assert np.array_equal(h["vert_codes"], ref_h["vert_codes"])
     assert np.array_equal(h["grid_codes"], ref_h["grid_codes"])
     assert np.array_equal(xo.view(np.uint8), ref_x.view(np.uint8))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_bin_tuning_keeps_the_mapping(dim):
+    """The bin edge only speeds up point location: a plan built with the
+    tuned edge, and plans built with each candidate edge, hold the same
+    mapping bit for bit; the tuner reports a time for every candidate."""
+    if dim == 2:
+        mesh = G.delaunay_2d(G.stratified_points_2d(120, np.random.default_rng(3), drop=50))
+        dims = (130, 117)
+    else:
+        mesh = G.kuhn_tet_mesh(24, 5)
+        dims = (27, 25, 26)
+    coords, cells = dev(mesh.coords), dev(mesh.cells)
+    grid = M.grid_from_dims(coords, dims)
+    best, rec = M.tune_bins(coords, cells, grid)
+    assert best in M.BIN_CANDIDATES
+    print(f"[bins D={dim}] chosen {best}: {rec}")
+    maps = []
+    for b in (best,) + M.BIN_CANDIDATES:
+        plan = M.Plan(coords, cells, grid=grid, bin_nodes=b)
+        assert plan.info()["bin_nodes"] == b
+        vid, w, cell = plan.mapping()
+        maps.append((vid.cpu().numpy(), w.cpu().numpy().view(np.uint32), cell.cpu().numpy()))
+    for m in maps[1:]:
+        for a, b in zip(maps[0], m):
+            assert np.array_equal(a, b)
+    auto = M.Plan(coords, cells, grid=grid, bin_nodes="auto")      # from the tuning cache now
+    assert auto.info()["bin_nodes"] == best
