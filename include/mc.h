@@ -388,11 +388,17 @@ mc_status mc_model_features(mc_model model, mc_plan plan, const mc_codes* codes,
 /* ---- batched compression ------------------------------------------------
  * Compresses many fields, on one or more plans, as one HIP graph.  The
  * first call with a given item list (compared byte for byte, so zero the
- * structs before filling them) captures the compress sequence of every item
- * into a graph: one chain of kernels per distinct plan, the chains forked
- * from and joined back to `stream`; items that share a plan run in list
- * order on their chain, since they share its workspace.  Later calls with the
- * same list replay the graph in one launch.  Each item follows mc_compress
+ * structs before filling them) captures the batch into a graph.  Fields on
+ * the plain Lorenzo path (MC_OPS_LINEAR plan, no model, MC_RESPRED_NONE,
+ * MC_GRIDPRED_LORENZO, no xhat_out or diagnostics) go through work-list
+ * stage launches: one launch per stage (range, range fold, resample, grid
+ * and vertex codes, outlier lists) over the tiles of all of them, each with
+ * its own workspace held by the graph (about 4 bytes per grid node plus
+ * 1 KB per 1,024 nodes and vertices).  The other fields run as one chain of
+ * kernels per distinct plan, forked from and joined back to the graph's
+ * origin; fields that share a plan run in list order on its chain, since
+ * they share its workspace.  Later calls with the same list replay the graph
+ * in one launch.  Each item follows mc_compress
  * exactly (same codes, outliers and result), including its error statuses,
  * which are written to that item's `codes.result` on the device.  Host-side
  * argument errors of any item fail the whole call before anything is
@@ -412,7 +418,10 @@ mc_status mc_batch_compress(const mc_batch_item* items, int32_t n_items, hipStre
 
 /* The inverse (Alg. 4 for every item), captured and replayed the same way:
  * each item follows mc_decompress exactly, writing d_out (T[n_vertices] of
- * its plan, caller-owned).  `codes` are the buffers a compress filled. */
+ * its plan, caller-owned).  `codes` are the buffers a compress filled.  The
+ * grid decodes run on one chain per plan, each into the field's own decoded
+ * grid held by the graph; the vertex decode of every field without a model
+ * and with value-by-value residual codes is then one work-list launch. */
 typedef struct {
     mc_plan plan;
     mc_codes codes;
@@ -422,6 +431,12 @@ typedef struct {
 } mc_batch_ditem;
 
 mc_status mc_batch_decompress(const mc_batch_ditem* items, int32_t n_items, hipStream_t stream);
+/* The cached graph of an item list (kind 0: mc_batch_item[n], 1:
+ * mc_batch_ditem[n], compared byte for byte as in the calls): how many of
+ * its fields run on the work-list stage launches and how many nodes the
+ * graph has.  MC_ERR_ARG when no graph is cached for the list.  (host) */
+mc_status mc_batch_graph_info(int32_t kind, const void* items, int32_t n_items, int32_t* n_batched,
+                              int64_t* n_nodes);
 /* Synchronises the device and frees every cached batch graph. */
 mc_status mc_batch_release(void);
 

@@ -21,15 +21,18 @@
 #include "mc_kernels.h"
 
 // ---------------------------------------------------------------------------
+// Block b of nb: min/max keys and non-finite flag of its share of x (a
+// grid-stride loop over nb blocks), written to partial[3b..3b+2]; the
+// blocks also clear zero[0, nzero).
 template <typename T, bool VEC>
-__global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long long n,
-                                               unsigned long long* __restrict__ partial,
-                                               unsigned int* __restrict__ zero, long long nzero)
+__device__ __forceinline__ void range_block(unsigned b, unsigned nb, const T* __restrict__ x, long long n,
+                                            unsigned long long* __restrict__ partial, unsigned int* __restrict__ zero,
+                                            long long nzero)
 {
     __shared__ unsigned long long s_mn[4], s_mx[4];
     __shared__ unsigned int s_fl[4];
-    const long long stride = (long long)gridDim.x * 256;
-    const long long gid = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long stride = (long long)nb * 256;
+    const long long gid = (long long)b * 256 + threadIdx.x;
     for (long long i = gid; i < nzero; i += stride) zero[i] = 0u;
     double mn = __builtin_inf(), mx = -__builtin_inf();
     bool bad = false;
@@ -110,17 +113,25 @@ __global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long lon
             kmx = s_mx[k] > kmx ? s_mx[k] : kmx;
             fl |= s_fl[k];
         }
-        partial[3 * blockIdx.x] = kmn;
-        partial[3 * blockIdx.x + 1] = kmx;
-        partial[3 * blockIdx.x + 2] = fl;
+        partial[3 * b] = kmn;
+        partial[3 * b + 1] = kmx;
+        partial[3 * b + 2] = fl;
     }
+}
+
+template <typename T, bool VEC>
+__global__ __launch_bounds__(256) void k_range(const T* __restrict__ x, long long n,
+                                               unsigned long long* __restrict__ partial,
+                                               unsigned int* __restrict__ zero, long long nzero)
+{
+    range_block<T, VEC>(blockIdx.x, gridDim.x, x, n, partial, zero, nzero);
 }
 
 // One workgroup folds the per-block partials into the range slot and
 // computes the error split once.
-__global__ __launch_bounds__(256) void k_range_final(const unsigned long long* __restrict__ partial, int nparts,
-                                                     RangeOut* __restrict__ out, BoundParams bp,
-                                                     DevBound* __restrict__ bout)
+__device__ __forceinline__ void range_final_block(const unsigned long long* __restrict__ partial, int nparts,
+                                                  RangeOut* __restrict__ out, BoundParams bp,
+                                                  DevBound* __restrict__ bout)
 {
     __shared__ unsigned long long s_mn[4], s_mx[4];
     __shared__ unsigned int s_fl[4];
@@ -168,19 +179,25 @@ __global__ __launch_bounds__(256) void k_range_final(const unsigned long long* _
     }
 }
 
+__global__ __launch_bounds__(256) void k_range_final(const unsigned long long* __restrict__ partial, int nparts,
+                                                     RangeOut* __restrict__ out, BoundParams bp,
+                                                     DevBound* __restrict__ bout)
+{
+    range_final_block(partial, nparts, out, bp, bout);
+}
+
 // ---------------------------------------------------------------------------
 template <typename T, int D, bool NT>
-__global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vid, const float* __restrict__ w,
-                                                  long long ng, const T* __restrict__ x,
-                                                  const DevBound* __restrict__ bnd,
-                                                  int32_t* __restrict__ p, float* __restrict__ xh,
-                                                  float* __restrict__ dbg_v, uint32_t* __restrict__ bflags,
-                                                  long long nbflags, unsigned int* __restrict__ err,
-                                                  mc_result* __restrict__ res, int dtype,
-                                                  unsigned int* __restrict__ gcount, long long ntg, unsigned remap)
+__device__ __forceinline__ void resample_block(unsigned t, const int32_t* __restrict__ vid,
+                                               const float* __restrict__ w, long long ng, const T* __restrict__ x,
+                                               const DevBound* __restrict__ bnd, int32_t* __restrict__ p,
+                                               float* __restrict__ xh, float* __restrict__ dbg_v,
+                                               uint32_t* __restrict__ bflags, long long nbflags,
+                                               unsigned int* __restrict__ err, mc_result* __restrict__ res,
+                                               int dtype, unsigned int* __restrict__ gcount, long long ntg)
 {
     const DevBound b = *bnd;
-    const long long j = (long long)tile_of(remap) * 256 + threadIdx.x;
+    const long long j = (long long)t * 256 + threadIdx.x;
     if (bflags && j < nbflags) bflags[j] = 0u;      // learned-block bits start clear
     if (j < ntg) gcount[j] = 0u;                    // grid outlier counts (k_lorenzo adds)
     if (j == 0) {
@@ -219,6 +236,20 @@ __global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vi
     p[j] = q;
     if (xh) xh[j] = xhat_of(q, b.c, b.step1);      // reconstructed grid x1', as the decoder rebuilds it
     if (dbg_v) dbg_v[j] = v;
+}
+
+template <typename T, int D, bool NT>
+__global__ __launch_bounds__(256) void k_resample(const int32_t* __restrict__ vid, const float* __restrict__ w,
+                                                  long long ng, const T* __restrict__ x,
+                                                  const DevBound* __restrict__ bnd,
+                                                  int32_t* __restrict__ p, float* __restrict__ xh,
+                                                  float* __restrict__ dbg_v, uint32_t* __restrict__ bflags,
+                                                  long long nbflags, unsigned int* __restrict__ err,
+                                                  mc_result* __restrict__ res, int dtype,
+                                                  unsigned int* __restrict__ gcount, long long ntg, unsigned remap)
+{
+    resample_block<T, D, NT>(tile_of(remap), vid, w, ng, x, bnd, p, xh, dbg_v, bflags, nbflags, err, res, dtype,
+                             gcount, ntg);
 }
 
 // ---------------------------------------------------------------------------
@@ -637,17 +668,18 @@ __global__ __launch_bounds__(MC_LTILES * MC_WG) void k_residual_learned(
 // recomputed, vertex outliers the raw value.  Block 0 also writes the list totals, the count of learned blocks
 // and the final status (capacity overflows included).
 template <typename T, int D>
-__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng, int gpred,
-                                                 const float* __restrict__ gref, const uint16_t* __restrict__ gcodes,
-                                                 const unsigned int* __restrict__ gcount,
-                                                 const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
-                                                 int32_t* __restrict__ gdelta, long long gcap, long long ntg,
-                                                 const T* __restrict__ x, long long nv,
-                                                 const uint16_t* __restrict__ vcodes,
-                                                 const unsigned int* __restrict__ vcount,
-                                                 const unsigned int* __restrict__ vsum, int32_t* __restrict__ vidx,
-                                                 T* __restrict__ vval, long long vcap,
-                                                 const unsigned int* __restrict__ err, mc_result* __restrict__ res)
+__device__ __forceinline__ void scatter_block(unsigned bidx, const int32_t* __restrict__ p, int n0, int n1,
+                                              long long ng, int gpred, const float* __restrict__ gref,
+                                              const uint16_t* __restrict__ gcodes,
+                                              const unsigned int* __restrict__ gcount,
+                                              const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
+                                              int32_t* __restrict__ gdelta, long long gcap, long long ntg,
+                                              const T* __restrict__ x, long long nv,
+                                              const uint16_t* __restrict__ vcodes,
+                                              const unsigned int* __restrict__ vcount,
+                                              const unsigned int* __restrict__ vsum, int32_t* __restrict__ vidx,
+                                              T* __restrict__ vval, long long vcap,
+                                              const unsigned int* __restrict__ err, mc_result* __restrict__ res)
 {
     __shared__ int s_cnt[MC_IPT * 4 + 1];
     __shared__ unsigned s_c[MC_SC_TILES], s_off[MC_SC_TILES];
@@ -655,7 +687,7 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
     const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
     const long long ngg = (ntg + MC_SC_TILES - 1) / MC_SC_TILES, ngv = (ntv + MC_SC_TILES - 1) / MC_SC_TILES;
     const int w = threadIdx.x >> 6;
-    if (blockIdx.x == 0) {
+    if (bidx == 0) {
         // totals of both lists and the learned-block count (bit 31 marks the
         // first tile of a learned block: every MC_LBLOCK / MC_TILE-th tile),
         // all loads of the three sums issued before any is added
@@ -697,8 +729,8 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
         }
         __syncthreads();                           // s_red is reused below
     }
-    const bool vert = blockIdx.x >= ngg;
-    const long long grp = vert ? blockIdx.x - ngg : blockIdx.x;
+    const bool vert = bidx >= ngg;
+    const long long grp = vert ? bidx - ngg : bidx;
     const long long ntl = vert ? ntv : ntg;
     const unsigned int* cnt = vert ? vcount : gcount;
     const long long t0 = grp * MC_SC_TILES;
@@ -774,6 +806,23 @@ __global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, 
     }
 }
 
+template <typename T, int D>
+__global__ __launch_bounds__(256) void k_scatter(const int32_t* __restrict__ p, int n0, int n1, long long ng, int gpred,
+                                                 const float* __restrict__ gref, const uint16_t* __restrict__ gcodes,
+                                                 const unsigned int* __restrict__ gcount,
+                                                 const unsigned int* __restrict__ gsum, int32_t* __restrict__ gidx,
+                                                 int32_t* __restrict__ gdelta, long long gcap, long long ntg,
+                                                 const T* __restrict__ x, long long nv,
+                                                 const uint16_t* __restrict__ vcodes,
+                                                 const unsigned int* __restrict__ vcount,
+                                                 const unsigned int* __restrict__ vsum, int32_t* __restrict__ vidx,
+                                                 T* __restrict__ vval, long long vcap,
+                                                 const unsigned int* __restrict__ err, mc_result* __restrict__ res)
+{
+    scatter_block<T, D>(blockIdx.x, p, n0, n1, ng, gpred, gref, gcodes, gcount, gsum, gidx, gdelta, gcap, ntg, x, nv,
+                        vcodes, vcount, vsum, vidx, vval, vcap, err, res);
+}
+
 // x1' of the whole grid from p (for consumers that read x1' after a plain
 // compression that wrote only p).
 __global__ __launch_bounds__(256) void k_xhat_from_p(const int32_t* __restrict__ p, long long ng,
@@ -782,6 +831,120 @@ __global__ __launch_bounds__(256) void k_xhat_from_p(const int32_t* __restrict__
     const double c = bnd->c, step1 = bnd->step1;
     const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
     if (j < ng) xh[j] = xhat_of(p[j], c, step1);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stages: one launch per stage over the tiles of every field of a
+// batch.  Block b belongs to the field i with base[i] <= b < base[i + 1]
+// (binary search in the small base table; uniform over the block, so the
+// field's descriptor is read with scalar loads) and runs that field's tile
+// b - base[i] with the field's own types: fields of both value types and
+// dimensions share one launch.
+using mck::BItemC;
+using mck::MC_KNOB_NT_MAP;
+using mck::MC_KNOB_NT_VERT;
+
+__global__ __launch_bounds__(256) void k_b_range(const BItemC* __restrict__ items, const unsigned* __restrict__ base,
+                                                 int n)
+{
+    const int i = item_of(base, n, blockIdx.x);
+    const BItemC* it = items + i;
+    const unsigned b = blockIdx.x - base[i];
+    if (it->cls >= 2) {
+        if (it->vec) range_block<double, true>(b, it->nparts, (const double*)it->x, it->nv, it->partial, it->small, it->nsmall);
+        else range_block<double, false>(b, it->nparts, (const double*)it->x, it->nv, it->partial, it->small, it->nsmall);
+    } else {
+        if (it->vec) range_block<float, true>(b, it->nparts, (const float*)it->x, it->nv, it->partial, it->small, it->nsmall);
+        else range_block<float, false>(b, it->nparts, (const float*)it->x, it->nv, it->partial, it->small, it->nsmall);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_b_range_final(const BItemC* __restrict__ items)
+{
+    const BItemC* it = items + blockIdx.x;
+    range_final_block(it->partial, (int)it->nparts, it->cur, it->bp, it->bnd);
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void b_resample(const BItemC* it, unsigned t)
+{
+    const int dtype = sizeof(T) == 8 ? MC_F64 : MC_F32;
+    if (it->knobs & MC_KNOB_NT_MAP)
+        resample_block<T, D, true>(t, it->vid, it->w, it->ng, (const T*)it->x, it->bnd, it->p, nullptr, nullptr,
+                                   it->bflags, it->nbflags, it->small + 2, it->res, dtype, it->gcount, it->ntg);
+    else
+        resample_block<T, D, false>(t, it->vid, it->w, it->ng, (const T*)it->x, it->bnd, it->p, nullptr, nullptr,
+                                    it->bflags, it->nbflags, it->small + 2, it->res, dtype, it->gcount, it->ntg);
+}
+
+__global__ __launch_bounds__(256) void k_b_resample(const BItemC* __restrict__ items,
+                                                    const unsigned* __restrict__ base, int n)
+{
+    const int i = item_of(base, n, blockIdx.x);
+    const BItemC* it = items + i;
+    const unsigned t = blockIdx.x - base[i];
+    switch (it->cls) {
+    case 0: b_resample<float, 2>(it, t); break;
+    case 1: b_resample<float, 3>(it, t); break;
+    case 2: b_resample<double, 2>(it, t); break;
+    default: b_resample<double, 3>(it, t); break;
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void b_codes(const BItemC* it, unsigned b)
+{
+    const long long ngg = (it->ntg + MC_SC_TILES - 1) / MC_SC_TILES;
+    unsigned* gsum = it->small + 16;
+    unsigned* vsum = gsum + ngg;
+    if (b < it->nbl) {
+        if (D == 3) lorenzo3_block(b, it->p, it->n0, it->n1, it->n2, it->nxs, it->nyb, it->nunits, it->gcodes, it->gcount, gsum);
+        else lorenzo_block<2>(b, it->p, it->n0, it->n1, it->n2, it->nxs, it->nunits, it->gcodes, it->gcount, gsum);
+    } else if (it->knobs & MC_KNOB_NT_VERT) {
+        residual_block<T, D, true, true>(b - it->nbl, it->coords, it->nv, it->gg, it->p, (const T*)it->x, it->bnd,
+                                         it->vcodes, nullptr, it->vcount, vsum);
+    } else {
+        residual_block<T, D, true, false>(b - it->nbl, it->coords, it->nv, it->gg, it->p, (const T*)it->x, it->bnd,
+                                          it->vcodes, nullptr, it->vcount, vsum);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_b_codes(const BItemC* __restrict__ items, const unsigned* __restrict__ base,
+                                                 int n)
+{
+    const int i = item_of(base, n, blockIdx.x);
+    const BItemC* it = items + i;
+    const unsigned b = blockIdx.x - base[i];
+    switch (it->cls) {
+    case 0: b_codes<float, 2>(it, b); break;
+    case 1: b_codes<float, 3>(it, b); break;
+    case 2: b_codes<double, 2>(it, b); break;
+    default: b_codes<double, 3>(it, b); break;
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void b_scatter(const BItemC* it, unsigned b)
+{
+    const long long ngg = (it->ntg + MC_SC_TILES - 1) / MC_SC_TILES;
+    unsigned* gsum = it->small + 16;
+    scatter_block<T, D>(b, it->p, it->n0, it->n1, it->ng, MC_GRIDPRED_LORENZO, nullptr, it->gcodes, it->gcount, gsum,
+                        it->gidx, it->gdelta, it->gcap, it->ntg, (const T*)it->x, it->nv, it->vcodes, it->vcount,
+                        gsum + ngg, it->vidx, (T*)it->vval, it->vcap, it->small + 2, it->res);
+}
+
+__global__ __launch_bounds__(256) void k_b_scatter(const BItemC* __restrict__ items, const unsigned* __restrict__ base,
+                                                   int n)
+{
+    const int i = item_of(base, n, blockIdx.x);
+    const BItemC* it = items + i;
+    const unsigned b = blockIdx.x - base[i];
+    switch (it->cls) {
+    case 0: b_scatter<float, 2>(it, b); break;
+    case 1: b_scatter<float, 3>(it, b); break;
+    case 2: b_scatter<double, 2>(it, b); break;
+    default: b_scatter<double, 3>(it, b); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -913,6 +1076,53 @@ hipError_t residual(const float* coords, long long nv, GridGeom gg, const float*
     else { if (gg.dim == 2) MC_RQD(float, 2); else MC_RQD(float, 3); }
 #undef MC_RQD
 #undef MC_RQ
+    return hipGetLastError();
+}
+
+void lorenzo_units(int dim, int n0, int n1, int n2, int* nxs, int* nyb, unsigned* nunits)
+{
+    *nxs = (n0 + MC_LZ_W - 1) / MC_LZ_W;
+    if (dim == 3) {
+        *nyb = (n1 + MC_LZ_RY - 1) / MC_LZ_RY;
+        *nunits = (unsigned)((long long)*nxs * *nyb * ((n2 + MC_LZ3_CH - 1) / MC_LZ3_CH));
+    } else {
+        *nyb = 0;
+        *nunits = (unsigned)((long long)*nxs * ((n1 + MC_LZ_CHUNK - 1) / MC_LZ_CHUNK));
+    }
+}
+
+hipError_t batch_range(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s)
+{
+    ProfScope ps("k_b_range", s);
+    hipLaunchKernelGGL(k_b_range, dim3(nblocks), dim3(256), 0, s, items, base, n);
+    return hipGetLastError();
+}
+
+hipError_t batch_range_final(const BItemC* items, int n, hipStream_t s)
+{
+    ProfScope ps("k_b_range_final", s);
+    hipLaunchKernelGGL(k_b_range_final, dim3((unsigned)n), dim3(256), 0, s, items);
+    return hipGetLastError();
+}
+
+hipError_t batch_resample(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s)
+{
+    ProfScope ps("k_b_resample", s);
+    hipLaunchKernelGGL(k_b_resample, dim3(nblocks), dim3(256), 0, s, items, base, n);
+    return hipGetLastError();
+}
+
+hipError_t batch_codes(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s)
+{
+    ProfScope ps("k_b_codes", s);
+    hipLaunchKernelGGL(k_b_codes, dim3(nblocks), dim3(256), 0, s, items, base, n);
+    return hipGetLastError();
+}
+
+hipError_t batch_scatter(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s)
+{
+    ProfScope ps("k_b_scatter", s);
+    hipLaunchKernelGGL(k_b_scatter, dim3(nblocks), dim3(256), 0, s, items, base, n);
     return hipGetLastError();
 }
 

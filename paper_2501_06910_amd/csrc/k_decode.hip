@@ -524,15 +524,13 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
 
 // Four vertices per thread (tile of 1024), every load issued before use.
 template <typename T, int D, bool LEARNED, bool NT>
-__global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
-                                                 const float* __restrict__ xh, const uint16_t* __restrict__ codes,
-                                                 const int32_t* __restrict__ oidx, const T* __restrict__ oval,
-                                                 const mc_result* __restrict__ res, long long vcap,
-                                                 const int32_t* __restrict__ rho_q,
-                                                 const uint32_t* __restrict__ bflags, T* __restrict__ xout,
-                                                 unsigned remap)
+__device__ __forceinline__ void vdecode_block(long long tile, const float* __restrict__ coords, long long nv,
+                                              const GridGeom& gg, const float* __restrict__ xh,
+                                              const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+                                              const T* __restrict__ oval, const mc_result* __restrict__ res,
+                                              long long vcap, const int32_t* __restrict__ rho_q,
+                                              const uint32_t* __restrict__ bflags, T* __restrict__ xout)
 {
-    const long long tile = tile_of(remap);
     bool learned = false;
     if (LEARNED) {
         const long long blk = (tile * MC_TILE) / MC_LBLOCK;       // a tile lies inside one block
@@ -563,6 +561,46 @@ __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coord
             const int q = code[i] - MC_R + rq[i];
             st_s<NT>(xout + v[i], (T)((double)g[i] + (double)q * step2));
         }
+    }
+}
+
+template <typename T, int D, bool LEARNED, bool NT>
+__global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
+                                                 const float* __restrict__ xh, const uint16_t* __restrict__ codes,
+                                                 const int32_t* __restrict__ oidx, const T* __restrict__ oval,
+                                                 const mc_result* __restrict__ res, long long vcap,
+                                                 const int32_t* __restrict__ rho_q,
+                                                 const uint32_t* __restrict__ bflags, T* __restrict__ xout,
+                                                 unsigned remap)
+{
+    vdecode_block<T, D, LEARNED, NT>(tile_of(remap), coords, nv, gg, xh, codes, oidx, oval, res, vcap, rho_q, bflags,
+                                     xout);
+}
+
+// Batched vertex decode: one launch over the tiles of every field (see the
+// batched compress stages in k_compress.hip), plain codes.
+template <typename T, int D>
+__device__ __forceinline__ void b_vdecode(const mck::BItemD* it, unsigned t)
+{
+    if (it->knobs & mck::MC_KNOB_NT_VERT)
+        vdecode_block<T, D, false, true>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
+                                         (const T*)it->vval, it->res, it->vcap, nullptr, nullptr, (T*)it->xout);
+    else
+        vdecode_block<T, D, false, false>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
+                                          (const T*)it->vval, it->res, it->vcap, nullptr, nullptr, (T*)it->xout);
+}
+
+__global__ __launch_bounds__(256) void k_b_vdecode(const mck::BItemD* __restrict__ items,
+                                                   const unsigned* __restrict__ base, int n)
+{
+    const int i = item_of(base, n, blockIdx.x);
+    const mck::BItemD* it = items + i;
+    const unsigned t = blockIdx.x - base[i];
+    switch (it->cls) {
+    case 0: b_vdecode<float, 2>(it, t); break;
+    case 1: b_vdecode<float, 3>(it, t); break;
+    case 2: b_vdecode<double, 2>(it, t); break;
+    default: b_vdecode<double, 3>(it, t); break;
     }
 }
 
@@ -849,6 +887,13 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t batch_vdecode(const BItemD* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s)
+{
+    ProfScope ps("k_b_vdecode", s);
+    hipLaunchKernelGGL(k_b_vdecode, dim3(nblocks), dim3(256), 0, s, items, base, n);
+    return hipGetLastError();
 }
 
 hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,

@@ -1046,26 +1046,36 @@ mc_status mc_check_decompress(mc_plan p, const mc_codes* codes, mc_model model, 
     return check_codes(p, codes, model != nullptr);
 }
 
-mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
-                                hipStream_t s)
+mc_status mc_grid_decode_enqueue(mc_plan p, const mc_codes* codes, float* xh, hipStream_t s)
 {
     hipError_t e;
 #define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     if (codes->grid_predictor == MC_GRIDPRED_LORENZO)
         ECHK(mck::grid_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
                               codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
-                              (int)p->grid.dims[2], p->p, p->xh, p->dws, p->knobs, s));
+                              (int)p->grid.dims[2], p->p, xh, p->dws, p->knobs, s));
     else if (codes->grid_predictor == MC_GRIDPRED_TEMPORAL)
         ECHK(mck::temporal_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
-                                  codes->result, codes->grid_ref, p->ng, p->p, p->xh, s));
+                                  codes->result, codes->grid_ref, p->ng, p->p, xh, s));
     else
         ECHK(mck::interp_decode(codes->grid_codes, codes->g_out_idx, codes->g_out_delta, codes->g_out_cap,
                                 codes->result, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1],
                                 (int)p->grid.dims[2], codes->grid_predictor == MC_GRIDPRED_INTERP_CUBIC, p->p,
-                                p->xh, s));
-    p->xh_valid = true;
+                                xh, s));
+    if (xh == p->xh) p->xh_valid = true;
     if (codes->xhat_out)
-        ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+        ECHK(hipMemcpyAsync(codes->xhat_out, xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
+#undef ECHK
+    return MC_OK;
+}
+
+mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
+                                hipStream_t s)
+{
+    hipError_t e;
+    mc_status gst = mc_grid_decode_enqueue(p, codes, p->xh, s);
+    if (gst != MC_OK) return gst;
+#define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     if (p->ops == MC_OPS_CLUSTER && codes->residual_predictor == MC_RESPRED_DELTA) {
         ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, p->m, codes->vert_codes, codes->v_out_idx,
                                       codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,

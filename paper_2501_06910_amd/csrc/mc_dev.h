@@ -285,6 +285,19 @@ __device__ __forceinline__ Quad<double> load_quad(const double* __restrict__ p)
     const double2 b = *reinterpret_cast<const double2*>(p + 2);
     return Quad<double>{{a.x, a.y, b.x, b.y}};
 }
+// Field of block b in a batched stage launch: the i with
+// base[i] <= b < base[i + 1] (base ascending, n fields).
+__device__ __forceinline__ int item_of(const unsigned* __restrict__ base, int n, unsigned b)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
 // Tile of this workgroup: XCD-contiguous order when `remap` is set.
 __device__ __forceinline__ unsigned tile_of(unsigned remap)
 {

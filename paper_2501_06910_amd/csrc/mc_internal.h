@@ -71,6 +71,10 @@ void mc_batch_forget(const void* obj);
 mc_status mc_check_decompress(mc_plan p, const mc_codes* codes, mc_model model, const void* d_out, mc_dtype dtype);
 mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model, void* d_out, mc_dtype dtype,
                                 hipStream_t s);
+// The grid part of a decompress (Alg. 4: x1' = D(mu1)) into xh (the plan's
+// x1' or a caller buffer of n_grid floats); the plan's p and decode
+// workspace are used, so calls on one plan must be ordered.
+mc_status mc_grid_decode_enqueue(mc_plan p, const mc_codes* codes, float* xh, hipStream_t s);
 mc_status mc_check_params(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,
                           const mc_codes* codes);
 mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, const mc_params* prm,

@@ -85,6 +85,69 @@ hipError_t compact(const int32_t* p, int dim, int n0, int n1, long long ng, int 
                    long long nv, const uint16_t* vcodes, unsigned int* vcount, unsigned int* vsum, int32_t* vidx,
                    void* vval, long long vcap, unsigned int* err, mc_result* res, hipStream_t s);
 
+// ---- batched stages (work lists over many fields) --------------------------
+// One field of a batched compress, as the stage kernels read it (a device
+// array of these, built by the batch layer).  The field's own workspace
+// (range partials, control block, per-call counters, per-tile counts, p)
+// belongs to the batch, so fields on one plan may run in the same launch.
+struct BItemC {
+    int cls;                          // 2 * (dtype == MC_F64) + (dim == 3)
+    int vec;                          // field 16-byte aligned (range loads)
+    int n0, n1, n2;
+    int nxs, nyb;                     // Lorenzo units: 63-column runs, row blocks (3-D)
+    unsigned nunits, nbl;             // Lorenzo units and their blocks (4 units per block)
+    unsigned nparts;                  // range blocks (partials)
+    unsigned knobs;                   // the plan's launch knobs (cache policy; tile order is launch order)
+    long long ng, nv, ntg, ntv, nsmall, nbflags, gcap, vcap;
+    GridGeom gg;
+    BoundParams bp;
+    const int32_t* vid;
+    const float* w;
+    const float* coords;
+    const void* x;
+    unsigned long long* partial;      // [3 * nparts]
+    RangeOut* cur;
+    DevBound* bnd;
+    unsigned* small;                  // err at 2, grid group sums from 16, vertex group sums after them
+    unsigned* gcount;                 // [ntg]
+    unsigned* vcount;                 // [ntv]
+    int32_t* p;                       // [ng]
+    uint16_t* gcodes;
+    int32_t* gidx;
+    int32_t* gdelta;
+    uint16_t* vcodes;
+    int32_t* vidx;
+    void* vval;
+    mc_result* res;
+    uint32_t* bflags;
+};
+// Lorenzo work units of a grid (63-column runs x row blocks x plane chunks in
+// 3-D, x row chunks in 2-D), as k_lorenzo3 / k_lorenzo and k_codes take them.
+void lorenzo_units(int dim, int n0, int n1, int n2, int* nxs, int* nyb, unsigned* nunits);
+// Stage launches of a batched compress: block ranges per field are given by
+// base tables (base[i] = first block of field i, base[n] = total blocks).
+hipError_t batch_range(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
+hipError_t batch_range_final(const BItemC* items, int n, hipStream_t s);
+hipError_t batch_resample(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
+hipError_t batch_codes(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
+hipError_t batch_scatter(const BItemC* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
+
+// One field of a batched vertex decode.
+struct BItemD {
+    int cls;                          // 2 * (dtype == MC_F64) + (dim == 3)
+    unsigned knobs;
+    long long nv, vcap;
+    GridGeom gg;
+    const float* coords;
+    const float* xh;                  // the field's decoded grid
+    const uint16_t* vcodes;
+    const int32_t* vidx;
+    const void* vval;
+    const mc_result* res;
+    void* xout;
+};
+hipError_t batch_vdecode(const BItemD* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
+
 // ---- decompression (k_decode.hip) -----------------------------------------
 // Launch-order knobs (results do not depend on them): bit k set = kernel k
 // takes its tiles in XCD-contiguous order (xcd_tile), clear = in launch

@@ -141,6 +141,7 @@ _SIGS = {
     "mc_model_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
     "mc_model_features": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int64, _P, _P]),
     "mc_batch_compress": (C.c_int, [_P, C.c_int32, _P]),
+    "mc_batch_graph_info": (C.c_int, [C.c_int32, _P, C.c_int32, _P, _P]),
     "mc_batch_release": (C.c_int, []),
     "mc_plan_get_tuning": (C.c_int, [_P, _P]),
     "mc_plan_set_tuning": (C.c_int, [_P, _P]),
@@ -723,10 +724,7 @@ class Model:
 # batching, profiling, entropy stage
 # ---------------------------------------------------------------------------
 
-def batch_compress(items):
-    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes[,
-    split_mode[, residual]]).  The first call with a given list captures a HIP graph;
-    later calls with the same plans, tensors and parameters replay it."""
+def _batch_items(items):
     arr = (McBatchItem * len(items))()
     for i, it in enumerate(items):
         plan, field, eb, mode, share, model, codes = it[:7]
@@ -739,12 +737,18 @@ def batch_compress(items):
                                  None if model is None else model.handle, _split_code(split),
                                  RESIDUAL_OPEN if resid == "open" else RESIDUAL_CLOSED)
         arr[i].codes = codes.struct
+    return arr
+
+
+def batch_compress(items):
+    """items: list of (plan, field, eb, eb_mode, grid_share, model, codes[,
+    split_mode[, residual]]).  The first call with a given list captures a HIP graph;
+    later calls with the same plans, tensors and parameters replay it."""
+    arr = _batch_items(items)
     _check(lib().mc_batch_compress(arr, len(items), _stream()), "mc_batch_compress")
 
 
-def batch_decompress(items):
-    """items: list of (plan, codes, model, out); graph captured and replayed
-    like batch_compress."""
+def _batch_ditems(items):
     arr = (McBatchDItem * len(items))()
     for i, (plan, codes, model, out) in enumerate(items):
         _require_cuda(out, "out")
@@ -753,7 +757,24 @@ def batch_decompress(items):
         arr[i].model = None if model is None else model.handle
         arr[i].d_out = out.data_ptr()
         arr[i].dtype = _dtype_code(out)
+    return arr
+
+
+def batch_decompress(items):
+    """items: list of (plan, codes, model, out); graph captured and replayed
+    like batch_compress."""
+    arr = _batch_ditems(items)
     _check(lib().mc_batch_decompress(arr, len(items), _stream()), "mc_batch_decompress")
+
+
+def batch_graph_info(items, decompress: bool = False) -> dict:
+    """The cached graph of this item list: fields on the work-list stage
+    launches and the graph's node count."""
+    arr = _batch_ditems(items) if decompress else _batch_items(items)
+    nb, nn = C.c_int32(), C.c_int64()
+    _check(lib().mc_batch_graph_info(1 if decompress else 0, arr, len(items), C.byref(nb), C.byref(nn)),
+           "mc_batch_graph_info")
+    return {"n_batched": nb.value, "n_nodes": nn.value}
 
 
 def batch_release():

@@ -241,3 +241,77 @@ def test_batch_grid_predictors(workload):
             b = M.decompress(items[i][0], ref)
             torch.cuda.synchronize()
             assert torch.equal(outs[i], b), (rep, i)
+
+
+def test_plain_items_take_the_work_list(workload):
+    """Plain Lorenzo items of both dimensions and value types, several per
+    mesh, go through the work-list stage launches (one launch per stage for
+    all of them: a handful of graph nodes instead of a chain per item), and
+    every item still equals its single call, over replays, both ways."""
+    meshes, grids, fields, plans, xs = workload
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
+    items = _items(fields, plans, xs, codes)
+    outs = [torch.empty_like(x) for x in xs]
+    ditems = [(plans[f["mesh"]], codes[i], None, outs[i]) for i, f in enumerate(fields)]
+    for rep in range(3):
+        for c, o in zip(codes, outs):
+            c.vert_codes.zero_()
+            o.fill_(3.0)
+        M.batch_compress(items)
+        M.batch_decompress(ditems)
+        torch.cuda.synchronize()
+        for i, f in enumerate(fields):
+            ref = M.compress(plans[f["mesh"]], xs[i], f["eb"], f["eb_mode"], f["split"])
+            same(codes[i].host(), ref.host())
+            b = M.decompress(plans[f["mesh"]], ref)
+            torch.cuda.synchronize()
+            assert torch.equal(outs[i].view(torch.uint8), b.view(torch.uint8)), (rep, i)
+    ic = M.batch_graph_info(items)
+    idc = M.batch_graph_info(ditems, decompress=True)
+    print(f"[batch] work list: compress {ic}, decompress {idc}")
+    assert ic["n_batched"] == len(items) and idc["n_batched"] == len(items)
+    assert ic["n_nodes"] <= 8            # five stage launches (plus capture bookkeeping)
+    kinds = {(m.dim, np.dtype(f["data"].dtype).itemsize) for f, m in ((f, meshes[f["mesh"]]) for f in fields)}
+    assert len(kinds) >= 2
+
+
+def test_batch_scale_005_every_field_against_the_oracle():
+    """The 12-mesh, 64-field batch at 5 % of its size (25K-1M vertices per
+    mesh, 2-D and 3-D, FP32 and FP64, eb 1e-3..1e-5): one batch compress and
+    one batch decompress, then every field's grid and vertex codes, outlier
+    lists and decoded values against the oracle, element by element."""
+    meshes, grids, fields = G.config_batch(seed=5, scale=0.05)
+    print(f"[batch] scale 0.05: {len(meshes)} meshes, nv {[m.n_vertices for m in meshes]}, {len(fields)} fields",
+          flush=True)
+    plans = [M.Plan(dev(m.coords), dev(m.cells), dims=g[:2] if g[2] == 1 else g) for m, g in zip(meshes, grids)]
+    xs = [dev(f["data"]) for f in fields]
+    codes = [M.Codes(plans[f["mesh"]], xs[i].dtype) for i, f in enumerate(fields)]
+    outs = [torch.empty_like(x) for x in xs]
+    items = _items(fields, plans, xs, codes)
+    M.batch_compress(items)
+    M.batch_decompress([(plans[f["mesh"]], codes[i], None, outs[i]) for i, f in enumerate(fields)])
+    torch.cuda.synchronize()
+    assert M.batch_graph_info(items)["n_batched"] == len(fields)
+    maps = {}
+    for i, f in enumerate(fields):
+        m = f["mesh"]
+        mesh = meshes[m]
+        g = grids[m][:2] if grids[m][2] == 1 else grids[m]
+        if m not in maps:
+            og = O.grid_from_dims(mesh.coords, g)
+            maps[m] = (og, O.locate(mesh.coords, mesh.cells, og, "raster", fill="nearest", fill_method="kdtree"))
+        og, om = maps[m]
+        oc = O.compress(mesh.coords, om, og, f["data"], f["eb"], True, f["split"])
+        h = codes[i].host()
+        assert h["result"]["status"] == 0
+        assert np.array_equal(h["grid_codes"], oc.grid.codes), i
+        assert np.array_equal(h["g_out_idx"], oc.grid.out_idx), i
+        assert np.array_equal(h["g_out_delta"], oc.grid.out_delta), i
+        assert np.array_equal(h["vert_codes"], oc.vert.codes), i
+        assert np.array_equal(h["v_out_idx"], oc.vert.out_idx), i
+        assert np.array_equal(h["v_out_val"].view(np.uint8), oc.vert.out_val.view(np.uint8)), i
+        xo = O.decompress(mesh.coords, og, oc.bound, oc.grid, oc.vert, f["data"].dtype)
+        assert np.array_equal(outs[i].cpu().numpy().view(np.uint8), xo.view(np.uint8)), i
+    print(f"[batch] scale 0.05: all {len(fields)} fields equal to the oracle", flush=True)
+    for p in plans:
+        p.destroy()
