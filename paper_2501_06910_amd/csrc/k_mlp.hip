@@ -56,6 +56,17 @@ __device__ __forceinline__ bf16x4 pack4(float a, float b, float c, float d)
     return r;
 }
 
+// ReLU of four BF16 values as packed signed 16-bit maxima with zero
+// (v_pk_max_i16, two values per instruction): a BF16 value is negative
+// exactly when its sign bit is set, i.e. when it is negative as an int16, so
+// max(v, 0) keeps positive values and gives +0 for the rest.  Rounding and
+// ReLU commute (rounding keeps the sign; -0 and +0 both become +0), so
+// relu_bf(pack4(x)) equals pack4(relu(x)) for every value that is not a NaN.
+__device__ __forceinline__ bf16x4 relu_bf(bf16x4 v)
+{
+    return __builtin_elementwise_max(v, (bf16x4){0, 0, 0, 0});
+}
+
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -418,12 +429,8 @@ __device__ __forceinline__ void hidden_layer_f(const bf16x8* wf, const float* b,
             for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma32(a, bin[nb][c], acc[nb]);
         }
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            float h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) h[i] = acc[nb][i] > 0.0f ? acc[nb][i] : 0.0f;
-            out[nb][mb] = pack4(h[0], h[1], h[2], h[3]);
-        }
+        for (int nb = 0; nb < 4; ++nb)
+            out[nb][mb] = relu_bf(pack4(acc[nb][0], acc[nb][1], acc[nb][2], acc[nb][3]));
     }
 }
 
