@@ -5,21 +5,16 @@
 // of a vertex: bf16((x1'[n] - g) * kappa) for the 4^D grid nodes around its
 // grid cell (indices clamped), then bf16(t_d - 0.5), zero padded to KPAD.
 //
-// Layout.  A wave owns 64 vertices (4 column blocks of 16).  Every layer is
-// computed transposed, H^T = W . X^T, with v_mfma_f32_16x16x16_bf16: A = a
-// 16x16 block of W (from LDS), B = 16 vertices x 16 inputs.  The output
-// fragment of one layer (lane l holds rows 4(l/16)..+3 of column l%16) is
-// exactly the B fragment the next layer needs, so activations never leave
-// registers in the forward pass.  Input fragments are built directly in that
-// layout: lane l computes inputs 4(l/16)+16kb+i of vertex l%16 of each block.
+// Layout.  In inference a wave owns 64 vertices (4 column blocks of 16).
+// Every layer is computed transposed, H^T = W . X^T, with
+// v_mfma_f32_16x16x32_bf16: A = a 16-row block of W (from the fragment
+// image in LDS), B = 16 vertices x 32 inputs.  The output fragment of one
+// layer (lane l holds rows 4(l/16)..+3 of column l%16) is exactly half of
+// the B fragment the next layer needs, so activations never leave registers
+// in the forward pass.  Input fragments are built directly in that layout:
+// lane l computes inputs 4(l/16)+16kb+i of vertex l%16 of each block.
 //
-// Training (one step): each wave takes 64 samples drawn with SplitMix64,
-// runs the forward pass, then backward: dZ = dH * [h > 0]; weight gradients
-// dW = dZ^T . H need both operands transposed, so dZ^T and H^T are staged in
-// LDS ([unit][sample], BF16) and read back as fragments; input gradients
-// dH = W^T . dZ use a transposed weight copy in LDS.  Each wave writes its
-// whole gradient to its own slot; a second kernel sums the slots in a fixed
-// order (deterministic) and applies Adam.
+// Training: see the block comment above stage_frag.
 #include "mc_dev.h"
 #include "mc_kernels.h"
 
@@ -99,46 +94,13 @@ template <int D> struct MlpShape {
     static constexpr int KB = KPAD / 16;
 };
 
-// Weights in LDS: bf16 W1[64][KPAD], W2[64][64], W3[64][64] (output-major),
-// optionally the transposes W2T, W3T; fp32 b1..b3, W4 (bf16 values), b4.
-template <int D, bool TRANSPOSED> struct LdsWeights {
-    unsigned short w1[HID * MlpShape<D>::KPAD];
-    unsigned short w2[HID * HID];
-    unsigned short w3[HID * HID];
-    unsigned short w2t[TRANSPOSED ? HID * HID : 1];
-    unsigned short w3t[TRANSPOSED ? HID * HID : 1];
-    float b1[HID], b2[HID], b3[HID], w4[HID];
-    float b4;
-};
-
-template <int D, bool TRANSPOSED>
-__device__ void load_weights(LdsWeights<D, TRANSPOSED>& s, const mck::MlpDev& m)
-{
-    constexpr int KPAD = MlpShape<D>::KPAD;
-    for (int i = threadIdx.x; i < HID * KPAD; i += blockDim.x) s.w1[i] = m.w1[i];
-    for (int i = threadIdx.x; i < HID * HID; i += blockDim.x) {
-        s.w2[i] = m.w2[i];
-        s.w3[i] = m.w3[i];
-        if (TRANSPOSED) {
-            const int r = i / HID, c = i % HID;
-            s.w2t[c * HID + r] = m.w2[i];
-            s.w3t[c * HID + r] = m.w3[i];
-        }
-    }
-    for (int i = threadIdx.x; i < HID; i += blockDim.x) {
-        s.b1[i] = m.b1[i];
-        s.b2[i] = m.b2[i];
-        s.b3[i] = m.b3[i];
-        s.w4[i] = bf2f(m.w4[i]);
-    }
-    if (threadIdx.x == 0) s.b4 = m.b4[0];
-    __syncthreads();
-}
-
-// Inference copy of the weights in LDS, fragment-major for the K = 32
-// instruction: the A fragment of row block mb and k pair c (16-blocks 2c
-// and 2c + 1) for lane l is entry (mb * KC + c) * 64 + l, so a wave reads
-// 1 KB of consecutive bytes per fragment (no bank conflicts).
+// Weights as MFMA A fragments for the K = 32 instruction ("fragment
+// image"): the fragment of row block mb and k pair c (16-blocks 2c and
+// 2c + 1) for lane l is entry (mb * KC + c) * 64 + l, so a wave reads 1 KB
+// of consecutive bytes per fragment (no LDS bank conflicts).  The image is
+// built once per model change in device memory and copied to LDS with
+// 16-byte loads.  LdsFrag is what inference needs; training also needs the
+// transposes of W2 and W3 (A operands of dH = W^T dZ).
 template <int D> struct LdsFrag {
     bf16x8 w1[4 * (MlpShape<D>::KB / 2) * 64];
     bf16x8 w2[8 * 64];
@@ -147,57 +109,92 @@ template <int D> struct LdsFrag {
     float b1[HID], b2[HID], b3[HID], w4[HID];
     float b4;
 };
+template <int D> struct FragImg {
+    LdsFrag<D> f;
+    bf16x8 w2t[8 * 64];
+    bf16x8 w3t[8 * 64];
+};
 
-__device__ __forceinline__ bf16x8 frag8_of(const unsigned short* w, int ld, int kpairs, int idx)
+// Short index of element (r, c) of a row-major matrix in its fragment
+// image with kpairs 32-wide column pairs: lane 16(c%16/4) + r%16 of entry
+// (r/16, c/32), slot 4((c/16)%2) + c%4.
+__device__ __forceinline__ int frag_pos(int r, int c, int kpairs)
 {
-    const int l = idx & 63, c = (idx >> 6) % kpairs, mb = (idx >> 6) / kpairs, g = l >> 4;
-    const unsigned short* row = w + (mb * 16 + (l & 15)) * ld;
-    typedef short s8 __attribute__((ext_vector_type(8)));
-    s8 r;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        r[i] = (short)row[(2 * c) * 16 + 4 * g + i];
-        r[4 + i] = (short)row[(2 * c + 1) * 16 + 4 * g + i];
-    }
-    return __builtin_bit_cast(bf16x8, r);
+    const int kb = c >> 4, within = c & 15;
+    const int lane = (within >> 2) * 16 + (r & 15);
+    return ((((r >> 4) * kpairs + (kb >> 1)) * 64 + lane) << 3) + ((kb & 1) << 2) + (within & 3);
+}
+// Short index of W4[u] in the head operand (row 0 of a 16 x 64 A operand).
+__device__ __forceinline__ int head_pos(int u)
+{
+    return (((u >> 5) * 64 + ((u & 15) >> 2) * 16) << 3) + (((u >> 4) & 1) << 2) + (u & 3);
 }
 
-template <int D>
-__device__ void load_frag(LdsFrag<D>& s, const mck::MlpDev& m)
+// Copies NBYTES (a multiple of 16) from global memory to LDS with NT
+// threads, all loads issued before the stores.
+template <int NBYTES, int NT>
+__device__ __forceinline__ void copy_to_lds(void* dst, const void* src)
 {
-    constexpr int KC = MlpShape<D>::KB / 2, KPAD = MlpShape<D>::KPAD;
-    for (int i = threadIdx.x; i < 4 * KC * 64; i += blockDim.x) s.w1[i] = frag8_of(m.w1, KPAD, KC, i);
-    for (int i = threadIdx.x; i < 8 * 64; i += blockDim.x) {
-        s.w2[i] = frag8_of(m.w2, HID, 2, i);
-        s.w3[i] = frag8_of(m.w3, HID, 2, i);
-    }
-    for (int i = threadIdx.x; i < HID; i += blockDim.x) {
-        s.b1[i] = m.b1[i];
-        s.b2[i] = m.b2[i];
-        s.b3[i] = m.b3[i];
-        s.w4[i] = bf2f(m.w4[i]);
-    }
-    for (int i = threadIdx.x; i < 2 * 64; i += blockDim.x) {
-        const int l = i & 63, c = i >> 6, g = l >> 4;
-        typedef short s8 __attribute__((ext_vector_type(8)));
-        s8 r;
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int N = NBYTES / 16, PER = (N + NT - 1) / NT;
+    static_assert(NBYTES % 16 == 0, "16-byte granules");
+    const u32x4* s = (const u32x4*)src;
+    u32x4* d = (u32x4*)dst;
+    u32x4 v[PER];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            r[k] = (l & 15) == 0 ? (short)m.w4[32 * c + 4 * g + k] : (short)0;
-            r[4 + k] = (l & 15) == 0 ? (short)m.w4[32 * c + 16 + 4 * g + k] : (short)0;
-        }
-        s.w4f[i] = __builtin_bit_cast(bf16x8, r);
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * NT + (int)threadIdx.x;
+        if (i < N) v[j] = s[i];
     }
-    if (threadIdx.x == 0) s.b4 = m.b4[0];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int i = j * NT + (int)threadIdx.x;
+        if (i < N) d[i] = v[j];
+    }
+}
+
+template <int D, int NT>
+__device__ __forceinline__ void load_frag(LdsFrag<D>& s, const mck::MlpDev& m)
+{
+    copy_to_lds<sizeof(LdsFrag<D>), NT>(&s, m.img);
     __syncthreads();
 }
 
-// A fragment: rows r0..r0+15 of a row-major bf16 matrix with leading
-// dimension ld, columns c0 + 4(l/16) .. +3 for lane l.
-__device__ __forceinline__ bf16x4 afrag(const unsigned short* w, int ld, int r0, int c0)
+// Builds the fragment image from the row-major BF16 weights and FP32
+// biases of a model (one thread per short of the image).
+template <int D>
+__global__ __launch_bounds__(256) void k_mlp_image(mck::MlpDev m, FragImg<D>* __restrict__ img)
 {
-    const int l = lane_id();
-    return *(const bf16x4*)(w + (r0 + (l & 15)) * ld + c0 + 4 * (l >> 4));
+    constexpr int KC = MlpShape<D>::KB / 2, KPAD = MlpShape<D>::KPAD;
+    unsigned short* w1 = (unsigned short*)img->f.w1;
+    unsigned short* w2 = (unsigned short*)img->f.w2;
+    unsigned short* w3 = (unsigned short*)img->f.w3;
+    unsigned short* w4f = (unsigned short*)img->f.w4f;
+    unsigned short* w2t = (unsigned short*)img->w2t;
+    unsigned short* w3t = (unsigned short*)img->w3t;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < HID * KPAD) {
+        const int r = i / KPAD, c = i % KPAD;
+        w1[frag_pos(r, c, KC)] = m.w1[i];
+    }
+    if (i < HID * HID) {
+        const int r = i >> 6, c = i & 63;
+        w2[frag_pos(r, c, 2)] = m.w2[i];
+        w3[frag_pos(r, c, 2)] = m.w3[i];
+        w2t[frag_pos(c, r, 2)] = m.w2[i];
+        w3t[frag_pos(c, r, 2)] = m.w3[i];
+    }
+    if (i < 2 * 64 * 8) {                    // head operand: W4 in row 0, zeros elsewhere
+        const int l = (i >> 3) & 63, c = i >> 9, slot = i & 7;
+        w4f[i] = (l & 15) == 0 ? m.w4[32 * c + 16 * (slot >> 2) + 4 * (l >> 4) + (slot & 3)] : (unsigned short)0;
+    }
+    if (i < HID) {
+        img->f.b1[i] = m.b1[i];
+        img->f.b2[i] = m.b2[i];
+        img->f.b3[i] = m.b3[i];
+        img->f.w4[i] = bf2f(m.w4[i]);
+    }
+    if (i == 0) img->f.b4 = m.b4[0];
 }
 
 // Geometry of one vertex: grid cell, in-cell offsets and g(x1').
@@ -370,37 +367,6 @@ __device__ __forceinline__ void build_inputs(bf16x4 (&zf)[4][MlpShape<D>::KB], c
     (void)valid_any;
 }
 
-// One hidden layer: out[mb][nb] = bf16(relu(W[mb-block] . in[.][nb] + b)).
-template <int KBLK>
-__device__ __forceinline__ void hidden_layer(const unsigned short* w, int ld, const float* b,
-                                             const bf16x4 (&in)[4][KBLK], bf16x4 (&out)[4][4], f32x4 (&pre)[4][4])
-{
-    const int g4 = 4 * (lane_id() >> 4);
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        f32x4 acc[4];
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < KBLK; ++kb) {
-            const bf16x4 a = afrag(w, ld, mb * 16, kb * 16);
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, in[nb][kb], acc[nb]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            float h[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float x = acc[nb][i] + b[mb * 16 + g4 + i];
-                h[i] = x > 0.0f ? x : 0.0f;
-            }
-            pre[mb][nb] = (f32x4){h[0], h[1], h[2], h[3]};
-            out[nb][mb] = pack4(h[0], h[1], h[2], h[3]);
-        }
-    }
-}
-
 // The same layer with the weights in fragment-major LDS and the K = 32
 // instruction (inference): KBLK 16-blocks of input, taken in pairs.
 template <int KBLK>
@@ -450,39 +416,6 @@ __device__ __forceinline__ void head_f(const bf16x8* w4f, float b4, const bf16x4
     }
 }
 
-// Head: rho of vertex nb*16 + l%16 for every nb, summed over the 64 units in
-// a fixed order (lane-local, then across the 4 row groups).
-__device__ __forceinline__ void head(const float* w4, float b4, const bf16x4 (&h3)[4][4], float (&rho)[4])
-{
-    const int g4 = 4 * (lane_id() >> 4);
-#pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        float s = 0.0f;
-#pragma unroll
-        for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) s = s + w4[mb * 16 + g4 + i] * bf2f((unsigned short)h3[nb][mb][i]);
-        s = s + __shfl_xor(s, 16, 64);
-        s = s + __shfl_xor(s, 32, 64);
-        rho[nb] = s + b4;
-    }
-}
-
-template <int D>
-__device__ __forceinline__ void forward(const LdsWeights<D, false>* sw0, const unsigned short* w1,
-                                        const unsigned short* w2, const unsigned short* w3, const float* b1,
-                                        const float* b2, const float* b3, const float* w4, float b4,
-                                        const bf16x4 (&zf)[4][MlpShape<D>::KB], bf16x4 (&h1)[4][4],
-                                        bf16x4 (&h2)[4][4], bf16x4 (&h3)[4][4], float (&rho)[4])
-{
-    f32x4 pre[4][4];
-    hidden_layer<MlpShape<D>::KB>(w1, MlpShape<D>::KPAD, b1, zf, h1, pre);
-    hidden_layer<4>(w2, HID, b2, h1, h2, pre);
-    hidden_layer<4>(w3, HID, b3, h2, h3, pre);
-    head(w4, b4, h3, rho);
-    (void)sw0;
-}
-
 template <int D>
 __device__ __forceinline__ void forward_f(const LdsFrag<D>& sw, const bf16x4 (&zf)[4][MlpShape<D>::KB],
                                           float (&rho)[4])
@@ -514,7 +447,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint32_t* __restrict__ only_blocks, int32_t* __restrict__ rho_q)
 {
     __shared__ LdsFrag<D> sw;
-    load_frag<D>(sw, m);
+    load_frag<D, 256>(sw, m);
     const long long ntiles = (nv + 63) / 64;
     const int l = lane_id();
     for (long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
@@ -561,7 +494,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward_z(mck::MlpDev m, const floa
                                                        float* __restrict__ out)
 {
     __shared__ LdsFrag<D> sw;
-    load_frag<D>(sw, m);
+    load_frag<D, 256>(sw, m);
     constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD;
     const long long ntiles = (batch + 63) / 64;
     const int l = lane_id(), g4 = 4 * (l >> 4);
@@ -655,65 +588,57 @@ template <int D> __device__ __forceinline__ ParamOffsets param_offsets()
     return o;
 }
 
-// Stages a D-layout fragment set (rows = units or inputs, cols = samples)
-// into LDS as bf16 [row][64 samples].
+// Training, one step of minibatch B:
+//  * k_mlp_sample draws the samples of several steps in one launch (a wave
+//    per 64 samples: SplitMix64 vertex, inputs as B fragments, target in
+//    code units), so no gather latency sits inside a step;
+//  * k_mlp_train: one workgroup of 8 waves per 64 samples.  Wave w takes
+//    column block nb = w % 4 (16 samples) and unit half mh = w / 4 (row
+//    blocks 2mh, 2mh + 1) of every layer; the halves of a layer's output
+//    meet in LDS as B fragments for the next layer.  Backward: dZ = dH *
+//    [h > 0]; dW = dZ^T . H with the samples as the K dimension (dZ^T and
+//    H^T staged [unit][sample] in LDS), dH = W^T . dZ from the transposed
+//    weight fragments.  Each workgroup writes its gradient to its own slot;
+//  * k_mlp_adam sums the slots in a fixed order (the same gradient on every
+//    run), applies Adam to the FP32 master parameters and writes the BF16
+//    weights both row-major and into the fragment image.
+
+// LDS row stride of the [row][sample] staging buffers: 72 shorts keeps the
+// 16 rows of a fragment read on different banks.
+#define SP 72
+
+// Stages a fragment (rows r0 + 4(l/16) + i, sample column nb*16 + l%16)
+// into a [row][sample] buffer.
 __device__ __forceinline__ void stage_frag(unsigned short* buf, int r0, const bf16x4& f, int nb)
 {
     const int l = lane_id(), g4 = 4 * (l >> 4), col = nb * 16 + (l & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) buf[(r0 + g4 + i) * 64 + col] = (unsigned short)f[i];
+    for (int i = 0; i < 4; ++i) buf[(r0 + g4 + i) * SP + col] = (unsigned short)f[i];
 }
 
-// dW[rows of A][rows of B] = sum over the 64 samples of A^T B (both staged
-// [row][sample]); writes the result to grad (row-major, ldg columns, only
-// columns < ncols).
-template <int NBB>
-__device__ __forceinline__ void weight_grad(const unsigned short* a, const unsigned short* b, float* grad, int ldg,
-                                            int ncols)
+// K = 32 operand of rows r0..r0+15 of a [row][sample] buffer, samples
+// 32c .. 32c+31 (the same slot order as cat8 of two 16-wide fragments).
+__device__ __forceinline__ bf16x8 staged8(const unsigned short* buf, int r0, int c)
 {
     const int l = lane_id(), g4 = 4 * (l >> 4);
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < NBB; ++nb) {
-            f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < 4; ++kb) {
-                const bf16x4 fa = *(const bf16x4*)(a + (mb * 16 + (l & 15)) * 64 + kb * 16 + g4);
-                const bf16x4 fb = *(const bf16x4*)(b + (nb * 16 + (l & 15)) * 64 + kb * 16 + g4);
-                acc = mfma16(fa, fb, acc);
-            }
-            const int col = nb * 16 + (l & 15);
-            if (col < ncols)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) grad[(mb * 16 + g4 + i) * ldg + col] = acc[i];
-        }
+    const unsigned short* row = buf + (r0 + (l & 15)) * SP + 32 * c + g4;
+    return cat8(*(const bf16x4*)row, *(const bf16x4*)(row + 16));
 }
 
-// dH = W^T . dZ, then dZ_prev = dH * [h > 0].  The A fragment of W^T
-// (rows = inputs k, columns = units u) is gathered from the row-major W.
-__device__ __forceinline__ void input_grad(const unsigned short* w, const bf16x4 (&dz)[4][4], const bf16x4 (&h)[4][4],
-                                           f32x4 (&dzp)[4][4])
+// One 16 x 16 tile of dW = A^T B over the 64 staged samples: rows of A
+// (units) ra..ra+15, rows of B cb..cb+15; written to grad[u * ldg + k] for
+// k < ncols.
+__device__ __forceinline__ void weight_tile(const unsigned short* a, int ra, const unsigned short* b, int cb,
+                                            float* grad, int ldg, int ncols)
 {
     const int l = lane_id(), g4 = 4 * (l >> 4);
+    f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+    acc = mfma32(staged8(a, ra, 0), staged8(b, cb, 0), acc);
+    acc = mfma32(staged8(a, ra, 1), staged8(b, cb, 1), acc);
+    const int k = cb + (l & 15);
+    if (k < ncols)
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-        f32x4 acc[4];
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 4; ++kb) {
-            bf16x4 a;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) a[i] = (short)w[(kb * 16 + g4 + i) * HID + mb * 16 + (l & 15)];
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) acc[nb] = mfma16(a, dz[nb][kb], acc[nb]);
-        }
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dzp[mb][nb][i] = bf2f((unsigned short)h[nb][mb][i]) > 0.0f ? acc[nb][i] : 0.0f;
-    }
+        for (int i = 0; i < 4; ++i) grad[(ra + g4 + i) * ldg + k] = acc[i];
 }
 
 // Sum over the 16 lanes that share l/16 (one row group), fixed order.
@@ -726,193 +651,324 @@ __device__ __forceinline__ float group16_sum(float s)
     return s;
 }
 
-// Bias gradient of one layer from its dZ (D-layout [mb][nb][i]): rows
-// mb*16 + 4(l/16) + i, summed over the 64 samples.
-__device__ __forceinline__ void bias_grad(const f32x4 (&dz)[4][4], float* grad)
+// Samples of steps [t0, t0 + nsteps): inputs as B fragments
+// zfr[((step * nparts + part) * 4 + nb) * KB + kb][lane] and targets
+// y[step * batch + s], s = part * 64 + lane (one wave per 64 samples).
+template <int D>
+__global__ __launch_bounds__(256) void k_mlp_sample(float kappa, const float* __restrict__ coords, long long nv,
+                                                    GridGeom gg, const float* __restrict__ xh,
+                                                    const mc_result* __restrict__ res, const void* __restrict__ xfield,
+                                                    int dtype, long long batch, unsigned long long seed, long long t0,
+                                                    long long nsteps, bf16x4* __restrict__ zfr, float* __restrict__ y)
 {
-    const int l = lane_id(), g4 = 4 * (l >> 4);
+    constexpr int KB = MlpShape<D>::KB;
+    const long long nparts = batch / 64;
+    const long long wv = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv >= nsteps * nparts) return;
+    const long long st = wv / nparts, part = wv % nparts;
+    const int l = lane_id();
+    const long long s = part * 64 + l;
+    const unsigned long long r = splitmix64_dev(seed, (unsigned long long)((t0 + st) * batch + s));
+    const long long v = (long long)(((r >> 32) * (unsigned long long)nv) >> 32);
+    const VGeom mine = vertex_geom<D>(coords, nv, v, gg, xh);
+    bf16x4 zf[4][KB];
+    const bool valid[4] = {true, true, true, true};
+    build_inputs<D>(zf, mine, true, gg, xh, kappa, valid);
+    bf16x4* out = zfr + (st * nparts + part) * 4 * KB * 64;
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            float s = ((dz[mb][0][i] + dz[mb][1][i]) + dz[mb][2][i]) + dz[mb][3][i];
-            s = group16_sum(s);
-            if ((l & 15) == 0) grad[mb * 16 + g4 + i] = s;
-        }
+        for (int kb = 0; kb < KB; ++kb) out[(nb * KB + kb) * 64 + l] = zf[nb][kb];
+    const double inv2 = 1.0 / (2.0 * res->tau2);
+    const double xv = dtype == MC_F64 ? ((const double*)xfield)[v] : (double)((const float*)xfield)[v];
+    y[st * batch + s] = (float)((xv - (double)mine.g) * inv2);
 }
 
+// Given inputs z[batch][KPAD] (BF16 values) and targets -> the fragment
+// layout of k_mlp_sample, zero padded to whole 64-sample parts.
 template <int D>
-__global__ __launch_bounds__(64) void k_mlp_train(mck::MlpDev m, const float* __restrict__ coords, long long nv,
-                                                   GridGeom gg, const float* __restrict__ xh,
-                                                   const mc_result* __restrict__ res, const void* __restrict__ xfield,
-                                                   int dtype, const float* __restrict__ zin,
-                                                   const float* __restrict__ yin, long long batch,
-                                                   unsigned long long seed, long long step,
-                                                   float* __restrict__ grad_part, float* __restrict__ loss_part)
+__global__ __launch_bounds__(256) void k_mlp_zfrag(const float* __restrict__ z, const float* __restrict__ yin,
+                                                   long long batch, bf16x4* __restrict__ zfr, float* __restrict__ y)
 {
-    constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD, KIN = MlpShape<D>::KIN;
-    // one wave per workgroup: weights plus two staging buffers stay well
-    // inside 64 KiB of LDS
-    __shared__ LdsWeights<D, false> sw;
-    constexpr int BROWS = KPAD > HID ? KPAD : HID;   // H^T (64 rows) or Z^T (KPAD rows)
-    __shared__ unsigned short sbuf[HID * 64 + BROWS * 64];
-    load_weights<D, false>(sw, m);
+    constexpr int KB = MlpShape<D>::KB, KPAD = MlpShape<D>::KPAD;
+    const long long wv = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wv * 64 >= batch) return;
     const int l = lane_id(), g4 = 4 * (l >> 4);
-    const long long part = blockIdx.x;                             // one wave = 64 samples
-    const bool active = part * 64 < batch;
-    unsigned short* bufA = sbuf;                 // dZ^T  [64 units][64 samples]
-    unsigned short* bufB = sbuf + HID * 64;      // H^T or Z^T [BROWS][64 samples]
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const long long sn = wv * 64 + nb * 16 + (l & 15);
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+            float f[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) f[i] = sn < batch ? z[sn * KPAD + kb * 16 + g4 + i] : 0.0f;
+            zfr[(wv * 4 + nb) * KB * 64 + kb * 64 + l] = pack4(f[0], f[1], f[2], f[3]);
+        }
+    }
+    const long long s = wv * 64 + l;
+    y[s] = s < batch ? yin[s] : 0.0f;
+}
+
+template <int D> struct TrainLds {
+    FragImg<D> w;
+    bf16x4 x[2][4][4][64];                          // exchange [buffer][nb][mb][lane]
+    unsigned short h1s[HID * SP], h2s[HID * SP];    // H1^T, H2^T [unit][sample]
+    unsigned short zs[MlpShape<D>::KPAD * SP];      // Z^T [input][sample]
+    unsigned short dzs[2][HID * SP];                // dZ^T of the current layers
+    float part[4][4][HID];                          // dW4, db3, db2, db1 over 16 samples: [quantity][nb][unit]
+    float dsum[4], loss[4];                         // db4 and squared error over 16 samples
+};
+
+template <int D>
+__global__ __launch_bounds__(512) void k_mlp_train(const FragImg<D>* __restrict__ img,
+                                                   const bf16x4* __restrict__ zfr, const float* __restrict__ y,
+                                                   long long batch, float* __restrict__ grad_part,
+                                                   float* __restrict__ loss_part)
+{
+    constexpr int KB = MlpShape<D>::KB, KC = KB / 2, KIN = MlpShape<D>::KIN;
+    __shared__ TrainLds<D> S;
+    const int l = lane_id(), g4 = 4 * (l >> 4), w = threadIdx.x >> 6;
+    const int nb = w & 3, mh = w >> 2;
+    const long long part = blockIdx.x;
     const ParamOffsets po = param_offsets<D>();
     float* grad = grad_part + part * po.n;
+    const FragImg<D>& W = S.w;
 
-    // ---- inputs and targets ----
-    bf16x4 zf[4][KB];
-    float y = 0.0f;
-    const long long s = part * 64 + l;
-    if (zin) {
+    // inputs of the wave's 16 samples (issued before the weight copy)
+    bf16x4 zf[KB];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const long long sn = part * 64 + nb * 16 + (l & 15);
+    for (int kb = 0; kb < KB; ++kb) zf[kb] = zfr[((part * 4 + nb) * KB + kb) * 64 + l];
+    const long long s = part * 64 + nb * 16 + (l & 15);
+    const bool ok = s < batch;
+    const float yv = y[s];
+    copy_to_lds<sizeof(FragImg<D>), 512>(&S.w, img);
+    if (mh == 0)
 #pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                float f[4];
+        for (int kb = 0; kb < KB; ++kb) stage_frag(S.zs, kb * 16, zf[kb], nb);
+    __syncthreads();
+
+    // ---- forward: the wave's two row blocks of each layer ----
+    bf16x4 h1m[2], h2m[2], h3m[2];
+    {
+        bf16x8 bin[KC];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) f[i] = (active && sn < batch) ? zin[sn * KPAD + kb * 16 + g4 + i] : 0.0f;
-                zf[nb][kb] = pack4(f[0], f[1], f[2], f[3]);
-            }
+        for (int c = 0; c < KC; ++c) bin[c] = cat8(zf[2 * c], zf[2 * c + 1]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = 2 * mh + j;
+            f32x4 acc = (f32x4){W.f.b1[mb * 16 + g4], W.f.b1[mb * 16 + g4 + 1], W.f.b1[mb * 16 + g4 + 2],
+                                W.f.b1[mb * 16 + g4 + 3]};
+#pragma unroll
+            for (int c = 0; c < KC; ++c) acc = mfma32(W.f.w1[(mb * KC + c) * 64 + l], bin[c], acc);
+            h1m[j] = relu_bf(pack4(acc[0], acc[1], acc[2], acc[3]));
+            S.x[0][nb][mb][l] = h1m[j];
+            stage_frag(S.h1s, mb * 16, h1m[j], nb);
         }
-        y = (active && s < batch) ? yin[s] : 0.0f;
-    } else {
-        const unsigned long long r = splitmix64_dev(seed, (unsigned long long)(step * batch + s));
-        const long long v = (long long)(((r >> 32) * (unsigned long long)nv) >> 32);
-        const VGeom mine = vertex_geom<D>(coords, nv, v, gg, xh);
-        bool valid[4] = {active, active, active, active};
-        build_inputs<D>(zf, mine, true, gg, xh, m.kappa, valid);
-        const double inv2 = 1.0 / (2.0 * res->tau2);
-        const double xv = dtype == MC_F64 ? ((const double*)xfield)[v] : (double)((const float*)xfield)[v];
-        y = (float)((xv - (double)mine.g) * inv2);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {
+        const bf16x8* wf = layer == 0 ? W.f.w2 : W.f.w3;
+        const float* b = layer == 0 ? W.f.b2 : W.f.b3;
+        const bf16x8 bin0 = cat8(S.x[layer][nb][0][l], S.x[layer][nb][1][l]);
+        const bf16x8 bin1 = cat8(S.x[layer][nb][2][l], S.x[layer][nb][3][l]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = 2 * mh + j;
+            f32x4 acc = (f32x4){b[mb * 16 + g4], b[mb * 16 + g4 + 1], b[mb * 16 + g4 + 2], b[mb * 16 + g4 + 3]};
+            acc = mfma32(wf[(mb * 2 + 0) * 64 + l], bin0, acc);
+            acc = mfma32(wf[(mb * 2 + 1) * 64 + l], bin1, acc);
+            const bf16x4 h = relu_bf(pack4(acc[0], acc[1], acc[2], acc[3]));
+            if (layer == 0) {
+                h2m[j] = h;
+                stage_frag(S.h2s, mb * 16, h, nb);
+            } else {
+                h3m[j] = h;
+            }
+            S.x[1 - layer][nb][mb][l] = h;
+        }
+        __syncthreads();
     }
 
-    // ---- forward ----
-    bf16x4 h1[4][4], h2[4][4], h3[4][4];
-    float rho[4];
-    forward<D>(nullptr, sw.w1, sw.w2, sw.w3, sw.b1, sw.b2, sw.b3, sw.w4, sw.b4, zf, h1, h2, h3, rho);
-    float r = rho[0];
-    if ((l >> 4) == 1) r = rho[1];
-    if ((l >> 4) == 2) r = rho[2];
-    if ((l >> 4) == 3) r = rho[3];
-    const bool mine_ok = active && s < batch;
-    const float e = mine_ok ? r - y : 0.0f;
-    const float dr_mine = mine_ok ? 2.0f * e / (float)batch : 0.0f;
-    const float lsum = wave_sum(e * e);
-
-    // dr of vertex nb*16 + l%16
-    float dr[4];
+    // ---- head, loss and dZ3 ----
+    float dr;
+    {
+        f32x4 acc = (f32x4){W.f.b4, W.f.b4, W.f.b4, W.f.b4};
+        acc = mfma32(W.f.w4f[l], cat8(S.x[0][nb][0][l], S.x[0][nb][1][l]), acc);
+        acc = mfma32(W.f.w4f[64 + l], cat8(S.x[0][nb][2][l], S.x[0][nb][3][l]), acc);
+        const float rho = __shfl(acc[0], l & 15, 64);      // sample l%16 of the block, in every row group
+        const float e = ok ? rho - yv : 0.0f;
+        dr = ok ? 2.0f * e / (float)batch : 0.0f;
+        const float se = group16_sum(e * e), sd = group16_sum(dr);
+        if (mh == 0 && l == 0) {
+            S.loss[nb] = se;
+            S.dsum[nb] = sd;
+        }
+    }
+    f32x4 dz[2];
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) dr[nb] = __shfl(dr_mine, nb * 16 + (l & 15), 64);
-
-    // ---- head gradients and dZ3 ----
-    f32x4 dz[4][4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int j = 0; j < 2; ++j) {
+        const int mb = 2 * mh + j;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int u = mb * 16 + g4 + i;
-            float gw = 0.0f;
-#pragma unroll
-            for (int nb = 0; nb < 4; ++nb) {
-                const float h = bf2f((unsigned short)h3[nb][mb][i]);
-                gw = gw + dr[nb] * h;
-                dz[mb][nb][i] = h > 0.0f ? sw.w4[u] * dr[nb] : 0.0f;
+            const float h = bf2f((unsigned short)h3m[j][i]);
+            dz[j][i] = h > 0.0f ? W.f.w4[u] * dr : 0.0f;
+            const float gw4 = group16_sum(dr * h), gb3 = group16_sum(dz[j][i]);
+            if ((l & 15) == 0) {
+                S.part[0][nb][u] = gw4;
+                S.part[1][nb][u] = gb3;
             }
-            gw = group16_sum(gw);
-            if ((l & 15) == 0 && active) grad[po.w4 + u] = gw;
         }
-    {
-        // dr[nb] is the same in the 4 row groups: sum one group's 16 lanes
-        float sb = (((dr[0] + dr[1]) + dr[2]) + dr[3]);
-        sb = group16_sum(sb);
-        if (l == 0 && active) {
-            grad[po.b4] = sb;
-            loss_part[part] = lsum;
-        }
+        const bf16x4 f = pack4(dz[j][0], dz[j][1], dz[j][2], dz[j][3]);
+        stage_frag(S.dzs[0], mb * 16, f, nb);
+        S.x[1][nb][mb][l] = f;           // x[1] (H2) was last read before the previous barrier
     }
-    if (active) bias_grad(dz, grad + po.b3);
+    __syncthreads();
 
-    // ---- layer 3: dW3 = dZ3^T . H2, dZ2 = (W3^T dZ3) * [h2 > 0] ----
-    bf16x4 dzf[4][4];
+    // ---- layers 3 and 2: dW = dZ^T H, dZ_prev = (W^T dZ) * [h_prev > 0] ----
 #pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
+    for (int layer = 0; layer < 2; ++layer) {
+        const unsigned short* dzcur = S.dzs[layer];
+        const unsigned short* hprev = layer == 0 ? S.h2s : S.h1s;
+        float* gw = grad + (layer == 0 ? po.w3 : po.w2);
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            dzf[nb][mb] = pack4(dz[mb][nb][0], dz[mb][nb][1], dz[mb][nb][2], dz[mb][nb][3]);
-            stage_frag(bufA, mb * 16, dzf[nb][mb], nb);
-            stage_frag(bufB, mb * 16, h2[nb][mb], nb);
+        for (int j = 0; j < 2; ++j) {
+            const int t = 2 * w + j;                       // 16 tiles over the 8 waves
+            weight_tile(dzcur, (t >> 2) * 16, hprev, (t & 3) * 16, gw, HID, HID);
         }
-    __syncthreads();
-    if (active) weight_grad<4>(bufA, bufB, grad + po.w3, HID, HID);
-    input_grad(sw.w3, dzf, h2, dz);
-    __syncthreads();
-    if (active) bias_grad(dz, grad + po.b2);
+        const bf16x8* wt = layer == 0 ? W.w3t : W.w2t;
+        const int xin = 1 - layer, xout = layer;          // dZ3 in x[1] -> dZ2 in x[0]
+        const bf16x8 bin0 = cat8(S.x[xin][nb][0][l], S.x[xin][nb][1][l]);
+        const bf16x8 bin1 = cat8(S.x[xin][nb][2][l], S.x[xin][nb][3][l]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int mb = 2 * mh + j;
+            f32x4 acc = (f32x4){0.f, 0.f, 0.f, 0.f};
+            acc = mfma32(wt[(mb * 2 + 0) * 64 + l], bin0, acc);
+            acc = mfma32(wt[(mb * 2 + 1) * 64 + l], bin1, acc);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = mb * 16 + g4 + i;
+                const bf16x4 hp = layer == 0 ? h2m[j] : h1m[j];
+                dz[j][i] = bf2f((unsigned short)hp[i]) > 0.0f ? acc[i] : 0.0f;
+                const float gb = group16_sum(dz[j][i]);
+                if ((l & 15) == 0) S.part[2 + layer][nb][u] = gb;
+            }
+            const bf16x4 f = pack4(dz[j][0], dz[j][1], dz[j][2], dz[j][3]);
+            stage_frag(S.dzs[1 - layer], mb * 16, f, nb);   // dzs[1 - layer] was last read two barriers ago
+            if (layer == 0) S.x[xout][nb][mb][l] = f;
+        }
+        __syncthreads();
+    }
 
-    // ---- layer 2 ----
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            dzf[nb][mb] = pack4(dz[mb][nb][0], dz[mb][nb][1], dz[mb][nb][2], dz[mb][nb][3]);
-            stage_frag(bufA, mb * 16, dzf[nb][mb], nb);
-            stage_frag(bufB, mb * 16, h1[nb][mb], nb);
-        }
-    __syncthreads();
-    if (active) weight_grad<4>(bufA, bufB, grad + po.w2, HID, HID);
-    input_grad(sw.w2, dzf, h1, dz);
-    __syncthreads();
-    if (active) bias_grad(dz, grad + po.b1);
-
-    // ---- layer 1: dW1 = dZ1^T . Z ----
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            const bf16x4 f = pack4(dz[mb][nb][0], dz[mb][nb][1], dz[mb][nb][2], dz[mb][nb][3]);
-            stage_frag(bufA, mb * 16, f, nb);
-        }
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb)
-#pragma unroll
-        for (int nb = 0; nb < 4; ++nb) stage_frag(bufB, kb * 16, zf[nb][kb], nb);
-    __syncthreads();
-    if (active) weight_grad<KB>(bufA, bufB, grad + po.w1, KIN, KIN);
+    // ---- layer 1: dW1 = dZ1^T Z over the KPAD inputs (columns < KIN kept) ----
+    for (int t = w; t < 4 * KB; t += 8) weight_tile(S.dzs[0], (t / KB) * 16, S.zs, (t % KB) * 16, grad + po.w1, KIN, KIN);
+    // biases, W4 and the loss: the four 16-sample sums in a fixed order
+    if (w < 4) {
+        const float (&p)[4][HID] = S.part[w];
+        const float v = ((p[0][l] + p[1][l]) + p[2][l]) + p[3][l];
+        const int off = w == 0 ? po.w4 : (w == 1 ? po.b3 : (w == 2 ? po.b2 : po.b1));
+        grad[off + l] = v;
+    } else if (w == 4 && l == 0) {
+        grad[po.b4] = ((S.dsum[0] + S.dsum[1]) + S.dsum[2]) + S.dsum[3];
+        loss_part[part] = ((S.loss[0] + S.loss[1]) + S.loss[2]) + S.loss[3];
+    }
 }
 
-// Sums the per-wave gradients in a fixed order; optionally one Adam step on
-// the FP32 master parameters.
-__global__ __launch_bounds__(256) void k_mlp_reduce_adam(int np, int nparts, const float* __restrict__ grad_part,
-                                                         const float* __restrict__ loss_part, float* __restrict__ grad,
-                                                         float* __restrict__ loss_out, float* __restrict__ params,
-                                                         float* __restrict__ mom, float* __restrict__ vel, float lr,
-                                                         float bc1, float bc2, int apply, float inv_batch)
+// Position of parameter k in the row-major device model and the fragment
+// image: writes the BF16 weight (or FP32 bias) of value p.
+template <int D>
+__device__ __forceinline__ void store_param(int k, float p, const ParamOffsets& o, uint16_t* w1, uint16_t* w2,
+                                            uint16_t* w3, uint16_t* w4, float* b1, float* b2, float* b3, float* b4,
+                                            FragImg<D>* img)
 {
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k == 0) {
+    constexpr int KIN = MlpShape<D>::KIN, KPAD = MlpShape<D>::KPAD, KC = MlpShape<D>::KB / 2;
+    const unsigned short h = f2bf(p);
+    if (k < o.b1) {
+        const int u = k / KIN, c = k % KIN;
+        w1[u * KPAD + c] = h;
+        ((unsigned short*)img->f.w1)[frag_pos(u, c, KC)] = h;
+    } else if (k < o.w2) {
+        b1[k - o.b1] = p;
+        img->f.b1[k - o.b1] = p;
+    } else if (k < o.b2) {
+        const int i = k - o.w2, u = i >> 6, c = i & 63;
+        w2[i] = h;
+        ((unsigned short*)img->f.w2)[frag_pos(u, c, 2)] = h;
+        ((unsigned short*)img->w2t)[frag_pos(c, u, 2)] = h;
+    } else if (k < o.w3) {
+        b2[k - o.b2] = p;
+        img->f.b2[k - o.b2] = p;
+    } else if (k < o.b3) {
+        const int i = k - o.w3, u = i >> 6, c = i & 63;
+        w3[i] = h;
+        ((unsigned short*)img->f.w3)[frag_pos(u, c, 2)] = h;
+        ((unsigned short*)img->w3t)[frag_pos(c, u, 2)] = h;
+    } else if (k < o.w4) {
+        b3[k - o.b3] = p;
+        img->f.b3[k - o.b3] = p;
+    } else if (k < o.b4) {
+        const int u = k - o.w4;
+        w4[u] = h;
+        ((unsigned short*)img->f.w4f)[head_pos(u)] = h;
+        img->f.w4[u] = bf2f(h);
+    } else {
+        b4[0] = p;
+        img->f.b4 = p;
+    }
+}
+
+// Sums the per-workgroup gradient slots in a fixed order (8 waves take
+// consecutive slot ranges, 8 running sums each, combined in a fixed tree);
+// optionally one Adam step on the FP32 master parameters, whose new values
+// go straight into the device model and its fragment image.
+template <int D>
+__global__ __launch_bounds__(512) void k_mlp_adam(int nparts, const float* __restrict__ grad_part,
+                                                  const float* __restrict__ loss_part, float* __restrict__ grad,
+                                                  float* __restrict__ loss_out, float inv_batch,
+                                                  float* __restrict__ params, float* __restrict__ mom,
+                                                  float* __restrict__ vel, float lr, float bc1, float bc2, int apply,
+                                                  mck::MlpDev md, FragImg<D>* __restrict__ img)
+{
+    __shared__ float red[8][64];
+    const ParamOffsets o = param_offsets<D>();
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + l;
+    const int p0 = (int)((long long)w * nparts / 8), p1 = (int)((long long)(w + 1) * nparts / 8);
+    float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (k < o.n) {
+        int p = p0;
+        for (; p + 8 <= p1; p += 8)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) a[j] = a[j] + grad_part[(long long)(p + j) * o.n + k];
+#pragma unroll
+        for (int j = 0; j < 7; ++j)
+            if (p + j < p1) a[j] = a[j] + grad_part[(long long)(p + j) * o.n + k];
+    }
+    red[w][l] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    if (blockIdx.x == 0 && w == 1) {
         float ls = 0.0f;
-        for (int p = 0; p < nparts; ++p) ls = ls + loss_part[p];
-        *loss_out = ls * inv_batch;
+        for (int p = l; p < nparts; p += 64) ls = ls + loss_part[p];
+        ls = wave_sum(ls);
+        if (l == 0) *loss_out = ls * inv_batch;
     }
-    if (k >= np) return;
-    float g = 0.0f;
-    for (int p = 0; p < nparts; ++p) g = g + grad_part[(long long)p * np + k];
-    grad[k] = g;
-    if (apply) {
-        const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-        const float mk = b1 * mom[k] + (1.0f - b1) * g;
-        const float vk = b2 * vel[k] + (1.0f - b2) * (g * g);
-        mom[k] = mk;
-        vel[k] = vk;
-        const float mh = mk / bc1, vh = vk / bc2;
-        params[k] = params[k] - lr * mh / (sqrtf(vh) + eps);
-    }
+    if (w != 0 || k >= o.n) return;
+    const float g = (((red[0][l] + red[1][l]) + (red[2][l] + red[3][l])) +
+                     ((red[4][l] + red[5][l]) + (red[6][l] + red[7][l])));
+    if (grad) grad[k] = g;
+    if (!apply) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float mk = b1 * mom[k] + (1.0f - b1) * g;
+    const float vk = b2 * vel[k] + (1.0f - b2) * (g * g);
+    mom[k] = mk;
+    vel[k] = vk;
+    const float mh = mk / bc1, vh = vk / bc2;
+    const float pk = params[k] - lr * mh / (sqrtf(vh) + eps);
+    params[k] = pk;
+    store_param<D>(k, pk, o, (uint16_t*)md.w1, (uint16_t*)md.w2, (uint16_t*)md.w3, (uint16_t*)md.w4, (float*)md.b1,
+                   (float*)md.b2, (float*)md.b3, (float*)md.b4, img);
 }
 
 // Master FP32 parameters -> the device model (bf16 weights, fp32 biases).
@@ -1007,32 +1063,80 @@ hipError_t mlp_feature_sumsq(const float* coords, long long nv, GridGeom gg, con
     return hipGetLastError();
 }
 
-hipError_t train_step_grad(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
-                           const mc_result* res, const float* z_given, const float* y_given, const void* x, int dtype,
-                           long long batch, unsigned long long seed, long long step, float* grad_part,
-                           float* loss_part, int nparts, hipStream_t s)
+size_t mlp_image_bytes(int dim) { return dim == 2 ? sizeof(FragImg<2>) : sizeof(FragImg<3>); }
+
+hipError_t mlp_image(const MlpDev& m, hipStream_t s)
 {
-    ProfScope ps("k_mlp_train", s);
-    dim3 grid((unsigned)nparts);
+    const int n = 64 * 96;
     if (m.dim == 2)
-        hipLaunchKernelGGL(k_mlp_train<2>, grid, dim3(64), 0, s, m, coords, nv, gg, xh, res, x, dtype, z_given,
-                           y_given, batch, seed, step, grad_part, loss_part);
+        hipLaunchKernelGGL(k_mlp_image<2>, dim3((n + 255) / 256), dim3(256), 0, s, m, (FragImg<2>*)m.img);
     else
-        hipLaunchKernelGGL(k_mlp_train<3>, grid, dim3(64), 0, s, m, coords, nv, gg, xh, res, x, dtype, z_given,
-                           y_given, batch, seed, step, grad_part, loss_part);
+        hipLaunchKernelGGL(k_mlp_image<3>, dim3((n + 255) / 256), dim3(256), 0, s, m, (FragImg<3>*)m.img);
     return hipGetLastError();
 }
 
-hipError_t train_reduce_adam(int nparams, int nparts, const float* grad_part, const float* loss_part, float* grad,
-                             float* loss_out, float* params, float* m, float* v, long long t, float lr, int apply,
-                             long long batch, hipStream_t s)
+size_t train_sample_bytes(int dim, long long batch)
+{
+    const long long kb = dim == 2 ? MlpShape<2>::KB : MlpShape<3>::KB;
+    return (size_t)((batch + 63) / 64) * 4 * kb * 64 * 8;
+}
+
+hipError_t train_sample(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                        const mc_result* res, const void* x, int dtype, long long batch, unsigned long long seed,
+                        long long t0, long long nsteps, void* zfr, float* y, hipStream_t s)
+{
+    ProfScope ps("k_mlp_sample", s);
+    const long long waves = nsteps * (batch / 64);
+    dim3 grid((unsigned)((waves + 3) / 4));
+    if (m.dim == 2)
+        hipLaunchKernelGGL(k_mlp_sample<2>, grid, dim3(256), 0, s, m.kappa, coords, nv, gg, xh, res, x, dtype, batch,
+                           seed, t0, nsteps, (bf16x4*)zfr, y);
+    else
+        hipLaunchKernelGGL(k_mlp_sample<3>, grid, dim3(256), 0, s, m.kappa, coords, nv, gg, xh, res, x, dtype, batch,
+                           seed, t0, nsteps, (bf16x4*)zfr, y);
+    return hipGetLastError();
+}
+
+hipError_t train_zfrag(int dim, const float* z, const float* y, long long batch, void* zfr, float* ypad,
+                       hipStream_t s)
+{
+    dim3 grid((unsigned)(((batch + 63) / 64 + 3) / 4));
+    if (dim == 2)
+        hipLaunchKernelGGL(k_mlp_zfrag<2>, grid, dim3(256), 0, s, z, y, batch, (bf16x4*)zfr, ypad);
+    else
+        hipLaunchKernelGGL(k_mlp_zfrag<3>, grid, dim3(256), 0, s, z, y, batch, (bf16x4*)zfr, ypad);
+    return hipGetLastError();
+}
+
+hipError_t train_grad(const MlpDev& m, const void* zfr, const float* y, long long batch, float* grad_part,
+                      float* loss_part, hipStream_t s)
+{
+    ProfScope ps("k_mlp_train", s);
+    dim3 grid((unsigned)((batch + 63) / 64));
+    if (m.dim == 2)
+        hipLaunchKernelGGL(k_mlp_train<2>, grid, dim3(512), 0, s, (const FragImg<2>*)m.img, (const bf16x4*)zfr, y,
+                           batch, grad_part, loss_part);
+    else
+        hipLaunchKernelGGL(k_mlp_train<3>, grid, dim3(512), 0, s, (const FragImg<3>*)m.img, (const bf16x4*)zfr, y,
+                           batch, grad_part, loss_part);
+    return hipGetLastError();
+}
+
+hipError_t train_adam(const MlpDev& m, int nparts, const float* grad_part, const float* loss_part, float* grad,
+                      float* loss_out, float* params, float* mom, float* vel, long long t, float lr, int apply,
+                      long long batch, hipStream_t s)
 {
     ProfScope ps("k_mlp_adam", s);
     const float bc1 = (float)(1.0 - pow(0.9, (double)(t > 0 ? t : 1)));
     const float bc2 = (float)(1.0 - pow(0.999, (double)(t > 0 ? t : 1)));
-    hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((nparams + 255) / 256), dim3(256), 0, s, nparams, nparts, grad_part,
-                       loss_part, grad, loss_out, params, m, v, lr, bc1, bc2, apply, 1.0f / (float)batch);
-    (void)n_params;
+    const int np = n_params(m.dim);
+    dim3 grid((unsigned)((np + 63) / 64));
+    if (m.dim == 2)
+        hipLaunchKernelGGL(k_mlp_adam<2>, grid, dim3(512), 0, s, nparts, grad_part, loss_part, grad, loss_out,
+                           1.0f / (float)batch, params, mom, vel, lr, bc1, bc2, apply, m, (FragImg<2>*)m.img);
+    else
+        hipLaunchKernelGGL(k_mlp_adam<3>, grid, dim3(512), 0, s, nparts, grad_part, loss_part, grad, loss_out,
+                           1.0f / (float)batch, params, mom, vel, lr, bc1, bc2, apply, m, (FragImg<3>*)m.img);
     return hipGetLastError();
 }
 

@@ -269,6 +269,7 @@ struct MlpDev {
     const uint16_t* w3;   // bf16 [64][64]
     const uint16_t* w4;   // bf16 [64]
     const float* b1; const float* b2; const float* b3; const float* b4;
+    void* img;            // the weights as MFMA A fragments (k_mlp.hip), mlp_image_bytes(dim)
 };
 hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, uint16_t* w3, uint16_t* w4,
                     float* b1, float* b2, float* b3, float* b4, hipStream_t s);
@@ -279,13 +280,25 @@ hipError_t mlp_features(const MlpDev& m, const float* coords, long long nv, Grid
 hipError_t mlp_forward_z(const MlpDev& m, const float* z, long long batch, float* rho, hipStream_t s);
 hipError_t mlp_feature_sumsq(const float* coords, long long nv, GridGeom gg, const float* xh, int dim,
                              double* partial, int nblocks, hipStream_t s);
-// training: one wave per 64 samples writes its gradient to grad_part[wave]
-hipError_t train_step_grad(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
-                           const mc_result* res, const float* z_given, const float* y_given, const void* x, int dtype,
-                           long long batch, unsigned long long seed, long long step, float* grad_part,
-                           float* loss_part, int nparts, hipStream_t s);
-hipError_t train_reduce_adam(int nparams, int nparts, const float* grad_part, const float* loss_part, float* grad,
-                             float* loss_out, float* params, float* m, float* v, long long t, float lr, int apply,
-                             long long batch, hipStream_t s);
+size_t mlp_image_bytes(int dim);
+// Builds m.img from the row-major weights and biases of m.
+hipError_t mlp_image(const MlpDev& m, hipStream_t s);
+// training: samples of steps [t0, t0 + nsteps) as input fragments
+// (train_sample_bytes per step) and targets [nsteps][batch]
+size_t train_sample_bytes(int dim, long long batch);
+hipError_t train_sample(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                        const mc_result* res, const void* x, int dtype, long long batch, unsigned long long seed,
+                        long long t0, long long nsteps, void* zfr, float* y, hipStream_t s);
+// given inputs [batch][kpad] and targets -> the same layout (ypad: whole 64-sample parts)
+hipError_t train_zfrag(int dim, const float* z, const float* y, long long batch, void* zfr, float* ypad,
+                       hipStream_t s);
+// one workgroup per 64 samples writes its gradient to grad_part[part]
+hipError_t train_grad(const MlpDev& m, const void* zfr, const float* y, long long batch, float* grad_part,
+                      float* loss_part, hipStream_t s);
+// fixed-order sum of the parts; with apply, Adam on params and the new
+// weights into m's row-major arrays and image
+hipError_t train_adam(const MlpDev& m, int nparts, const float* grad_part, const float* loss_part, float* grad,
+                      float* loss_out, float* params, float* mom, float* vel, long long t, float lr, int apply,
+                      long long batch, hipStream_t s);
 
 }  // namespace mck

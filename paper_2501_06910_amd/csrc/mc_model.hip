@@ -2,6 +2,7 @@
 // parameter vector, serialisation, inference on a plan, GPU training.
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -24,7 +25,8 @@ int mc_model_dim(mc_model m) { return m ? m->dim : 0; }
 static mc_status model_upload(mc_model m)
 {
     const size_t nw = 64 * (size_t)m->kpad + 64 * 64 * 2 + 64;
-    const size_t bytes = nw * 2 + (64 * 3 + 4) * 4 + (size_t)mc_model_param_count(m->dim) * 4;
+    const size_t img_off = (nw * 2 + (64 * 3 + 4) * 4 + (size_t)mc_model_param_count(m->dim) * 4 + 255) & ~(size_t)255;
+    const size_t bytes = img_off + mck::mlp_image_bytes(m->dim);
     if (!m->dev) {
         hipError_t e = hipMalloc(&m->dev, bytes);
         if (e != hipSuccess) return mc_fail(MC_ERR_NOMEM, "model upload: %s", hipGetErrorString(e));
@@ -39,15 +41,17 @@ static mc_status model_upload(mc_model m)
     float* b4 = b3 + 64;
     float* master = b4 + 4;
     hipError_t e = hipMemcpy(master, m->params.data(), m->params.size() * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = mck::mlp_pack(master, m->dim, w1, w2, w3, w4, b1, b2, b3, b4, nullptr);
-    if (e == hipSuccess) e = hipDeviceSynchronize();
-    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "model upload: %s", hipGetErrorString(e));
     m->md.dim = m->dim;
     m->md.kin = m->kin;
     m->md.kpad = m->kpad;
     m->md.kappa = m->kappa;
     m->md.w1 = w1; m->md.w2 = w2; m->md.w3 = w3; m->md.w4 = w4;
     m->md.b1 = b1; m->md.b2 = b2; m->md.b3 = b3; m->md.b4 = b4;
+    m->md.img = (char*)m->dev + img_off;
+    if (e == hipSuccess) e = mck::mlp_pack(master, m->dim, w1, w2, w3, w4, b1, b2, b3, b4, nullptr);
+    if (e == hipSuccess) e = mck::mlp_image(m->md, nullptr);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "model upload: %s", hipGetErrorString(e));
     return MC_OK;
 }
 
@@ -163,8 +167,8 @@ extern "C" mc_status mc_model_features(mc_model m, mc_plan p, const mc_codes* co
     return MC_OK;
 }
 
-// Per-wave gradient partials are reduced in a fixed order, so the gradient
-// is the same on every run.
+// Per-workgroup gradient partials (64 samples each) are reduced in a fixed
+// order, so the gradient is the same on every run.
 static int parts_of(long long batch) { return (int)((batch + 63) / 64); }
 
 extern "C" mc_status mc_model_loss_grad(mc_model m, const float* d_z, const float* d_y, int64_t batch, float* d_grad,
@@ -173,20 +177,24 @@ extern "C" mc_status mc_model_loss_grad(mc_model m, const float* d_z, const floa
     if (!m || !d_z || !d_y || !d_grad || batch <= 0) return mc_fail(MC_ERR_ARG, "invalid loss_grad arguments");
     const int np = (int)mc_model_param_count(m->dim);
     const int nparts = parts_of(batch);
-    float *gp = nullptr, *lp = nullptr, *lo = nullptr;
+    float *gp = nullptr, *lp = nullptr, *lo = nullptr, *yp = nullptr;
+    void* zf = nullptr;
     hipError_t e = hipMalloc(&gp, (size_t)nparts * np * 4);
     if (e == hipSuccess) e = hipMalloc(&lp, (size_t)nparts * 4);
     if (e == hipSuccess) e = hipMalloc(&lo, 4);
+    if (e == hipSuccess) e = hipMalloc(&yp, (size_t)nparts * 64 * 4);
+    if (e == hipSuccess) e = hipMalloc(&zf, mck::train_sample_bytes(m->dim, batch));
+    if (e == hipSuccess) e = mck::train_zfrag(m->dim, d_z, d_y, batch, zf, yp, s);
+    if (e == hipSuccess) e = mck::train_grad(m->md, zf, yp, batch, gp, lp, s);
     if (e == hipSuccess)
-        e = mck::train_step_grad(m->md, nullptr, 0, GridGeom{}, nullptr, nullptr, d_z, d_y, nullptr, 0, batch, 0, 0,
-                                 gp, lp, nparts, s);
-    if (e == hipSuccess)
-        e = mck::train_reduce_adam(np, nparts, gp, lp, d_grad, d_loss ? d_loss : lo, nullptr, nullptr, nullptr, 0, 0.f,
-                                   0, batch, s);
+        e = mck::train_adam(m->md, nparts, gp, lp, d_grad, d_loss ? d_loss : lo, nullptr, nullptr, nullptr, 0, 0.f, 0,
+                            batch, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     hipFree(gp);
     hipFree(lp);
     hipFree(lo);
+    hipFree(yp);
+    hipFree(zf);
     if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "loss_grad: %s", hipGetErrorString(e));
     return MC_OK;
 }
@@ -233,6 +241,11 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     float* gp = (float*)dalloc((size_t)nparts * np * 4);
     float* lp = (float*)dalloc((size_t)nparts * 4);
     float* dev_state = (float*)dalloc((size_t)np * 4 * 4 + 64 * 4);
+    // samples of up to `chunk` steps are drawn in one launch (<= 256 MB)
+    const size_t zstep = mck::train_sample_bytes(dim, batch), ystep = (size_t)batch * 4;
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)steps, ((size_t)256 << 20) / (zstep + ystep)));
+    char* zbuf = (char*)dalloc(zstep * chunk);
+    float* ybuf = (float*)dalloc(ystep * chunk);
     double* ssq = (double*)dalloc(2048 * 8);
     for (void* q : tmp)
         if (!q) { cleanup(); return mc_fail(MC_ERR_NOMEM, "training scratch allocation failed"); }
@@ -269,15 +282,13 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     float* loss = dev_state + 3 * np;
     e = hipMemsetAsync(am, 0, (size_t)np * 2 * 4, s);
     for (int t = 0; t < steps && e == hipSuccess; ++t) {
-        e = mck::train_step_grad(m->md, plan->coords, plan->nv, plan->gg, plan->xh, c.result, nullptr, nullptr, d_field,
-                                 dtype, batch, seed, t, gp, lp, nparts, s);
+        const int tc = t % chunk;
+        if (tc == 0)
+            e = mck::train_sample(m->md, plan->coords, plan->nv, plan->gg, plan->xh, c.result, d_field, dtype, batch,
+                                  seed, t, std::min(chunk, steps - t), zbuf, ybuf, s);
+        if (e == hipSuccess) e = mck::train_grad(m->md, zbuf + zstep * tc, ybuf + (size_t)batch * tc, batch, gp, lp, s);
         if (e == hipSuccess)
-            e = mck::train_reduce_adam(np, nparts, gp, lp, grad, loss + (t % 64), master, am, av, t + 1, lr, 1, batch,
-                                       s);
-        if (e == hipSuccess)
-            e = mck::mlp_pack(master, dim, (uint16_t*)m->md.w1, (uint16_t*)m->md.w2, (uint16_t*)m->md.w3,
-                              (uint16_t*)m->md.w4, (float*)m->md.b1, (float*)m->md.b2, (float*)m->md.b3,
-                              (float*)m->md.b4, s);
+            e = mck::train_adam(m->md, nparts, gp, lp, grad, loss + (t % 64), master, am, av, t + 1, lr, 1, batch, s);
         if (e == hipSuccess && opts && opts->h_loss_out && (t % 64 == 63 || t == steps - 1)) {
             const int first = t - (t % 64);
             e = hipMemcpyAsync(opts->h_loss_out + first, loss, (size_t)(t - first + 1) * 4, hipMemcpyDeviceToHost, s);
