@@ -289,7 +289,7 @@ typedef float f4a4 __attribute__((ext_vector_type(4), aligned(4)));
 // gathers are issued NBB column blocks at a time, all before any is used,
 // with no branch around them (an invalid vertex gathers a clamped node and
 // its inputs are zeroed afterwards).
-template <int D>
+template <int D, bool MASK = true>
 __device__ __forceinline__ void build_inputs(bf16x4 (&zf)[4][MlpShape<D>::KB], const VGeom& mine, bool valid_any,
                                              const GridGeom& gg, const float* __restrict__ xh, float kappa,
                                              const bool (&valid)[4])
@@ -358,7 +358,7 @@ __device__ __forceinline__ void build_inputs(bf16x4 (&zf)[4][MlpShape<D>::KB], c
                     } else {
                         x = 0.0f;
                     }
-                    f[i] = valid[nb] ? x : 0.0f;
+                    f[i] = (!MASK || valid[nb]) ? x : 0.0f;
                 }
                 zf[nb][kb] = pack4(f[0], f[1], f[2], f[3]);
             }
@@ -427,12 +427,15 @@ __device__ __forceinline__ void forward_f(const LdsFrag<D>& sw, const bf16x4 (&z
     head_f(sw.w4f, sw.b4, h3, rho);
 }
 
+// clamp(rint(r), -(R-1), R-1), 0 for a non-finite r.  Rounding in FP32 is
+// exact (every float of magnitude >= 2^23 is an integer already), so this
+// equals rounding the value widened to FP64.
 __device__ __forceinline__ int rho_quant(float r)
 {
-    const double q = rint((double)r);
+    const float q = rintf(r);
     if (!(q == q) || isinf(q)) return 0;
-    if (q > (double)(MC_R - 1)) return MC_R - 1;
-    if (q < -(double)(MC_R - 1)) return -(MC_R - 1);
+    if (q > (float)(MC_R - 1)) return MC_R - 1;
+    if (q < -(float)(MC_R - 1)) return -(MC_R - 1);
     return (int)q;
 }
 
@@ -463,7 +466,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
         bf16x4 zf[4][MlpShape<D>::KB];
-        build_inputs<D>(zf, mine, true, gg, xh, m.kappa, valid);
+        if (D == 2 && v0 + 64 <= nv)        // whole tile: no vertex to mask (3-D: registers are short)
+            build_inputs<D, false>(zf, mine, true, gg, xh, m.kappa, valid);
+        else
+            build_inputs<D, true>(zf, mine, true, gg, xh, m.kappa, valid);
         float rho[4];
         forward_f<D>(sw, zf, rho);
         // lane l holds vertex l of the tile as rho[l / 16]
