@@ -665,13 +665,12 @@ def grid_sweep(log, ks=(2.0, 5.0, 10.0, 20.0, 30.0, 40.0, 50.0, 60.0, 70.0, 80.0
     return {"g_max": g_max, "eb": eb, "rows": rows}
 
 
-def batch_main(args, log):
+def batch_section(args, log) -> dict:
     """Many fields on many meshes: 12 meshes of 0.5M..20M vertices (2-D and
     3-D, float32 and float64), 64 fields; a step is one batch compress and
     one batch decompress, each a single HIP graph launch.  Measured plain and
     with the learned predictor per block (one model per mesh, trained on its
-    first field); ``value`` is the learned form's GB/s of mesh values over all
-    fields."""
+    first field)."""
     import torch
     import meshgen as G
     from paper_2501_06910_amd import mc as M
@@ -760,21 +759,34 @@ def batch_main(args, log):
     learned = measure(models, "learned")
     learned["train_seconds"] = round(train_s, 3)
     nv_all = [m.n_vertices for m in meshes]
+    res = {"workload": f"batch: {len(meshes)} meshes ({min(nv_all)}..{max(nv_all)} vertices, "
+                       f"even 2-D jittered triangulations, odd 3-D Kuhn tetrahedra), {len(fields)} fields "
+                       f"(float32 on 2-D, float64 on 3-D meshes), relative eb 1e-3/1e-4/1e-5, grids of "
+                       f"about n_v/4 nodes, split 0.5, learned predictor per block (one model per mesh)",
+           "scale": args.batch_scale, "n_vertices_total": int(sum(x.numel() for x in xs)), "raw_bytes": raw,
+           "steps": args.steps, "warmup": args.warmup,
+           "learned": learned, "plain": plain, "plan_seconds": round(plan_s, 3)}
+    del plans, xs, outs, models
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def batch_main(args, log):
+    """The batch workload as the line's workload: ``value`` is the learned
+    form's GB/s of mesh values over all fields."""
+    b = batch_section(args, log)
     line = {
         "metric": "compress/decompress GB/s of mesh values + CR, learned vs plain, eb=1e-4",
-        "value": learned["GBps"], "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": learned["ms_per_step"],
+        "value": b["learned"]["GBps"], "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": b["learned"]["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"batch: {len(meshes)} meshes ({min(nv_all)}..{max(nv_all)} vertices, "
-                               f"even 2-D jittered triangulations, odd 3-D Kuhn tetrahedra), {len(fields)} fields "
-                               f"(float32 on 2-D, float64 on 3-D meshes), relative eb 1e-3/1e-4/1e-5, grids of "
-                               f"about n_v/4 nodes, split 0.5, learned predictor per block (one model per mesh)",
-                   "scale": args.batch_scale, "n_vertices_total": int(sum(x.numel() for x in xs)),
-                   "raw_bytes": raw},
-        "learned": learned,
-        "plain": plain,
-        "plan_seconds": round(plan_s, 3),
+        "config": {"workload": b["workload"], "scale": b["scale"], "n_vertices_total": b["n_vertices_total"],
+                   "raw_bytes": b["raw_bytes"]},
+        "learned": b["learned"],
+        "plain": b["plain"],
+        "plan_seconds": b["plan_seconds"],
     }
     print(json.dumps(line), flush=True)
 
@@ -791,6 +803,7 @@ def main():
                     help="seconds of untimed steps before the warm-up steps (clock ramp under load)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-vs-plain time series section")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-fields batch section")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the 1-D baseline and the design points (profiled runs: only the timed step's kernels)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch order (no autotuning)")
@@ -1009,6 +1022,9 @@ def main():
                                               split_mode="sum", operators="cluster", residual="open", coarsen=True)]
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
+    if not args.no_batch and args.workload == "tet3d":
+        # the many-fields workload (12 meshes, 64 fields) with its own steps
+        line["batch"] = batch_section(args, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle, one thread, the same inputs) ...")
         line["cpu_baseline"] = cpu_baseline(mesh, f, cfg, args.eb, args.split, h_gpu=h, x_gpu=xr_host)

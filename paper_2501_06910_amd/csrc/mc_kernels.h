@@ -164,9 +164,10 @@ enum {
     MC_KNOB_NT_VERT = 1u << 8,      // residual codes and vertex decode: coordinates, field, codes and
                                     // decoded values streamed with the non-temporal policy
     MC_KNOB_ALL = 0x1ffu,           // every valid bit
-    MC_KNOB_DEFAULT = 0x1e0u        // a new plan: the best mask measured on the 16M-vertex tet mesh (launch
-                                    // order for resample, Lorenzo, residual and vertex decode, XCD order
-                                    // for the 3-D decode, non-temporal streams)
+    MC_KNOB_DEFAULT = 0x1ecu        // a new plan: on the 16M-vertex tet mesh launch order for resample and
+                                    // Lorenzo, XCD order for the vertex kernels (same time as launch order,
+                                    // each grid line fetched once per pass instead of 1.4x) and for the
+                                    // 3-D decode, non-temporal streams
 };
 
 #define MC_D2_R 8                  // 2-D decode: rows per chunk (rows of DecodeWs in 2-D)
