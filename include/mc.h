@@ -288,6 +288,12 @@ mc_status mc_plan_get_grid(mc_plan plan, mc_grid* out);
  * plan's (coarsened) grid (MC_OPS_CLUSTER plans; MC_ERR_UNSUPPORTED
  * otherwise). */
 mc_status mc_plan_nodes(mc_plan plan, int32_t* d_m, hipStream_t stream);
+/* Copies the vertex list of every node, the sets whose means are the
+ * cluster resampling f (Sec. IV-D): node j's vertices, in ascending id
+ * order, are d_vlist[d_noff[j] .. d_noff[j+1]); d_noff int64[n_grid + 1],
+ * d_vlist int32[n_vertices], either may be NULL (MC_OPS_CLUSTER plans;
+ * MC_ERR_UNSUPPORTED otherwise). */
+mc_status mc_plan_node_lists(mc_plan plan, int64_t* d_noff, int32_t* d_vlist, hipStream_t stream);
 /* Grid_Coarsen (Alg. 2) of a plan made with mc_plan_opts.coarsen = 1 (sync):
  * h_keep (host, int32[dims0 + dims1 + dims2] of the grid given at plan
  * creation, axis 0 first) receives each original plane's index on the

@@ -4,16 +4,14 @@
 // residual of Alg. 3 taken against the uncompressed grid (open loop) or the
 // reconstructed one (closed loop).
 //   plan:        k_nearest_node (node of every vertex, counts per node)
-//                -> scan of the counts -> stable radix sort of (node,
-//                vertex) pairs: each node's vertices in ascending id order
+//                -> scan of the counts -> stable LSD radix sort of (node,
+//                vertex) pairs (k_rs_*): each node's vertices in ascending
+//                id order
 //   compress:    k_cluster_mean (one thread per node sums its vertices in
 //                FP64 in ascending id order, prequantises) -> Lorenzo ->
 //                k_residual_nearest -> scatter
 //   decompress:  grid decode -> k_vdecode_nearest
 #include <cstring>
-
-#include <rocprim/device/device_radix_sort.hpp>
-#include <rocprim/iterator/counting_iterator.hpp>
 
 #include "mc_dev.h"
 #include "mc_kernels.h"
@@ -269,14 +267,133 @@ hipError_t count_empty(const unsigned* count, long long ng, unsigned* out, hipSt
     return hipGetLastError();
 }
 
+// Stable LSD radix sort of (key, index) pairs, 8-bit digits, tiles of
+// RS_TILE keys per workgroup (4 waves x 1024 consecutive keys):
+//   k_rs_count    digit histogram of every tile, stored digit-major, so the
+//                 exclusive scan of the array gives each (digit, tile) its
+//                 first output position
+//   k_rs_scatter  per wave, its digit counts offset by the earlier waves'
+//                 of the tile; then 64 keys at a time in order, each key's
+//                 rank among the lanes with the same digit from eight
+//                 ballots, and a running per-digit position in LDS
+#define RS_TILE 4096
+
+__global__ __launch_bounds__(256) void k_rs_count(const uint32_t* __restrict__ keys, long long n, int shift,
+                                                  unsigned* __restrict__ hist, unsigned nblk)
+{
+    __shared__ unsigned s_h[256];
+    s_h[threadIdx.x] = 0u;
+    __syncthreads();
+    const long long base = (long long)blockIdx.x * RS_TILE;
+    for (int i = threadIdx.x; i < RS_TILE; i += 256) {
+        const long long k = base + i;
+        if (k < n) atomicAdd(&s_h[(keys[k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblk + blockIdx.x] = s_h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const uint32_t* __restrict__ kin, const int32_t* __restrict__ vin,
+                                                    long long n, int shift, const long long* __restrict__ off,
+                                                    unsigned nblk, uint32_t* __restrict__ kout,
+                                                    int32_t* __restrict__ vout)
+{
+    __shared__ unsigned s_cnt[4][256];
+    __shared__ long long s_base[256];
+    const int w = threadIdx.x >> 6, l = lane_id();
+    for (int i = threadIdx.x; i < 4 * 256; i += 256) (&s_cnt[0][0])[i] = 0u;
+    __syncthreads();
+    const long long wb = (long long)blockIdx.x * RS_TILE + (long long)w * (RS_TILE / 4);
+    for (int r = 0; r < RS_TILE / 4 / 64; ++r) {
+        const long long k = wb + r * 64 + l;
+        if (k < n) atomicAdd(&s_cnt[w][(kin[k] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        unsigned run = 0u;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const unsigned c = s_cnt[v][d];
+            s_cnt[v][d] = run;
+            run += c;
+        }
+        s_base[d] = off[(size_t)d * nblk + blockIdx.x];
+    }
+    __syncthreads();
+    const unsigned long long lt = (1ull << l) - 1ull;
+    for (int r = 0; r < RS_TILE / 4 / 64; ++r) {
+        const long long k = wb + r * 64 + l;
+        const bool valid = k < n;
+        const uint32_t key = valid ? kin[k] : 0u;
+        const int32_t val = valid ? (vin ? vin[k] : (int32_t)k) : 0;
+        const unsigned d = (key >> shift) & 255u;
+        unsigned long long eq = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const unsigned long long bb = __ballot(bit);
+            eq &= bit ? bb : ~bb;
+        }
+        const unsigned rank = (unsigned)__popcll(eq & lt);
+        const unsigned run = s_cnt[w][d];      // read by every lane before the group's update below
+        if (valid) {
+            const long long pos = s_base[d] + run + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+            if (rank == 0u) s_cnt[w][d] = run + (unsigned)__popcll(eq);
+        }
+    }
+}
+
+static size_t rs_align(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace: temp_bytes is set when temp is NULL.  keys_out[i] and vlist[i]
+// get the i-th (key, index) pair in key order, equal keys by index.
 hipError_t sort_by_node(const int32_t* m, long long nv, long long ng, uint32_t* keys_out, int32_t* vlist,
                         void* temp, size_t* temp_bytes, hipStream_t s)
 {
-    unsigned bits = 1;
+    const unsigned nblk = (unsigned)((nv + RS_TILE - 1) / RS_TILE > 0 ? (nv + RS_TILE - 1) / RS_TILE : 1);
+    const long long nh = 256ll * nblk;
+    const long long nst = (nh + MC_TILE - 1) / MC_TILE;
+    const size_t b_kt = rs_align((size_t)nv * 4), b_vt = b_kt, b_h = rs_align((size_t)nh * 4),
+                 b_off = rs_align((size_t)(nh + 1) * 8), b_st = rs_align((size_t)nst * 8), b_tk = 256;
+    const size_t need = b_kt + b_vt + b_h + b_off + b_st + b_tk;
+    if (!temp) {
+        *temp_bytes = need;
+        return hipSuccess;
+    }
+    if (*temp_bytes < need) return hipErrorInvalidValue;
+    if (nv <= 0) return hipSuccess;
+    char* q = (char*)temp;
+    uint32_t* kt = (uint32_t*)q;
+    int32_t* vt = (int32_t*)(q + b_kt);
+    unsigned* hist = (unsigned*)(q + b_kt + b_vt);
+    long long* off = (long long*)(q + b_kt + b_vt + b_h);
+    unsigned long long* st = (unsigned long long*)(q + b_kt + b_vt + b_h + b_off);
+    unsigned* ticket = (unsigned*)(q + b_kt + b_vt + b_h + b_off + b_st);
+    int bits = 1;
     while (bits < 32 && (1ll << bits) < ng) ++bits;
-    rocprim::counting_iterator<int32_t> iota(0);
-    return rocprim::radix_sort_pairs(temp, *temp_bytes, (const uint32_t*)m, keys_out, iota, vlist, (size_t)nv, 0u,
-                                     bits, s);
+    const int passes = (bits + 7) / 8;
+    const uint32_t* kin = (const uint32_t*)m;
+    const int32_t* vin = nullptr;                   // pass 0: the indices themselves
+    for (int p = 0; p < passes; ++p) {
+        // the last pass writes the caller's arrays
+        const bool to_out = ((passes - 1 - p) & 1) == 0;
+        uint32_t* ko = to_out ? keys_out : kt;
+        int32_t* vo = to_out ? vlist : vt;
+        hipError_t e = hipMemsetAsync(st, 0, b_st + b_tk, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_count, dim3(nblk), dim3(256), 0, s, kin, nv, 8 * p, hist, nblk);
+        e = scan_u32(hist, nh, off, st, ticket, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(256), 0, s, kin, vin, nv, 8 * p, off, nblk, ko, vo);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        kin = ko;
+        vin = vo;
+    }
+    return hipSuccess;
 }
 
 hipError_t cluster_mean(const long long* noff, const int32_t* vlist, long long ng, const void* x, int dtype,

@@ -866,6 +866,18 @@ extern "C" mc_status mc_plan_nodes(mc_plan p, int32_t* d_m, hipStream_t s)
     return MC_OK;
 }
 
+extern "C" mc_status mc_plan_node_lists(mc_plan p, int64_t* d_noff, int32_t* d_vlist, hipStream_t s)
+{
+    if (!p) return mc_fail(MC_ERR_ARG, "plan is NULL");
+    if (p->ops != MC_OPS_CLUSTER) return mc_fail(MC_ERR_UNSUPPORTED, "the plan has no node lists (MC_OPS_LINEAR)");
+    hipError_t e = hipSuccess;
+    if (d_noff) e = hipMemcpyAsync(d_noff, p->noff, (size_t)(p->ng + 1) * 8, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && d_vlist)
+        e = hipMemcpyAsync(d_vlist, p->vlist, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "node list copy: %s", hipGetErrorString(e));
+    return MC_OK;
+}
+
 extern "C" mc_status mc_plan_destroy(mc_plan p)
 {
     if (!p) return MC_OK;

@@ -125,6 +125,7 @@ _SIGS = {
     "mc_plan_get_grid": (C.c_int, [_P, _P]),
     "mc_plan_destroy": (C.c_int, [_P]),
     "mc_plan_nodes": (C.c_int, [_P, _P, _P]),
+    "mc_plan_node_lists": (C.c_int, [_P, _P, _P, _P]),
     "mc_plan_kept_planes": (C.c_int, [_P, _P, C.c_int64]),
     "mc_compress": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
     "mc_decompress": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
@@ -347,6 +348,16 @@ class Plan:
         m = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
         _check(lib().mc_plan_nodes(self.handle, _ptr(m), _stream()), "mc_plan_nodes")
         return m
+
+    def node_lists(self):
+        """(noff int64[n_grid + 1], vlist int32[n_vertices]): node j's
+        vertices in ascending id order are vlist[noff[j]:noff[j+1]]
+        (cluster plans)."""
+        torch = _torch()
+        noff = torch.empty(self.n_grid + 1, dtype=torch.int64, device="cuda")
+        vlist = torch.empty(self.n_vertices, dtype=torch.int32, device="cuda")
+        _check(lib().mc_plan_node_lists(self.handle, _ptr(noff), _ptr(vlist), _stream()), "mc_plan_node_lists")
+        return noff, vlist
 
     @property
     def remap_mask(self) -> int:

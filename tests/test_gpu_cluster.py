@@ -78,6 +78,18 @@ def test_node_map_and_cluster_means(case):
     print(f"[cluster] {case.name}: {int((oc.count == 0).sum())} empty nodes of {oc.count.size}")
 
 
+def test_node_lists_are_a_stable_sort(case):
+    """The plan's per-node vertex lists (its own LSD radix sort) against the
+    definition: vertices ordered by node, equal nodes by id, and node j's
+    run starting at the number of vertices on nodes before j."""
+    m = case.plan.nodes().cpu().numpy()
+    noff, vlist = case.plan.node_lists()
+    noff, vlist = noff.cpu().numpy(), vlist.cpu().numpy()
+    assert np.array_equal(vlist, np.argsort(m, kind="stable").astype(np.int32))
+    counts = np.bincount(m, minlength=noff.size - 1)
+    assert np.array_equal(noff, np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+
+
 def test_codes_bitexact(case):
     oc = case.oracle()
     h = case.gpu().host()
