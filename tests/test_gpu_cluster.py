@@ -90,6 +90,24 @@ def test_node_lists_are_a_stable_sort(case):
     assert np.array_equal(noff, np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
 
 
+@pytest.mark.parametrize("dims", [(6, 5, 4), (300, 262)])
+def test_node_lists_one_and_three_sort_passes(dims):
+    """Node lists where the radix sort takes one 8-bit pass (120 nodes) and
+    three (78,600 nodes, 17 bits), on a vertex count that is no multiple of
+    the sort's 4,096-key tile."""
+    if len(dims) == 3:
+        mesh = G.kuhn_tet_mesh(19, 3)
+    else:
+        mesh = G.structured_tri_mesh(211, 173, np.random.default_rng(3), 0.2)
+    assert mesh.n_vertices % 4096 != 0
+    plan = M.Plan(dev(mesh.coords), None, dims=dims, operators="cluster")
+    m = plan.nodes().cpu().numpy()
+    noff, vlist = plan.node_lists()
+    assert np.array_equal(vlist.cpu().numpy(), np.argsort(m, kind="stable").astype(np.int32))
+    counts = np.bincount(m, minlength=plan.n_grid)
+    assert np.array_equal(noff.cpu().numpy(), np.concatenate([[0], np.cumsum(counts)]).astype(np.int64))
+
+
 def test_codes_bitexact(case):
     oc = case.oracle()
     h = case.gpu().host()
@@ -167,6 +185,9 @@ def test_grid_coarsen(which, dims, open_loop, gpred):
     assert np.array_equal(plan.kept_planes(), keep)
     assert tuple(plan.grid.dims) == ogc.dims() and plan.n_grid == ogc.count
     assert np.array_equal(plan.nodes().cpu().numpy(), om)
+    noff, vlist = plan.node_lists()                  # the lists on the coarsened grid
+    assert np.array_equal(vlist.cpu().numpy(), np.argsort(om, kind="stable").astype(np.int32))
+    assert int(noff[-1]) == mesh.n_vertices and noff.numel() == ogc.count + 1
     xt = dev(x)
     kw = {} if ref is None else dict(grid_ref=dev(ref))
     codes = M.Codes(plan, xt.dtype, grid_predictor=gpred, **kw)
