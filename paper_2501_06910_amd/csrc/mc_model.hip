@@ -334,7 +334,5 @@ static void host_init(int dim, uint64_t seed, std::vector<float>& p)
     }
 }
 
-// ---------------------------------------------------------------------------
-// batched compression: the items run back to back on one stream; the
-// persistent single-launch form lives in mc_batch.hip
-// ---------------------------------------------------------------------------
+// Batched compression and decompression (HIP graphs of per-stage work-list
+// launches) are in mc_batch.hip.
