@@ -365,6 +365,9 @@ typedef struct {
     float lr;                /* default 1e-3 */
     uint64_t seed;           /* SplitMix64 seed for init and sampling */
     float* h_loss_out;       /* optional host float[steps]: loss per step */
+    int32_t sample_steps;    /* steps whose samples one launch draws; 0: as many
+                                as fit in 256 MB.  The trained model does not
+                                depend on it. */
 } mc_train_opts;
 
 int64_t mc_model_param_count(int32_t dim);

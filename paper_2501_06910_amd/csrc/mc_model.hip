@@ -243,7 +243,8 @@ extern "C" mc_status mc_model_train(mc_plan plan, const void* d_field, mc_dtype 
     float* dev_state = (float*)dalloc((size_t)np * 4 * 4 + 64 * 4);
     // samples of up to `chunk` steps are drawn in one launch (<= 256 MB)
     const size_t zstep = mck::train_sample_bytes(dim, batch), ystep = (size_t)batch * 4;
-    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)steps, ((size_t)256 << 20) / (zstep + ystep)));
+    int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)steps, ((size_t)256 << 20) / (zstep + ystep)));
+    if (opts && opts->sample_steps > 0) chunk = std::min(steps, (int)opts->sample_steps);
     char* zbuf = (char*)dalloc(zstep * chunk);
     float* ybuf = (float*)dalloc(ystep * chunk);
     double* ssq = (double*)dalloc(2048 * 8);

@@ -78,7 +78,7 @@ class McCodes(C.Structure):
 
 class McTrainOpts(C.Structure):
     _fields_ = [("steps", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("seed", C.c_uint64),
-                ("h_loss_out", C.c_void_p)]
+                ("h_loss_out", C.c_void_p), ("sample_steps", C.c_int32)]
 
 
 class McBatchItem(C.Structure):
@@ -665,10 +665,10 @@ class Model:
 
     @classmethod
     def train(cls, plan: Plan, field, eb=1e-4, eb_mode="rel", grid_share=0.5, steps=2000, batch=8192,
-              lr=1e-3, seed=0, return_loss=False, split_mode="sum"):
+              lr=1e-3, seed=0, return_loss=False, split_mode="sum", sample_steps=0):
         prm = McParams(eb, EB_REL if eb_mode == "rel" else EB_ABS, grid_share, None, _split_code(split_mode))
         loss = np.zeros(steps, np.float32)
-        opts = McTrainOpts(steps, batch, lr, seed, loss.ctypes.data)
+        opts = McTrainOpts(steps, batch, lr, seed, loss.ctypes.data, sample_steps)
         h = C.c_void_p()
         _check(lib().mc_model_train(plan.handle, _ptr(field), _dtype_code(field), C.byref(prm), C.byref(opts),
                                     _stream(), C.byref(h)), "mc_model_train")

@@ -221,6 +221,25 @@ def test_training_trajectory_matches_oracle(dim):
         assert rp <= 2e-2, (a, b)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_training_sample_chunks_do_not_change_the_model(dim):
+    """The samples of several steps are drawn per launch; drawing them 5
+    steps at a time (launches at steps 0, 5, ..., 20) must train exactly
+    the model that one launch for all 24 steps trains (the draw of step t
+    depends on t only), so the oracle trajectory above also covers the
+    chunked path the 2,000-step training takes."""
+    mesh, series, dims = _series_case(dim)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    kw = dict(eb=1e-4, steps=24, batch=1024, lr=1e-3, seed=91, return_loss=True)
+    m1, l1 = M.Model.train(plan, dev(series[0]), **kw)
+    m5, l5 = M.Model.train(plan, dev(series[0]), sample_steps=5, **kw)
+    p1, k1 = m1.params()
+    p5, k5 = m5.params()
+    assert k1 == k5
+    assert np.array_equal(p1.view(np.uint32), p5.view(np.uint32))
+    assert np.array_equal(np.asarray(l1).view(np.uint32), np.asarray(l5).view(np.uint32))
+
+
 def test_learned_gain_on_time_series():
     """Train on t=0, compress t=1 and t=2: the per-block choice makes the
     learned stream no larger than the plain one by construction; here the
