@@ -51,12 +51,46 @@ __device__ __forceinline__ void excl_prefix_strided(int* __restrict__ a, long lo
     }
 }
 
-__global__ __launch_bounds__(256) void k_dec_xy_carry(int* __restrict__ agg, int n0, int n2, int nyc)
+// Exclusive prefix over the nyc row chunks of every (plane, column), in
+// place.  A 1,024-thread workgroup takes 64 columns of one plane (lane =
+// column, so every load and store is coalesced): in rounds of 256 chunks,
+// wave w scans chunks 16w .. 16w+15 of the round in registers (all 16
+// loads issued first), the 16 wave totals per column are combined through
+// LDS, and a running total per column carries from round to round.
+__global__ __launch_bounds__(1024) void k_dec_xy_carry(int* __restrict__ agg, int n0, int n2, int nyc)
 {
-    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (i >= (long long)n0 * n2) return;
-    const long long z = i / n0, c = i % n0;
-    excl_prefix_strided(agg, z * nyc * n0 + c, n0, nyc);
+    __shared__ int s_tot[16][64];
+    __shared__ int s_run[64];
+    const int l = lane_id(), w = threadIdx.x >> 6;
+    const long long ncb = (n0 + 63) / 64;
+    const long long z = blockIdx.x / ncb;
+    const int c = (int)(blockIdx.x % ncb) * 64 + l;
+    const bool act = c < n0 && z < n2;
+    int* col = agg + z * (long long)nyc * n0 + (act ? c : 0);
+    if (w == 0) s_run[l] = 0;
+    for (int r0 = 0; r0 < nyc; r0 += 256) {
+        const int j0 = r0 + 16 * w;
+        int t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = (act && j0 + u < nyc) ? col[(long long)(j0 + u) * n0] : 0;
+        int sum = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int v = t[u];
+            t[u] = sum;
+            sum += v;
+        }
+        s_tot[w][l] = sum;
+        __syncthreads();                            // also orders the first round after s_run's clearing
+        int off = s_run[l];
+        for (int v = 0; v < w; ++v) off += s_tot[v][l];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (act && j0 + u < nyc) col[(long long)(j0 + u) * n0] = off + t[u];
+        __syncthreads();                            // every wave has read s_run and s_tot
+        if (w == 15) s_run[l] = off + sum;          // wave 15's offset plus its total: the round's end
+        __syncthreads();
+    }
 }
 
 template <int CPT, bool FROM_CODES>
@@ -771,7 +805,7 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
         }
         {
             ProfScope ps("k_dec_xy_carry", s);
-            hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)((n0 + 255) / 256)), dim3(256), 0, s, ws.agg_xy, n0, 1,
+            hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)((n0 + 63) / 64)), dim3(1024), 0, s, ws.agg_xy, n0, 1,
                                ws.nyc);
             if ((e = hipGetLastError()) != hipSuccess) return e;
         }
@@ -865,7 +899,7 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
     }
     {
         ProfScope ps("k_dec_xy_carry", s);
-        hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)(((long long)n0 * n2 + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)((long long)((n0 + 63) / 64) * n2)), dim3(1024), 0, s,
                            ws.agg_xy, n0, n2, ws.nyc);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
