@@ -412,13 +412,13 @@ __global__ __launch_bounds__(256, 3) void k_d3_carry(int* __restrict__ agg_z, in
         const long long i = (long long)(b - nbt - nbz) * 256 + threadIdx.x;
         if (i < (long long)n0 * n2) {
             const long long z = i / n0, c = i % n0;
-            excl_prefix_b<16>(agg_y + z * nyc * n0 + c, (unsigned)n0, nyc);
+            excl_prefix_b<32>(agg_y + z * nyc * n0 + c, (unsigned)n0, nyc);
         }
         return;
     }
     if (b >= nbt) {
         const long long pos = (long long)(b - nbt) * 256 + threadIdx.x;
-        if (pos < nxy) excl_prefix_b<16>(agg_z + pos, (unsigned)nxy, nzc);
+        if (pos < nxy) excl_prefix_b<32>(agg_z + pos, (unsigned)nxy, nzc);
         return;
     }
     const int x = (int)(b << xb_log) + (int)(threadIdx.x & ((1u << xb_log) - 1u));
