@@ -177,6 +177,11 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2501_06910_amd.build` (no CPU fallback exists)")
+        # torch first: the library's HIP runtime dependency then resolves to
+        # the one torch has loaded, so both share one runtime and device
+        # state (opened the other way round, two runtimes are loaded and the
+        # library's sees no device)
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             f = getattr(L, name)
