@@ -62,11 +62,6 @@ __device__ __forceinline__ bf16x4 relu_bf(bf16x4 v)
     return __builtin_elementwise_max(v, (bf16x4){0, 0, 0, 0});
 }
 
-__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
 // K = 32 products per instruction (gfx950).  Each lane supplies 8 values of
 // A and 8 of B; the instruction pairs A's and B's values of the same lane
 // group and slot, so any assignment of the 32 k indices to (lane group,
