@@ -476,6 +476,64 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     }
 }
 
+// Learned decompress in one pass: every 64-vertex tile decodes its
+// vertices, x' = (T)(g + (q + rho_q) * 2 tau2) with q = code - R (raw values
+// for outliers), where g is the back-interpolation the network's inputs
+// already need (the same operations as the vertex decoder's, so the same
+// bits) and rho_q is the network's shift in learned blocks, 0 elsewhere (no
+// network evaluation there).  The shifts never reach memory.
+template <int D, typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_vdecode(
+    mck::MlpDev m, const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
+    const uint32_t* __restrict__ bflags, const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
+    const T* __restrict__ oval, const mc_result* __restrict__ res, long long vcap, T* __restrict__ xout)
+{
+    __shared__ LdsFrag<D> sw;
+    load_frag<D, 256>(sw, m);
+    const long long ntiles = (nv + 63) / 64;
+    const int l = lane_id();
+    const double step2 = 2.0 * res->tau2;
+    const long long nout = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
+    for (long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
+         tile += (long long)gridDim.x * 4) {
+        const long long v0 = tile * 64;
+        const long long blk = v0 / MC_LBLOCK;                    // a tile lies inside one block
+        const bool learned = (bflags[blk >> 5] >> (blk & 31)) & 1u;
+        const long long v = v0 + l;
+        const long long vc = v < nv ? v : nv - 1;
+        const VGeom mine = vertex_geom<D>(coords, nv, vc, gg, xh);
+        const float g = mine.g;
+        int rq = 0;
+        if (learned) {                                           // uniform over the wave
+            bool valid[4];
+#pragma unroll
+            for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
+            bf16x4 zf[4][MlpShape<D>::KB];
+            if (D == 2 && v0 + 64 <= nv)
+                build_inputs<D, false>(zf, mine, true, gg, xh, m.kappa, valid);
+            else
+                build_inputs<D, true>(zf, mine, true, gg, xh, m.kappa, valid);
+            float rho[4];
+            forward_f<D>(sw, zf, rho);
+            float r = rho[0];
+            if ((l >> 4) == 1) r = rho[1];
+            if ((l >> 4) == 2) r = rho[2];
+            if ((l >> 4) == 3) r = rho[3];
+            rq = rho_quant(r);
+        }
+        if (v < nv) {
+            const int code = codes[v];                           // loaded after the network: fewer live registers
+            if (code == 0) {
+                const long long k = find_outlier(oidx, nout, v);
+                xout[v] = k >= 0 ? oval[k] : (T)0;
+            } else {
+                const int q = code - MC_R + rq;
+                xout[v] = (T)((double)g + (double)q * step2);
+            }
+        }
+    }
+}
+
 // Inputs of vertices [v0, v0 + count) as floats [count][KPAD].
 template <int D>
 __global__ __launch_bounds__(256) void k_mlp_features(float kappa, const float* __restrict__ coords, long long nv,
@@ -1027,6 +1085,22 @@ hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeo
         hipLaunchKernelGGL(k_mlp_infer<2>, dim3((unsigned)nb), dim3(256), 0, s, m, coords, nv, gg, xh, only_blocks, rho_q);
     else
         hipLaunchKernelGGL(k_mlp_infer<3>, dim3((unsigned)nb), dim3(256), 0, s, m, coords, nv, gg, xh, only_blocks, rho_q);
+    return hipGetLastError();
+}
+
+hipError_t mlp_vdecode(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                       const uint32_t* bflags, const uint16_t* codes, const int32_t* oidx, const void* oval,
+                       const mc_result* res, long long vcap, void* xout, int dtype, hipStream_t s)
+{
+    ProfScope ps("k_mlp_vdecode", s);
+    long long nb = (nv + 255) / 256;
+    if (nb > 2048) nb = 2048;
+    if (nb < 1) nb = 1;
+#define MC_MVD(D, T) hipLaunchKernelGGL((k_mlp_vdecode<D, T>), dim3((unsigned)nb), dim3(256), 0, s, m, coords, nv, gg, \
+                                        xh, bflags, codes, oidx, (const T*)oval, res, vcap, (T*)xout)
+    if (m.dim == 2) { if (dtype == MC_F64) MC_MVD(2, double); else MC_MVD(2, float); }
+    else { if (dtype == MC_F64) MC_MVD(3, double); else MC_MVD(3, float); }
+#undef MC_MVD
     return hipGetLastError();
 }
 

@@ -1099,6 +1099,12 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
                                         codes->v_out_cap, codes->result, d_out, dtype, s));
         return MC_OK;
     }
+    if (model && codes->residual_predictor != MC_RESPRED_DELTA) {
+        // network shifts and vertex decode in one pass
+        ECHK(mck::mlp_vdecode(model->md, p->coords, p->nv, p->gg, p->xh, codes->block_flags, codes->vert_codes,
+                              codes->v_out_idx, codes->v_out_val, codes->result, codes->v_out_cap, d_out, dtype, s));
+        return MC_OK;
+    }
     const int32_t* rho = nullptr;
     if (model) {
         mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);

@@ -276,6 +276,10 @@ hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, ui
                     float* b1, float* b2, float* b3, float* b4, hipStream_t s);
 hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
                      const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s);
+// Learned decompress of every vertex (network shifts in learned blocks).
+hipError_t mlp_vdecode(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                       const uint32_t* bflags, const uint16_t* codes, const int32_t* oidx, const void* oval,
+                       const mc_result* res, long long vcap, void* xout, int dtype, hipStream_t s);
 hipError_t mlp_features(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh, long long v0,
                         long long count, float* z, hipStream_t s);
 hipError_t mlp_forward_z(const MlpDev& m, const float* z, long long batch, float* rho, hipStream_t s);
