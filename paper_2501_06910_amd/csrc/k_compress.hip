@@ -13,8 +13,6 @@
 //                    or from p and converted as the decoder does), residual
 //                    quantisation with the per-vertex bound check, per-tile
 //                    outlier counts
-//   k_residual_learned  learned mode, one workgroup per 4096-vertex block:
-//                    both code costs, the cheaper kind, then the codes
 //   k_scatter        outlier lists in index order (wave ballots)
 #include "mc_dev.h"
 #include "mc_interp.h"
@@ -469,25 +467,6 @@ __global__ __launch_bounds__(256) void k_lorenzo3(const int32_t* __restrict__ p,
 }
 
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int zz_bits(int k)
-{
-    const unsigned z = ((unsigned)k << 1) ^ (unsigned)(k >> 31);
-    return 32 - __clz(z);
-}
-
-// Residual quantisation of one vertex: r = x - g, q = rint(r / (2 tau2)),
-// x' = (T)(g + q * 2 tau2); accepted iff |q| <= R-1 and |x - x'| <= tau2.
-template <typename T>
-__device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound& b, int& qi)
-{
-    const double r = (double)xv - (double)g;
-    const double q = rint(r * b.inv2);
-    const T xr = (T)((double)g + q * b.step2);
-    const bool ok = fabs(q) <= (double)(MC_R - 1) && fabs((double)xv - (double)xr) <= b.tau2;
-    qi = ok ? (int)q : 0;
-    return ok;
-}
-
 // Residual codes of one tile (1024 vertices) and its outlier count.
 template <typename T, int D, bool FROM_P, bool NT>
 __device__ __forceinline__ void residual_block(long long tile, const float* __restrict__ coords, long long nv,
@@ -563,100 +542,6 @@ __global__ __launch_bounds__(256) void k_codes(const int32_t* __restrict__ p, in
         const unsigned b = bi - nbl, nbr = gridDim.x - nbl;
         residual_block<T, D, FROM_P, NT>(remap_r ? xcd_tile(b, nbr) : b, coords, nv, gg, xh, x, bnd, vcodes, dbg_g,
                                           vcount, vsum);
-    }
-}
-
-// Learned mode: one workgroup per decision block of MC_LBLOCK vertices (its
-// MC_LBLOCK / MC_TILE tiles, 256 threads each, with the plain kernel's
-// vertex order).  The block's cost of the plain and of the shifted codes
-// (sum of bitlen(zigzag(code)) over coded vertices plus (32 + 8 sizeof(T))
-// per outlier), the choice (shifted only when strictly cheaper), then the
-// codes and each tile's outlier count; bit 31 of the count marks the first
-// tile of a learned block.  One back-interpolation serves both.
-constexpr int MC_LTILES = MC_LBLOCK / MC_TILE;
-static_assert(MC_LBLOCK % MC_TILE == 0 && MC_LTILES * MC_WG <= 1024, "decision block = whole tiles, <= 1024 threads");
-
-template <typename T, int D>
-__global__ __launch_bounds__(MC_LTILES * MC_WG) void k_residual_learned(
-    const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
-    const T* __restrict__ x, const DevBound* __restrict__ bnd, const int32_t* __restrict__ rho_q,
-    uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags, float* __restrict__ dbg_g,
-    unsigned int* __restrict__ count, unsigned int* __restrict__ vsum, long long ntv, unsigned remap)
-{
-    constexpr int NW = MC_LTILES * MC_WG / 64;
-    __shared__ long long s_sp[NW], s_sl[NW];
-    __shared__ int s_cnt[NW];
-    const DevBound b = *bnd;
-    const long long blk = tile_of(remap);
-    const int sub = threadIdx.x / MC_WG, lt = threadIdx.x % MC_WG;
-    const long long tile = blk * MC_LTILES + sub;
-    const int ocost = 32 + 8 * (int)sizeof(T);
-    long long v[MC_IPT];
-    bool act[MC_IPT];
-    T xv[MC_IPT];
-    int rq[MC_IPT];
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        v[i] = tile * MC_TILE + i * MC_WG + lt;
-        act[i] = v[i] < nv && b.ok;
-        const long long vc = act[i] ? v[i] : 0;
-        xv[i] = x[vc];
-        rq[i] = rho_q[vc];
-    }
-    float g[MC_IPT];
-    back_interp_n<D, MC_IPT, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
-    int qv[MC_IPT];
-    bool okv[MC_IPT];
-    long long cp = 0, cl = 0;
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        okv[i] = act[i] && quantize_residual<T>(xv[i], g[i], b, qv[i]);
-        if (!act[i]) continue;
-        if (okv[i]) {
-            const int l = qv[i] - rq[i];
-            cp += zz_bits(qv[i]);
-            cl += (l >= -(MC_R - 1) && l <= MC_R - 1) ? zz_bits(l) : ocost;
-        } else {
-            cp += ocost;
-            cl += ocost;
-        }
-    }
-    cp = wave_sum(cp);
-    cl = wave_sum(cl);
-    const int w = threadIdx.x >> 6;
-    if (lane_id() == 0) { s_sp[w] = cp; s_sl[w] = cl; }
-    __syncthreads();
-    long long sp = 0, sl = 0;
-#pragma unroll
-    for (int k = 0; k < NW; ++k) { sp += s_sp[k]; sl += s_sl[k]; }
-    const bool learned = sl < sp;                                // uniform over the workgroup
-    int nout = 0;
-#pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        if (!act[i]) continue;
-        if (dbg_g) dbg_g[v[i]] = g[i];
-        int qi = qv[i];
-        bool ok = okv[i];
-        if (ok && learned) {
-            qi -= rq[i];
-            ok = qi >= -(MC_R - 1) && qi <= MC_R - 1;
-        }
-        codes[v[i]] = ok ? (uint16_t)(qi + MC_R) : (uint16_t)0;
-        nout += ok ? 0 : 1;
-    }
-    nout = wave_sum(nout);
-    if (lane_id() == 0) s_cnt[w] = nout;
-    __syncthreads();
-    if (lt == 0 && tile < ntv) {
-        unsigned c = 0;
-#pragma unroll
-        for (int k = 0; k < MC_WG / 64; ++k) c += (unsigned)s_cnt[sub * (MC_WG / 64) + k];
-        if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
-        if (learned && sub == 0) {
-            c |= 0x80000000u;
-            atomicOr(&bflags[blk >> 5], 1u << (blk & 31));
-        }
-        count[tile] = c;
     }
 }
 
@@ -1048,23 +933,12 @@ hipError_t codes(const int32_t* p, int dim, int n0, int n1, int n2, uint16_t* gc
 }
 
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* pq,
-                    const void* x, int dtype, const DevBound* bnd, const int32_t* rho_q, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
-                    hipStream_t s)
+                    const void* x, int dtype, const DevBound* bnd, uint16_t* codes, float* dbg_g,
+                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s)
 {
     const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
     remap &= MC_KNOB_RESIDUAL;
     const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
-    if (rho_q) {
-        ProfScope ps("k_residual_learned", s);
-        const dim3 grid((unsigned)((nv + MC_LBLOCK - 1) / MC_LBLOCK));
-#define MC_RL(T, D) hipLaunchKernelGGL((k_residual_learned<T, D>), grid, dim3(MC_LTILES * MC_WG), 0, s, coords, nv, gg, \
-                                       xh, (const T*)x, bnd, rho_q, codes, bflags, dbg_g, count, vsum, ntv, remap)
-        if (dtype == MC_F64) { if (gg.dim == 2) MC_RL(double, 2); else MC_RL(double, 3); }
-        else { if (gg.dim == 2) MC_RL(float, 2); else MC_RL(float, 3); }
-#undef MC_RL
-        return hipGetLastError();
-    }
     ProfScope ps("k_residual", s);
     const dim3 grid((unsigned)ntv);
 #define MC_RQ(T, D, FP, NT) hipLaunchKernelGGL((k_residual<T, D, FP, NT>), grid, dim3(256), 0, s, coords, nv, gg, \

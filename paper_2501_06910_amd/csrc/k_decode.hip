@@ -557,29 +557,21 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
 }
 
 // Four vertices per thread (tile of 1024), every load issued before use.
-template <typename T, int D, bool LEARNED, bool NT>
+template <typename T, int D, bool NT>
 __device__ __forceinline__ void vdecode_block(long long tile, const float* __restrict__ coords, long long nv,
                                               const GridGeom& gg, const float* __restrict__ xh,
                                               const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                               const T* __restrict__ oval, const mc_result* __restrict__ res,
-                                              long long vcap, const int32_t* __restrict__ rho_q,
-                                              const uint32_t* __restrict__ bflags, T* __restrict__ xout)
+                                              long long vcap, T* __restrict__ xout)
 {
-    bool learned = false;
-    if (LEARNED) {
-        const long long blk = (tile * MC_TILE) / MC_LBLOCK;       // a tile lies inside one block
-        learned = (bflags[blk >> 5] >> (blk & 31)) & 1u;
-    }
     long long v[MC_IPT];
     bool act[MC_IPT];
-    int code[MC_IPT], rq[MC_IPT];
+    int code[MC_IPT];
 #pragma unroll
     for (int i = 0; i < MC_IPT; ++i) {
         v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
         act[i] = v[i] < nv;
-        const long long vc = act[i] ? v[i] : 0;
-        code[i] = ld_s<NT>(codes + vc);
-        rq[i] = (LEARNED && learned) ? rho_q[vc] : 0;
+        code[i] = ld_s<NT>(codes + (act[i] ? v[i] : 0));
     }
     float g[MC_IPT];
     back_interp_n<D, MC_IPT, false, NT>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
@@ -592,23 +584,20 @@ __device__ __forceinline__ void vdecode_block(long long tile, const float* __res
             const long long k = find_outlier(oidx, n, v[i]);
             st_s<NT>(xout + v[i], k >= 0 ? oval[k] : (T)0);
         } else {
-            const int q = code[i] - MC_R + rq[i];
+            const int q = code[i] - MC_R;
             st_s<NT>(xout + v[i], (T)((double)g[i] + (double)q * step2));
         }
     }
 }
 
-template <typename T, int D, bool LEARNED, bool NT>
+template <typename T, int D, bool NT>
 __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                  const float* __restrict__ xh, const uint16_t* __restrict__ codes,
                                                  const int32_t* __restrict__ oidx, const T* __restrict__ oval,
                                                  const mc_result* __restrict__ res, long long vcap,
-                                                 const int32_t* __restrict__ rho_q,
-                                                 const uint32_t* __restrict__ bflags, T* __restrict__ xout,
-                                                 unsigned remap)
+                                                 T* __restrict__ xout, unsigned remap)
 {
-    vdecode_block<T, D, LEARNED, NT>(tile_of(remap), coords, nv, gg, xh, codes, oidx, oval, res, vcap, rho_q, bflags,
-                                     xout);
+    vdecode_block<T, D, NT>(tile_of(remap), coords, nv, gg, xh, codes, oidx, oval, res, vcap, xout);
 }
 
 // Batched vertex decode: one launch over the tiles of every field (see the
@@ -617,11 +606,11 @@ template <typename T, int D>
 __device__ __forceinline__ void b_vdecode(const mck::BItemD* it, unsigned t)
 {
     if (it->knobs & mck::MC_KNOB_NT_VERT)
-        vdecode_block<T, D, false, true>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
-                                         (const T*)it->vval, it->res, it->vcap, nullptr, nullptr, (T*)it->xout);
+        vdecode_block<T, D, true>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
+                                  (const T*)it->vval, it->res, it->vcap, (T*)it->xout);
     else
-        vdecode_block<T, D, false, false>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
-                                          (const T*)it->vval, it->res, it->vcap, nullptr, nullptr, (T*)it->xout);
+        vdecode_block<T, D, false>(t, it->coords, it->nv, it->gg, it->xh, it->vcodes, it->vidx,
+                                   (const T*)it->vval, it->res, it->vcap, (T*)it->xout);
 }
 
 __global__ __launch_bounds__(256) void k_b_vdecode(const mck::BItemD* __restrict__ items,
@@ -931,25 +920,18 @@ hipError_t batch_vdecode(const BItemD* items, const unsigned* base, int n, unsig
 }
 
 hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
-                         const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
-                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
-                         hipStream_t s)
+                         const int32_t* oidx, const void* oval, long long vcap, const mc_result* res, void* xout,
+                         int dtype, unsigned remap, hipStream_t s)
 {
     const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
     remap &= MC_KNOB_VDECODE;
-    ProfScope ps(rho_q ? "k_vdecode_learned" : "k_vdecode", s);
+    ProfScope ps("k_vdecode", s);
     dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
-#define MC_VD0(T, D, L, NT) hipLaunchKernelGGL((k_vdecode<T, D, L, NT>), grid, dim3(256), 0, s, coords, nv, gg, xh, \
-                                               codes, oidx, (const T*)oval, res, vcap, rho_q, bflags, (T*)xout, remap)
-#define MC_VD(T, D, L) do { if (nt) MC_VD0(T, D, L, true); else MC_VD0(T, D, L, false); } while (0)
-    const bool L = rho_q != nullptr;
-    if (dtype == MC_F64) {
-        if (gg.dim == 2) { if (L) MC_VD(double, 2, true); else MC_VD(double, 2, false); }
-        else { if (L) MC_VD(double, 3, true); else MC_VD(double, 3, false); }
-    } else {
-        if (gg.dim == 2) { if (L) MC_VD(float, 2, true); else MC_VD(float, 2, false); }
-        else { if (L) MC_VD(float, 3, true); else MC_VD(float, 3, false); }
-    }
+#define MC_VD0(T, D, NT) hipLaunchKernelGGL((k_vdecode<T, D, NT>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, \
+                                            oidx, (const T*)oval, res, vcap, (T*)xout, remap)
+#define MC_VD(T, D) do { if (nt) MC_VD0(T, D, true); else MC_VD0(T, D, false); } while (0)
+    if (dtype == MC_F64) { if (gg.dim == 2) MC_VD(double, 2); else MC_VD(double, 3); }
+    else { if (gg.dim == 2) MC_VD(float, 2); else MC_VD(float, 3); }
 #undef MC_VD
 #undef MC_VD0
     return hipGetLastError();

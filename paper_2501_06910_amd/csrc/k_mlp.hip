@@ -434,45 +434,124 @@ __device__ __forceinline__ int rho_quant(float r)
     return (int)q;
 }
 
-// ---------------------------------------------------------------------------
-// inference: rho_q for every vertex (or only those in learned blocks)
-// ---------------------------------------------------------------------------
-// Register use is capped at 128 (4 waves per SIMD): the inputs, the layer
-// activations and the accumulators of a 64-vertex tile fit without spills.
-template <int D>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_infer(
-    mck::MlpDev m, const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
-    const uint32_t* __restrict__ only_blocks, int32_t* __restrict__ rho_q)
+// Learned vertex codes in one kernel: one 512-thread workgroup per
+// 4,096-vertex decision block, two workgroups per CU so that one's memory
+// phase overlaps the other's network.  The 8 waves first run the network on
+// the block's 64-vertex tiles (8 per wave) and keep each vertex's shift
+// rho_q and back-interpolation g in LDS.  Pass A quantizes every vertex
+// against g (q replaces g in LDS) and sums the block's cost of the plain and
+// of the shifted codes (bitlen(zigzag(code)) per coded vertex plus
+// (32 + 8 sizeof(T)) per outlier); pass B writes the codes of the cheaper
+// choice (shifted only when strictly cheaper) and each 1,024-vertex tile's
+// outlier count, bit 31 marking the first tile of a learned block.  rho_out
+// (optional) receives rho_q.
+template <typename T, int D>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_residual(mck::MlpDev m, const float* __restrict__ coords, long long nv,
+                                                      GridGeom gg, const float* __restrict__ xh,
+                                                      const T* __restrict__ x, const DevBound* __restrict__ bnd,
+                                                      uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags,
+                                                      float* __restrict__ dbg_g, int32_t* __restrict__ rho_out,
+                                                      unsigned int* __restrict__ count,
+                                                      unsigned int* __restrict__ vsum, long long ntv)
 {
+    constexpr int NT = 512, NW = NT / 64, PT = MC_LBLOCK / NT, LT = MC_LBLOCK / MC_TILE;
+    static_assert(MC_LBLOCK % NT == 0 && MC_TILE % NT == 0 && LT <= NW, "decision block layout");
+    constexpr int OUT = -0x7fffffff - 1;                        // q marker of an outlier
     __shared__ LdsFrag<D> sw;
-    load_frag<D, 256>(sw, m);
-    const long long ntiles = (nv + 63) / 64;
-    const int l = lane_id();
-    for (long long tile = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); tile < ntiles;
-         tile += (long long)gridDim.x * 4) {
-        const long long v0 = tile * 64;
-        if (only_blocks) {
-            const long long blk = v0 / MC_LBLOCK;
-            if (!((only_blocks[blk >> 5] >> (blk & 31)) & 1u)) continue;
-        }
+    __shared__ int s_rq[MC_LBLOCK];
+    __shared__ union { float g; int q; } s_gq[MC_LBLOCK];
+    __shared__ long long s_sp[NW], s_sl[NW];
+    __shared__ int s_cnt[LT][NW];
+    load_frag<D, NT>(sw, m);
+    const long long blk = blockIdx.x, vb = blk * MC_LBLOCK;
+    const int w = threadIdx.x >> 6, l = lane_id();
+    for (int t = w; t < MC_LBLOCK / 64; t += NW) {
+        const long long v0 = vb + t * 64;
+        if (v0 >= nv) break;                                     // uniform over the wave
         const long long v = v0 + l;
         const VGeom mine = vertex_geom<D>(coords, nv, v < nv ? v : nv - 1, gg, xh);
         bool valid[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
         bf16x4 zf[4][MlpShape<D>::KB];
-        if (D == 2 && v0 + 64 <= nv)        // whole tile: no vertex to mask (3-D: registers are short)
+        if (D == 2 && v0 + 64 <= nv)
             build_inputs<D, false>(zf, mine, true, gg, xh, m.kappa, valid);
         else
             build_inputs<D, true>(zf, mine, true, gg, xh, m.kappa, valid);
         float rho[4];
         forward_f<D>(sw, zf, rho);
-        // lane l holds vertex l of the tile as rho[l / 16]
         float r = rho[0];
         if ((l >> 4) == 1) r = rho[1];
         if ((l >> 4) == 2) r = rho[2];
         if ((l >> 4) == 3) r = rho[3];
-        if (v < nv) rho_q[v] = rho_quant(r);
+        const int rq = rho_quant(r);
+        s_rq[t * 64 + l] = rq;
+        s_gq[t * 64 + l].g = mine.g;
+        if (rho_out && v < nv) rho_out[v] = rq;
+    }
+    __syncthreads();
+    const DevBound b = *bnd;
+    const int ocost = 32 + 8 * (int)sizeof(T);
+    long long cp = 0, cl = 0;
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {                               // pass A: quantize and price both choices
+        const int k = i * NT + (int)threadIdx.x;
+        const long long v = vb + k;
+        if (v >= nv || !b.ok) continue;
+        const float g = s_gq[k].g;
+        int q;
+        const bool ok = quantize_residual<T>(x[v], g, b, q);
+        if (dbg_g) dbg_g[v] = g;
+        s_gq[k].q = ok ? q : OUT;
+        if (ok) {
+            const int lq = q - s_rq[k];
+            cp += zz_bits(q);
+            cl += (lq >= -(MC_R - 1) && lq <= MC_R - 1) ? zz_bits(lq) : ocost;
+        } else {
+            cp += ocost;
+            cl += ocost;
+        }
+    }
+    cp = wave_sum(cp);
+    cl = wave_sum(cl);
+    if (l == 0) { s_sp[w] = cp; s_sl[w] = cl; }
+    __syncthreads();
+    long long sp = 0, sl = 0;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) { sp += s_sp[k]; sl += s_sl[k]; }
+    const bool learned = sl < sp;                                // uniform over the workgroup
+    int nout[LT] = {};
+#pragma unroll
+    for (int i = 0; i < PT; ++i) {                               // pass B: codes of the cheaper choice
+        const int k = i * NT + (int)threadIdx.x;
+        const long long v = vb + k;
+        if (v >= nv || !b.ok) continue;
+        int q = s_gq[k].q;
+        bool ok = q != OUT;
+        if (ok && learned) {
+            q -= s_rq[k];
+            ok = q >= -(MC_R - 1) && q <= MC_R - 1;
+        }
+        codes[v] = ok ? (uint16_t)(q + MC_R) : (uint16_t)0;
+        nout[k / MC_TILE] += ok ? 0 : 1;
+    }
+#pragma unroll
+    for (int tl = 0; tl < LT; ++tl) {
+        const int c = wave_sum(nout[tl]);
+        if (l == 0) s_cnt[tl][w] = c;
+    }
+    __syncthreads();
+    const long long tile = blk * LT + threadIdx.x;
+    if (threadIdx.x < LT && tile < ntv) {
+        unsigned c = 0;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) c += (unsigned)s_cnt[threadIdx.x][k];
+        if (c) atomicAdd(&vsum[tile / MC_SC_TILES], c);
+        if (learned && threadIdx.x == 0) {
+            c |= 0x80000000u;
+            atomicOr(&bflags[blk >> 5], 1u << (blk & 31));
+        }
+        count[tile] = c;
     }
 }
 
@@ -1074,17 +1153,18 @@ hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, ui
     return hipGetLastError();
 }
 
-hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
-                     const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s)
+hipError_t mlp_residual(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                        const void* x, int dtype, const DevBound* bnd, uint16_t* codes, uint32_t* bflags,
+                        float* dbg_g, int32_t* rho_out, unsigned int* count, unsigned int* vsum, hipStream_t s)
 {
-    ProfScope ps(only_blocks ? "k_mlp_infer_d" : "k_mlp_infer_c", s);
-    long long nb = (nv + 255) / 256;
-    if (nb > 2048) nb = 2048;
-    if (nb < 1) nb = 1;
-    if (m.dim == 2)
-        hipLaunchKernelGGL(k_mlp_infer<2>, dim3((unsigned)nb), dim3(256), 0, s, m, coords, nv, gg, xh, only_blocks, rho_q);
-    else
-        hipLaunchKernelGGL(k_mlp_infer<3>, dim3((unsigned)nb), dim3(256), 0, s, m, coords, nv, gg, xh, only_blocks, rho_q);
+    ProfScope ps("k_mlp_residual", s);
+    const long long ntv = (nv + MC_TILE - 1) / MC_TILE;
+    const dim3 grid((unsigned)((nv + MC_LBLOCK - 1) / MC_LBLOCK));
+#define MC_MR(T, D) hipLaunchKernelGGL((k_mlp_residual<T, D>), grid, dim3(512), 0, s, m, coords, nv, gg, xh, \
+                                       (const T*)x, bnd, codes, bflags, dbg_g, rho_out, count, vsum, ntv)
+    if (m.dim == 2) { if (dtype == MC_F64) MC_MR(double, 2); else MC_MR(float, 2); }
+    else { if (dtype == MC_F64) MC_MR(double, 3); else MC_MR(float, 3); }
+#undef MC_MR
     return hipGetLastError();
 }
 

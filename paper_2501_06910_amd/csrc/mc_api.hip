@@ -681,7 +681,6 @@ extern "C" mc_status mc_plan_create(const float* d_coords, const int32_t* d_cell
     p->ntv = (nv + MC_TILE - 1) / MC_TILE;
     p->nblk = (nv + MC_LBLOCK - 1) / MC_LBLOCK;
     PCHK(plan_alloc(p, &p->p, (size_t)ngw));
-    PCHK(plan_alloc(p, &p->rho, (size_t)nv));
     PCHK(plan_alloc(p, &p->ctl, 64));
     p->rbuf = (RangeOut*)p->ctl;                       // 2 slots of 3 words
     p->bound = (DevBound*)(p->ctl + 16);               // 11 words at word 16
@@ -980,19 +979,17 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
         return MC_OK;
     }
     ECHK(grid_codes(p, codes, s));
-    const int32_t* rho = nullptr;
-    if (prm->model) {
-        mc_status ms = mc_model_infer(prm->model, p, codes->result, nullptr, s);
-        if (ms != MC_OK) return ms;
-        rho = p->rho;
-    }
-    if (codes->residual_predictor == MC_RESPRED_DELTA) {
+    if (codes->residual_predictor == MC_RESPRED_DELTA) {         // no model with this predictor
         ECHK(mck::residual_delta(p->coords, p->nv, p->gg, p->xh, nullptr, d_field, dtype, p->bound,
                                  codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->err, s));
+    } else if (prm->model) {
+        // network shifts, block choice and vertex codes in one pass
+        ECHK(mck::mlp_residual(prm->model->md, p->coords, p->nv, p->gg, p->xh, d_field, dtype, p->bound,
+                               codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, codes->rho_q, p->vcount,
+                               p->vsum, s));
     } else {
-        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, from_p ? p->p : nullptr, d_field, dtype, p->bound, rho,
-                           codes->vert_codes, codes->block_flags, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs,
-                           s));
+        ECHK(mck::residual(p->coords, p->nv, p->gg, p->xh, from_p ? p->p : nullptr, d_field, dtype, p->bound,
+                           codes->vert_codes, codes->dbg_vertex_g, p->vcount, p->vsum, p->knobs, s));
     }
     ECHK(mck::compact(p->p, p->dim, (int)p->grid.dims[0], (int)p->grid.dims[1], p->ng, codes->grid_predictor,
                       codes->grid_ref, codes->grid_codes, p->gcount, p->gsum, codes->g_out_idx, codes->g_out_delta,
@@ -1000,7 +997,6 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
                       codes->v_out_idx, codes->v_out_val, codes->v_out_cap, p->err, codes->result, s));
     if (codes->dbg_grid_p) ECHK(hipMemcpyAsync(codes->dbg_grid_p, p->p, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
     if (codes->xhat_out) ECHK(hipMemcpyAsync(codes->xhat_out, p->xh, (size_t)p->ng * 4, hipMemcpyDeviceToDevice, s));
-    if (codes->rho_q && rho) ECHK(hipMemcpyAsync(codes->rho_q, p->rho, (size_t)p->nv * 4, hipMemcpyDeviceToDevice, s));
 #undef ECHK
     return MC_OK;
 }
@@ -1105,12 +1101,6 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
                               codes->v_out_idx, codes->v_out_val, codes->result, codes->v_out_cap, d_out, dtype, s));
         return MC_OK;
     }
-    const int32_t* rho = nullptr;
-    if (model) {
-        mc_status ms = mc_model_infer(model, p, codes->result, codes->block_flags, s);
-        if (ms != MC_OK) return ms;
-        rho = p->rho;
-    }
     if (codes->residual_predictor == MC_RESPRED_DELTA) {
         ECHK(mck::vertex_decode_delta(p->coords, p->nv, p->gg, p->xh, nullptr, codes->vert_codes, codes->v_out_idx,
                                       codes->v_out_val, codes->v_out_cap, codes->result, p->dagg, p->dcarry, d_out,
@@ -1118,7 +1108,7 @@ mc_status mc_decompress_enqueue(mc_plan p, const mc_codes* codes, mc_model model
         return MC_OK;
     }
     ECHK(mck::vertex_decode(p->coords, p->nv, p->gg, p->xh, codes->vert_codes, codes->v_out_idx, codes->v_out_val,
-                            codes->v_out_cap, codes->result, rho, codes->block_flags, d_out, dtype, p->knobs, s));
+                            codes->v_out_cap, codes->result, d_out, dtype, p->knobs, s));
 #undef ECHK
     return MC_OK;
 }

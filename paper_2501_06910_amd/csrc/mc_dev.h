@@ -114,6 +114,27 @@ __device__ __forceinline__ long long find_outlier(const int32_t* __restrict__ oi
     return (lo < n && (long long)oidx[lo] == j) ? lo : -1;
 }
 
+// Bits of the zigzag code of k (the cost of a code in the learned block
+// choice).
+__device__ __forceinline__ int zz_bits(int k)
+{
+    const unsigned z = ((unsigned)k << 1) ^ (unsigned)(k >> 31);
+    return 32 - __clz(z);
+}
+
+// Residual quantisation of one vertex: r = x - g, q = rint(r / (2 tau2)),
+// x' = (T)(g + q * 2 tau2); accepted iff |q| <= R-1 and |x - x'| <= tau2.
+template <typename T>
+__device__ __forceinline__ bool quantize_residual(T xv, float g, const DevBound& b, int& qi)
+{
+    const double r = (double)xv - (double)g;
+    const double q = rint(r * b.inv2);
+    const T xr = (T)((double)g + q * b.step2);
+    const bool ok = fabs(q) <= (double)(MC_R - 1) && fabs((double)xv - (double)xr) <= b.tau2;
+    qi = ok ? (int)q : 0;
+    return ok;
+}
+
 // Prediction error of grid node j: its code, or its outlier entry.
 __device__ __forceinline__ int delta_at(const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                         const int32_t* __restrict__ odelta, long long nout, long long j)

@@ -28,7 +28,6 @@ struct mc_plan_s {
     int32_t* cell = nullptr;       // [ng]
     // workspace (device)
     int32_t* p = nullptr;          // prequantised grid [ng]
-    int32_t* rho = nullptr;        // learned shift [nv]
     float* xh = nullptr;           // reconstructed grid x1' [ng]
     bool xh_valid = false;         // xh holds the x1' of the last enqueued call (a plain
                                    // compression writes only p: mc_plan_ensure_xh converts)
@@ -83,5 +82,3 @@ int mc_model_dim(mc_model m);
 // Makes p->xh the x1' of the last enqueued compression (converting p when
 // that call wrote only p).  Stream-ordered.
 mc_status mc_plan_ensure_xh(mc_plan p, hipStream_t s);
-// rho_q for every vertex (only_blocks == NULL) or the learned blocks only.
-mc_status mc_model_infer(mc_model m, mc_plan p, const mc_result* res, const uint32_t* only_blocks, hipStream_t s);

@@ -71,9 +71,8 @@ hipError_t codes(const int32_t* p, int dim, int n0, int n1, int n2, uint16_t* gc
 // prequantised grid and converted as x1' = (float)(c + p * 2 tau1); else
 // from x1' (xh).
 hipError_t residual(const float* coords, long long nv, GridGeom gg, const float* xh, const int32_t* pq,
-                    const void* x, int dtype, const DevBound* bnd, const int32_t* rho_q, uint16_t* codes,
-                    uint32_t* bflags, float* dbg_g, unsigned int* count, unsigned int* vsum, unsigned remap,
-                    hipStream_t s);
+                    const void* x, int dtype, const DevBound* bnd, uint16_t* codes, float* dbg_g,
+                    unsigned int* count, unsigned int* vsum, unsigned remap, hipStream_t s);
 // x1' = (float)(c + p * 2 tau1) over the whole grid (bound from bnd).
 hipError_t xhat_from_p(const int32_t* p, long long ng, const DevBound* bnd, float* xh, hipStream_t s);
 // gpred: the mc_grid_predictor whose errors the grid outliers carry (gref:
@@ -201,9 +200,8 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
                        const mc_result* res, int dim, int n0, int n1, int n2, int32_t* pz, float* xh, DecodeWs& ws,
                        unsigned remap, hipStream_t s);
 hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const float* xh, const uint16_t* codes,
-                         const int32_t* oidx, const void* oval, long long vcap, const mc_result* res,
-                         const int32_t* rho_q, const uint32_t* bflags, void* xout, int dtype, unsigned remap,
-                         hipStream_t s);
+                         const int32_t* oidx, const void* oval, long long vcap, const mc_result* res, void* xout,
+                         int dtype, unsigned remap, hipStream_t s);
 
 // ---- 1-D serialisation baseline (k_serial.hip) ----------------------------
 hipError_t serial_codes(const void* x, int dtype, long long n, const DevBound* bnd, uint16_t* codes, unsigned* count,
@@ -274,8 +272,11 @@ struct MlpDev {
 };
 hipError_t mlp_pack(const float* params, int dim, uint16_t* w1, uint16_t* w2, uint16_t* w3, uint16_t* w4,
                     float* b1, float* b2, float* b3, float* b4, hipStream_t s);
-hipError_t mlp_infer(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
-                     const uint32_t* only_blocks, int32_t* rho_q, hipStream_t s);
+// Learned vertex codes (network, block choice, codes, tile counts) in one
+// launch; rho_out optional.
+hipError_t mlp_residual(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
+                        const void* x, int dtype, const DevBound* bnd, uint16_t* codes, uint32_t* bflags,
+                        float* dbg_g, int32_t* rho_out, unsigned int* count, unsigned int* vsum, hipStream_t s);
 // Learned decompress of every vertex (network shifts in learned blocks).
 hipError_t mlp_vdecode(const MlpDev& m, const float* coords, long long nv, GridGeom gg, const float* xh,
                        const uint32_t* bflags, const uint16_t* codes, const int32_t* oidx, const void* oval,

@@ -137,14 +137,6 @@ extern "C" mc_status mc_model_import(const void* h_buf, size_t n, mc_model* out)
     return st == MC_ERR_ARG ? mc_fail(MC_ERR_FORMAT, "model file holds invalid values") : st;
 }
 
-mc_status mc_model_infer(mc_model m, mc_plan p, const mc_result* res, const uint32_t* only_blocks, hipStream_t s)
-{
-    (void)res;
-    hipError_t e = mck::mlp_infer(m->md, p->coords, p->nv, p->gg, p->xh, only_blocks, p->rho, s);
-    if (e != hipSuccess) return mc_fail(MC_ERR_DEVICE, "mlp_infer: %s", hipGetErrorString(e));
-    return MC_OK;
-}
-
 extern "C" mc_status mc_model_forward(mc_model m, const float* d_z, int64_t batch, float* d_rho, hipStream_t s)
 {
     if (!m || !d_z || !d_rho || batch < 0) return mc_fail(MC_ERR_ARG, "invalid forward arguments");
