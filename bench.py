@@ -922,13 +922,27 @@ def main():
     ms_step_ev = ev2.elapsed_time(ev3) / args.steps
     log(f"profiled pass: {ms_step_ev:.4f} ms/step with per-launch events")
     prof = M.profile_read()
+    # then each kernel in a pass of its own, events around its launches only
+    # (events around every launch lengthen some kernels by up to 15 %)
+    iso = {}
+    for name in prof:
+        M.profile_only(name)
+        M.profile_reset()
+        M.profile_enable(True)
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        M.profile_enable(False)
+        iso[name] = M.profile_read()[name]
+    M.profile_only(None)
     kernels = {}
     comp_ms = dec_ms = 0.0
-    for name, (cnt, tot) in prof.items():
+    for name, (cnt, tot) in iso.items():
         avg = tot / cnt
         b = alg_bytes(name, nv, ng, D, sT)
         kernels[name] = {"avg_ms": round(avg, 5), "launches": cnt, "alg_bytes": b,
-                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None}
+                         "GBps": round(b / (avg * 1e-3) / 1e9, 1) if b else None,
+                         "avg_ms_events_on_all": round(prof[name][1] / prof[name][0], 5)}
         if name.startswith(COMPRESS_PREFIXES):
             comp_ms += avg
         elif name.startswith(DECOMPRESS_PREFIXES):

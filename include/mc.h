@@ -502,6 +502,9 @@ mc_status mc_serial_compress_noalloc(const void* d_field, mc_dtype dtype, int64_
  * launch stream; mc_profile_read returns per-kernel launch counts and
  * summed milliseconds (sync). */
 mc_status mc_profile_enable(int32_t on);
+/* Brackets only the launches of the named kernel (NULL or "": every kernel),
+ * so that one kernel is timed without events around its neighbours. */
+mc_status mc_profile_only(const char* name);
 mc_status mc_profile_reset(void);
 /* Writes up to cap entries: names (each a static string), counts, total ms. */
 int32_t mc_profile_read(const char** names, int64_t* counts, double* total_ms, int32_t cap);

@@ -56,6 +56,7 @@ struct ProfRec {
 };
 std::mutex g_pm;
 bool g_prof_on = false;
+std::string g_prof_only;        // empty: every kernel; else only launches of this name
 std::vector<ProfRec> g_recs;
 std::vector<hipEvent_t> g_pool;
 
@@ -66,8 +67,10 @@ hipEvent_t pool_get()
         g_pool.pop_back();
         return e;
     }
+    // timing only: no system-scope fence at record, which would write back
+    // and invalidate the caches between the launch and its neighbours
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 }  // namespace
@@ -76,6 +79,7 @@ mck::ProfScope::ProfScope(const char* n, hipStream_t s) : name(n), stream(s), id
 {
     if (!g_prof_on || mc_capturing) return;
     std::lock_guard<std::mutex> lk(g_pm);
+    if (!g_prof_only.empty() && g_prof_only != n) return;
     hipEvent_t a = pool_get(), b = pool_get();
     if (!a || !b) return;
     (void)hipEventRecord(a, s);
@@ -119,6 +123,13 @@ extern "C" mc_status mc_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_pm);
     g_prof_on = on != 0;
+    return MC_OK;
+}
+
+extern "C" mc_status mc_profile_only(const char* name)
+{
+    std::lock_guard<std::mutex> lk(g_pm);
+    g_prof_only = name ? name : "";
     return MC_OK;
 }
 
@@ -754,7 +765,7 @@ extern "C" mc_status mc_plan_tune_bins(const float* d_coords, const int32_t* d_c
     unsigned* ctr = keep.get<unsigned>(16, e);
     TCHK(e);
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    for (int k = 0; k < 4; ++k) TCHK(hipEventCreate(&ev[k]));
+    for (int k = 0; k < 4; ++k) TCHK(hipEventCreateWithFlags(&ev[k], hipEventDisableSystemFence));
     struct EvFree {
         hipEvent_t* ev;
         ~EvFree() { for (int k = 0; k < 4; ++k) if (ev[k]) (void)hipEventDestroy(ev[k]); }
@@ -1152,7 +1163,8 @@ extern "C" mc_status mc_plan_tune(mc_plan p, const void* d_field, mc_dtype dtype
     // untimed pass; the per-launch profiler stays off while timing, since its
     // events would add to every launch)
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (hipEventCreateWithFlags(&e0, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e1, hipEventDisableSystemFence) != hipSuccess) {
         if (e0) (void)hipEventDestroy(e0);
         return mc_fail(MC_ERR_DEVICE, "hipEventCreate failed");
     }

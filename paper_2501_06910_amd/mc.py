@@ -156,6 +156,7 @@ _SIGS = {
     "mc_serial_compress_noalloc": (C.c_int, [_P, C.c_int, C.c_int64, C.c_double, C.c_int32, _P, _P]),
     "mc_profile_enable": (C.c_int, [C.c_int32]),
     "mc_profile_reset": (C.c_int, []),
+    "mc_profile_only": (C.c_int, [C.c_char_p]),
     "mc_profile_read": (C.c_int32, [_P, _P, _P, C.c_int32]),
     "mc_huffman_size": (C.c_int64, [_P, C.c_int64]),
     "mc_huffman_encode": (C.c_int64, [_P, C.c_int64, _P, C.c_int64]),
@@ -897,6 +898,11 @@ def serial_stream_bytes(host: dict, value_bytes: int | None = None) -> dict:
 
 def profile_enable(on=True):
     lib().mc_profile_enable(1 if on else 0)
+
+
+def profile_only(name=None):
+    """Bracket only the launches of kernel `name` (None: every kernel)."""
+    lib().mc_profile_only(name.encode() if name else None)
 
 
 def profile_reset():
