@@ -320,7 +320,10 @@ mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
  * kernel streams once: set = non-temporal loads and stores, so the stream
  * does not evict lines that other threads read again; 7 the resample's
  * mapping, 8 the coordinates, field, codes and decoded values of the
- * residual codes and the vertex decode.
+ * residual codes and the vertex decode.  Bits 9-12 pick launch shapes:
+ * bits 9-10 the vertex decode's vertices per thread (0: 4, 1: 2, 2: 8,
+ * 3: 4), bits 11-12 the field range's partial blocks (0: 2048, 1: 1024,
+ * 2: 512, 3: 2048).  Any other bit is rejected.
  * Codes and values never depend on the knobs.  Default: 0x1ec (on a
  * 16M-vertex tetrahedral mesh with a 256^3 grid: the fastest mask of a
  * sweep with XCD order for the two vertex kernels, which leaves their time

@@ -838,9 +838,9 @@ __global__ __launch_bounds__(256) void k_b_scatter(const BItemC* __restrict__ it
 namespace mck {
 
 hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
-                 DevBound* bnd, unsigned int* zero, long long nzero, hipStream_t s)
+                 DevBound* bnd, unsigned int* zero, long long nzero, unsigned knobs, hipStream_t s)
 {
-    const int nblocks = MC_RANGE_BLOCKS;      // one batch of 8 quads per thread at 16M values
+    const int nblocks = knob_range_blocks(knobs);   // 2048: one batch of 8 quads per thread at 16M values
     {
         ProfScope ps("k_range", s);
         const bool V = ((uintptr_t)x & 15u) == 0;

@@ -556,28 +556,28 @@ __global__ __launch_bounds__(256, NXS == 1 ? 4 : 2) void k_d3_apply(const uint16
     }
 }
 
-// Four vertices per thread (tile of 1024), every load issued before use.
-template <typename T, int D, bool NT>
+// VPT vertices per thread (tile of 256 VPT), every load issued before use.
+template <typename T, int D, bool NT, int VPT = MC_IPT>
 __device__ __forceinline__ void vdecode_block(long long tile, const float* __restrict__ coords, long long nv,
                                               const GridGeom& gg, const float* __restrict__ xh,
                                               const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx,
                                               const T* __restrict__ oval, const mc_result* __restrict__ res,
                                               long long vcap, T* __restrict__ xout)
 {
-    long long v[MC_IPT];
-    bool act[MC_IPT];
-    int code[MC_IPT];
+    long long v[VPT];
+    bool act[VPT];
+    int code[VPT];
 #pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
-        v[i] = tile * MC_TILE + i * MC_WG + threadIdx.x;
+    for (int i = 0; i < VPT; ++i) {
+        v[i] = tile * (VPT * MC_WG) + i * MC_WG + threadIdx.x;
         act[i] = v[i] < nv;
         code[i] = ld_s<NT>(codes + (act[i] ? v[i] : 0));
     }
-    float g[MC_IPT];
-    back_interp_n<D, MC_IPT, false, NT>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
+    float g[VPT];
+    back_interp_n<D, VPT, false, NT>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
     const double step2 = 2.0 * res->tau2;
 #pragma unroll
-    for (int i = 0; i < MC_IPT; ++i) {
+    for (int i = 0; i < VPT; ++i) {
         if (!act[i]) continue;
         if (code[i] == 0) {
             const long long n = res->n_vertex_outliers < vcap ? res->n_vertex_outliers : vcap;
@@ -590,14 +590,14 @@ __device__ __forceinline__ void vdecode_block(long long tile, const float* __res
     }
 }
 
-template <typename T, int D, bool NT>
+template <typename T, int D, bool NT, int VPT>
 __global__ __launch_bounds__(256) void k_vdecode(const float* __restrict__ coords, long long nv, GridGeom gg,
                                                  const float* __restrict__ xh, const uint16_t* __restrict__ codes,
                                                  const int32_t* __restrict__ oidx, const T* __restrict__ oval,
                                                  const mc_result* __restrict__ res, long long vcap,
                                                  T* __restrict__ xout, unsigned remap)
 {
-    vdecode_block<T, D, NT>(tile_of(remap), coords, nv, gg, xh, codes, oidx, oval, res, vcap, xout);
+    vdecode_block<T, D, NT, VPT>(tile_of(remap), coords, nv, gg, xh, codes, oidx, oval, res, vcap, xout);
 }
 
 // Batched vertex decode: one launch over the tiles of every field (see the
@@ -924,15 +924,20 @@ hipError_t vertex_decode(const float* coords, long long nv, GridGeom gg, const f
                          int dtype, unsigned remap, hipStream_t s)
 {
     const bool nt = (remap & MC_KNOB_NT_VERT) != 0;
+    const int vpt = knob_vpt(remap);
     remap &= MC_KNOB_VDECODE;
     ProfScope ps("k_vdecode", s);
-    dim3 grid((unsigned)((nv + MC_TILE - 1) / MC_TILE));
-#define MC_VD0(T, D, NT) hipLaunchKernelGGL((k_vdecode<T, D, NT>), grid, dim3(256), 0, s, coords, nv, gg, xh, codes, \
-                                            oidx, (const T*)oval, res, vcap, (T*)xout, remap)
-#define MC_VD(T, D) do { if (nt) MC_VD0(T, D, true); else MC_VD0(T, D, false); } while (0)
+    const long long per = 256LL * vpt;
+    dim3 grid((unsigned)((nv + per - 1) / per));
+#define MC_VD0(T, D, NT, V) hipLaunchKernelGGL((k_vdecode<T, D, NT, V>), grid, dim3(256), 0, s, coords, nv, gg, xh, \
+                                               codes, oidx, (const T*)oval, res, vcap, (T*)xout, remap)
+#define MC_VD1(T, D, V) do { if (nt) MC_VD0(T, D, true, V); else MC_VD0(T, D, false, V); } while (0)
+#define MC_VD(T, D) do { if (vpt == 2) MC_VD1(T, D, 2); else if (vpt == 8) MC_VD1(T, D, 8); else MC_VD1(T, D, 4); } \
+                    while (0)
     if (dtype == MC_F64) { if (gg.dim == 2) MC_VD(double, 2); else MC_VD(double, 3); }
     else { if (gg.dim == 2) MC_VD(float, 2); else MC_VD(float, 3); }
 #undef MC_VD
+#undef MC_VD1
 #undef MC_VD0
     return hipGetLastError();
 }

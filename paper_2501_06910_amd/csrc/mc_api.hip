@@ -945,7 +945,7 @@ mc_status mc_compress_enqueue(mc_plan p, const void* d_field, mc_dtype dtype, co
     hipError_t e;
 #define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     RangeOut* cur = p->rbuf;
-    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, bp, p->bound, p->small, p->nsmall, s));
+    ECHK(mck::range(d_field, dtype, p->nv, p->range_partial, cur, bp, p->bound, p->small, p->nsmall, p->knobs, s));
     if (p->ops == MC_OPS_CLUSTER) {
         double* x1 = prm->residual == MC_RESIDUAL_OPEN ? p->x1 : nullptr;
         ECHK(mck::cluster_mean(p->noff, p->vlist, p->ng, d_field, dtype, p->bound, p->p, p->xh, x1,

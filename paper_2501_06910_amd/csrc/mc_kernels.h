@@ -52,8 +52,9 @@ hipError_t fill_midrange(int dim, const int32_t* unres, long long n_unres, int32
 
 // ---- compression (k_compress.hip) -----------------------------------------
 // Field range and error split (k_range, then one workgroup folds the partials).
+// knobs: the partial-block count (partial holds 3 * MC_RANGE_BLOCKS words)
 hipError_t range(const void* x, int dtype, long long n, unsigned long long* partial, RangeOut* cur, BoundParams bp,
-                 DevBound* bnd, unsigned int* zero, long long nzero, hipStream_t s);
+                 DevBound* bnd, unsigned int* zero, long long nzero, unsigned knobs, hipStream_t s);
 // xh may be NULL (x1' not written)
 hipError_t resample(const int32_t* vid, const float* w, int dim, long long ng, const void* x, int dtype,
                     const DevBound* bnd, int32_t* p, float* xh, float* dbg_v, uint32_t* bflags,
@@ -148,9 +149,10 @@ struct BItemD {
 hipError_t batch_vdecode(const BItemD* items, const unsigned* base, int n, unsigned nblocks, hipStream_t s);
 
 // ---- decompression (k_decode.hip) -----------------------------------------
-// Launch-order knobs (results do not depend on them): bit k set = kernel k
-// takes its tiles in XCD-contiguous order (xcd_tile), clear = in launch
-// order.  Chosen per plan by mc_plan_tune.
+// Launch knobs (results do not depend on them): bit k set = kernel k takes
+// its tiles in XCD-contiguous order (xcd_tile), clear = in launch order;
+// bits 7 and 8 the cache policy of streamed arrays; bits 9-10 and 11-12
+// launch shapes.  Chosen per plan by mc_plan_tune.
 enum {
     MC_KNOB_RESAMPLE = 1u << 0,
     MC_KNOB_LORENZO = 1u << 1,
@@ -162,12 +164,26 @@ enum {
     MC_KNOB_NT_MAP = 1u << 7,       // resample: the mapping streamed with the non-temporal policy
     MC_KNOB_NT_VERT = 1u << 8,      // residual codes and vertex decode: coordinates, field, codes and
                                     // decoded values streamed with the non-temporal policy
-    MC_KNOB_ALL = 0x1ffu,           // every valid bit
+    MC_KNOB_VPT = 3u << 9,          // vertex decode, vertices per thread: 0 -> 4, 1 -> 2, 2 -> 8, 3 -> 4
+    MC_KNOB_RANGE = 3u << 11,       // field range, partial blocks: 0 -> 2048, 1 -> 1024, 2 -> 512, 3 -> 2048
+    MC_KNOB_ALL = 0x1fffu,          // every valid bit
     MC_KNOB_DEFAULT = 0x1ecu        // a new plan: on the 16M-vertex tet mesh launch order for resample and
                                     // Lorenzo, XCD order for the vertex kernels (same time as launch order,
                                     // each grid line fetched once per pass instead of 1.4x) and for the
                                     // 3-D decode, non-temporal streams
 };
+
+// Launch shapes of a knob word.
+inline int knob_vpt(unsigned k)
+{
+    const unsigned f = (k & MC_KNOB_VPT) >> 9;
+    return f == 1u ? 2 : (f == 2u ? 8 : 4);
+}
+inline int knob_range_blocks(unsigned k)
+{
+    const unsigned f = (k & MC_KNOB_RANGE) >> 11;
+    return f == 1u ? MC_RANGE_BLOCKS / 2 : (f == 2u ? MC_RANGE_BLOCKS / 4 : MC_RANGE_BLOCKS);
+}
 
 #define MC_D2_R 8                  // 2-D decode: rows per chunk (rows of DecodeWs in 2-D)
 struct DecodeWs {

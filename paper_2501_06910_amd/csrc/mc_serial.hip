@@ -99,7 +99,7 @@ extern "C" mc_status mc_serial_compress(mc_serial s, const void* d_field, mc_dty
     unsigned int* vsum = s->small + 16;
     hipError_t e;
 #define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
-    ECHK(mck::range(d_field, dtype, n, s->partial, cur, bp, bound, s->small, s->nsmall, stream));
+    ECHK(mck::range(d_field, dtype, n, s->partial, cur, bp, bound, s->small, s->nsmall, 0u, stream));
     ECHK(mck::serial_codes(d_field, dtype, n, bound, codes->vert_codes, s->count, vsum, err, codes->result, stream));
     ECHK(mck::compact(nullptr, 1, 1, 1, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_field, dtype, n,
                       codes->vert_codes, s->count, vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, err,
@@ -185,7 +185,7 @@ extern "C" mc_status mc_serial_compress_noalloc(const void* d_field, mc_dtype dt
     hipError_t e;
 #define ECHK(x) do { if ((e = (x)) != hipSuccess) return mc_fail(MC_ERR_DEVICE, "%s: %s", #x, hipGetErrorString(e)); } while (0)
     // k_range clears small[0 .. nsmall) (err, the outlier sums) before anything reads it
-    ECHK(mck::range(d_field, dtype, n, partial, cur, bp, bound, small, nsmall, stream));
+    ECHK(mck::range(d_field, dtype, n, partial, cur, bp, bound, small, nsmall, 0u, stream));
     ECHK(mck::serial_codes(d_field, dtype, n, bound, codes->vert_codes, count, vsum, err, codes->result, stream));
     ECHK(mck::compact(nullptr, 1, 1, 1, 0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, d_field, dtype, n,
                       codes->vert_codes, count, vsum, codes->v_out_idx, codes->v_out_val, codes->v_out_cap, err,

@@ -426,8 +426,8 @@ def tuning_key(plan: "Plan", dtype) -> str:
     arch = torch.cuda.get_device_properties(torch.cuda.current_device()).gcnArchName.split(":")[0]
     g = plan.grid
     dims = "x".join(str(int(g.dims[d])) for d in range(plan.dim))
-    # "k9": masks over the nine knob bits of this library version
-    return f"{arch}|k9|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
+    # "k13": masks over the thirteen knob bits of this library version
+    return f"{arch}|k13|dim{plan.dim}|{dims}|nv{plan.n_vertices}|{str(dtype).replace('torch.', '')}"
 
 
 BIN_CANDIDATES = (1, 2, 3, 4)

@@ -1,5 +1,6 @@
-"""GPU tests of the launch-order autotuner: every knob setting gives the
-same codes, outliers and decoded values (the knobs only reorder tiles), and
+"""GPU tests of the launch autotuner: every knob setting gives the same
+codes, outliers and decoded values (the knobs reorder tiles, pick cache
+policies and launch shapes), and
 mc_plan_tune picks a valid mask, restores the profiler state, and leaves
 the results unchanged."""
 import numpy as np
@@ -41,7 +42,9 @@ def test_knobs_do_not_change_results(dim):
     assert plan.remap_mask == 0x1EC
     ref_h, ref_x = _run(plan, x, 1e-5)
     rng = np.random.default_rng(0)
-    for mask in [0, 0x7F, 0x1FF, 0x55, 0x12A, 0x180] + [int(m) for m in rng.integers(0, 512, 3)]:
+    # bits 9-10: vertex decode 2 / 8 / 4 vertices per thread; 11-12: 1024 / 512 / 2048 range blocks
+    for mask in ([0, 0x7F, 0x1FF, 0x55, 0x12A, 0x180, 0x3EC, 0x5EC, 0x7EC, 0x9EC, 0x11EC, 0x1FFF, 0xA00]
+                 + [int(m) for m in rng.integers(0, 0x2000, 4)]):
         plan.remap_mask = mask
         h, xo = _run(plan, x, 1e-5)
         assert h["result"] == ref_h["result"], mask
@@ -49,7 +52,7 @@ def test_knobs_do_not_change_results(dim):
             assert np.array_equal(h[k], ref_h[k]), (mask, k)
         assert np.array_equal(xo.view(np.uint8), ref_x.view(np.uint8)), mask
     with pytest.raises(RuntimeError):
-        plan.remap_mask = 0x200
+        plan.remap_mask = 0x2000
 
 
 def test_tune_picks_a_mask_and_keeps_results():
@@ -64,7 +67,7 @@ def test_tune_picks_a_mask_and_keeps_results():
     torch.cuda.synchronize()
     assert "k_resample" in M.profile_read()      # profiling was left on
     M.profile_enable(False)
-    assert 0 <= mask <= 0x1FF and plan.remap_mask == mask
+    assert 0 <= mask <= 0x1FFF and plan.remap_mask == mask
     print(f"[tune] chosen remap mask 0x{mask:02x}")
     h, xo = _run(plan, x, 1e-4)
     assert np.array_equal(h["vert_codes"], ref_h["vert_codes"])
