@@ -324,11 +324,10 @@ mc_status mc_decompress(mc_plan plan, const mc_codes* codes, mc_model model,
  * bits 9-10 the vertex decode's vertices per thread (0: 4, 1: 2, 2: 8,
  * 3: 4), bits 11-12 the field range's partial blocks (0: 2048, 1: 1024,
  * 2: 512, 3: 2048).  Any other bit is rejected.
- * Codes and values never depend on the knobs.  Default: 0x9ec (on a
+ * Codes and values never depend on the knobs.  Default: 0x1ec (on a
  * 16M-vertex tetrahedral mesh with a 256^3 grid: the fastest mask of a
  * sweep with XCD order for the two vertex kernels, which leaves their time
- * unchanged and fetches each grid line once per pass instead of 1.4x, and
- * 1024 range blocks). */
+ * unchanged and fetches each grid line once per pass instead of 1.4x). */
 typedef struct {
     uint32_t remap_mask;
     uint32_t reserved[3];

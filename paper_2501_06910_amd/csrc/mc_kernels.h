@@ -167,10 +167,10 @@ enum {
     MC_KNOB_VPT = 3u << 9,          // vertex decode, vertices per thread: 0 -> 4, 1 -> 2, 2 -> 8, 3 -> 4
     MC_KNOB_RANGE = 3u << 11,       // field range, partial blocks: 0 -> 2048, 1 -> 1024, 2 -> 512, 3 -> 2048
     MC_KNOB_ALL = 0x1fffu,          // every valid bit
-    MC_KNOB_DEFAULT = 0x9ecu        // a new plan: on the 16M-vertex tet mesh launch order for resample and
+    MC_KNOB_DEFAULT = 0x1ecu        // a new plan: on the 16M-vertex tet mesh launch order for resample and
                                     // Lorenzo, XCD order for the vertex kernels (same time as launch order,
                                     // each grid line fetched once per pass instead of 1.4x) and for the
-                                    // 3-D decode, non-temporal streams, 4 vertices per thread, 1024 range
+                                    // 3-D decode, non-temporal streams, 4 vertices per thread, 2048 range
                                     // blocks
 };
 

@@ -39,7 +39,7 @@ def test_knobs_do_not_change_results(dim):
         dims = (32, 28, 36)          # x a multiple of 4: the quad decode kernels
     x = dev(G.field_octaves(mesh.coords, np.random.default_rng(4)))
     plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
-    assert plan.remap_mask == 0x9EC
+    assert plan.remap_mask == 0x1EC
     ref_h, ref_x = _run(plan, x, 1e-5)
     rng = np.random.default_rng(0)
     # bits 9-10: vertex decode 2 / 8 / 4 vertices per thread; 11-12: 1024 / 512 / 2048 range blocks
