@@ -889,16 +889,11 @@ def main():
         n_settle += 10
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
-    res = codes.result_host()
-    if res["status"] != 0:
-        raise SystemExit(f"compress status {res['status']}")
-    err = (x.double() - out.double()).abs().max().item()
-    if not err <= res["tau2"]:
-        raise SystemExit(f"bound violated: {err} > {res['tau2']}")
-    log(f"warmup ok: max |x - x'| = {err:.3e} <= tau2 = {res['tau2']:.3e}")
 
-    # timed region: K steps, no per-kernel events
+    # timed region: K steps, no per-kernel events, right after the warm-up
+    # (the bound check allocates three field-sized FP64 temporaries; the
+    # steps that follow such allocations run slower for about a millisecond,
+    # so it checks the last timed step instead, after the region)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record()
@@ -908,6 +903,13 @@ def main():
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
     log(f"timed {args.steps} steps: {ms_step:.4f} ms/step")
+    res = codes.result_host()
+    if res["status"] != 0:
+        raise SystemExit(f"compress status {res['status']}")
+    err = (x.double() - out.double()).abs().max().item()
+    if not err <= res["tau2"]:
+        raise SystemExit(f"bound violated: {err} > {res['tau2']}")
+    log(f"timed steps ok: max |x - x'| = {err:.3e} <= tau2 = {res['tau2']:.3e}")
 
     # per-kernel durations: HIP events around each launch on its stream
     M.profile_reset()
