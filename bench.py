@@ -197,18 +197,20 @@ def copy_ceiling_gbps(nbytes: int = 1 << 30, reps: int = 10) -> float:
 
 
 def _timed(fn, reps=5):
-    """Median device milliseconds of fn() over reps, HIP events on the
-    current stream."""
+    """Mean device milliseconds of fn() over reps back-to-back calls after
+    one untimed call, HIP events on the current stream around the reps (an
+    event pair around each single call would also count the launch latency
+    of the call's first kernel)."""
     import torch
-    ts = []
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     for _ in range(reps):
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
         fn()
-        b.record()
-        torch.cuda.synchronize()
-        ts.append(a.elapsed_time(b))
-    return float(np.median(ts))
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
 
 
 def serial_compare(M, x, eb, h_mc, ms_mc, log, label, shuffle_seed=None):
@@ -721,6 +723,8 @@ def batch_section(args, log) -> dict:
             total += M.stream_bytes(h, x.element_size())["total"]
         if learned:
             total += sum(len(m.export()) for m in models.values())   # every model file charged once
+        for _ in range(args.warmup):        # untimed again after the check's fresh allocations
+            step()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record()
