@@ -11,8 +11,9 @@
 //   k_dec_z_*  (3-D, longer rows) inclusive prefix along z in chunks of
 //              planes: totals, prefix over the chunks, apply; in place
 //   k_vdecode  g(x1') at each vertex from the decoded grid, dequantisation
-//              x' = (T)(g + q * 2 tau2), learned shift in learned blocks,
-//              raw values for outliers
+//              x' = (T)(g + q * 2 tau2), raw values for outliers (the
+//              learned decode, which adds the network's shift, is
+//              k_mlp_vdecode in k_mlp.hip)
 #include "mc_dev.h"
 #include "mc_kernels.h"
 

@@ -14,7 +14,10 @@
 // in the forward pass.  Input fragments are built directly in that layout:
 // lane l computes inputs 4(l/16)+16kb+i of vertex l%16 of each block.
 //
-// Training: see the block comment above stage_frag.
+// Kernels: k_mlp_residual (compress: the network on every vertex of a
+// 4,096-vertex decision block, then the block's codes) and k_mlp_vdecode
+// (decompress: the network on the learned blocks, every vertex decoded);
+// training: see the block comment above stage_frag.
 #include "mc_dev.h"
 #include "mc_kernels.h"
 
