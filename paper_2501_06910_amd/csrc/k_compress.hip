@@ -523,8 +523,10 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ coor
 // [0, nbl) take Lorenzo units and the rest residual tiles (nbl a multiple
 // of 8, so each part keeps its own XCD order); one launch boundary less,
 // and the tail of one part overlaps the other.
+// At most 80 VGPRs (6 waves per SIMD, from 84 and 5): more gathers in
+// flight; 64 (8 waves) leaves fewer loads per wave and is slower.
 template <typename T, int D, bool FROM_P, bool NT>
-__global__ __launch_bounds__(256) void k_codes(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_codes(const int32_t* __restrict__ p, int n0, int n1, int n2, int nxs,
                                                int nyb, unsigned nunits, uint16_t* __restrict__ gcodes,
                                                unsigned int* __restrict__ gcount, unsigned int* __restrict__ gsum,
                                                unsigned nbl, const float* __restrict__ coords, long long nv,
