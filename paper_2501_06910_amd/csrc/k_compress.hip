@@ -32,7 +32,9 @@ __device__ __forceinline__ void range_block(unsigned b, unsigned nb, const T* __
     const long long stride = (long long)nb * 256;
     const long long gid = (long long)b * 256 + threadIdx.x;
     for (long long i = gid; i < nzero; i += stride) zero[i] = 0u;
-    double mn = __builtin_inf(), mx = -__builtin_inf();
+    // running extremes in the field's own type (min and max are exact, so
+    // widening the two results gives the same keys as widening every value)
+    T mn = (T)__builtin_inf(), mx = -(T)__builtin_inf();
     bool bad = false;
     if (VEC) {
         // quads of 16-byte aligned values, 4 quads per thread in flight
@@ -47,7 +49,7 @@ __device__ __forceinline__ void range_block(unsigned b, unsigned nb, const T* __
             for (int u = 0; u < UQ; ++u)
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const double d = (double)v[u].v[e];
+                    const T d = v[u].v[e];
                     bad |= !isfinite(d);
                     mn = fmin(mn, d);
                     mx = fmax(mx, d);
@@ -57,14 +59,14 @@ __device__ __forceinline__ void range_block(unsigned b, unsigned nb, const T* __
             const Quad<T> v = load_quad(x + 4 * q);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const double d = (double)v.v[e];
+                const T d = v.v[e];
                 bad |= !isfinite(d);
                 mn = fmin(mn, d);
                 mx = fmax(mx, d);
             }
         }
         if (gid < n - 4 * nq) {
-            const double d = (double)x[4 * nq + gid];
+            const T d = x[4 * nq + gid];
             bad |= !isfinite(d);
             mn = fmin(mn, d);
             mx = fmax(mx, d);
@@ -78,22 +80,22 @@ __device__ __forceinline__ void range_block(unsigned b, unsigned nb, const T* __
         for (int u = 0; u < U; ++u) v[u] = x[i + u * stride];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double d = (double)v[u];
+            const T d = v[u];
             bad |= !isfinite(d);
             mn = fmin(mn, d);
             mx = fmax(mx, d);
         }
     }
     for (; i < n; i += stride) {
-        const double d = (double)x[i];
+        const T d = x[i];
         bad |= !isfinite(d);
         mn = fmin(mn, d);
         mx = fmax(mx, d);
     }
     // keys of the per-thread extremes (-0 and +0 share a key; an empty
     // thread contributes the neutral keys)
-    unsigned long long kmn = mn <= mx ? dkey(mn) : ~0ull;
-    unsigned long long kmx = mn <= mx ? dkey(mx) : 0ull;
+    unsigned long long kmn = mn <= mx ? dkey((double)mn) : ~0ull;
+    unsigned long long kmx = mn <= mx ? dkey((double)mx) : 0ull;
     unsigned int fl = bad ? MC_EBIT_NONFINITE : 0u;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
