@@ -373,6 +373,44 @@ def learned_design_point(M, mesh, series, cfg, serial_bytes, log, dims=512, spli
     return row
 
 
+def large2d_plain(M, plan, mesh, log) -> dict:
+    """The large 2-D configuration (the refined annulus mesh, its own
+    float64 tanh front plus Fourier noise field, 2048^2 grid, split 0.5),
+    plain path at relative eb 1e-4 and 1e-6: CR from the written stream and
+    both directions' GB/s (back-to-back means)."""
+    import torch
+    import meshgen as G
+    x = torch.from_numpy(G.field_large_2d(mesh.coords)).cuda()
+    nv, sT = mesh.n_vertices, x.element_size()
+    rows = []
+    for eb in (1e-4, 1e-6):
+        codes = M.Codes(plan, x.dtype)
+        out = torch.empty_like(x)
+        M.compress(plan, x, eb, "rel", 0.5, codes=codes)
+        M.decompress(plan, codes, out=out)
+        torch.cuda.synchronize()
+        h = codes.host()
+        r = h["result"]
+        if r["status"]:
+            raise SystemExit(f"large2d eb={eb}: status {r['status']}")
+        err = (x - out).abs().max().item()
+        if not err <= r["tau2"]:
+            raise SystemExit(f"large2d eb={eb}: bound violated")
+        sb = M.stream_bytes(h, sT)
+        tc = _timed(lambda: M.compress(plan, x, eb, "rel", 0.5, codes=codes))
+        td = _timed(lambda: M.decompress(plan, codes, out=out))
+        rows.append({"eb": eb, "cr": round(nv * sT / sb["total"], 3),
+                     "compress_GBps": round(nv * sT / (tc * 1e-3) / 1e9, 2),
+                     "decompress_GBps": round(nv * sT / (td * 1e-3) / 1e9, 2),
+                     "ms_per_step": round(tc + td, 4),
+                     "outliers": {"grid": r["n_grid_outliers"], "vertex": r["n_vertex_outliers"]},
+                     "max_abs_err_over_tau": round(err / r["tau"], 4)})
+        log(f"large2d: {rows[-1]}")
+    return {"workload": f"refined-annulus Delaunay mesh ({nv} vertices), float64 tanh front + Fourier noise, "
+                        f"grid 2048^2, relative eb 1e-4 and 1e-6, split 0.5, plain path",
+            "results": rows}
+
+
 def learned_section(log, train_steps=2000, batch=8192):
     """Learned vs plain on the rotating-front time series over the refined
     2-D mesh: train on t=0, compress t=1..8 both ways at eb 1e-4; CR with the
@@ -504,6 +542,7 @@ def learned_section(log, train_steps=2000, batch=8192):
         "n_vertices": nv, "n_grid": ng,
         "design_point": learned_design_point(M, mesh, series, cfg, tot["serial"], log, train_steps=train_steps,
                                              batch=batch),
+        "large2d": large2d_plain(M, plan, mesh, log),
     }
 
 
@@ -1043,6 +1082,7 @@ def main():
                                               split_mode="sum", operators="cluster", residual="open", coarsen=True)]
     if not args.no_learned:
         line["learned"] = learned_section(log, train_steps=args.train_steps)
+        line["large2d"] = line["learned"].pop("large2d")
     if not args.no_batch and args.workload == "tet3d":
         # the many-fields workload (12 meshes, 64 fields) with its own steps
         line["batch"] = batch_section(args, log)

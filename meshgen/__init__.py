@@ -345,6 +345,12 @@ def config_large_2d(seed: int = 2, h0: float = 7.615e-4, eb: float = 1e-4,
     return mesh, f, dict(dims=(dims, dims, 1), eb=eb, eb_mode="rel", split=0.5)
 
 
+def field_large_2d(coords: np.ndarray, seed: int = 2) -> np.ndarray:
+    """The field of config_large_2d(seed) on given vertices (the same mesh
+    is also the one config_learned_series builds)."""
+    return field_front_2d(coords, _rngs(seed, 2)[1])
+
+
 def config_tet_3d(seed: int = 3, n: int = 252, dims: int = 256, eb: float = 1e-4,
                   split: float = 0.5):
     """n^3 jittered lattice (+-20% of the spacing), 6 Kuhn tets per cube;

@@ -11,7 +11,9 @@ inputs and the integer shifts on a seeded sample of 65,536 vertices
 (inputs bit-exact, shifts equal to the oracle network's on >= 99.9 % of
 them: the MFMA summation order differs from the oracle's); and, given the
 GPU's shifts, every vertex code, every block flag, the outlier list and
-every decoded value, bit for bit."""
+every decoded value, bit for bit.  On the same mesh and grid, the large 2-D
+configuration's own field on the plain path at eb 1e-4 and 1e-6: every
+array bit for bit."""
 import numpy as np
 import pytest
 
@@ -46,11 +48,11 @@ def run():
     om = O.locate(mesh.coords, mesh.cells, og, "raster", fill="nearest", fill_method="kdtree")
     pc = O.compress(mesh.coords, om, og, x, cfg["eb"], True, 0.5)
     print(f"[learned-full] oracle compress done ({om.n_unresolved} nodes filled)", flush=True)
-    return mesh, x, plan, model, codes, h, plain, xr, z, og, pc
+    return mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om
 
 
 def test_grid_and_back_interpolation(run):
-    mesh, x, plan, model, codes, h, plain, xr, z, og, pc = run
+    mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om = run
     assert h["result"]["status"] == 0
     assert np.array_equal(h["grid_codes"], pc.grid.codes)
     assert np.array_equal(h["g_out_idx"], pc.grid.out_idx)
@@ -61,7 +63,7 @@ def test_grid_and_back_interpolation(run):
 
 
 def test_inputs_and_shifts_sampled(run):
-    mesh, x, plan, model, codes, h, plain, xr, z, og, pc = run
+    mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om = run
     params, kappa = model.params()
     vs = np.sort(np.random.default_rng(77).choice(mesh.n_vertices, 65536, replace=False))
     zo = O.mlp_features(np.ascontiguousarray(mesh.coords[:, vs]), og, pc.xhat, np.ascontiguousarray(pc.gv[vs]),
@@ -76,7 +78,7 @@ def test_inputs_and_shifts_sampled(run):
 
 
 def test_codes_given_shifts_everywhere(run):
-    mesh, x, plan, model, codes, h, plain, xr, z, og, pc = run
+    mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om = run
     rho_q = codes.rho_q.cpu().numpy()
     lc = O.learned_codes(x, pc.gv, pc.bound, rho_q)
     assert np.array_equal(h["vert_codes"], lc.codes)
@@ -95,7 +97,7 @@ def test_codes_given_shifts_everywhere(run):
 def test_trained_network_gains(run):
     """What the trained network gains at this size: some blocks take the
     learned codes, and the vertex stream and its code entropy shrink."""
-    mesh, x, plan, model, codes, h, plain, xr, z, og, pc = run
+    mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om = run
     hl = dict(h)
     hl["learned"] = True
     sp = M.stream_bytes(plain, 8)
@@ -106,3 +108,33 @@ def test_trained_network_gains(run):
     assert h["result"]["n_learned_blocks"] > 0
     assert sl["vert"] + sl["vert_outliers"] < sp["vert"] + sp["vert_outliers"]
     assert el < ep
+
+
+@pytest.mark.parametrize("eb", [1e-4, 1e-6])
+def test_plain_large2d_field_everywhere(run, eb):
+    """The large 2-D configuration's own field (tanh front plus Fourier
+    noise, float64) on the same mesh and grid, plain path, relative eb 1e-4
+    and 1e-6: every grid and vertex code, both outlier lists and every
+    decoded value equal to the oracle's; every vertex within tau2."""
+    mesh, x, plan, model, codes, h, plain, xr, z, og, pc, om = run
+    f = G.field_large_2d(mesh.coords)
+    xg = torch.from_numpy(f).cuda()
+    c = M.compress(plan, xg, eb, "rel", 0.5)
+    xd = M.decompress(plan, c).cpu().numpy()
+    torch.cuda.synchronize()
+    hg = c.host()
+    assert hg["result"]["status"] == 0
+    oc = O.compress(mesh.coords, om, og, f, eb, True, 0.5)
+    for k in ("tau", "tau1", "tau2", "c"):
+        assert hg["result"][k] == getattr(oc.bound, k), k
+    assert np.array_equal(hg["grid_codes"], oc.grid.codes)
+    assert np.array_equal(hg["g_out_idx"], oc.grid.out_idx)
+    assert np.array_equal(hg["g_out_delta"], oc.grid.out_delta)
+    assert np.array_equal(hg["vert_codes"], oc.vert.codes)
+    assert np.array_equal(hg["v_out_idx"], oc.vert.out_idx)
+    assert np.array_equal(hg["v_out_val"].view(np.uint64), oc.vert.out_val.view(np.uint64))
+    xo = O.decompress(mesh.coords, og, oc.bound, oc.grid, oc.vert, f.dtype)
+    assert np.array_equal(xd.view(np.uint64), xo.view(np.uint64))
+    assert np.all(np.abs(f - xd) <= oc.bound.tau2)
+    print(f"[large2d eb={eb:g}] whole arrays equal: grid outliers {oc.grid.out_idx.size}, vertex outliers "
+          f"{oc.vert.out_idx.size}", flush=True)
