@@ -305,12 +305,11 @@ __global__ __launch_bounds__(256) void k_locate(const float* __restrict__ coords
             for (int q = 0; q <= D; ++q) lam_best[q] = lam[q];
         }
     }
-    if (best == 0x7fffffff) {
+    const bool un = best == 0x7fffffff;
+    if (un) {
         cell_out[j] = -1;
 #pragma unroll
         for (int q = 0; q <= D; ++q) { vid[q * ng + j] = -1; w[q * ng + j] = 0.0f; }
-        const unsigned k = atomicAdd(n_unres, 1u);
-        unres[k] = (int32_t)j;
     } else {
         cell_out[j] = best;
 #pragma unroll
@@ -318,8 +317,20 @@ __global__ __launch_bounds__(256) void k_locate(const float* __restrict__ coords
             vid[q * ng + j] = cells[q * nc + best];
             w[q * ng + j] = lam_best[q];
         }
-        if (best_nd) atomicAdd(n_neardeg, 1u);
     }
+    // unresolved ids compacted per wave: one atomic reserves the wave's run
+    // of the list, ballot ranks place its nodes (in ascending id within the
+    // run; the fill treats every listed node on its own, so the order of the
+    // runs is free); the near-degenerate count likewise one atomic per wave
+    const unsigned long long mu = __ballot(un), mn = __ballot(!un && best_nd);
+    if (mu) {
+        const int lead = __ffsll((long long)mu) - 1;
+        unsigned base = 0;
+        if (lane_id() == lead) base = atomicAdd(n_unres, (unsigned)__popcll(mu));
+        base = __shfl(base, lead, 64);
+        if (un) unres[base + (unsigned)mbcnt64(mu)] = (int32_t)j;
+    }
+    if (mn && lane_id() == __ffsll((long long)mn) - 1) atomicAdd(n_neardeg, (unsigned)__popcll(mn));
 }
 
 // ---- vertex bins --------------------------------------------------------
