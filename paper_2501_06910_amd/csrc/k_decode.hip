@@ -775,6 +775,61 @@ __global__ __launch_bounds__(256) void k_d2_apply(const uint16_t* __restrict__ c
     }
 }
 
+// Rows of at most MC_D2_SEG_MAX segments: one workgroup per chunk of rows,
+// one wave per segment.  After the carries each wave has Y on its segment;
+// the per-row segment sums meet in LDS, so the apply needs no separate pass
+// for them (k_d2_rowsum) and reads the codes once more instead of twice.
+#define MC_D2_SEG_MAX 16
+__global__ __launch_bounds__(64 * MC_D2_SEG_MAX) void k_d2_apply_rows(
+    const uint16_t* __restrict__ codes, const int32_t* __restrict__ oidx, const int32_t* __restrict__ odelta,
+    const mc_result* __restrict__ res, long long gcap, int n0, int n1, const int* __restrict__ carry,
+    float* __restrict__ xh)
+{
+    __shared__ int s_sum[MC_D2_R][MC_D2_SEG_MAX];
+    const int sg = threadIdx.x >> 6, l = lane_id();
+    const int ch = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int y0 = ch * MC_D2_R, y1 = min(n1, y0 + MC_D2_R);
+    const long long nout = res->n_grid_outliers < gcap ? res->n_grid_outliers : gcap;
+    const double c = res->c, step1 = 2.0 * res->tau1;
+    const long long row = (long long)ch * n0;
+    int col[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int x = sg * 256 + l + 64 * k;
+        col[k] = x < n0 ? carry[row + x] : 0;
+    }
+    int e[MC_D2_R][4];
+    d2_errors(codes, oidx, odelta, nout, n0, n1, sg * 256, y0, y1, e);
+    {
+        int cy[4] = {col[0], col[1], col[2], col[3]};
+#pragma unroll
+        for (int r = 0; r < MC_D2_R; ++r) {
+            int t = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                cy[k] += e[r][k];
+                t += cy[k];
+            }
+            t = wave_sum(t);
+            if (l == 0) s_sum[r][sg] = t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < MC_D2_R; ++r) {
+        if (y0 + r >= y1) break;                         // uniform across the workgroup
+        int run = wave_sum(l < sg ? s_sum[r][l] : 0);
+        const long long base = (long long)(y0 + r) * n0 + sg * 256 + l;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            col[k] += e[r][k];
+            const int inc = wave_incl_scan(col[k]);
+            if (sg * 256 + l + 64 * k < n0) xh[base + 64 * k] = xhat_of(run + inc, c, step1);
+            run += __shfl(inc, 63, 64);
+        }
+    }
+}
+
 namespace mck {
 
 hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t* odelta, long long gcap,
@@ -798,6 +853,12 @@ hipError_t grid_decode(const uint16_t* codes, const int32_t* oidx, const int32_t
             hipLaunchKernelGGL(k_dec_xy_carry, dim3((unsigned)((n0 + 63) / 64)), dim3(1024), 0, s, ws.agg_xy, n0, 1,
                                ws.nyc);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
+        if (nseg <= MC_D2_SEG_MAX) {
+            ProfScope ps("k_dec_xy_apply", s);
+            hipLaunchKernelGGL(k_d2_apply_rows, dim3((unsigned)ws.nyc), dim3(64 * nseg), 0, s, codes, oidx, odelta,
+                               res, gcap, n0, n1, ws.agg_xy, xh);
+            return hipGetLastError();
         }
         {
             ProfScope ps("k_dec_xy_rowsum", s);

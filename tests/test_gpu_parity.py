@@ -54,6 +54,13 @@ def _cases():
     rng = np.random.default_rng(12)
     m2 = G.structured_tri_mesh(301, 257, rng, 0.2)
     out.append(("struct2d_f32_ragged", m2, G.field_octaves(m2.coords, rng), (190, 171), 1e-5, True, 0.3, "midrange"))
+    # 2-D rows of 12 and 16 segments of 256 columns (one workgroup per chunk
+    # of rows, the last segment ragged in the first) and of 17 (the
+    # row-segment decoder with its separate pass of segment sums)
+    f2 = G.field_octaves(m2.coords, np.random.default_rng(13))
+    out.append(("struct2d_f32_3000cols", m2, f2, (3000, 11), 1e-5, True, 0.5, "nearest"))
+    out.append(("struct2d_f32_4096cols", m2, f2, (4096, 9), 1e-6, True, 0.5, "nearest"))
+    out.append(("struct2d_f32_4300cols", m2, f2, (4300, 10), 1e-5, True, 0.5, "nearest"))
     m3 = G.kuhn_tet_mesh(22, 5)
     out.append(("kuhn3d_f32", m3, G.field_octaves(m3.coords, np.random.default_rng(1)), (25, 23, 21), 1e-4, True,
                 0.5, "nearest"))
