@@ -640,6 +640,8 @@ __global__ __launch_bounds__(256) void k_b_vdecode(const mck::BItemD* __restrict
 //   k_d2_apply  per (segment, chunk): Y again, its prefix along the segment
 //               (four wave scans) plus the S of the segments to the left:
 //               the decoded grid, x1' written
+// Rows of at most 16 segments take k_d2_apply_rows after the carries
+// instead of the last two (the segment sums exchanged in LDS).
 // Every partial sum is a difference of two decoded values, so int32 holds it.
 __device__ __forceinline__ void d2_unit(int unit, int nseg, int n0, int n1, int& sg, int& y0, int& y1)
 {
