@@ -8,7 +8,7 @@ then decompress (grid decode, vertex decode).  The default workload is the
 cube, a float32 three-octave field, a 256^3 grid, relative eb 1e-4 and a
 50/50 split.  ``value`` is GB/s of mesh values (n_v * 4 bytes) per step.
 
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -860,8 +860,8 @@ def main():
                     help="also run a plain 1 GiB device copy (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(the multi-GPU decomposition is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                                   "(no multi-GPU decomposition is built)"}))
         sys.exit(2)
 
     import torch

@@ -55,7 +55,7 @@ typedef enum {
     MC_ERR_NOMEM = 4,       /* device allocation failed */
     MC_ERR_DEVICE = 5,      /* a HIP call failed */
     MC_ERR_FORMAT = 6,      /* malformed serialized model or stream */
-    MC_ERR_UNSUPPORTED = 7  /* valid request outside what this build supports */
+    MC_ERR_UNSUPPORTED = 7  /* valid request outside what the library supports */
 } mc_status;
 
 typedef enum { MC_F32 = 0, MC_F64 = 1 } mc_dtype;
