@@ -437,42 +437,102 @@ __device__ __forceinline__ int rho_quant(float r)
     return (int)q;
 }
 
+// Cell and in-cell offsets of one vertex, with its g(x1') given.
+template <int D>
+__device__ __forceinline__ VGeom vertex_cell(const float* __restrict__ coords, long long nv, long long v,
+                                             const GridGeom& gg, float g)
+{
+    VGeom q;
+    q.i2 = 0;
+    q.t2 = 0.0f;
+    const float p0 = coords[v], p1 = coords[nv + v], p2 = D == 3 ? coords[2 * nv + v] : 0.0f;
+    axis_cell(p0, gg.of[0], gg.ihf[0], gg.n0, q.i0, q.t0);
+    axis_cell(p1, gg.of[1], gg.ihf[1], gg.n1, q.i1, q.t1);
+    if (D == 3) axis_cell(p2, gg.of[2], gg.ihf[2], gg.n2, q.i2, q.t2);
+    q.g = g;
+    return q;
+}
+
 // Learned vertex codes in one kernel: one 512-thread workgroup per
 // 4,096-vertex decision block, two workgroups per CU so that one's memory
-// phase overlaps the other's network.  The 8 waves first run the network on
-// the block's 64-vertex tiles (8 per wave) and keep each vertex's shift
-// rho_q and back-interpolation g in LDS.  Pass A quantizes every vertex
-// against g (q replaces g in LDS) and sums the block's cost of the plain and
-// of the shifted codes (bitlen(zigzag(code)) per coded vertex plus
-// (32 + 8 sizeof(T)) per outlier); pass B writes the codes of the cheaper
-// choice (shifted only when strictly cheaper) and each 1,024-vertex tile's
-// outlier count, bit 31 marking the first tile of a learned block.  rho_out
-// (optional) receives rho_q.
+// phase overlaps the other's network.
+//   phase 0  g(x1') and the plain code q of every vertex of the block (LDS);
+//            a block whose plain codes are all zero (no outlier) costs 0
+//            bits, so the shifted codes cannot be strictly cheaper: its
+//            plain codes are written and the network is not run (unless
+//            the shifts are asked for, rho_out)
+//   phase 1  the network on the block's 64-vertex tiles (8 per wave), the
+//            shift rho_q of every vertex kept in LDS
+//   pass A   the block's cost of the plain and of the shifted codes
+//            (bitlen(zigzag(code)) per coded vertex plus (32 + 8 sizeof(T))
+//            per outlier)
+//   pass B   the codes of the cheaper choice (shifted only when strictly
+//            cheaper) and each 1,024-vertex tile's outlier count, bit 31
+//            marking the first tile of a learned block
+// rho_out (optional) receives rho_q.
 template <typename T, int D>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_residual(mck::MlpDev m, const float* __restrict__ coords, long long nv,
-                                                      GridGeom gg, const float* __restrict__ xh,
-                                                      const T* __restrict__ x, const DevBound* __restrict__ bnd,
-                                                      uint16_t* __restrict__ codes, uint32_t* __restrict__ bflags,
-                                                      float* __restrict__ dbg_g, int32_t* __restrict__ rho_out,
-                                                      unsigned int* __restrict__ count,
-                                                      unsigned int* __restrict__ vsum, long long ntv)
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k_mlp_residual(
+    mck::MlpDev m, const float* __restrict__ coords, long long nv, GridGeom gg, const float* __restrict__ xh,
+    const T* __restrict__ x, const DevBound* __restrict__ bnd, uint16_t* __restrict__ codes,
+    uint32_t* __restrict__ bflags, float* __restrict__ dbg_g, int32_t* __restrict__ rho_out,
+    unsigned int* __restrict__ count, unsigned int* __restrict__ vsum, long long ntv)
 {
-    constexpr int NT = 512, NW = NT / 64, PT = MC_LBLOCK / NT, LT = MC_LBLOCK / MC_TILE;
-    static_assert(MC_LBLOCK % NT == 0 && MC_TILE % NT == 0 && LT <= NW, "decision block layout");
-    constexpr int OUT = -0x7fffffff - 1;                        // q marker of an outlier
+    constexpr int NT = 512, NW = NT / 64, PT = MC_LBLOCK / NT, LT = MC_LBLOCK / MC_TILE, H = 4;
+    static_assert(MC_LBLOCK % NT == 0 && MC_TILE % NT == 0 && LT <= NW && PT % H == 0, "decision block layout");
+    static_assert(MC_R - 1 <= 32767, "codes and shifts fit int16");
+    constexpr short OUT = -32768;                               // q marker of an outlier
     __shared__ LdsFrag<D> sw;
-    __shared__ int s_rq[MC_LBLOCK];
-    __shared__ union { float g; int q; } s_gq[MC_LBLOCK];
+    __shared__ float s_g[MC_LBLOCK];
+    __shared__ short s_q[MC_LBLOCK], s_rq[MC_LBLOCK];
     __shared__ long long s_sp[NW], s_sl[NW];
     __shared__ int s_cnt[LT][NW];
-    load_frag<D, NT>(sw, m);
     const long long blk = blockIdx.x, vb = blk * MC_LBLOCK;
     const int w = threadIdx.x >> 6, l = lane_id();
-    for (int t = w; t < MC_LBLOCK / 64; t += NW) {
+    const DevBound b = *bnd;
+    bool nz = false;
+#pragma unroll
+    for (int h = 0; h < PT; h += H) {                            // phase 0
+        long long v[H];
+        bool act[H];
+        T xv[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            v[i] = vb + (h + i) * NT + (int)threadIdx.x;
+            act[i] = v[i] < nv;
+            xv[i] = x[act[i] ? v[i] : 0];
+        }
+        float g[H];
+        back_interp_n<D, H, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            if (!act[i]) continue;
+            const int k = (h + i) * NT + (int)threadIdx.x;
+            s_g[k] = g[i];
+            if (!b.ok) continue;
+            int q;
+            const bool ok = quantize_residual<T>(xv[i], g[i], b, q);
+            s_q[k] = ok ? (short)q : OUT;
+            nz = nz || !ok || q != 0;
+            if (dbg_g) dbg_g[v[i]] = g[i];
+        }
+    }
+    const bool any = __syncthreads_or(nz) != 0;
+    if (!any && !rho_out) {                                      // uniform over the workgroup
+#pragma unroll
+        for (int i = 0; i < PT; ++i) {
+            const long long v = vb + i * NT + (int)threadIdx.x;
+            if (v < nv && b.ok) codes[v] = (uint16_t)MC_R;
+        }
+        const long long tile = blk * LT + threadIdx.x;
+        if (threadIdx.x < LT && tile < ntv) count[tile] = 0u;
+        return;
+    }
+    load_frag<D, NT>(sw, m);
+    for (int t = w; t < MC_LBLOCK / 64; t += NW) {               // phase 1
         const long long v0 = vb + t * 64;
         if (v0 >= nv) break;                                     // uniform over the wave
         const long long v = v0 + l;
-        const VGeom mine = vertex_geom<D>(coords, nv, v < nv ? v : nv - 1, gg, xh);
+        const VGeom mine = vertex_cell<D>(coords, nv, v < nv ? v : nv - 1, gg, v < nv ? s_g[t * 64 + l] : 0.0f);
         bool valid[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
@@ -488,25 +548,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
         if ((l >> 4) == 2) r = rho[2];
         if ((l >> 4) == 3) r = rho[3];
         const int rq = rho_quant(r);
-        s_rq[t * 64 + l] = rq;
-        s_gq[t * 64 + l].g = mine.g;
+        s_rq[t * 64 + l] = (short)rq;
         if (rho_out && v < nv) rho_out[v] = rq;
     }
     __syncthreads();
-    const DevBound b = *bnd;
     const int ocost = 32 + 8 * (int)sizeof(T);
     long long cp = 0, cl = 0;
 #pragma unroll
-    for (int i = 0; i < PT; ++i) {                               // pass A: quantize and price both choices
+    for (int i = 0; i < PT; ++i) {                               // pass A
         const int k = i * NT + (int)threadIdx.x;
-        const long long v = vb + k;
-        if (v >= nv || !b.ok) continue;
-        const float g = s_gq[k].g;
-        int q;
-        const bool ok = quantize_residual<T>(x[v], g, b, q);
-        if (dbg_g) dbg_g[v] = g;
-        s_gq[k].q = ok ? q : OUT;
-        if (ok) {
+        if (vb + k >= nv || !b.ok) continue;
+        const int q = s_q[k];
+        if (q != OUT) {
             const int lq = q - s_rq[k];
             cp += zz_bits(q);
             cl += (lq >= -(MC_R - 1) && lq <= MC_R - 1) ? zz_bits(lq) : ocost;
@@ -525,11 +578,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const bool learned = sl < sp;                                // uniform over the workgroup
     int nout[LT] = {};
 #pragma unroll
-    for (int i = 0; i < PT; ++i) {                               // pass B: codes of the cheaper choice
+    for (int i = 0; i < PT; ++i) {                               // pass B
         const int k = i * NT + (int)threadIdx.x;
         const long long v = vb + k;
         if (v >= nv || !b.ok) continue;
-        int q = s_gq[k].q;
+        int q = s_q[k];
         bool ok = q != OUT;
         if (ok && learned) {
             q -= s_rq[k];

@@ -149,6 +149,41 @@ def test_learned_codes_parity(dim):
     assert np.all(np.abs(x.astype(np.float64) - xr) <= pc.bound.tau2)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_blocks_skip_the_network(dim):
+    """A block whose plain codes are all zero costs 0 bits, so the shifted
+    codes cannot be cheaper and the network is not run for it (unless the
+    shifts are asked for).  The codes, flags, outliers and result equal
+    those of the run that evaluates the network everywhere (debug shifts
+    on), over bounds that give both kinds of block."""
+    mesh, series, dims = _series_case(dim)
+    plan = M.Plan(dev(mesh.coords), dev(mesh.cells), dims=dims)
+    model = M.Model.train(plan, dev(series[0]), eb=1e-4, steps=60, batch=1024, seed=3)
+    # the series' next step over several bounds, and a linear field with
+    # most of a loose bound on the vertices (the multilinear g reproduces it
+    # up to the grid's quantisation error and, at the mesh boundary, the
+    # nearest-vertex fill, both well inside tau2: its plain codes are zero)
+    lin = mesh.coords.sum(axis=0).astype(series[1].dtype)
+    zero = other = 0
+    for xs, eb, split in [(series[1], 1e-4, 0.5), (series[1], 1e-3, 0.5), (series[1], 1e-2, 0.5),
+                          (lin, 1e-1, 0.1)]:
+        x = dev(xs)
+        full = M.compress(plan, x, eb, "rel", split, model=model, debug=True).host()
+        fast = M.compress(plan, x, eb, "rel", split, model=model).host()
+        torch.cuda.synchronize()
+        assert full["result"] == fast["result"], eb
+        for k in ("vert_codes", "block_flags", "v_out_idx", "v_out_val", "grid_codes", "g_out_idx"):
+            assert np.array_equal(full[k], fast[k]), (eb, k)
+        vc = M.compress(plan, x, eb, "rel", split).host()["vert_codes"]
+        nb = (vc.size + 4095) // 4096
+        z = sum(bool(np.all(vc[b * 4096:(b + 1) * 4096] == 32768)) for b in range(nb))
+        print(f"[skip D={dim}] eb {eb:g}: {z} of {nb} blocks all zero, "
+              f"{full['result']['n_learned_blocks']} learned")
+        zero += z
+        other += nb - z
+    assert zero > 0 and other > 0
+
+
 def test_one_training_step_matches_oracle():
     dim = 2
     mesh, series, dims = _series_case(dim)
