@@ -498,8 +498,13 @@ def learned_section(log, train_steps=2000, batch=8192):
                       "blocks": (nv + 4095) // 4096})
         log(f"learned: t={t} {per_t[-1]}")
     med = {k: float(np.median(v)) for k, v in times.items()}
-    # the learned vertex-code kernel (network on every vertex, then the
-    # codes): MFMA rate over its whole duration
+    # the learned vertex-code kernel (the network on every block whose plain
+    # codes are not all zero, then the codes): MFMA rate over its whole
+    # duration, counting the vertices of the blocks the network runs on
+    vc0 = M.compress(plan, x0, cfg["eb"], "rel", 0.5).host()["vert_codes"]
+    nblk = (nv + 4095) // 4096
+    run_b = [b for b in range(nblk) if not np.all(vc0[b * 4096:(b + 1) * 4096] == 32768)]
+    run_v = sum(min(4096, nv - b * 4096) for b in run_b)
     M.profile_reset()
     M.profile_enable(True)
     for _ in range(5):
@@ -509,7 +514,7 @@ def learned_section(log, train_steps=2000, batch=8192):
     iprof = M.profile_read()
     inf = iprof.get("k_mlp_residual")
     inf_ms = inf[1] / inf[0] if inf else None
-    fl = mlp_flops_per_vertex(D) * nv
+    fl = mlp_flops_per_vertex(D) * run_v
     tr = tprof.get("k_mlp_train")
     tr_ms = tr[1] / tr[0] if tr else None
     train_fl = 3 * mlp_flops_per_vertex(D) * batch      # forward + two backward products per layer
@@ -536,6 +541,7 @@ def learned_section(log, train_steps=2000, batch=8192):
                          "decompress": round(nv * sT / (med["learned_d"] * 1e-3) / 1e9, 2)},
         "inference": {"kernel": "k_mlp_residual", "avg_ms": round(inf_ms, 5) if inf_ms else None,
                       "flops_per_vertex": mlp_flops_per_vertex(D),
+                      "vertices_run": int(run_v), "blocks_skipped": nblk - len(run_b),
                       "TFLOPs": round(fl / (inf_ms * 1e-3) / 1e12, 2) if inf_ms else None,
                       "mfma_peak_bf16_TFLOPs": 2500.0},
         "per_timestep": per_t,
