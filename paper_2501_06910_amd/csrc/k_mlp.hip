@@ -18,6 +18,8 @@
 // 4,096-vertex decision block, then the block's codes) and k_mlp_vdecode
 // (decompress: the network on the learned blocks, every vertex decoded);
 // training: see the block comment above stage_frag.
+#include <type_traits>
+
 #include "mc_dev.h"
 #include "mc_kernels.h"
 
@@ -456,8 +458,11 @@ __device__ __forceinline__ VGeom vertex_cell(const float* __restrict__ coords, l
 // Learned vertex codes in one kernel: one 512-thread workgroup per
 // 4,096-vertex decision block, two workgroups per CU so that one's memory
 // phase overlaps the other's network.
-//   phase 0  g(x1') and the plain code q of every vertex of the block (LDS);
-//            a block whose plain codes are all zero (no outlier) costs 0
+//   phase 0  g(x1') and the plain code q of the block's first 512 vertices;
+//            if one of them is not zero, the block is coded directly
+//            (phase 1 recomputes g with the network's inputs, pass A
+//            quantises the rest).  Otherwise the rest of the block too: a
+//            block whose plain codes are all zero (no outlier) costs 0
 //            bits, so the shifted codes cannot be strictly cheaper: its
 //            plain codes are written and the network is not run (unless
 //            the shifts are asked for, rho_out)
@@ -477,8 +482,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     uint32_t* __restrict__ bflags, float* __restrict__ dbg_g, int32_t* __restrict__ rho_out,
     unsigned int* __restrict__ count, unsigned int* __restrict__ vsum, long long ntv)
 {
-    constexpr int NT = 512, NW = NT / 64, PT = MC_LBLOCK / NT, LT = MC_LBLOCK / MC_TILE, H = 4;
-    static_assert(MC_LBLOCK % NT == 0 && MC_TILE % NT == 0 && LT <= NW && PT % H == 0, "decision block layout");
+    constexpr int NT = 512, NW = NT / 64, PT = MC_LBLOCK / NT, LT = MC_LBLOCK / MC_TILE;
+    static_assert(MC_LBLOCK % NT == 0 && MC_TILE % NT == 0 && LT <= NW && PT == 8, "block layout: rows 1..7 as 4 + 3");
     static_assert(MC_R - 1 <= 32767, "codes and shifts fit int16");
     constexpr short OUT = -32768;                               // q marker of an outlier
     __shared__ LdsFrag<D> sw;
@@ -490,23 +495,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
     const int w = threadIdx.x >> 6, l = lane_id();
     const DevBound b = *bnd;
     bool nz = false;
+    // g and the plain code of vertices vb + k, k = i NT + tid for i in [i0, i0 + N)
+    auto quantize_rows = [&](auto n_tag, int i0) {
+        constexpr int N = decltype(n_tag)::value;
+        long long v[N];
+        bool act[N];
+        T xv[N];
 #pragma unroll
-    for (int h = 0; h < PT; h += H) {                            // phase 0
-        long long v[H];
-        bool act[H];
-        T xv[H];
-#pragma unroll
-        for (int i = 0; i < H; ++i) {
-            v[i] = vb + (h + i) * NT + (int)threadIdx.x;
+        for (int i = 0; i < N; ++i) {
+            v[i] = vb + (i0 + i) * NT + (int)threadIdx.x;
             act[i] = v[i] < nv;
             xv[i] = x[act[i] ? v[i] : 0];
         }
-        float g[H];
-        back_interp_n<D, H, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
+        float g[N];
+        back_interp_n<D, N, false>(coords, nv, gg, xh, 0.0, 0.0, v, act, g);
 #pragma unroll
-        for (int i = 0; i < H; ++i) {
+        for (int i = 0; i < N; ++i) {
             if (!act[i]) continue;
-            const int k = (h + i) * NT + (int)threadIdx.x;
+            const int k = (i0 + i) * NT + (int)threadIdx.x;
             s_g[k] = g[i];
             if (!b.ok) continue;
             int q;
@@ -515,24 +521,35 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
             nz = nz || !ok || q != 0;
             if (dbg_g) dbg_g[v[i]] = g[i];
         }
-    }
-    const bool any = __syncthreads_or(nz) != 0;
-    if (!any && !rho_out) {                                      // uniform over the workgroup
+    };
+    // the network's weights are copied to LDS first, so that their loads
+    // overlap phase 0; the barrier after phase 0 completes the copy
+    copy_to_lds<sizeof(LdsFrag<D>), NT>(&sw, m.img);
+    quantize_rows(std::integral_constant<int, 1>{}, 0);          // phase 0
+    const bool direct = __syncthreads_or(nz) != 0;              // uniform over the workgroup
+    if (!direct) {
+        quantize_rows(std::integral_constant<int, 4>{}, 1);
+        quantize_rows(std::integral_constant<int, 3>{}, 5);
+        const bool any = __syncthreads_or(nz) != 0;
+        if (!any && !rho_out) {
 #pragma unroll
-        for (int i = 0; i < PT; ++i) {
-            const long long v = vb + i * NT + (int)threadIdx.x;
-            if (v < nv && b.ok) codes[v] = (uint16_t)MC_R;
+            for (int i = 0; i < PT; ++i) {
+                const long long v = vb + i * NT + (int)threadIdx.x;
+                if (v < nv && b.ok) codes[v] = (uint16_t)MC_R;
+            }
+            const long long tile = blk * LT + threadIdx.x;
+            if (threadIdx.x < LT && tile < ntv) count[tile] = 0u;
+            return;
         }
-        const long long tile = blk * LT + threadIdx.x;
-        if (threadIdx.x < LT && tile < ntv) count[tile] = 0u;
-        return;
     }
-    load_frag<D, NT>(sw, m);
     for (int t = w; t < MC_LBLOCK / 64; t += NW) {               // phase 1
         const long long v0 = vb + t * 64;
         if (v0 >= nv) break;                                     // uniform over the wave
         const long long v = v0 + l;
-        const VGeom mine = vertex_cell<D>(coords, nv, v < nv ? v : nv - 1, gg, v < nv ? s_g[t * 64 + l] : 0.0f);
+        const long long vc = v < nv ? v : nv - 1;
+        const VGeom mine = direct ? vertex_geom<D>(coords, nv, vc, gg, xh)
+                                  : vertex_cell<D>(coords, nv, vc, gg, v < nv ? s_g[t * 64 + l] : 0.0f);
+        if (direct && v < nv) s_g[t * 64 + l] = mine.g;
         bool valid[4];
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb) valid[nb] = v0 + nb * 16 + (l & 15) < nv;
@@ -557,7 +574,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
     for (int i = 0; i < PT; ++i) {                               // pass A
         const int k = i * NT + (int)threadIdx.x;
-        if (vb + k >= nv || !b.ok) continue;
+        const long long v = vb + k;
+        if (v >= nv || !b.ok) continue;
+        if (direct && i > 0) {                                   // not quantised in phase 0
+            const float g = s_g[k];
+            int qq;
+            const bool ok = quantize_residual<T>(x[v], g, b, qq);
+            s_q[k] = ok ? (short)qq : OUT;
+            if (dbg_g) dbg_g[v] = g;
+        }
         const int q = s_q[k];
         if (q != OUT) {
             const int lq = q - s_rq[k];
