@@ -314,7 +314,12 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
                                                 int nzc, int* __restrict__ agg_z, int* __restrict__ agg_y,
                                                 int* __restrict__ agg_t, unsigned remap)
 {
-    __shared__ int4 s_p[MC_DZ + 1][4][64];                      // per plane, then the tile total; per wave
+    // per plane (then the tile total) and per wave; the planes in two
+    // rounds of MC_DZ / 2, so the buffer is half the tile (20 KB: more
+    // workgroups per CU)
+    constexpr int HZ = MC_DZ / 2;
+    static_assert(MC_DZ % 2 == 0, "two rounds of planes");
+    __shared__ int4 s_p[HZ + 1][4][64];
     const unsigned t = tile_of(remap);                           // grid = exactly the tiles: no early exit
     const unsigned xs = t % (unsigned)nxs, r = t / (unsigned)nxs;
     const unsigned yc = r % (unsigned)nyc, zc = r / (unsigned)nyc;
@@ -348,32 +353,39 @@ __global__ __launch_bounds__(256) void k_d3_tot(const uint16_t* __restrict__ cod
         bnd = run_bound(oidx, nout, s0, s0 + min(256, n0 - (int)xs * 256), yr < (unsigned)n1 && zr < z1);
     }
     int4 sz[2] = {make_int4(0, 0, 0, 0), make_int4(0, 0, 0, 0)};
+    int4 cs[MC_DZ];
 #pragma unroll
     for (int k = 0; k < MC_DZ; ++k) {
-        int4 cs = make_int4(0, 0, 0, 0);
+        cs[k] = make_int4(0, 0, 0, 0);
 #pragma unroll
         for (int q = 0; q < 2; ++q)
             if (ar[q] && z0 + k < z1) {
                 const int4 d = dec4r(c[k][q], oidx, odelta, bnd, 2 * k + q, rb[q] + nxy * (unsigned)(z0 + k));
                 sz[q] = add4(sz[q], d);
-                cs = add4(cs, d);
+                cs[k] = add4(cs[k], d);
             }
-        s_p[k][w][lane] = cs;
     }
-    s_p[MC_DZ][w][lane] = add4(sz[0], sz[1]);
 #pragma unroll
     for (int q = 0; q < 2; ++q)
         if (ar[q]) *reinterpret_cast<int4*>(agg_z + (size_t)zc * nxyp + rp[q]) = sz[q];
-    __syncthreads();
-    for (int k = w; k <= MC_DZ; k += 4) {
-        if (!actx) continue;
-        int4 a = s_p[k][0][lane];
 #pragma unroll
-        for (int v = 1; v < 4; ++v) a = add4(a, s_p[k][v][lane]);
-        if (k < MC_DZ) {
-            if (z0 + k < z1) *reinterpret_cast<int4*>(agg_y + ((size_t)(z0 + k) * nyc + yc) * n0p + x) = a;
-        } else {
-            *reinterpret_cast<int4*>(agg_t + ((size_t)yc * nzc + zc) * n0p + x) = a;
+    for (int h = 0; h < 2; ++h) {
+        if (h) __syncthreads();                                  // the first round's reads are done
+#pragma unroll
+        for (int k = 0; k < HZ; ++k) s_p[k][w][lane] = cs[h * HZ + k];
+        if (h) s_p[HZ][w][lane] = add4(sz[0], sz[1]);
+        __syncthreads();
+        for (int k = w; k < HZ + h; k += 4) {
+            if (!actx) continue;
+            int4 a = s_p[k][0][lane];
+#pragma unroll
+            for (int v = 1; v < 4; ++v) a = add4(a, s_p[k][v][lane]);
+            if (k < HZ) {
+                const int zk = z0 + h * HZ + k;
+                if (zk < z1) *reinterpret_cast<int4*>(agg_y + ((size_t)zk * nyc + yc) * n0p + x) = a;
+            } else {
+                *reinterpret_cast<int4*>(agg_t + ((size_t)yc * nzc + zc) * n0p + x) = a;
+            }
         }
     }
 }
