@@ -915,7 +915,7 @@ def main():
     if not args.no_tune:
         t0 = time.time()
         tune["cached"] = tune["key"] in M.tuning_cache()
-        tune["remap_mask"] = plan.tune(x, args.eb, "rel", args.split, reps=5, cache=True)
+        tune["remap_mask"] = plan.tune(x, args.eb, "rel", args.split, reps=10, cache=True)
         tune["seconds"] = round(time.time() - t0, 3)
         log(f"launch order: remap mask 0x{tune['remap_mask']:02x} "
             f"({'from the tuning cache' if tune['cached'] else 'tuned'}) in {tune['seconds']} s")

@@ -338,7 +338,7 @@ mc_status mc_plan_set_tuning(mc_plan plan, const mc_tuning* tuning);
 /* Coordinate descent over the knob bits from the default mask (two sweeps):
  * each candidate is timed as `reps` whole compress + decompress passes of
  * d_field (HIP events on the stream, after one untimed pass) and a bit is
- * flipped when that makes the passes faster.  codes and d_out
+ * flipped when that makes the passes faster by more than 0.5 %.  codes and d_out
  * (T[n_vertices]) receive the last pass's results.  The per-launch
  * profiler is paused while timing and left as it was.  Writes the choice
  * to *chosen if not NULL.  (sync) */
